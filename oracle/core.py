@@ -1,0 +1,203 @@
+"""ctypes wrapper of the C oracle (nested_oracle.c).  Test infrastructure only.
+
+Arrays are numpy float64, C-contiguous, indexed [k, j, i] (x fastest) in 3-D
+and [j, i] in 2-D.  A nested level l is a padded array of n_l + 4 points per
+axis; a multigrid level L is an array of N^L + 2 points per axis.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+MAXLEV = 8
+MAXMG = 32
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int)
+
+
+class OrcConfig(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int),
+        ("nlevels", ctypes.c_int),
+        ("n", ctypes.c_int * MAXLEV),
+        ("off", (ctypes.c_int * 3) * MAXLEV),
+        ("dx0", ctypes.c_double),
+        ("G", ctypes.c_double),
+        ("n_pre", ctypes.c_int),
+        ("n_post", ctypes.c_int),
+        ("tol", ctypes.c_double),
+        ("max_cycles", ctypes.c_int),
+        ("stop_rule", ctypes.c_int),
+        ("ghost_literal", ctypes.c_int),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Load oracle/liboracle.so, building it with gcc if it is not there."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB):
+            _build.build()
+        L = ctypes.CDLL(_build.LIB)
+        L.orc_plan.argtypes = [ctypes.c_int, _ip, ctypes.c_int]
+        L.orc_plan.restype = ctypes.c_int
+        L.orc_ghost_rule.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _ip, _dp]
+        L.orc_ghost_fill.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int]
+        L.orc_rb_sweep.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                   _dp, _dp, ctypes.c_int]
+        L.orc_residual.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp, _dp, _dp]
+        L.orc_residual_norm.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp, _dp]
+        L.orc_residual_norm.restype = ctypes.c_double
+        L.orc_restrict.argtypes = [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int, _dp]
+        L.orc_prolong_add.argtypes = [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int, _dp]
+        L.orc_interface_fill.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, ctypes.c_int, _ip, _dp,
+                                         ctypes.c_double, _dp, _dp]
+        L.orc_forces.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp, _dp, _dp, _dp]
+        L.orc_validate.argtypes = [ctypes.POINTER(OrcConfig)]
+        L.orc_validate.restype = ctypes.c_int
+        L.orc_solve.argtypes = [ctypes.POINTER(OrcConfig), ctypes.POINTER(_dp), _dp, ctypes.POINTER(_dp), _ip,
+                                _ip, _dp, _dp]
+        L.orc_solve.restype = ctypes.c_int
+        L.orc_vcycle_patch.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp, _dp, ctypes.c_int,
+                                       ctypes.c_int, ctypes.c_int]
+        L.orc_vcycle_patch.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(_dp)
+
+
+def _shape(dim, Q):
+    return (Q, Q, Q) if dim == 3 else (Q, Q)
+
+
+# ---------------------------------------------------------------- operators
+def plan(N0):
+    """Active cells per axis of every multigrid level (Sec. 2.2)."""
+    buf = (ctypes.c_int * MAXMG)()
+    m = lib().orc_plan(int(N0), buf, MAXMG)
+    if m < 1:
+        raise ValueError("bad N0")
+    return [buf[i] for i in range(m)]
+
+
+def ghost_rule(N0, L, N, literal=False):
+    one = ctypes.c_int()
+    c = ctypes.c_double()
+    lib().orc_ghost_rule(N0, L, N, int(literal), ctypes.byref(one), ctypes.byref(c))
+    return bool(one.value), c.value
+
+
+def ghost_fill(dim, N0, L, e, literal=False):
+    N = e.shape[0] - 2
+    lib().orc_ghost_fill(dim, N0, L, N, _p(e), int(literal))
+
+
+def rb_sweep(dim, N0, L, h, u, f, literal=False):
+    N = u.shape[0] - 2
+    lib().orc_rb_sweep(dim, N0, L, N, h, _p(u), _p(f), int(literal))
+
+
+def residual(dim, h, u, f):
+    r = np.zeros_like(u)
+    lib().orc_residual(dim, u.shape[0] - 2, h, _p(u), _p(f), _p(r))
+    return r
+
+
+def residual_norm(dim, h, u, f):
+    return lib().orc_residual_norm(dim, u.shape[0] - 2, h, _p(u), _p(f))
+
+
+def restrict(dim, r, Nc):
+    fc = np.zeros(_shape(dim, Nc + 2))
+    lib().orc_restrict(dim, r.shape[0] - 2, _p(r), Nc, _p(fc))
+    return fc
+
+
+def prolong_add(dim, ec, uf):
+    lib().orc_prolong_add(dim, ec.shape[0] - 2, _p(ec), uf.shape[0] - 2, _p(uf))
+
+
+def interface_fill(dim, phic, fc, nf, off, rho, fourpiG):
+    """Coarse-to-fine fill of a level l >= 1: returns (phi_f, f_f), padded."""
+    phif = np.zeros(_shape(dim, nf + 4))
+    ff = np.zeros_like(phif)
+    offa = (ctypes.c_int * 3)(*(list(off) + [0] * (3 - len(off))))
+    rho = np.ascontiguousarray(rho, dtype=np.float64)
+    lib().orc_interface_fill(dim, phic.shape[0] - 4, _p(phic), _p(fc), nf, offa, _p(rho), fourpiG, _p(phif), _p(ff))
+    return phif, ff
+
+
+def forces(dim, dx, phi):
+    """F = -grad(Phi) on Omega of a padded level array (fourth-order stencil)."""
+    n = phi.shape[0] - 4
+    shp = (n, n, n) if dim == 3 else (n, n)
+    fx, fy, fz = np.zeros(shp), np.zeros(shp), np.zeros(shp if dim == 3 else (1,))
+    lib().orc_forces(dim, n, dx, _p(phi), _p(fx), _p(fy), _p(fz))
+    return (fx, fy, fz) if dim == 3 else (fx, fy)
+
+
+def vcycle_patch(dim, h0, u, f, n_pre=2, n_post=1, literal=False):
+    N0 = u.shape[0] - 2
+    rc = lib().orc_vcycle_patch(dim, N0, h0, _p(u), _p(f), n_pre, n_post, int(literal))
+    if rc:
+        raise RuntimeError("vcycle_patch failed")
+
+
+# ---------------------------------------------------------------- nested solve
+STATUS = {0: "ok", -1: "invalid", -2: "nonfinite", -3: "not converged", -4: "diverged"}
+
+
+def make_config(geom, n_pre=2, n_post=1, tol=1e-10, max_cycles=50, stop_rule=0, ghost_literal=False):
+    c = OrcConfig()
+    c.dim = geom.dim
+    c.nlevels = geom.nlevels
+    for l in range(geom.nlevels):
+        c.n[l] = geom.n[l]
+        for a in range(3):
+            c.off[l][a] = geom.off[l][a] if a < len(geom.off[l]) else 0
+    c.dx0 = geom.dx0
+    c.G = geom.G
+    c.n_pre, c.n_post = n_pre, n_post
+    c.tol = tol
+    c.max_cycles = max_cycles
+    c.stop_rule = stop_rule
+    c.ghost_literal = int(ghost_literal)
+    return c
+
+
+def validate(geom):
+    c = make_config(geom)
+    return lib().orc_validate(ctypes.byref(c)) == 0
+
+
+def solve(geom, rho, phi_outer, fixed_cycles=None, **kw):
+    """Nested solve.  rho[0]: (n0+2)^d, rho[l>=1]: n_l^d, phi_outer: (n0+4)^d.
+
+    Returns dict(phi=[padded arrays], cycles, final_rel, hist, status)."""
+    cfg = make_config(geom, **kw)
+    d = geom.dim
+    nl = geom.nlevels
+    rho = [np.ascontiguousarray(r, dtype=np.float64) for r in rho]
+    phi_outer = np.ascontiguousarray(phi_outer, dtype=np.float64)
+    phi = [np.zeros(_shape(d, geom.n[l] + 4)) for l in range(nl)]
+    rho_p = (_dp * nl)(*[_p(r) for r in rho])
+    phi_p = (_dp * nl)(*[_p(a) for a in phi])
+    fixed = None
+    if fixed_cycles is not None:
+        fixed = (ctypes.c_int * nl)(*[int(x) for x in fixed_cycles])
+    cycles = (ctypes.c_int * nl)()
+    final = (ctypes.c_double * nl)()
+    hist = np.full(nl * (cfg.max_cycles + 1), np.nan)
+    st = lib().orc_solve(ctypes.byref(cfg), rho_p, _p(phi_outer), phi_p, fixed, cycles, final, _p(hist))
+    return dict(phi=phi, cycles=[cycles[l] for l in range(nl)], final_rel=[final[l] for l in range(nl)],
+                hist=hist.reshape(nl, cfg.max_cycles + 1), status=st, status_name=STATUS.get(st, str(st)))

@@ -1,0 +1,138 @@
+"""Direct solve of the nested discrete system: the plain definition of the
+fixed point the multigrid iteration converges to (test infrastructure).
+
+For each level l in order (one-way scheme, Sec. 2.1):
+  * unknowns: Phi at the centres of Gamma^l = Omega^l plus its inner buffer
+    layer ((n_l+2)^d cells);
+  * Dirichlet data at the outer buffer layer: the caller's potential for
+    l = 0, the multilinear interpolant of Phi^{l-1} for l >= 1;
+  * right-hand side 4 pi G rho on Omega^l, and on the inner buffer layer the
+    multilinear interpolant of level l-1's right-hand side (l >= 1) or the
+    caller's density (l = 0);
+  * operator: the 5-/7-point Laplacian (eqn:Laplacian2D/3D) with the outer
+    layer moved to the right-hand side.
+The interpolation is evaluated from physical cell-centre coordinates (the
+bilinear/trilinear formula of Appendix A at the fine centre), not from index
+tables, so it is an independent route to the same weights.  The linear system
+is solved with scipy's sparse direct solver.
+"""
+import math
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+
+def _interp(geom, l, coarse_padded, first, count):
+    """Multilinear interpolation of a padded level-(l-1) array at the centres of
+    level-l cells first..first+count-1 along every axis (index -2 = outer layer)."""
+    d = geom.dim
+    lo_c = geom.lo(l - 1)
+    lo_f = geom.lo(l)
+    dxc, dxf = geom.dx(l - 1), geom.dx(l)
+    idx = []
+    wts = []
+    for a in range(d):
+        i = np.arange(first, first + count)
+        x = lo_f[a] + (i + 0.5) * dxf
+        t = (x - lo_c[a]) / dxc - 0.5          # continuous coarse cell index
+        il = np.floor(t).astype(int)
+        w = t - il
+        idx.append(il + 2)                      # padded coarse index
+        wts.append(w)
+    out = np.zeros((count,) * d)
+    for corner in range(1 << d):
+        sel = [(corner >> a) & 1 for a in range(d)]
+        # weights along each axis
+        wa = [wts[a] if sel[a] else 1.0 - wts[a] for a in range(d)]
+        ia = [idx[a] + sel[a] for a in range(d)]
+        if d == 3:
+            vals = coarse_padded[np.ix_(ia[2], ia[1], ia[0])]
+            w = wa[2][:, None, None] * wa[1][None, :, None] * wa[0][None, None, :]
+        else:
+            vals = coarse_padded[np.ix_(ia[1], ia[0])]
+            w = wa[1][:, None] * wa[0][None, :]
+        out += w * vals
+    return out
+
+
+def _laplacian_system(d, m, h):
+    """Sparse matrix of the m^d-cell Laplacian with homogeneous Dirichlet data
+    outside (the boundary values are added to the right-hand side separately)."""
+    one = np.ones(m)
+    T = sp.diags([one[:-1], -2 * one, one[:-1]], [-1, 0, 1], shape=(m, m))
+    I = sp.identity(m)
+    if d == 2:
+        A = sp.kron(I, T) + sp.kron(T, I)
+    else:
+        A = sp.kron(sp.kron(I, I), T) + sp.kron(sp.kron(I, T), I) + sp.kron(sp.kron(T, I), I)
+    return (A / (h * h)).tocsc()
+
+
+def _boundary_term(d, phi_padded, h):
+    """Contribution of the outer-layer values to the Laplacian of each Gamma cell."""
+    P = phi_padded.shape[0]
+    m = P - 2
+    b = np.zeros((m,) * d)
+    ring = phi_padded.copy()
+    inner = (slice(1, P - 1),) * d
+    ring[inner] = 0.0
+    # sum of the face neighbours that are outer-layer points
+    for a in range(d):
+        for s in (-1, 1):
+            sl = []
+            for ax in range(d):
+                if ax == a:
+                    sl.append(slice(1 + s, P - 1 + s))
+                else:
+                    sl.append(slice(1, P - 1))
+            b += ring[tuple(sl)]
+    return b / (h * h)
+
+
+def solve(geom, rho, phi_outer):
+    """Exact nested solution.  Returns (phi_padded list, f_padded list)."""
+    d = geom.dim
+    fourpiG = 4 * math.pi * geom.G
+    phis, fs = [], []
+    for l in range(geom.nlevels):
+        n = geom.n[l]
+        P = n + 4
+        h = geom.dx(l)
+        phi = np.zeros((P,) * d)
+        f = np.zeros((P,) * d)
+        core = (slice(2, n + 2),) * d
+        if l == 0:
+            phi[...] = np.asarray(phi_outer)
+            f[(slice(1, n + 3),) * d] = fourpiG * np.asarray(rho[0])
+        else:
+            phi[...] = _interp(geom, l, phis[l - 1], -2, n + 4)
+            f[(slice(1, n + 3),) * d] = _interp(geom, l, fs[l - 1], -1, n + 2)
+            f[core] = fourpiG * np.asarray(rho[l])
+        m = n + 2
+        A = _laplacian_system(d, m, h)
+        rhs = f[(slice(1, n + 3),) * d] - _boundary_term(d, phi, h)
+        x = spla.spsolve(A, rhs.reshape(-1))
+        phi[(slice(1, n + 3),) * d] = x.reshape((m,) * d)
+        phis.append(phi)
+        fs.append(f)
+    return phis, fs
+
+
+def forces(dim, dx, phi):
+    """F = -grad(Phi) on Omega from a padded array, fourth-order central
+    difference (Eqn:force_evaluation), written with array slices."""
+    P = phi.shape[0]
+    n = P - 4
+    out = []
+    for a in range(dim):
+        ax = dim - 1 - a  # numpy axis of physical axis a ([k, j, i] order)
+
+        def sh(off):
+            sl = [slice(2, n + 2)] * dim
+            sl[ax] = slice(2 + off, n + 2 + off)
+            return phi[tuple(sl)]
+
+        g = 8.0 * (sh(1) - sh(-1)) - (sh(2) - sh(-2))
+        out.append(-g / (12.0 * dx))
+    return tuple(out)

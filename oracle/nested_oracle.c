@@ -1,0 +1,607 @@
+/*
+ * Plain FP64 CPU oracle for the nested-grid multigrid Poisson solver of
+ * Wang & Yen, "Self-gravitational Force Calculation of Second Order Accuracy
+ * Using Multigrid Method on Nested Grids" (arXiv:2001.02327).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or
+ * call this file; only the test-suite, the smoke check and the CPU-baseline
+ * leg of the benchmark use it.  It shares no code, header, table or helper
+ * with the HIP library.
+ *
+ * Everything is plain loops over natural (x-fastest) arrays, in the order the
+ * paper states the steps.  No blocking, fusion or colour-split layout.
+ *
+ * Array conventions
+ *   Nested level l: Omega^l has n cells per axis.  Its padded array has
+ *   P = n + 4 points per axis: index 0 / P-1 = outer buffer layer (Dirichlet
+ *   potential interpolated from level l-1), 1 / P-2 = inner buffer layer
+ *   (relaxed with the patch), 2..n+1 = Omega^l.  Sec. 2.1, Fig. 1b-c.
+ *   Multigrid level L of that patch: N^L active cells per axis, arrays of
+ *   (N^L + 2)^d points, active 1..N^L, one ghost layer.  Sec. 2.2.
+ *   Multigrid level 0 of patch l *is* the padded level array
+ *   (N^0 = n + 2, Gamma^l = Omega^l plus the inner buffer layer).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_MAXLEV 8   /* nested levels */
+#define ORC_MAXMG 32   /* multigrid levels per patch */
+
+/* ------------------------------------------------------------------ */
+/* configuration passed in from Python (ctypes mirror in oracle/core.py) */
+typedef struct {
+    int dim;                    /* 2 or 3 */
+    int nlevels;                /* number of nested levels */
+    int n[ORC_MAXLEV];          /* cells per axis of Omega^l */
+    int off[ORC_MAXLEV][3];     /* l>=1: lower corner of Omega^l, in cells of level l-1 */
+    double dx0;                 /* cell size of level 0 */
+    double G;                   /* gravitational constant */
+    int n_pre, n_post;          /* smoothing counts (Sec. 3: 2 and 1) */
+    double tol;                 /* stop tolerance */
+    int max_cycles;
+    int stop_rule;              /* 0: ||r||_inf <= tol*||f||_inf ; 1: max|F^q - F^{q-1}| < tol */
+    int ghost_literal;          /* 1: use the right-ghost factor exactly as printed (negative tests) */
+} orc_config;
+
+/* ------------------------------------------------------------------ */
+static size_t idx3(int Q, int i, int j, int k) { return ((size_t)k * Q + j) * Q + i; }
+
+static size_t npts(int dim, int Q) { return dim == 3 ? (size_t)Q * Q * Q : (size_t)Q * Q; }
+
+/* ------------------------------------------------------------------ */
+/* Multigrid hierarchy, Sec. 2.2 items 1-4.
+ * h^0 = 1/N^0, h^L = 2 h^{L-1}, N^L = round(1/h^L) with ties rounded up,
+ * stop once N^L = 1.  1/h^L = N^0 / 2^L exactly, so the rounding is done in
+ * integers: floor((N^0 + 2^{L-1}) / 2^L).  Returns the number of levels. */
+int orc_plan(int N0, int *NL, int maxlev)
+{
+    if (N0 < 1 || maxlev < 1) return -1;
+    NL[0] = N0;
+    int L = 0;
+    while (NL[L] > 1) {
+        L++;
+        if (L >= maxlev) return -1;
+        long num = (long)N0 + (1L << (L - 1));
+        NL[L] = (int)(num >> L);
+    }
+    return L + 1;
+}
+
+/* Right-ghost rule of Sec. 2.4 for multigrid level L >= 1 (one axis).
+ * The right-most active centre is x_N = (N - 1/2) h^L with h^L = 2^L / N^0.
+ * If x_N == 1: ghost = -e_{N-1}.  Otherwise the ghost is the value at
+ * x_N + h^L of the straight line through (x_N, e_N) that vanishes at x = 1:
+ *     e_{N+1} = e_N (1 - x_N - h^L) / (1 - x_N).
+ * (The printed factor (1 - h)/(1 - x_N) is a misprint: it does not vanish at
+ * x = 1 and its gain exceeds one; it is kept behind `literal` so the tests
+ * can show that it diverges.) */
+void orc_ghost_rule(int N0, int L, int N, int literal, int *xn_is_one, double *coef)
+{
+    *xn_is_one = ((long)(2 * N - 1) * (1L << (L - 1)) == (long)N0);
+    if (literal) {
+        double h = ldexp(1.0, L) / (double)N0;
+        double xN = ((double)N - 0.5) * h;
+        *coef = (1.0 - h) / (1.0 - xN);
+    } else {
+        /* multiply numerator and denominator by 2 N^0: both are integers, so the
+         * factor is a single correctly rounded division */
+        double num = 2.0 * N0 - (double)(2 * N + 1) * ldexp(1.0, L);
+        double den = 2.0 * N0 - (double)(2 * N - 1) * ldexp(1.0, L);
+        *coef = num / den;
+    }
+}
+
+/* Fill the ghost layer of a multigrid level L >= 1 (Sec. 2.4): left
+ * e_0 = -e_1, right per orc_ghost_rule; the 1-D rule is applied along x over
+ * the active y,z range, then along y over the x range including ghosts, then
+ * along z over the full x,y range, so edges and corners receive the rule of
+ * every axis on which they are ghosts. */
+void orc_ghost_fill(int dim, int N0, int L, int N, double *e, int literal)
+{
+    int Q = N + 2;
+    int one;
+    double c;
+    orc_ghost_rule(N0, L, N, literal, &one, &c);
+    int klo = dim == 3 ? 1 : 0, khi = dim == 3 ? N : 0;
+    /* x */
+    for (int k = klo; k <= khi; k++)
+        for (int j = 1; j <= N; j++) {
+            e[idx3(Q, 0, j, k)] = -e[idx3(Q, 1, j, k)];
+            e[idx3(Q, N + 1, j, k)] = one ? -e[idx3(Q, N - 1, j, k)] : c * e[idx3(Q, N, j, k)];
+        }
+    /* y */
+    for (int k = klo; k <= khi; k++)
+        for (int i = 0; i <= N + 1; i++) {
+            e[idx3(Q, i, 0, k)] = -e[idx3(Q, i, 1, k)];
+            e[idx3(Q, i, N + 1, k)] = one ? -e[idx3(Q, i, N - 1, k)] : c * e[idx3(Q, i, N, k)];
+        }
+    /* z */
+    if (dim == 3)
+        for (int j = 0; j <= N + 1; j++)
+            for (int i = 0; i <= N + 1; i++) {
+                e[idx3(Q, i, j, 0)] = -e[idx3(Q, i, j, 1)];
+                e[idx3(Q, i, j, N + 1)] = one ? -e[idx3(Q, i, j, N - 1)] : c * e[idx3(Q, i, j, N)];
+            }
+}
+
+/* ------------------------------------------------------------------ */
+/* Discrete Laplacian, eqn:Laplacian2D / eqn:Laplacian3D: sum of the 2d face
+ * neighbours minus 2d times the centre, over (Delta x^L_MG)^2. */
+static double laplacian(int dim, int Q, const double *u, int i, int j, int k, double h)
+{
+    if (dim == 3)
+        return (u[idx3(Q, i - 1, j, k)] + u[idx3(Q, i + 1, j, k)] + u[idx3(Q, i, j - 1, k)] +
+                u[idx3(Q, i, j + 1, k)] + u[idx3(Q, i, j, k - 1)] + u[idx3(Q, i, j, k + 1)] -
+                6.0 * u[idx3(Q, i, j, k)]) / (h * h);
+    return (u[idx3(Q, i - 1, j, 0)] + u[idx3(Q, i + 1, j, 0)] + u[idx3(Q, i, j - 1, 0)] +
+            u[idx3(Q, i, j + 1, 0)] - 4.0 * u[idx3(Q, i, j, 0)]) / (h * h);
+}
+
+/* One Gauss-Seidel half sweep over the cells of one colour.  Red (colour 0)
+ * cells have an even sum of 0-based active indices.  Solving the discrete
+ * Poisson equation at a cell for its own value, with the neighbours held,
+ * gives u_c = (sum of neighbours - h^2 f_c) / (2d).  Cells of one colour only
+ * read cells of the other colour, so the loop order inside a colour does not
+ * matter. */
+static void half_sweep(int dim, int N, double h, double *u, const double *f, int colour)
+{
+    int Q = N + 2;
+    int klo = dim == 3 ? 1 : 0, khi = dim == 3 ? N : 0;
+#pragma omp parallel for schedule(static)
+    for (int k = klo; k <= khi; k++)
+        for (int j = 1; j <= N; j++)
+            for (int i = 1; i <= N; i++) {
+                int par = ((i - 1) + (j - 1) + (dim == 3 ? k - 1 : 0)) & 1;
+                if (par != colour) continue;
+                double s;
+                if (dim == 3)
+                    s = u[idx3(Q, i - 1, j, k)] + u[idx3(Q, i + 1, j, k)] + u[idx3(Q, i, j - 1, k)] +
+                        u[idx3(Q, i, j + 1, k)] + u[idx3(Q, i, j, k - 1)] + u[idx3(Q, i, j, k + 1)];
+                else
+                    s = u[idx3(Q, i - 1, j, 0)] + u[idx3(Q, i + 1, j, 0)] + u[idx3(Q, i, j - 1, 0)] +
+                        u[idx3(Q, i, j + 1, 0)];
+                size_t c = idx3(Q, i, j, k);
+                u[c] = (s - h * h * f[c]) / (2.0 * dim);
+            }
+}
+
+/* A full red-black sweep.  Multigrid level 0 keeps its ghost layer fixed
+ * (Dirichlet data of the patch); levels L >= 1 refresh their ghosts from the
+ * current interior before each half sweep (Sec. 2.4, last paragraph). */
+void orc_rb_sweep(int dim, int N0, int L, int N, double h, double *u, const double *f, int literal)
+{
+    for (int colour = 0; colour < 2; colour++) {
+        if (L > 0) orc_ghost_fill(dim, N0, L, N, u, literal);
+        half_sweep(dim, N, h, u, f, colour);
+    }
+}
+
+/* Residual r = f - lap(u) on active cells; zero on ghosts.  The paper's
+ * density residual (step 4) is lap(u) - 4 pi G rho and its coarse problem
+ * (step 6) carries a minus sign, so the coarse right-hand side is R(r) with
+ * this r. */
+void orc_residual(int dim, int N, double h, const double *u, const double *f, double *r)
+{
+    int Q = N + 2;
+    memset(r, 0, npts(dim, Q) * sizeof(double));
+    int klo = dim == 3 ? 1 : 0, khi = dim == 3 ? N : 0;
+#pragma omp parallel for schedule(static)
+    for (int k = klo; k <= khi; k++)
+        for (int j = 1; j <= N; j++)
+            for (int i = 1; i <= N; i++) {
+                size_t c = idx3(Q, i, j, k);
+                r[c] = f[c] - laplacian(dim, Q, u, i, j, k, h);
+            }
+}
+
+/* max over active cells of |f - lap(u)| */
+double orc_residual_norm(int dim, int N, double h, const double *u, const double *f)
+{
+    int Q = N + 2;
+    int klo = dim == 3 ? 1 : 0, khi = dim == 3 ? N : 0;
+    double m = 0.0;
+    int bad = 0;
+    for (int k = klo; k <= khi; k++)
+        for (int j = 1; j <= N; j++)
+            for (int i = 1; i <= N; i++) {
+                double a = fabs(f[idx3(Q, i, j, k)] - laplacian(dim, Q, u, i, j, k, h));
+                if (!isfinite(a)) bad = 1;
+                if (a > m) m = a;
+            }
+    return bad ? NAN : m;
+}
+
+double orc_active_absmax(int dim, int N, const double *f)
+{
+    int Q = N + 2;
+    int klo = dim == 3 ? 1 : 0, khi = dim == 3 ? N : 0;
+    double m = 0.0;
+    for (int k = klo; k <= khi; k++)
+        for (int j = 1; j <= N; j++)
+            for (int i = 1; i <= N; i++) {
+                double a = fabs(f[idx3(Q, i, j, k)]);
+                if (a > m) m = a;
+            }
+    return m;
+}
+
+/* Restriction, eqn:restriction2D/3D: coarse value = mean of the 2^d fine
+ * children.  Coarse active cell I covers fine cells 2I-1 and 2I per axis.
+ * Children outside the fine active range 1..Nf hold no residual and count as
+ * zero (the coarse grids' right edges float, Sec. 2.2). */
+void orc_restrict(int dim, int Nf, const double *r, int Nc, double *fc)
+{
+    int Qf = Nf + 2, Qc = Nc + 2;
+    memset(fc, 0, npts(dim, Qc) * sizeof(double));
+    int klo = dim == 3 ? 1 : 0, khi = dim == 3 ? Nc : 0;
+#pragma omp parallel for schedule(static)
+    for (int K = klo; K <= khi; K++)
+        for (int J = 1; J <= Nc; J++)
+            for (int I = 1; I <= Nc; I++) {
+                double sum = 0.0;
+                int kc0 = dim == 3 ? 2 * K - 1 : 0, kc1 = dim == 3 ? 2 * K : 0;
+                for (int k = kc0; k <= kc1; k++)
+                    for (int j = 2 * J - 1; j <= 2 * J; j++)
+                        for (int i = 2 * I - 1; i <= 2 * I; i++) {
+                            int inside = i <= Nf && j <= Nf && (dim == 2 || k <= Nf);
+                            if (inside) sum += r[idx3(Qf, i, j, k)];
+                        }
+                fc[idx3(Qc, I, J, K)] = sum / (dim == 3 ? 8.0 : 4.0);
+            }
+}
+
+/* Multilinear interpolation of eqn:prolongation2D/3D, in the paper's integer
+ * form: the nearest coarse value carries 9/16 (2-D) or 27/64 (3-D), each value
+ * displaced along one axis 3/16 or 9/64, along two axes 1/16 or 3/64, along
+ * three axes 1/64 (Appendix A: bilinear/trilinear interpolation at the
+ * quarter points).  `ci/cj/ck` are the nearest coarse indices and `si/sj/sk`
+ * the direction (+1/-1) toward the fine point along each axis. */
+static double interp_point(int dim, int Qc, const double *c, int ci, int cj, int ck, int si, int sj,
+                           int sk)
+{
+    if (dim == 2) {
+        double A = c[idx3(Qc, ci, cj, 0)];
+        double B = c[idx3(Qc, ci + si, cj, 0)];
+        double D = c[idx3(Qc, ci, cj + sj, 0)];
+        double C = c[idx3(Qc, ci + si, cj + sj, 0)];
+        return (9.0 * A + 3.0 * B + C + 3.0 * D) / 16.0;
+    }
+    double near = c[idx3(Qc, ci, cj, ck)];
+    double face = c[idx3(Qc, ci + si, cj, ck)] + c[idx3(Qc, ci, cj + sj, ck)] + c[idx3(Qc, ci, cj, ck + sk)];
+    double edge = c[idx3(Qc, ci + si, cj + sj, ck)] + c[idx3(Qc, ci + si, cj, ck + sk)] +
+                  c[idx3(Qc, ci, cj + sj, ck + sk)];
+    double corner = c[idx3(Qc, ci + si, cj + sj, ck + sk)];
+    return (27.0 * near + 9.0 * face + 3.0 * edge + corner) / 64.0;
+}
+
+/* Prolongation and correction, step 10: u^{L-1} += P(e^L) on the active
+ * cells of level L-1.  Fine active cell a lies in coarse cell ceil(a/2); an
+ * odd a is the left child, so its second coarse neighbour is on the left. */
+void orc_prolong_add(int dim, int Nc, const double *ec, int Nf, double *uf)
+{
+    int Qf = Nf + 2, Qc = Nc + 2;
+    (void)Nc;
+    int klo = dim == 3 ? 1 : 0, khi = dim == 3 ? Nf : 0;
+#pragma omp parallel for schedule(static)
+    for (int k = klo; k <= khi; k++)
+        for (int j = 1; j <= Nf; j++)
+            for (int i = 1; i <= Nf; i++) {
+                int ci = (i + 1) / 2, cj = (j + 1) / 2, ck = dim == 3 ? (k + 1) / 2 : 0;
+                int si = (i & 1) ? -1 : 1, sj = (j & 1) ? -1 : 1, sk = (k & 1) ? -1 : 1;
+                uf[idx3(Qf, i, j, k)] += interp_point(dim, Qc, ec, ci, cj, ck, si, sj, sk);
+            }
+}
+
+/* ------------------------------------------------------------------ */
+/* One V-cycle, steps 2-13 of Sec. 2.3, on patch storage:
+ *   mg_u[0] = potential (level array), mg_f[0] = 4 pi G rho,
+ *   mg_u[L], mg_f[L] (L >= 1) = correction and its right-hand side,
+ *   mg_r[L] = residual scratch.
+ * Coarse corrections start from zero each cycle.  The coarsest level gets
+ * only the N_pre sweeps (steps 6-8). */
+typedef struct {
+    int dim, nmg, N0;
+    int N[ORC_MAXMG];
+    double h[ORC_MAXMG];
+    double *u[ORC_MAXMG], *f[ORC_MAXMG], *r[ORC_MAXMG];
+    int literal;
+} orc_mg;
+
+static void vcycle(orc_mg *m, int n_pre, int n_post)
+{
+    int d = m->dim;
+    for (int s = 0; s < n_pre; s++) orc_rb_sweep(d, m->N0, 0, m->N[0], m->h[0], m->u[0], m->f[0], m->literal);
+    int L = 0;
+    while (m->N[L] > 1) {
+        if (L > 0) orc_ghost_fill(d, m->N0, L, m->N[L], m->u[L], m->literal);
+        orc_residual(d, m->N[L], m->h[L], m->u[L], m->f[L], m->r[L]);
+        orc_restrict(d, m->N[L], m->r[L], m->N[L + 1], m->f[L + 1]);
+        memset(m->u[L + 1], 0, npts(d, m->N[L + 1] + 2) * sizeof(double));
+        for (int s = 0; s < n_pre; s++)
+            orc_rb_sweep(d, m->N0, L + 1, m->N[L + 1], m->h[L + 1], m->u[L + 1], m->f[L + 1], m->literal);
+        L++;
+    }
+    while (L > 0) {
+        orc_ghost_fill(d, m->N0, L, m->N[L], m->u[L], m->literal);
+        orc_prolong_add(d, m->N[L], m->u[L], m->N[L - 1], m->u[L - 1]);
+        for (int s = 0; s < n_post; s++)
+            orc_rb_sweep(d, m->N0, L - 1, m->N[L - 1], m->h[L - 1], m->u[L - 1], m->f[L - 1], m->literal);
+        L--;
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Coarse-to-fine fill of patch l >= 1 (Sec. 2.1, Sec. 2.4 first paragraph):
+ * the potential on every padded point (outer buffer = Dirichlet data, the
+ * rest = initial guess) and the right-hand side on the inner buffer layer are
+ * interpolated from level l-1; Omega^l takes the caller's density.  Fine
+ * padded index p along an axis is fine cell p-2, which sits in coarse cell
+ * off + floor((p-2)/2), i.e. coarse padded index q = off + 2 + floor((p-2)/2);
+ * an even p-2 is a left child, so the second coarse point is q-1.
+ * Interpolating f = 4 pi G rho is the same linear map as interpolating rho. */
+void orc_interface_fill(int dim, int nc, const double *phic, const double *fc, int nf, const int *off,
+                        const double *rho, double fourpiG, double *phif, double *ff)
+{
+    int Pc = nc + 4, Pf = nf + 4;
+    int kmax = dim == 3 ? Pf - 1 : 0;
+    for (int k = 0; k <= kmax; k++)
+        for (int j = 0; j < Pf; j++)
+            for (int i = 0; i < Pf; i++) {
+                int p[3] = {i, j, k}, q[3] = {0, 0, 0}, s[3] = {0, 0, 0};
+                for (int a = 0; a < dim; a++) {
+                    int fine = p[a] - 2;
+                    int fl = (fine >= 0) ? fine / 2 : -((1 - fine) / 2); /* floor(fine/2) */
+                    q[a] = off[a] + 2 + fl;
+                    s[a] = (fine % 2 == 0) ? -1 : 1;
+                }
+                size_t c = idx3(Pf, i, j, k);
+                phif[c] = interp_point(dim, Pc, phic, q[0], q[1], q[2], s[0], s[1], s[2]);
+                int ring = 0, omega = 1;
+                for (int a = 0; a < dim; a++) {
+                    if (p[a] == 0 || p[a] == Pf - 1) ring = 2;
+                    else if ((p[a] == 1 || p[a] == Pf - 2) && ring < 1) ring = 1;
+                    if (p[a] < 2 || p[a] > nf + 1) omega = 0;
+                }
+                if (omega) {
+                    size_t ri = dim == 3 ? (((size_t)(k - 2) * nf + (j - 2)) * nf + (i - 2))
+                                         : ((size_t)(j - 2) * nf + (i - 2));
+                    ff[c] = fourpiG * rho[ri];
+                } else if (ring == 1) {
+                    ff[c] = interp_point(dim, Pc, fc, q[0], q[1], q[2], s[0], s[1], s[2]);
+                } else {
+                    ff[c] = 0.0;
+                }
+            }
+}
+
+/* Forces F = -grad(Phi) on Omega^l with the fourth-order central difference
+ * of Eqn:force_evaluation: dPhi/dx = (4/3)(Phi_{i+1}-Phi_{i-1})/(2 dx)
+ *                                  - (1/3)(Phi_{i+2}-Phi_{i-2})/(4 dx).
+ * Output arrays are n^d, natural order. */
+void orc_forces(int dim, int n, double dx, const double *phi, double *fx, double *fy, double *fz)
+{
+    int P = n + 4;
+    int kmax = dim == 3 ? n - 1 : 0;
+    for (int k = 0; k <= kmax; k++)
+        for (int j = 0; j < n; j++)
+            for (int i = 0; i < n; i++) {
+                int pi = i + 2, pj = j + 2, pk = dim == 3 ? k + 2 : 0;
+                size_t o = dim == 3 ? (((size_t)k * n + j) * n + i) : ((size_t)j * n + i);
+                double dpx = (4.0 / 3.0) * (phi[idx3(P, pi + 1, pj, pk)] - phi[idx3(P, pi - 1, pj, pk)]) / (2.0 * dx) -
+                             (1.0 / 3.0) * (phi[idx3(P, pi + 2, pj, pk)] - phi[idx3(P, pi - 2, pj, pk)]) / (4.0 * dx);
+                double dpy = (4.0 / 3.0) * (phi[idx3(P, pi, pj + 1, pk)] - phi[idx3(P, pi, pj - 1, pk)]) / (2.0 * dx) -
+                             (1.0 / 3.0) * (phi[idx3(P, pi, pj + 2, pk)] - phi[idx3(P, pi, pj - 2, pk)]) / (4.0 * dx);
+                fx[o] = -dpx;
+                fy[o] = -dpy;
+                if (dim == 3) {
+                    double dpz = (4.0 / 3.0) * (phi[idx3(P, pi, pj, pk + 1)] - phi[idx3(P, pi, pj, pk - 1)]) / (2.0 * dx) -
+                                 (1.0 / 3.0) * (phi[idx3(P, pi, pj, pk + 2)] - phi[idx3(P, pi, pj, pk - 2)]) / (4.0 * dx);
+                    fz[o] = -dpz;
+                }
+            }
+}
+
+/* ------------------------------------------------------------------ */
+/* Validation of the nested geometry: returns 0 or a negative code. */
+int orc_validate(const orc_config *cfg)
+{
+    if (cfg->dim != 2 && cfg->dim != 3) return -1;
+    if (cfg->nlevels < 1 || cfg->nlevels > ORC_MAXLEV) return -1;
+    for (int l = 0; l < cfg->nlevels; l++) {
+        if (cfg->n[l] < 4 || (cfg->n[l] & 1)) return -1;
+        if (l == 0) continue;
+        for (int a = 0; a < cfg->dim; a++) {
+            int o = cfg->off[l][a];
+            if (o < 1 || o + cfg->n[l] / 2 > cfg->n[l - 1] - 1) return -1;
+        }
+    }
+    if (!(cfg->dx0 > 0.0)) return -1;
+    return 0;
+}
+
+static double maxabs_diff(size_t m, const double *a, const double *b)
+{
+    double x = 0.0;
+    for (size_t i = 0; i < m; i++) {
+        double t = fabs(a[i] - b[i]);
+        if (!(t <= x)) x = t; /* propagates NaN */
+    }
+    return x;
+}
+
+/* Nested solve, one-way scheme (Sec. 2.1): level 0 first, each finer level
+ * from the converged coarser one.
+ *   rho[0]  : (n0+2)^d, Omega^0 plus its inner buffer layer (caller data)
+ *   rho[l]  : n_l^d on Omega^l (l >= 1)
+ *   phi_outer: (n0+4)^d, only its outer layer is read (Dirichlet data of level 0)
+ *   phi[l]  : out, (n_l+4)^d padded potential
+ *   fixed_cycles: NULL, or per-level cycle counts to run instead of the stop rule
+ *   cycles, final_rel: out per level; hist: NULL or out, nlevels*(max_cycles+1)
+ *     relative residual before the first cycle and after each cycle.
+ * Returns 0, -2 (non-finite), -3 (cap reached without convergence),
+ * -4 (diverged), -1 (invalid geometry or allocation failure). */
+int orc_solve(const orc_config *cfg, const double *const *rho, const double *phi_outer, double **phi,
+              const int *fixed_cycles, int *cycles, double *final_rel, double *hist)
+{
+    if (orc_validate(cfg)) return -1;
+    int d = cfg->dim;
+    double fourpiG = 4.0 * M_PI * cfg->G;
+    int status = 0;
+    double *fl[ORC_MAXLEV] = {0};
+    for (int l = 0; l < cfg->nlevels; l++) {
+        fl[l] = calloc(npts(d, cfg->n[l] + 4), sizeof(double));
+        if (!fl[l]) { status = -1; goto done; }
+    }
+    for (int l = 0; l < cfg->nlevels; l++) {
+        int n = cfg->n[l];
+        int P = n + 4;
+        double dx = ldexp(cfg->dx0, -l);
+        size_t m0 = npts(d, P);
+        double *f0 = fl[l];
+        double *u0 = phi[l];
+        if (l == 0) {
+            /* Dirichlet data from the caller; Gamma^0 starts from zero */
+            memcpy(u0, phi_outer, m0 * sizeof(double));
+            int kmin = d == 3 ? 1 : 0, kmax = d == 3 ? P - 2 : 0;
+            for (int k = kmin; k <= kmax; k++)
+                for (int j = 1; j <= P - 2; j++)
+                    for (int i = 1; i <= P - 2; i++) {
+                        size_t c = idx3(P, i, j, k);
+                        u0[c] = 0.0;
+                        size_t ri = d == 3 ? (((size_t)(k - 1) * (n + 2) + (j - 1)) * (n + 2) + (i - 1))
+                                           : ((size_t)(j - 1) * (n + 2) + (i - 1));
+                        f0[c] = fourpiG * rho[0][ri];
+                    }
+        } else {
+            orc_interface_fill(d, cfg->n[l - 1], phi[l - 1], fl[l - 1], n, cfg->off[l], rho[l], fourpiG, u0, f0);
+        }
+
+        orc_mg m;
+        memset(&m, 0, sizeof m);
+        m.dim = d;
+        m.N0 = n + 2;
+        m.literal = cfg->ghost_literal;
+        m.nmg = orc_plan(m.N0, m.N, ORC_MAXMG);
+        if (m.nmg < 1) { status = -1; goto done; }
+        m.u[0] = u0;
+        m.f[0] = f0;
+        int oom = 0;
+        for (int L = 0; L < m.nmg; L++) {
+            m.h[L] = dx * ldexp(1.0, L);
+            size_t mm = npts(d, m.N[L] + 2);
+            if (L > 0) {
+                m.u[L] = calloc(mm, sizeof(double));
+                m.f[L] = calloc(mm, sizeof(double));
+                if (!m.u[L] || !m.f[L]) oom = 1;
+            }
+            m.r[L] = calloc(mm, sizeof(double));
+            if (!m.r[L]) oom = 1;
+        }
+
+        /* reference scale of the stop test: ||f||_inf over Gamma^l, or, for a
+         * zero density, the residual of the zero potential */
+        double scale = orc_active_absmax(d, m.N[0], f0);
+        if (!(scale > 0.0) && !oom) {
+            double *z = malloc(m0 * sizeof(double));
+            if (!z) oom = 1;
+            else {
+                memcpy(z, u0, m0 * sizeof(double));
+                int kmin = d == 3 ? 1 : 0, kmax = d == 3 ? P - 2 : 0;
+                for (int k = kmin; k <= kmax; k++)
+                    for (int j = 1; j <= P - 2; j++)
+                        for (int i = 1; i <= P - 2; i++) z[idx3(P, i, j, k)] = 0.0;
+                scale = orc_residual_norm(d, m.N[0], m.h[0], z, f0);
+                free(z);
+            }
+        }
+
+        size_t nf = (size_t)n * n * (d == 3 ? n : 1);
+        double *Fprev = NULL, *Fcur = NULL;
+        if (cfg->stop_rule == 1 && !oom) {
+            Fprev = calloc(3 * nf, sizeof(double));
+            Fcur = calloc(3 * nf, sizeof(double));
+            if (!Fprev || !Fcur) oom = 1;
+            else orc_forces(d, n, dx, u0, Fprev, Fprev + nf, Fprev + 2 * nf);
+        }
+
+        int lvl_status = 0, q = 0;
+        double r = 0.0;
+        if (oom) lvl_status = -1;
+        else {
+            r = orc_residual_norm(d, m.N[0], m.h[0], u0, f0);
+            double r0 = r;
+            double *hl = hist ? hist + (size_t)l * (cfg->max_cycles + 1) : NULL;
+            if (hl) hl[0] = scale > 0 ? r / scale : r;
+            int pinned = fixed_cycles && fixed_cycles[l] >= 0;
+            for (;;) {
+                if (!isfinite(r)) { lvl_status = -2; break; }
+                if (pinned) {
+                    if (q >= fixed_cycles[l]) break;
+                } else if (cfg->stop_rule == 0 && r <= cfg->tol * scale) {
+                    break;
+                }
+                if (q >= cfg->max_cycles) { lvl_status = -3; break; }
+                vcycle(&m, cfg->n_pre, cfg->n_post);
+                q++;
+                r = orc_residual_norm(d, m.N[0], m.h[0], u0, f0);
+                if (hl && q <= cfg->max_cycles) hl[q] = scale > 0 ? r / scale : r;
+                if (!isfinite(r)) { lvl_status = -2; break; }
+                if (r0 > 0 && r > 1e3 * r0) { lvl_status = -4; break; }
+                if (cfg->stop_rule == 1 && !pinned) {
+                    orc_forces(d, n, dx, u0, Fcur, Fcur + nf, Fcur + 2 * nf);
+                    double dF = maxabs_diff((size_t)d * nf, Fcur, Fprev);
+                    double *t = Fprev; Fprev = Fcur; Fcur = t;
+                    if (dF < cfg->tol) break;
+                }
+            }
+        }
+        cycles[l] = q;
+        final_rel[l] = scale > 0 ? r / scale : r;
+        free(Fprev);
+        free(Fcur);
+        for (int L = 0; L < m.nmg; L++) {
+            if (L > 0) { free(m.u[L]); free(m.f[L]); }
+            free(m.r[L]);
+        }
+        if (lvl_status && !status) status = lvl_status;
+        if (lvl_status == -1 || lvl_status == -2 || lvl_status == -4) goto done;
+    }
+done:
+    for (int l = 0; l < cfg->nlevels; l++) free(fl[l]);
+    return status;
+}
+
+/* ------------------------------------------------------------------ */
+/* Single-patch entry points used by the operator tests. */
+
+/* one V-cycle on a single patch with caller-provided level-0 arrays
+ * (padded (N0+2)^d potential with fixed ghosts, and f) */
+int orc_vcycle_patch(int dim, int N0, double h0, double *u, const double *f, int n_pre, int n_post, int literal)
+{
+    orc_mg m;
+    memset(&m, 0, sizeof m);
+    m.dim = dim;
+    m.N0 = N0;
+    m.literal = literal;
+    m.nmg = orc_plan(N0, m.N, ORC_MAXMG);
+    if (m.nmg < 1) return -1;
+    m.u[0] = u;
+    m.f[0] = (double *)f;
+    for (int L = 0; L < m.nmg; L++) {
+        m.h[L] = h0 * ldexp(1.0, L);
+        size_t mm = npts(dim, m.N[L] + 2);
+        if (L > 0) {
+            m.u[L] = calloc(mm, sizeof(double));
+            m.f[L] = calloc(mm, sizeof(double));
+        }
+        m.r[L] = calloc(mm, sizeof(double));
+    }
+    vcycle(&m, n_pre, n_post);
+    for (int L = 0; L < m.nmg; L++) {
+        if (L > 0) { free(m.u[L]); free(m.f[L]); }
+        free(m.r[L]);
+    }
+    return 0;
+}

@@ -1,0 +1,340 @@
+"""Seeded synthetic inputs: nested geometries and closed-form density/potential
+pairs.  This module holds the problem definitions only (geometry, densities,
+analytic potentials and forces); it contains none of the solver's arithmetic,
+so both the HIP path and the CPU oracle can take their inputs from it.
+
+Problems
+  * Paper2D   -- the 2-D model of Sec. 3.1: sigma = 4 R0^2/(R^2+R0^2)^2,
+                 Phi = ln(R^2/R0^2 + 1), G = 1/(4 pi), R0 = 0.3.
+  * Paper3D   -- the 3-D model of Sec. 3.2: rho = rho0 (1 - r^2/r0^2)^2 inside
+                 r0, piecewise closed-form Phi and f_r, G = 1.
+  * Plummer   -- superposed Plummer spheres, rho = 3M/(4 pi a^3) (1+r^2/a^2)^(-5/2),
+                 Phi = -G M / sqrt(r^2+a^2) (textbook pair).
+  * Gaussian  -- manufactured Phi = exp(-r^2/s^2), rho = lap(Phi)/(4 pi G).
+
+Geometries follow Sec. 2.1: level l has n_l cells per axis of size
+dx0 / 2^l; its lower corner sits `off[l]` coarse cells above that of level
+l-1.  Level-0 boundary data (outer buffer potential, inner-buffer density) are
+taken from the closed form.
+
+Arrays are torch float64 tensors indexed [k, j, i] (x fastest); they can be
+built on any device.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import List, Sequence, Tuple
+
+import numpy as np
+import torch
+
+
+# ------------------------------------------------------------------ geometry
+@dataclass
+class Geometry:
+    dim: int
+    n: List[int]                      # cells per axis of Omega^l
+    off: List[Tuple[int, int, int]]   # l >= 1: corner offset in coarse cells (off[0] unused)
+    lo0: Tuple[float, float, float]   # physical lower corner of Omega^0
+    dx0: float
+    G: float = 1.0
+
+    @property
+    def nlevels(self) -> int:
+        return len(self.n)
+
+    def dx(self, l: int) -> float:
+        return self.dx0 / (1 << l)
+
+    def lo(self, l: int) -> Tuple[float, ...]:
+        x = list(self.lo0[: self.dim])
+        for ll in range(1, l + 1):
+            for a in range(self.dim):
+                x[a] += self.off[ll][a] * self.dx(ll - 1)
+        return tuple(x)
+
+    def centres(self, l: int, first: int, count: int, device="cpu"):
+        """Per-axis cell-centre coordinates for Omega^l cell indices first..first+count-1
+        (index -2 = outer buffer layer, -1 = inner buffer layer)."""
+        lo = self.lo(l)
+        dx = self.dx(l)
+        i = torch.arange(first, first + count, dtype=torch.float64, device=device)
+        return [lo[a] + (i + 0.5) * dx for a in range(self.dim)]
+
+    def mesh(self, l: int, first: int, count: int, device="cpu"):
+        """Coordinate arrays (x, y[, z]) broadcast to [k, j, i] shape."""
+        ax = self.centres(l, first, count, device)
+        if self.dim == 3:
+            z, y, x = torch.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
+            return x, y, z
+        y, x = torch.meshgrid(ax[1], ax[0], indexing="ij")
+        return x, y
+
+    def describe(self) -> dict:
+        return dict(dim=self.dim, n=list(self.n), off=[list(o) for o in self.off], lo0=list(self.lo0[: self.dim]),
+                    dx0=self.dx0, G=self.G)
+
+
+def centred_geometry(dim: int, nlevels: int, N: int, half_width0: float, G: float) -> Geometry:
+    """Levels of N cells each, level l covering [-w/2^l, w/2^l]^d (each level
+    half the extent of the previous, so the offset is N/4 coarse cells)."""
+    if N % 4:
+        raise ValueError("N must be a multiple of 4 for centred nesting")
+    off = [(0, 0, 0)] + [(N // 4,) * 3 for _ in range(1, nlevels)]
+    return Geometry(dim=dim, n=[N] * nlevels, off=off, lo0=(-half_width0,) * 3, dx0=2 * half_width0 / N, G=G)
+
+
+# ------------------------------------------------------------------ problems
+class Problem:
+    """Closed-form density/potential/force triple."""
+    G: float = 1.0
+
+    def rho(self, *x):
+        raise NotImplementedError
+
+    def phi(self, *x):
+        raise NotImplementedError
+
+    def force(self, *x):
+        """Analytic F = -grad(Phi), tuple of d arrays."""
+        raise NotImplementedError
+
+
+class Paper2D(Problem):
+    """Sec. 3.1 model (G = 1/(4 pi), so 4 pi G rho = sigma)."""
+
+    def __init__(self, R0: float = 0.3):
+        self.R0 = R0
+        self.G = 1.0 / (4.0 * math.pi)
+
+    def rho(self, x, y):
+        R2 = x * x + y * y
+        return 4 * self.R0 ** 2 / (R2 + self.R0 ** 2) ** 2
+
+    def phi(self, x, y):
+        return torch.log((x * x + y * y) / self.R0 ** 2 + 1.0)
+
+    def force(self, x, y):
+        R2 = x * x + y * y
+        g = 2.0 / (R2 + self.R0 ** 2)   # f_R / R
+        return (-g * x, -g * y)
+
+    def fR(self, x, y):
+        """The paper's radial acceleration f_R = |grad Phi| (positive)."""
+        R = torch.sqrt(x * x + y * y)
+        return 2 * R / (R * R + self.R0 ** 2)
+
+
+class Paper3D(Problem):
+    """Sec. 3.2 model: n = 2 polytrope-like ball, G = 1."""
+
+    def __init__(self, rho0: float = 1.0, r0: float = 0.25):
+        self.rho0, self.r0 = rho0, r0
+        self.G = 1.0
+        self.M = 32 * math.pi * rho0 * r0 ** 3 / 105
+
+    def rho(self, x, y, z):
+        r2 = x * x + y * y + z * z
+        inside = r2 <= self.r0 ** 2
+        return torch.where(inside, self.rho0 * (1 - r2 / self.r0 ** 2) ** 2, torch.zeros_like(r2))
+
+    def phi(self, x, y, z):
+        r2 = x * x + y * y + z * z
+        r = torch.sqrt(r2)
+        p, r0 = self.rho0, self.r0
+        inner = -2.0 / 3.0 * math.pi * p * r0 ** 2 + 4 * math.pi * p * (r2 / 6 - r2 * r2 / (10 * r0 ** 2) +
+                                                                        r2 ** 3 / (42 * r0 ** 4))
+        outer = -self.M / torch.where(r > 0, r, torch.ones_like(r))
+        return torch.where(r <= r0, inner, outer)
+
+    def fr(self, x, y, z):
+        """Radial acceleration f_r = -dPhi/dr (negative: pointing inward)."""
+        r = torch.sqrt(x * x + y * y + z * z)
+        p, r0 = self.rho0, self.r0
+        inner = -4 * math.pi * p * (r / 3 - 2.0 / 5.0 * r ** 3 / r0 ** 2 + 1.0 / 7.0 * r ** 5 / r0 ** 4)
+        outer = -self.M / torch.where(r > 0, r * r, torch.ones_like(r))
+        return torch.where(r <= r0, inner, outer)
+
+    def force(self, x, y, z):
+        r = torch.sqrt(x * x + y * y + z * z)
+        fr = self.fr(x, y, z)
+        safe = torch.where(r > 0, r, torch.ones_like(r))
+        s = torch.where(r > 0, fr / safe, torch.zeros_like(r))
+        return (s * x, s * y, s * z)
+
+
+class Plummer(Problem):
+    """Superposition of Plummer spheres [(M, a, (cx, cy, cz)), ...]."""
+
+    def __init__(self, spheres: Sequence[Tuple[float, float, Sequence[float]]], G: float = 1.0):
+        self.spheres = [(float(M), float(a), tuple(float(c) for c in cen)) for M, a, cen in spheres]
+        self.G = G
+
+    def rho(self, *x):
+        out = torch.zeros_like(x[0])
+        for M, a, c in self.spheres:
+            r2 = sum((x[i] - c[i]) ** 2 for i in range(len(x)))
+            out = out + 3 * M / (4 * math.pi * a ** 3) * (1 + r2 / a ** 2) ** (-2.5)
+        return out
+
+    def phi(self, *x):
+        out = torch.zeros_like(x[0])
+        for M, a, c in self.spheres:
+            r2 = sum((x[i] - c[i]) ** 2 for i in range(len(x)))
+            out = out - self.G * M / torch.sqrt(r2 + a * a)
+        return out
+
+    def force(self, *x):
+        out = [torch.zeros_like(x[0]) for _ in x]
+        for M, a, c in self.spheres:
+            r2 = sum((x[i] - c[i]) ** 2 for i in range(len(x)))
+            s = -self.G * M / (r2 + a * a) ** 1.5
+            for i in range(len(x)):
+                out[i] = out[i] + s * (x[i] - c[i])
+        return tuple(out)
+
+
+class Gaussian(Problem):
+    """Manufactured Phi = exp(-r^2/s^2); 4 pi G rho = lap(Phi) = Phi (4 r^2/s^4 - 2d/s^2)."""
+
+    def __init__(self, s: float = 0.1, G: float = 1.0):
+        self.s, self.G = s, G
+
+    def phi(self, *x):
+        r2 = sum(xi * xi for xi in x)
+        return torch.exp(-r2 / self.s ** 2)
+
+    def rho(self, *x):
+        d = len(x)
+        r2 = sum(xi * xi for xi in x)
+        lap = torch.exp(-r2 / self.s ** 2) * (4 * r2 / self.s ** 4 - 2 * d / self.s ** 2)
+        return lap / (4 * math.pi * self.G)
+
+    def force(self, *x):
+        ph = self.phi(*x)
+        return tuple(2 * xi / self.s ** 2 * ph for xi in x)
+
+
+class Linear(Problem):
+    """rho = 0, Phi = a.x + b: the interpolation and the Laplacian are exact on it."""
+
+    def __init__(self, grad: Sequence[float], const: float = 0.0, G: float = 1.0):
+        self.g = tuple(float(v) for v in grad)
+        self.c = const
+        self.G = G
+
+    def rho(self, *x):
+        return torch.zeros_like(x[0])
+
+    def phi(self, *x):
+        return self.c + sum(self.g[i] * x[i] for i in range(len(x)))
+
+    def force(self, *x):
+        return tuple(torch.full_like(x[0], -self.g[i]) for i in range(len(x)))
+
+
+class Quadratic(Problem):
+    """Phi = |x|^2 (+ const); lap Phi = 2d exactly, also for the discrete Laplacian."""
+
+    def __init__(self, dim: int, G: float = 1.0, const: float = 0.0):
+        self.d, self.G, self.c = dim, G, const
+
+    def rho(self, *x):
+        return torch.full_like(x[0], 2.0 * self.d / (4 * math.pi * self.G))
+
+    def phi(self, *x):
+        return self.c + sum(xi * xi for xi in x)
+
+    def force(self, *x):
+        return tuple(-2 * xi for xi in x)
+
+
+# ------------------------------------------------------------------ inputs
+def make_inputs(geom: Geometry, prob: Problem, device="cpu"):
+    """Caller inputs of a nested solve.
+
+    rho[0]   : (n0+2)^d   Omega^0 plus its inner buffer layer
+    rho[l>=1]: n_l^d      Omega^l
+    phi_outer: (n0+4)^d   closed-form potential (only its outer layer is used)
+    """
+    rho = []
+    for l in range(geom.nlevels):
+        n = geom.n[l]
+        if l == 0:
+            x = geom.mesh(0, -1, n + 2, device)
+        else:
+            x = geom.mesh(l, 0, n, device)
+        rho.append(prob.rho(*x).contiguous())
+    x = geom.mesh(0, -2, geom.n[0] + 4, device)
+    phi_outer = prob.phi(*x).contiguous()
+    return rho, phi_outer
+
+
+# ------------------------------------------------------------------ configs
+def sphere_draw(seed: int):
+    """Seeded 1..8 Plummer spheres: centres U[-0.4,0.4]^3, M ~ lognormal(0, 0.5),
+    a ~ U[0.02, 0.1]; draw order K, centres, masses, radii."""
+    rng = np.random.default_rng(seed)
+    K = int(rng.integers(1, 9))
+    cen = rng.uniform(-0.4, 0.4, size=(K, 3))
+    M = rng.lognormal(mean=0.0, sigma=0.5, size=K)
+    a = rng.uniform(0.02, 0.1, size=K)
+    return [(float(M[i]), float(a[i]), tuple(float(v) for v in cen[i])) for i in range(K)]
+
+
+@dataclass
+class Workload:
+    name: str
+    geom: Geometry
+    prob: Problem
+    note: str = ""
+    extra: dict = field(default_factory=dict)
+
+
+def c1_gaussian_2d(N: int = 64) -> Workload:
+    """2-D Gaussian manufactured solution on [-1,1]^2, N^2 base cells, one
+    nested level at twice the resolution over [-0.5,0.5]^2 (N^2 cells)."""
+    g = Geometry(dim=2, n=[N, N], off=[(0, 0, 0), (N // 4, N // 4, 0)], lo0=(-1.0, -1.0, 0.0), dx0=2.0 / N, G=1.0)
+    return Workload("gaussian2d_2lev_%d" % N, g, Gaussian(0.1, 1.0))
+
+
+def c2_plummer(N: int = 128, nlevels: int = 3) -> Workload:
+    """3-D Plummer M=1, a=0.05 at the origin; domain [-1,1]^3; levels of N^3
+    cells at 2x refinement, level k covering [-2^-k, 2^-k]^3."""
+    g = centred_geometry(3, nlevels, N, 1.0, 1.0)
+    return Workload("plummer_%dlev_%d" % (nlevels, N), g, Plummer([(1.0, 0.05, (0, 0, 0))]))
+
+
+def c3_plummer_offset(N: int = 256, nlevels: int = 4) -> Workload:
+    """Plummer a=0.02 (M=1) offset to (0.1,-0.05,0.03); 4 levels of N^3."""
+    g = centred_geometry(3, nlevels, N, 1.0, 1.0)
+    return Workload("plummer_offset_%dlev_%d" % (nlevels, N), g, Plummer([(1.0, 0.02, (0.1, -0.05, 0.03))]))
+
+
+def c4_multi_plummer(seed: int, N: int = 128, nlevels: int = 3) -> Workload:
+    g = centred_geometry(3, nlevels, N, 1.0, 1.0)
+    return Workload("multi_plummer_seed%d_%dlev_%d" % (seed, nlevels, N), g, Plummer(sphere_draw(seed)),
+                    extra=dict(seed=seed))
+
+
+def c5_two_plummer(N: int = 512, nlevels: int = 5) -> Workload:
+    """Two Plummer spheres: M=1, a=0.03 at the origin and M=0.3, a=0.015 at
+    (0.2, 0, 0); 5 levels of N^3 cells."""
+    g = centred_geometry(3, nlevels, N, 1.0, 1.0)
+    return Workload("two_plummer_%dlev_%d" % (nlevels, N), g,
+                    Plummer([(1.0, 0.03, (0, 0, 0)), (0.3, 0.015, (0.2, 0.0, 0.0))]))
+
+
+def paper2d(N: int, nlevels: int = 4) -> Workload:
+    """Sec. 3.1 setup: Omega^0 = [-0.5,0.5]^2, levels 0..3, N cells per axis each."""
+    p = Paper2D(0.3)
+    g = centred_geometry(2, nlevels, N, 0.5, p.G)
+    return Workload("paper2d_%d" % N, g, p)
+
+
+def paper3d(N: int, nlevels: int = 3) -> Workload:
+    """Sec. 3.2 setup: Omega^0 = [-0.5,0.5]^3, levels 0..2, N cells per axis each."""
+    p = Paper3D(1.0, 0.25)
+    g = centred_geometry(3, nlevels, N, 0.5, p.G)
+    return Workload("paper3d_%d" % N, g, p)

@@ -1,0 +1,187 @@
+"""Pins of the oracle's nested solve (no GPU): the direct solve of the nested
+discrete system, closed-form interface cases, second-order convergence and the
+paper's Tables 1-2."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from conftest import read_table
+from oracle import core, dense, norms
+from paper_2001_02327_amd import workloads as W
+
+
+def _inputs(wl):
+    rho, po = W.make_inputs(wl.geom, wl.prob)
+    return [r.numpy() for r in rho], po.numpy()
+
+
+# ------------------------------------------------------------ fixed point
+@pytest.mark.parametrize("wl", [W.paper2d(8), W.c1_gaussian_2d(16), W.paper3d(8), W.c2_plummer(8),
+                                W.c4_multi_plummer(3, N=8)], ids=lambda w: w.name)
+def test_multigrid_reaches_the_direct_solution(wl):
+    """The V-cycle iteration converges to the exact solution of the nested
+    discrete system (direct sparse solve, interpolation from coordinates)."""
+    rho, po = _inputs(wl)
+    res = core.solve(wl.geom, rho, po, tol=1e-13, max_cycles=80)
+    assert res["status"] in (0, -3)
+    ex, _ = dense.solve(wl.geom, rho, po)
+    for l in range(wl.geom.nlevels):
+        err = np.abs(res["phi"][l] - ex[l]).max() / np.abs(ex[l]).max()
+        assert err < 1e-11, (l, err)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_linear_potential_is_exact_on_every_level(dim):
+    """rho = 0, Phi = a.x + b: interpolation (App. A) and the Laplacian are exact,
+    so every level reproduces Phi at its centres and F = -a everywhere; the
+    interpolated initial guess of levels l >= 1 is already converged."""
+    N = 8
+    geom = W.centred_geometry(dim, 3, N, 0.5, 1.0)
+    prob = W.Linear([0.7, -1.3, 0.4][:dim], 2.0)
+    rho, po = W.make_inputs(geom, prob)
+    res = core.solve(geom, [r.numpy() for r in rho], po.numpy(), tol=1e-13, max_cycles=60)
+    assert res["status"] == 0
+    for l in range(geom.nlevels):
+        x = geom.mesh(l, -2, N + 4)
+        want = prob.phi(*x).numpy()
+        np.testing.assert_allclose(res["phi"][l], want, rtol=0, atol=2e-11)
+        F = core.forces(dim, geom.dx(l), res["phi"][l])
+        for a in range(dim):
+            np.testing.assert_allclose(F[a], -prob.g[a], rtol=0, atol=1e-9)
+        if l > 0:
+            assert res["cycles"][l] == 0
+
+
+def test_quadratic_potential_nested():
+    """Phi = |x|^2 with constant density.  The Laplacian is exact on it, so
+    level 0 is exact.  Linear interpolation at the quarter points (App. A)
+    overestimates x^2 by exactly (1/4)(3/4) H^2 = 3 H^2/16 per axis (H = coarse
+    cell), so level 1's boundary data are |x|^2 + 3 d H^2/16 and its discrete
+    solution is exactly that constant shift of |x|^2."""
+    dim, N = 3, 8
+    geom = W.centred_geometry(dim, 2, N, 0.5, 1.0)
+    prob = W.Quadratic(dim)
+    rho, po = W.make_inputs(geom, prob)
+    res = core.solve(geom, [r.numpy() for r in rho], po.numpy(), tol=1e-13, max_cycles=80)
+    x = geom.mesh(0, -2, N + 4)
+    np.testing.assert_allclose(res["phi"][0], prob.phi(*x).numpy(), rtol=0, atol=1e-12)
+    x = geom.mesh(1, -2, N + 4)
+    H = geom.dx(0)
+    np.testing.assert_allclose(res["phi"][1], prob.phi(*x).numpy() + 3 * dim * H * H / 16, rtol=0, atol=1e-12)
+
+
+# ------------------------------------------------------------ accuracy vs the paper
+def _paper_errors(wl, stop_rule=1):
+    geom, prob = wl.geom, wl.prob
+    rho, po = _inputs(wl)
+    res = core.solve(geom, rho, po, tol=1e-10, stop_rule=stop_rule, max_cycles=80)
+    assert res["status"] == 0
+    ex, er = [], []
+    for l in range(geom.nlevels):
+        F = core.forces(geom.dim, geom.dx(l), res["phi"][l])
+        x = geom.mesh(l, 0, geom.n[l])
+        Fa = [a.numpy() for a in prob.force(*x)]
+        ex.append(F[0] - Fa[0])
+        xs = [a.numpy() for a in x]
+        if geom.dim == 2:
+            er.append(np.hypot(F[0], F[1]) - prob.fR(*x).numpy())
+        else:
+            r = np.sqrt(sum(a * a for a in xs))
+            fr = sum(F[a] * xs[a] for a in range(3)) / r
+            er.append(fr - prob.fr(*x).numpy())
+    return norms.composite_norms(geom, ex) + norms.composite_norms(geom, er), res
+
+
+def _check_table(table, Ns, make):
+    rows = {int(r[0]): [float(v) for v in r[1:]] for r in read_table(table)}
+    got = {}
+    for N in Ns:
+        errs, res = _paper_errors(make(N))
+        got[N] = errs
+        ratio = np.array(errs) / np.array(rows[N])
+        # soft pin: the paper leaves the base-level boundary data and the norm
+        # details unstated; magnitudes agree within 25 %
+        assert np.all(ratio > 0.8) and np.all(ratio < 1.25), (N, ratio)
+    for a, b in zip(Ns[:-1], Ns[1:]):
+        o = [norms.order(x, y) for x, y in zip(got[a], got[b])]
+        if a >= 32:
+            assert min(o) > 1.85, (a, b, o)
+    return got
+
+
+def test_table1_paper2d():
+    """Table 1 (Sec. 3.1): errors of f_x and f_R within 25 % of the printed
+    values, second order between successive N."""
+    _check_table("table1_paper2d.txt", [8, 16, 32, 64, 128, 256], W.paper2d)
+
+
+def test_table2_paper3d():
+    """Table 2 (Sec. 3.2): errors of f_x and f_r within 25 % of the printed values."""
+    _check_table("table2_paper3d.txt", [8, 16, 32, 64], W.paper3d)
+
+
+def test_paper_iteration_counts_independent_of_N():
+    """Sec. 3.1: with the interpolated initial guess the number of V-cycles to
+    max|f^q - f^{q-1}| < 1e-10 on the refined levels is small and does not grow with N."""
+    counts = []
+    for N in [32, 64, 128, 256]:
+        _, res = _paper_errors(W.paper2d(N))
+        counts.append(res["cycles"][1:])
+    counts = np.array(counts)
+    assert counts.max() <= 16
+    assert np.all(np.diff(counts, axis=0) <= 1)
+
+
+# ------------------------------------------------------------ grid-doubling order
+def _order_run(make, Ns):
+    out = []
+    for N in Ns:
+        wl = make(N)
+        geom, prob = wl.geom, wl.prob
+        rho, po = _inputs(wl)
+        res = core.solve(geom, rho, po, tol=1e-10, max_cycles=80)
+        assert res["status"] == 0
+        ef, ep = [], []
+        for l in range(geom.nlevels):
+            F = core.forces(geom.dim, geom.dx(l), res["phi"][l])
+            x = geom.mesh(l, 0, geom.n[l])
+            Fa = [a.numpy() for a in prob.force(*x)]
+            ef.append(np.sqrt(sum((F[a] - Fa[a]) ** 2 for a in range(geom.dim))))
+            sl = (slice(2, -2),) * geom.dim
+            ep.append(res["phi"][l][sl] - prob.phi(*x).numpy())
+        out.append((norms.composite_norms(geom, ef), norms.composite_norms(geom, ep)))
+    return out
+
+
+@pytest.mark.parametrize("make,Ns", [
+    (W.c1_gaussian_2d, [64, 128, 256]),
+    (lambda N: W.c2_plummer(N), [64, 128]),
+], ids=["gaussian2d", "plummer3d"])
+def test_second_order_under_grid_doubling(make, Ns):
+    """Second order of Phi and |F| in L1, L2 and Linf (abstract, Sec. 3)."""
+    out = _order_run(make, Ns)
+    for (fa, pa), (fb, pb) in zip(out[:-1], out[1:]):
+        for x, y in list(zip(fa, fb)) + list(zip(pa, pb)):
+            assert norms.order(x, y) > 1.75, (fa, fb, pa, pb)
+
+
+def test_interface_error_not_spiking():
+    """Fig. 3 / Sec. 3.1: no spurious force spike next to a coarse-fine
+    interface: the max error within two cells of the edge of Omega^l is at most
+    twice the max error elsewhere on the same level."""
+    wl = W.paper2d(128)
+    geom, prob = wl.geom, wl.prob
+    rho, po = _inputs(wl)
+    res = core.solve(geom, rho, po, tol=1e-10, max_cycles=80)
+    for l in range(1, geom.nlevels):
+        F = core.forces(2, geom.dx(l), res["phi"][l])
+        x = geom.mesh(l, 0, geom.n[l])
+        Fa = [a.numpy() for a in prob.force(*x)]
+        e = np.hypot(F[0] - Fa[0], F[1] - Fa[1])
+        edge = np.zeros_like(e, dtype=bool)
+        edge[:2, :] = edge[-2:, :] = edge[:, :2] = edge[:, -2:] = True
+        covered = ~norms.uncovered_mask(geom, l)
+        rest = ~edge & ~covered
+        assert e[edge].max() <= 2.0 * e[rest].max(), (l, e[edge].max(), e[rest].max())
