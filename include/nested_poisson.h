@@ -1,0 +1,177 @@
+/*
+ * nested_poisson.h -- C ABI of the MI355X (gfx950) nested-grid multigrid
+ * self-gravity solver.
+ *
+ * Method: H.-H. Wang & C.-C. Yen, "Self-gravitational Force Calculation of
+ * Second Order Accuracy Using Multigrid Method on Nested Grids"
+ * (arXiv:2001.02327).  The solver computes the potential of
+ *     lap(Phi) = 4 pi G rho          (Sec. 1, first equation)
+ * on a stack of nested Cartesian patches with refinement ratio 2 (Sec. 2.1),
+ * level by level from coarse to fine (one-way interface scheme), and the
+ * forces F = -grad(Phi) with the fourth-order central difference
+ * (Eqn:force_evaluation).
+ *
+ * Geometry (Sec. 2.1).  Level l is a cube (square in 2-D) of n[l] cells per
+ * axis with cell size dx0 / 2^l.  For l >= 1 its lower corner lies
+ * offset[l][a] cells of level l-1 above the lower corner of level l-1 along
+ * axis a; it must keep at least one coarse cell of margin on every side:
+ *     1 <= offset[l][a]  and  offset[l][a] + n[l]/2 <= n[l-1] - 1.
+ * Each level carries a two-cell buffer.  Its padded array has n[l] + 4
+ * points per axis: index 0 and n+3 are the outer buffer layer (Dirichlet
+ * potential), 1 and n+2 the inner buffer layer (relaxed together with the
+ * patch), 2..n+1 the patch itself.  Cell i of the patch is centred at
+ * lo_l + (i + 1/2) dx_l.
+ *
+ * Memory.  Every array crossing this ABI is row-major with x fastest
+ * ([k][j][i] in 3-D, [j][i] in 2-D), FP64, in DEVICE memory of the device
+ * that was current at create time.  The library allocates and owns all of
+ * its working storage; the caller owns every pointer it passes and must keep
+ * it valid until the call returns (solve) or until the work queued on the
+ * handle's stream has completed (forces, potential).
+ *
+ * Errors.  Every function returns 0 on success or a negative NP_E* code; no
+ * C++ exception or abort crosses the ABI.  nested_poisson_last_error() gives a
+ * message for the last failure on a handle.  A handle is not thread-safe:
+ * use one handle per host thread and stream.
+ */
+#ifndef NESTED_POISSON_H
+#define NESTED_POISSON_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NP_MAX_LEVELS 8   /* nested refinement levels per solver */
+#define NP_MAX_MG 32      /* multigrid levels per patch */
+#define NP_MAX_CYCLES 200 /* cap on max_cycles */
+
+/* return codes */
+#define NP_OK 0
+#define NP_EINVAL (-1)      /* invalid argument or geometry */
+#define NP_ENOMEM (-2)      /* device or host allocation failed */
+#define NP_EHIP (-3)        /* a HIP runtime call failed */
+#define NP_ENONFINITE (-4)  /* NaN/Inf in the input or the residual */
+#define NP_ENOTCONV (-5)    /* max_cycles reached; the potential is still valid */
+#define NP_EDIVERGED (-6)   /* residual grew beyond 1e3 x its initial value */
+#define NP_ESTATE (-7)      /* call out of order (e.g. forces before solve) */
+#define NP_ENODEV (-8)      /* no HIP device available */
+
+/* stop rules (Sec. 2.3 step 14 and Sec. 3.1) */
+#define NP_STOP_RESIDUAL 0    /* ||f - lap Phi||_inf <= tol * ||f||_inf on the patch and its inner layer */
+#define NP_STOP_FORCE_DELTA 1 /* max over the patch of |F^q - F^{q-1}| < tol (the paper's rule) */
+
+/* arithmetic of the V-cycles */
+#define NP_PREC_FP64 0     /* every operator in FP64 */
+#define NP_PREC_FP32_DC 1  /* FP32 V-cycles inside FP64 defect correction */
+#define NP_PREC_FP16S_DC 2 /* FP16-stored, FP32-computed finest-level V-cycle arrays inside FP64 defect correction */
+
+/* initial guess of levels l >= 1 */
+#define NP_GUESS_INTERP 0  /* interpolated from level l-1 (Sec. 2.4) */
+#define NP_GUESS_LEARNED 1 /* interpolated guess plus the correction predicted by the conv net */
+
+typedef struct np_config {
+    int dim;                        /* 2 or 3 */
+    int nlevels;                    /* 1..NP_MAX_LEVELS */
+    int n[NP_MAX_LEVELS];           /* cells per axis of level l: even, >= 4 */
+    int offset[NP_MAX_LEVELS][3];   /* l >= 1: corner offset in cells of level l-1 (see above) */
+    double dx0;                     /* cell size of level 0, > 0 */
+    double G;                       /* gravitational constant */
+    int n_pre;                      /* pre-smoothing sweeps (the paper uses 2), 0..16 */
+    int n_post;                     /* post-smoothing sweeps (the paper uses 1), 0..16 */
+    double tol;                     /* stop tolerance, > 0 */
+    int max_cycles;                 /* 1..NP_MAX_CYCLES */
+    int stop_rule;                  /* NP_STOP_* */
+    int precision;                  /* NP_PREC_* */
+    int inner_cycles;               /* low-precision V-cycles per defect-correction step, 1..8 */
+    int guess;                      /* NP_GUESS_* */
+} np_config;
+
+/* Fills `cfg` with the paper's solver settings (N_pre = 2, N_post = 1,
+ * Sec. 3) and tol = 1e-10, max_cycles = 50, FP64, residual stop,
+ * interpolated guess.  Geometry fields are zeroed. */
+void nested_poisson_default_config(np_config* cfg);
+
+/* Multigrid hierarchy of one patch (Sec. 2.2): N^0 = n + 2 (patch plus its
+ * inner buffer layer), N^L = round(N^0 / 2^L) with halves rounded up, until
+ * N^L = 1.  For L >= 1, right-ghost rule of Sec. 2.4: xn_is_one[L] is 1 when
+ * the right-most active centre sits exactly at x_MG = 1 (ghost = -e_{N-1}),
+ * otherwise ghost = ghost_coef[L] * e_N, the value at x_N + h^L of the line
+ * through (x_N, e_N) that vanishes at x_MG = 1. */
+typedef struct np_plan {
+    int nmg[NP_MAX_LEVELS];                   /* multigrid levels of each nested level */
+    int N[NP_MAX_LEVELS][NP_MAX_MG];          /* active cells per axis */
+    int xn_is_one[NP_MAX_LEVELS][NP_MAX_MG];
+    double ghost_coef[NP_MAX_LEVELS][NP_MAX_MG];
+} np_plan;
+
+/* Validates `cfg` and computes the hierarchy on the host; touches no device.
+ * Returns NP_EINVAL for an invalid configuration. */
+int nested_poisson_plan(const np_config* cfg, np_plan* out);
+
+typedef struct np_solver np_solver;
+
+/* Creates a solver on the current HIP device.  `hip_stream` is a hipStream_t
+ * (NULL = the null stream); all device work of the handle is queued on it.
+ * Allocates the per-level potential and right-hand side and the multigrid
+ * scratch.  Errors: NP_EINVAL (cfg invalid; checked before any device call),
+ * NP_ENODEV, NP_ENOMEM, NP_EHIP. */
+int nested_poisson_create(const np_config* cfg, void* hip_stream, np_solver** out);
+
+/* Nested solve (Sec. 2.1 one-way scheme, Sec. 2.3 V-cycle).
+ *   rho[0]    : (n0+2)^d density of level 0 including its inner buffer layer
+ *   rho[l>=1] : n_l^d density of level l (the inner buffer layer of l >= 1
+ *               gets the density interpolated from level l-1)
+ *   phi_outer : (n0+4)^d; only the outer layer is read (Dirichlet data of
+ *               level 0)
+ * Level 0 starts from Phi = 0; level l >= 1 from the potential interpolated
+ * from level l-1 (plus the learned correction with NP_GUESS_LEARNED).
+ * Returns after the last stop test of the finest level (host-synchronous).
+ * `stats` may be NULL.  Errors: NP_EINVAL, NP_ENONFINITE, NP_ENOTCONV (the
+ * cap was hit on some level; results are valid), NP_EDIVERGED, NP_EHIP. */
+typedef struct np_stats {
+    int cycles[NP_MAX_LEVELS];                /* V-cycles (outer steps for DC) per level */
+    double initial_rel_residual[NP_MAX_LEVELS];
+    double final_rel_residual[NP_MAX_LEVELS]; /* ||r||_inf / scale at exit */
+    double scale[NP_MAX_LEVELS];              /* reference norm of the stop test */
+    double level_ms[NP_MAX_LEVELS];           /* host wall time per level */
+    double total_ms;
+} np_stats;
+int nested_poisson_solve(np_solver* s, const double* const* rho, const double* phi_outer, np_stats* stats);
+
+/* Runs exactly cycles[l] V-cycles on level l instead of the stop rule
+ * (cycles[l] < 0 keeps the stop rule for that level).  NULL clears.  Used to
+ * compare iterates at equal cycle counts.  The array has nlevels entries. */
+int nested_poisson_set_fixed_cycles(np_solver* s, const int* cycles);
+
+/* Relative residual after each cycle of the last solve on `level`:
+ * out[0] is before the first cycle.  Writes min(cap, cycles+1) values and
+ * returns their count (or a negative error). */
+int nested_poisson_history(const np_solver* s, int level, double* out, int cap);
+
+/* F = -grad(Phi) on the n_l^d cells of level `level` (Eqn:force_evaluation),
+ * written to device arrays fx, fy (and fz in 3-D; ignored in 2-D), each n_l^d.
+ * Queued on the handle's stream; does not synchronise.
+ * Errors: NP_EINVAL (level out of range, null pointer), NP_ESTATE (no solve). */
+int nested_poisson_forces(np_solver* s, int level, double* fx, double* fy, double* fz);
+
+/* Copies the padded (n_l+4)^d potential of `level` into the device array
+ * `phi_padded` (both buffer layers included).  Queued on the stream.
+ * Errors: as nested_poisson_forces. */
+int nested_poisson_potential(np_solver* s, int level, double* phi_padded);
+
+/* Frees every library allocation of the handle.  NULL-safe. */
+void nested_poisson_destroy(np_solver* s);
+
+/* Static text of an NP_* code. */
+const char* nested_poisson_strerror(int code);
+/* Message of the last failure on `s`; with s == NULL, of the last failed
+ * nested_poisson_plan or nested_poisson_create on the calling thread. */
+const char* nested_poisson_last_error(const np_solver* s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NESTED_POISSON_H */

@@ -1,0 +1,146 @@
+"""ctypes declarations of the C ABI in include/nested_poisson.h.
+
+Loads paper_2001_02327_amd/libnested_poisson.so (built in-tree by
+paper_2001_02327_amd/build.py).  There is no fallback: if the library is
+missing every entry point raises.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libnested_poisson.so")
+
+NP_MAX_LEVELS = 8
+NP_MAX_MG = 32
+
+NP_OK = 0
+NP_EINVAL = -1
+NP_ENOMEM = -2
+NP_EHIP = -3
+NP_ENONFINITE = -4
+NP_ENOTCONV = -5
+NP_EDIVERGED = -6
+NP_ESTATE = -7
+NP_ENODEV = -8
+
+STOP_RULES = {"residual": 0, "force_delta": 1}
+PRECISIONS = {"fp64": 0, "fp32_dc": 1, "fp16s_dc": 2}
+GUESSES = {"interp": 0, "learned": 1}
+
+
+class NpConfig(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int),
+        ("nlevels", ctypes.c_int),
+        ("n", ctypes.c_int * NP_MAX_LEVELS),
+        ("offset", (ctypes.c_int * 3) * NP_MAX_LEVELS),
+        ("dx0", ctypes.c_double),
+        ("G", ctypes.c_double),
+        ("n_pre", ctypes.c_int),
+        ("n_post", ctypes.c_int),
+        ("tol", ctypes.c_double),
+        ("max_cycles", ctypes.c_int),
+        ("stop_rule", ctypes.c_int),
+        ("precision", ctypes.c_int),
+        ("inner_cycles", ctypes.c_int),
+        ("guess", ctypes.c_int),
+    ]
+
+
+class NpPlan(ctypes.Structure):
+    _fields_ = [
+        ("nmg", ctypes.c_int * NP_MAX_LEVELS),
+        ("N", (ctypes.c_int * NP_MAX_MG) * NP_MAX_LEVELS),
+        ("xn_is_one", (ctypes.c_int * NP_MAX_MG) * NP_MAX_LEVELS),
+        ("ghost_coef", (ctypes.c_double * NP_MAX_MG) * NP_MAX_LEVELS),
+    ]
+
+
+class NpStats(ctypes.Structure):
+    _fields_ = [
+        ("cycles", ctypes.c_int * NP_MAX_LEVELS),
+        ("initial_rel_residual", ctypes.c_double * NP_MAX_LEVELS),
+        ("final_rel_residual", ctypes.c_double * NP_MAX_LEVELS),
+        ("scale", ctypes.c_double * NP_MAX_LEVELS),
+        ("level_ms", ctypes.c_double * NP_MAX_LEVELS),
+        ("total_ms", ctypes.c_double),
+    ]
+
+
+# every symbol the header declares, with its signature
+_vp = ctypes.c_void_p
+_dp = ctypes.POINTER(ctypes.c_double)
+SIGNATURES = {
+    "nested_poisson_default_config": (None, [ctypes.POINTER(NpConfig)]),
+    "nested_poisson_plan": (ctypes.c_int, [ctypes.POINTER(NpConfig), ctypes.POINTER(NpPlan)]),
+    "nested_poisson_create": (ctypes.c_int, [ctypes.POINTER(NpConfig), _vp, ctypes.POINTER(_vp)]),
+    "nested_poisson_solve": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), _vp, ctypes.POINTER(NpStats)]),
+    "nested_poisson_set_fixed_cycles": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int)]),
+    "nested_poisson_history": (ctypes.c_int, [_vp, ctypes.c_int, _dp, ctypes.c_int]),
+    "nested_poisson_forces": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _vp]),
+    "nested_poisson_potential": (ctypes.c_int, [_vp, ctypes.c_int, _vp]),
+    "nested_poisson_destroy": (None, [_vp]),
+    "nested_poisson_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "nested_poisson_last_error": (ctypes.c_char_p, [_vp]),
+}
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("HIP library %s is not built; run `python -m paper_2001_02327_amd.build` "
+                               "(there is no CPU fallback)" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+class NestedPoissonError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (lib().nested_poisson_strerror(code).decode(), code, msg))
+        self.code = code
+
+
+def make_config(geom, n_pre=2, n_post=1, tol=1e-10, max_cycles=50, stop_rule="residual", precision="fp64",
+                inner_cycles=1, guess="interp"):
+    """np_config from a geometry (attributes dim, n, off, dx0, G) and solver settings."""
+    c = NpConfig()
+    lib().nested_poisson_default_config(ctypes.byref(c))
+    c.dim = int(geom.dim)
+    c.nlevels = len(geom.n)
+    for l, n in enumerate(geom.n):
+        c.n[l] = int(n)
+        off = list(geom.off[l]) + [0, 0, 0]
+        for a in range(3):
+            c.offset[l][a] = int(off[a])
+    c.dx0 = float(geom.dx0)
+    c.G = float(geom.G)
+    c.n_pre, c.n_post = int(n_pre), int(n_post)
+    c.tol = float(tol)
+    c.max_cycles = int(max_cycles)
+    c.stop_rule = STOP_RULES[stop_rule] if isinstance(stop_rule, str) else int(stop_rule)
+    c.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    c.inner_cycles = int(inner_cycles)
+    c.guess = GUESSES[guess] if isinstance(guess, str) else int(guess)
+    return c
+
+
+def plan(cfg):
+    """Validate and plan on the host (no device needed)."""
+    p = NpPlan()
+    rc = lib().nested_poisson_plan(ctypes.byref(cfg), ctypes.byref(p))
+    if rc:
+        raise NestedPoissonError(rc, lib().nested_poisson_last_error(None).decode())
+    out = []
+    for l in range(cfg.nlevels):
+        m = p.nmg[l]
+        out.append(dict(N=[p.N[l][L] for L in range(m)], xn_is_one=[p.xn_is_one[l][L] for L in range(m)],
+                        coef=[p.ghost_coef[l][L] for L in range(m)]))
+    return out

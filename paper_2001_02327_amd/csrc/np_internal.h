@@ -1,0 +1,72 @@
+// Internal declarations of the nested-grid multigrid library (gfx950).
+//
+// Storage: every grid (a nested level's padded array, or one multigrid level)
+// is a cube (square in 2-D) of nx points per axis in "colour-split" form: the
+// red points (even sum of 0-based active indices) and the black points are
+// stored in two separate arrays, each holding hx = (nx+1)/2 points per row:
+//     value(pi, pj, pk) = a[c * cs + (pk * nx + pj) * hx + (pi >> 1)],
+//     c = (pi + pj + pk + dim) & 1          (0 = red),
+// with pi, pj, pk padded indices (0 = ghost / outer buffer layer).  A
+// red-black half sweep then reads one colour and writes the other with unit
+// stride, so one full sweep streams each array once.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace np {
+
+struct SGrid {
+    int nx;     // padded points per axis
+    int hx;     // compact points per row and colour
+    int nz;     // nx in 3-D, 1 in 2-D
+    size_t cs;  // elements per colour array
+};
+
+inline SGrid make_grid(int dim, int nx)
+{
+    SGrid g;
+    g.nx = nx;
+    g.hx = (nx + 1) / 2;
+    g.nz = dim == 3 ? nx : 1;
+    g.cs = (size_t)g.hx * nx * g.nz;
+    return g;
+}
+
+// ------------------------------------------------------------------ launches
+// All launches are asynchronous on `st`.  Grids and sizes are checked by the
+// caller (the runtime) before any launch.
+
+// FP64 level operators (nested-level arrays, multigrid level 0)
+void launch_level0_init(int dim, hipStream_t st, SGrid g, const double* rho0, const double* phi_outer,
+                        double fourpiG, double* phi, double* f);
+void launch_interface_fill(int dim, hipStream_t st, SGrid gc, const double* phic, const double* fc, SGrid gf,
+                           int nf, int offx, int offy, int offz, const double* rho, double fourpiG, double* phif,
+                           double* ff);
+void launch_forces(int dim, hipStream_t st, SGrid g, int n, double dx, const double* phi, double* fx, double* fy,
+                   double* fz);
+void launch_force_delta(int dim, hipStream_t st, SGrid g, int n, double dx, const double* phi, double* F,
+                        unsigned long long* maxbits);
+void launch_export(int dim, hipStream_t st, SGrid g, const double* a, double* out);
+
+// norms over the active points 1..nx-2 (mode 0: |f - lap u|, 1: |f|, 2: |f - lap u| with
+// the active part of u taken as zero); result is max of the bit patterns of |value|
+void launch_norm(int dim, hipStream_t st, SGrid g, const double* u, const double* f, double inv_h2, int mode,
+                 unsigned long long* maxbits);
+void launch_set_u64(hipStream_t st, unsigned long long* p, int count, unsigned long long v);
+
+// multigrid operators, templated on storage type T (double, float)
+template <typename T>
+void launch_half_sweep(int dim, hipStream_t st, SGrid g, T* u, const T* f, int colour, double h2);
+template <typename T>
+void launch_ghost_fill(int dim, hipStream_t st, SGrid g, T* u, int xn_is_one, double coef);
+template <typename T>
+void launch_resid_restrict(int dim, hipStream_t st, SGrid gf, const T* u, const T* f, double inv_h2, SGrid gc,
+                           T* fc, T* ec);
+template <typename T>
+void launch_prolong_add(int dim, hipStream_t st, SGrid gc, const T* ec, SGrid gf, T* u);
+
+}  // namespace np

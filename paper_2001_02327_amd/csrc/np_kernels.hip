@@ -1,0 +1,584 @@
+// HIP kernels of the nested-grid multigrid solver for gfx950 (MI355X).
+//
+// Every kernel is a bandwidth-bound stencil sweep over colour-split storage
+// (see np_internal.h).  One thread handles one compact (h, pj, pk) position;
+// consecutive threads take consecutive h, so each wavefront of 64 lanes reads
+// and writes 64 consecutive elements of a colour array.
+#include "np_internal.h"
+
+namespace np {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+__host__ __device__ inline int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }
+
+template <int D>
+__device__ __forceinline__ int colour_of(int pi, int pj, int pk)
+{
+    return (pi + pj + pk + D) & 1;
+}
+
+__device__ __forceinline__ size_t row_base(const SGrid& g, int pj, int pk)
+{
+    return ((size_t)pk * g.nx + pj) * g.hx;
+}
+
+template <int D, typename T>
+__device__ __forceinline__ T at(const T* __restrict__ a, const SGrid& g, int pi, int pj, int pk)
+{
+    return a[(size_t)colour_of<D>(pi, pj, pk) * g.cs + row_base(g, pj, pk) + (pi >> 1)];
+}
+
+template <int D, typename T>
+__device__ __forceinline__ size_t pos(const SGrid& g, int pi, int pj, int pk)
+{
+    return (size_t)colour_of<D>(pi, pj, pk) * g.cs + row_base(g, pj, pk) + (pi >> 1);
+}
+
+// Maximum of non-negative doubles through their bit patterns: the unsigned
+// order of the patterns is the numeric order, +inf above every finite value
+// and a (positive) NaN above +inf, so NaN and Inf survive the reduction.
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
+{
+    for (int off = 32; off > 0; off >>= 1) {
+        unsigned long long o = __shfl_xor(v, off, 64);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ void block_max_to(unsigned long long v, unsigned long long* out)
+{
+    __shared__ unsigned long long red[kBlock / 64];
+    v = wave_max_u64(v);
+    int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long m = red[0];
+        for (int w = 1; w < kBlock / 64; w++) m = red[w] > m ? red[w] : m;
+        atomicMax(out, m);
+    }
+}
+
+__device__ __forceinline__ unsigned long long abs_bits(double a)
+{
+    return (unsigned long long)__double_as_longlong(fabs(a));
+}
+
+// ------------------------------------------------------------------ level setup
+// Level 0: potential = caller's outer layer on the ring, zero on Gamma^0;
+// right-hand side = 4 pi G rho on Gamma^0 (caller gives Omega^0 plus its inner
+// layer, (n+2)^d points).
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_level0_init(SGrid g, const double* __restrict__ rho0,
+                                                        const double* __restrict__ phi_outer, double fourpiG,
+                                                        double* __restrict__ phi, double* __restrict__ f)
+{
+    long t = (long)blockIdx.x * kBlock + threadIdx.x;
+    long total = (long)g.nx * g.nx * g.nz;
+    if (t >= total) return;
+    int pi = (int)(t % g.nx);
+    long r = t / g.nx;
+    int pj = (int)(r % g.nx);
+    int pk = (int)(r / g.nx);
+    int last = g.nx - 1;
+    bool ring = pi == 0 || pi == last || pj == 0 || pj == last || (D == 3 && (pk == 0 || pk == last));
+    size_t p = pos<D, double>(g, pi, pj, pk);
+    if (ring) {
+        phi[p] = phi_outer[t];
+        f[p] = 0.0;
+    } else {
+        int m = g.nx - 2;
+        size_t ri = D == 3 ? (((size_t)(pk - 1) * m + (pj - 1)) * m + (pi - 1)) : ((size_t)(pj - 1) * m + (pi - 1));
+        phi[p] = 0.0;
+        f[p] = fourpiG * rho0[ri];
+    }
+}
+
+// Interpolation weight pair along one axis for fine padded index p of a
+// level whose corner sits `off` coarse cells into the coarse patch: the fine
+// cell p-2 lies in coarse cell off + floor((p-2)/2) (padded q = that + 2);
+// the second coarse point is on the side of the fine centre.
+__device__ __forceinline__ void fine_to_coarse(int p, int off, int& q, int& s)
+{
+    int fine = p - 2;
+    q = off + 2 + (fine >> 1);  // arithmetic shift = floor for negatives
+    s = (fine & 1) ? 1 : -1;
+}
+
+template <int D>
+__device__ __forceinline__ double interp_tensor(const double* __restrict__ c, const SGrid& gc, int qi, int qj, int qk,
+                                                int si, int sj, int sk)
+{
+    const double w0 = 0.75, w1 = 0.25;
+    double y0 = w0 * at<D>(c, gc, qi, qj, qk) + w1 * at<D>(c, gc, qi + si, qj, qk);
+    double y1 = w0 * at<D>(c, gc, qi, qj + sj, qk) + w1 * at<D>(c, gc, qi + si, qj + sj, qk);
+    double z0 = w0 * y0 + w1 * y1;
+    if (D == 2) return z0;
+    double y2 = w0 * at<D>(c, gc, qi, qj, qk + sk) + w1 * at<D>(c, gc, qi + si, qj, qk + sk);
+    double y3 = w0 * at<D>(c, gc, qi, qj + sj, qk + sk) + w1 * at<D>(c, gc, qi + si, qj + sj, qk + sk);
+    double z1 = w0 * y2 + w1 * y3;
+    return w0 * z0 + w1 * z1;
+}
+
+// Level l >= 1 from level l-1: potential everywhere (outer layer = Dirichlet
+// data, rest = initial guess) and right-hand side of the inner layer
+// interpolated; Omega^l takes 4 pi G rho from the caller (n^d points).
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_interface_fill(SGrid gc, const double* __restrict__ phic,
+                                                           const double* __restrict__ fc, SGrid gf, int nf, int offx,
+                                                           int offy, int offz, const double* __restrict__ rho,
+                                                           double fourpiG, double* __restrict__ phif,
+                                                           double* __restrict__ ff)
+{
+    long t = (long)blockIdx.x * kBlock + threadIdx.x;
+    long total = (long)gf.nx * gf.nx * gf.nz;
+    if (t >= total) return;
+    int pi = (int)(t % gf.nx);
+    long r = t / gf.nx;
+    int pj = (int)(r % gf.nx);
+    int pk = (int)(r / gf.nx);
+    int qi, qj, qk = 0, si, sj, sk = 1;
+    fine_to_coarse(pi, offx, qi, si);
+    fine_to_coarse(pj, offy, qj, sj);
+    if (D == 3) fine_to_coarse(pk, offz, qk, sk);
+    size_t p = pos<D, double>(gf, pi, pj, pk);
+    phif[p] = interp_tensor<D>(phic, gc, qi, qj, qk, si, sj, sk);
+    int last = gf.nx - 1;
+    bool outer = pi == 0 || pi == last || pj == 0 || pj == last || (D == 3 && (pk == 0 || pk == last));
+    bool omega = pi >= 2 && pi <= nf + 1 && pj >= 2 && pj <= nf + 1 && (D == 2 || (pk >= 2 && pk <= nf + 1));
+    double v;
+    if (outer) {
+        v = 0.0;
+    } else if (omega) {
+        size_t ri = D == 3 ? (((size_t)(pk - 2) * nf + (pj - 2)) * nf + (pi - 2)) : ((size_t)(pj - 2) * nf + (pi - 2));
+        v = fourpiG * rho[ri];
+    } else {
+        v = interp_tensor<D>(fc, gc, qi, qj, qk, si, sj, sk);
+    }
+    ff[p] = v;
+}
+
+// ------------------------------------------------------------------ forces
+// F = -grad Phi with the fourth-order central difference:
+// dPhi/dx = [8 (Phi_{i+1} - Phi_{i-1}) - (Phi_{i+2} - Phi_{i-2})] / (12 dx).
+template <int D>
+__device__ __forceinline__ double d4(const double* __restrict__ phi, const SGrid& g, int pi, int pj, int pk, int ax,
+                                     double m12dx)
+{
+    int e[3] = {0, 0, 0};
+    e[ax] = 1;
+    double p1 = at<D>(phi, g, pi + e[0], pj + e[1], pk + e[2]);
+    double m1 = at<D>(phi, g, pi - e[0], pj - e[1], pk - e[2]);
+    double p2 = at<D>(phi, g, pi + 2 * e[0], pj + 2 * e[1], pk + 2 * e[2]);
+    double m2 = at<D>(phi, g, pi - 2 * e[0], pj - 2 * e[1], pk - 2 * e[2]);
+    return (8.0 * (p1 - m1) - (p2 - m2)) * m12dx;
+}
+
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_forces(SGrid g, int n, double m12dx, const double* __restrict__ phi,
+                                                   double* __restrict__ fx, double* __restrict__ fy,
+                                                   double* __restrict__ fz)
+{
+    long t = (long)blockIdx.x * kBlock + threadIdx.x;
+    long total = D == 3 ? (long)n * n * n : (long)n * n;
+    if (t >= total) return;
+    int i = (int)(t % n);
+    long r = t / n;
+    int j = (int)(r % n);
+    int k = (int)(r / n);
+    int pi = i + 2, pj = j + 2, pk = D == 3 ? k + 2 : 0;
+    fx[t] = d4<D>(phi, g, pi, pj, pk, 0, m12dx);
+    fy[t] = d4<D>(phi, g, pi, pj, pk, 1, m12dx);
+    if (D == 3) fz[t] = d4<D>(phi, g, pi, pj, pk, 2, m12dx);
+}
+
+// Forces into F (d arrays of n^d) and the maximum change against the values
+// F held before (the stop rule of Sec. 3.1).
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_force_delta(SGrid g, int n, double m12dx, const double* __restrict__ phi,
+                                                        double* __restrict__ F, unsigned long long* maxbits)
+{
+    long t = (long)blockIdx.x * kBlock + threadIdx.x;
+    long total = D == 3 ? (long)n * n * n : (long)n * n;
+    unsigned long long m = 0;
+    if (t < total) {
+        int i = (int)(t % n);
+        long r = t / n;
+        int j = (int)(r % n);
+        int k = (int)(r / n);
+        int pi = i + 2, pj = j + 2, pk = D == 3 ? k + 2 : 0;
+        for (int ax = 0; ax < D; ax++) {
+            double v = d4<D>(phi, g, pi, pj, pk, ax, m12dx);
+            double old = F[ax * total + t];
+            F[ax * total + t] = v;
+            unsigned long long b = abs_bits(v - old);
+            m = b > m ? b : m;
+        }
+    }
+    block_max_to(m, maxbits);
+}
+
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_export(SGrid g, const double* __restrict__ a, double* __restrict__ out)
+{
+    long t = (long)blockIdx.x * kBlock + threadIdx.x;
+    long total = (long)g.nx * g.nx * g.nz;
+    if (t >= total) return;
+    int pi = (int)(t % g.nx);
+    long r = t / g.nx;
+    int pj = (int)(r % g.nx);
+    int pk = (int)(r / g.nx);
+    out[t] = at<D>(a, g, pi, pj, pk);
+}
+
+// ------------------------------------------------------------------ norms
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_norm(SGrid g, const double* __restrict__ u, const double* __restrict__ f,
+                                                 double inv_h2, int mode, unsigned long long* maxbits)
+{
+    long t = (long)blockIdx.x * kBlock + threadIdx.x;
+    int m = g.nx - 2;
+    long total = (long)g.hx * m * (D == 3 ? m : 1);
+    unsigned long long best = 0;
+    if (t < total) {
+        int h = (int)(t % g.hx);
+        long r = t / g.hx;
+        int pj = 1 + (int)(r % m);
+        int pk = D == 3 ? 1 + (int)(r / m) : 0;
+        size_t row = row_base(g, pj, pk);
+        size_t ny = (size_t)g.hx, nz = (size_t)g.nx * g.hx;
+        for (int c = 0; c < 2; c++) {
+            int pi = 2 * h + ((c + pj + pk + D) & 1);
+            if (pi < 1 || pi > g.nx - 2) continue;
+            const double* o = u + (size_t)(c ^ 1) * g.cs;
+            size_t self = (size_t)c * g.cs + row + h;
+            double val;
+            if (mode == 1) {
+                val = f[self];
+            } else {
+                double s = o[row + ((pi - 1) >> 1)];
+                s = s + o[row + ((pi + 1) >> 1)];
+                s = s + o[row - ny + h];
+                s = s + o[row + ny + h];
+                if (D == 3) {
+                    s = s + o[row - nz + h];
+                    s = s + o[row + nz + h];
+                }
+                double uc = u[self];
+                if (mode == 2) {
+                    // interior zero: keep only neighbours on the ghost layer
+                    s = 0.0;
+                    if (pi - 1 == 0) s += o[row + ((pi - 1) >> 1)];
+                    if (pi + 1 == g.nx - 1) s += o[row + ((pi + 1) >> 1)];
+                    if (pj - 1 == 0) s += o[row - ny + h];
+                    if (pj + 1 == g.nx - 1) s += o[row + ny + h];
+                    if (D == 3 && pk - 1 == 0) s += o[row - nz + h];
+                    if (D == 3 && pk + 1 == g.nx - 1) s += o[row + nz + h];
+                    uc = 0.0;
+                }
+                val = f[self] - (s - (2.0 * D) * uc) * inv_h2;
+            }
+            unsigned long long b = abs_bits(val);
+            best = b > best ? b : best;
+        }
+    }
+    block_max_to(best, maxbits);
+}
+
+__global__ void k_set_u64(unsigned long long* p, int count, unsigned long long v)
+{
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < count) p[t] = v;
+}
+
+// ------------------------------------------------------------------ multigrid
+template <typename T>
+struct Compute { using type = T; };
+template <>
+struct Compute<__half> { using type = float; };
+
+// Red-black Gauss-Seidel half sweep: u_c = (sum of the 2d neighbours - h^2 f_c) / (2d)
+// over the active points of one colour; the neighbours are all of the other colour.
+template <int D, typename T>
+__global__ void __launch_bounds__(kBlock) k_half_sweep(T* __restrict__ u, const T* __restrict__ f, SGrid g,
+                                                       int colour, typename Compute<T>::type h2,
+                                                       typename Compute<T>::type inv2d)
+{
+    using C = typename Compute<T>::type;
+    long t = (long)blockIdx.x * kBlock + threadIdx.x;
+    int m = g.nx - 2;
+    long total = (long)g.hx * m * (D == 3 ? m : 1);
+    if (t >= total) return;
+    int h = (int)(t % g.hx);
+    long r = t / g.hx;
+    int pj = 1 + (int)(r % m);
+    int pk = D == 3 ? 1 + (int)(r / m) : 0;
+    int pi = 2 * h + ((colour + pj + pk + D) & 1);
+    if (pi < 1 || pi > g.nx - 2) return;
+    const T* __restrict__ o = u + (size_t)(colour ^ 1) * g.cs;
+    size_t row = row_base(g, pj, pk);
+    size_t ny = (size_t)g.hx, nz = (size_t)g.nx * g.hx;
+    C s = (C)o[row + ((pi - 1) >> 1)];
+    s = s + (C)o[row + ((pi + 1) >> 1)];
+    s = s + (C)o[row - ny + h];
+    s = s + (C)o[row + ny + h];
+    if (D == 3) {
+        s = s + (C)o[row - nz + h];
+        s = s + (C)o[row + nz + h];
+    }
+    size_t self = (size_t)colour * g.cs + row + h;
+    u[self] = (T)((s - h2 * (C)f[self]) * inv2d);
+}
+
+// Ghost layer of a multigrid level L >= 1 (Sec. 2.4): left e_0 = -e_1; right
+// -e_{N-1} when x_N = 1, else coef * e_N; edges and corners compose the rule
+// of each axis they are ghosts on, applied in the order x, y, z.
+// blockIdx.y = face (2 per axis).
+template <int D, typename T>
+__global__ void __launch_bounds__(kBlock) k_ghost_fill(T* __restrict__ u, SGrid g, int xn_is_one,
+                                                       typename Compute<T>::type coef)
+{
+    using C = typename Compute<T>::type;
+    int Q = g.nx, N = Q - 2;
+    int t = blockIdx.x * kBlock + threadIdx.x;
+    int per = D == 3 ? Q * Q : Q;
+    if (t >= per) return;
+    int face = blockIdx.y;
+    int axis = face >> 1, side = face & 1;
+    int p[3] = {0, 0, 0};
+    int a = t % Q, b = t / Q;
+    if (D == 3) {
+        p[axis] = side ? Q - 1 : 0;
+        p[(axis + 1) % 3] = a;
+        p[(axis + 2) % 3] = b;
+    } else {
+        p[axis] = side ? Q - 1 : 0;
+        p[1 - axis] = a;
+    }
+    int src[3] = {p[0], p[1], p[2]};
+    C fac[3] = {1, 1, 1};
+    bool scaled[3] = {false, false, false};
+    for (int ax = 0; ax < D; ax++) {
+        if (src[ax] == 0) {
+            src[ax] = 1;
+            fac[ax] = -1;
+            scaled[ax] = true;
+        } else if (src[ax] == Q - 1) {
+            if (xn_is_one) {
+                src[ax] = N - 1;
+                fac[ax] = -1;
+            } else {
+                src[ax] = N;
+                fac[ax] = coef;
+            }
+            scaled[ax] = true;
+        }
+    }
+    C v = (C)at<D>(u, g, src[0], src[1], src[2]);
+    for (int ax = 0; ax < D; ax++)
+        if (scaled[ax]) v = fac[ax] * v;
+    u[pos<D, T>(g, p[0], p[1], p[2])] = (T)v;
+}
+
+// Residual r = f - lap(u) on the 2^d children of each coarse active point and
+// their mean (eqn:restriction2D/3D) into the coarse right-hand side;
+// children beyond the fine active range count as zero.  Also clears the
+// coarse correction.
+template <int D, typename T>
+__global__ void __launch_bounds__(kBlock) k_resid_restrict(const T* __restrict__ u, const T* __restrict__ f, SGrid gf,
+                                                           typename Compute<T>::type inv_h2, SGrid gc,
+                                                           T* __restrict__ fc, T* __restrict__ ec)
+{
+    using C = typename Compute<T>::type;
+    int Nc = gc.nx - 2, Nf = gf.nx - 2;
+    long t = (long)blockIdx.x * kBlock + threadIdx.x;
+    long total = D == 3 ? (long)Nc * Nc * Nc : (long)Nc * Nc;
+    if (t >= total) return;
+    int I = 1 + (int)(t % Nc);
+    long r = t / Nc;
+    int J = 1 + (int)(r % Nc);
+    int K = D == 3 ? 1 + (int)(r / Nc) : 0;
+    C sum = 0;
+    int k0 = D == 3 ? 2 * K - 1 : 0, k1 = D == 3 ? 2 * K : 0;
+    for (int k = k0; k <= k1; k++)
+        for (int j = 2 * J - 1; j <= 2 * J; j++)
+            for (int i = 2 * I - 1; i <= 2 * I; i++) {
+                if (i > Nf || j > Nf || (D == 3 && k > Nf)) continue;
+                C s = (C)at<D>(u, gf, i - 1, j, k);
+                s = s + (C)at<D>(u, gf, i + 1, j, k);
+                s = s + (C)at<D>(u, gf, i, j - 1, k);
+                s = s + (C)at<D>(u, gf, i, j + 1, k);
+                if (D == 3) {
+                    s = s + (C)at<D>(u, gf, i, j, k - 1);
+                    s = s + (C)at<D>(u, gf, i, j, k + 1);
+                }
+                C uc = (C)at<D>(u, gf, i, j, k);
+                sum += (C)at<D>(f, gf, i, j, k) - (s - (C)(2 * D) * uc) * inv_h2;
+            }
+    size_t pc = pos<D, T>(gc, I, J, K);
+    fc[pc] = (T)(sum * (C)(D == 3 ? 0.125 : 0.25));
+    ec[pc] = (T)0;
+}
+
+// u += P(e) on the fine active points (eqn:prolongation2D/3D as the tensor
+// product of (3/4, 1/4) along each axis: the coarse parent ceil(p/2) weighs
+// 3/4, its neighbour on the side of the fine centre 1/4).  Each thread does
+// the red and the black point of one compact position.
+template <int D, typename T>
+__global__ void __launch_bounds__(kBlock) k_prolong_add(const T* __restrict__ e, SGrid gc, T* __restrict__ u, SGrid gf)
+{
+    using C = typename Compute<T>::type;
+    int m = gf.nx - 2;
+    long t = (long)blockIdx.x * kBlock + threadIdx.x;
+    long total = (long)gf.hx * m * (D == 3 ? m : 1);
+    if (t >= total) return;
+    int h = (int)(t % gf.hx);
+    long r = t / gf.hx;
+    int pj = 1 + (int)(r % m);
+    int pk = D == 3 ? 1 + (int)(r / m) : 0;
+    const C w0 = (C)0.75, w1 = (C)0.25;
+    int qj = (pj + 1) >> 1, sj = (pj & 1) ? -1 : 1;
+    int qk = D == 3 ? (pk + 1) >> 1 : 0, sk = (pk & 1) ? -1 : 1;
+    for (int c = 0; c < 2; c++) {
+        int pi = 2 * h + ((c + pj + pk + D) & 1);
+        if (pi < 1 || pi > gf.nx - 2) continue;
+        int qi = (pi + 1) >> 1, si = (pi & 1) ? -1 : 1;
+        C y0 = w0 * (C)at<D>(e, gc, qi, qj, qk) + w1 * (C)at<D>(e, gc, qi + si, qj, qk);
+        C y1 = w0 * (C)at<D>(e, gc, qi, qj + sj, qk) + w1 * (C)at<D>(e, gc, qi + si, qj + sj, qk);
+        C v = w0 * y0 + w1 * y1;
+        if (D == 3) {
+            C y2 = w0 * (C)at<D>(e, gc, qi, qj, qk + sk) + w1 * (C)at<D>(e, gc, qi + si, qj, qk + sk);
+            C y3 = w0 * (C)at<D>(e, gc, qi, qj + sj, qk + sk) + w1 * (C)at<D>(e, gc, qi + si, qj + sj, qk + sk);
+            v = w0 * v + w1 * (w0 * y2 + w1 * y3);
+        }
+        size_t p = (size_t)c * gf.cs + row_base(gf, pj, pk) + h;
+        u[p] = (T)((C)u[p] + v);
+    }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+#define NP_DISPATCH(dim, KERNEL, grid, block, st, ...)                                    \
+    do {                                                                                  \
+        if ((dim) == 3) hipLaunchKernelGGL((KERNEL<3>), (grid), (block), 0, (st), __VA_ARGS__); \
+        else hipLaunchKernelGGL((KERNEL<2>), (grid), (block), 0, (st), __VA_ARGS__);           \
+    } while (0)
+
+static long npoints(const SGrid& g) { return (long)g.nx * g.nx * g.nz; }
+static long ncompact_active(int dim, const SGrid& g)
+{
+    long m = g.nx - 2;
+    return (long)g.hx * m * (dim == 3 ? m : 1);
+}
+
+void launch_level0_init(int dim, hipStream_t st, SGrid g, const double* rho0, const double* phi_outer,
+                        double fourpiG, double* phi, double* f)
+{
+    NP_DISPATCH(dim, k_level0_init, dim3(ceil_div(npoints(g), kBlock)), dim3(kBlock), st, g, rho0, phi_outer, fourpiG,
+                phi, f);
+}
+
+void launch_interface_fill(int dim, hipStream_t st, SGrid gc, const double* phic, const double* fc, SGrid gf,
+                           int nf, int offx, int offy, int offz, const double* rho, double fourpiG, double* phif,
+                           double* ff)
+{
+    NP_DISPATCH(dim, k_interface_fill, dim3(ceil_div(npoints(gf), kBlock)), dim3(kBlock), st, gc, phic, fc, gf, nf,
+                offx, offy, offz, rho, fourpiG, phif, ff);
+}
+
+void launch_forces(int dim, hipStream_t st, SGrid g, int n, double dx, const double* phi, double* fx, double* fy,
+                   double* fz)
+{
+    long total = dim == 3 ? (long)n * n * n : (long)n * n;
+    double m12dx = -1.0 / (12.0 * dx);
+    NP_DISPATCH(dim, k_forces, dim3(ceil_div(total, kBlock)), dim3(kBlock), st, g, n, m12dx, phi, fx, fy, fz);
+}
+
+void launch_force_delta(int dim, hipStream_t st, SGrid g, int n, double dx, const double* phi, double* F,
+                        unsigned long long* maxbits)
+{
+    long total = dim == 3 ? (long)n * n * n : (long)n * n;
+    double m12dx = -1.0 / (12.0 * dx);
+    NP_DISPATCH(dim, k_force_delta, dim3(ceil_div(total, kBlock)), dim3(kBlock), st, g, n, m12dx, phi, F, maxbits);
+}
+
+void launch_export(int dim, hipStream_t st, SGrid g, const double* a, double* out)
+{
+    NP_DISPATCH(dim, k_export, dim3(ceil_div(npoints(g), kBlock)), dim3(kBlock), st, g, a, out);
+}
+
+void launch_norm(int dim, hipStream_t st, SGrid g, const double* u, const double* f, double inv_h2, int mode,
+                 unsigned long long* maxbits)
+{
+    NP_DISPATCH(dim, k_norm, dim3(ceil_div(ncompact_active(dim, g), kBlock)), dim3(kBlock), st, g, u, f, inv_h2, mode,
+                maxbits);
+}
+
+void launch_set_u64(hipStream_t st, unsigned long long* p, int count, unsigned long long v)
+{
+    hipLaunchKernelGGL(k_set_u64, dim3(ceil_div(count, 64)), dim3(64), 0, st, p, count, v);
+}
+
+template <typename T>
+void launch_half_sweep(int dim, hipStream_t st, SGrid g, T* u, const T* f, int colour, double h2)
+{
+    using C = typename Compute<T>::type;
+    dim3 grid(ceil_div(ncompact_active(dim, g), kBlock));
+    C inv2d = (C)(1.0 / (2.0 * dim));
+    if (dim == 3)
+        hipLaunchKernelGGL((k_half_sweep<3, T>), grid, dim3(kBlock), 0, st, u, f, g, colour, (C)h2, inv2d);
+    else
+        hipLaunchKernelGGL((k_half_sweep<2, T>), grid, dim3(kBlock), 0, st, u, f, g, colour, (C)h2, inv2d);
+}
+
+template <typename T>
+void launch_ghost_fill(int dim, hipStream_t st, SGrid g, T* u, int xn_is_one, double coef)
+{
+    using C = typename Compute<T>::type;
+    int per = dim == 3 ? g.nx * g.nx : g.nx;
+    dim3 grid(ceil_div(per, kBlock), 2 * dim);
+    if (dim == 3)
+        hipLaunchKernelGGL((k_ghost_fill<3, T>), grid, dim3(kBlock), 0, st, u, g, xn_is_one, (C)coef);
+    else
+        hipLaunchKernelGGL((k_ghost_fill<2, T>), grid, dim3(kBlock), 0, st, u, g, xn_is_one, (C)coef);
+}
+
+template <typename T>
+void launch_resid_restrict(int dim, hipStream_t st, SGrid gf, const T* u, const T* f, double inv_h2, SGrid gc, T* fc,
+                           T* ec)
+{
+    using C = typename Compute<T>::type;
+    long Nc = gc.nx - 2;
+    long total = dim == 3 ? Nc * Nc * Nc : Nc * Nc;
+    dim3 grid(ceil_div(total, kBlock));
+    if (dim == 3)
+        hipLaunchKernelGGL((k_resid_restrict<3, T>), grid, dim3(kBlock), 0, st, u, f, gf, (C)inv_h2, gc, fc, ec);
+    else
+        hipLaunchKernelGGL((k_resid_restrict<2, T>), grid, dim3(kBlock), 0, st, u, f, gf, (C)inv_h2, gc, fc, ec);
+}
+
+template <typename T>
+void launch_prolong_add(int dim, hipStream_t st, SGrid gc, const T* ec, SGrid gf, T* u)
+{
+    dim3 grid(ceil_div(ncompact_active(dim, gf), kBlock));
+    if (dim == 3)
+        hipLaunchKernelGGL((k_prolong_add<3, T>), grid, dim3(kBlock), 0, st, ec, gc, u, gf);
+    else
+        hipLaunchKernelGGL((k_prolong_add<2, T>), grid, dim3(kBlock), 0, st, ec, gc, u, gf);
+}
+
+#define NP_INSTANTIATE(T)                                                                                   \
+    template void launch_half_sweep<T>(int, hipStream_t, SGrid, T*, const T*, int, double);                 \
+    template void launch_ghost_fill<T>(int, hipStream_t, SGrid, T*, int, double);                           \
+    template void launch_resid_restrict<T>(int, hipStream_t, SGrid, const T*, const T*, double, SGrid, T*, T*); \
+    template void launch_prolong_add<T>(int, hipStream_t, SGrid, const T*, SGrid, T*);
+
+NP_INSTANTIATE(double)
+NP_INSTANTIATE(float)
+
+}  // namespace np

@@ -1,0 +1,529 @@
+// Host runtime of the nested-grid multigrid solver: geometry validation,
+// multigrid planning, device storage, the V-cycle schedule and the C ABI
+// declared in include/nested_poisson.h.
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/nested_poisson.h"
+#include "np_internal.h"
+
+using namespace np;
+
+namespace {
+
+// ------------------------------------------------------------------ planning
+// Validation of the nested geometry (Sec. 2.1): even cell counts of at least
+// 4, patches on whole coarse cells with one coarse cell of margin.
+bool validate(const np_config* c, char* why, size_t nwhy)
+{
+    auto fail = [&](const char* fmt, int a, int b) {
+        snprintf(why, nwhy, fmt, a, b);
+        return false;
+    };
+    if (!c) return fail("null config%s", 0, 0);
+    if (c->dim != 2 && c->dim != 3) return fail("dim must be 2 or 3 (got %d)", c->dim, 0);
+    if (c->nlevels < 1 || c->nlevels > NP_MAX_LEVELS) return fail("nlevels must be 1..%d (got %d)", NP_MAX_LEVELS, c->nlevels);
+    for (int l = 0; l < c->nlevels; l++) {
+        int n = c->n[l];
+        if (n < 4 || (n & 1)) return fail("level %d: n must be even and >= 4 (got %d)", l, n);
+        if (n > 1 << 14) return fail("level %d: n too large (%d)", l, n);
+        if (l == 0) continue;
+        for (int a = 0; a < c->dim; a++) {
+            int o = c->offset[l][a];
+            if (o < 1 || o + n / 2 > c->n[l - 1] - 1)
+                return fail("level %d: offset leaves less than one coarse cell of margin on axis %d", l, a);
+        }
+    }
+    if (!(c->dx0 > 0.0) || !std::isfinite(c->dx0)) return fail("dx0 must be positive%s", 0, 0);
+    if (!std::isfinite(c->G)) return fail("G must be finite%s", 0, 0);
+    if (c->n_pre < 0 || c->n_pre > 16 || c->n_post < 0 || c->n_post > 16)
+        return fail("n_pre/n_post must be 0..16 (got %d, %d)", c->n_pre, c->n_post);
+    if (!(c->tol > 0.0)) return fail("tol must be positive%s", 0, 0);
+    if (c->max_cycles < 1 || c->max_cycles > NP_MAX_CYCLES) return fail("max_cycles must be 1..%d (got %d)", NP_MAX_CYCLES, c->max_cycles);
+    if (c->stop_rule != NP_STOP_RESIDUAL && c->stop_rule != NP_STOP_FORCE_DELTA) return fail("bad stop_rule %d%s", c->stop_rule, 0);
+    if (c->precision != NP_PREC_FP64) return fail("precision %d not available in this build%s", c->precision, 0);
+    if (c->guess != NP_GUESS_INTERP) return fail("guess %d not available in this build%s", c->guess, 0);
+    if (c->inner_cycles < 1 || c->inner_cycles > 8) return fail("inner_cycles must be 1..8 (got %d)%s", c->inner_cycles, 0);
+    return true;
+}
+
+// Sec. 2.2: N^0 = n + 2; N^L = round(N^0 / 2^L), halves up, until 1.
+int plan_levels(int N0, int* NL)
+{
+    NL[0] = N0;
+    int L = 0;
+    while (NL[L] > 1) {
+        if (L + 1 >= NP_MAX_MG) return -1;
+        L++;
+        NL[L] = (int)(((long long)N0 + (1LL << (L - 1))) >> L);
+    }
+    return L + 1;
+}
+
+// Sec. 2.4 right ghost of level L: the line through (x_N, e_N) vanishing at
+// x_MG = 1, evaluated at x_N + h^L; with x_N = (N - 1/2) 2^L / N^0 the factor
+// is (2 N^0 - (2N+1) 2^L) / (2 N^0 - (2N-1) 2^L).  x_N = 1 exactly when
+// (2N - 1) 2^(L-1) = N^0, where the rule is e_{N+1} = -e_{N-1}.
+void ghost_rule(int N0, int L, int N, int* one, double* coef)
+{
+    long long twoL = 1LL << L;
+    *one = ((long long)(2 * N - 1) * (twoL / 2) == (long long)N0) ? 1 : 0;
+    double num = 2.0 * N0 - (double)((2LL * N + 1) * twoL);
+    double den = 2.0 * N0 - (double)((2LL * N - 1) * twoL);
+    *coef = *one ? -1.0 : num / den;
+}
+
+// The kernels index coarse grids from fine ones; these bounds are what keeps
+// every access inside the padded arrays:
+//   prolongation: fine active a in 1..Nf reads coarse ceil(a/2) and its
+//     neighbour towards a, so ceil(Nf/2) <= Nc + 1 and floor(Nf/2) <= Nc;
+//   restriction: coarse I in 1..Nc has children 2I-1, 2I <= Nf + 1;
+//   the x_N = 1 rule reads e_{N-1}, so N >= 2 there.
+bool plan_in_bounds(const np_plan* p, int l)
+{
+    for (int L = 0; L + 1 < p->nmg[l]; L++) {
+        int Nf = p->N[l][L], Nc = p->N[l][L + 1];
+        if ((Nf + 1) / 2 > Nc + 1 || Nf / 2 > Nc || 2 * Nc > Nf + 1) return false;
+    }
+    for (int L = 1; L < p->nmg[l]; L++)
+        if (p->xn_is_one[l][L] && p->N[l][L] < 2) return false;
+    return true;
+}
+
+int make_plan(const np_config* c, np_plan* p)
+{
+    memset(p, 0, sizeof(*p));
+    for (int l = 0; l < c->nlevels; l++) {
+        int m = plan_levels(c->n[l] + 2, p->N[l]);
+        if (m < 2) return NP_EINVAL;
+        p->nmg[l] = m;
+        for (int L = 1; L < m; L++) ghost_rule(c->n[l] + 2, L, p->N[l][L], &p->xn_is_one[l][L], &p->ghost_coef[l][L]);
+        if (!plan_in_bounds(p, l)) return NP_EINVAL;
+    }
+    return NP_OK;
+}
+
+double bits_to_double(unsigned long long b)
+{
+    double d;
+    memcpy(&d, &b, sizeof d);
+    return d;
+}
+
+thread_local char g_last_error[256] = "";
+
+}  // namespace
+
+// ------------------------------------------------------------------ handle
+struct np_solver {
+    np_config cfg;
+    np_plan plan;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    SGrid lg[NP_MAX_LEVELS];          // level grids (= multigrid level 0)
+    double* phi[NP_MAX_LEVELS] = {};  // split potential per level
+    double* f[NP_MAX_LEVELS] = {};    // split right-hand side per level
+    // multigrid scratch for L >= 1, shared by the levels (sized for the largest)
+    double* mg_u[NP_MAX_MG] = {};
+    double* mg_f[NP_MAX_MG] = {};
+    double* force_scratch = nullptr;  // FORCE_DELTA stop rule
+    unsigned long long* d_bits = nullptr;  // device reduction slots
+    unsigned long long* h_bits = nullptr;  // pinned host copy
+    int fixed[NP_MAX_LEVELS];
+    bool has_fixed = false;
+    bool solved = false;
+    std::vector<double> hist[NP_MAX_LEVELS];
+    char err[512] = {0};
+};
+
+namespace {
+
+int set_err(np_solver* s, int code, const char* fmt, ...)
+{
+    if (s) {
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(s->err, sizeof s->err, fmt, ap);
+        va_end(ap);
+    }
+    return code;
+}
+
+#define HIPCHK(s, call)                                                                          \
+    do {                                                                                         \
+        hipError_t e_ = (call);                                                                  \
+        if (e_ != hipSuccess) return set_err((s), NP_EHIP, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+SGrid mg_grid(const np_solver* s, int l, int L) { return make_grid(s->cfg.dim, s->plan.N[l][L] + 2); }
+
+// One V-cycle (Sec. 2.3 steps 2-13) on nested level l in FP64.
+void vcycle(np_solver* s, int l)
+{
+    const np_config& c = s->cfg;
+    const int d = c.dim;
+    const int nmg = s->plan.nmg[l];
+    hipStream_t st = s->stream;
+    double dx = std::ldexp(c.dx0, -l);
+    double* u[NP_MAX_MG];
+    double* f[NP_MAX_MG];
+    SGrid g[NP_MAX_MG];
+    double h[NP_MAX_MG];
+    for (int L = 0; L < nmg; L++) {
+        u[L] = L == 0 ? s->phi[l] : s->mg_u[L];
+        f[L] = L == 0 ? s->f[l] : s->mg_f[L];
+        g[L] = L == 0 ? s->lg[l] : mg_grid(s, l, L);
+        h[L] = std::ldexp(dx, L);
+    }
+    auto sweep = [&](int L) {
+        for (int colour = 0; colour < 2; colour++) {
+            if (L > 0) launch_ghost_fill<double>(d, st, g[L], u[L], s->plan.xn_is_one[l][L], s->plan.ghost_coef[l][L]);
+            launch_half_sweep<double>(d, st, g[L], u[L], f[L], colour, h[L] * h[L]);
+        }
+    };
+    for (int it = 0; it < c.n_pre; it++) sweep(0);
+    int L = 0;
+    while (s->plan.N[l][L] > 1) {
+        if (L > 0) launch_ghost_fill<double>(d, st, g[L], u[L], s->plan.xn_is_one[l][L], s->plan.ghost_coef[l][L]);
+        launch_resid_restrict<double>(d, st, g[L], u[L], f[L], 1.0 / (h[L] * h[L]), g[L + 1], f[L + 1], u[L + 1]);
+        for (int it = 0; it < c.n_pre; it++) sweep(L + 1);
+        L++;
+    }
+    while (L > 0) {
+        launch_ghost_fill<double>(d, st, g[L], u[L], s->plan.xn_is_one[l][L], s->plan.ghost_coef[l][L]);
+        launch_prolong_add<double>(d, st, g[L], u[L], g[L - 1], u[L - 1]);
+        for (int it = 0; it < c.n_post; it++) sweep(L - 1);
+        L--;
+    }
+}
+
+// Queue a norm into slot `slot` and return it (host-synchronous).
+int norm_sync(np_solver* s, int l, int mode, double* out)
+{
+    double dx = std::ldexp(s->cfg.dx0, -l);
+    launch_set_u64(s->stream, s->d_bits, 1, 0ULL);
+    launch_norm(s->cfg.dim, s->stream, s->lg[l], s->phi[l], s->f[l], 1.0 / (dx * dx), mode, s->d_bits);
+    HIPCHK(s, hipGetLastError());
+    HIPCHK(s, hipMemcpyAsync(s->h_bits, s->d_bits, sizeof(unsigned long long), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    *out = bits_to_double(s->h_bits[0]);
+    return NP_OK;
+}
+
+int force_delta_sync(np_solver* s, int l, double* out)
+{
+    double dx = std::ldexp(s->cfg.dx0, -l);
+    launch_set_u64(s->stream, s->d_bits + 1, 1, 0ULL);
+    launch_force_delta(s->cfg.dim, s->stream, s->lg[l], s->cfg.n[l], dx, s->phi[l], s->force_scratch, s->d_bits + 1);
+    HIPCHK(s, hipGetLastError());
+    HIPCHK(s, hipMemcpyAsync(s->h_bits + 1, s->d_bits + 1, sizeof(unsigned long long), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    *out = bits_to_double(s->h_bits[1]);
+    return NP_OK;
+}
+
+void free_all(np_solver* s)
+{
+    for (int l = 0; l < NP_MAX_LEVELS; l++) {
+        if (s->phi[l]) (void)hipFree(s->phi[l]);
+        if (s->f[l]) (void)hipFree(s->f[l]);
+        s->phi[l] = s->f[l] = nullptr;
+    }
+    for (int L = 0; L < NP_MAX_MG; L++) {
+        if (s->mg_u[L]) (void)hipFree(s->mg_u[L]);
+        if (s->mg_f[L]) (void)hipFree(s->mg_f[L]);
+        s->mg_u[L] = s->mg_f[L] = nullptr;
+    }
+    if (s->force_scratch) (void)hipFree(s->force_scratch);
+    if (s->d_bits) (void)hipFree(s->d_bits);
+    if (s->h_bits) (void)hipHostFree(s->h_bits);
+    s->force_scratch = nullptr;
+    s->d_bits = nullptr;
+    s->h_bits = nullptr;
+}
+
+int alloc_dev(np_solver* s, void** p, size_t bytes)
+{
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return set_err(s, NP_ENOMEM, "hipMalloc(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
+    }
+    return NP_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ C ABI
+extern "C" {
+
+void nested_poisson_default_config(np_config* c)
+{
+    if (!c) return;
+    memset(c, 0, sizeof(*c));
+    c->G = 1.0;
+    c->n_pre = 2;
+    c->n_post = 1;
+    c->tol = 1e-10;
+    c->max_cycles = 50;
+    c->stop_rule = NP_STOP_RESIDUAL;
+    c->precision = NP_PREC_FP64;
+    c->inner_cycles = 1;
+    c->guess = NP_GUESS_INTERP;
+}
+
+int nested_poisson_plan(const np_config* cfg, np_plan* out)
+{
+    if (!out) return NP_EINVAL;
+    if (!validate(cfg, g_last_error, sizeof g_last_error)) return NP_EINVAL;
+    if (make_plan(cfg, out) != NP_OK) {
+        snprintf(g_last_error, sizeof g_last_error, "multigrid hierarchy too deep");
+        return NP_EINVAL;
+    }
+    return NP_OK;
+}
+
+int nested_poisson_create(const np_config* cfg, void* hip_stream, np_solver** out)
+{
+    if (!out) return NP_EINVAL;
+    *out = nullptr;
+    if (!validate(cfg, g_last_error, sizeof g_last_error)) return NP_EINVAL;
+    np_solver* s = new (std::nothrow) np_solver();
+    if (!s) return NP_ENOMEM;
+    s->cfg = *cfg;
+    if (make_plan(cfg, &s->plan) != NP_OK) {
+        delete s;
+        return NP_EINVAL;
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+        (void)hipGetLastError();
+        snprintf(g_last_error, sizeof g_last_error, "no HIP device");
+        delete s;
+        return NP_ENODEV;
+    }
+    if (hipGetDevice(&s->device) != hipSuccess) {
+        delete s;
+        return NP_EHIP;
+    }
+    s->stream = (hipStream_t)hip_stream;
+    const int d = cfg->dim;
+    int rc = NP_OK;
+    int maxn = 0;
+    for (int l = 0; l < cfg->nlevels && rc == NP_OK; l++) {
+        s->lg[l] = make_grid(d, cfg->n[l] + 4);
+        size_t bytes = 2 * s->lg[l].cs * sizeof(double);
+        rc = alloc_dev(s, (void**)&s->phi[l], bytes);
+        if (rc == NP_OK) rc = alloc_dev(s, (void**)&s->f[l], bytes);
+        if (cfg->n[l] > maxn) maxn = cfg->n[l];
+    }
+    // multigrid scratch: per level L the largest grid over the nested levels
+    for (int L = 1; L < NP_MAX_MG && rc == NP_OK; L++) {
+        size_t best = 0;
+        for (int l = 0; l < cfg->nlevels; l++)
+            if (L < s->plan.nmg[l]) {
+                size_t b = 2 * make_grid(d, s->plan.N[l][L] + 2).cs;
+                if (b > best) best = b;
+            }
+        if (!best) break;
+        rc = alloc_dev(s, (void**)&s->mg_u[L], best * sizeof(double));
+        if (rc == NP_OK) rc = alloc_dev(s, (void**)&s->mg_f[L], best * sizeof(double));
+    }
+    if (rc == NP_OK && cfg->stop_rule == NP_STOP_FORCE_DELTA) {
+        size_t cells = (size_t)maxn * maxn * (d == 3 ? maxn : 1);
+        rc = alloc_dev(s, (void**)&s->force_scratch, (size_t)d * cells * sizeof(double));
+    }
+    if (rc == NP_OK) rc = alloc_dev(s, (void**)&s->d_bits, 8 * sizeof(unsigned long long));
+    if (rc == NP_OK && hipHostMalloc((void**)&s->h_bits, 8 * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        s->h_bits = nullptr;
+        rc = NP_ENOMEM;
+    }
+    if (rc != NP_OK) {
+        snprintf(g_last_error, sizeof g_last_error, "%s", s->err);
+        free_all(s);
+        delete s;
+        return rc;
+    }
+    for (int l = 0; l < NP_MAX_LEVELS; l++) s->fixed[l] = -1;
+    *out = s;
+    return NP_OK;
+}
+
+int nested_poisson_set_fixed_cycles(np_solver* s, const int* cycles)
+{
+    if (!s) return NP_EINVAL;
+    if (!cycles) {
+        s->has_fixed = false;
+        for (int l = 0; l < NP_MAX_LEVELS; l++) s->fixed[l] = -1;
+        return NP_OK;
+    }
+    for (int l = 0; l < s->cfg.nlevels; l++) {
+        if (cycles[l] > NP_MAX_CYCLES) return set_err(s, NP_EINVAL, "fixed cycle count %d too large", cycles[l]);
+        s->fixed[l] = cycles[l];
+    }
+    s->has_fixed = true;
+    return NP_OK;
+}
+
+int nested_poisson_solve(np_solver* s, const double* const* rho, const double* phi_outer, np_stats* stats)
+{
+    if (!s) return NP_EINVAL;
+    if (!rho || !phi_outer) return set_err(s, NP_EINVAL, "null input pointer");
+    for (int l = 0; l < s->cfg.nlevels; l++)
+        if (!rho[l]) return set_err(s, NP_EINVAL, "rho[%d] is null", l);
+    HIPCHK(s, hipSetDevice(s->device));
+    const np_config& c = s->cfg;
+    const int d = c.dim;
+    const double fourpiG = 4.0 * M_PI * c.G;
+    np_stats st;
+    memset(&st, 0, sizeof st);
+    s->solved = false;
+    int status = NP_OK;
+    auto t_all = std::chrono::steady_clock::now();
+    for (int l = 0; l < c.nlevels; l++) {
+        auto t0 = std::chrono::steady_clock::now();
+        s->hist[l].clear();
+        if (l == 0) {
+            launch_level0_init(d, s->stream, s->lg[0], rho[0], phi_outer, fourpiG, s->phi[0], s->f[0]);
+        } else {
+            launch_interface_fill(d, s->stream, s->lg[l - 1], s->phi[l - 1], s->f[l - 1], s->lg[l], c.n[l],
+                                  c.offset[l][0], c.offset[l][1], d == 3 ? c.offset[l][2] : 0, rho[l], fourpiG,
+                                  s->phi[l], s->f[l]);
+        }
+        HIPCHK(s, hipGetLastError());
+        double scale = 0.0;
+        int rc = norm_sync(s, l, 1, &scale);
+        if (rc) return rc;
+        if (!std::isfinite(scale)) return set_err(s, NP_ENONFINITE, "level %d: non-finite density", l);
+        if (!(scale > 0.0)) {
+            rc = norm_sync(s, l, 2, &scale);
+            if (rc) return rc;
+            if (!std::isfinite(scale)) return set_err(s, NP_ENONFINITE, "level %d: non-finite boundary data", l);
+        }
+        double Fdelta = 0.0;
+        bool pinned = s->has_fixed && s->fixed[l] >= 0;
+        if (c.stop_rule == NP_STOP_FORCE_DELTA && !pinned) {
+            rc = force_delta_sync(s, l, &Fdelta);  // seeds the previous-force buffer
+            if (rc) return rc;
+        }
+        double r = 0.0;
+        rc = norm_sync(s, l, 0, &r);
+        if (rc) return rc;
+        const double r0 = r;
+        s->hist[l].push_back(scale > 0 ? r / scale : r);
+        int q = 0;
+        int lvl = NP_OK;
+        for (;;) {
+            if (!std::isfinite(r)) { lvl = NP_ENONFINITE; break; }
+            if (pinned) {
+                if (q >= s->fixed[l]) break;
+            } else if (c.stop_rule == NP_STOP_RESIDUAL && r <= c.tol * scale) {
+                break;
+            }
+            if (q >= c.max_cycles) { lvl = NP_ENOTCONV; break; }
+            vcycle(s, l);
+            HIPCHK(s, hipGetLastError());
+            q++;
+            rc = norm_sync(s, l, 0, &r);
+            if (rc) return rc;
+            s->hist[l].push_back(scale > 0 ? r / scale : r);
+            if (!std::isfinite(r)) { lvl = NP_ENONFINITE; break; }
+            if (r0 > 0 && r > 1e3 * r0) { lvl = NP_EDIVERGED; break; }
+            if (c.stop_rule == NP_STOP_FORCE_DELTA && !pinned) {
+                rc = force_delta_sync(s, l, &Fdelta);
+                if (rc) return rc;
+                if (Fdelta < c.tol) break;
+            }
+        }
+        st.cycles[l] = q;
+        st.scale[l] = scale;
+        st.initial_rel_residual[l] = s->hist[l].front();
+        st.final_rel_residual[l] = scale > 0 ? r / scale : r;
+        st.level_ms[l] = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        if (lvl == NP_ENONFINITE || lvl == NP_EDIVERGED) {
+            if (stats) *stats = st;
+            return set_err(s, lvl, "level %d: %s after %d cycles", l,
+                           lvl == NP_ENONFINITE ? "non-finite residual" : "residual diverged", q);
+        }
+        if (lvl == NP_ENOTCONV && status == NP_OK) {
+            status = NP_ENOTCONV;
+            set_err(s, NP_ENOTCONV, "level %d: not converged in %d cycles (rel. residual %.3e)", l, q,
+                    st.final_rel_residual[l]);
+        }
+    }
+    st.total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_all).count();
+    if (stats) *stats = st;
+    s->solved = true;
+    return status;
+}
+
+int nested_poisson_history(const np_solver* s, int level, double* out, int cap)
+{
+    if (!s || !out || cap < 0 || level < 0 || level >= s->cfg.nlevels) return NP_EINVAL;
+    int m = (int)s->hist[level].size();
+    if (m > cap) m = cap;
+    for (int i = 0; i < m; i++) out[i] = s->hist[level][i];
+    return m;
+}
+
+int nested_poisson_forces(np_solver* s, int level, double* fx, double* fy, double* fz)
+{
+    if (!s) return NP_EINVAL;
+    if (level < 0 || level >= s->cfg.nlevels) return set_err(s, NP_EINVAL, "level %d out of range", level);
+    if (!fx || !fy || (s->cfg.dim == 3 && !fz)) return set_err(s, NP_EINVAL, "null force pointer");
+    if (!s->solved) return set_err(s, NP_ESTATE, "forces requested before a successful solve");
+    HIPCHK(s, hipSetDevice(s->device));
+    launch_forces(s->cfg.dim, s->stream, s->lg[level], s->cfg.n[level], std::ldexp(s->cfg.dx0, -level),
+                  s->phi[level], fx, fy, fz);
+    HIPCHK(s, hipGetLastError());
+    return NP_OK;
+}
+
+int nested_poisson_potential(np_solver* s, int level, double* phi_padded)
+{
+    if (!s) return NP_EINVAL;
+    if (level < 0 || level >= s->cfg.nlevels) return set_err(s, NP_EINVAL, "level %d out of range", level);
+    if (!phi_padded) return set_err(s, NP_EINVAL, "null output pointer");
+    if (!s->solved) return set_err(s, NP_ESTATE, "potential requested before a successful solve");
+    HIPCHK(s, hipSetDevice(s->device));
+    launch_export(s->cfg.dim, s->stream, s->lg[level], s->phi[level], phi_padded);
+    HIPCHK(s, hipGetLastError());
+    return NP_OK;
+}
+
+void nested_poisson_destroy(np_solver* s)
+{
+    if (!s) return;
+    (void)hipSetDevice(s->device);
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    else (void)hipDeviceSynchronize();
+    free_all(s);
+    delete s;
+}
+
+const char* nested_poisson_strerror(int code)
+{
+    switch (code) {
+    case NP_OK: return "ok";
+    case NP_EINVAL: return "invalid argument";
+    case NP_ENOMEM: return "out of memory";
+    case NP_EHIP: return "HIP runtime error";
+    case NP_ENONFINITE: return "non-finite value";
+    case NP_ENOTCONV: return "not converged";
+    case NP_EDIVERGED: return "diverged";
+    case NP_ESTATE: return "call out of order";
+    case NP_ENODEV: return "no HIP device";
+    default: return "unknown error";
+    }
+}
+
+const char* nested_poisson_last_error(const np_solver* s) { return s ? s->err : g_last_error; }
+
+}  // extern "C"

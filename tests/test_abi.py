@@ -1,0 +1,115 @@
+"""The C-ABI library on the host (no GPU): it loads, exports every function
+include/nested_poisson.h declares, validates geometry before touching a
+device, and plans the same multigrid hierarchy as the oracle."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from conftest import ROOT
+from oracle import core
+from paper_2001_02327_amd import _lib
+from paper_2001_02327_amd import workloads as W
+
+
+def _declared():
+    names = set()
+    inc = os.path.join(ROOT, "include")
+    for fn in os.listdir(inc):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(inc, fn)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"\b(nested_poisson_\w+|np_\w+)\s*\(", txt))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib.lib()
+    declared = _declared()
+    assert declared, "no declarations found"
+    for name in declared:
+        assert hasattr(L, name), name
+    # the binding declares exactly the header's functions
+    assert declared == set(_lib.SIGNATURES)
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT (\w+)", out))
+    assert declared <= exported
+
+
+def test_library_links_no_oracle():
+    out = subprocess.run(["nm", "-D", _lib.LIB_PATH], capture_output=True, text=True).stdout
+    assert "orc_" not in out
+    ldd = subprocess.run(["ldd", _lib.LIB_PATH], capture_output=True, text=True).stdout
+    assert "oracle" not in ldd
+
+
+@pytest.mark.parametrize("wl", [W.c1_gaussian_2d(64), W.c2_plummer(128), W.c3_plummer_offset(256),
+                                W.c5_two_plummer(512), W.paper2d(1024), W.paper3d(10 * 4)],
+                         ids=lambda w: w.name)
+def test_host_plan_matches_oracle(wl):
+    cfg = _lib.make_config(wl.geom)
+    plan = _lib.plan(cfg)
+    for l, p in enumerate(plan):
+        N0 = wl.geom.n[l] + 2
+        assert p["N"] == core.plan(N0)
+        for L in range(1, len(p["N"])):
+            one, c = core.ghost_rule(N0, L, p["N"][L])
+            assert bool(p["xn_is_one"][L]) == one
+            if not one:
+                assert p["coef"][L] == c  # same rational, one rounding
+
+
+def _bad(**kw):
+    g = W.centred_geometry(3, 3, 16, 0.5, 1.0)
+    cfg = _lib.make_config(g)
+    for k, v in kw.items():
+        if k == "n":
+            cfg.n[v[0]] = v[1]
+        elif k == "off":
+            cfg.offset[v[0]][v[1]] = v[2]
+        else:
+            setattr(cfg, k, v)
+    return cfg
+
+
+@pytest.mark.parametrize("kw", [
+    dict(dim=4), dict(nlevels=0), dict(nlevels=9), dict(n=(1, 7)), dict(n=(0, 2)), dict(off=(1, 0, 0)),
+    dict(off=(2, 2, 9)), dict(dx0=0.0), dict(tol=-1.0), dict(max_cycles=0), dict(max_cycles=100000),
+    dict(n_pre=-1), dict(stop_rule=7), dict(inner_cycles=0),
+], ids=lambda k: ",".join("%s=%s" % kv for kv in k.items()))
+def test_invalid_geometry_rejected_before_any_device_call(kw):
+    cfg = _bad(**kw)
+    p = _lib.NpPlan()
+    assert _lib.lib().nested_poisson_plan(ctypes.byref(cfg), ctypes.byref(p)) == _lib.NP_EINVAL
+    assert _lib.lib().nested_poisson_last_error(None)
+    h = ctypes.c_void_p()
+    assert _lib.lib().nested_poisson_create(ctypes.byref(cfg), None, ctypes.byref(h)) == _lib.NP_EINVAL
+    assert not h.value
+
+
+def test_margin_rule_matches_oracle():
+    for off in range(0, 12):
+        g = W.Geometry(dim=2, n=[16, 12], off=[(0, 0, 0), (off, off, 0)], lo0=(0, 0, 0), dx0=1.0)
+        cfg = _lib.make_config(g)
+        ok = _lib.lib().nested_poisson_plan(ctypes.byref(cfg), ctypes.byref(_lib.NpPlan())) == 0
+        assert ok == core.validate(g), off
+
+
+def test_null_handle_calls_are_safe():
+    L = _lib.lib()
+    assert L.nested_poisson_forces(None, 0, None, None, None) == _lib.NP_EINVAL
+    assert L.nested_poisson_potential(None, 0, None) == _lib.NP_EINVAL
+    assert L.nested_poisson_set_fixed_cycles(None, None) == _lib.NP_EINVAL
+    L.nested_poisson_destroy(None)
+    assert L.nested_poisson_strerror(_lib.NP_ENOTCONV) == b"not converged"
+
+
+def test_plan_accepts_every_even_patch_size():
+    """Every even n (so every N^0 = n + 2) plans within the index bounds the
+    kernels rely on (checked inside nested_poisson_plan)."""
+    for n in range(4, 6000, 2):
+        g = W.Geometry(dim=3, n=[n], off=[(0, 0, 0)], lo0=(0, 0, 0), dx0=1.0)
+        cfg = _lib.make_config(g)
+        assert _lib.lib().nested_poisson_plan(ctypes.byref(cfg), ctypes.byref(_lib.NpPlan())) == 0, n
