@@ -1,0 +1,239 @@
+#!/usr/bin/env python3
+"""Benchmark: nested multigrid self-gravity solve on one MI355X.
+
+A step is one nested solve (every level, coarse to fine, V(2,1) cycles to a
+relative residual of 1e-10) followed by the forces on every level, on inputs
+already resident in HBM.  Default workload: two Plummer spheres (M = 1,
+a = 0.03 at the origin; M = 0.3, a = 0.015 at (0.2, 0, 0)), 5 nested levels
+of 512^3 cells, level k covering [-2^-k, 2^-k]^3, FP64.
+
+Prints one JSON line (rank 0): time per nested solve, the roofline of the
+level-0 smoother measured with HIP events inside the timed steps, the force
+error against the closed form, and the CPU oracle timed on a bounded sample.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "nested solve time at fixed Linf force error; smoother GB/s; plain vs mixed+learned"
+PEAK_HBM_GBS = 8000.0   # MI355X HBM3E peak
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def workload(name, N):
+    from paper_2001_02327_amd import workloads as W
+    if name == "two_plummer":
+        return W.c5_two_plummer(N=N)
+    if name == "plummer":
+        return W.c2_plummer(N=N)
+    if name == "plummer_offset":
+        return W.c3_plummer_offset(N=N)
+    if name == "paper3d":
+        return W.paper3d(N)
+    raise SystemExit("unknown workload %s" % name)
+
+
+def linf_force_error(solver, wl, F):
+    """Composite max |F_num - F_analytic| over the cells of each level not covered by a finer one."""
+    import torch
+    geom = wl.geom
+    worst = 0.0
+    for l in range(geom.nlevels):
+        solver.forces(l, out=F)
+        x = geom.mesh(l, 0, geom.n[l], device=F[0].device)
+        Fa = wl.prob.force(*x)
+        e = torch.zeros_like(F[0])
+        for a in range(geom.dim):
+            e += (F[a] - Fa[a]) ** 2
+        e = e.sqrt()
+        if l + 1 < geom.nlevels:
+            o, h = geom.off[l + 1], geom.n[l + 1] // 2
+            e[o[2]:o[2] + h, o[1]:o[1] + h, o[0]:o[0] + h] = 0.0
+        worst = max(worst, float(e.max()))
+        del x, Fa, e
+    return worst
+
+
+def cpu_baseline(wl, rho0, phi_outer, cycles_total, sample_cycles):
+    """The oracle's V(2,1) cycle on level 0 of the workload, timed on the host;
+    scaled to one nested solve by the total cycle count of the GPU solve (all
+    levels have the same size)."""
+    import numpy as np
+    from oracle import core
+    g = wl.geom
+    n = g.n[0]
+    P = n + 4
+    u = np.ascontiguousarray(phi_outer.cpu().numpy())
+    u[1:-1, 1:-1, 1:-1] = 0.0
+    f = np.zeros_like(u)
+    f[1:-1, 1:-1, 1:-1] = 4 * math.pi * g.G * rho0.cpu().numpy()
+    core.vcycle_patch(3, g.dx0, u, f)  # first touch of the pages
+    t0 = time.perf_counter()
+    for _ in range(sample_cycles):
+        core.vcycle_patch(3, g.dx0, u, f)
+    t = (time.perf_counter() - t0) / sample_cycles
+    ms_per_solve = t * 1e3 * cycles_total
+    return dict(value=ms_per_solve, unit="ms/solve", cores=core.num_threads(), kind="oracle",
+                sample="%d V(2,1) cycle(s) of level 0 (%d^3 active cells, padded %d^3) timed at %.3f s each, "
+                       "scaled by the %d cycles of one nested solve; setup, interface fills and forces not included"
+                       % (sample_cycles, n + 2, P, t, cycles_total))
+
+
+def copy_calibration():
+    """A plain device copy of known size (for scaling the PMC byte counters)."""
+    import torch
+    nbytes = 1 << 30
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps(dict(copy_bytes_read=nbytes, copy_bytes_written=nbytes, launches=5)))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="two_plummer")
+    ap.add_argument("--N", type=int, default=512, help="cells per axis of every level")
+    ap.add_argument("--cpu-sample-cycles", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true", help="run only a 1 GiB device copy x5")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the nested solve has no multi-GPU path in this build "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs the GPU")
+    torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        copy_calibration()
+        return
+
+    from paper_2001_02327_amd import workloads as W
+    from paper_2001_02327_amd.solver import NestedPoissonSolver
+
+    wl = workload(args.workload, args.N)
+    geom = wl.geom
+    dev = torch.device("cuda", 0)
+    log("workload", wl.name, geom.describe())
+    rho, phi_outer = W.make_inputs(geom, wl.prob, device=dev)
+    n = geom.n
+    if len(set(n)) != 1:
+        raise SystemExit("bench workloads use the same cell count on every level")
+    F = [torch.empty((n[0],) * geom.dim, dtype=torch.float64, device=dev) for _ in range(geom.dim)]
+
+    solver = NestedPoissonSolver(geom)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        st = solver.solve(rho, phi_outer)
+        for l in range(geom.nlevels):
+            solver.forces(l, out=F)
+        return st
+
+    for i in range(args.warmup):
+        st = step()
+        log("warmup", i, "cycles", st["cycles"], "ms %.1f" % st["total_ms"])
+    torch.cuda.synchronize()
+
+    solver.set_profiling(True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    stats = []
+    for i in range(args.steps):
+        stats.append(step())
+        log("step", i, "cycles", stats[-1]["cycles"])
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall_ms = (time.perf_counter() - t0) * 1e3
+    gpu_ms = e0.elapsed_time(e1)
+    prof = solver.profile()
+    solver.set_profiling(False)
+    ms_per_step = gpu_ms / args.steps
+
+    cycles = stats[-1]["cycles"]
+    cyc_total = sum(cycles)
+    N0 = n[0] + 2
+    # algorithmic bytes of one level-0 half sweep: read the other colour (8 B per
+    # point of that colour), read f of this colour, write this colour:
+    # 12 B per active point of the grid (both colours counted)
+    half_sweep_bytes = 12.0 * N0 ** geom.dim
+    sm_count, sm_ms = prof["smooth"]
+    sm_avg_ms = sm_ms / max(sm_count, 1)
+    achieved = half_sweep_bytes / (sm_avg_ms * 1e-3) / 1e9
+
+    linf = linf_force_error(solver, wl, F)
+    log("Linf force error %.4e" % linf)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a sample ...")
+        cpu = cpu_baseline(wl, rho[0], phi_outer, cyc_total, args.cpu_sample_cycles)
+        log("cpu baseline", cpu)
+    solver.close()
+
+    kern = {k: dict(launches=c, ms_per_step=m / args.steps, avg_us=(1e3 * m / c if c else None))
+            for k, (c, m) in prof.items()}
+    out = {
+        "metric": METRIC,
+        "value": round(ms_per_step, 3),
+        "unit": "ms/solve",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": wl.name,
+            "levels": geom.nlevels,
+            "cells_per_level": "%d^%d" % (n[0], geom.dim),
+            "precision": "fp64",
+            "guess": "interp",
+            "stop": "||r||_inf <= 1e-10 ||f||_inf per level",
+            "step": "nested solve + forces on every level",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_smooth_fine<3,double> (level-0 red-black half sweep)",
+            "achieved": round(achieved, 1),
+            "peak": PEAK_HBM_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 4),
+            "traffic": None,
+            "bytes_per_launch": half_sweep_bytes,
+            "avg_launch_us": round(sm_avg_ms * 1e3, 2),
+        },
+        "cpu_baseline": cpu,
+        "linf_force_error": linf,
+        "cycles_per_level": cycles,
+        "wall_ms_per_step": round(wall_ms / args.steps, 3),
+        "kernels": kern,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -161,6 +161,27 @@ int nested_poisson_forces(np_solver* s, int level, double* fx, double* fy, doubl
  * Errors: as nested_poisson_forces. */
 int nested_poisson_potential(np_solver* s, int level, double* phi_padded);
 
+/* Kernel-class timing.  With profiling enabled the handle records a HIP
+ * event pair on its stream around each launch (or group of launches) of a
+ * class and accumulates the elapsed device time; classes: */
+#define NP_KCLASS_SMOOTH 0   /* red-black half sweeps on the nested-level arrays (multigrid level 0) */
+#define NP_KCLASS_RESTRICT 1 /* fused residual + restriction out of multigrid level 0 */
+#define NP_KCLASS_PROLONG 2  /* prolongation + correction into multigrid level 0 */
+#define NP_KCLASS_COARSE 3   /* all work on multigrid levels >= 1 (one interval per V-cycle) */
+#define NP_KCLASS_NORM 4     /* max-norm reductions of the stop test */
+#define NP_KCLASS_FILL 5     /* level-0 setup and coarse-to-fine fills */
+#define NP_KCLASS_FORCES 6   /* force evaluation */
+#define NP_NKCLASS 8
+typedef struct np_profile {
+    long count[NP_NKCLASS]; /* launches (intervals) recorded */
+    double ms[NP_NKCLASS];  /* summed device time */
+} np_profile;
+/* enable != 0 starts (and zeroes) the counters, 0 stops and frees the events. */
+int nested_poisson_set_profiling(np_solver* s, int enable);
+/* Synchronises the stream and returns the totals since profiling was enabled.
+ * Errors: NP_EINVAL, NP_ESTATE (profiling off), NP_EHIP. */
+int nested_poisson_get_profile(np_solver* s, np_profile* out);
+
 /* Frees every library allocation of the handle.  NULL-safe. */
 void nested_poisson_destroy(np_solver* s);
 

@@ -67,6 +67,7 @@ def lib():
         L.orc_vcycle_patch.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp, _dp, ctypes.c_int,
                                        ctypes.c_int, ctypes.c_int]
         L.orc_vcycle_patch.restype = ctypes.c_int
+        L.orc_num_threads.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -144,6 +145,10 @@ def forces(dim, dx, phi):
     fx, fy, fz = np.zeros(shp), np.zeros(shp), np.zeros(shp if dim == 3 else (1,))
     lib().orc_forces(dim, n, dx, _p(phi), _p(fx), _p(fy), _p(fz))
     return (fx, fy, fz) if dim == 3 else (fx, fy)
+
+
+def num_threads():
+    return lib().orc_num_threads()
 
 
 def vcycle_patch(dim, h0, u, f, n_pre=2, n_post=1, literal=False):

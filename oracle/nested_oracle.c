@@ -22,6 +22,7 @@
  *   (N^0 = n + 2, Gamma^l = Omega^l plus the inner buffer layer).
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -605,3 +606,6 @@ int orc_vcycle_patch(int dim, int N0, double h0, double *u, const double *f, int
     }
     return 0;
 }
+
+/* threads the OpenMP loops of the oracle use */
+int orc_num_threads(void) { return omp_get_max_threads(); }

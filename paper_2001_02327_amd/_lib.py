@@ -67,6 +67,14 @@ class NpStats(ctypes.Structure):
     ]
 
 
+NP_NKCLASS = 8
+KCLASSES = ["smooth", "restrict", "prolong", "coarse", "norm", "fill", "forces"]
+
+
+class NpProfile(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_long * NP_NKCLASS), ("ms", ctypes.c_double * NP_NKCLASS)]
+
+
 # every symbol the header declares, with its signature
 _vp = ctypes.c_void_p
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -79,6 +87,8 @@ SIGNATURES = {
     "nested_poisson_history": (ctypes.c_int, [_vp, ctypes.c_int, _dp, ctypes.c_int]),
     "nested_poisson_forces": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _vp]),
     "nested_poisson_potential": (ctypes.c_int, [_vp, ctypes.c_int, _vp]),
+    "nested_poisson_set_profiling": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "nested_poisson_get_profile": (ctypes.c_int, [_vp, ctypes.POINTER(NpProfile)]),
     "nested_poisson_destroy": (None, [_vp]),
     "nested_poisson_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "nested_poisson_last_error": (ctypes.c_char_p, [_vp]),

@@ -59,8 +59,9 @@ void launch_norm(int dim, hipStream_t st, SGrid g, const double* u, const double
 void launch_set_u64(hipStream_t st, unsigned long long* p, int count, unsigned long long v);
 
 // multigrid operators, templated on storage type T (double, float)
+// fine != 0: the nested-level arrays (multigrid level 0, fixed ghost layer)
 template <typename T>
-void launch_half_sweep(int dim, hipStream_t st, SGrid g, T* u, const T* f, int colour, double h2);
+void launch_half_sweep(int dim, hipStream_t st, SGrid g, T* u, const T* f, int colour, double h2, int fine);
 template <typename T>
 void launch_ghost_fill(int dim, hipStream_t st, SGrid g, T* u, int xn_is_one, double coef);
 template <typename T>

@@ -14,6 +14,17 @@ constexpr int kBlock = 256;
 
 __host__ __device__ inline int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }
 
+// Workgroups are dealt to the 8 XCDs of the chip round-robin (workgroup b runs
+// on XCD b % 8).  Renumber them so that XCD x processes one contiguous run of
+// logical blocks: stencil neighbours (rows above/below, planes in front/behind)
+// are then fetched into the same XCD's L2 instead of eight different ones.
+__device__ __forceinline__ long xcd_block()
+{
+    long nb = gridDim.x, b = blockIdx.x;
+    long q = nb >> 3, r = nb & 7, x = b & 7, k = b >> 3;
+    return x * q + (x < r ? x : r) + k;
+}
+
 template <int D>
 __device__ __forceinline__ int colour_of(int pi, int pj, int pk)
 {
@@ -77,7 +88,7 @@ __global__ void __launch_bounds__(kBlock) k_level0_init(SGrid g, const double* _
                                                         const double* __restrict__ phi_outer, double fourpiG,
                                                         double* __restrict__ phi, double* __restrict__ f)
 {
-    long t = (long)blockIdx.x * kBlock + threadIdx.x;
+    long t = xcd_block() * kBlock + threadIdx.x;
     long total = (long)g.nx * g.nx * g.nz;
     if (t >= total) return;
     int pi = (int)(t % g.nx);
@@ -134,7 +145,7 @@ __global__ void __launch_bounds__(kBlock) k_interface_fill(SGrid gc, const doubl
                                                            double fourpiG, double* __restrict__ phif,
                                                            double* __restrict__ ff)
 {
-    long t = (long)blockIdx.x * kBlock + threadIdx.x;
+    long t = xcd_block() * kBlock + threadIdx.x;
     long total = (long)gf.nx * gf.nx * gf.nz;
     if (t >= total) return;
     int pi = (int)(t % gf.nx);
@@ -183,7 +194,7 @@ __global__ void __launch_bounds__(kBlock) k_forces(SGrid g, int n, double m12dx,
                                                    double* __restrict__ fx, double* __restrict__ fy,
                                                    double* __restrict__ fz)
 {
-    long t = (long)blockIdx.x * kBlock + threadIdx.x;
+    long t = xcd_block() * kBlock + threadIdx.x;
     long total = D == 3 ? (long)n * n * n : (long)n * n;
     if (t >= total) return;
     int i = (int)(t % n);
@@ -202,7 +213,7 @@ template <int D>
 __global__ void __launch_bounds__(kBlock) k_force_delta(SGrid g, int n, double m12dx, const double* __restrict__ phi,
                                                         double* __restrict__ F, unsigned long long* maxbits)
 {
-    long t = (long)blockIdx.x * kBlock + threadIdx.x;
+    long t = xcd_block() * kBlock + threadIdx.x;
     long total = D == 3 ? (long)n * n * n : (long)n * n;
     unsigned long long m = 0;
     if (t < total) {
@@ -225,7 +236,7 @@ __global__ void __launch_bounds__(kBlock) k_force_delta(SGrid g, int n, double m
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_export(SGrid g, const double* __restrict__ a, double* __restrict__ out)
 {
-    long t = (long)blockIdx.x * kBlock + threadIdx.x;
+    long t = xcd_block() * kBlock + threadIdx.x;
     long total = (long)g.nx * g.nx * g.nz;
     if (t >= total) return;
     int pi = (int)(t % g.nx);
@@ -236,21 +247,23 @@ __global__ void __launch_bounds__(kBlock) k_export(SGrid g, const double* __rest
 }
 
 // ------------------------------------------------------------------ norms
+// Grid-stride loop over a bounded grid so that only a few thousand blocks
+// meet in the final atomic maximum.
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_norm(SGrid g, const double* __restrict__ u, const double* __restrict__ f,
                                                  double inv_h2, int mode, unsigned long long* maxbits)
 {
-    long t = (long)blockIdx.x * kBlock + threadIdx.x;
     int m = g.nx - 2;
     long total = (long)g.hx * m * (D == 3 ? m : 1);
+    long stride = (long)gridDim.x * kBlock;
+    size_t ny = (size_t)g.hx, nz = (size_t)g.nx * g.hx;
     unsigned long long best = 0;
-    if (t < total) {
+    for (long t = xcd_block() * kBlock + threadIdx.x; t < total; t += stride) {
         int h = (int)(t % g.hx);
         long r = t / g.hx;
         int pj = 1 + (int)(r % m);
         int pk = D == 3 ? 1 + (int)(r / m) : 0;
         size_t row = row_base(g, pj, pk);
-        size_t ny = (size_t)g.hx, nz = (size_t)g.nx * g.hx;
         for (int c = 0; c < 2; c++) {
             int pi = 2 * h + ((c + pj + pk + D) & 1);
             if (pi < 1 || pi > g.nx - 2) continue;
@@ -259,6 +272,16 @@ __global__ void __launch_bounds__(kBlock) k_norm(SGrid g, const double* __restri
             double val;
             if (mode == 1) {
                 val = f[self];
+            } else if (mode == 2) {
+                // the active part of u taken as zero: only ghost-layer neighbours remain
+                double s = 0.0;
+                if (pi - 1 == 0) s += o[row + ((pi - 1) >> 1)];
+                if (pi + 1 == g.nx - 1) s += o[row + ((pi + 1) >> 1)];
+                if (pj - 1 == 0) s += o[row - ny + h];
+                if (pj + 1 == g.nx - 1) s += o[row + ny + h];
+                if (D == 3 && pk - 1 == 0) s += o[row - nz + h];
+                if (D == 3 && pk + 1 == g.nx - 1) s += o[row + nz + h];
+                val = f[self] - s * inv_h2;
             } else {
                 double s = o[row + ((pi - 1) >> 1)];
                 s = s + o[row + ((pi + 1) >> 1)];
@@ -268,22 +291,66 @@ __global__ void __launch_bounds__(kBlock) k_norm(SGrid g, const double* __restri
                     s = s + o[row - nz + h];
                     s = s + o[row + nz + h];
                 }
-                double uc = u[self];
-                if (mode == 2) {
-                    // interior zero: keep only neighbours on the ghost layer
-                    s = 0.0;
-                    if (pi - 1 == 0) s += o[row + ((pi - 1) >> 1)];
-                    if (pi + 1 == g.nx - 1) s += o[row + ((pi + 1) >> 1)];
-                    if (pj - 1 == 0) s += o[row - ny + h];
-                    if (pj + 1 == g.nx - 1) s += o[row + ny + h];
-                    if (D == 3 && pk - 1 == 0) s += o[row - nz + h];
-                    if (D == 3 && pk + 1 == g.nx - 1) s += o[row + nz + h];
-                    uc = 0.0;
-                }
-                val = f[self] - (s - (2.0 * D) * uc) * inv_h2;
+                val = f[self] - (s - (2.0 * D) * u[self]) * inv_h2;
             }
             unsigned long long b = abs_bits(val);
             best = b > best ? b : best;
+        }
+    }
+    block_max_to(best, maxbits);
+}
+
+// 3-D residual max-norm on a nested-level array, marching along z like
+// k_smooth_fine3: a thread owns compact (h, pj), treats the red and the black
+// point of that position on every plane of its chunk, and keeps both colours'
+// values at pk-1, pk, pk+1 of its column in registers.
+constexpr int kNormChunk = 64;
+
+__global__ void __launch_bounds__(kBlock) k_resid_norm3(SGrid g, const double* __restrict__ u,
+                                                        const double* __restrict__ f, double inv_h2, int pblocks,
+                                                        unsigned long long* maxbits)
+{
+    const int m = g.nx - 2;
+    const long lb = xcd_block();
+    const int zc = (int)(lb / pblocks);
+    const long t = (lb - (long)zc * pblocks) * kBlock + threadIdx.x;
+    unsigned long long best = 0;
+    if (t < (long)g.hx * m) {
+        const int h = (int)(t % g.hx);
+        const int pj = 1 + (int)(t / g.hx);
+        const int k0 = 1 + zc * kNormChunk;
+        const int k1 = min(k0 + kNormChunk - 1, m);
+        const size_t plane = (size_t)g.nx * g.hx;
+        const size_t col = (size_t)pj * g.hx + h;
+        const double* __restrict__ a[2] = {u, u + g.cs};
+        double below[2], cur[2];
+        for (int c = 0; c < 2; c++) {
+            below[c] = a[c][(size_t)(k0 - 1) * plane + col];
+            cur[c] = a[c][(size_t)k0 * plane + col];
+        }
+        for (int pk = k0; pk <= k1; pk++) {
+            const size_t here = (size_t)pk * plane + col;
+            double above[2] = {a[0][here + plane], a[1][here + plane]};
+            for (int c = 0; c < 2; c++) {
+                const int o = c ^ 1;
+                const int par = (c + pj + pk + 3) & 1;
+                const int pi = 2 * h + par;
+                if (pi < 1 || pi > g.nx - 2) continue;
+                double xm = par ? cur[o] : a[o][here - 1];
+                double xp = par ? a[o][here + 1] : cur[o];
+                double s = xm + xp;
+                s = s + a[o][here - g.hx];
+                s = s + a[o][here + g.hx];
+                s = s + below[o];
+                s = s + above[o];
+                double r = f[(size_t)c * g.cs + here] - (s - 6.0 * cur[c]) * inv_h2;
+                unsigned long long b = abs_bits(r);
+                best = b > best ? b : best;
+            }
+            for (int c = 0; c < 2; c++) {
+                below[c] = cur[c];
+                cur[c] = above[c];
+            }
         }
     }
     block_max_to(best, maxbits);
@@ -303,13 +370,15 @@ struct Compute<__half> { using type = float; };
 
 // Red-black Gauss-Seidel half sweep: u_c = (sum of the 2d neighbours - h^2 f_c) / (2d)
 // over the active points of one colour; the neighbours are all of the other colour.
+// k_smooth_fine runs it on the nested-level arrays (multigrid level 0, whose
+// ghost layer is the fixed outer buffer), k_half_sweep on the coarse levels.
 template <int D, typename T>
-__global__ void __launch_bounds__(kBlock) k_half_sweep(T* __restrict__ u, const T* __restrict__ f, SGrid g,
+__device__ __forceinline__ void half_sweep_body(T* __restrict__ u, const T* __restrict__ f, SGrid g,
                                                        int colour, typename Compute<T>::type h2,
                                                        typename Compute<T>::type inv2d)
 {
     using C = typename Compute<T>::type;
-    long t = (long)blockIdx.x * kBlock + threadIdx.x;
+    long t = xcd_block() * kBlock + threadIdx.x;
     int m = g.nx - 2;
     long total = (long)g.hx * m * (D == 3 ? m : 1);
     if (t >= total) return;
@@ -332,6 +401,110 @@ __global__ void __launch_bounds__(kBlock) k_half_sweep(T* __restrict__ u, const 
     }
     size_t self = (size_t)colour * g.cs + row + h;
     u[self] = (T)((s - h2 * (C)f[self]) * inv2d);
+}
+
+
+template <int D, typename T>
+__global__ void __launch_bounds__(kBlock) k_smooth_fine(T* __restrict__ u, const T* __restrict__ f, SGrid g, int colour,
+                                                        typename Compute<T>::type h2, typename Compute<T>::type inv2d)
+{
+    half_sweep_body<D, T>(u, f, g, colour, h2, inv2d);
+}
+
+// 3-D level-0 half sweep marching along z.  A thread owns one compact (h, pj)
+// position and walks kZChunk planes, keeping the other colour's values at
+// planes pk-1, pk, pk+1 of its own column in registers: each value of the
+// other colour is loaded once per chunk as the "plane above" and reused as the
+// centre's x-neighbour and the next planes' z-neighbours.  Logical blocks run
+// over the flattened (pj, h) plane fastest, so the blocks resident on one XCD
+// cover adjacent rows of the same planes and the y-neighbour rows come from
+// its L2.
+constexpr int kZChunk = 8;
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_smooth_fine3(T* __restrict__ u, const T* __restrict__ f, SGrid g, int colour,
+                                                         typename Compute<T>::type h2,
+                                                         typename Compute<T>::type inv2d, int pblocks)
+{
+    using C = typename Compute<T>::type;
+    const int m = g.nx - 2;
+    const long lb = xcd_block();
+    const int zc = (int)(lb / pblocks);
+    const long t = (lb - (long)zc * pblocks) * kBlock + threadIdx.x;
+    if (t >= (long)g.hx * m) return;
+    const int h = (int)(t % g.hx);
+    const int pj = 1 + (int)(t / g.hx);
+    const int k0 = 1 + zc * kZChunk;
+    const int k1 = min(k0 + kZChunk - 1, m);
+    const size_t plane = (size_t)g.nx * g.hx;
+    const size_t col = (size_t)pj * g.hx + h;  // offset of (h, pj) inside a plane
+    const T* __restrict__ o = u + (size_t)(colour ^ 1) * g.cs;
+    T* __restrict__ uc = u + (size_t)colour * g.cs;
+    const T* __restrict__ fc = f + (size_t)colour * g.cs;
+    C below = (C)o[(size_t)(k0 - 1) * plane + col];
+    C cur = (C)o[(size_t)k0 * plane + col];
+    int pk = k0;
+    // groups of 4 planes: every load of the group is issued before the first
+    // update so that each wave keeps ~20 loads in flight.  Loads at inactive
+    // (ghost) positions stay inside the arrays: h-1 / h+1 fall in the
+    // neighbouring row of the same plane and f covers the whole padded grid.
+    for (; pk + 3 <= k1; pk += 4) {
+        C ab[4], xo[4], ym[4], yp[4], fv[4];
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            const size_t here = (size_t)(pk + q) * plane + col;
+            const int par = (colour + pj + pk + q + 3) & 1;
+            ab[q] = (C)o[here + plane];
+            xo[q] = (C)o[par ? here + 1 : here - 1];
+            ym[q] = (C)o[here - g.hx];
+            yp[q] = (C)o[here + g.hx];
+            fv[q] = (C)fc[here];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            const size_t here = (size_t)(pk + q) * plane + col;
+            const int par = (colour + pj + pk + q + 3) & 1;
+            const int pi = 2 * h + par;
+            if (pi >= 1 && pi <= g.nx - 2) {
+                C xm = par ? cur : xo[q];
+                C xp = par ? xo[q] : cur;
+                C s = xm + xp;
+                s = s + ym[q];
+                s = s + yp[q];
+                s = s + below;
+                s = s + ab[q];
+                uc[here] = (T)((s - h2 * fv[q]) * inv2d);
+            }
+            below = cur;
+            cur = ab[q];
+        }
+    }
+    for (; pk <= k1; pk++) {
+        const size_t here = (size_t)pk * plane + col;
+        C above = (C)o[here + plane];
+        const int par = (colour + pj + pk + 3) & 1;  // pi = 2h + par
+        const int pi = 2 * h + par;
+        if (pi >= 1 && pi <= g.nx - 2) {
+            // x-neighbours pi-1, pi+1: compact h-1 and h (par 0) or h and h+1 (par 1)
+            C xm = par ? cur : (C)o[here - 1];
+            C xp = par ? (C)o[here + 1] : cur;
+            C s = xm + xp;
+            s = s + (C)o[here - g.hx];
+            s = s + (C)o[here + g.hx];
+            s = s + below;
+            s = s + above;
+            uc[here] = (T)((s - h2 * (C)fc[here]) * inv2d);
+        }
+        below = cur;
+        cur = above;
+    }
+}
+
+template <int D, typename T>
+__global__ void __launch_bounds__(kBlock) k_half_sweep(T* __restrict__ u, const T* __restrict__ f, SGrid g, int colour,
+                                                       typename Compute<T>::type h2, typename Compute<T>::type inv2d)
+{
+    half_sweep_body<D, T>(u, f, g, colour, h2, inv2d);
 }
 
 // Ghost layer of a multigrid level L >= 1 (Sec. 2.4): left e_0 = -e_1; right
@@ -395,7 +568,7 @@ __global__ void __launch_bounds__(kBlock) k_resid_restrict(const T* __restrict__
 {
     using C = typename Compute<T>::type;
     int Nc = gc.nx - 2, Nf = gf.nx - 2;
-    long t = (long)blockIdx.x * kBlock + threadIdx.x;
+    long t = xcd_block() * kBlock + threadIdx.x;
     long total = D == 3 ? (long)Nc * Nc * Nc : (long)Nc * Nc;
     if (t >= total) return;
     int I = 1 + (int)(t % Nc);
@@ -433,7 +606,7 @@ __global__ void __launch_bounds__(kBlock) k_prolong_add(const T* __restrict__ e,
 {
     using C = typename Compute<T>::type;
     int m = gf.nx - 2;
-    long t = (long)blockIdx.x * kBlock + threadIdx.x;
+    long t = xcd_block() * kBlock + threadIdx.x;
     long total = (long)gf.hx * m * (D == 3 ? m : 1);
     if (t >= total) return;
     int h = (int)(t % gf.hx);
@@ -515,8 +688,17 @@ void launch_export(int dim, hipStream_t st, SGrid g, const double* a, double* ou
 void launch_norm(int dim, hipStream_t st, SGrid g, const double* u, const double* f, double inv_h2, int mode,
                  unsigned long long* maxbits)
 {
-    NP_DISPATCH(dim, k_norm, dim3(ceil_div(ncompact_active(dim, g), kBlock)), dim3(kBlock), st, g, u, f, inv_h2, mode,
-                maxbits);
+    if (dim == 3 && mode == 0) {
+        long m = g.nx - 2;
+        int pblocks = ceil_div((long)g.hx * m, kBlock);
+        int chunks = ceil_div(m, kNormChunk);
+        hipLaunchKernelGGL(k_resid_norm3, dim3(pblocks * chunks), dim3(kBlock), 0, st, g, u, f, inv_h2, pblocks,
+                           maxbits);
+        return;
+    }
+    int blocks = ceil_div(ncompact_active(dim, g), kBlock);
+    if (blocks > 2048) blocks = 2048;
+    NP_DISPATCH(dim, k_norm, dim3(blocks), dim3(kBlock), st, g, u, f, inv_h2, mode, maxbits);
 }
 
 void launch_set_u64(hipStream_t st, unsigned long long* p, int count, unsigned long long v)
@@ -525,15 +707,26 @@ void launch_set_u64(hipStream_t st, unsigned long long* p, int count, unsigned l
 }
 
 template <typename T>
-void launch_half_sweep(int dim, hipStream_t st, SGrid g, T* u, const T* f, int colour, double h2)
+void launch_half_sweep(int dim, hipStream_t st, SGrid g, T* u, const T* f, int colour, double h2, int fine)
 {
     using C = typename Compute<T>::type;
     dim3 grid(ceil_div(ncompact_active(dim, g), kBlock));
     C inv2d = (C)(1.0 / (2.0 * dim));
-    if (dim == 3)
-        hipLaunchKernelGGL((k_half_sweep<3, T>), grid, dim3(kBlock), 0, st, u, f, g, colour, (C)h2, inv2d);
-    else
-        hipLaunchKernelGGL((k_half_sweep<2, T>), grid, dim3(kBlock), 0, st, u, f, g, colour, (C)h2, inv2d);
+    if (fine) {
+        if (dim == 3) {
+            long m = g.nx - 2;
+            int pblocks = ceil_div((long)g.hx * m, kBlock);
+            int chunks = ceil_div(m, kZChunk);
+            hipLaunchKernelGGL((k_smooth_fine3<T>), dim3(pblocks * chunks), dim3(kBlock), 0, st, u, f, g, colour, (C)h2,
+                               inv2d, pblocks);
+        } else
+            hipLaunchKernelGGL((k_smooth_fine<2, T>), grid, dim3(kBlock), 0, st, u, f, g, colour, (C)h2, inv2d);
+    } else {
+        if (dim == 3)
+            hipLaunchKernelGGL((k_half_sweep<3, T>), grid, dim3(kBlock), 0, st, u, f, g, colour, (C)h2, inv2d);
+        else
+            hipLaunchKernelGGL((k_half_sweep<2, T>), grid, dim3(kBlock), 0, st, u, f, g, colour, (C)h2, inv2d);
+    }
 }
 
 template <typename T>
@@ -573,7 +766,7 @@ void launch_prolong_add(int dim, hipStream_t st, SGrid gc, const T* ec, SGrid gf
 }
 
 #define NP_INSTANTIATE(T)                                                                                   \
-    template void launch_half_sweep<T>(int, hipStream_t, SGrid, T*, const T*, int, double);                 \
+    template void launch_half_sweep<T>(int, hipStream_t, SGrid, T*, const T*, int, double, int);                 \
     template void launch_ghost_fill<T>(int, hipStream_t, SGrid, T*, int, double);                           \
     template void launch_resid_restrict<T>(int, hipStream_t, SGrid, const T*, const T*, double, SGrid, T*, T*); \
     template void launch_prolong_add<T>(int, hipStream_t, SGrid, const T*, SGrid, T*);

@@ -139,6 +139,14 @@ struct np_solver {
     bool solved = false;
     std::vector<double> hist[NP_MAX_LEVELS];
     char err[512] = {0};
+    // kernel-class timing with HIP events on the handle's stream
+    bool prof = false;
+    std::vector<hipEvent_t> ev;  // pairs (start, stop)
+    std::vector<int> ev_cls;
+    int ev_used = 0;
+    int cur_cls = 0;
+    long prof_count[NP_NKCLASS] = {};
+    double prof_ms[NP_NKCLASS] = {};
 };
 
 namespace {
@@ -162,6 +170,47 @@ int set_err(np_solver* s, int code, const char* fmt, ...)
 
 SGrid mg_grid(const np_solver* s, int l, int L) { return make_grid(s->cfg.dim, s->plan.N[l][L] + 2); }
 
+// Fold the recorded event pairs into the per-class totals (synchronises).
+int prof_flush(np_solver* s)
+{
+    if (!s->ev_used) return NP_OK;
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    for (int i = 0; i + 1 < s->ev_used; i += 2) {
+        float ms = 0.f;
+        HIPCHK(s, hipEventElapsedTime(&ms, s->ev[i], s->ev[i + 1]));
+        int c = s->ev_cls[i / 2];
+        s->prof_ms[c] += ms;
+        s->prof_count[c] += 1;
+    }
+    s->ev_used = 0;
+    return NP_OK;
+}
+
+void prof_begin(np_solver* s, int cls)
+{
+    if (!s->prof) return;
+    if (s->ev_used + 2 > (int)s->ev.size()) prof_flush(s);
+    s->cur_cls = cls;
+    (void)hipEventRecord(s->ev[s->ev_used], s->stream);
+}
+
+void prof_end(np_solver* s)
+{
+    if (!s->prof) return;
+    (void)hipEventRecord(s->ev[s->ev_used + 1], s->stream);
+    s->ev_cls[s->ev_used / 2] = s->cur_cls;
+    s->ev_used += 2;
+}
+
+void prof_release(np_solver* s)
+{
+    for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
+    s->ev.clear();
+    s->ev_cls.clear();
+    s->ev_used = 0;
+    s->prof = false;
+}
+
 // One V-cycle (Sec. 2.3 steps 2-13) on nested level l in FP64.
 void vcycle(np_solver* s, int l)
 {
@@ -183,20 +232,32 @@ void vcycle(np_solver* s, int l)
     auto sweep = [&](int L) {
         for (int colour = 0; colour < 2; colour++) {
             if (L > 0) launch_ghost_fill<double>(d, st, g[L], u[L], s->plan.xn_is_one[l][L], s->plan.ghost_coef[l][L]);
-            launch_half_sweep<double>(d, st, g[L], u[L], f[L], colour, h[L] * h[L]);
+            if (L == 0) prof_begin(s, NP_KCLASS_SMOOTH);
+            launch_half_sweep<double>(d, st, g[L], u[L], f[L], colour, h[L] * h[L], L == 0);
+            if (L == 0) prof_end(s);
         }
     };
     for (int it = 0; it < c.n_pre; it++) sweep(0);
     int L = 0;
     while (s->plan.N[l][L] > 1) {
         if (L > 0) launch_ghost_fill<double>(d, st, g[L], u[L], s->plan.xn_is_one[l][L], s->plan.ghost_coef[l][L]);
+        if (L == 0) prof_begin(s, NP_KCLASS_RESTRICT);
         launch_resid_restrict<double>(d, st, g[L], u[L], f[L], 1.0 / (h[L] * h[L]), g[L + 1], f[L + 1], u[L + 1]);
+        if (L == 0) {
+            prof_end(s);
+            prof_begin(s, NP_KCLASS_COARSE);
+        }
         for (int it = 0; it < c.n_pre; it++) sweep(L + 1);
         L++;
     }
     while (L > 0) {
         launch_ghost_fill<double>(d, st, g[L], u[L], s->plan.xn_is_one[l][L], s->plan.ghost_coef[l][L]);
+        if (L == 1) {
+            prof_end(s);
+            prof_begin(s, NP_KCLASS_PROLONG);
+        }
         launch_prolong_add<double>(d, st, g[L], u[L], g[L - 1], u[L - 1]);
+        if (L == 1) prof_end(s);
         for (int it = 0; it < c.n_post; it++) sweep(L - 1);
         L--;
     }
@@ -207,7 +268,9 @@ int norm_sync(np_solver* s, int l, int mode, double* out)
 {
     double dx = std::ldexp(s->cfg.dx0, -l);
     launch_set_u64(s->stream, s->d_bits, 1, 0ULL);
+    prof_begin(s, NP_KCLASS_NORM);
     launch_norm(s->cfg.dim, s->stream, s->lg[l], s->phi[l], s->f[l], 1.0 / (dx * dx), mode, s->d_bits);
+    prof_end(s);
     HIPCHK(s, hipGetLastError());
     HIPCHK(s, hipMemcpyAsync(s->h_bits, s->d_bits, sizeof(unsigned long long), hipMemcpyDeviceToHost, s->stream));
     HIPCHK(s, hipStreamSynchronize(s->stream));
@@ -390,6 +453,7 @@ int nested_poisson_solve(np_solver* s, const double* const* rho, const double* p
     for (int l = 0; l < c.nlevels; l++) {
         auto t0 = std::chrono::steady_clock::now();
         s->hist[l].clear();
+        prof_begin(s, NP_KCLASS_FILL);
         if (l == 0) {
             launch_level0_init(d, s->stream, s->lg[0], rho[0], phi_outer, fourpiG, s->phi[0], s->f[0]);
         } else {
@@ -397,6 +461,7 @@ int nested_poisson_solve(np_solver* s, const double* const* rho, const double* p
                                   c.offset[l][0], c.offset[l][1], d == 3 ? c.offset[l][2] : 0, rho[l], fourpiG,
                                   s->phi[l], s->f[l]);
         }
+        prof_end(s);
         HIPCHK(s, hipGetLastError());
         double scale = 0.0;
         int rc = norm_sync(s, l, 1, &scale);
@@ -480,8 +545,10 @@ int nested_poisson_forces(np_solver* s, int level, double* fx, double* fy, doubl
     if (!fx || !fy || (s->cfg.dim == 3 && !fz)) return set_err(s, NP_EINVAL, "null force pointer");
     if (!s->solved) return set_err(s, NP_ESTATE, "forces requested before a successful solve");
     HIPCHK(s, hipSetDevice(s->device));
+    prof_begin(s, NP_KCLASS_FORCES);
     launch_forces(s->cfg.dim, s->stream, s->lg[level], s->cfg.n[level], std::ldexp(s->cfg.dx0, -level),
                   s->phi[level], fx, fy, fz);
+    prof_end(s);
     HIPCHK(s, hipGetLastError());
     return NP_OK;
 }
@@ -504,8 +571,56 @@ void nested_poisson_destroy(np_solver* s)
     (void)hipSetDevice(s->device);
     if (s->stream) (void)hipStreamSynchronize(s->stream);
     else (void)hipDeviceSynchronize();
+    prof_release(s);
     free_all(s);
     delete s;
+}
+
+int nested_poisson_set_profiling(np_solver* s, int enable)
+{
+    if (!s) return NP_EINVAL;
+    HIPCHK(s, hipSetDevice(s->device));
+    if (s->prof) {
+        int rc = prof_flush(s);
+        if (rc) return rc;
+    }
+    for (int c = 0; c < NP_NKCLASS; c++) {
+        s->prof_count[c] = 0;
+        s->prof_ms[c] = 0.0;
+    }
+    if (!enable) {
+        prof_release(s);
+        return NP_OK;
+    }
+    if (s->ev.empty()) {
+        const int pool = 4096;
+        s->ev.resize(pool);
+        s->ev_cls.resize(pool / 2);
+        for (int i = 0; i < pool; i++) {
+            if (hipEventCreate(&s->ev[i]) != hipSuccess) {
+                s->ev.resize(i);
+                prof_release(s);
+                return set_err(s, NP_EHIP, "hipEventCreate failed");
+            }
+        }
+    }
+    s->ev_used = 0;
+    s->prof = true;
+    return NP_OK;
+}
+
+int nested_poisson_get_profile(np_solver* s, np_profile* out)
+{
+    if (!s || !out) return NP_EINVAL;
+    if (!s->prof) return set_err(s, NP_ESTATE, "profiling is not enabled");
+    HIPCHK(s, hipSetDevice(s->device));
+    int rc = prof_flush(s);
+    if (rc) return rc;
+    for (int c = 0; c < NP_NKCLASS; c++) {
+        out->count[c] = s->prof_count[c];
+        out->ms[c] = s->prof_ms[c];
+    }
+    return NP_OK;
 }
 
 const char* nested_poisson_strerror(int code)

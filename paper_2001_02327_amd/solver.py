@@ -97,6 +97,15 @@ class NestedPoissonSolver:
         self._check(_lib.lib().nested_poisson_potential(self._h, level, ctypes.c_void_p(out.data_ptr())))
         return out
 
+    def set_profiling(self, enable=True):
+        self._check(_lib.lib().nested_poisson_set_profiling(self._h, int(bool(enable))))
+
+    def profile(self):
+        """{class: (launches, device ms)} since profiling was enabled."""
+        p = _lib.NpProfile()
+        self._check(_lib.lib().nested_poisson_get_profile(self._h, ctypes.byref(p)))
+        return {name: (p.count[i], p.ms[i]) for i, name in enumerate(_lib.KCLASSES)}
+
     def close(self):
         if self._h:
             _lib.lib().nested_poisson_destroy(self._h)
