@@ -108,6 +108,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="two_plummer")
     ap.add_argument("--N", type=int, default=512, help="cells per axis of every level")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32_dc", "fp16s_dc"])
+    ap.add_argument("--inner-cycles", type=int, default=1)
     ap.add_argument("--cpu-sample-cycles", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true", help="run only a 1 GiB device copy x5")
@@ -139,7 +141,7 @@ def main():
         raise SystemExit("bench workloads use the same cell count on every level")
     F = [torch.empty((n[0],) * geom.dim, dtype=torch.float64, device=dev) for _ in range(geom.dim)]
 
-    solver = NestedPoissonSolver(geom)
+    solver = NestedPoissonSolver(geom, precision=args.precision, inner_cycles=args.inner_cycles)
     stream = torch.cuda.current_stream()
 
     def step():
@@ -176,7 +178,8 @@ def main():
     # algorithmic bytes of one level-0 half sweep: read the other colour (8 B per
     # point of that colour), read f of this colour, write this colour:
     # 12 B per active point of the grid (both colours counted)
-    half_sweep_bytes = 12.0 * N0 ** geom.dim
+    elem = {"fp64": 8, "fp32_dc": 4, "fp16s_dc": 2}[args.precision]
+    half_sweep_bytes = 1.5 * elem * N0 ** geom.dim
     sm_count, sm_ms = prof["smooth"]
     sm_avg_ms = sm_ms / max(sm_count, 1)
     achieved = half_sweep_bytes / (sm_avg_ms * 1e-3) / 1e9
@@ -204,20 +207,20 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": {"fp64": "f64", "fp32_dc": "f64+f32", "fp16s_dc": "f64+f16/f32"}[args.precision],
         "data": "synthetic",
         "config": {
             "workload": wl.name,
             "levels": geom.nlevels,
             "cells_per_level": "%d^%d" % (n[0], geom.dim),
-            "precision": "fp64",
+            "precision": args.precision,
             "guess": "interp",
             "stop": "||r||_inf <= 1e-10 ||f||_inf per level",
             "step": "nested solve + forces on every level",
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_smooth_fine<3,double> (level-0 red-black half sweep)",
+            "kernel": "k_smooth_zmarch3 (level-0 red-black half sweep, %s storage)" % {8: "FP64", 4: "FP32", 2: "FP16"}[elem],
             "achieved": round(achieved, 1),
             "peak": PEAK_HBM_GBS,
             "unit": "GB/s",

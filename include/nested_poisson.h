@@ -171,6 +171,7 @@ int nested_poisson_potential(np_solver* s, int level, double* phi_padded);
 #define NP_KCLASS_NORM 4     /* max-norm reductions of the stop test */
 #define NP_KCLASS_FILL 5     /* level-0 setup and coarse-to-fine fills */
 #define NP_KCLASS_FORCES 6   /* force evaluation */
+#define NP_KCLASS_DC 7       /* FP64 residual / correction passes of the defect correction */
 #define NP_NKCLASS 8
 typedef struct np_profile {
     long count[NP_NKCLASS]; /* launches (intervals) recorded */

@@ -68,7 +68,7 @@ class NpStats(ctypes.Structure):
 
 
 NP_NKCLASS = 8
-KCLASSES = ["smooth", "restrict", "prolong", "coarse", "norm", "fill", "forces"]
+KCLASSES = ["smooth", "restrict", "prolong", "coarse", "norm", "fill", "forces", "dc"]
 
 
 class NpProfile(ctypes.Structure):

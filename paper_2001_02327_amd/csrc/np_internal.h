@@ -58,16 +58,27 @@ void launch_norm(int dim, hipStream_t st, SGrid g, const double* u, const double
                  unsigned long long* maxbits);
 void launch_set_u64(hipStream_t st, unsigned long long* p, int count, unsigned long long v);
 
-// multigrid operators, templated on storage type T (double, float)
+// multigrid operators, templated on the storage type (double, float; __half
+// only on multigrid level 0 of the FP16-storage defect correction)
 // fine != 0: the nested-level arrays (multigrid level 0, fixed ghost layer)
 template <typename T>
 void launch_half_sweep(int dim, hipStream_t st, SGrid g, T* u, const T* f, int colour, double h2, int fine);
 template <typename T>
 void launch_ghost_fill(int dim, hipStream_t st, SGrid g, T* u, int xn_is_one, double coef);
-template <typename T>
-void launch_resid_restrict(int dim, hipStream_t st, SGrid gf, const T* u, const T* f, double inv_h2, SGrid gc,
-                           T* fc, T* ec);
-template <typename T>
-void launch_prolong_add(int dim, hipStream_t st, SGrid gc, const T* ec, SGrid gf, T* u);
+// fine grid of type TF, coarse of type TC; the coarse right-hand side is multiplied by out_scale
+template <typename TF, typename TC>
+void launch_resid_restrict(int dim, hipStream_t st, SGrid gf, const TF* u, const TF* f, double inv_h2, double out_scale,
+                           SGrid gc, TC* fc, TC* ec);
+// black_only != 0 corrects only the black points
+template <typename TC, typename TF>
+void launch_prolong_add(int dim, hipStream_t st, SGrid gc, const TC* ec, SGrid gf, TF* u, int black_only);
+
+// defect correction: r = (f - lap phi) * rscale in low precision (+ its FP64 max
+// norm), clearing the black (and with clear_red the red) points of e; phi += factor * e
+template <typename TL>
+void launch_dc_residual(int dim, hipStream_t st, SGrid g, const double* phi, const double* f, double inv_h2,
+                        double rscale, TL* r, TL* e, int clear_red, unsigned long long* maxbits);
+template <typename TL>
+void launch_dc_update(int dim, hipStream_t st, SGrid g, double* phi, const TL* e, double factor);
 
 }  // namespace np

@@ -25,6 +25,49 @@ __device__ __forceinline__ long xcd_block()
     return x * q + (x < r ? x : r) + k;
 }
 
+// Strip ordering of a 3-D box of points (x fastest): the y range is cut into
+// strips of R rows and logical blocks run over (strip, z, block of the strip
+// plane).  With the XCD-contiguous numbering above, every XCD walks whole
+// strips plane by plane, so the planes a stencil revisits (z-neighbours) and
+// the rows it shares (y-neighbours) are still in that XCD's L2.
+struct Strip {
+    int nxa, nya, nza;  // box extents
+    int R;              // rows per strip
+    int B;              // blocks per strip plane
+};
+
+inline Strip make_strip(int nxa, int nya, int nza, int nstrip)
+{
+    Strip s;
+    s.nxa = nxa;
+    s.nya = nya;
+    s.nza = nza;
+    s.R = (nya + nstrip - 1) / nstrip;
+    s.B = (int)(((long)s.R * nxa + kBlock - 1) / kBlock);
+    return s;
+}
+
+inline long strip_blocks(const Strip& s)
+{
+    long nstrip = (s.nya + s.R - 1) / s.R;
+    return nstrip * s.nza * s.B;
+}
+
+__device__ __forceinline__ bool strip_point(const Strip& s, int& x, int& y, int& z)
+{
+    const long lb = xcd_block();
+    const long per = (long)s.nza * s.B;
+    const int st = (int)(lb / per);
+    const long rem = lb - st * per;
+    z = (int)(rem / s.B);
+    const int blk = (int)(rem - (long)z * s.B);
+    const int tin = blk * kBlock + threadIdx.x;
+    const int rr = tin / s.nxa;
+    x = tin - rr * s.nxa;
+    y = st * s.R + rr;
+    return rr < s.R && y < s.nya;
+}
+
 template <int D>
 __device__ __forceinline__ int colour_of(int pi, int pj, int pk)
 {
@@ -192,15 +235,19 @@ __device__ __forceinline__ double d4(const double* __restrict__ phi, const SGrid
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_forces(SGrid g, int n, double m12dx, const double* __restrict__ phi,
                                                    double* __restrict__ fx, double* __restrict__ fy,
-                                                   double* __restrict__ fz)
+                                                   double* __restrict__ fz, Strip sp)
 {
-    long t = xcd_block() * kBlock + threadIdx.x;
-    long total = D == 3 ? (long)n * n * n : (long)n * n;
-    if (t >= total) return;
-    int i = (int)(t % n);
-    long r = t / n;
-    int j = (int)(r % n);
-    int k = (int)(r / n);
+    int i, j, k = 0;
+    long t;
+    if (D == 3) {
+        if (!strip_point(sp, i, j, k)) return;
+        t = ((long)k * n + j) * n + i;
+    } else {
+        t = xcd_block() * kBlock + threadIdx.x;
+        if (t >= (long)n * n) return;
+        i = (int)(t % n);
+        j = (int)(t / n);
+    }
     int pi = i + 2, pj = j + 2, pk = D == 3 ? k + 2 : 0;
     fx[t] = d4<D>(phi, g, pi, pj, pk, 0, m12dx);
     fy[t] = d4<D>(phi, g, pi, pj, pk, 1, m12dx);
@@ -304,7 +351,7 @@ __global__ void __launch_bounds__(kBlock) k_norm(SGrid g, const double* __restri
 // k_smooth_fine3: a thread owns compact (h, pj), treats the red and the black
 // point of that position on every plane of its chunk, and keeps both colours'
 // values at pk-1, pk, pk+1 of its column in registers.
-constexpr int kNormChunk = 64;
+constexpr int kNormChunk = 8;
 
 __global__ void __launch_bounds__(kBlock) k_resid_norm3(SGrid g, const double* __restrict__ u,
                                                         const double* __restrict__ f, double inv_h2, int pblocks,
@@ -421,10 +468,10 @@ __global__ void __launch_bounds__(kBlock) k_smooth_fine(T* __restrict__ u, const
 // its L2.
 constexpr int kZChunk = 8;
 
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_smooth_fine3(T* __restrict__ u, const T* __restrict__ f, SGrid g, int colour,
-                                                         typename Compute<T>::type h2,
-                                                         typename Compute<T>::type inv2d, int pblocks)
+template <typename T, int TAG>
+__global__ void __launch_bounds__(kBlock) k_smooth_zmarch3(T* __restrict__ u, const T* __restrict__ f, SGrid g, int colour,
+                                                           typename Compute<T>::type h2,
+                                                           typename Compute<T>::type inv2d, int pblocks)
 {
     using C = typename Compute<T>::type;
     const int m = g.nx - 2;
@@ -558,15 +605,17 @@ __global__ void __launch_bounds__(kBlock) k_ghost_fill(T* __restrict__ u, SGrid 
 }
 
 // Residual r = f - lap(u) on the 2^d children of each coarse active point and
-// their mean (eqn:restriction2D/3D) into the coarse right-hand side;
-// children beyond the fine active range count as zero.  Also clears the
-// coarse correction.
-template <int D, typename T>
-__global__ void __launch_bounds__(kBlock) k_resid_restrict(const T* __restrict__ u, const T* __restrict__ f, SGrid gf,
-                                                           typename Compute<T>::type inv_h2, SGrid gc,
-                                                           T* __restrict__ fc, T* __restrict__ ec)
+// their mean (eqn:restriction2D/3D) into the coarse right-hand side, times
+// out_scale (1 except below a scaled level-0 defect problem); children beyond
+// the fine active range count as zero.  Also clears the coarse correction.
+// TF: fine storage, TC: coarse storage.
+template <int D, typename TF, typename TC>
+__global__ void __launch_bounds__(kBlock) k_resid_restrict(const TF* __restrict__ u, const TF* __restrict__ f, SGrid gf,
+                                                           typename Compute<TC>::type inv_h2,
+                                                           typename Compute<TC>::type out_scale, SGrid gc,
+                                                           TC* __restrict__ fc, TC* __restrict__ ec)
 {
-    using C = typename Compute<T>::type;
+    using C = typename Compute<TC>::type;
     int Nc = gc.nx - 2, Nf = gf.nx - 2;
     long t = xcd_block() * kBlock + threadIdx.x;
     long total = D == 3 ? (long)Nc * Nc * Nc : (long)Nc * Nc;
@@ -592,19 +641,22 @@ __global__ void __launch_bounds__(kBlock) k_resid_restrict(const T* __restrict__
                 C uc = (C)at<D>(u, gf, i, j, k);
                 sum += (C)at<D>(f, gf, i, j, k) - (s - (C)(2 * D) * uc) * inv_h2;
             }
-    size_t pc = pos<D, T>(gc, I, J, K);
-    fc[pc] = (T)(sum * (C)(D == 3 ? 0.125 : 0.25));
-    ec[pc] = (T)0;
+    size_t pc = pos<D, TC>(gc, I, J, K);
+    fc[pc] = (TC)(sum * ((C)(D == 3 ? 0.125 : 0.25) * out_scale));
+    ec[pc] = (TC)0;
 }
 
 // u += P(e) on the fine active points (eqn:prolongation2D/3D as the tensor
 // product of (3/4, 1/4) along each axis: the coarse parent ceil(p/2) weighs
 // 3/4, its neighbour on the side of the fine centre 1/4).  Each thread does
-// the red and the black point of one compact position.
-template <int D, typename T>
-__global__ void __launch_bounds__(kBlock) k_prolong_add(const T* __restrict__ e, SGrid gc, T* __restrict__ u, SGrid gf)
+// the red and the black point of one compact position; with black_only the
+// red points are left alone (used when a red half sweep that reads only
+// black values follows on a grid with a fixed ghost layer).
+template <int D, typename TC, typename TF>
+__global__ void __launch_bounds__(kBlock) k_prolong_add(const TC* __restrict__ e, SGrid gc, TF* __restrict__ u, SGrid gf,
+                                                        int black_only)
 {
-    using C = typename Compute<T>::type;
+    using C = typename Compute<TC>::type;
     int m = gf.nx - 2;
     long t = xcd_block() * kBlock + threadIdx.x;
     long total = (long)gf.hx * m * (D == 3 ? m : 1);
@@ -616,7 +668,7 @@ __global__ void __launch_bounds__(kBlock) k_prolong_add(const T* __restrict__ e,
     const C w0 = (C)0.75, w1 = (C)0.25;
     int qj = (pj + 1) >> 1, sj = (pj & 1) ? -1 : 1;
     int qk = D == 3 ? (pk + 1) >> 1 : 0, sk = (pk & 1) ? -1 : 1;
-    for (int c = 0; c < 2; c++) {
+    for (int c = black_only; c < 2; c++) {
         int pi = 2 * h + ((c + pj + pk + D) & 1);
         if (pi < 1 || pi > gf.nx - 2) continue;
         int qi = (pi + 1) >> 1, si = (pi & 1) ? -1 : 1;
@@ -629,7 +681,132 @@ __global__ void __launch_bounds__(kBlock) k_prolong_add(const T* __restrict__ e,
             v = w0 * v + w1 * (w0 * y2 + w1 * y3);
         }
         size_t p = (size_t)c * gf.cs + row_base(gf, pj, pk) + h;
-        u[p] = (T)((C)u[p] + v);
+        u[p] = (TF)((C)u[p] + v);
+    }
+}
+
+// ------------------------------------------------------------------ defect correction
+// Outer FP64 step of the mixed-precision solve: r64 = f - lap(phi) on the
+// level-0 active points (same arithmetic as the stop-test norm), its max
+// norm, and the scaled low-precision copy r = r64 * rscale; the correction e
+// is cleared where the first relaxation reads it (black only when a red half
+// sweep comes first, both colours otherwise).
+template <int D, typename TL>
+__global__ void __launch_bounds__(kBlock) k_dc_residual(SGrid g, const double* __restrict__ phi,
+                                                        const double* __restrict__ f, double inv_h2, double rscale,
+                                                        TL* __restrict__ r, TL* __restrict__ e, int clear_red,
+                                                        unsigned long long* maxbits)
+{
+    int m = g.nx - 2;
+    long total = (long)g.hx * m * (D == 3 ? m : 1);
+    long stride = (long)gridDim.x * kBlock;
+    size_t ny = (size_t)g.hx, nz = (size_t)g.nx * g.hx;
+    unsigned long long best = 0;
+    for (long t = xcd_block() * kBlock + threadIdx.x; t < total; t += stride) {
+        int h = (int)(t % g.hx);
+        long rr = t / g.hx;
+        int pj = 1 + (int)(rr % m);
+        int pk = D == 3 ? 1 + (int)(rr / m) : 0;
+        size_t row = row_base(g, pj, pk);
+        for (int c = 0; c < 2; c++) {
+            int pi = 2 * h + ((c + pj + pk + D) & 1);
+            if (pi < 1 || pi > g.nx - 2) continue;
+            const double* o = phi + (size_t)(c ^ 1) * g.cs;
+            size_t self = (size_t)c * g.cs + row + h;
+            double s = o[row + ((pi - 1) >> 1)];
+            s = s + o[row + ((pi + 1) >> 1)];
+            s = s + o[row - ny + h];
+            s = s + o[row + ny + h];
+            if (D == 3) {
+                s = s + o[row - nz + h];
+                s = s + o[row + nz + h];
+            }
+            double v = f[self] - (s - (2.0 * D) * phi[self]) * inv_h2;
+            r[self] = (TL)(float)(v * rscale);
+            if (c == 1 || clear_red) e[self] = (TL)0.0f;
+            unsigned long long b = abs_bits(v);
+            best = b > best ? b : best;
+        }
+    }
+    block_max_to(best, maxbits);
+}
+
+// 3-D form of k_dc_residual marching along z like k_resid_norm3 (both colours
+// of one compact column per thread, z-neighbours from registers).
+template <typename TL>
+__global__ void __launch_bounds__(kBlock) k_dc_residual3(SGrid g, const double* __restrict__ u,
+                                                         const double* __restrict__ f, double inv_h2, double rscale,
+                                                         TL* __restrict__ r, TL* __restrict__ e, int clear_red,
+                                                         int pblocks, unsigned long long* maxbits)
+{
+    const int m = g.nx - 2;
+    const long lb = xcd_block();
+    const int zc = (int)(lb / pblocks);
+    const long t = (lb - (long)zc * pblocks) * kBlock + threadIdx.x;
+    unsigned long long best = 0;
+    if (t < (long)g.hx * m) {
+        const int h = (int)(t % g.hx);
+        const int pj = 1 + (int)(t / g.hx);
+        const int k0 = 1 + zc * kNormChunk;
+        const int k1 = min(k0 + kNormChunk - 1, m);
+        const size_t plane = (size_t)g.nx * g.hx;
+        const size_t col = (size_t)pj * g.hx + h;
+        const double* __restrict__ a[2] = {u, u + g.cs};
+        double below[2], cur[2];
+        for (int c = 0; c < 2; c++) {
+            below[c] = a[c][(size_t)(k0 - 1) * plane + col];
+            cur[c] = a[c][(size_t)k0 * plane + col];
+        }
+        for (int pk = k0; pk <= k1; pk++) {
+            const size_t here = (size_t)pk * plane + col;
+            double above[2] = {a[0][here + plane], a[1][here + plane]};
+            for (int c = 0; c < 2; c++) {
+                const int o = c ^ 1;
+                const int par = (c + pj + pk + 3) & 1;
+                const int pi = 2 * h + par;
+                if (pi < 1 || pi > g.nx - 2) continue;
+                double xm = par ? cur[o] : a[o][here - 1];
+                double xp = par ? a[o][here + 1] : cur[o];
+                double s = xm + xp;
+                s = s + a[o][here - g.hx];
+                s = s + a[o][here + g.hx];
+                s = s + below[o];
+                s = s + above[o];
+                const size_t self = (size_t)c * g.cs + here;
+                double v = f[self] - (s - 6.0 * cur[c]) * inv_h2;
+                r[self] = (TL)(float)(v * rscale);
+                if (c == 1 || clear_red) e[self] = (TL)0.0f;
+                unsigned long long b = abs_bits(v);
+                best = b > best ? b : best;
+            }
+            for (int c = 0; c < 2; c++) {
+                below[c] = cur[c];
+                cur[c] = above[c];
+            }
+        }
+    }
+    block_max_to(best, maxbits);
+}
+
+// phi += factor * e on the level-0 active points (the FP64 correction update).
+template <int D, typename TL>
+__global__ void __launch_bounds__(kBlock) k_dc_update(SGrid g, double* __restrict__ phi, const TL* __restrict__ e,
+                                                      double factor)
+{
+    int m = g.nx - 2;
+    long t = xcd_block() * kBlock + threadIdx.x;
+    long total = (long)g.hx * m * (D == 3 ? m : 1);
+    if (t >= total) return;
+    int h = (int)(t % g.hx);
+    long rr = t / g.hx;
+    int pj = 1 + (int)(rr % m);
+    int pk = D == 3 ? 1 + (int)(rr / m) : 0;
+    size_t row = row_base(g, pj, pk);
+    for (int c = 0; c < 2; c++) {
+        int pi = 2 * h + ((c + pj + pk + D) & 1);
+        if (pi < 1 || pi > g.nx - 2) continue;
+        size_t self = (size_t)c * g.cs + row + h;
+        phi[self] += factor * (double)(float)e[self];
     }
 }
 
@@ -667,9 +844,10 @@ void launch_interface_fill(int dim, hipStream_t st, SGrid gc, const double* phic
 void launch_forces(int dim, hipStream_t st, SGrid g, int n, double dx, const double* phi, double* fx, double* fy,
                    double* fz)
 {
-    long total = dim == 3 ? (long)n * n * n : (long)n * n;
     double m12dx = -1.0 / (12.0 * dx);
-    NP_DISPATCH(dim, k_forces, dim3(ceil_div(total, kBlock)), dim3(kBlock), st, g, n, m12dx, phi, fx, fy, fz);
+    Strip sp = make_strip(n, n, dim == 3 ? n : 1, 16);
+    long blocks = dim == 3 ? strip_blocks(sp) : ceil_div((long)n * n, kBlock);
+    NP_DISPATCH(dim, k_forces, dim3(blocks), dim3(kBlock), st, g, n, m12dx, phi, fx, fy, fz, sp);
 }
 
 void launch_force_delta(int dim, hipStream_t st, SGrid g, int n, double dx, const double* phi, double* F,
@@ -712,15 +890,22 @@ void launch_half_sweep(int dim, hipStream_t st, SGrid g, T* u, const T* f, int c
     using C = typename Compute<T>::type;
     dim3 grid(ceil_div(ncompact_active(dim, g), kBlock));
     C inv2d = (C)(1.0 / (2.0 * dim));
+    if (dim == 3 && (fine || g.nx >= 34)) {
+        // z-march; the level-0 instance (TAG 0) is kept apart from the
+        // coarse-level one (TAG 1) so that profiles separate them
+        long m = g.nx - 2;
+        int pblocks = ceil_div((long)g.hx * m, kBlock);
+        int chunks = ceil_div(m, kZChunk);
+        if (fine)
+            hipLaunchKernelGGL((k_smooth_zmarch3<T, 0>), dim3(pblocks * chunks), dim3(kBlock), 0, st, u, f, g, colour,
+                               (C)h2, inv2d, pblocks);
+        else
+            hipLaunchKernelGGL((k_smooth_zmarch3<T, 1>), dim3(pblocks * chunks), dim3(kBlock), 0, st, u, f, g, colour,
+                               (C)h2, inv2d, pblocks);
+        return;
+    }
     if (fine) {
-        if (dim == 3) {
-            long m = g.nx - 2;
-            int pblocks = ceil_div((long)g.hx * m, kBlock);
-            int chunks = ceil_div(m, kZChunk);
-            hipLaunchKernelGGL((k_smooth_fine3<T>), dim3(pblocks * chunks), dim3(kBlock), 0, st, u, f, g, colour, (C)h2,
-                               inv2d, pblocks);
-        } else
-            hipLaunchKernelGGL((k_smooth_fine<2, T>), grid, dim3(kBlock), 0, st, u, f, g, colour, (C)h2, inv2d);
+        hipLaunchKernelGGL((k_smooth_fine<2, T>), grid, dim3(kBlock), 0, st, u, f, g, colour, (C)h2, inv2d);
     } else {
         if (dim == 3)
             hipLaunchKernelGGL((k_half_sweep<3, T>), grid, dim3(kBlock), 0, st, u, f, g, colour, (C)h2, inv2d);
@@ -741,37 +926,78 @@ void launch_ghost_fill(int dim, hipStream_t st, SGrid g, T* u, int xn_is_one, do
         hipLaunchKernelGGL((k_ghost_fill<2, T>), grid, dim3(kBlock), 0, st, u, g, xn_is_one, (C)coef);
 }
 
-template <typename T>
-void launch_resid_restrict(int dim, hipStream_t st, SGrid gf, const T* u, const T* f, double inv_h2, SGrid gc, T* fc,
-                           T* ec)
+template <typename TF, typename TC>
+void launch_resid_restrict(int dim, hipStream_t st, SGrid gf, const TF* u, const TF* f, double inv_h2, double out_scale,
+                           SGrid gc, TC* fc, TC* ec)
 {
-    using C = typename Compute<T>::type;
+    using C = typename Compute<TC>::type;
     long Nc = gc.nx - 2;
     long total = dim == 3 ? Nc * Nc * Nc : Nc * Nc;
     dim3 grid(ceil_div(total, kBlock));
     if (dim == 3)
-        hipLaunchKernelGGL((k_resid_restrict<3, T>), grid, dim3(kBlock), 0, st, u, f, gf, (C)inv_h2, gc, fc, ec);
+        hipLaunchKernelGGL((k_resid_restrict<3, TF, TC>), grid, dim3(kBlock), 0, st, u, f, gf, (C)inv_h2, (C)out_scale,
+                           gc, fc, ec);
     else
-        hipLaunchKernelGGL((k_resid_restrict<2, T>), grid, dim3(kBlock), 0, st, u, f, gf, (C)inv_h2, gc, fc, ec);
+        hipLaunchKernelGGL((k_resid_restrict<2, TF, TC>), grid, dim3(kBlock), 0, st, u, f, gf, (C)inv_h2, (C)out_scale,
+                           gc, fc, ec);
 }
 
-template <typename T>
-void launch_prolong_add(int dim, hipStream_t st, SGrid gc, const T* ec, SGrid gf, T* u)
+template <typename TC, typename TF>
+void launch_prolong_add(int dim, hipStream_t st, SGrid gc, const TC* ec, SGrid gf, TF* u, int black_only)
 {
     dim3 grid(ceil_div(ncompact_active(dim, gf), kBlock));
     if (dim == 3)
-        hipLaunchKernelGGL((k_prolong_add<3, T>), grid, dim3(kBlock), 0, st, ec, gc, u, gf);
+        hipLaunchKernelGGL((k_prolong_add<3, TC, TF>), grid, dim3(kBlock), 0, st, ec, gc, u, gf, black_only);
     else
-        hipLaunchKernelGGL((k_prolong_add<2, T>), grid, dim3(kBlock), 0, st, ec, gc, u, gf);
+        hipLaunchKernelGGL((k_prolong_add<2, TC, TF>), grid, dim3(kBlock), 0, st, ec, gc, u, gf, black_only);
 }
 
-#define NP_INSTANTIATE(T)                                                                                   \
-    template void launch_half_sweep<T>(int, hipStream_t, SGrid, T*, const T*, int, double, int);                 \
-    template void launch_ghost_fill<T>(int, hipStream_t, SGrid, T*, int, double);                           \
-    template void launch_resid_restrict<T>(int, hipStream_t, SGrid, const T*, const T*, double, SGrid, T*, T*); \
-    template void launch_prolong_add<T>(int, hipStream_t, SGrid, const T*, SGrid, T*);
+template <typename TL>
+void launch_dc_residual(int dim, hipStream_t st, SGrid g, const double* phi, const double* f, double inv_h2,
+                        double rscale, TL* r, TL* e, int clear_red, unsigned long long* maxbits)
+{
+    int blocks = ceil_div(ncompact_active(dim, g), kBlock);
+    if (blocks > 4096) blocks = 4096;
+    if (dim == 3) {
+        long m = g.nx - 2;
+        int pblocks = ceil_div((long)g.hx * m, kBlock);
+        int chunks = ceil_div(m, kNormChunk);
+        hipLaunchKernelGGL((k_dc_residual3<TL>), dim3(pblocks * chunks), dim3(kBlock), 0, st, g, phi, f, inv_h2,
+                           rscale, r, e, clear_red, pblocks, maxbits);
+    } else
+        hipLaunchKernelGGL((k_dc_residual<2, TL>), dim3(blocks), dim3(kBlock), 0, st, g, phi, f, inv_h2, rscale, r, e,
+                           clear_red, maxbits);
+}
 
-NP_INSTANTIATE(double)
-NP_INSTANTIATE(float)
+template <typename TL>
+void launch_dc_update(int dim, hipStream_t st, SGrid g, double* phi, const TL* e, double factor)
+{
+    dim3 grid(ceil_div(ncompact_active(dim, g), kBlock));
+    if (dim == 3)
+        hipLaunchKernelGGL((k_dc_update<3, TL>), grid, dim3(kBlock), 0, st, g, phi, e, factor);
+    else
+        hipLaunchKernelGGL((k_dc_update<2, TL>), grid, dim3(kBlock), 0, st, g, phi, e, factor);
+}
+
+template void launch_half_sweep<double>(int, hipStream_t, SGrid, double*, const double*, int, double, int);
+template void launch_half_sweep<float>(int, hipStream_t, SGrid, float*, const float*, int, double, int);
+template void launch_half_sweep<__half>(int, hipStream_t, SGrid, __half*, const __half*, int, double, int);
+template void launch_ghost_fill<double>(int, hipStream_t, SGrid, double*, int, double);
+template void launch_ghost_fill<float>(int, hipStream_t, SGrid, float*, int, double);
+template void launch_resid_restrict<double, double>(int, hipStream_t, SGrid, const double*, const double*, double,
+                                                    double, SGrid, double*, double*);
+template void launch_resid_restrict<float, float>(int, hipStream_t, SGrid, const float*, const float*, double, double,
+                                                  SGrid, float*, float*);
+template void launch_resid_restrict<__half, float>(int, hipStream_t, SGrid, const __half*, const __half*, double,
+                                                   double, SGrid, float*, float*);
+template void launch_prolong_add<double, double>(int, hipStream_t, SGrid, const double*, SGrid, double*, int);
+template void launch_prolong_add<float, float>(int, hipStream_t, SGrid, const float*, SGrid, float*, int);
+template void launch_prolong_add<float, __half>(int, hipStream_t, SGrid, const float*, SGrid, __half*, int);
+template void launch_dc_residual<float>(int, hipStream_t, SGrid, const double*, const double*, double, double, float*,
+                                        float*, int, unsigned long long*);
+template void launch_dc_residual<__half>(int, hipStream_t, SGrid, const double*, const double*, double, double,
+                                         __half*, __half*, int, unsigned long long*);
+template void launch_dc_update<float>(int, hipStream_t, SGrid, double*, const float*, double);
+template void launch_dc_update<__half>(int, hipStream_t, SGrid, double*, const __half*, double);
 
 }  // namespace np

@@ -46,7 +46,8 @@ bool validate(const np_config* c, char* why, size_t nwhy)
     if (!(c->tol > 0.0)) return fail("tol must be positive%s", 0, 0);
     if (c->max_cycles < 1 || c->max_cycles > NP_MAX_CYCLES) return fail("max_cycles must be 1..%d (got %d)", NP_MAX_CYCLES, c->max_cycles);
     if (c->stop_rule != NP_STOP_RESIDUAL && c->stop_rule != NP_STOP_FORCE_DELTA) return fail("bad stop_rule %d%s", c->stop_rule, 0);
-    if (c->precision != NP_PREC_FP64) return fail("precision %d not available in this build%s", c->precision, 0);
+    if (c->precision != NP_PREC_FP64 && c->precision != NP_PREC_FP32_DC && c->precision != NP_PREC_FP16S_DC)
+        return fail("bad precision %d%s", c->precision, 0);
     if (c->guess != NP_GUESS_INTERP) return fail("guess %d not available in this build%s", c->guess, 0);
     if (c->inner_cycles < 1 || c->inner_cycles > 8) return fail("inner_cycles must be 1..8 (got %d)%s", c->inner_cycles, 0);
     return true;
@@ -147,6 +148,17 @@ struct np_solver {
     int cur_cls = 0;
     long prof_count[NP_NKCLASS] = {};
     double prof_ms[NP_NKCLASS] = {};
+    // coarse part of the V-cycle as one HIP graph per nested level
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t coarse_exec[NP_MAX_LEVELS] = {};
+    // mixed-precision defect correction: level-0 correction and defect in
+    // FP32 or FP16 (colour-split, sized for the largest level), FP32 coarse levels
+    void* e_lo = nullptr;
+    void* r_lo = nullptr;
+    size_t lo_bytes = 0;
+    float* mg_u32[NP_MAX_MG] = {};
+    float* mg_f32[NP_MAX_MG] = {};
+    hipGraphExec_t coarse_exec32[NP_MAX_LEVELS] = {};
 };
 
 namespace {
@@ -211,56 +223,149 @@ void prof_release(np_solver* s)
     s->prof = false;
 }
 
-// One V-cycle (Sec. 2.3 steps 2-13) on nested level l in FP64.
-void vcycle(np_solver* s, int l)
+// Pointers, grids and spacings of the multigrid levels L >= 1 of nested level
+// l (entry 0 describes multigrid level 0 for grid and spacing only).
+template <typename T>
+struct MGView {
+    int nmg;
+    T* u[NP_MAX_MG];
+    T* f[NP_MAX_MG];
+    SGrid g[NP_MAX_MG];
+    double h[NP_MAX_MG];
+};
+
+template <typename T>
+MGView<T> mg_view(const np_solver* s, int l, T* const* mu, T* const* mf)
+{
+    MGView<T> v;
+    v.nmg = s->plan.nmg[l];
+    double dx = std::ldexp(s->cfg.dx0, -l);
+    for (int L = 0; L < v.nmg; L++) {
+        v.u[L] = L == 0 ? nullptr : mu[L];
+        v.f[L] = L == 0 ? nullptr : mf[L];
+        v.g[L] = L == 0 ? s->lg[l] : mg_grid(s, l, L);
+        v.h[L] = std::ldexp(dx, L);
+    }
+    return v;
+}
+
+// One red-black sweep on multigrid level L >= 1: ghost layer refreshed from the
+// interior before each half sweep (Sec. 2.4, last paragraph).
+template <typename T>
+void coarse_sweep(const np_solver* s, int l, const MGView<T>& v, int L, hipStream_t st)
+{
+    const int d = s->cfg.dim;
+    for (int colour = 0; colour < 2; colour++) {
+        launch_ghost_fill<T>(d, st, v.g[L], v.u[L], s->plan.xn_is_one[l][L], s->plan.ghost_coef[l][L]);
+        launch_half_sweep<T>(d, st, v.g[L], v.u[L], v.f[L], colour, v.h[L] * v.h[L], 0);
+    }
+}
+
+// Everything a V-cycle does on levels L >= 1 (Sec. 2.3 steps 6-13 below the
+// finest multigrid level): from the pre-smoothing of level 1 down to the
+// coarsest level and back up to the ghost refresh of level 1 that precedes the
+// prolongation into level 0.  The sequence is the same in every cycle of a
+// nested level, so it is captured once into a HIP graph.
+template <typename T>
+void coarse_part(const np_solver* s, int l, const MGView<T>& v, hipStream_t st)
 {
     const np_config& c = s->cfg;
     const int d = c.dim;
-    const int nmg = s->plan.nmg[l];
-    hipStream_t st = s->stream;
-    double dx = std::ldexp(c.dx0, -l);
-    double* u[NP_MAX_MG];
-    double* f[NP_MAX_MG];
-    SGrid g[NP_MAX_MG];
-    double h[NP_MAX_MG];
-    for (int L = 0; L < nmg; L++) {
-        u[L] = L == 0 ? s->phi[l] : s->mg_u[L];
-        f[L] = L == 0 ? s->f[l] : s->mg_f[L];
-        g[L] = L == 0 ? s->lg[l] : mg_grid(s, l, L);
-        h[L] = std::ldexp(dx, L);
-    }
-    auto sweep = [&](int L) {
-        for (int colour = 0; colour < 2; colour++) {
-            if (L > 0) launch_ghost_fill<double>(d, st, g[L], u[L], s->plan.xn_is_one[l][L], s->plan.ghost_coef[l][L]);
-            if (L == 0) prof_begin(s, NP_KCLASS_SMOOTH);
-            launch_half_sweep<double>(d, st, g[L], u[L], f[L], colour, h[L] * h[L], L == 0);
-            if (L == 0) prof_end(s);
-        }
-    };
-    for (int it = 0; it < c.n_pre; it++) sweep(0);
-    int L = 0;
+    for (int it = 0; it < c.n_pre; it++) coarse_sweep(s, l, v, 1, st);
+    int L = 1;
     while (s->plan.N[l][L] > 1) {
-        if (L > 0) launch_ghost_fill<double>(d, st, g[L], u[L], s->plan.xn_is_one[l][L], s->plan.ghost_coef[l][L]);
-        if (L == 0) prof_begin(s, NP_KCLASS_RESTRICT);
-        launch_resid_restrict<double>(d, st, g[L], u[L], f[L], 1.0 / (h[L] * h[L]), g[L + 1], f[L + 1], u[L + 1]);
-        if (L == 0) {
-            prof_end(s);
-            prof_begin(s, NP_KCLASS_COARSE);
-        }
-        for (int it = 0; it < c.n_pre; it++) sweep(L + 1);
+        launch_ghost_fill<T>(d, st, v.g[L], v.u[L], s->plan.xn_is_one[l][L], s->plan.ghost_coef[l][L]);
+        launch_resid_restrict<T, T>(d, st, v.g[L], v.u[L], v.f[L], 1.0 / (v.h[L] * v.h[L]), 1.0, v.g[L + 1], v.f[L + 1],
+                                    v.u[L + 1]);
+        for (int it = 0; it < c.n_pre; it++) coarse_sweep(s, l, v, L + 1, st);
         L++;
     }
-    while (L > 0) {
-        launch_ghost_fill<double>(d, st, g[L], u[L], s->plan.xn_is_one[l][L], s->plan.ghost_coef[l][L]);
-        if (L == 1) {
-            prof_end(s);
-            prof_begin(s, NP_KCLASS_PROLONG);
-        }
-        launch_prolong_add<double>(d, st, g[L], u[L], g[L - 1], u[L - 1]);
-        if (L == 1) prof_end(s);
-        for (int it = 0; it < c.n_post; it++) sweep(L - 1);
+    while (L > 1) {
+        launch_ghost_fill<T>(d, st, v.g[L], v.u[L], s->plan.xn_is_one[l][L], s->plan.ghost_coef[l][L]);
+        launch_prolong_add<T, T>(d, st, v.g[L], v.u[L], v.g[L - 1], v.u[L - 1], 0);
+        for (int it = 0; it < c.n_post; it++) coarse_sweep(s, l, v, L - 1, st);
         L--;
     }
+    launch_ghost_fill<T>(d, st, v.g[1], v.u[1], s->plan.xn_is_one[l][1], s->plan.ghost_coef[l][1]);
+}
+
+template <typename T>
+int run_coarse(np_solver* s, int l, const MGView<T>& v, hipGraphExec_t* exec)
+{
+    if (!s->cap_stream) {
+        coarse_part(s, l, v, s->stream);
+        HIPCHK(s, hipGetLastError());
+        return NP_OK;
+    }
+    if (!exec[l]) {
+        HIPCHK(s, hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
+        coarse_part(s, l, v, s->cap_stream);
+        hipGraph_t graph = nullptr;
+        HIPCHK(s, hipStreamEndCapture(s->cap_stream, &graph));
+        hipError_t e = hipGraphInstantiate(&exec[l], graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            exec[l] = nullptr;
+            return set_err(s, NP_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+        }
+    }
+    HIPCHK(s, hipGraphLaunch(exec[l], s->stream));
+    return NP_OK;
+}
+
+// One V-cycle (Sec. 2.3 steps 2-13) on nested level l.  Multigrid level 0 is
+// (u0, f0) of type T0 with half-sweep factor h2_0 and residual factor
+// inv_h2_0; the restricted right-hand side is multiplied by out_scale_0; the
+// coarse levels are of type TC.
+template <typename T0, typename TC>
+int vcycle_t(np_solver* s, int l, T0* u0, const T0* f0, double h2_0, double inv_h2_0, double out_scale_0,
+             const MGView<TC>& v, hipGraphExec_t* exec)
+{
+    const np_config& c = s->cfg;
+    const int d = c.dim;
+    hipStream_t st = s->stream;
+    auto sweep0 = [&]() {
+        for (int colour = 0; colour < 2; colour++) {
+            prof_begin(s, NP_KCLASS_SMOOTH);
+            launch_half_sweep<T0>(d, st, v.g[0], u0, f0, colour, h2_0, 1);
+            prof_end(s);
+        }
+    };
+    for (int it = 0; it < c.n_pre; it++) sweep0();
+    prof_begin(s, NP_KCLASS_RESTRICT);
+    launch_resid_restrict<T0, TC>(d, st, v.g[0], u0, f0, inv_h2_0, out_scale_0, v.g[1], v.f[1], v.u[1]);
+    prof_end(s);
+    prof_begin(s, NP_KCLASS_COARSE);
+    int rc = run_coarse(s, l, v, exec);
+    prof_end(s);
+    if (rc) return rc;
+    prof_begin(s, NP_KCLASS_PROLONG);
+    // on level 0 (fixed ghost layer) the red corrections are dead when a
+    // post-smoothing red half sweep follows: it reads only black points
+    launch_prolong_add<TC, T0>(d, st, v.g[1], v.u[1], v.g[0], u0, c.n_post > 0);
+    prof_end(s);
+    for (int it = 0; it < c.n_post; it++) sweep0();
+    return NP_OK;
+}
+
+// Plain FP64 V-cycle on the level's potential.
+int vcycle(np_solver* s, int l)
+{
+    MGView<double> v = mg_view<double>(s, l, s->mg_u, s->mg_f);
+    double h = v.h[0];
+    return vcycle_t<double, double>(s, l, s->phi[l], s->f[l], h * h, 1.0 / (h * h), 1.0, v, s->coarse_exec);
+}
+
+// Inner V-cycle of the defect correction, on the scaled level-0 problem
+// L e'' = r'' (L = h^2 lap, the integer stencil, r'' = r / ||r||) in low
+// precision TL, with FP32 coarse levels: the coarse right-hand side is
+// R(r'' - L e'') / h^2, in the same units as e''.
+template <typename TL>
+int vcycle_lo(np_solver* s, int l)
+{
+    MGView<float> v = mg_view<float>(s, l, s->mg_u32, s->mg_f32);
+    double h = v.h[0];
+    return vcycle_t<TL, float>(s, l, (TL*)s->e_lo, (const TL*)s->r_lo, 1.0, 1.0, 1.0 / (h * h), v, s->coarse_exec32);
 }
 
 // Queue a norm into slot `slot` and return it (host-synchronous).
@@ -290,8 +395,58 @@ int force_delta_sync(np_solver* s, int l, double* out)
     return NP_OK;
 }
 
+// Defect-correction residual of level l: r'' = (f - lap phi) * rscale into the
+// low-precision defect, correction cleared; returns ||f - lap phi||_inf.
+int dc_residual_sync(np_solver* s, int l, double rscale, double* out)
+{
+    const np_config& c = s->cfg;
+    double dx = std::ldexp(c.dx0, -l);
+    int clear_red = c.n_pre == 0;
+    launch_set_u64(s->stream, s->d_bits, 1, 0ULL);
+    prof_begin(s, NP_KCLASS_DC);
+    if (c.precision == NP_PREC_FP16S_DC)
+        launch_dc_residual<__half>(c.dim, s->stream, s->lg[l], s->phi[l], s->f[l], 1.0 / (dx * dx), rscale,
+                                   (__half*)s->r_lo, (__half*)s->e_lo, clear_red, s->d_bits);
+    else
+        launch_dc_residual<float>(c.dim, s->stream, s->lg[l], s->phi[l], s->f[l], 1.0 / (dx * dx), rscale,
+                                  (float*)s->r_lo, (float*)s->e_lo, clear_red, s->d_bits);
+    prof_end(s);
+    HIPCHK(s, hipGetLastError());
+    HIPCHK(s, hipMemcpyAsync(s->h_bits, s->d_bits, sizeof(unsigned long long), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    *out = bits_to_double(s->h_bits[0]);
+    return NP_OK;
+}
+
+// One defect-correction step (extension of Sec. 2.3 with FP32 or FP16-stored
+// inner cycles): inner_cycles low-precision V-cycles on the scaled defect
+// r'' = r / r_scale, then phi += h^2 r_scale e'' in FP64.
+int dc_step(np_solver* s, int l, double r_scale)
+{
+    const np_config& c = s->cfg;
+    for (int it = 0; it < c.inner_cycles; it++) {
+        int rc = c.precision == NP_PREC_FP16S_DC ? vcycle_lo<__half>(s, l) : vcycle_lo<float>(s, l);
+        if (rc) return rc;
+    }
+    double dx = std::ldexp(c.dx0, -l);
+    prof_begin(s, NP_KCLASS_DC);
+    if (c.precision == NP_PREC_FP16S_DC)
+        launch_dc_update<__half>(c.dim, s->stream, s->lg[l], s->phi[l], (const __half*)s->e_lo, dx * dx * r_scale);
+    else
+        launch_dc_update<float>(c.dim, s->stream, s->lg[l], s->phi[l], (const float*)s->e_lo, dx * dx * r_scale);
+    prof_end(s);
+    HIPCHK(s, hipGetLastError());
+    return NP_OK;
+}
+
 void free_all(np_solver* s)
 {
+    for (int l = 0; l < NP_MAX_LEVELS; l++) {
+        if (s->coarse_exec[l]) (void)hipGraphExecDestroy(s->coarse_exec[l]);
+        s->coarse_exec[l] = nullptr;
+    }
+    if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
+    s->cap_stream = nullptr;
     for (int l = 0; l < NP_MAX_LEVELS; l++) {
         if (s->phi[l]) (void)hipFree(s->phi[l]);
         if (s->f[l]) (void)hipFree(s->f[l]);
@@ -300,8 +455,18 @@ void free_all(np_solver* s)
     for (int L = 0; L < NP_MAX_MG; L++) {
         if (s->mg_u[L]) (void)hipFree(s->mg_u[L]);
         if (s->mg_f[L]) (void)hipFree(s->mg_f[L]);
+        if (s->mg_u32[L]) (void)hipFree(s->mg_u32[L]);
+        if (s->mg_f32[L]) (void)hipFree(s->mg_f32[L]);
         s->mg_u[L] = s->mg_f[L] = nullptr;
+        s->mg_u32[L] = s->mg_f32[L] = nullptr;
     }
+    for (int l = 0; l < NP_MAX_LEVELS; l++) {
+        if (s->coarse_exec32[l]) (void)hipGraphExecDestroy(s->coarse_exec32[l]);
+        s->coarse_exec32[l] = nullptr;
+    }
+    if (s->e_lo) (void)hipFree(s->e_lo);
+    if (s->r_lo) (void)hipFree(s->r_lo);
+    s->e_lo = s->r_lo = nullptr;
     if (s->force_scratch) (void)hipFree(s->force_scratch);
     if (s->d_bits) (void)hipFree(s->d_bits);
     if (s->h_bits) (void)hipHostFree(s->h_bits);
@@ -386,7 +551,9 @@ int nested_poisson_create(const np_config* cfg, void* hip_stream, np_solver** ou
         if (rc == NP_OK) rc = alloc_dev(s, (void**)&s->f[l], bytes);
         if (cfg->n[l] > maxn) maxn = cfg->n[l];
     }
-    // multigrid scratch: per level L the largest grid over the nested levels
+    // multigrid scratch: per level L the largest grid over the nested levels,
+    // FP64 for the plain solve, FP32 for the defect correction's inner cycles
+    const bool dc = cfg->precision != NP_PREC_FP64;
     for (int L = 1; L < NP_MAX_MG && rc == NP_OK; L++) {
         size_t best = 0;
         for (int l = 0; l < cfg->nlevels; l++)
@@ -395,8 +562,22 @@ int nested_poisson_create(const np_config* cfg, void* hip_stream, np_solver** ou
                 if (b > best) best = b;
             }
         if (!best) break;
-        rc = alloc_dev(s, (void**)&s->mg_u[L], best * sizeof(double));
-        if (rc == NP_OK) rc = alloc_dev(s, (void**)&s->mg_f[L], best * sizeof(double));
+        if (dc) {
+            rc = alloc_dev(s, (void**)&s->mg_u32[L], best * sizeof(float));
+            if (rc == NP_OK) rc = alloc_dev(s, (void**)&s->mg_f32[L], best * sizeof(float));
+        } else {
+            rc = alloc_dev(s, (void**)&s->mg_u[L], best * sizeof(double));
+            if (rc == NP_OK) rc = alloc_dev(s, (void**)&s->mg_f[L], best * sizeof(double));
+        }
+    }
+    if (rc == NP_OK && dc) {
+        size_t best = 0;
+        for (int l = 0; l < cfg->nlevels; l++)
+            if (2 * s->lg[l].cs > best) best = 2 * s->lg[l].cs;
+        size_t esz = cfg->precision == NP_PREC_FP16S_DC ? sizeof(__half) : sizeof(float);
+        s->lo_bytes = best * esz;
+        rc = alloc_dev(s, &s->e_lo, s->lo_bytes);
+        if (rc == NP_OK) rc = alloc_dev(s, &s->r_lo, s->lo_bytes);
     }
     if (rc == NP_OK && cfg->stop_rule == NP_STOP_FORCE_DELTA) {
         size_t cells = (size_t)maxn * maxn * (d == 3 ? maxn : 1);
@@ -415,6 +596,11 @@ int nested_poisson_create(const np_config* cfg, void* hip_stream, np_solver** ou
         return rc;
     }
     for (int l = 0; l < NP_MAX_LEVELS; l++) s->fixed[l] = -1;
+    // private stream used only to record the coarse-cycle graphs (nothing runs on it)
+    if (hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        s->cap_stream = nullptr;  // launch the coarse part directly instead
+    }
     *out = s;
     return NP_OK;
 }
@@ -485,6 +671,16 @@ int nested_poisson_solve(np_solver* s, const double* const* rho, const double* p
         s->hist[l].push_back(scale > 0 ? r / scale : r);
         int q = 0;
         int lvl = NP_OK;
+        // defect correction: r_lo holds (f - lap phi) / r_scale for the current phi
+        const bool dc = c.precision != NP_PREC_FP64;
+        bool have_defect = false;
+        double r_scale = 1.0;
+        if (dc) {
+            // multigrid level 0 of the correction has a zero ghost layer; clear the
+            // whole array once per level (it is shared by levels of other sizes)
+            size_t esz = c.precision == NP_PREC_FP16S_DC ? sizeof(__half) : sizeof(float);
+            HIPCHK(s, hipMemsetAsync(s->e_lo, 0, 2 * s->lg[l].cs * esz, s->stream));
+        }
         for (;;) {
             if (!std::isfinite(r)) { lvl = NP_ENONFINITE; break; }
             if (pinned) {
@@ -493,11 +689,31 @@ int nested_poisson_solve(np_solver* s, const double* const* rho, const double* p
                 break;
             }
             if (q >= c.max_cycles) { lvl = NP_ENOTCONV; break; }
-            vcycle(s, l);
-            HIPCHK(s, hipGetLastError());
-            q++;
-            rc = norm_sync(s, l, 0, &r);
-            if (rc) return rc;
+            if (dc) {
+                if (!have_defect) {
+                    double same = 0.0;
+                    r_scale = r > 0 ? r : 1.0;
+                    rc = dc_residual_sync(s, l, 1.0 / r_scale, &same);
+                    if (rc) return rc;
+                    have_defect = true;
+                }
+                rc = dc_step(s, l, r_scale);
+                if (rc) return rc;
+                q++;
+                // residual of the updated potential, scaled by the previous norm
+                // (the new one is not known until this pass ends)
+                double rprev = r > 0 ? r : 1.0;
+                rc = dc_residual_sync(s, l, 1.0 / rprev, &r);
+                if (rc) return rc;
+                r_scale = rprev;
+            } else {
+                rc = vcycle(s, l);
+                if (rc) return rc;
+                HIPCHK(s, hipGetLastError());
+                q++;
+                rc = norm_sync(s, l, 0, &r);
+                if (rc) return rc;
+            }
             s->hist[l].push_back(scale > 0 ? r / scale : r);
             if (!std::isfinite(r)) { lvl = NP_ENONFINITE; break; }
             if (r0 > 0 && r > 1e3 * r0) { lvl = NP_EDIVERGED; break; }

@@ -1,0 +1,100 @@
+"""Mixed-precision defect correction on the GPU (FP32 or FP16-stored inner
+V-cycles inside an FP64 outer residual and correction).
+
+The inner cycles solve the scaled level-0 problem in low precision, so their
+iterates differ from the FP64 schedule; what must hold is that the FP64 outer
+iteration reaches the same discrete solution to the stop tolerance.  Bars:
+  * potential vs the oracle's solution converged to 1e-13:
+        max|dPhi| / max|Phi| <= 1e-8 (the 1e-10 residual stop bounds the
+        error by about cond * 1e-10 relative in the worst mode; 1e-8 leaves
+        room for that and is far above FP64 rounding);
+  * composite Linf force error vs the closed form equal to the FP64 solve's
+    within 0.5 %;
+  * outer steps within two of the FP64 cycle count (one FP32 or FP16 inner
+    V-cycle contracts the error like an FP64 one as long as its rounding,
+    ~1e-7 or ~5e-4 relative, stays below the ~0.3 contraction).
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import core
+from paper_2001_02327_amd import workloads as W
+from paper_2001_02327_amd.solver import NestedPoissonSolver
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need the MI355X"
+
+
+def _solve(wl, **kw):
+    dev = torch.device("cuda")
+    rho, po = W.make_inputs(wl.geom, wl.prob, device=dev)
+    s = NestedPoissonSolver(wl.geom, **kw)
+    st = s.solve(rho, po)
+    phi = [s.potential(l).cpu().numpy() for l in range(wl.geom.nlevels)]
+    F = [tuple(a.cpu().numpy() for a in s.forces(l)) for l in range(wl.geom.nlevels)]
+    s.close()
+    return phi, F, st
+
+
+def _linf_force_error(wl, F):
+    from oracle import norms
+    errs = []
+    for l in range(wl.geom.nlevels):
+        x = wl.geom.mesh(l, 0, wl.geom.n[l])
+        Fa = [a.numpy() for a in wl.prob.force(*x)]
+        errs.append(np.sqrt(sum((F[l][a] - Fa[a]) ** 2 for a in range(wl.geom.dim))))
+    return norms.composite_norms(wl.geom, errs)[2]
+
+
+CASES = [W.c2_plummer(32), W.paper2d(32), W.c3_plummer_offset(32), W.c4_multi_plummer(7, N=32), W.paper3d(16)]
+
+
+@pytest.mark.parametrize("precision", ["fp32_dc", "fp16s_dc"])
+@pytest.mark.parametrize("wl", CASES, ids=lambda w: w.name)
+def test_dc_reaches_fp64_solution(wl, precision):
+    rho, po = W.make_inputs(wl.geom, wl.prob)
+    ref = core.solve(wl.geom, [r.numpy() for r in rho], po.numpy(), tol=1e-13, max_cycles=120)
+    phi64, F64, st64 = _solve(wl)
+    phi, F, st = _solve(wl, precision=precision)
+    for l in range(wl.geom.nlevels):
+        err = np.abs(phi[l] - ref["phi"][l]).max() / np.abs(ref["phi"][l]).max()
+        assert err <= 1e-8, (l, err)
+        assert st["final_rel_residual"][l] <= 1e-10
+        assert st["cycles"][l] <= st64["cycles"][l] + 2, (st["cycles"], st64["cycles"])
+    e64 = _linf_force_error(wl, F64)
+    e = _linf_force_error(wl, F)
+    assert abs(e - e64) <= 5e-3 * e64, (e, e64)
+
+
+@pytest.mark.parametrize("precision", ["fp32_dc", "fp16s_dc"])
+def test_dc_inner_cycles_and_stress(precision):
+    """Two inner cycles per step; the offset a = 0.02 Plummer puts ||4 pi G rho||
+    near 3.7e5, beyond FP16 range unless the defect is scaled."""
+    wl = W.c3_plummer_offset(64)
+    phi64, F64, st64 = _solve(wl)
+    phi, F, st = _solve(wl, precision=precision, inner_cycles=2)
+    for l in range(wl.geom.nlevels):
+        err = np.abs(phi[l] - phi64[l]).max() / np.abs(phi64[l]).max()
+        assert err <= 1e-8, (l, err)
+        assert st["cycles"][l] <= st64["cycles"][l]
+    e64 = _linf_force_error(wl, F64)
+    assert abs(_linf_force_error(wl, F) - e64) <= 5e-3 * e64
+
+
+def test_dc_zero_density_and_force_rule():
+    geom = W.centred_geometry(3, 2, 16, 0.5, 1.0)
+    wl = W.Workload("linear", geom, W.Linear([0.7, -1.3, 0.4], 2.0))
+    phi, F, st = _solve(wl, precision="fp32_dc", tol=1e-12, max_cycles=80)
+    for l in range(geom.nlevels):
+        x = geom.mesh(l, -2, geom.n[l] + 4)
+        np.testing.assert_allclose(phi[l], wl.prob.phi(*x).numpy(), rtol=0, atol=1e-9)
+    wl = W.paper3d(16)
+    phi64, _, st64 = _solve(wl, stop_rule="force_delta")
+    phi, _, st = _solve(wl, precision="fp32_dc", stop_rule="force_delta")
+    for l in range(wl.geom.nlevels):
+        assert np.abs(phi[l] - phi64[l]).max() / np.abs(phi64[l]).max() <= 1e-8

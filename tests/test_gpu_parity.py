@@ -135,8 +135,10 @@ def test_cycle_by_cycle(wl):
         assert_parity(wl, phi_g, F_g, res, F_o)
 
 
-@pytest.mark.parametrize("n_pre,n_post", [(1, 1), (3, 2), (0, 2)])
+@pytest.mark.parametrize("n_pre,n_post", [(1, 1), (3, 2), (0, 2), (2, 0)])
 def test_other_smoothing_counts(n_pre, n_post):
+    """Other smoothing counts; n_post = 0 takes the full (both-colour)
+    prolongation into level 0, n_post > 0 the black-only one."""
     wl = W.c2_plummer(16)
     res, F_o = oracle_solve(wl, n_pre=n_pre, n_post=n_post, max_cycles=120)
     phi_g, F_g, st, _ = gpu_solve(wl, fixed=res["cycles"], n_pre=n_pre, n_post=n_post, max_cycles=120)
