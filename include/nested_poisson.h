@@ -137,6 +137,8 @@ typedef struct np_stats {
     double scale[NP_MAX_LEVELS];              /* reference norm of the stop test */
     double level_ms[NP_MAX_LEVELS];           /* host wall time per level */
     double total_ms;
+    int learned_used[NP_MAX_LEVELS];          /* 1 where the learned guess was kept */
+    double interp_rel_residual[NP_MAX_LEVELS];/* relative residual of the interpolated guess */
 } np_stats;
 int nested_poisson_solve(np_solver* s, const double* const* rho, const double* phi_outer, np_stats* stats);
 
@@ -172,7 +174,8 @@ int nested_poisson_potential(np_solver* s, int level, double* phi_padded);
 #define NP_KCLASS_FILL 5     /* level-0 setup and coarse-to-fine fills */
 #define NP_KCLASS_FORCES 6   /* force evaluation */
 #define NP_KCLASS_DC 7       /* FP64 residual / correction passes of the defect correction */
-#define NP_NKCLASS 8
+#define NP_KCLASS_GUESS 8    /* learned initial guess (features, three convolutions, update) */
+#define NP_NKCLASS 10
 typedef struct np_profile {
     long count[NP_NKCLASS]; /* launches (intervals) recorded */
     double ms[NP_NKCLASS];  /* summed device time */
@@ -182,6 +185,64 @@ int nested_poisson_set_profiling(np_solver* s, int enable);
 /* Synchronises the stream and returns the totals since profiling was enabled.
  * Errors: NP_EINVAL, NP_ESTATE (profiling off), NP_EHIP. */
 int nested_poisson_get_profile(np_solver* s, np_profile* out);
+
+/* ------------------------------------------------------------------ learned initial guess
+ * A 3-D convolution network predicts, for a level l >= 1, the correction of
+ * the interpolated initial guess (an extension; the paper interpolates only):
+ *   input  x = (f / ||f||_inf, r0 / ||f||_inf) on Gamma^l, r0 = f - lap(Phi_interp),
+ *   output y on Gamma^l, guess = Phi_interp + ||f||_inf dx_l^2 y,
+ * network conv3x3x3(2->16) -> ReLU -> conv3x3x3(16->16) -> ReLU ->
+ * conv3x3x3(16->1), zero padding, same size.  The V-cycles then iterate to the
+ * same tolerance; the learned guess is kept only if its max-norm residual is
+ * at most half that of the interpolated guess (else, or if non-finite, it is
+ * discarded).
+ * Parameter vector (NP_NET_PARAMS floats): for each layer its weights
+ * [27 taps][cout][cin] (taps ordered dz, dy, dx in -1..1, dx fastest) then its
+ * cout biases.  Activations of the np_net_* kernels are FP32 (or bfloat16 as
+ * stated) channel-last [batch][z][y][x][channel] device arrays; weights are
+ * bfloat16 device arrays; every call is queued on `stream` (hipStream_t). */
+#define NP_NET_PARAMS 8241
+
+/* Copies the host parameter vector (FP32, NP_NET_PARAMS values) into the
+ * handle; required before a solve with guess = NP_GUESS_LEARNED.
+ * Errors: NP_EINVAL (size), NP_ENOMEM, NP_EHIP. */
+int nested_poisson_set_guess_weights(np_solver* s, const float* theta, size_t n);
+
+/* Training data of level `level` >= 1 after a successful solve: the network
+ * input x ((n+2)^3 x 2 FP32, channel-last) built from the interpolated guess,
+ * and target = (Phi_converged - Phi_interp) / (||f||_inf dx_l^2) ((n+2)^3 FP32,
+ * may be NULL).  Device arrays.  Errors: NP_EINVAL, NP_ESTATE, NP_ENOMEM. */
+int nested_poisson_guess_features(np_solver* s, int level, float* x, float* target);
+
+/* Workspace (bytes) needed by np_net_conv3d_bwd_weight for (cin, cout) and by
+ * np_net_mse for n values. */
+size_t np_net_workspace_bytes(int cin, int cout, long nvox);
+/* out = conv(in) + bias (ReLU if relu != 0); FP32 activations, bfloat16
+ * weights, FP32 accumulation; 1 <= cin, cout <= 16. */
+int np_net_conv3d_fwd(const float* in, int cin, const unsigned short* w_bf16, const float* bias, int cout, int relu,
+                      int batch, int nz, int ny, int nx, float* out, void* stream);
+/* The 16 -> 16 layer on the matrix cores: bfloat16 activations in and out,
+ * FP32 accumulation (v_mfma_f32_16x16x16 bf16); 8-byte aligned arrays. */
+int np_net_conv3d_fwd_mfma(const unsigned short* in_bf16, const unsigned short* w_bf16, const float* bias, int relu,
+                           int batch, int nz, int ny, int nx, unsigned short* out_bf16, void* stream);
+/* gin = d loss / d in given gout = d loss / d out. */
+int np_net_conv3d_bwd_data(const float* gout, int cout, const unsigned short* w_bf16, int cin, int batch, int nz,
+                           int ny, int nx, float* gin, void* stream);
+/* gw [27][cout][cin] and gb [cout] (FP32), summed in a fixed order (deterministic). */
+int np_net_conv3d_bwd_weight(const float* in, int cin, const float* gout, int cout, int batch, int nz, int ny, int nx,
+                             float* gw, float* gb, float* workspace, size_t workspace_bytes, void* stream);
+/* grad *= (act > 0) */
+int np_net_relu_bwd(const float* act, float* grad, long n, void* stream);
+/* loss[0] = sum(mask (pred - target)^2) / count, grad = 2 mask (pred - target) / count
+ * (mask may be NULL = all ones). */
+int np_net_mse(const float* pred, const float* target, const float* mask, long n, float count, float* grad,
+               float* loss, float* workspace, size_t workspace_bytes, void* stream);
+/* Adam with bias correction (step >= 1) on FP32 master weights; refreshes the
+ * bfloat16 copy when w_bf16 is not NULL. */
+int np_net_adam(float* w, const float* g, float* m, float* v, long n, float lr, float beta1, float beta2, float eps,
+                int step, unsigned short* w_bf16, void* stream);
+/* bfloat16 copy (round to nearest even). */
+int np_net_to_bf16(const float* a, unsigned short* b, long n, void* stream);
 
 /* Frees every library allocation of the handle.  NULL-safe. */
 void nested_poisson_destroy(np_solver* s);

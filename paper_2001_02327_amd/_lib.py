@@ -64,11 +64,14 @@ class NpStats(ctypes.Structure):
         ("scale", ctypes.c_double * NP_MAX_LEVELS),
         ("level_ms", ctypes.c_double * NP_MAX_LEVELS),
         ("total_ms", ctypes.c_double),
+        ("learned_used", ctypes.c_int * NP_MAX_LEVELS),
+        ("interp_rel_residual", ctypes.c_double * NP_MAX_LEVELS),
     ]
 
 
-NP_NKCLASS = 8
-KCLASSES = ["smooth", "restrict", "prolong", "coarse", "norm", "fill", "forces", "dc"]
+NP_NKCLASS = 10
+KCLASSES = ["smooth", "restrict", "prolong", "coarse", "norm", "fill", "forces", "dc", "guess"]
+NP_NET_PARAMS = 8241
 
 
 class NpProfile(ctypes.Structure):
@@ -89,6 +92,22 @@ SIGNATURES = {
     "nested_poisson_potential": (ctypes.c_int, [_vp, ctypes.c_int, _vp]),
     "nested_poisson_set_profiling": (ctypes.c_int, [_vp, ctypes.c_int]),
     "nested_poisson_get_profile": (ctypes.c_int, [_vp, ctypes.POINTER(NpProfile)]),
+    "nested_poisson_set_guess_weights": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_float), ctypes.c_size_t]),
+    "nested_poisson_guess_features": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp]),
+    "np_net_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int, ctypes.c_int, ctypes.c_long]),
+    "np_net_conv3d_fwd": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                         ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp]),
+    "np_net_conv3d_fwd_mfma": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                              ctypes.c_int, _vp, _vp]),
+    "np_net_conv3d_bwd_data": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                              ctypes.c_int, ctypes.c_int, _vp, _vp]),
+    "np_net_conv3d_bwd_weight": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                                ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
+    "np_net_relu_bwd": (ctypes.c_int, [_vp, _vp, ctypes.c_long, _vp]),
+    "np_net_mse": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_long, ctypes.c_float, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
+    "np_net_adam": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_long, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                   ctypes.c_float, ctypes.c_int, _vp, _vp]),
+    "np_net_to_bf16": (ctypes.c_int, [_vp, _vp, ctypes.c_long, _vp]),
     "nested_poisson_destroy": (None, [_vp]),
     "nested_poisson_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "nested_poisson_last_error": (ctypes.c_char_p, [_vp]),

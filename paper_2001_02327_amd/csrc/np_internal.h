@@ -81,4 +81,34 @@ void launch_dc_residual(int dim, hipStream_t st, SGrid g, const double* phi, con
 template <typename TL>
 void launch_dc_update(int dim, hipStream_t st, SGrid g, double* phi, const TL* e, double factor);
 
+// learned initial guess network (np_net.hip); activations channel-last,
+// weights bfloat16 [27][cout][cin]
+void net_conv_fwd_f32(hipStream_t st, const float* in, int cin, const uint16_t* w, const float* bias, int cout, int relu,
+                      int B, int Z, int Y, int X, float* out);
+void net_conv_fwd_bf16(hipStream_t st, const uint16_t* in, int cin, const uint16_t* w, const float* bias, int cout,
+                       int relu, int B, int Z, int Y, int X, uint16_t* out);
+void net_conv_fwd_bf16_to_f32(hipStream_t st, const uint16_t* in, int cin, const uint16_t* w, const float* bias,
+                              int cout, int relu, int B, int Z, int Y, int X, float* out);
+void net_conv16_mfma(hipStream_t st, const uint16_t* in, const uint16_t* w, const float* bias, int relu, int B, int Z,
+                     int Y, int X, uint16_t* out);
+void net_conv_bwd_data(hipStream_t st, const float* gout, int cout, const uint16_t* w, int cin, int B, int Z, int Y,
+                       int X, float* gin);
+size_t net_bwd_weight_workspace(int cin, int cout);
+void net_conv_bwd_weight(hipStream_t st, const float* in, int cin, const float* gout, int cout, int B, int Z, int Y,
+                         int X, float* gw, float* gb, float* part);
+void net_relu_bwd(hipStream_t st, const float* act, float* g, long n);
+size_t net_mse_workspace(long n);
+void net_mse(hipStream_t st, const float* pred, const float* target, const float* mask, long n, float count,
+             float* grad, float* part, float* loss);
+void net_adam(hipStream_t st, float* w, const float* g, float* m, float* v, long n, float lr, float b1, float b2,
+              float eps, int step, uint16_t* wb);
+void net_to_bf16(hipStream_t st, const float* a, uint16_t* b, long n);
+// solver glue on a nested level's Gamma ((n+2)^3 points)
+void net_features_bf16(hipStream_t st, SGrid g, const double* phi, const double* f, double inv_fnorm, double inv_h2,
+                       uint16_t* x);
+void net_features_f32(hipStream_t st, SGrid g, const double* phi, const double* f, double inv_fnorm, double inv_h2,
+                      float* x);
+void net_apply(hipStream_t st, SGrid g, double* phi, const float* out, double s);
+void net_target(hipStream_t st, SGrid g, const double* pa, const double* pb, double inv_s, float* t);
+
 }  // namespace np

@@ -554,6 +554,87 @@ __global__ void __launch_bounds__(kBlock) k_half_sweep(T* __restrict__ u, const 
     half_sweep_body<D, T>(u, f, g, colour, h2, inv2d);
 }
 
+// Paired form of the level-0 z-march for 2- and 4-byte storage: a thread owns
+// the two compact points h0 = 2 hp and h0 + 1 of a row and moves them with
+// one 2-element load or store; the extra x-neighbour (h0 - 1 or h0 + 2) is a
+// single load.  Same arithmetic, in the same order, as k_smooth_zmarch3.
+// Requires an even row length hx (so pairs never straddle rows and stay
+// aligned).
+template <typename T>
+struct alignas(2 * sizeof(T)) Pair {
+    T a, b;
+};
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_smooth_zmarch3_pair(T* __restrict__ u, const T* __restrict__ f, SGrid g,
+                                                                int colour, typename Compute<T>::type h2,
+                                                                typename Compute<T>::type inv2d, int pblocks)
+{
+    using C = typename Compute<T>::type;
+    const int m = g.nx - 2;
+    const int hp_n = g.hx >> 1;
+    const long lb = xcd_block();
+    const int zc = (int)(lb / pblocks);
+    const long t = (lb - (long)zc * pblocks) * kBlock + threadIdx.x;
+    if (t >= (long)hp_n * m) return;
+    const int h0 = 2 * (int)(t % hp_n);
+    const int pj = 1 + (int)(t / hp_n);
+    const int k0 = 1 + zc * kZChunk;
+    const int k1 = min(k0 + kZChunk - 1, m);
+    const size_t plane = (size_t)g.nx * g.hx;
+    const size_t col = (size_t)pj * g.hx + h0;
+    const T* __restrict__ o = u + (size_t)(colour ^ 1) * g.cs;
+    T* __restrict__ uc = u + (size_t)colour * g.cs;
+    const T* __restrict__ fc = f + (size_t)colour * g.cs;
+    Pair<T> below = *(const Pair<T>*)(o + (size_t)(k0 - 1) * plane + col);
+    Pair<T> cur = *(const Pair<T>*)(o + (size_t)k0 * plane + col);
+    for (int pk = k0; pk <= k1; pk++) {
+        const size_t here = (size_t)pk * plane + col;
+        const Pair<T> above = *(const Pair<T>*)(o + here + plane);
+        const Pair<T> ym = *(const Pair<T>*)(o + here - g.hx);
+        const Pair<T> yp = *(const Pair<T>*)(o + here + g.hx);
+        const Pair<T> fv = *(const Pair<T>*)(fc + here);
+        const int par = (colour + pj + pk + 3) & 1;
+        // the extra x-neighbour stays inside the plane (neighbouring row at the row ends)
+        const C ex = (C)o[par ? here + 2 : here - 1];
+        C xm0, xp0, xm1, xp1;
+        if (par) {
+            xm0 = (C)cur.a;
+            xp0 = (C)cur.b;
+            xm1 = (C)cur.b;
+            xp1 = ex;
+        } else {
+            xm0 = ex;
+            xp0 = (C)cur.a;
+            xm1 = (C)cur.a;
+            xp1 = (C)cur.b;
+        }
+        C s0 = xm0 + xp0;
+        s0 = s0 + (C)ym.a;
+        s0 = s0 + (C)yp.a;
+        s0 = s0 + (C)below.a;
+        s0 = s0 + (C)above.a;
+        C s1 = xm1 + xp1;
+        s1 = s1 + (C)ym.b;
+        s1 = s1 + (C)yp.b;
+        s1 = s1 + (C)below.b;
+        s1 = s1 + (C)above.b;
+        Pair<T> r;
+        r.a = (T)((s0 - h2 * (C)fv.a) * inv2d);
+        r.b = (T)((s1 - h2 * (C)fv.b) * inv2d);
+        const int pi0 = 2 * h0 + par;
+        const bool a0 = pi0 >= 1, a1 = pi0 + 2 <= g.nx - 2;
+        if (a0 && a1) {
+            *(Pair<T>*)(uc + here) = r;
+        } else {
+            if (a0) uc[here] = r.a;
+            if (a1) uc[here + 1] = r.b;
+        }
+        below = cur;
+        cur = above;
+    }
+}
+
 // Ghost layer of a multigrid level L >= 1 (Sec. 2.4): left e_0 = -e_1; right
 // -e_{N-1} when x_N = 1, else coef * e_N; edges and corners compose the rule
 // of each axis they are ghosts on, applied in the order x, y, z.
@@ -890,6 +971,15 @@ void launch_half_sweep(int dim, hipStream_t st, SGrid g, T* u, const T* f, int c
     using C = typename Compute<T>::type;
     dim3 grid(ceil_div(ncompact_active(dim, g), kBlock));
     C inv2d = (C)(1.0 / (2.0 * dim));
+    if (dim == 3 && fine && sizeof(T) <= 4 && (g.hx % 2) == 0) {
+        // 2- and 4-byte storage: two compact points per thread, paired loads
+        long m = g.nx - 2;
+        int pblocks = ceil_div((long)(g.hx / 2) * m, kBlock);
+        int chunks = ceil_div(m, kZChunk);
+        hipLaunchKernelGGL((k_smooth_zmarch3_pair<T>), dim3(pblocks * chunks), dim3(kBlock), 0, st, u, f, g, colour,
+                           (C)h2, inv2d, pblocks);
+        return;
+    }
     if (dim == 3 && (fine || g.nx >= 34)) {
         // z-march; the level-0 instance (TAG 0) is kept apart from the
         // coarse-level one (TAG 1) so that profiles separate them

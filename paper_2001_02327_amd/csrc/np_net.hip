@@ -1,0 +1,560 @@
+// Kernels of the learned initial-guess network (gfx950).
+//
+// Network: conv3x3x3(2->16) -> ReLU -> conv3x3x3(16->16) -> ReLU ->
+// conv3x3x3(16->1), zero padding, same-size output.  Activations are
+// channel-last [batch][z][y][x][c]; the weights of a layer are bfloat16
+// [27 taps][cout][cin] with taps ordered (dz, dy, dx), dx fastest, offsets
+// -1..1; biases FP32.  Training keeps FP32 master weights (Adam) and runs the
+// convolutions with the bfloat16 weights and FP32 activations and
+// accumulation; inference of the 16->16 layer runs on the matrix cores
+// (bfloat16 x bfloat16 -> FP32 MFMA).
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "../../include/nested_poisson.h"
+#include "np_internal.h"
+
+namespace np {
+
+namespace {
+
+constexpr int kNB = 256;
+
+__host__ __device__ inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// round to nearest even; NaN stays NaN
+__device__ __forceinline__ uint16_t f32_to_bf16(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x7fffffu)) return (uint16_t)((u >> 16) | 0x40);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+template <typename T>
+__device__ __forceinline__ float ld(const T* p);
+template <>
+__device__ __forceinline__ float ld<float>(const float* p) { return *p; }
+template <>
+__device__ __forceinline__ float ld<uint16_t>(const uint16_t* p) { return bf16_to_f32(*p); }
+
+template <typename T>
+__device__ __forceinline__ void st(T* p, float v);
+template <>
+__device__ __forceinline__ void st<float>(float* p, float v) { *p = v; }
+template <>
+__device__ __forceinline__ void st<uint16_t>(uint16_t* p, float v) { *p = f32_to_bf16(v); }
+
+// ------------------------------------------------------------------ convolution, FP32 accumulate
+// Thread per output voxel; the layer's weights are staged in LDS as FP32.
+template <typename TI, typename TO>
+__global__ void __launch_bounds__(kNB) k_conv_fwd(const TI* __restrict__ in, int cin, const uint16_t* __restrict__ w,
+                                                 const float* __restrict__ bias, int cout, int relu, int B, int Z, int Y,
+                                                 int X, TO* __restrict__ out)
+{
+    __shared__ float ws[27 * 16 * 16];
+    const int nw = 27 * cout * cin;
+    for (int i = threadIdx.x; i < nw; i += kNB) ws[i] = bf16_to_f32(w[i]);
+    __syncthreads();
+    const long nvox = (long)B * Z * Y * X;
+    const long v = (long)blockIdx.x * kNB + threadIdx.x;
+    if (v >= nvox) return;
+    const int x = (int)(v % X);
+    long r = v / X;
+    const int y = (int)(r % Y);
+    r /= Y;
+    const int z = (int)(r % Z);
+    const int b = (int)(r / Z);
+    float acc[16];
+    for (int o = 0; o < cout; o++) acc[o] = bias[o];
+    int t = 0;
+    for (int dz = -1; dz <= 1; dz++)
+        for (int dy = -1; dy <= 1; dy++)
+            for (int dx = -1; dx <= 1; dx++, t++) {
+                const int zz = z + dz, yy = y + dy, xx = x + dx;
+                if (zz < 0 || zz >= Z || yy < 0 || yy >= Y || xx < 0 || xx >= X) continue;
+                const TI* src = in + ((((long)b * Z + zz) * Y + yy) * X + xx) * cin;
+                const float* wt = ws + t * cout * cin;
+                for (int i = 0; i < cin; i++) {
+                    const float a = ld(src + i);
+                    for (int o = 0; o < cout; o++) acc[o] = fmaf(wt[o * cin + i], a, acc[o]);
+                }
+            }
+    TO* dst = out + v * cout;
+    for (int o = 0; o < cout; o++) st(dst + o, relu ? fmaxf(acc[o], 0.0f) : acc[o]);
+}
+
+// Data gradient: gin[v][i] = sum_taps sum_o w[t][o][i] * gout[v - tap][o].
+__global__ void __launch_bounds__(kNB) k_conv_bwd_data(const float* __restrict__ gout, int cout,
+                                                      const uint16_t* __restrict__ w, int cin, int B, int Z, int Y, int X,
+                                                      float* __restrict__ gin)
+{
+    __shared__ float ws[27 * 16 * 16];
+    const int nw = 27 * cout * cin;
+    for (int i = threadIdx.x; i < nw; i += kNB) ws[i] = bf16_to_f32(w[i]);
+    __syncthreads();
+    const long nvox = (long)B * Z * Y * X;
+    const long v = (long)blockIdx.x * kNB + threadIdx.x;
+    if (v >= nvox) return;
+    const int x = (int)(v % X);
+    long r = v / X;
+    const int y = (int)(r % Y);
+    r /= Y;
+    const int z = (int)(r % Z);
+    const int b = (int)(r / Z);
+    float acc[16];
+    for (int i = 0; i < cin; i++) acc[i] = 0.0f;
+    int t = 0;
+    for (int dz = -1; dz <= 1; dz++)
+        for (int dy = -1; dy <= 1; dy++)
+            for (int dx = -1; dx <= 1; dx++, t++) {
+                const int zz = z - dz, yy = y - dy, xx = x - dx;
+                if (zz < 0 || zz >= Z || yy < 0 || yy >= Y || xx < 0 || xx >= X) continue;
+                const float* g = gout + ((((long)b * Z + zz) * Y + yy) * X + xx) * cout;
+                const float* wt = ws + t * cout * cin;
+                for (int o = 0; o < cout; o++) {
+                    const float go = g[o];
+                    for (int i = 0; i < cin; i++) acc[i] = fmaf(wt[o * cin + i], go, acc[i]);
+                }
+            }
+    float* dst = gin + v * cin;
+    for (int i = 0; i < cin; i++) dst[i] = acc[i];
+}
+
+// Weight and bias gradients, first stage: block `blk` sums over the voxel rows
+// blk, blk + gridDim.x, ... and writes its partial (27*cout*cin weights, then
+// cout biases) to part[blk].  Each thread owns weight entries
+// e = threadIdx.x, threadIdx.x + 256, ...; the row's inputs (3x3 neighbour
+// rows with a one-voxel halo) and output gradients are staged in LDS.
+constexpr int kRowMax = 64;  // longest row segment staged at once (longer rows are split)
+
+__global__ void __launch_bounds__(kNB) k_conv_bwd_weight_part(const float* __restrict__ in, int cin,
+                                                             const float* __restrict__ gout, int cout, int B, int Z,
+                                                             int Y, int X, float* __restrict__ part)
+{
+    __shared__ float sin[9][kRowMax + 2][16];
+    __shared__ float sg[kRowMax][16];
+    const int nw = 27 * cout * cin;
+    const int ne = nw + cout;
+    float acc[28];  // ceil((27*16*16 + 16) / 256) = 28 entries per thread at most
+    for (int q = 0; q < 28; q++) acc[q] = 0.0f;
+    const int nseg = (X + kRowMax - 1) / kRowMax;
+    const long nrows = (long)B * Z * Y * nseg;
+    for (long row = blockIdx.x; row < nrows; row += gridDim.x) {
+        const int seg = (int)(row % nseg);
+        long rr = row / nseg;
+        const int y = (int)(rr % Y);
+        rr /= Y;
+        const int z = (int)(rr % Z);
+        const int b = (int)(rr / Z);
+        const int x0 = seg * kRowMax;
+        const int len = min(kRowMax, X - x0);
+        __syncthreads();
+        // stage 9 neighbour rows (dz, dy) with x in [x0-1, x0+len] and the output gradients
+        for (int idx = threadIdx.x; idx < 9 * (len + 2) * cin; idx += kNB) {
+            const int i = idx % cin;
+            const int xs = (idx / cin) % (len + 2);
+            const int nr = idx / (cin * (len + 2));
+            const int zz = z + nr / 3 - 1, yy = y + nr % 3 - 1, xx = x0 + xs - 1;
+            float vv = 0.0f;
+            if (zz >= 0 && zz < Z && yy >= 0 && yy < Y && xx >= 0 && xx < X)
+                vv = in[((((long)b * Z + zz) * Y + yy) * X + xx) * cin + i];
+            sin[nr][xs][i] = vv;
+        }
+        for (int idx = threadIdx.x; idx < len * cout; idx += kNB) {
+            const int o = idx % cout, xs = idx / cout;
+            sg[xs][o] = gout[((((long)b * Z + z) * Y + y) * X + x0 + xs) * cout + o];
+        }
+        __syncthreads();
+        int q = 0;
+        for (int e = threadIdx.x; e < ne; e += kNB, q++) {
+            float s = 0.0f;
+            if (e < nw) {
+                const int i = e % cin;
+                const int o = (e / cin) % cout;
+                const int t = e / (cin * cout);
+                const int nr = t / 3, dx = t % 3;  // (dz, dy) row index and x offset + 1
+                for (int xs = 0; xs < len; xs++) s = fmaf(sg[xs][o], sin[nr][xs + dx][i], s);
+            } else {
+                const int o = e - nw;
+                for (int xs = 0; xs < len; xs++) s += sg[xs][o];
+            }
+            acc[q] += s;
+        }
+    }
+    int q = 0;
+    for (int e = threadIdx.x; e < ne; e += kNB, q++) part[(long)blockIdx.x * ne + e] = acc[q];
+}
+
+// Second stage: gw/gb = sum over the partials, in a fixed order.
+__global__ void k_sum_parts(const float* __restrict__ part, int nparts, int ne, int nw, float* __restrict__ gw,
+                            float* __restrict__ gb)
+{
+    const int e = blockIdx.x * kNB + threadIdx.x;
+    if (e >= ne) return;
+    float s = 0.0f;
+    for (int p = 0; p < nparts; p++) s += part[(long)p * ne + e];
+    if (e < nw) gw[e] = s;
+    else gb[e - nw] = s;
+}
+
+__global__ void k_relu_bwd(const float* __restrict__ act, float* __restrict__ g, long n)
+{
+    const long i = (long)blockIdx.x * kNB + threadIdx.x;
+    if (i < n && !(act[i] > 0.0f)) g[i] = 0.0f;
+}
+
+// Masked mean squared error: grad = 2 mask (pred - target) / sum(mask), and
+// per-block partial sums of mask (pred - target)^2 and of mask.
+__global__ void k_mse(const float* __restrict__ pred, const float* __restrict__ target, const float* __restrict__ mask,
+                      long n, float inv_count, float* __restrict__ grad, float* __restrict__ part)
+{
+    __shared__ float red[kNB];
+    const long i = (long)blockIdx.x * kNB + threadIdx.x;
+    float d = 0.0f;
+    if (i < n) {
+        const float m = mask ? mask[i] : 1.0f;
+        const float diff = (pred[i] - target[i]) * m;
+        grad[i] = 2.0f * diff * inv_count;
+        d = diff * diff;
+    }
+    red[threadIdx.x] = d;
+    __syncthreads();
+    for (int s = kNB / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void k_sum(const float* __restrict__ part, int n, float scale, float* __restrict__ out)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        float s = 0.0f;
+        for (int i = 0; i < n; i++) s += part[i];
+        out[0] = s * scale;
+    }
+}
+
+// Adam (Kingma & Ba) with bias correction on FP32 master weights; the
+// bfloat16 copy used by the convolutions is refreshed.
+__global__ void k_adam(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m, float* __restrict__ v,
+                       long n, float lr, float b1, float b2, float eps, float c1, float c2, uint16_t* __restrict__ wb)
+{
+    const long i = (long)blockIdx.x * kNB + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    w[i] = wi;
+    if (wb) wb[i] = f32_to_bf16(wi);
+}
+
+__global__ void k_to_bf16(const float* __restrict__ a, uint16_t* __restrict__ b, long n)
+{
+    const long i = (long)blockIdx.x * kNB + threadIdx.x;
+    if (i < n) b[i] = f32_to_bf16(a[i]);
+}
+
+// ------------------------------------------------------------------ 16 -> 16 layer on the matrix cores
+// One wavefront computes 16 consecutive voxels along x (rows of the MFMA) times
+// the 16 output channels (columns), accumulating the 27 taps as 27
+// v_mfma_f32_16x16x16 bf16 products with K = 16 input channels.  Operand
+// layout of the 16x16x16 MFMA: lane l supplies A[row l%16][k 4(l/16)..+3] and
+// B[k 4(l/16)..+3][col l%16], and receives D[rows 4(l/16)..+3][col l%16].
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(kNB) k_conv16_mfma(const uint16_t* __restrict__ in, const uint16_t* __restrict__ w,
+                                                    const float* __restrict__ bias, int relu, int B, int Z, int Y,
+                                                    int X, uint16_t* __restrict__ out)
+{
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int tiles_x = (X + 15) / 16;
+    const long tile = (long)blockIdx.x * (kNB / 64) + wave;
+    const long ntiles = (long)B * Z * Y * tiles_x;
+    if (tile >= ntiles) return;
+    const int tx = (int)(tile % tiles_x);
+    long r = tile / tiles_x;
+    const int y = (int)(r % Y);
+    r /= Y;
+    const int z = (int)(r % Z);
+    const int b = (int)(r / Z);
+    const int row = lane & 15;   // voxel within the tile (A row) / output channel (B, D column)
+    const int kq = lane >> 4;    // which 4 of the 16 input channels
+    const int x = tx * 16 + row;
+    v4f acc = {0.f, 0.f, 0.f, 0.f};
+    int t = 0;
+    for (int dz = -1; dz <= 1; dz++)
+        for (int dy = -1; dy <= 1; dy++)
+            for (int dx = -1; dx <= 1; dx++, t++) {
+                const int zz = z + dz, yy = y + dy, xx = x + dx;
+                v4s a = {0, 0, 0, 0};
+                if (zz >= 0 && zz < Z && yy >= 0 && yy < Y && xx >= 0 && xx < X)
+                    a = *(const v4s*)(in + ((((long)b * Z + zz) * Y + yy) * X + xx) * 16 + 4 * kq);
+                const v4s bw = *(const v4s*)(w + (t * 16 + row) * 16 + 4 * kq);
+                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bw, acc, 0, 0, 0);
+            }
+    const float bo = bias[row];
+    for (int q = 0; q < 4; q++) {
+        const int xo = tx * 16 + 4 * kq + q;
+        if (xo >= X) continue;
+        float v = acc[q] + bo;
+        if (relu) v = fmaxf(v, 0.0f);
+        out[((((long)b * Z + z) * Y + y) * X + xo) * 16 + row] = f32_to_bf16(v);
+    }
+}
+
+// ------------------------------------------------------------------ solver glue
+// Features of a nested level's Gamma ((n+2)^3 points, channel-last, 2 channels):
+// f / ||f|| and r0 / ||f|| with r0 = f - lap(phi) of the interpolated guess.
+template <typename TA>
+__global__ void __launch_bounds__(kNB) k_net_features(SGrid g, const double* __restrict__ phi,
+                                                     const double* __restrict__ f, double inv_fnorm, double inv_h2,
+                                                     TA* __restrict__ x)
+{
+    const int m = g.nx - 2;
+    const long nv = (long)m * m * m;
+    const long v = (long)blockIdx.x * kNB + threadIdx.x;
+    if (v >= nv) return;
+    const int i = (int)(v % m) + 1;
+    const int j = (int)((v / m) % m) + 1;
+    const int k = (int)(v / ((long)m * m)) + 1;
+    auto at = [&](const double* a, int pi, int pj, int pk) {
+        return a[(size_t)((pi + pj + pk + 3) & 1) * g.cs + ((size_t)pk * g.nx + pj) * g.hx + (pi >> 1)];
+    };
+    const double lap = (at(phi, i - 1, j, k) + at(phi, i + 1, j, k) + at(phi, i, j - 1, k) + at(phi, i, j + 1, k) +
+                        at(phi, i, j, k - 1) + at(phi, i, j, k + 1) - 6.0 * at(phi, i, j, k)) * inv_h2;
+    const double fv = at(f, i, j, k);
+    st(x + 2 * v, (float)(fv * inv_fnorm));
+    st(x + 2 * v + 1, (float)((fv - lap) * inv_fnorm));
+}
+
+// phi += s * out on Gamma (out: (n+2)^3 FP32)
+__global__ void __launch_bounds__(kNB) k_net_apply(SGrid g, double* __restrict__ phi, const float* __restrict__ out,
+                                                  double s)
+{
+    const int m = g.nx - 2;
+    const long nv = (long)m * m * m;
+    const long v = (long)blockIdx.x * kNB + threadIdx.x;
+    if (v >= nv) return;
+    const int i = (int)(v % m) + 1;
+    const int j = (int)((v / m) % m) + 1;
+    const int k = (int)(v / ((long)m * m)) + 1;
+    phi[(size_t)((i + j + k + 3) & 1) * g.cs + ((size_t)k * g.nx + j) * g.hx + (i >> 1)] += s * (double)out[v];
+}
+
+// target = (phi_a - phi_b) * inv_s on Gamma
+__global__ void __launch_bounds__(kNB) k_net_target(SGrid g, const double* __restrict__ pa,
+                                                   const double* __restrict__ pb, double inv_s, float* __restrict__ t)
+{
+    const int m = g.nx - 2;
+    const long nv = (long)m * m * m;
+    const long v = (long)blockIdx.x * kNB + threadIdx.x;
+    if (v >= nv) return;
+    const int i = (int)(v % m) + 1;
+    const int j = (int)((v / m) % m) + 1;
+    const int k = (int)(v / ((long)m * m)) + 1;
+    const size_t p = (size_t)((i + j + k + 3) & 1) * g.cs + ((size_t)k * g.nx + j) * g.hx + (i >> 1);
+    t[v] = (float)((pa[p] - pb[p]) * inv_s);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+constexpr int kNetParts = 2048;  // blocks (partial sums) of the weight-gradient reduction
+
+void net_conv_fwd_f32(hipStream_t st, const float* in, int cin, const uint16_t* w, const float* bias, int cout, int relu,
+                      int B, int Z, int Y, int X, float* out)
+{
+    long nv = (long)B * Z * Y * X;
+    hipLaunchKernelGGL((k_conv_fwd<float, float>), dim3(cdiv(nv, kNB)), dim3(kNB), 0, st, in, cin, w, bias, cout, relu, B,
+                       Z, Y, X, out);
+}
+
+void net_conv_fwd_bf16(hipStream_t st, const uint16_t* in, int cin, const uint16_t* w, const float* bias, int cout,
+                       int relu, int B, int Z, int Y, int X, uint16_t* out)
+{
+    long nv = (long)B * Z * Y * X;
+    hipLaunchKernelGGL((k_conv_fwd<uint16_t, uint16_t>), dim3(cdiv(nv, kNB)), dim3(kNB), 0, st, in, cin, w, bias, cout,
+                       relu, B, Z, Y, X, out);
+}
+
+void net_conv_fwd_bf16_to_f32(hipStream_t st, const uint16_t* in, int cin, const uint16_t* w, const float* bias,
+                              int cout, int relu, int B, int Z, int Y, int X, float* out)
+{
+    long nv = (long)B * Z * Y * X;
+    hipLaunchKernelGGL((k_conv_fwd<uint16_t, float>), dim3(cdiv(nv, kNB)), dim3(kNB), 0, st, in, cin, w, bias, cout,
+                       relu, B, Z, Y, X, out);
+}
+
+void net_conv16_mfma(hipStream_t st, const uint16_t* in, const uint16_t* w, const float* bias, int relu, int B, int Z,
+                     int Y, int X, uint16_t* out)
+{
+    long ntiles = (long)B * Z * Y * ((X + 15) / 16);
+    hipLaunchKernelGGL(k_conv16_mfma, dim3(cdiv(ntiles, kNB / 64)), dim3(kNB), 0, st, in, w, bias, relu, B, Z, Y, X,
+                       out);
+}
+
+void net_conv_bwd_data(hipStream_t st, const float* gout, int cout, const uint16_t* w, int cin, int B, int Z, int Y,
+                       int X, float* gin)
+{
+    long nv = (long)B * Z * Y * X;
+    hipLaunchKernelGGL(k_conv_bwd_data, dim3(cdiv(nv, kNB)), dim3(kNB), 0, st, gout, cout, w, cin, B, Z, Y, X, gin);
+}
+
+size_t net_bwd_weight_workspace(int cin, int cout) { return (size_t)kNetParts * (27 * cin * cout + cout) * sizeof(float); }
+
+void net_conv_bwd_weight(hipStream_t st, const float* in, int cin, const float* gout, int cout, int B, int Z, int Y,
+                         int X, float* gw, float* gb, float* part)
+{
+    int ne = 27 * cin * cout + cout;
+    hipLaunchKernelGGL(k_conv_bwd_weight_part, dim3(kNetParts), dim3(kNB), 0, st, in, cin, gout, cout, B, Z, Y, X, part);
+    hipLaunchKernelGGL(k_sum_parts, dim3(cdiv(ne, kNB)), dim3(kNB), 0, st, part, kNetParts, ne, 27 * cin * cout, gw, gb);
+}
+
+void net_relu_bwd(hipStream_t st, const float* act, float* g, long n)
+{
+    hipLaunchKernelGGL(k_relu_bwd, dim3(cdiv(n, kNB)), dim3(kNB), 0, st, act, g, n);
+}
+
+size_t net_mse_workspace(long n) { return (size_t)cdiv(n, kNB) * sizeof(float); }
+
+void net_mse(hipStream_t st, const float* pred, const float* target, const float* mask, long n, float count,
+             float* grad, float* part, float* loss)
+{
+    int nb = cdiv(n, kNB);
+    hipLaunchKernelGGL(k_mse, dim3(nb), dim3(kNB), 0, st, pred, target, mask, n, 1.0f / count, grad, part);
+    hipLaunchKernelGGL(k_sum, dim3(1), dim3(1), 0, st, part, nb, 1.0f / count, loss);
+}
+
+void net_adam(hipStream_t st, float* w, const float* g, float* m, float* v, long n, float lr, float b1, float b2,
+              float eps, int step, uint16_t* wb)
+{
+    float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
+    hipLaunchKernelGGL(k_adam, dim3(cdiv(n, kNB)), dim3(kNB), 0, st, w, g, m, v, n, lr, b1, b2, eps, c1, c2, wb);
+}
+
+void net_to_bf16(hipStream_t st, const float* a, uint16_t* b, long n)
+{
+    hipLaunchKernelGGL(k_to_bf16, dim3(cdiv(n, kNB)), dim3(kNB), 0, st, a, b, n);
+}
+
+void net_features_bf16(hipStream_t st, SGrid g, const double* phi, const double* f, double inv_fnorm, double inv_h2,
+                       uint16_t* x)
+{
+    long m = g.nx - 2;
+    hipLaunchKernelGGL((k_net_features<uint16_t>), dim3(cdiv(m * m * m, kNB)), dim3(kNB), 0, st, g, phi, f, inv_fnorm,
+                       inv_h2, x);
+}
+
+void net_features_f32(hipStream_t st, SGrid g, const double* phi, const double* f, double inv_fnorm, double inv_h2,
+                      float* x)
+{
+    long m = g.nx - 2;
+    hipLaunchKernelGGL((k_net_features<float>), dim3(cdiv(m * m * m, kNB)), dim3(kNB), 0, st, g, phi, f, inv_fnorm,
+                       inv_h2, x);
+}
+
+void net_apply(hipStream_t st, SGrid g, double* phi, const float* out, double s)
+{
+    long m = g.nx - 2;
+    hipLaunchKernelGGL(k_net_apply, dim3(cdiv(m * m * m, kNB)), dim3(kNB), 0, st, g, phi, out, s);
+}
+
+void net_target(hipStream_t st, SGrid g, const double* pa, const double* pb, double inv_s, float* t)
+{
+    long m = g.nx - 2;
+    hipLaunchKernelGGL(k_net_target, dim3(cdiv(m * m * m, kNB)), dim3(kNB), 0, st, g, pa, pb, inv_s, t);
+}
+
+}  // namespace np
+
+// ------------------------------------------------------------------ C ABI (include/nested_poisson.h)
+using namespace np;
+
+static bool net_ok(int cin, int cout) { return cin >= 1 && cin <= 16 && cout >= 1 && cout <= 16; }
+static bool dims_ok(int b, int z, int y, int x) { return b >= 1 && z >= 1 && y >= 1 && x >= 1; }
+
+extern "C" {
+
+size_t np_net_workspace_bytes(int cin, int cout, long nvox)
+{
+    size_t a = net_ok(cin, cout) ? net_bwd_weight_workspace(cin, cout) : 0;
+    size_t b = nvox > 0 ? net_mse_workspace(nvox) : 0;
+    return a > b ? a : b;
+}
+
+int np_net_conv3d_fwd(const float* in, int cin, const unsigned short* w, const float* bias, int cout, int relu,
+                      int batch, int nz, int ny, int nx, float* out, void* stream)
+{
+    if (!in || !w || !bias || !out || !net_ok(cin, cout) || !dims_ok(batch, nz, ny, nx)) return NP_EINVAL;
+    net_conv_fwd_f32((hipStream_t)stream, in, cin, w, bias, cout, relu, batch, nz, ny, nx, out);
+    return hipGetLastError() == hipSuccess ? NP_OK : NP_EHIP;
+}
+
+int np_net_conv3d_fwd_mfma(const unsigned short* in, const unsigned short* w, const float* bias, int relu, int batch,
+                           int nz, int ny, int nx, unsigned short* out, void* stream)
+{
+    if (!in || !w || !bias || !out || !dims_ok(batch, nz, ny, nx)) return NP_EINVAL;
+    if (((uintptr_t)in & 7) || ((uintptr_t)w & 7)) return NP_EINVAL;
+    net_conv16_mfma((hipStream_t)stream, in, w, bias, relu, batch, nz, ny, nx, out);
+    return hipGetLastError() == hipSuccess ? NP_OK : NP_EHIP;
+}
+
+int np_net_conv3d_bwd_data(const float* gout, int cout, const unsigned short* w, int cin, int batch, int nz, int ny,
+                           int nx, float* gin, void* stream)
+{
+    if (!gout || !w || !gin || !net_ok(cin, cout) || !dims_ok(batch, nz, ny, nx)) return NP_EINVAL;
+    net_conv_bwd_data((hipStream_t)stream, gout, cout, w, cin, batch, nz, ny, nx, gin);
+    return hipGetLastError() == hipSuccess ? NP_OK : NP_EHIP;
+}
+
+int np_net_conv3d_bwd_weight(const float* in, int cin, const float* gout, int cout, int batch, int nz, int ny, int nx,
+                             float* gw, float* gb, float* workspace, size_t workspace_bytes, void* stream)
+{
+    if (!in || !gout || !gw || !gb || !workspace || !net_ok(cin, cout) || !dims_ok(batch, nz, ny, nx)) return NP_EINVAL;
+    if (workspace_bytes < net_bwd_weight_workspace(cin, cout)) return NP_EINVAL;
+    net_conv_bwd_weight((hipStream_t)stream, in, cin, gout, cout, batch, nz, ny, nx, gw, gb, workspace);
+    return hipGetLastError() == hipSuccess ? NP_OK : NP_EHIP;
+}
+
+int np_net_relu_bwd(const float* act, float* grad, long n, void* stream)
+{
+    if (!act || !grad || n < 0) return NP_EINVAL;
+    if (n) net_relu_bwd((hipStream_t)stream, act, grad, n);
+    return hipGetLastError() == hipSuccess ? NP_OK : NP_EHIP;
+}
+
+int np_net_mse(const float* pred, const float* target, const float* mask, long n, float count, float* grad,
+               float* loss, float* workspace, size_t workspace_bytes, void* stream)
+{
+    if (!pred || !target || !grad || !loss || !workspace || n < 1 || !(count > 0)) return NP_EINVAL;
+    if (workspace_bytes < net_mse_workspace(n)) return NP_EINVAL;
+    net_mse((hipStream_t)stream, pred, target, mask, n, count, grad, workspace, loss);
+    return hipGetLastError() == hipSuccess ? NP_OK : NP_EHIP;
+}
+
+int np_net_adam(float* w, const float* g, float* m, float* v, long n, float lr, float beta1, float beta2, float eps,
+                int step, unsigned short* w_bf16, void* stream)
+{
+    if (!w || !g || !m || !v || n < 0 || step < 1) return NP_EINVAL;
+    if (n) net_adam((hipStream_t)stream, w, g, m, v, n, lr, beta1, beta2, eps, step, w_bf16);
+    return hipGetLastError() == hipSuccess ? NP_OK : NP_EHIP;
+}
+
+int np_net_to_bf16(const float* a, unsigned short* b, long n, void* stream)
+{
+    if (!a || !b || n < 0) return NP_EINVAL;
+    if (n) net_to_bf16((hipStream_t)stream, a, b, n);
+    return hipGetLastError() == hipSuccess ? NP_OK : NP_EHIP;
+}
+
+}  // extern "C"

@@ -48,7 +48,8 @@ bool validate(const np_config* c, char* why, size_t nwhy)
     if (c->stop_rule != NP_STOP_RESIDUAL && c->stop_rule != NP_STOP_FORCE_DELTA) return fail("bad stop_rule %d%s", c->stop_rule, 0);
     if (c->precision != NP_PREC_FP64 && c->precision != NP_PREC_FP32_DC && c->precision != NP_PREC_FP16S_DC)
         return fail("bad precision %d%s", c->precision, 0);
-    if (c->guess != NP_GUESS_INTERP) return fail("guess %d not available in this build%s", c->guess, 0);
+    if (c->guess != NP_GUESS_INTERP && c->guess != NP_GUESS_LEARNED) return fail("bad guess %d%s", c->guess, 0);
+    if (c->guess == NP_GUESS_LEARNED && c->dim != 3) return fail("the learned guess is 3-D only (dim %d)%s", c->dim, 0);
     if (c->inner_cycles < 1 || c->inner_cycles > 8) return fail("inner_cycles must be 1..8 (got %d)%s", c->inner_cycles, 0);
     return true;
 }
@@ -159,6 +160,18 @@ struct np_solver {
     float* mg_u32[NP_MAX_MG] = {};
     float* mg_f32[NP_MAX_MG] = {};
     hipGraphExec_t coarse_exec32[NP_MAX_LEVELS] = {};
+    // learned initial guess: weights (bfloat16 per layer, FP32 biases) and
+    // activations on Gamma of the largest level
+    bool have_weights = false;
+    uint16_t* net_w[3] = {};
+    float* net_b[3] = {};
+    uint16_t* net_x = nullptr;
+    uint16_t* net_a1 = nullptr;
+    uint16_t* net_a2 = nullptr;
+    float* net_out = nullptr;
+    // training-feature scratch (interpolated guess of one level), on demand
+    double* feat_phi = nullptr;
+    double* feat_f = nullptr;
 };
 
 namespace {
@@ -439,6 +452,47 @@ int dc_step(np_solver* s, int l, double r_scale)
     return NP_OK;
 }
 
+constexpr double kLearnedKeep = 0.5;
+
+// Learned initial guess of level l >= 1 (3-D): the network's prediction from
+// the interpolated guess, kept only if it lowers the max-norm residual by
+// kLearnedKeep or more; otherwise the interpolated guess is restored.  *r is the residual norm of
+// the guess in effect on return.
+int learned_guess(np_solver* s, int l, const double* rho_l, double fourpiG, double fnorm, double* r, int* used)
+{
+    *used = 0;
+    if (!s->have_weights || !(fnorm > 0.0) || !std::isfinite(*r)) return NP_OK;
+    const np_config& c = s->cfg;
+    hipStream_t st = s->stream;
+    SGrid g = s->lg[l];
+    const int m = g.nx - 2;
+    const double dx = std::ldexp(c.dx0, -l);
+    prof_begin(s, NP_KCLASS_GUESS);
+    net_features_bf16(st, g, s->phi[l], s->f[l], 1.0 / fnorm, 1.0 / (dx * dx), s->net_x);
+    net_conv_fwd_bf16(st, s->net_x, 2, s->net_w[0], s->net_b[0], 16, 1, 1, m, m, m, s->net_a1);
+    net_conv16_mfma(st, s->net_a1, s->net_w[1], s->net_b[1], 1, 1, m, m, m, s->net_a2);
+    net_conv_fwd_bf16_to_f32(st, s->net_a2, 16, s->net_w[2], s->net_b[2], 1, 0, 1, m, m, m, s->net_out);
+    net_apply(st, g, s->phi[l], s->net_out, fnorm * dx * dx);
+    prof_end(s);
+    HIPCHK(s, hipGetLastError());
+    double rl = 0.0;
+    int rc = norm_sync(s, l, 0, &rl);
+    if (rc) return rc;
+    // keep the network's guess only if it at least halves the max-norm residual
+    // of the interpolated guess (it then removed the dominant local error);
+    // otherwise the V-cycles start from the interpolant
+    if (rl <= kLearnedKeep * *r) {
+        *r = rl;
+        *used = 1;
+        return NP_OK;
+    }
+    // fallback: restore the interpolated guess
+    launch_interface_fill(c.dim, st, s->lg[l - 1], s->phi[l - 1], s->f[l - 1], g, c.n[l], c.offset[l][0],
+                          c.offset[l][1], c.offset[l][2], rho_l, fourpiG, s->phi[l], s->f[l]);
+    HIPCHK(s, hipGetLastError());
+    return NP_OK;
+}
+
 void free_all(np_solver* s)
 {
     for (int l = 0; l < NP_MAX_LEVELS; l++) {
@@ -467,6 +521,18 @@ void free_all(np_solver* s)
     if (s->e_lo) (void)hipFree(s->e_lo);
     if (s->r_lo) (void)hipFree(s->r_lo);
     s->e_lo = s->r_lo = nullptr;
+    for (int k = 0; k < 3; k++) {
+        if (s->net_w[k]) (void)hipFree(s->net_w[k]);
+        if (s->net_b[k]) (void)hipFree(s->net_b[k]);
+        s->net_w[k] = nullptr;
+        s->net_b[k] = nullptr;
+    }
+    void* net[] = {s->net_x, s->net_a1, s->net_a2, s->net_out, s->feat_phi, s->feat_f};
+    for (void* p : net)
+        if (p) (void)hipFree(p);
+    s->net_x = s->net_a1 = s->net_a2 = nullptr;
+    s->net_out = nullptr;
+    s->feat_phi = s->feat_f = nullptr;
     if (s->force_scratch) (void)hipFree(s->force_scratch);
     if (s->d_bits) (void)hipFree(s->d_bits);
     if (s->h_bits) (void)hipHostFree(s->h_bits);
@@ -579,6 +645,24 @@ int nested_poisson_create(const np_config* cfg, void* hip_stream, np_solver** ou
         rc = alloc_dev(s, &s->e_lo, s->lo_bytes);
         if (rc == NP_OK) rc = alloc_dev(s, &s->r_lo, s->lo_bytes);
     }
+    if (rc == NP_OK && cfg->guess == NP_GUESS_LEARNED) {
+        size_t vox = 0;
+        for (int l = 1; l < cfg->nlevels; l++) {
+            size_t m = (size_t)cfg->n[l] + 2;
+            if (m * m * m > vox) vox = m * m * m;
+        }
+        const int cin[3] = {2, 16, 16}, cout[3] = {16, 16, 1};
+        for (int k = 0; k < 3 && rc == NP_OK; k++) {
+            rc = alloc_dev(s, (void**)&s->net_w[k], 27 * cin[k] * cout[k] * sizeof(uint16_t));
+            if (rc == NP_OK) rc = alloc_dev(s, (void**)&s->net_b[k], 16 * sizeof(float));
+        }
+        if (rc == NP_OK && vox) {
+            rc = alloc_dev(s, (void**)&s->net_x, vox * 2 * sizeof(uint16_t));
+            if (rc == NP_OK) rc = alloc_dev(s, (void**)&s->net_a1, vox * 16 * sizeof(uint16_t));
+            if (rc == NP_OK) rc = alloc_dev(s, (void**)&s->net_a2, vox * 16 * sizeof(uint16_t));
+            if (rc == NP_OK) rc = alloc_dev(s, (void**)&s->net_out, vox * sizeof(float));
+        }
+    }
     if (rc == NP_OK && cfg->stop_rule == NP_STOP_FORCE_DELTA) {
         size_t cells = (size_t)maxn * maxn * (d == 3 ? maxn : 1);
         rc = alloc_dev(s, (void**)&s->force_scratch, (size_t)d * cells * sizeof(double));
@@ -649,14 +733,23 @@ int nested_poisson_solve(np_solver* s, const double* const* rho, const double* p
         }
         prof_end(s);
         HIPCHK(s, hipGetLastError());
-        double scale = 0.0;
-        int rc = norm_sync(s, l, 1, &scale);
+        double fnorm = 0.0;
+        int rc = norm_sync(s, l, 1, &fnorm);
         if (rc) return rc;
-        if (!std::isfinite(scale)) return set_err(s, NP_ENONFINITE, "level %d: non-finite density", l);
+        if (!std::isfinite(fnorm)) return set_err(s, NP_ENONFINITE, "level %d: non-finite density", l);
+        double scale = fnorm;
         if (!(scale > 0.0)) {
             rc = norm_sync(s, l, 2, &scale);
             if (rc) return rc;
             if (!std::isfinite(scale)) return set_err(s, NP_ENONFINITE, "level %d: non-finite boundary data", l);
+        }
+        double r = 0.0;
+        rc = norm_sync(s, l, 0, &r);
+        if (rc) return rc;
+        st.interp_rel_residual[l] = scale > 0 ? r / scale : r;
+        if (l > 0 && c.guess == NP_GUESS_LEARNED) {
+            rc = learned_guess(s, l, rho[l], fourpiG, fnorm, &r, &st.learned_used[l]);
+            if (rc) return rc;
         }
         double Fdelta = 0.0;
         bool pinned = s->has_fixed && s->fixed[l] >= 0;
@@ -664,9 +757,6 @@ int nested_poisson_solve(np_solver* s, const double* const* rho, const double* p
             rc = force_delta_sync(s, l, &Fdelta);  // seeds the previous-force buffer
             if (rc) return rc;
         }
-        double r = 0.0;
-        rc = norm_sync(s, l, 0, &r);
-        if (rc) return rc;
         const double r0 = r;
         s->hist[l].push_back(scale > 0 ? r / scale : r);
         int q = 0;
@@ -790,6 +880,67 @@ void nested_poisson_destroy(np_solver* s)
     prof_release(s);
     free_all(s);
     delete s;
+}
+
+int nested_poisson_set_guess_weights(np_solver* s, const float* theta, size_t n)
+{
+    if (!s) return NP_EINVAL;
+    if (!theta || n != NP_NET_PARAMS) return set_err(s, NP_EINVAL, "expected %d parameters", NP_NET_PARAMS);
+    if (s->cfg.guess != NP_GUESS_LEARNED) return set_err(s, NP_ESTATE, "handle created without the learned guess");
+    HIPCHK(s, hipSetDevice(s->device));
+    float* tmp = nullptr;
+    int rc = alloc_dev(s, (void**)&tmp, n * sizeof(float));
+    if (rc) return rc;
+    hipError_t e = hipMemcpyAsync(tmp, theta, n * sizeof(float), hipMemcpyHostToDevice, s->stream);
+    const int cin[3] = {2, 16, 16}, cout[3] = {16, 16, 1};
+    size_t k0 = 0;
+    for (int k = 0; k < 3 && e == hipSuccess; k++) {
+        size_t nw = 27 * (size_t)cin[k] * cout[k];
+        net_to_bf16(s->stream, tmp + k0, s->net_w[k], (long)nw);
+        e = hipMemcpyAsync(s->net_b[k], tmp + k0 + nw, cout[k] * sizeof(float), hipMemcpyDeviceToDevice, s->stream);
+        k0 += nw + cout[k];
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    (void)hipFree(tmp);
+    if (e != hipSuccess) return set_err(s, NP_EHIP, "setting weights: %s", hipGetErrorString(e));
+    s->have_weights = true;
+    return NP_OK;
+}
+
+int nested_poisson_guess_features(np_solver* s, int level, float* x, float* target)
+{
+    if (!s) return NP_EINVAL;
+    const np_config& c = s->cfg;
+    if (c.dim != 3 || level < 1 || level >= c.nlevels || !x)
+        return set_err(s, NP_EINVAL, "features need a 3-D level >= 1 and an output array");
+    if (!s->solved) return set_err(s, NP_ESTATE, "features requested before a successful solve");
+    HIPCHK(s, hipSetDevice(s->device));
+    if (!s->feat_phi) {
+        size_t best = 0;
+        for (int l = 0; l < c.nlevels; l++)
+            if (2 * s->lg[l].cs > best) best = 2 * s->lg[l].cs;
+        int rc = alloc_dev(s, (void**)&s->feat_phi, best * sizeof(double));
+        if (rc == NP_OK) rc = alloc_dev(s, (void**)&s->feat_f, best * sizeof(double));
+        if (rc) return rc;
+    }
+    // the interpolated guess of this level, rebuilt from the converged coarser level;
+    // the density of the patch itself does not enter Phi_interp, so the level's own
+    // right-hand side serves as the density argument (only f_tmp's patch part uses it)
+    const int l = level;
+    double dx = std::ldexp(c.dx0, -l);
+    double fourpiG = 4.0 * M_PI * c.G;
+    launch_interface_fill(c.dim, s->stream, s->lg[l - 1], s->phi[l - 1], s->f[l - 1], s->lg[l], c.n[l], c.offset[l][0],
+                          c.offset[l][1], c.offset[l][2], s->f[l], 0.0, s->feat_phi, s->feat_f);
+    double fnorm = 0.0;
+    int rc = norm_sync(s, l, 1, &fnorm);
+    if (rc) return rc;
+    if (!(fnorm > 0.0)) return set_err(s, NP_EINVAL, "level %d has zero density", l);
+    (void)fourpiG;
+    net_features_f32(s->stream, s->lg[l], s->feat_phi, s->f[l], 1.0 / fnorm, 1.0 / (dx * dx), x);
+    if (target) net_target(s->stream, s->lg[l], s->phi[l], s->feat_phi, 1.0 / (fnorm * dx * dx), target);
+    HIPCHK(s, hipGetLastError());
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    return NP_OK;
 }
 
 int nested_poisson_set_profiling(np_solver* s, int enable)

@@ -62,6 +62,8 @@ class NestedPoissonSolver:
             scale=[st.scale[l] for l in range(L)],
             level_ms=[st.level_ms[l] for l in range(L)],
             total_ms=st.total_ms,
+            learned_used=[st.learned_used[l] for l in range(L)],
+            interp_rel_residual=[st.interp_rel_residual[l] for l in range(L)],
         )
         return self.last_stats
 
@@ -96,6 +98,23 @@ class NestedPoissonSolver:
         self._tensor(out, (n + 4,) * d, "phi")
         self._check(_lib.lib().nested_poisson_potential(self._h, level, ctypes.c_void_p(out.data_ptr())))
         return out
+
+    def set_guess_weights(self, theta):
+        """Network parameters (NP_NET_PARAMS floats, host array-like)."""
+        import numpy as np
+        th = np.ascontiguousarray(np.asarray(theta, dtype=np.float32).reshape(-1))
+        self._check(_lib.lib().nested_poisson_set_guess_weights(
+            self._h, th.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), th.size))
+
+    def guess_features(self, level, with_target=True):
+        """(x, target) of the learned guess for a level >= 1 after a solve:
+        x is (n+2)^3 x 2 channel-last, target (n+2)^3 (FP32 device tensors)."""
+        m = self.n[level] + 2
+        x = torch.empty((m, m, m, 2), dtype=torch.float32, device=self.device)
+        t = torch.empty((m, m, m), dtype=torch.float32, device=self.device) if with_target else None
+        self._check(_lib.lib().nested_poisson_guess_features(self._h, level, ctypes.c_void_p(x.data_ptr()),
+                                                             ctypes.c_void_p(t.data_ptr() if t is not None else 0)))
+        return x, t
 
     def set_profiling(self, enable=True):
         self._check(_lib.lib().nested_poisson_set_profiling(self._h, int(bool(enable))))
