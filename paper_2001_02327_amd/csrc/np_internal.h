@@ -60,26 +60,43 @@ void launch_set_u64(hipStream_t st, unsigned long long* p, int count, unsigned l
 
 // multigrid operators, templated on the storage type (double, float; __half
 // only on multigrid level 0 of the FP16-storage defect correction)
-// fine != 0: the nested-level arrays (multigrid level 0, fixed ghost layer)
+// fine != 0: the nested-level arrays (multigrid level 0, ghost layer in
+// memory); fine == 0: a multigrid level L >= 1 whose ghost values follow the
+// rule (xn1 = x_N is 1, coef = right coefficient) where they are read
 template <typename T>
-void launch_half_sweep(int dim, hipStream_t st, SGrid g, T* u, const T* f, int colour, double h2, int fine);
-template <typename T>
-void launch_ghost_fill(int dim, hipStream_t st, SGrid g, T* u, int xn_is_one, double coef);
-// fine grid of type TF, coarse of type TC; the coarse right-hand side is multiplied by out_scale
+void launch_half_sweep(int dim, hipStream_t st, SGrid g, T* u, const T* f, int colour, double h2, int fine, int xn1,
+                       double coef);
+// fine grid of type TF, coarse of type TC; the coarse right-hand side is
+// multiplied by out_scale; rule != 0: the fine grid is a level L >= 1
 template <typename TF, typename TC>
 void launch_resid_restrict(int dim, hipStream_t st, SGrid gf, const TF* u, const TF* f, double inv_h2, double out_scale,
-                           SGrid gc, TC* fc, TC* ec);
-// black_only != 0 corrects only the black points
+                           SGrid gc, TC* fc, TC* ec, int rule, int xn1, double coef);
+// black_only != 0 corrects only the black points; (xn1, coef): the coarse level's rule
 template <typename TC, typename TF>
-void launch_prolong_add(int dim, hipStream_t st, SGrid gc, const TC* ec, SGrid gf, TF* u, int black_only);
+void launch_prolong_add(int dim, hipStream_t st, SGrid gc, const TC* ec, SGrid gf, TF* u, int black_only, int xn1,
+                        double coef);
 
-// defect correction: r = (f - lap phi) * rscale in low precision (+ its FP64 max
-// norm), clearing the black (and with clear_red the red) points of e; phi += factor * e
+// coarse tail: levels Lt .. Lt+nlev-1 of one V-cycle (N[a], spacing h[a], rule
+// xn1[a]/coef[a]; N[nlev-1] == 1) in one workgroup with the levels in LDS;
+// reads f and writes the correction u of level Lt (grid g0).  Returns -1
+// without launching when the levels do not fit (coarse_tail_lds_bytes).
+constexpr int kTailMaxLevels = 8;
+constexpr size_t kTailLdsBytes = 64 * 1024;
+size_t coarse_tail_lds_bytes(int dim, const int* N, int nlev, size_t esz);
+template <typename T>
+int launch_coarse_tail(int dim, hipStream_t st, int nlev, const int* N, const double* h, const int* xn1,
+                       const double* coef, int n_pre, int n_post, SGrid g0, const T* f0, T* u0);
+
+// defect correction, one fused outer pass: phi_out = phi_in + factor * e_in
+// (no update and no write of phi_out when e_in is null), r = (f - lap phi_out)
+// * rscale in low precision (+ its FP64 max norm into maxbits), and the next
+// correction e_out: zero, or with first_red the first red half sweep from zero
 template <typename TL>
-void launch_dc_residual(int dim, hipStream_t st, SGrid g, const double* phi, const double* f, double inv_h2,
-                        double rscale, TL* r, TL* e, int clear_red, unsigned long long* maxbits);
-template <typename TL>
-void launch_dc_update(int dim, hipStream_t st, SGrid g, double* phi, const TL* e, double factor);
+void launch_dc_outer(int dim, hipStream_t st, SGrid g, const double* phi_in, const TL* e_in, double factor,
+                     double* phi_out, const double* f, double inv_h2, double rscale, TL* r, TL* e_out, int first_red,
+                     unsigned long long* maxbits);
+// ghost layer of a nested-level array copied from src to dst
+void launch_copy_ghosts(int dim, hipStream_t st, SGrid g, const double* src, double* dst);
 
 // learned initial guess network (np_net.hip); activations channel-last,
 // weights bfloat16 [27][cout][cin]

@@ -415,14 +415,66 @@ struct Compute { using type = T; };
 template <>
 struct Compute<__half> { using type = float; };
 
+// Ghost rule of a multigrid level L >= 1 (Sec. 2.4): the layer outside the
+// active points 1..N is anti-symmetric, e_0 = -e_1 on the left and on the right
+// e_{N+1} = -e_{N-1} when x_N = 1, else coef * e_N; points outside along several
+// axes compose the rule of each axis in the order x, y, z.  The kernels never
+// store this layer: they evaluate it where they read it.  That gives the values
+// a refresh before every half sweep would: a face ghost next to an active
+// point p depends only on p itself or on the point beyond p on the same axis,
+// which has the other colour, and neither changes before p's own update.
+template <typename C>
+struct GRule {
+    int xn1;
+    C coef;
+};
+
+// Value at padded point p of a level with a rule ghost layer (any point, ghost
+// along any number of axes).  Factors are applied per axis in x, y, z order.
+template <int D, typename T, typename C>
+__device__ __forceinline__ C rule_at(const T* __restrict__ a, const SGrid& g, int pi, int pj, int pk,
+                                     const GRule<C>& gr)
+{
+    const int N = g.nx - 2;
+    int p[3] = {pi, pj, pk};
+    C fac[3] = {(C)1, (C)1, (C)1};
+    bool sc[3] = {false, false, false};
+    for (int ax = 0; ax < D; ax++) {
+        if (p[ax] == 0) {
+            p[ax] = 1;
+            fac[ax] = (C)-1;
+            sc[ax] = true;
+        } else if (p[ax] == N + 1) {
+            p[ax] = gr.xn1 ? N - 1 : N;
+            fac[ax] = gr.xn1 ? (C)-1 : gr.coef;
+            sc[ax] = true;
+        }
+    }
+    C v = (C)at<D>(a, g, p[0], p[1], p[2]);
+    for (int ax = 0; ax < D; ax++)
+        if (sc[ax]) v = fac[ax] * v;
+    return v;
+}
+
+// Face-ghost substitution for a 7-point stencil at active index q (1..N) along
+// one axis: the neighbour below (q = 1) is -self; the neighbour above (q = N)
+// is -(the neighbour below) when x_N = 1, else coef * self.
+template <typename C>
+__device__ __forceinline__ void rule_pair(int q, int N, C self, C& lo, C& hi, const GRule<C>& gr)
+{
+    if (q == 1) lo = -self;
+    if (q == N) hi = gr.xn1 ? -lo : gr.coef * self;
+}
+
 // Red-black Gauss-Seidel half sweep: u_c = (sum of the 2d neighbours - h^2 f_c) / (2d)
 // over the active points of one colour; the neighbours are all of the other colour.
 // k_smooth_fine runs it on the nested-level arrays (multigrid level 0, whose
 // ghost layer is the fixed outer buffer), k_half_sweep on the coarse levels.
-template <int D, typename T>
+template <int D, typename T, bool RULE>
 __device__ __forceinline__ void half_sweep_body(T* __restrict__ u, const T* __restrict__ f, SGrid g,
                                                        int colour, typename Compute<T>::type h2,
-                                                       typename Compute<T>::type inv2d)
+                                                       typename Compute<T>::type inv2d,
+                                                       GRule<typename Compute<T>::type> gr)
 {
     using C = typename Compute<T>::type;
     long t = xcd_block() * kBlock + threadIdx.x;
@@ -438,15 +490,30 @@ __device__ __forceinline__ void half_sweep_body(T* __restrict__ u, const T* __re
     const T* __restrict__ o = u + (size_t)(colour ^ 1) * g.cs;
     size_t row = row_base(g, pj, pk);
     size_t ny = (size_t)g.hx, nz = (size_t)g.nx * g.hx;
-    C s = (C)o[row + ((pi - 1) >> 1)];
-    s = s + (C)o[row + ((pi + 1) >> 1)];
-    s = s + (C)o[row - ny + h];
-    s = s + (C)o[row + ny + h];
-    if (D == 3) {
-        s = s + (C)o[row - nz + h];
-        s = s + (C)o[row + nz + h];
-    }
     size_t self = (size_t)colour * g.cs + row + h;
+    C xm = (C)o[row + ((pi - 1) >> 1)], xp = (C)o[row + ((pi + 1) >> 1)];
+    C ym = (C)o[row - ny + h], yp = (C)o[row + ny + h];
+    C zm = 0, zp = 0;
+    if (D == 3) {
+        zm = (C)o[row - nz + h];
+        zp = (C)o[row + nz + h];
+    }
+    if (RULE) {
+        const int N = g.nx - 2;
+        if (pi == 1 || pi == N || pj == 1 || pj == N || (D == 3 && (pk == 1 || pk == N))) {
+            const C me = (C)u[self];
+            rule_pair(pi, N, me, xm, xp, gr);
+            rule_pair(pj, N, me, ym, yp, gr);
+            if (D == 3) rule_pair(pk, N, me, zm, zp, gr);
+        }
+    }
+    C s = xm + xp;
+    s = s + ym;
+    s = s + yp;
+    if (D == 3) {
+        s = s + zm;
+        s = s + zp;
+    }
     u[self] = (T)((s - h2 * (C)f[self]) * inv2d);
 }
 
@@ -455,7 +522,7 @@ template <int D, typename T>
 __global__ void __launch_bounds__(kBlock) k_smooth_fine(T* __restrict__ u, const T* __restrict__ f, SGrid g, int colour,
                                                         typename Compute<T>::type h2, typename Compute<T>::type inv2d)
 {
-    half_sweep_body<D, T>(u, f, g, colour, h2, inv2d);
+    half_sweep_body<D, T, false>(u, f, g, colour, h2, inv2d, GRule<typename Compute<T>::type>{0, 0});
 }
 
 // 3-D level-0 half sweep marching along z.  A thread owns one compact (h, pj)
@@ -468,12 +535,16 @@ __global__ void __launch_bounds__(kBlock) k_smooth_fine(T* __restrict__ u, const
 // its L2.
 constexpr int kZChunk = 8;
 
+// TAG 0: level 0 (ghost layer in memory); TAG 1: coarse levels, whose ghost
+// values come from the rule (GRule) where a boundary point reads them.
 template <typename T, int TAG>
 __global__ void __launch_bounds__(kBlock) k_smooth_zmarch3(T* __restrict__ u, const T* __restrict__ f, SGrid g, int colour,
                                                            typename Compute<T>::type h2,
-                                                           typename Compute<T>::type inv2d, int pblocks)
+                                                           typename Compute<T>::type inv2d, int pblocks,
+                                                           GRule<typename Compute<T>::type> gr)
 {
     using C = typename Compute<T>::type;
+    constexpr bool RULE = TAG == 1;
     const int m = g.nx - 2;
     const long lb = xcd_block();
     const int zc = (int)(lb / pblocks);
@@ -515,11 +586,21 @@ __global__ void __launch_bounds__(kBlock) k_smooth_zmarch3(T* __restrict__ u, co
             if (pi >= 1 && pi <= g.nx - 2) {
                 C xm = par ? cur : xo[q];
                 C xp = par ? xo[q] : cur;
+                C y0 = ym[q], y1 = yp[q], z0 = below, z1 = ab[q];
+                if (RULE) {
+                    const int kk = pk + q;
+                    if (pi == 1 || pi == m || pj == 1 || pj == m || kk == 1 || kk == m) {
+                        const C me = (C)uc[here];
+                        rule_pair(pi, m, me, xm, xp, gr);
+                        rule_pair(pj, m, me, y0, y1, gr);
+                        rule_pair(kk, m, me, z0, z1, gr);
+                    }
+                }
                 C s = xm + xp;
-                s = s + ym[q];
-                s = s + yp[q];
-                s = s + below;
-                s = s + ab[q];
+                s = s + y0;
+                s = s + y1;
+                s = s + z0;
+                s = s + z1;
                 uc[here] = (T)((s - h2 * fv[q]) * inv2d);
             }
             below = cur;
@@ -535,11 +616,20 @@ __global__ void __launch_bounds__(kBlock) k_smooth_zmarch3(T* __restrict__ u, co
             // x-neighbours pi-1, pi+1: compact h-1 and h (par 0) or h and h+1 (par 1)
             C xm = par ? cur : (C)o[here - 1];
             C xp = par ? (C)o[here + 1] : cur;
+            C y0 = (C)o[here - g.hx], y1 = (C)o[here + g.hx], z0 = below, z1 = above;
+            if (RULE) {
+                if (pi == 1 || pi == m || pj == 1 || pj == m || pk == 1 || pk == m) {
+                    const C me = (C)uc[here];
+                    rule_pair(pi, m, me, xm, xp, gr);
+                    rule_pair(pj, m, me, y0, y1, gr);
+                    rule_pair(pk, m, me, z0, z1, gr);
+                }
+            }
             C s = xm + xp;
-            s = s + (C)o[here - g.hx];
-            s = s + (C)o[here + g.hx];
-            s = s + below;
-            s = s + above;
+            s = s + y0;
+            s = s + y1;
+            s = s + z0;
+            s = s + z1;
             uc[here] = (T)((s - h2 * (C)fc[here]) * inv2d);
         }
         below = cur;
@@ -549,9 +639,10 @@ __global__ void __launch_bounds__(kBlock) k_smooth_zmarch3(T* __restrict__ u, co
 
 template <int D, typename T>
 __global__ void __launch_bounds__(kBlock) k_half_sweep(T* __restrict__ u, const T* __restrict__ f, SGrid g, int colour,
-                                                       typename Compute<T>::type h2, typename Compute<T>::type inv2d)
+                                                       typename Compute<T>::type h2, typename Compute<T>::type inv2d,
+                                                       GRule<typename Compute<T>::type> gr)
 {
-    half_sweep_body<D, T>(u, f, g, colour, h2, inv2d);
+    half_sweep_body<D, T, true>(u, f, g, colour, h2, inv2d, gr);
 }
 
 // Paired form of the level-0 z-march for 2- and 4-byte storage: a thread owns
@@ -635,66 +726,18 @@ __global__ void __launch_bounds__(kBlock) k_smooth_zmarch3_pair(T* __restrict__ 
     }
 }
 
-// Ghost layer of a multigrid level L >= 1 (Sec. 2.4): left e_0 = -e_1; right
-// -e_{N-1} when x_N = 1, else coef * e_N; edges and corners compose the rule
-// of each axis they are ghosts on, applied in the order x, y, z.
-// blockIdx.y = face (2 per axis).
-template <int D, typename T>
-__global__ void __launch_bounds__(kBlock) k_ghost_fill(T* __restrict__ u, SGrid g, int xn_is_one,
-                                                       typename Compute<T>::type coef)
-{
-    using C = typename Compute<T>::type;
-    int Q = g.nx, N = Q - 2;
-    int t = blockIdx.x * kBlock + threadIdx.x;
-    int per = D == 3 ? Q * Q : Q;
-    if (t >= per) return;
-    int face = blockIdx.y;
-    int axis = face >> 1, side = face & 1;
-    int p[3] = {0, 0, 0};
-    int a = t % Q, b = t / Q;
-    if (D == 3) {
-        p[axis] = side ? Q - 1 : 0;
-        p[(axis + 1) % 3] = a;
-        p[(axis + 2) % 3] = b;
-    } else {
-        p[axis] = side ? Q - 1 : 0;
-        p[1 - axis] = a;
-    }
-    int src[3] = {p[0], p[1], p[2]};
-    C fac[3] = {1, 1, 1};
-    bool scaled[3] = {false, false, false};
-    for (int ax = 0; ax < D; ax++) {
-        if (src[ax] == 0) {
-            src[ax] = 1;
-            fac[ax] = -1;
-            scaled[ax] = true;
-        } else if (src[ax] == Q - 1) {
-            if (xn_is_one) {
-                src[ax] = N - 1;
-                fac[ax] = -1;
-            } else {
-                src[ax] = N;
-                fac[ax] = coef;
-            }
-            scaled[ax] = true;
-        }
-    }
-    C v = (C)at<D>(u, g, src[0], src[1], src[2]);
-    for (int ax = 0; ax < D; ax++)
-        if (scaled[ax]) v = fac[ax] * v;
-    u[pos<D, T>(g, p[0], p[1], p[2])] = (T)v;
-}
-
 // Residual r = f - lap(u) on the 2^d children of each coarse active point and
 // their mean (eqn:restriction2D/3D) into the coarse right-hand side, times
 // out_scale (1 except below a scaled level-0 defect problem); children beyond
 // the fine active range count as zero.  Also clears the coarse correction.
-// TF: fine storage, TC: coarse storage.
-template <int D, typename TF, typename TC>
+// TF: fine storage, TC: coarse storage; RULE: the fine level is a coarse
+// multigrid level whose ghost values come from its rule.
+template <int D, typename TF, typename TC, bool RULE>
 __global__ void __launch_bounds__(kBlock) k_resid_restrict(const TF* __restrict__ u, const TF* __restrict__ f, SGrid gf,
                                                            typename Compute<TC>::type inv_h2,
                                                            typename Compute<TC>::type out_scale, SGrid gc,
-                                                           TC* __restrict__ fc, TC* __restrict__ ec)
+                                                           TC* __restrict__ fc, TC* __restrict__ ec,
+                                                           GRule<typename Compute<TC>::type> gr)
 {
     using C = typename Compute<TC>::type;
     int Nc = gc.nx - 2, Nf = gf.nx - 2;
@@ -711,15 +754,26 @@ __global__ void __launch_bounds__(kBlock) k_resid_restrict(const TF* __restrict_
         for (int j = 2 * J - 1; j <= 2 * J; j++)
             for (int i = 2 * I - 1; i <= 2 * I; i++) {
                 if (i > Nf || j > Nf || (D == 3 && k > Nf)) continue;
-                C s = (C)at<D>(u, gf, i - 1, j, k);
-                s = s + (C)at<D>(u, gf, i + 1, j, k);
-                s = s + (C)at<D>(u, gf, i, j - 1, k);
-                s = s + (C)at<D>(u, gf, i, j + 1, k);
+                C xm = (C)at<D>(u, gf, i - 1, j, k), xp = (C)at<D>(u, gf, i + 1, j, k);
+                C ym = (C)at<D>(u, gf, i, j - 1, k), yp = (C)at<D>(u, gf, i, j + 1, k);
+                C zm = 0, zp = 0;
                 if (D == 3) {
-                    s = s + (C)at<D>(u, gf, i, j, k - 1);
-                    s = s + (C)at<D>(u, gf, i, j, k + 1);
+                    zm = (C)at<D>(u, gf, i, j, k - 1);
+                    zp = (C)at<D>(u, gf, i, j, k + 1);
                 }
                 C uc = (C)at<D>(u, gf, i, j, k);
+                if (RULE) {
+                    rule_pair(i, Nf, uc, xm, xp, gr);
+                    rule_pair(j, Nf, uc, ym, yp, gr);
+                    if (D == 3) rule_pair(k, Nf, uc, zm, zp, gr);
+                }
+                C s = xm + xp;
+                s = s + ym;
+                s = s + yp;
+                if (D == 3) {
+                    s = s + zm;
+                    s = s + zp;
+                }
                 sum += (C)at<D>(f, gf, i, j, k) - (s - (C)(2 * D) * uc) * inv_h2;
             }
     size_t pc = pos<D, TC>(gc, I, J, K);
@@ -732,10 +786,36 @@ __global__ void __launch_bounds__(kBlock) k_resid_restrict(const TF* __restrict_
 // 3/4, its neighbour on the side of the fine centre 1/4).  Each thread does
 // the red and the black point of one compact position; with black_only the
 // red points are left alone (used when a red half sweep that reads only
-// black values follows on a grid with a fixed ghost layer).
+// black values follows on a grid with a fixed ghost layer).  The coarse level
+// is a multigrid level L >= 1: where the parent q or its neighbour q + s is a
+// ghost (the parent of the last fine point is one when N_f = 2 N_c + 1), its
+// value comes from the rule.
+template <typename C>
+struct AxisNb {
+    int q;       // neighbour index after the rule
+    C fac;       // rule factor
+    bool ghost;  // the factor applies
+};
+
+template <typename C>
+__device__ __forceinline__ AxisNb<C> axis_nb(int q, int N, const GRule<C>& gr)
+{
+    AxisNb<C> a{q, (C)1, false};
+    if (q == 0) {
+        a.q = 1;
+        a.fac = (C)-1;
+        a.ghost = true;
+    } else if (q == N + 1) {
+        a.q = gr.xn1 ? N - 1 : N;
+        a.fac = gr.xn1 ? (C)-1 : gr.coef;
+        a.ghost = true;
+    }
+    return a;
+}
+
 template <int D, typename TC, typename TF>
 __global__ void __launch_bounds__(kBlock) k_prolong_add(const TC* __restrict__ e, SGrid gc, TF* __restrict__ u, SGrid gf,
-                                                        int black_only)
+                                                        int black_only, GRule<typename Compute<TC>::type> gr)
 {
     using C = typename Compute<TC>::type;
     int m = gf.nx - 2;
@@ -747,18 +827,34 @@ __global__ void __launch_bounds__(kBlock) k_prolong_add(const TC* __restrict__ e
     int pj = 1 + (int)(r % m);
     int pk = D == 3 ? 1 + (int)(r / m) : 0;
     const C w0 = (C)0.75, w1 = (C)0.25;
+    const int Nc = gc.nx - 2;
     int qj = (pj + 1) >> 1, sj = (pj & 1) ? -1 : 1;
     int qk = D == 3 ? (pk + 1) >> 1 : 0, sk = (pk & 1) ? -1 : 1;
+    const AxisNb<C> pj_ = axis_nb(qj, Nc, gr), nj = axis_nb(qj + sj, Nc, gr);
+    const AxisNb<C> none{0, (C)1, false};
+    const AxisNb<C> pk_ = D == 3 ? axis_nb(qk, Nc, gr) : none, nk = D == 3 ? axis_nb(qk + sk, Nc, gr) : none;
     for (int c = black_only; c < 2; c++) {
         int pi = 2 * h + ((c + pj + pk + D) & 1);
         if (pi < 1 || pi > gf.nx - 2) continue;
         int qi = (pi + 1) >> 1, si = (pi & 1) ? -1 : 1;
-        C y0 = w0 * (C)at<D>(e, gc, qi, qj, qk) + w1 * (C)at<D>(e, gc, qi + si, qj, qk);
-        C y1 = w0 * (C)at<D>(e, gc, qi, qj + sj, qk) + w1 * (C)at<D>(e, gc, qi + si, qj + sj, qk);
+        const AxisNb<C> pi_ = axis_nb(qi, Nc, gr), ni = axis_nb(qi + si, Nc, gr);
+        // coarse value at (parent or neighbour) per axis, rule factors in x, y, z order
+        auto E = [&](bool bx, bool by, bool bz) -> C {
+            const AxisNb<C>& ax = bx ? ni : pi_;
+            const AxisNb<C>& ay = by ? nj : pj_;
+            const AxisNb<C>& az = bz ? nk : pk_;
+            C v = (C)at<D>(e, gc, ax.q, ay.q, az.q);
+            if (ax.ghost) v = ax.fac * v;
+            if (ay.ghost) v = ay.fac * v;
+            if (az.ghost) v = az.fac * v;
+            return v;
+        };
+        C y0 = w0 * E(false, false, false) + w1 * E(true, false, false);
+        C y1 = w0 * E(false, true, false) + w1 * E(true, true, false);
         C v = w0 * y0 + w1 * y1;
         if (D == 3) {
-            C y2 = w0 * (C)at<D>(e, gc, qi, qj, qk + sk) + w1 * (C)at<D>(e, gc, qi + si, qj, qk + sk);
-            C y3 = w0 * (C)at<D>(e, gc, qi, qj + sj, qk + sk) + w1 * (C)at<D>(e, gc, qi + si, qj + sj, qk + sk);
+            C y2 = w0 * E(false, false, true) + w1 * E(true, false, true);
+            C y3 = w0 * E(false, true, true) + w1 * E(true, true, true);
             v = w0 * v + w1 * (w0 * y2 + w1 * y3);
         }
         size_t p = (size_t)c * gf.cs + row_base(gf, pj, pk) + h;
@@ -766,17 +862,341 @@ __global__ void __launch_bounds__(kBlock) k_prolong_add(const TC* __restrict__ e
     }
 }
 
+// 3-D prolongation marching along the coarse z axis: a thread owns one coarse
+// column (I, J) and a chunk of coarse planes K, keeps the 3 x 3 x 3 coarse
+// neighbourhood of (I, J, K) in registers (each step loads the 3 x 3 values of
+// plane K + 1, with the rule applied where they are ghosts) and corrects the
+// 2 x 2 x 2 fine children of (I, J, K), or the black ones with black_only.  The
+// coarse index runs to ceil(N_f / 2), which is N_c + 1 when N_f = 2 N_c + 1
+// (a ghost parent with one active child).  Per child the arithmetic is that
+// of k_prolong_add.
+constexpr int kProlongChunk = 8;
+
+template <typename C>
+__device__ __forceinline__ AxisNb<C> axis_nb_clamped(int q, int N, const GRule<C>& gr)
+{
+    // q = N + 2 only beside a ghost parent, on the side it has no child: any
+    // in-bounds value serves
+    return axis_nb(q > N + 1 ? N + 1 : q, N, gr);
+}
+
+template <typename TC, typename TF>
+__global__ void __launch_bounds__(kBlock) k_prolong3_zm(const TC* __restrict__ e, SGrid gc, TF* __restrict__ u,
+                                                         SGrid gf, int black_only, GRule<typename Compute<TC>::type> gr,
+                                                         int pblocks)
+{
+    using C = typename Compute<TC>::type;
+    const int Nc = gc.nx - 2, Nf = gf.nx - 2;
+    const int Mq = (Nf + 1) >> 1;  // coarse parents per axis
+    const long lb = xcd_block();
+    const int zc = (int)(lb / pblocks);
+    const long t = (lb - (long)zc * pblocks) * kBlock + threadIdx.x;
+    if (t >= (long)Mq * Mq) return;
+    const int I = 1 + (int)(t % Mq), J = 1 + (int)(t / Mq);
+    const int K0 = 1 + zc * kProlongChunk;
+    const int K1 = min(K0 + kProlongChunk - 1, Mq);
+    AxisNb<C> mx[3], my[3];
+    for (int a = 0; a < 3; a++) {
+        mx[a] = axis_nb_clamped(I - 1 + a, Nc, gr);
+        my[a] = axis_nb_clamped(J - 1 + a, Nc, gr);
+    }
+    // coarse values, index [z][y][x] = plane K-1+z, row J-1+y, column I-1+x
+    C cv[3][3][3];
+    auto load_plane = [&](int kk, C (&pl)[3][3]) {
+        const AxisNb<C> mz = axis_nb_clamped(kk, Nc, gr);
+#pragma unroll
+        for (int y = 0; y < 3; y++)
+#pragma unroll
+            for (int x = 0; x < 3; x++) {
+                C v = (C)at<3>(e, gc, mx[x].q, my[y].q, mz.q);
+                if (mx[x].ghost) v = mx[x].fac * v;
+                if (my[y].ghost) v = my[y].fac * v;
+                if (mz.ghost) v = mz.fac * v;
+                pl[y][x] = v;
+            }
+    };
+    load_plane(K0 - 1, cv[0]);
+    load_plane(K0, cv[1]);
+    const C w0 = (C)0.75, w1 = (C)0.25;
+    for (int K = K0; K <= K1; K++) {
+        load_plane(K + 1, cv[2]);
+#pragma unroll
+        for (int dz = 0; dz < 2; dz++) {
+            const int pk = 2 * K - 1 + dz;
+            if (pk > Nf) continue;
+            const int zs = 1 + (dz ? 1 : -1);
+#pragma unroll
+            for (int dy = 0; dy < 2; dy++) {
+                const int pj = 2 * J - 1 + dy;
+                if (pj > Nf) continue;
+                const int ys = 1 + (dy ? 1 : -1);
+                const size_t row = row_base(gf, pj, pk);
+#pragma unroll
+                for (int dx = 0; dx < 2; dx++) {
+                    const int pi = 2 * I - 1 + dx;
+                    if (pi > Nf) continue;
+                    const int colour = (pi + pj + pk + 3) & 1;
+                    if (black_only && colour == 0) continue;
+                    const int xs = 1 + (dx ? 1 : -1);
+                    C y0 = w0 * cv[1][1][1] + w1 * cv[1][1][xs];
+                    C y1 = w0 * cv[1][ys][1] + w1 * cv[1][ys][xs];
+                    C v = w0 * y0 + w1 * y1;
+                    C y2 = w0 * cv[zs][1][1] + w1 * cv[zs][1][xs];
+                    C y3 = w0 * cv[zs][ys][1] + w1 * cv[zs][ys][xs];
+                    v = w0 * v + w1 * (w0 * y2 + w1 * y3);
+                    const size_t p = (size_t)colour * gf.cs + row + (pi >> 1);
+                    u[p] = (TF)((C)u[p] + v);
+                }
+            }
+        }
+#pragma unroll
+        for (int y = 0; y < 3; y++)
+#pragma unroll
+            for (int x = 0; x < 3; x++) {
+                cv[0][y][x] = cv[1][y][x];
+                cv[1][y][x] = cv[2][y][x];
+            }
+    }
+}
+
+// ------------------------------------------------------------------ coarse tail
+// The smallest multigrid levels of a V-cycle, from a level Lt whose data and
+// that of every coarser level fit in LDS together, down to the one-point level
+// and back, in one workgroup: as separate launches their cost would be launch
+// latency, not work.  Same operations in the same order and arithmetic as the
+// per-level kernels: n_pre sweeps on Lt; per level down, the restriction
+// (correction cleared) and n_pre sweeps; per level up, the prolongation and
+// n_post sweeps.  Each level lives in LDS in natural order (x fastest) on its
+// (N+2)^d box; the ghost slots are never written, the rule supplies their values.
+constexpr int kTailThreads = 1024;
+
+template <typename C>
+struct TailParams {
+    int nlev;                   // levels Lt .. Lt + nlev - 1 (the last has N = 1)
+    int N[kTailMaxLevels];
+    int off[kTailMaxLevels];    // LDS element offset of level a's u; its f follows (N+2)^d later
+    C h2[kTailMaxLevels];       // smoother factor (2^L h)^2
+    C inv_h2[kTailMaxLevels];   // residual factor 1 / (2^L h)^2
+    GRule<C> gr[kTailMaxLevels];
+    int n_pre, n_post;
+};
+
+template <int D>
+__device__ __forceinline__ int box_size(int N)
+{
+    const int Q = N + 2;
+    return D == 3 ? Q * Q * Q : Q * Q;
+}
+
+template <int D>
+__device__ __forceinline__ void tail_point(int t, int N, int& i, int& j, int& k)
+{
+    i = 1 + t % N;
+    const int r = t / N;
+    j = 1 + (D == 3 ? r % N : r);
+    k = D == 3 ? 1 + r / N : 0;
+}
+
+template <int D, typename C>
+__device__ __forceinline__ void tail_sweep(C* U, const C* F, int N, C h2, C inv2d, const GRule<C>& gr, int colour)
+{
+    const int Q = N + 2, total = D == 3 ? N * N * N : N * N;
+    for (int t = threadIdx.x; t < total; t += kTailThreads) {
+        int i, j, k;
+        tail_point<D>(t, N, i, j, k);
+        if (((i + j + k + D) & 1) != colour) continue;
+        const int idx = (k * Q + j) * Q + i;
+        C xm = U[idx - 1], xp = U[idx + 1], ym = U[idx - Q], yp = U[idx + Q], zm = 0, zp = 0;
+        if (D == 3) {
+            zm = U[idx - Q * Q];
+            zp = U[idx + Q * Q];
+        }
+        const C me = U[idx];
+        rule_pair(i, N, me, xm, xp, gr);
+        rule_pair(j, N, me, ym, yp, gr);
+        if (D == 3) rule_pair(k, N, me, zm, zp, gr);
+        C s = xm + xp;
+        s = s + ym;
+        s = s + yp;
+        if (D == 3) {
+            s = s + zm;
+            s = s + zp;
+        }
+        U[idx] = (s - h2 * F[idx]) * inv2d;
+    }
+}
+
+template <int D, typename C>
+__device__ __forceinline__ void tail_restrict(const C* U, const C* F, int Nf, C inv_h2, const GRule<C>& gr, C* Uc,
+                                              C* Fc, int Nc)
+{
+    const int Qf = Nf + 2, Qc = Nc + 2, total = D == 3 ? Nc * Nc * Nc : Nc * Nc;
+    for (int t = threadIdx.x; t < total; t += kTailThreads) {
+        int I, J, K;
+        tail_point<D>(t, Nc, I, J, K);
+        C sum = 0;
+        const int k0 = D == 3 ? 2 * K - 1 : 0, k1 = D == 3 ? 2 * K : 0;
+        for (int k = k0; k <= k1; k++)
+            for (int j = 2 * J - 1; j <= 2 * J; j++)
+                for (int i = 2 * I - 1; i <= 2 * I; i++) {
+                    if (i > Nf || j > Nf || (D == 3 && k > Nf)) continue;
+                    const int idx = (k * Qf + j) * Qf + i;
+                    C xm = U[idx - 1], xp = U[idx + 1], ym = U[idx - Qf], yp = U[idx + Qf], zm = 0, zp = 0;
+                    if (D == 3) {
+                        zm = U[idx - Qf * Qf];
+                        zp = U[idx + Qf * Qf];
+                    }
+                    const C uc = U[idx];
+                    rule_pair(i, Nf, uc, xm, xp, gr);
+                    rule_pair(j, Nf, uc, ym, yp, gr);
+                    if (D == 3) rule_pair(k, Nf, uc, zm, zp, gr);
+                    C s = xm + xp;
+                    s = s + ym;
+                    s = s + yp;
+                    if (D == 3) {
+                        s = s + zm;
+                        s = s + zp;
+                    }
+                    sum += F[idx] - (s - (C)(2 * D) * uc) * inv_h2;
+                }
+        const int pc = (K * Qc + J) * Qc + I;
+        Fc[pc] = sum * ((C)(D == 3 ? 0.125 : 0.25) * (C)1);
+        Uc[pc] = (C)0;
+    }
+}
+
+template <int D, typename C>
+__device__ __forceinline__ void tail_prolong(const C* Ue, int Nc, const GRule<C>& gr, C* U, int Nf)
+{
+    const int Qc = Nc + 2, Qf = Nf + 2, total = D == 3 ? Nf * Nf * Nf : Nf * Nf;
+    const C w0 = (C)0.75, w1 = (C)0.25;
+    const AxisNb<C> none{0, (C)1, false};
+    for (int t = threadIdx.x; t < total; t += kTailThreads) {
+        int i, j, k;
+        tail_point<D>(t, Nf, i, j, k);
+        const int qi = (i + 1) >> 1, si = (i & 1) ? -1 : 1;
+        const int qj = (j + 1) >> 1, sj = (j & 1) ? -1 : 1;
+        const int qk = D == 3 ? (k + 1) >> 1 : 0, sk = (k & 1) ? -1 : 1;
+        const AxisNb<C> pi_ = axis_nb(qi, Nc, gr), ni = axis_nb(qi + si, Nc, gr);
+        const AxisNb<C> pj_ = axis_nb(qj, Nc, gr), nj = axis_nb(qj + sj, Nc, gr);
+        const AxisNb<C> pk_ = D == 3 ? axis_nb(qk, Nc, gr) : none, nk = D == 3 ? axis_nb(qk + sk, Nc, gr) : none;
+        auto E = [&](bool bx, bool by, bool bz) -> C {
+            const AxisNb<C>& ax = bx ? ni : pi_;
+            const AxisNb<C>& ay = by ? nj : pj_;
+            const AxisNb<C>& az = bz ? nk : pk_;
+            C v = Ue[(az.q * Qc + ay.q) * Qc + ax.q];
+            if (ax.ghost) v = ax.fac * v;
+            if (ay.ghost) v = ay.fac * v;
+            if (az.ghost) v = az.fac * v;
+            return v;
+        };
+        C y0 = w0 * E(false, false, false) + w1 * E(true, false, false);
+        C y1 = w0 * E(false, true, false) + w1 * E(true, true, false);
+        C v = w0 * y0 + w1 * y1;
+        if (D == 3) {
+            C y2 = w0 * E(false, false, true) + w1 * E(true, false, true);
+            C y3 = w0 * E(false, true, true) + w1 * E(true, true, true);
+            v = w0 * v + w1 * (w0 * y2 + w1 * y3);
+        }
+        const int idx = (k * Qf + j) * Qf + i;
+        U[idx] = U[idx] + v;
+    }
+}
+
+template <int D, typename C>
+__global__ void __launch_bounds__(kTailThreads) k_coarse_tail(TailParams<C> P, SGrid g0, const C* __restrict__ fg,
+                                                              C* __restrict__ ug)
+{
+    extern __shared__ __align__(16) unsigned char tail_lds[];
+    C* const lds = reinterpret_cast<C*>(tail_lds);
+    const C inv2d = (C)(1.0 / (2.0 * D));
+    auto U = [&](int a) { return lds + P.off[a]; };
+    auto F = [&](int a) { return lds + P.off[a] + box_size<D>(P.N[a]); };
+    auto sweep = [&](int a) {
+        for (int colour = 0; colour < 2; colour++) {
+            tail_sweep<D, C>(U(a), F(a), P.N[a], P.h2[a], inv2d, P.gr[a], colour);
+            __syncthreads();
+        }
+    };
+    {
+        const int N = P.N[0], Q = N + 2, total = D == 3 ? N * N * N : N * N;
+        C* u = U(0);
+        C* f = F(0);
+        for (int t = threadIdx.x; t < total; t += kTailThreads) {
+            int i, j, k;
+            tail_point<D>(t, N, i, j, k);
+            const int idx = (k * Q + j) * Q + i;
+            f[idx] = fg[pos<D, C>(g0, i, j, k)];
+            u[idx] = (C)0;
+        }
+        __syncthreads();
+    }
+    for (int it = 0; it < P.n_pre; it++) sweep(0);
+    int a = 0;
+    while (a + 1 < P.nlev) {
+        tail_restrict<D, C>(U(a), F(a), P.N[a], P.inv_h2[a], P.gr[a], U(a + 1), F(a + 1), P.N[a + 1]);
+        __syncthreads();
+        for (int it = 0; it < P.n_pre; it++) sweep(a + 1);
+        a++;
+    }
+    while (a > 0) {
+        tail_prolong<D, C>(U(a), P.N[a], P.gr[a], U(a - 1), P.N[a - 1]);
+        __syncthreads();
+        for (int it = 0; it < P.n_post; it++) sweep(a - 1);
+        a--;
+    }
+    {
+        const int N = P.N[0], Q = N + 2, total = D == 3 ? N * N * N : N * N;
+        const C* u = U(0);
+        for (int t = threadIdx.x; t < total; t += kTailThreads) {
+            int i, j, k;
+            tail_point<D>(t, N, i, j, k);
+            ug[pos<D, C>(g0, i, j, k)] = u[(k * Q + j) * Q + i];
+        }
+    }
+}
+
 // ------------------------------------------------------------------ defect correction
-// Outer FP64 step of the mixed-precision solve: r64 = f - lap(phi) on the
-// level-0 active points (same arithmetic as the stop-test norm), its max
-// norm, and the scaled low-precision copy r = r64 * rscale; the correction e
-// is cleared where the first relaxation reads it (black only when a red half
-// sweep comes first, both colours otherwise).
-template <int D, typename TL>
-__global__ void __launch_bounds__(kBlock) k_dc_residual(SGrid g, const double* __restrict__ phi,
-                                                        const double* __restrict__ f, double inv_h2, double rscale,
-                                                        TL* __restrict__ r, TL* __restrict__ e, int clear_red,
-                                                        unsigned long long* maxbits)
+// Outer FP64 pass of the mixed-precision solve, fused into one sweep over the
+// level-0 active points:
+//   1. phi_out = phi_in + factor * e_in (only when UPD; e_in is zero on the
+//      ghost layer, so the updated potential there is phi_in's);
+//   2. r64 = f - lap(phi_out), the stop test's residual, and its max norm;
+//   3. r = r64 * rscale in the low precision TL (the next inner right-hand side);
+//   4. the next correction's start e_out: zero, except that with first_red the
+//      first red half sweep from e = 0 is done here (e = -h2 r / 2d on red
+//      points, in the smoother's arithmetic), so the inner cycle starts with black.
+// phi_out and e_out are other buffers than phi_in and e_in: neighbours read the
+// old values while the pass writes the new ones.
+template <typename TL, bool UPD>
+struct DcIn {
+    const double* __restrict__ p;
+    const TL* __restrict__ e;
+    double factor;
+    __device__ __forceinline__ double operator()(size_t i) const
+    {
+        double v = p[i];
+        if (UPD) v = __fma_rn(factor, (double)(float)e[i], v);
+        return v;
+    }
+};
+
+template <typename TL>
+__device__ __forceinline__ void dc_out(size_t self, int colour, double v, double rscale, TL* __restrict__ r,
+                                       TL* __restrict__ eout, int first_red, float h2l, float inv2d)
+{
+    const TL rl = (TL)(float)(v * rscale);
+    r[self] = rl;
+    TL e0 = (TL)0.0f;
+    if (colour == 0 && first_red) e0 = (TL)((0.0f - h2l * (float)rl) * inv2d);
+    eout[self] = e0;
+}
+
+template <int D, typename TL, bool UPD>
+__global__ void __launch_bounds__(kBlock) k_dc_outer(SGrid g, DcIn<TL, UPD> in, double* __restrict__ pout,
+                                                     const double* __restrict__ f, double inv_h2, double rscale,
+                                                     TL* __restrict__ r, TL* __restrict__ eout, int first_red,
+                                                     float h2l, float inv2d, unsigned long long* maxbits)
 {
     int m = g.nx - 2;
     long total = (long)g.hx * m * (D == 3 ? m : 1);
@@ -792,19 +1212,20 @@ __global__ void __launch_bounds__(kBlock) k_dc_residual(SGrid g, const double* _
         for (int c = 0; c < 2; c++) {
             int pi = 2 * h + ((c + pj + pk + D) & 1);
             if (pi < 1 || pi > g.nx - 2) continue;
-            const double* o = phi + (size_t)(c ^ 1) * g.cs;
+            size_t o = (size_t)(c ^ 1) * g.cs + row;
             size_t self = (size_t)c * g.cs + row + h;
-            double s = o[row + ((pi - 1) >> 1)];
-            s = s + o[row + ((pi + 1) >> 1)];
-            s = s + o[row - ny + h];
-            s = s + o[row + ny + h];
+            double s = in(o + ((pi - 1) >> 1));
+            s = s + in(o + ((pi + 1) >> 1));
+            s = s + in(o - ny + h);
+            s = s + in(o + ny + h);
             if (D == 3) {
-                s = s + o[row - nz + h];
-                s = s + o[row + nz + h];
+                s = s + in(o - nz + h);
+                s = s + in(o + nz + h);
             }
-            double v = f[self] - (s - (2.0 * D) * phi[self]) * inv_h2;
-            r[self] = (TL)(float)(v * rscale);
-            if (c == 1 || clear_red) e[self] = (TL)0.0f;
+            const double cen = in(self);
+            if (UPD) pout[self] = cen;
+            double v = f[self] - (s - (2.0 * D) * cen) * inv_h2;
+            dc_out<TL>(self, c, v, rscale, r, eout, first_red, h2l, inv2d);
             unsigned long long b = abs_bits(v);
             best = b > best ? b : best;
         }
@@ -812,13 +1233,15 @@ __global__ void __launch_bounds__(kBlock) k_dc_residual(SGrid g, const double* _
     block_max_to(best, maxbits);
 }
 
-// 3-D form of k_dc_residual marching along z like k_resid_norm3 (both colours
-// of one compact column per thread, z-neighbours from registers).
-template <typename TL>
-__global__ void __launch_bounds__(kBlock) k_dc_residual3(SGrid g, const double* __restrict__ u,
-                                                         const double* __restrict__ f, double inv_h2, double rscale,
-                                                         TL* __restrict__ r, TL* __restrict__ e, int clear_red,
-                                                         int pblocks, unsigned long long* maxbits)
+// 3-D form marching along z like k_resid_norm3: a thread owns both colours of
+// one compact column of a chunk of planes and keeps the updated potential at
+// pk-1, pk, pk+1 in registers.
+template <typename TL, bool UPD>
+__global__ void __launch_bounds__(kBlock) k_dc_outer3(SGrid g, DcIn<TL, UPD> in, double* __restrict__ pout,
+                                                      const double* __restrict__ f, double inv_h2, double rscale,
+                                                      TL* __restrict__ r, TL* __restrict__ eout, int first_red,
+                                                      float h2l, float inv2d, int pblocks,
+                                                      unsigned long long* maxbits)
 {
     const int m = g.nx - 2;
     const long lb = xcd_block();
@@ -832,31 +1255,32 @@ __global__ void __launch_bounds__(kBlock) k_dc_residual3(SGrid g, const double* 
         const int k1 = min(k0 + kNormChunk - 1, m);
         const size_t plane = (size_t)g.nx * g.hx;
         const size_t col = (size_t)pj * g.hx + h;
-        const double* __restrict__ a[2] = {u, u + g.cs};
+        const size_t cs = g.cs;
         double below[2], cur[2];
         for (int c = 0; c < 2; c++) {
-            below[c] = a[c][(size_t)(k0 - 1) * plane + col];
-            cur[c] = a[c][(size_t)k0 * plane + col];
+            below[c] = in(c * cs + (size_t)(k0 - 1) * plane + col);
+            cur[c] = in(c * cs + (size_t)k0 * plane + col);
         }
         for (int pk = k0; pk <= k1; pk++) {
             const size_t here = (size_t)pk * plane + col;
-            double above[2] = {a[0][here + plane], a[1][here + plane]};
+            double above[2] = {in(here + plane), in(cs + here + plane)};
             for (int c = 0; c < 2; c++) {
                 const int o = c ^ 1;
                 const int par = (c + pj + pk + 3) & 1;
                 const int pi = 2 * h + par;
                 if (pi < 1 || pi > g.nx - 2) continue;
-                double xm = par ? cur[o] : a[o][here - 1];
-                double xp = par ? a[o][here + 1] : cur[o];
+                const size_t oh = o * cs + here;
+                double xm = par ? cur[o] : in(oh - 1);
+                double xp = par ? in(oh + 1) : cur[o];
                 double s = xm + xp;
-                s = s + a[o][here - g.hx];
-                s = s + a[o][here + g.hx];
+                s = s + in(oh - g.hx);
+                s = s + in(oh + g.hx);
                 s = s + below[o];
                 s = s + above[o];
-                const size_t self = (size_t)c * g.cs + here;
+                const size_t self = c * cs + here;
+                if (UPD) pout[self] = cur[c];
                 double v = f[self] - (s - 6.0 * cur[c]) * inv_h2;
-                r[self] = (TL)(float)(v * rscale);
-                if (c == 1 || clear_red) e[self] = (TL)0.0f;
+                dc_out<TL>(self, c, v, rscale, r, eout, first_red, h2l, inv2d);
                 unsigned long long b = abs_bits(v);
                 best = b > best ? b : best;
             }
@@ -869,26 +1293,152 @@ __global__ void __launch_bounds__(kBlock) k_dc_residual3(SGrid g, const double* 
     block_max_to(best, maxbits);
 }
 
-// phi += factor * e on the level-0 active points (the FP64 correction update).
-template <int D, typename TL>
-__global__ void __launch_bounds__(kBlock) k_dc_update(SGrid g, double* __restrict__ phi, const TL* __restrict__ e,
-                                                      double factor)
+// Paired form of k_dc_outer3 (row length hx even): a thread owns the compact
+// points h0 = 2 hp and h0 + 1 of both colours and moves each pair of the
+// potential with one 16-byte access and each pair of e, r with one 2- or
+// 4-byte access; the extra x-neighbour (h0 - 1 or h0 + 2) is a single load.
+// Same arithmetic per point as k_dc_outer3.
+template <typename TL, bool UPD>
+__device__ __forceinline__ Pair<double> dc_pair(const DcIn<TL, UPD>& in, size_t i)
 {
-    int m = g.nx - 2;
-    long t = xcd_block() * kBlock + threadIdx.x;
-    long total = (long)g.hx * m * (D == 3 ? m : 1);
-    if (t >= total) return;
-    int h = (int)(t % g.hx);
-    long rr = t / g.hx;
-    int pj = 1 + (int)(rr % m);
-    int pk = D == 3 ? 1 + (int)(rr / m) : 0;
-    size_t row = row_base(g, pj, pk);
-    for (int c = 0; c < 2; c++) {
-        int pi = 2 * h + ((c + pj + pk + D) & 1);
-        if (pi < 1 || pi > g.nx - 2) continue;
-        size_t self = (size_t)c * g.cs + row + h;
-        phi[self] += factor * (double)(float)e[self];
+    Pair<double> v = *(const Pair<double>*)(in.p + i);
+    if (UPD) {
+        const Pair<TL> e = *(const Pair<TL>*)(in.e + i);
+        v.a = __fma_rn(in.factor, (double)(float)e.a, v.a);
+        v.b = __fma_rn(in.factor, (double)(float)e.b, v.b);
     }
+    return v;
+}
+
+template <typename TL, bool UPD>
+__global__ void __launch_bounds__(kBlock) k_dc_outer3_pair(SGrid g, DcIn<TL, UPD> in, double* __restrict__ pout,
+                                                           const double* __restrict__ f, double inv_h2, double rscale,
+                                                           TL* __restrict__ r, TL* __restrict__ eout, int first_red,
+                                                           float h2l, float inv2d, int pblocks,
+                                                           unsigned long long* maxbits)
+{
+    const int m = g.nx - 2;
+    const int hp_n = g.hx >> 1;
+    const long lb = xcd_block();
+    const int zc = (int)(lb / pblocks);
+    const long t = (lb - (long)zc * pblocks) * kBlock + threadIdx.x;
+    unsigned long long best = 0;
+    if (t < (long)hp_n * m) {
+        const int h0 = 2 * (int)(t % hp_n);
+        const int pj = 1 + (int)(t / hp_n);
+        const int k0 = 1 + zc * kNormChunk;
+        const int k1 = min(k0 + kNormChunk - 1, m);
+        const size_t plane = (size_t)g.nx * g.hx;
+        const size_t col = (size_t)pj * g.hx + h0;
+        const size_t cs = g.cs;
+        Pair<double> below[2], cur[2];
+        for (int c = 0; c < 2; c++) {
+            below[c] = dc_pair(in, c * cs + (size_t)(k0 - 1) * plane + col);
+            cur[c] = dc_pair(in, c * cs + (size_t)k0 * plane + col);
+        }
+        for (int pk = k0; pk <= k1; pk++) {
+            const size_t here = (size_t)pk * plane + col;
+            Pair<double> above[2] = {dc_pair(in, here + plane), dc_pair(in, cs + here + plane)};
+            Pair<double> ym[2], yp[2];
+            for (int c = 0; c < 2; c++) {
+                ym[c] = dc_pair(in, c * cs + here - g.hx);
+                yp[c] = dc_pair(in, c * cs + here + g.hx);
+            }
+            for (int c = 0; c < 2; c++) {
+                const int o = c ^ 1;
+                const int par = (c + pj + pk + 3) & 1;
+                const int pi0 = 2 * h0 + par;
+                const bool a0 = pi0 >= 1, a1 = pi0 + 2 <= g.nx - 2;
+                // the extra x-neighbour stays inside the plane (neighbouring row at the row ends)
+                const double ex = in(o * cs + (par ? here + 2 : here - 1));
+                double xm0, xp0, xm1, xp1;
+                if (par) {
+                    xm0 = cur[o].a;
+                    xp0 = cur[o].b;
+                    xm1 = cur[o].b;
+                    xp1 = ex;
+                } else {
+                    xm0 = ex;
+                    xp0 = cur[o].a;
+                    xm1 = cur[o].a;
+                    xp1 = cur[o].b;
+                }
+                double s0 = xm0 + xp0;
+                s0 = s0 + ym[o].a;
+                s0 = s0 + yp[o].a;
+                s0 = s0 + below[o].a;
+                s0 = s0 + above[o].a;
+                double s1 = xm1 + xp1;
+                s1 = s1 + ym[o].b;
+                s1 = s1 + yp[o].b;
+                s1 = s1 + below[o].b;
+                s1 = s1 + above[o].b;
+                const size_t self = c * cs + here;
+                const Pair<double> fv = *(const Pair<double>*)(f + self);
+                const double v0 = fv.a - (s0 - 6.0 * cur[c].a) * inv_h2;
+                const double v1 = fv.b - (s1 - 6.0 * cur[c].b) * inv_h2;
+                Pair<TL> rl, el;
+                rl.a = (TL)(float)(v0 * rscale);
+                rl.b = (TL)(float)(v1 * rscale);
+                el.a = el.b = (TL)0.0f;
+                if (c == 0 && first_red) {
+                    el.a = (TL)((0.0f - h2l * (float)rl.a) * inv2d);
+                    el.b = (TL)((0.0f - h2l * (float)rl.b) * inv2d);
+                }
+                if (a0 && a1) {
+                    if (UPD) *(Pair<double>*)(pout + self) = cur[c];
+                    *(Pair<TL>*)(r + self) = rl;
+                    *(Pair<TL>*)(eout + self) = el;
+                    unsigned long long b0 = abs_bits(v0), b1 = abs_bits(v1);
+                    b0 = b1 > b0 ? b1 : b0;
+                    best = b0 > best ? b0 : best;
+                } else {
+                    if (a0) {
+                        if (UPD) pout[self] = cur[c].a;
+                        r[self] = rl.a;
+                        eout[self] = el.a;
+                        unsigned long long b0 = abs_bits(v0);
+                        best = b0 > best ? b0 : best;
+                    }
+                    if (a1) {
+                        if (UPD) pout[self + 1] = cur[c].b;
+                        r[self + 1] = rl.b;
+                        eout[self + 1] = el.b;
+                        unsigned long long b1 = abs_bits(v1);
+                        best = b1 > best ? b1 : best;
+                    }
+                }
+            }
+            for (int c = 0; c < 2; c++) {
+                below[c] = cur[c];
+                cur[c] = above[c];
+            }
+        }
+    }
+    block_max_to(best, maxbits);
+}
+
+// Copy of the ghost layer (the points outside the active box) of a nested-level
+// array: gives a second potential buffer the same fixed outer values.
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_copy_ghosts(SGrid g, const double* __restrict__ src, double* __restrict__ dst)
+{
+    int Q = g.nx;
+    int t = blockIdx.x * kBlock + threadIdx.x;
+    int per = D == 3 ? Q * Q : Q;
+    if (t >= per) return;
+    int face = blockIdx.y;
+    int axis = face >> 1, side = face & 1;
+    int p[3] = {0, 0, 0};
+    p[axis] = side ? Q - 1 : 0;
+    if (D == 3) {
+        p[(axis + 1) % 3] = t % Q;
+        p[(axis + 2) % 3] = t / Q;
+    } else {
+        p[axis ^ 1] = t;
+    }
+    size_t i = pos<D, double>(g, p[0], p[1], D == 3 ? p[2] : 0);
+    dst[i] = src[i];
 }
 
 }  // namespace
@@ -966,11 +1516,13 @@ void launch_set_u64(hipStream_t st, unsigned long long* p, int count, unsigned l
 }
 
 template <typename T>
-void launch_half_sweep(int dim, hipStream_t st, SGrid g, T* u, const T* f, int colour, double h2, int fine)
+void launch_half_sweep(int dim, hipStream_t st, SGrid g, T* u, const T* f, int colour, double h2, int fine, int xn1,
+                       double coef)
 {
     using C = typename Compute<T>::type;
     dim3 grid(ceil_div(ncompact_active(dim, g), kBlock));
     C inv2d = (C)(1.0 / (2.0 * dim));
+    const GRule<C> gr{xn1, (C)coef};
     if (dim == 3 && fine && sizeof(T) <= 4 && (g.hx % 2) == 0) {
         // 2- and 4-byte storage: two compact points per thread, paired loads
         long m = g.nx - 2;
@@ -988,106 +1540,178 @@ void launch_half_sweep(int dim, hipStream_t st, SGrid g, T* u, const T* f, int c
         int chunks = ceil_div(m, kZChunk);
         if (fine)
             hipLaunchKernelGGL((k_smooth_zmarch3<T, 0>), dim3(pblocks * chunks), dim3(kBlock), 0, st, u, f, g, colour,
-                               (C)h2, inv2d, pblocks);
+                               (C)h2, inv2d, pblocks, gr);
         else
             hipLaunchKernelGGL((k_smooth_zmarch3<T, 1>), dim3(pblocks * chunks), dim3(kBlock), 0, st, u, f, g, colour,
-                               (C)h2, inv2d, pblocks);
+                               (C)h2, inv2d, pblocks, gr);
         return;
     }
     if (fine) {
         hipLaunchKernelGGL((k_smooth_fine<2, T>), grid, dim3(kBlock), 0, st, u, f, g, colour, (C)h2, inv2d);
     } else {
         if (dim == 3)
-            hipLaunchKernelGGL((k_half_sweep<3, T>), grid, dim3(kBlock), 0, st, u, f, g, colour, (C)h2, inv2d);
+            hipLaunchKernelGGL((k_half_sweep<3, T>), grid, dim3(kBlock), 0, st, u, f, g, colour, (C)h2, inv2d, gr);
         else
-            hipLaunchKernelGGL((k_half_sweep<2, T>), grid, dim3(kBlock), 0, st, u, f, g, colour, (C)h2, inv2d);
+            hipLaunchKernelGGL((k_half_sweep<2, T>), grid, dim3(kBlock), 0, st, u, f, g, colour, (C)h2, inv2d, gr);
     }
-}
-
-template <typename T>
-void launch_ghost_fill(int dim, hipStream_t st, SGrid g, T* u, int xn_is_one, double coef)
-{
-    using C = typename Compute<T>::type;
-    int per = dim == 3 ? g.nx * g.nx : g.nx;
-    dim3 grid(ceil_div(per, kBlock), 2 * dim);
-    if (dim == 3)
-        hipLaunchKernelGGL((k_ghost_fill<3, T>), grid, dim3(kBlock), 0, st, u, g, xn_is_one, (C)coef);
-    else
-        hipLaunchKernelGGL((k_ghost_fill<2, T>), grid, dim3(kBlock), 0, st, u, g, xn_is_one, (C)coef);
 }
 
 template <typename TF, typename TC>
 void launch_resid_restrict(int dim, hipStream_t st, SGrid gf, const TF* u, const TF* f, double inv_h2, double out_scale,
-                           SGrid gc, TC* fc, TC* ec)
+                           SGrid gc, TC* fc, TC* ec, int rule, int xn1, double coef)
 {
     using C = typename Compute<TC>::type;
     long Nc = gc.nx - 2;
     long total = dim == 3 ? Nc * Nc * Nc : Nc * Nc;
     dim3 grid(ceil_div(total, kBlock));
-    if (dim == 3)
-        hipLaunchKernelGGL((k_resid_restrict<3, TF, TC>), grid, dim3(kBlock), 0, st, u, f, gf, (C)inv_h2, (C)out_scale,
-                           gc, fc, ec);
-    else
-        hipLaunchKernelGGL((k_resid_restrict<2, TF, TC>), grid, dim3(kBlock), 0, st, u, f, gf, (C)inv_h2, (C)out_scale,
-                           gc, fc, ec);
+    const GRule<C> gr{xn1, (C)coef};
+    if (dim == 3) {
+        if (rule)
+            hipLaunchKernelGGL((k_resid_restrict<3, TF, TC, true>), grid, dim3(kBlock), 0, st, u, f, gf, (C)inv_h2,
+                               (C)out_scale, gc, fc, ec, gr);
+        else
+            hipLaunchKernelGGL((k_resid_restrict<3, TF, TC, false>), grid, dim3(kBlock), 0, st, u, f, gf, (C)inv_h2,
+                               (C)out_scale, gc, fc, ec, gr);
+    } else {
+        if (rule)
+            hipLaunchKernelGGL((k_resid_restrict<2, TF, TC, true>), grid, dim3(kBlock), 0, st, u, f, gf, (C)inv_h2,
+                               (C)out_scale, gc, fc, ec, gr);
+        else
+            hipLaunchKernelGGL((k_resid_restrict<2, TF, TC, false>), grid, dim3(kBlock), 0, st, u, f, gf, (C)inv_h2,
+                               (C)out_scale, gc, fc, ec, gr);
+    }
 }
 
 template <typename TC, typename TF>
-void launch_prolong_add(int dim, hipStream_t st, SGrid gc, const TC* ec, SGrid gf, TF* u, int black_only)
+void launch_prolong_add(int dim, hipStream_t st, SGrid gc, const TC* ec, SGrid gf, TF* u, int black_only, int xn1,
+                        double coef)
 {
+    using C = typename Compute<TC>::type;
+    const GRule<C> gr{xn1, (C)coef};
     dim3 grid(ceil_div(ncompact_active(dim, gf), kBlock));
+    if (dim == 3) {
+        const long Mq = (gf.nx - 1) / 2;  // ceil(N_f / 2) coarse parents per axis
+        const int pblocks = ceil_div(Mq * Mq, kBlock);
+        const int chunks = ceil_div(Mq, kProlongChunk);
+        hipLaunchKernelGGL((k_prolong3_zm<TC, TF>), dim3(pblocks * chunks), dim3(kBlock), 0, st, ec, gc, u, gf,
+                           black_only, gr, pblocks);
+    } else
+        hipLaunchKernelGGL((k_prolong_add<2, TC, TF>), grid, dim3(kBlock), 0, st, ec, gc, u, gf, black_only, gr);
+}
+
+size_t coarse_tail_lds_bytes(int dim, const int* N, int nlev, size_t esz)
+{
+    size_t e = 0;
+    for (int a = 0; a < nlev; a++) {
+        size_t Q = (size_t)N[a] + 2;
+        e += 2 * (dim == 3 ? Q * Q * Q : Q * Q);
+    }
+    return e * esz;
+}
+
+template <typename T>
+int launch_coarse_tail(int dim, hipStream_t st, int nlev, const int* N, const double* h, const int* xn1,
+                       const double* coef, int n_pre, int n_post, SGrid g0, const T* f0, T* u0)
+{
+    if (nlev < 1 || nlev > kTailMaxLevels || N[nlev - 1] != 1) return -1;
+    const size_t bytes = coarse_tail_lds_bytes(dim, N, nlev, sizeof(T));
+    if (bytes > kTailLdsBytes) return -1;
+    TailParams<T> P{};
+    P.nlev = nlev;
+    P.n_pre = n_pre;
+    P.n_post = n_post;
+    int off = 0;
+    for (int a = 0; a < nlev; a++) {
+        P.N[a] = N[a];
+        P.off[a] = off;
+        const int Q = N[a] + 2;
+        off += 2 * (dim == 3 ? Q * Q * Q : Q * Q);
+        P.h2[a] = (T)(h[a] * h[a]);
+        P.inv_h2[a] = (T)(1.0 / (h[a] * h[a]));
+        P.gr[a] = GRule<T>{xn1[a], (T)coef[a]};
+    }
     if (dim == 3)
-        hipLaunchKernelGGL((k_prolong_add<3, TC, TF>), grid, dim3(kBlock), 0, st, ec, gc, u, gf, black_only);
+        hipLaunchKernelGGL((k_coarse_tail<3, T>), dim3(1), dim3(kTailThreads), bytes, st, P, g0, f0, u0);
     else
-        hipLaunchKernelGGL((k_prolong_add<2, TC, TF>), grid, dim3(kBlock), 0, st, ec, gc, u, gf, black_only);
+        hipLaunchKernelGGL((k_coarse_tail<2, T>), dim3(1), dim3(kTailThreads), bytes, st, P, g0, f0, u0);
+    return 0;
 }
 
 template <typename TL>
-void launch_dc_residual(int dim, hipStream_t st, SGrid g, const double* phi, const double* f, double inv_h2,
-                        double rscale, TL* r, TL* e, int clear_red, unsigned long long* maxbits)
+void launch_dc_outer(int dim, hipStream_t st, SGrid g, const double* phi_in, const TL* e_in, double factor,
+                     double* phi_out, const double* f, double inv_h2, double rscale, TL* r, TL* e_out, int first_red,
+                     unsigned long long* maxbits)
 {
-    int blocks = ceil_div(ncompact_active(dim, g), kBlock);
-    if (blocks > 4096) blocks = 4096;
+    const float h2l = 1.0f, inv2d = (float)(1.0 / (2.0 * dim));
+    const bool upd = e_in != nullptr;
+    if (dim == 3 && g.hx % 2 == 0 && g.cs % 2 == 0) {
+        long m = g.nx - 2;
+        int pblocks = ceil_div((long)(g.hx / 2) * m, kBlock);
+        dim3 grid(pblocks * ceil_div(m, kNormChunk));
+        if (upd)
+            hipLaunchKernelGGL((k_dc_outer3_pair<TL, true>), grid, dim3(kBlock), 0, st, g,
+                               DcIn<TL, true>{phi_in, e_in, factor}, phi_out, f, inv_h2, rscale, r, e_out, first_red,
+                               h2l, inv2d, pblocks, maxbits);
+        else
+            hipLaunchKernelGGL((k_dc_outer3_pair<TL, false>), grid, dim3(kBlock), 0, st, g,
+                               DcIn<TL, false>{phi_in, nullptr, 0.0}, phi_out, f, inv_h2, rscale, r, e_out, first_red,
+                               h2l, inv2d, pblocks, maxbits);
+        return;
+    }
     if (dim == 3) {
         long m = g.nx - 2;
         int pblocks = ceil_div((long)g.hx * m, kBlock);
-        int chunks = ceil_div(m, kNormChunk);
-        hipLaunchKernelGGL((k_dc_residual3<TL>), dim3(pblocks * chunks), dim3(kBlock), 0, st, g, phi, f, inv_h2,
-                           rscale, r, e, clear_red, pblocks, maxbits);
-    } else
-        hipLaunchKernelGGL((k_dc_residual<2, TL>), dim3(blocks), dim3(kBlock), 0, st, g, phi, f, inv_h2, rscale, r, e,
-                           clear_red, maxbits);
-}
-
-template <typename TL>
-void launch_dc_update(int dim, hipStream_t st, SGrid g, double* phi, const TL* e, double factor)
-{
-    dim3 grid(ceil_div(ncompact_active(dim, g), kBlock));
-    if (dim == 3)
-        hipLaunchKernelGGL((k_dc_update<3, TL>), grid, dim3(kBlock), 0, st, g, phi, e, factor);
+        dim3 grid(pblocks * ceil_div(m, kNormChunk));
+        if (upd)
+            hipLaunchKernelGGL((k_dc_outer3<TL, true>), grid, dim3(kBlock), 0, st, g, DcIn<TL, true>{phi_in, e_in, factor},
+                               phi_out, f, inv_h2, rscale, r, e_out, first_red, h2l, inv2d, pblocks, maxbits);
+        else
+            hipLaunchKernelGGL((k_dc_outer3<TL, false>), grid, dim3(kBlock), 0, st, g,
+                               DcIn<TL, false>{phi_in, nullptr, 0.0}, phi_out, f, inv_h2, rscale, r, e_out, first_red,
+                               h2l, inv2d, pblocks, maxbits);
+        return;
+    }
+    int blocks = ceil_div(ncompact_active(dim, g), kBlock);
+    if (blocks > 4096) blocks = 4096;
+    if (upd)
+        hipLaunchKernelGGL((k_dc_outer<2, TL, true>), dim3(blocks), dim3(kBlock), 0, st, g,
+                           DcIn<TL, true>{phi_in, e_in, factor}, phi_out, f, inv_h2, rscale, r, e_out, first_red, h2l,
+                           inv2d, maxbits);
     else
-        hipLaunchKernelGGL((k_dc_update<2, TL>), grid, dim3(kBlock), 0, st, g, phi, e, factor);
+        hipLaunchKernelGGL((k_dc_outer<2, TL, false>), dim3(blocks), dim3(kBlock), 0, st, g,
+                           DcIn<TL, false>{phi_in, nullptr, 0.0}, phi_out, f, inv_h2, rscale, r, e_out, first_red, h2l,
+                           inv2d, maxbits);
 }
 
-template void launch_half_sweep<double>(int, hipStream_t, SGrid, double*, const double*, int, double, int);
-template void launch_half_sweep<float>(int, hipStream_t, SGrid, float*, const float*, int, double, int);
-template void launch_half_sweep<__half>(int, hipStream_t, SGrid, __half*, const __half*, int, double, int);
-template void launch_ghost_fill<double>(int, hipStream_t, SGrid, double*, int, double);
-template void launch_ghost_fill<float>(int, hipStream_t, SGrid, float*, int, double);
+void launch_copy_ghosts(int dim, hipStream_t st, SGrid g, const double* src, double* dst)
+{
+    int per = dim == 3 ? g.nx * g.nx : g.nx;
+    dim3 grid(ceil_div(per, kBlock), 2 * dim);
+    if (dim == 3)
+        hipLaunchKernelGGL((k_copy_ghosts<3>), grid, dim3(kBlock), 0, st, g, src, dst);
+    else
+        hipLaunchKernelGGL((k_copy_ghosts<2>), grid, dim3(kBlock), 0, st, g, src, dst);
+}
+
+template void launch_half_sweep<double>(int, hipStream_t, SGrid, double*, const double*, int, double, int, int, double);
+template void launch_half_sweep<float>(int, hipStream_t, SGrid, float*, const float*, int, double, int, int, double);
+template void launch_half_sweep<__half>(int, hipStream_t, SGrid, __half*, const __half*, int, double, int, int, double);
 template void launch_resid_restrict<double, double>(int, hipStream_t, SGrid, const double*, const double*, double,
-                                                    double, SGrid, double*, double*);
+                                                    double, SGrid, double*, double*, int, int, double);
 template void launch_resid_restrict<float, float>(int, hipStream_t, SGrid, const float*, const float*, double, double,
-                                                  SGrid, float*, float*);
+                                                  SGrid, float*, float*, int, int, double);
 template void launch_resid_restrict<__half, float>(int, hipStream_t, SGrid, const __half*, const __half*, double,
-                                                   double, SGrid, float*, float*);
-template void launch_prolong_add<double, double>(int, hipStream_t, SGrid, const double*, SGrid, double*, int);
-template void launch_prolong_add<float, float>(int, hipStream_t, SGrid, const float*, SGrid, float*, int);
-template void launch_prolong_add<float, __half>(int, hipStream_t, SGrid, const float*, SGrid, __half*, int);
-template void launch_dc_residual<float>(int, hipStream_t, SGrid, const double*, const double*, double, double, float*,
-                                        float*, int, unsigned long long*);
-template void launch_dc_residual<__half>(int, hipStream_t, SGrid, const double*, const double*, double, double,
-                                         __half*, __half*, int, unsigned long long*);
-template void launch_dc_update<float>(int, hipStream_t, SGrid, double*, const float*, double);
-template void launch_dc_update<__half>(int, hipStream_t, SGrid, double*, const __half*, double);
+                                                   double, SGrid, float*, float*, int, int, double);
+template void launch_prolong_add<double, double>(int, hipStream_t, SGrid, const double*, SGrid, double*, int, int, double);
+template void launch_prolong_add<float, float>(int, hipStream_t, SGrid, const float*, SGrid, float*, int, int, double);
+template void launch_prolong_add<float, __half>(int, hipStream_t, SGrid, const float*, SGrid, __half*, int, int, double);
+template int launch_coarse_tail<float>(int, hipStream_t, int, const int*, const double*, const int*, const double*,
+                                       int, int, SGrid, const float*, float*);
+template int launch_coarse_tail<double>(int, hipStream_t, int, const int*, const double*, const int*, const double*,
+                                        int, int, SGrid, const double*, double*);
+template void launch_dc_outer<float>(int, hipStream_t, SGrid, const double*, const float*, double, double*,
+                                     const double*, double, double, float*, float*, int, unsigned long long*);
+template void launch_dc_outer<__half>(int, hipStream_t, SGrid, const double*, const __half*, double, double*,
+                                      const double*, double, double, __half*, __half*, int, unsigned long long*);
 
 }  // namespace np

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <utility>
 #include <vector>
 
 #include "../../include/nested_poisson.h"
@@ -154,9 +155,16 @@ struct np_solver {
     hipGraphExec_t coarse_exec[NP_MAX_LEVELS] = {};
     // mixed-precision defect correction: level-0 correction and defect in
     // FP32 or FP16 (colour-split, sized for the largest level), FP32 coarse levels
+    // e_lo is the correction the inner cycles work on, e_nx the one the next
+    // outer pass starts; phi_alt is the second FP64 potential buffer the outer
+    // pass writes the updated potential into (the pointers rotate)
     void* e_lo = nullptr;
+    void* e_nx = nullptr;
     void* r_lo = nullptr;
     size_t lo_bytes = 0;
+    double* phi_alt = nullptr;
+    size_t alt_cap = 0;
+    size_t phi_cap[NP_MAX_LEVELS] = {};
     float* mg_u32[NP_MAX_MG] = {};
     float* mg_f32[NP_MAX_MG] = {};
     hipGraphExec_t coarse_exec32[NP_MAX_LEVELS] = {};
@@ -262,44 +270,80 @@ MGView<T> mg_view(const np_solver* s, int l, T* const* mu, T* const* mf)
     return v;
 }
 
-// One red-black sweep on multigrid level L >= 1: ghost layer refreshed from the
-// interior before each half sweep (Sec. 2.4, last paragraph).
+// One red-black sweep on multigrid level L >= 1.  The ghost layer is the
+// level's rule (Sec. 2.4), evaluated by the kernels where they read it; that is
+// the same as refreshing it before each half sweep.
 template <typename T>
 void coarse_sweep(const np_solver* s, int l, const MGView<T>& v, int L, hipStream_t st)
 {
     const int d = s->cfg.dim;
-    for (int colour = 0; colour < 2; colour++) {
-        launch_ghost_fill<T>(d, st, v.g[L], v.u[L], s->plan.xn_is_one[l][L], s->plan.ghost_coef[l][L]);
-        launch_half_sweep<T>(d, st, v.g[L], v.u[L], v.f[L], colour, v.h[L] * v.h[L], 0);
+    for (int colour = 0; colour < 2; colour++)
+        launch_half_sweep<T>(d, st, v.g[L], v.u[L], v.f[L], colour, v.h[L] * v.h[L], 0, s->plan.xn_is_one[l][L],
+                             s->plan.ghost_coef[l][L]);
+}
+
+// First multigrid level of the coarse tail of nested level l (the levels from
+// there to the one-point level fit in LDS together, elements of esz bytes),
+// or 0 if none does.
+int tail_level(const np_solver* s, int l, size_t esz)
+{
+    const int nmg = s->plan.nmg[l];
+    for (int L = 1; L < nmg; L++) {
+        const int nlev = nmg - L;
+        if (nlev <= kTailMaxLevels &&
+            coarse_tail_lds_bytes(s->cfg.dim, &s->plan.N[l][L], nlev, esz) <= kTailLdsBytes)
+            return L;
     }
+    return 0;
 }
 
 // Everything a V-cycle does on levels L >= 1 (Sec. 2.3 steps 6-13 below the
 // finest multigrid level): from the pre-smoothing of level 1 down to the
-// coarsest level and back up to the ghost refresh of level 1 that precedes the
-// prolongation into level 0.  The sequence is the same in every cycle of a
-// nested level, so it is captured once into a HIP graph.
+// coarsest level and back up to the post-smoothing of level 1, which precedes
+// the prolongation into level 0; the levels from the tail level down run as one
+// kernel.  The sequence is the same in every cycle of a nested level, so it is
+// captured once into a HIP graph.
 template <typename T>
 void coarse_part(const np_solver* s, int l, const MGView<T>& v, hipStream_t st)
 {
     const np_config& c = s->cfg;
     const int d = c.dim;
+    const int Lt = tail_level(s, l, sizeof(T));
+    auto tail = [&](int L0) {
+        const int nlev = s->plan.nmg[l] - L0;
+        int N[kTailMaxLevels], xn[kTailMaxLevels];
+        double h[kTailMaxLevels], coef[kTailMaxLevels];
+        for (int a = 0; a < nlev; a++) {
+            N[a] = s->plan.N[l][L0 + a];
+            xn[a] = s->plan.xn_is_one[l][L0 + a];
+            coef[a] = s->plan.ghost_coef[l][L0 + a];
+            h[a] = v.h[L0 + a];
+        }
+        launch_coarse_tail<T>(d, st, nlev, N, h, xn, coef, c.n_pre, c.n_post, v.g[L0], v.f[L0], v.u[L0]);
+    };
+    if (Lt == 1) {
+        tail(1);
+        return;
+    }
     for (int it = 0; it < c.n_pre; it++) coarse_sweep(s, l, v, 1, st);
     int L = 1;
     while (s->plan.N[l][L] > 1) {
-        launch_ghost_fill<T>(d, st, v.g[L], v.u[L], s->plan.xn_is_one[l][L], s->plan.ghost_coef[l][L]);
         launch_resid_restrict<T, T>(d, st, v.g[L], v.u[L], v.f[L], 1.0 / (v.h[L] * v.h[L]), 1.0, v.g[L + 1], v.f[L + 1],
-                                    v.u[L + 1]);
+                                    v.u[L + 1], 1, s->plan.xn_is_one[l][L], s->plan.ghost_coef[l][L]);
+        if (L + 1 == Lt) {
+            tail(Lt);
+            L = Lt;
+            break;
+        }
         for (int it = 0; it < c.n_pre; it++) coarse_sweep(s, l, v, L + 1, st);
         L++;
     }
     while (L > 1) {
-        launch_ghost_fill<T>(d, st, v.g[L], v.u[L], s->plan.xn_is_one[l][L], s->plan.ghost_coef[l][L]);
-        launch_prolong_add<T, T>(d, st, v.g[L], v.u[L], v.g[L - 1], v.u[L - 1], 0);
+        launch_prolong_add<T, T>(d, st, v.g[L], v.u[L], v.g[L - 1], v.u[L - 1], 0, s->plan.xn_is_one[l][L],
+                                 s->plan.ghost_coef[l][L]);
         for (int it = 0; it < c.n_post; it++) coarse_sweep(s, l, v, L - 1, st);
         L--;
     }
-    launch_ghost_fill<T>(d, st, v.g[1], v.u[1], s->plan.xn_is_one[l][1], s->plan.ghost_coef[l][1]);
 }
 
 template <typename T>
@@ -330,23 +374,26 @@ int run_coarse(np_solver* s, int l, const MGView<T>& v, hipGraphExec_t* exec)
 // (u0, f0) of type T0 with half-sweep factor h2_0 and residual factor
 // inv_h2_0; the restricted right-hand side is multiplied by out_scale_0; the
 // coarse levels are of type TC.
+// With red_done the first red half sweep has already been done (by the
+// defect-correction outer pass) and the cycle starts with black.
 template <typename T0, typename TC>
 int vcycle_t(np_solver* s, int l, T0* u0, const T0* f0, double h2_0, double inv_h2_0, double out_scale_0,
-             const MGView<TC>& v, hipGraphExec_t* exec)
+             const MGView<TC>& v, hipGraphExec_t* exec, bool red_done = false)
 {
     const np_config& c = s->cfg;
     const int d = c.dim;
     hipStream_t st = s->stream;
     auto sweep0 = [&]() {
-        for (int colour = 0; colour < 2; colour++) {
+        for (int colour = red_done ? 1 : 0; colour < 2; colour++) {
+            red_done = false;
             prof_begin(s, NP_KCLASS_SMOOTH);
-            launch_half_sweep<T0>(d, st, v.g[0], u0, f0, colour, h2_0, 1);
+            launch_half_sweep<T0>(d, st, v.g[0], u0, f0, colour, h2_0, 1, 0, 0.0);
             prof_end(s);
         }
     };
     for (int it = 0; it < c.n_pre; it++) sweep0();
     prof_begin(s, NP_KCLASS_RESTRICT);
-    launch_resid_restrict<T0, TC>(d, st, v.g[0], u0, f0, inv_h2_0, out_scale_0, v.g[1], v.f[1], v.u[1]);
+    launch_resid_restrict<T0, TC>(d, st, v.g[0], u0, f0, inv_h2_0, out_scale_0, v.g[1], v.f[1], v.u[1], 0, 0, 0.0);
     prof_end(s);
     prof_begin(s, NP_KCLASS_COARSE);
     int rc = run_coarse(s, l, v, exec);
@@ -355,7 +402,8 @@ int vcycle_t(np_solver* s, int l, T0* u0, const T0* f0, double h2_0, double inv_
     prof_begin(s, NP_KCLASS_PROLONG);
     // on level 0 (fixed ghost layer) the red corrections are dead when a
     // post-smoothing red half sweep follows: it reads only black points
-    launch_prolong_add<TC, T0>(d, st, v.g[1], v.u[1], v.g[0], u0, c.n_post > 0);
+    launch_prolong_add<TC, T0>(d, st, v.g[1], v.u[1], v.g[0], u0, c.n_post > 0, s->plan.xn_is_one[l][1],
+                               s->plan.ghost_coef[l][1]);
     prof_end(s);
     for (int it = 0; it < c.n_post; it++) sweep0();
     return NP_OK;
@@ -374,11 +422,12 @@ int vcycle(np_solver* s, int l)
 // precision TL, with FP32 coarse levels: the coarse right-hand side is
 // R(r'' - L e'') / h^2, in the same units as e''.
 template <typename TL>
-int vcycle_lo(np_solver* s, int l)
+int vcycle_lo(np_solver* s, int l, bool red_done)
 {
     MGView<float> v = mg_view<float>(s, l, s->mg_u32, s->mg_f32);
     double h = v.h[0];
-    return vcycle_t<TL, float>(s, l, (TL*)s->e_lo, (const TL*)s->r_lo, 1.0, 1.0, 1.0 / (h * h), v, s->coarse_exec32);
+    return vcycle_t<TL, float>(s, l, (TL*)s->e_lo, (const TL*)s->r_lo, 1.0, 1.0, 1.0 / (h * h), v, s->coarse_exec32,
+                               red_done);
 }
 
 // Queue a norm into slot `slot` and return it (host-synchronous).
@@ -408,47 +457,65 @@ int force_delta_sync(np_solver* s, int l, double* out)
     return NP_OK;
 }
 
-// Defect-correction residual of level l: r'' = (f - lap phi) * rscale into the
-// low-precision defect, correction cleared; returns ||f - lap phi||_inf.
-int dc_residual_sync(np_solver* s, int l, double rscale, double* out)
+// Outer pass of the defect correction on level l (host-synchronous): with
+// update, phi += factor * e'' into the other potential buffer and the buffers
+// rotate; then r'' = (f - lap phi) * rscale into the low-precision defect and
+// the next correction's start (its first red half sweep when n_pre > 0).
+// Returns ||f - lap phi||_inf of the (updated) potential.
+int dc_outer_sync(np_solver* s, int l, bool update, double factor, double rscale, double* out)
 {
     const np_config& c = s->cfg;
     double dx = std::ldexp(c.dx0, -l);
-    int clear_red = c.n_pre == 0;
+    int first_red = c.n_pre > 0;
+    void* e_in = update ? s->e_lo : nullptr;
+    void* e_out = update ? s->e_nx : s->e_lo;
+    double* p_out = update ? s->phi_alt : nullptr;
     launch_set_u64(s->stream, s->d_bits, 1, 0ULL);
     prof_begin(s, NP_KCLASS_DC);
     if (c.precision == NP_PREC_FP16S_DC)
-        launch_dc_residual<__half>(c.dim, s->stream, s->lg[l], s->phi[l], s->f[l], 1.0 / (dx * dx), rscale,
-                                   (__half*)s->r_lo, (__half*)s->e_lo, clear_red, s->d_bits);
+        launch_dc_outer<__half>(c.dim, s->stream, s->lg[l], s->phi[l], (const __half*)e_in, factor, p_out, s->f[l],
+                                1.0 / (dx * dx), rscale, (__half*)s->r_lo, (__half*)e_out, first_red, s->d_bits);
     else
-        launch_dc_residual<float>(c.dim, s->stream, s->lg[l], s->phi[l], s->f[l], 1.0 / (dx * dx), rscale,
-                                  (float*)s->r_lo, (float*)s->e_lo, clear_red, s->d_bits);
+        launch_dc_outer<float>(c.dim, s->stream, s->lg[l], s->phi[l], (const float*)e_in, factor, p_out, s->f[l],
+                               1.0 / (dx * dx), rscale, (float*)s->r_lo, (float*)e_out, first_red, s->d_bits);
     prof_end(s);
     HIPCHK(s, hipGetLastError());
+    if (update) {
+        std::swap(s->e_lo, s->e_nx);
+        std::swap(s->phi[l], s->phi_alt);
+        std::swap(s->phi_cap[l], s->alt_cap);
+    }
     HIPCHK(s, hipMemcpyAsync(s->h_bits, s->d_bits, sizeof(unsigned long long), hipMemcpyDeviceToHost, s->stream));
     HIPCHK(s, hipStreamSynchronize(s->stream));
     *out = bits_to_double(s->h_bits[0]);
     return NP_OK;
 }
 
-// One defect-correction step (extension of Sec. 2.3 with FP32 or FP16-stored
-// inner cycles): inner_cycles low-precision V-cycles on the scaled defect
-// r'' = r / r_scale, then phi += h^2 r_scale e'' in FP64.
-int dc_step(np_solver* s, int l, double r_scale)
+// Inner cycles of one defect-correction step (extension of Sec. 2.3 with FP32
+// or FP16-stored inner cycles): inner_cycles low-precision V-cycles on the
+// scaled defect r'' = r / r_scale, the first one starting from the state the
+// outer pass left (e'' = 0, red points relaxed when n_pre > 0).
+int dc_inner(np_solver* s, int l)
 {
     const np_config& c = s->cfg;
     for (int it = 0; it < c.inner_cycles; it++) {
-        int rc = c.precision == NP_PREC_FP16S_DC ? vcycle_lo<__half>(s, l) : vcycle_lo<float>(s, l);
+        const bool red_done = it == 0 && c.n_pre > 0;
+        int rc = c.precision == NP_PREC_FP16S_DC ? vcycle_lo<__half>(s, l, red_done) : vcycle_lo<float>(s, l, red_done);
         if (rc) return rc;
     }
-    double dx = std::ldexp(c.dx0, -l);
-    prof_begin(s, NP_KCLASS_DC);
-    if (c.precision == NP_PREC_FP16S_DC)
-        launch_dc_update<__half>(c.dim, s->stream, s->lg[l], s->phi[l], (const __half*)s->e_lo, dx * dx * r_scale);
-    else
-        launch_dc_update<float>(c.dim, s->stream, s->lg[l], s->phi[l], (const float*)s->e_lo, dx * dx * r_scale);
-    prof_end(s);
-    HIPCHK(s, hipGetLastError());
+    return NP_OK;
+}
+
+// End of a level's defect correction: the level's potential must live in a
+// buffer of the level's own capacity unless every buffer is as large as the
+// spare one; otherwise copy it back into the level's own buffer.
+int dc_settle(np_solver* s, int l)
+{
+    if (s->alt_cap >= s->phi_cap[l]) return NP_OK;
+    size_t bytes = 2 * s->lg[l].cs * sizeof(double);
+    HIPCHK(s, hipMemcpyAsync(s->phi_alt, s->phi[l], bytes, hipMemcpyDeviceToDevice, s->stream));
+    std::swap(s->phi[l], s->phi_alt);
+    std::swap(s->phi_cap[l], s->alt_cap);
     return NP_OK;
 }
 
@@ -519,8 +586,11 @@ void free_all(np_solver* s)
         s->coarse_exec32[l] = nullptr;
     }
     if (s->e_lo) (void)hipFree(s->e_lo);
+    if (s->e_nx) (void)hipFree(s->e_nx);
     if (s->r_lo) (void)hipFree(s->r_lo);
-    s->e_lo = s->r_lo = nullptr;
+    if (s->phi_alt) (void)hipFree(s->phi_alt);
+    s->e_lo = s->e_nx = s->r_lo = nullptr;
+    s->phi_alt = nullptr;
     for (int k = 0; k < 3; k++) {
         if (s->net_w[k]) (void)hipFree(s->net_w[k]);
         if (s->net_b[k]) (void)hipFree(s->net_b[k]);
@@ -615,6 +685,7 @@ int nested_poisson_create(const np_config* cfg, void* hip_stream, np_solver** ou
         size_t bytes = 2 * s->lg[l].cs * sizeof(double);
         rc = alloc_dev(s, (void**)&s->phi[l], bytes);
         if (rc == NP_OK) rc = alloc_dev(s, (void**)&s->f[l], bytes);
+        s->phi_cap[l] = bytes;
         if (cfg->n[l] > maxn) maxn = cfg->n[l];
     }
     // multigrid scratch: per level L the largest grid over the nested levels,
@@ -643,7 +714,10 @@ int nested_poisson_create(const np_config* cfg, void* hip_stream, np_solver** ou
         size_t esz = cfg->precision == NP_PREC_FP16S_DC ? sizeof(__half) : sizeof(float);
         s->lo_bytes = best * esz;
         rc = alloc_dev(s, &s->e_lo, s->lo_bytes);
+        if (rc == NP_OK) rc = alloc_dev(s, &s->e_nx, s->lo_bytes);
         if (rc == NP_OK) rc = alloc_dev(s, &s->r_lo, s->lo_bytes);
+        s->alt_cap = best * sizeof(double);
+        if (rc == NP_OK) rc = alloc_dev(s, (void**)&s->phi_alt, s->alt_cap);
     }
     if (rc == NP_OK && cfg->guess == NP_GUESS_LEARNED) {
         size_t vox = 0;
@@ -770,6 +844,10 @@ int nested_poisson_solve(np_solver* s, const double* const* rho, const double* p
             // whole array once per level (it is shared by levels of other sizes)
             size_t esz = c.precision == NP_PREC_FP16S_DC ? sizeof(__half) : sizeof(float);
             HIPCHK(s, hipMemsetAsync(s->e_lo, 0, 2 * s->lg[l].cs * esz, s->stream));
+            HIPCHK(s, hipMemsetAsync(s->e_nx, 0, 2 * s->lg[l].cs * esz, s->stream));
+            // the outer pass writes only active points of the other potential
+            // buffer: give it this level's fixed ghost layer
+            launch_copy_ghosts(c.dim, s->stream, s->lg[l], s->phi[l], s->phi_alt);
         }
         for (;;) {
             if (!std::isfinite(r)) { lvl = NP_ENONFINITE; break; }
@@ -783,17 +861,18 @@ int nested_poisson_solve(np_solver* s, const double* const* rho, const double* p
                 if (!have_defect) {
                     double same = 0.0;
                     r_scale = r > 0 ? r : 1.0;
-                    rc = dc_residual_sync(s, l, 1.0 / r_scale, &same);
+                    rc = dc_outer_sync(s, l, false, 0.0, 1.0 / r_scale, &same);
                     if (rc) return rc;
                     have_defect = true;
                 }
-                rc = dc_step(s, l, r_scale);
+                rc = dc_inner(s, l);
                 if (rc) return rc;
                 q++;
-                // residual of the updated potential, scaled by the previous norm
-                // (the new one is not known until this pass ends)
+                // phi += h^2 r_scale e'', then the residual of the updated potential,
+                // scaled by the previous norm (the new one is not known until the pass ends)
                 double rprev = r > 0 ? r : 1.0;
-                rc = dc_residual_sync(s, l, 1.0 / rprev, &r);
+                double dx = std::ldexp(c.dx0, -l);
+                rc = dc_outer_sync(s, l, true, dx * dx * r_scale, 1.0 / rprev, &r);
                 if (rc) return rc;
                 r_scale = rprev;
             } else {
@@ -812,6 +891,10 @@ int nested_poisson_solve(np_solver* s, const double* const* rho, const double* p
                 if (rc) return rc;
                 if (Fdelta < c.tol) break;
             }
+        }
+        if (dc) {
+            rc = dc_settle(s, l);
+            if (rc) return rc;
         }
         st.cycles[l] = q;
         st.scale[l] = scale;

@@ -98,3 +98,38 @@ def test_dc_zero_density_and_force_rule():
     phi, _, st = _solve(wl, precision="fp32_dc", stop_rule="force_delta")
     for l in range(wl.geom.nlevels):
         assert np.abs(phi[l] - phi64[l]).max() / np.abs(phi64[l]).max() <= 1e-8
+
+
+def _ragged_levels_3d():
+    # level sizes 16, 8, 12: the spare potential buffer of the defect correction
+    # is larger than levels 1 and 2, so an odd number of outer passes there
+    # ends with the copy back into the level's own buffer
+    g = W.Geometry(dim=3, n=[16, 8, 12], off=[(0, 0, 0), (6, 5, 4), (1, 1, 1)], lo0=(-0.5, -0.5, -0.5),
+                   dx0=1.0 / 16)
+    return W.Workload("ragged3d_16_8_12", g, W.Plummer([(1.0, 0.1, (0.02, -0.03, 0.01))]))
+
+
+def _ragged_levels_2d():
+    g = W.Geometry(dim=2, n=[30, 14, 6], off=[(0, 0, 0), (5, 9, 0), (3, 2, 0)], lo0=(-0.5, -0.5, 0.0),
+                   dx0=1.0 / 30, G=1.0)
+    return W.Workload("ragged2d_30_14_6", g, W.Gaussian(0.15, 1.0))
+
+
+@pytest.mark.parametrize("n_pre,inner", [(2, 1), (0, 1), (1, 2), (2, 3)])
+@pytest.mark.parametrize("precision", ["fp32_dc", "fp16s_dc"])
+@pytest.mark.parametrize("make", [_ragged_levels_3d, _ragged_levels_2d], ids=["3d", "2d"])
+def test_dc_ragged_levels_and_schedules(make, precision, n_pre, inner):
+    """Levels of different sizes, with and without pre-smoothing (the outer
+    pass then starts the correction at zero instead of relaxing its red
+    points) and with several inner cycles: the FP64 outer iteration still
+    reaches the oracle's converged solution."""
+    wl = make()
+    rho, po = W.make_inputs(wl.geom, wl.prob)
+    ref = core.solve(wl.geom, [r.numpy() for r in rho], po.numpy(), tol=1e-13, max_cycles=200, n_pre=n_pre,
+                     n_post=2 if n_pre == 0 else 1)
+    phi, F, st = _solve(wl, precision=precision, n_pre=n_pre, n_post=2 if n_pre == 0 else 1, inner_cycles=inner,
+                        max_cycles=100)
+    for l in range(wl.geom.nlevels):
+        err = np.abs(phi[l] - ref["phi"][l]).max() / np.abs(ref["phi"][l]).max()
+        assert err <= 1e-8, (l, err, st["cycles"])
+        assert st["final_rel_residual"][l] <= 1e-10
