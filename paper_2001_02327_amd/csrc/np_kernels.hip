@@ -534,6 +534,7 @@ __global__ void __launch_bounds__(kBlock) k_smooth_fine(T* __restrict__ u, const
 // cover adjacent rows of the same planes and the y-neighbour rows come from
 // its L2.
 constexpr int kZChunk = 8;
+constexpr int kZGroup = 8;  // planes whose loads are issued together (divides kZChunk)
 
 // TAG 0: level 0 (ghost layer in memory); TAG 1: coarse levels, whose ghost
 // values come from the rule (GRule) where a boundary point reads them.
@@ -562,14 +563,14 @@ __global__ void __launch_bounds__(kBlock) k_smooth_zmarch3(T* __restrict__ u, co
     C below = (C)o[(size_t)(k0 - 1) * plane + col];
     C cur = (C)o[(size_t)k0 * plane + col];
     int pk = k0;
-    // groups of 4 planes: every load of the group is issued before the first
-    // update so that each wave keeps ~20 loads in flight.  Loads at inactive
-    // (ghost) positions stay inside the arrays: h-1 / h+1 fall in the
+    // groups of kZGroup planes: every load of the group is issued before the
+    // first update so that each wave keeps many loads in flight.  Loads at
+    // inactive (ghost) positions stay inside the arrays: h-1 / h+1 fall in the
     // neighbouring row of the same plane and f covers the whole padded grid.
-    for (; pk + 3 <= k1; pk += 4) {
-        C ab[4], xo[4], ym[4], yp[4], fv[4];
+    for (; pk + kZGroup - 1 <= k1; pk += kZGroup) {
+        C ab[kZGroup], xo[kZGroup], ym[kZGroup], yp[kZGroup], fv[kZGroup];
 #pragma unroll
-        for (int q = 0; q < 4; q++) {
+        for (int q = 0; q < kZGroup; q++) {
             const size_t here = (size_t)(pk + q) * plane + col;
             const int par = (colour + pj + pk + q + 3) & 1;
             ab[q] = (C)o[here + plane];
@@ -579,7 +580,7 @@ __global__ void __launch_bounds__(kBlock) k_smooth_zmarch3(T* __restrict__ u, co
             fv[q] = (C)fc[here];
         }
 #pragma unroll
-        for (int q = 0; q < 4; q++) {
+        for (int q = 0; q < kZGroup; q++) {
             const size_t here = (size_t)(pk + q) * plane + col;
             const int par = (colour + pj + pk + q + 3) & 1;
             const int pi = 2 * h + par;
@@ -679,15 +680,9 @@ __global__ void __launch_bounds__(kBlock) k_smooth_zmarch3_pair(T* __restrict__ 
     const T* __restrict__ fc = f + (size_t)colour * g.cs;
     Pair<T> below = *(const Pair<T>*)(o + (size_t)(k0 - 1) * plane + col);
     Pair<T> cur = *(const Pair<T>*)(o + (size_t)k0 * plane + col);
-    for (int pk = k0; pk <= k1; pk++) {
+    auto step = [&](int pk, const Pair<T>& above, const Pair<T>& ym, const Pair<T>& yp, const Pair<T>& fv, C ex) {
         const size_t here = (size_t)pk * plane + col;
-        const Pair<T> above = *(const Pair<T>*)(o + here + plane);
-        const Pair<T> ym = *(const Pair<T>*)(o + here - g.hx);
-        const Pair<T> yp = *(const Pair<T>*)(o + here + g.hx);
-        const Pair<T> fv = *(const Pair<T>*)(fc + here);
         const int par = (colour + pj + pk + 3) & 1;
-        // the extra x-neighbour stays inside the plane (neighbouring row at the row ends)
-        const C ex = (C)o[par ? here + 2 : here - 1];
         C xm0, xp0, xm1, xp1;
         if (par) {
             xm0 = (C)cur.a;
@@ -723,6 +718,31 @@ __global__ void __launch_bounds__(kBlock) k_smooth_zmarch3_pair(T* __restrict__ 
         }
         below = cur;
         cur = above;
+    };
+    // the extra x-neighbour stays inside the plane (neighbouring row at the row ends)
+    auto extra = [&](int pk, size_t here) -> C { return (C)o[((colour + pj + pk + 3) & 1) ? here + 2 : here - 1]; };
+    if (k1 - k0 + 1 == kZChunk) {
+        // a full chunk: every load of its planes is issued before the first
+        // update, so that each wave keeps ~40 loads in flight
+        Pair<T> ab[kZChunk], ym[kZChunk], yp[kZChunk], fv[kZChunk];
+        C ex[kZChunk];
+#pragma unroll
+        for (int q = 0; q < kZChunk; q++) {
+            const size_t here = (size_t)(k0 + q) * plane + col;
+            ab[q] = *(const Pair<T>*)(o + here + plane);
+            ym[q] = *(const Pair<T>*)(o + here - g.hx);
+            yp[q] = *(const Pair<T>*)(o + here + g.hx);
+            fv[q] = *(const Pair<T>*)(fc + here);
+            ex[q] = extra(k0 + q, here);
+        }
+#pragma unroll
+        for (int q = 0; q < kZChunk; q++) step(k0 + q, ab[q], ym[q], yp[q], fv[q], ex[q]);
+        return;
+    }
+    for (int pk = k0; pk <= k1; pk++) {
+        const size_t here = (size_t)pk * plane + col;
+        step(pk, *(const Pair<T>*)(o + here + plane), *(const Pair<T>*)(o + here - g.hx),
+             *(const Pair<T>*)(o + here + g.hx), *(const Pair<T>*)(fc + here), extra(pk, here));
     }
 }
 
