@@ -163,6 +163,7 @@ def run_variant(name, wl, rho, phi_outer, F, steps, warmup, inner_cycles):
         ms_per_solve=round(ms, 3),
         wall_ms_per_step=round(wall_ms / steps, 3),
         cycles_per_level=stats[-1]["cycles"],
+        outer_steps_per_level=stats[-1]["outer_steps"],
         learned_kept=stats[-1]["learned_used"],
         linf_force_error=linf,
         smoother=dict(elem_bytes=elem, bytes_per_launch=half_sweep_bytes, avg_launch_us=round(sm_avg_ms * 1e3, 2),
@@ -181,11 +182,14 @@ def main():
     ap.add_argument("--N", type=int, default=512, help="cells per axis of every level")
     ap.add_argument("--variants", default="fp64,fp16s_dc,fp16s_dc+learned",
                     help="comma-separated subset of " + ",".join(VARIANTS))
-    ap.add_argument("--inner-cycles", type=int, default=1)
+    ap.add_argument("--inner-cycles", default="adaptive",
+                    help="V-cycles per defect-correction step: 1..8, or 'adaptive' (1..4 per step)")
     ap.add_argument("--cpu-sample-cycles", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true", help="run only a 1 GiB device copy x5")
     args = ap.parse_args()
+    if args.inner_cycles != "adaptive":
+        args.inner_cycles = int(args.inner_cycles)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the nested solve has no multi-GPU path in this build "
@@ -256,6 +260,7 @@ def main():
             "variant": best,
             "stop": "||r||_inf <= 1e-10 ||f||_inf per level",
             "step": "nested solve + forces on every level",
+            "inner_cycles": args.inner_cycles,
         },
         "roofline": {
             "bound": "hbm",

@@ -66,6 +66,7 @@ extern "C" {
 #define NP_PREC_FP64 0     /* every operator in FP64 */
 #define NP_PREC_FP32_DC 1  /* FP32 V-cycles inside FP64 defect correction */
 #define NP_PREC_FP16S_DC 2 /* FP16-stored, FP32-computed finest-level V-cycle arrays inside FP64 defect correction */
+#define NP_INNER_ADAPTIVE 0 /* inner_cycles: chosen per step from the measured contraction */
 
 /* initial guess of levels l >= 1 */
 #define NP_GUESS_INTERP 0  /* interpolated from level l-1 (Sec. 2.4) */
@@ -84,7 +85,10 @@ typedef struct np_config {
     int max_cycles;                 /* 1..NP_MAX_CYCLES */
     int stop_rule;                  /* NP_STOP_* */
     int precision;                  /* NP_PREC_* */
-    int inner_cycles;               /* low-precision V-cycles per defect-correction step, 1..8 */
+    int inner_cycles;               /* low-precision V-cycles per defect-correction step: 1..8,
+                                       or NP_INNER_ADAPTIVE (0): 1..4 per step (1..3 with FP16
+                                       storage), as many as the contraction measured so far
+                                       says the stop test needs */
     int guess;                      /* NP_GUESS_* */
 } np_config;
 
@@ -131,7 +135,7 @@ int nested_poisson_create(const np_config* cfg, void* hip_stream, np_solver** ou
  * `stats` may be NULL.  Errors: NP_EINVAL, NP_ENONFINITE, NP_ENOTCONV (the
  * cap was hit on some level; results are valid), NP_EDIVERGED, NP_EHIP. */
 typedef struct np_stats {
-    int cycles[NP_MAX_LEVELS];                /* V-cycles (outer steps for DC) per level */
+    int cycles[NP_MAX_LEVELS];                /* V-cycles per level (inner ones for DC) */
     double initial_rel_residual[NP_MAX_LEVELS];
     double final_rel_residual[NP_MAX_LEVELS]; /* ||r||_inf / scale at exit */
     double scale[NP_MAX_LEVELS];              /* reference norm of the stop test */
@@ -139,6 +143,7 @@ typedef struct np_stats {
     double total_ms;
     int learned_used[NP_MAX_LEVELS];          /* 1 where the learned guess was kept */
     double interp_rel_residual[NP_MAX_LEVELS];/* relative residual of the interpolated guess */
+    int outer_steps[NP_MAX_LEVELS];           /* defect-correction steps (0 for NP_PREC_FP64) */
 } np_stats;
 int nested_poisson_solve(np_solver* s, const double* const* rho, const double* phi_outer, np_stats* stats);
 
@@ -147,8 +152,8 @@ int nested_poisson_solve(np_solver* s, const double* const* rho, const double* p
  * compare iterates at equal cycle counts.  The array has nlevels entries. */
 int nested_poisson_set_fixed_cycles(np_solver* s, const int* cycles);
 
-/* Relative residual after each cycle of the last solve on `level`:
- * out[0] is before the first cycle.  Writes min(cap, cycles+1) values and
+/* Relative residual after each cycle (each outer step for the defect
+ * correction) of the last solve on `level`: out[0] is before the first one.  Writes min(cap, cycles+1) values and
  * returns their count (or a negative error). */
 int nested_poisson_history(const np_solver* s, int level, double* out, int cap);
 

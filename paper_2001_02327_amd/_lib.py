@@ -66,6 +66,7 @@ class NpStats(ctypes.Structure):
         ("total_ms", ctypes.c_double),
         ("learned_used", ctypes.c_int * NP_MAX_LEVELS),
         ("interp_rel_residual", ctypes.c_double * NP_MAX_LEVELS),
+        ("outer_steps", ctypes.c_int * NP_MAX_LEVELS),
     ]
 
 
@@ -156,7 +157,7 @@ def make_config(geom, n_pre=2, n_post=1, tol=1e-10, max_cycles=50, stop_rule="re
     c.max_cycles = int(max_cycles)
     c.stop_rule = STOP_RULES[stop_rule] if isinstance(stop_rule, str) else int(stop_rule)
     c.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
-    c.inner_cycles = int(inner_cycles)
+    c.inner_cycles = 0 if inner_cycles == "adaptive" else int(inner_cycles)
     c.guess = GUESSES[guess] if isinstance(guess, str) else int(guess)
     return c
 

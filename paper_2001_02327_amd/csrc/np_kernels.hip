@@ -801,6 +801,113 @@ __global__ void __launch_bounds__(kBlock) k_resid_restrict(const TF* __restrict_
     ec[pc] = (TC)0;
 }
 
+// 3-D restriction marching along the coarse z axis: a thread owns one coarse
+// column (I, J) and a chunk of coarse planes K.  For each fine plane it loads
+// the 2 x 2 children of its column and their x/y neighbours (a cross of 12
+// values) once; the z neighbours of a child plane are the centres of the
+// planes before and after it, kept in registers.  Per child and in the sum
+// over children the arithmetic and order are those of k_resid_restrict.
+// Fine indices beyond N_f + 1 (beside children past the active range, which
+// count as zero) are clamped into the array and never used.
+template <typename TF, typename TC, bool RULE>
+__global__ void __launch_bounds__(kBlock) k_restrict3_zm(const TF* __restrict__ u, const TF* __restrict__ f, SGrid gf,
+                                                         typename Compute<TC>::type inv_h2,
+                                                         typename Compute<TC>::type out_scale, SGrid gc,
+                                                         TC* __restrict__ fc, TC* __restrict__ ec,
+                                                         GRule<typename Compute<TC>::type> gr, int pblocks, int kch)
+{
+    using C = typename Compute<TC>::type;
+    const int Nc = gc.nx - 2, Nf = gf.nx - 2;
+    const long lb = xcd_block();
+    const int zc = (int)(lb / pblocks);
+    const long t = (lb - (long)zc * pblocks) * kBlock + threadIdx.x;
+    if (t >= (long)Nc * Nc) return;
+    const int I = 1 + (int)(t % Nc), J = 1 + (int)(t / Nc);
+    const int K0 = 1 + zc * kch;
+    const int K1 = min(K0 + kch - 1, Nc);
+    auto cl = [&](int a) { return a > Nf + 1 ? Nf + 1 : a; };
+    int xi[4], yj[4];
+    for (int a = 0; a < 4; a++) {
+        xi[a] = cl(2 * I - 2 + a);
+        yj[a] = cl(2 * J - 2 + a);
+    }
+    // cross of fine plane k: P[r][c] = u(2I-2+c, 2J-2+r, k); the corners are not loaded
+    auto load_cross = [&](int k, C (&P)[4][4]) {
+        const int kk = cl(k);
+#pragma unroll
+        for (int r = 0; r < 4; r++)
+#pragma unroll
+            for (int c = 0; c < 4; c++) {
+                if ((r == 0 || r == 3) && (c == 0 || c == 3)) continue;
+                P[r][c] = (C)at<3>(u, gf, xi[c], yj[r], kk);
+            }
+    };
+    C pc[2][2];       // centres of the plane below the current pair
+    C p1[4][4], p2[4][4], p3[4][4];
+    {
+        const int kk = cl(2 * K0 - 2);
+        for (int r = 0; r < 2; r++)
+            for (int c = 0; c < 2; c++) pc[r][c] = (C)at<3>(u, gf, xi[1 + c], yj[1 + r], kk);
+    }
+    load_cross(2 * K0 - 1, p1);
+    for (int K = K0; K <= K1; K++) {
+        load_cross(2 * K, p2);
+        load_cross(2 * K + 1, p3);
+        C fv[2][2][2];
+#pragma unroll
+        for (int dz = 0; dz < 2; dz++)
+#pragma unroll
+            for (int dy = 0; dy < 2; dy++)
+#pragma unroll
+                for (int dx = 0; dx < 2; dx++)
+                    fv[dz][dy][dx] = (C)at<3>(f, gf, xi[1 + dx], yj[1 + dy], cl(2 * K - 1 + dz));
+        C sum = 0;
+#pragma unroll
+        for (int dz = 0; dz < 2; dz++) {
+            const int k = 2 * K - 1 + dz;
+            if (k > Nf) continue;
+#pragma unroll
+            for (int dy = 0; dy < 2; dy++) {
+                const int j = 2 * J - 1 + dy;
+                if (j > Nf) continue;
+#pragma unroll
+                for (int dx = 0; dx < 2; dx++) {
+                    const int i = 2 * I - 1 + dx;
+                    if (i > Nf) continue;
+                    const C(&P)[4][4] = dz ? p2 : p1;
+                    const C uc = P[1 + dy][1 + dx];
+                    C xm = P[1 + dy][dx], xp = P[1 + dy][2 + dx];
+                    C ym = P[dy][1 + dx], yp = P[2 + dy][1 + dx];
+                    C zm = dz ? p1[1 + dy][1 + dx] : pc[dy][dx];
+                    C zp = dz ? p3[1 + dy][1 + dx] : p2[1 + dy][1 + dx];
+                    if (RULE) {
+                        rule_pair(i, Nf, uc, xm, xp, gr);
+                        rule_pair(j, Nf, uc, ym, yp, gr);
+                        rule_pair(k, Nf, uc, zm, zp, gr);
+                    }
+                    C s = xm + xp;
+                    s = s + ym;
+                    s = s + yp;
+                    s = s + zm;
+                    s = s + zp;
+                    sum += fv[dz][dy][dx] - (s - (C)6 * uc) * inv_h2;
+                }
+            }
+        }
+        const size_t q = pos<3, TC>(gc, I, J, K);
+        fc[q] = (TC)(sum * ((C)0.125 * out_scale));
+        ec[q] = (TC)0;
+#pragma unroll
+        for (int r = 0; r < 2; r++)
+#pragma unroll
+            for (int c = 0; c < 2; c++) pc[r][c] = p2[1 + r][1 + c];
+#pragma unroll
+        for (int r = 0; r < 4; r++)
+#pragma unroll
+            for (int c = 0; c < 4; c++) p1[r][c] = p3[r][c];
+    }
+}
+
 // u += P(e) on the fine active points (eqn:prolongation2D/3D as the tensor
 // product of (3/4, 1/4) along each axis: the coarse parent ceil(p/2) weighs
 // 3/4, its neighbour on the side of the fine centre 1/4).  Each thread does
@@ -890,8 +997,6 @@ __global__ void __launch_bounds__(kBlock) k_prolong_add(const TC* __restrict__ e
 // coarse index runs to ceil(N_f / 2), which is N_c + 1 when N_f = 2 N_c + 1
 // (a ghost parent with one active child).  Per child the arithmetic is that
 // of k_prolong_add.
-constexpr int kProlongChunk = 8;
-
 template <typename C>
 __device__ __forceinline__ AxisNb<C> axis_nb_clamped(int q, int N, const GRule<C>& gr)
 {
@@ -903,7 +1008,7 @@ __device__ __forceinline__ AxisNb<C> axis_nb_clamped(int q, int N, const GRule<C
 template <typename TC, typename TF>
 __global__ void __launch_bounds__(kBlock) k_prolong3_zm(const TC* __restrict__ e, SGrid gc, TF* __restrict__ u,
                                                          SGrid gf, int black_only, GRule<typename Compute<TC>::type> gr,
-                                                         int pblocks)
+                                                         int pblocks, int kch)
 {
     using C = typename Compute<TC>::type;
     const int Nc = gc.nx - 2, Nf = gf.nx - 2;
@@ -913,8 +1018,8 @@ __global__ void __launch_bounds__(kBlock) k_prolong3_zm(const TC* __restrict__ e
     const long t = (lb - (long)zc * pblocks) * kBlock + threadIdx.x;
     if (t >= (long)Mq * Mq) return;
     const int I = 1 + (int)(t % Mq), J = 1 + (int)(t / Mq);
-    const int K0 = 1 + zc * kProlongChunk;
-    const int K1 = min(K0 + kProlongChunk - 1, Mq);
+    const int K0 = 1 + zc * kch;
+    const int K1 = min(K0 + kch - 1, Mq);
     AxisNb<C> mx[3], my[3];
     for (int a = 0; a < 3; a++) {
         mx[a] = axis_nb_clamped(I - 1 + a, Nc, gr);
@@ -1586,12 +1691,17 @@ void launch_resid_restrict(int dim, hipStream_t st, SGrid gf, const TF* u, const
     dim3 grid(ceil_div(total, kBlock));
     const GRule<C> gr{xn1, (C)coef};
     if (dim == 3) {
+        // z-march: 4 coarse planes per thread on large grids, 1 on small ones
+        // (there the column count alone does not fill the chip)
+        const int kch = Nc >= 128 ? 4 : 1;
+        const int pblocks = ceil_div(Nc * Nc, kBlock);
+        const dim3 zgrid(pblocks * ceil_div(Nc, kch));
         if (rule)
-            hipLaunchKernelGGL((k_resid_restrict<3, TF, TC, true>), grid, dim3(kBlock), 0, st, u, f, gf, (C)inv_h2,
-                               (C)out_scale, gc, fc, ec, gr);
+            hipLaunchKernelGGL((k_restrict3_zm<TF, TC, true>), zgrid, dim3(kBlock), 0, st, u, f, gf, (C)inv_h2,
+                               (C)out_scale, gc, fc, ec, gr, pblocks, kch);
         else
-            hipLaunchKernelGGL((k_resid_restrict<3, TF, TC, false>), grid, dim3(kBlock), 0, st, u, f, gf, (C)inv_h2,
-                               (C)out_scale, gc, fc, ec, gr);
+            hipLaunchKernelGGL((k_restrict3_zm<TF, TC, false>), zgrid, dim3(kBlock), 0, st, u, f, gf, (C)inv_h2,
+                               (C)out_scale, gc, fc, ec, gr, pblocks, kch);
     } else {
         if (rule)
             hipLaunchKernelGGL((k_resid_restrict<2, TF, TC, true>), grid, dim3(kBlock), 0, st, u, f, gf, (C)inv_h2,
@@ -1611,10 +1721,13 @@ void launch_prolong_add(int dim, hipStream_t st, SGrid gc, const TC* ec, SGrid g
     dim3 grid(ceil_div(ncompact_active(dim, gf), kBlock));
     if (dim == 3) {
         const long Mq = (gf.nx - 1) / 2;  // ceil(N_f / 2) coarse parents per axis
+        // 8 coarse planes per thread on large grids, 2 on small ones (there the
+        // column count alone does not fill the chip)
+        const int kch = Mq >= 200 ? 8 : 2;
         const int pblocks = ceil_div(Mq * Mq, kBlock);
-        const int chunks = ceil_div(Mq, kProlongChunk);
+        const int chunks = ceil_div(Mq, kch);
         hipLaunchKernelGGL((k_prolong3_zm<TC, TF>), dim3(pblocks * chunks), dim3(kBlock), 0, st, ec, gc, u, gf,
-                           black_only, gr, pblocks);
+                           black_only, gr, pblocks, kch);
     } else
         hipLaunchKernelGGL((k_prolong_add<2, TC, TF>), grid, dim3(kBlock), 0, st, ec, gc, u, gf, black_only, gr);
 }

@@ -87,6 +87,105 @@ __global__ void __launch_bounds__(kNB) k_conv_fwd(const TI* __restrict__ in, int
     for (int o = 0; o < cout; o++) st(dst + o, relu ? fmaxf(acc[o], 0.0f) : acc[o]);
 }
 
+// The same convolution for the network's own channel counts, fixed at compile
+// time: the accumulators stay in registers, the input channels of a tap come in
+// with 8- to 16-byte loads and the outputs leave the same way.  Same
+// arithmetic in the same order as k_conv_fwd.
+template <int N, typename T>
+__device__ __forceinline__ void ld_vec(const T* p, float (&a)[N])
+{
+    if constexpr (sizeof(T) == 2 && N % 8 == 0) {
+#pragma unroll
+        for (int q = 0; q < N / 8; q++) {
+            const uint4 u = ((const uint4*)p)[q];
+            const uint32_t w4[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                a[8 * q + 2 * e] = __uint_as_float(w4[e] << 16);
+                a[8 * q + 2 * e + 1] = __uint_as_float(w4[e] & 0xffff0000u);
+            }
+        }
+    } else if constexpr (sizeof(T) == 2 && N == 2) {
+        const uint32_t u = *(const uint32_t*)p;
+        a[0] = __uint_as_float(u << 16);
+        a[1] = __uint_as_float(u & 0xffff0000u);
+    } else if constexpr (sizeof(T) == 4 && N % 4 == 0) {
+#pragma unroll
+        for (int q = 0; q < N / 4; q++) {
+            const float4 u = ((const float4*)p)[q];
+            a[4 * q] = u.x;
+            a[4 * q + 1] = u.y;
+            a[4 * q + 2] = u.z;
+            a[4 * q + 3] = u.w;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < N; i++) a[i] = ld(p + i);
+    }
+}
+
+template <int N, typename T>
+__device__ __forceinline__ void st_vec(T* p, const float (&a)[N])
+{
+    if constexpr (sizeof(T) == 2 && N % 8 == 0) {
+#pragma unroll
+        for (int q = 0; q < N / 8; q++) {
+            uint32_t w4[4];
+#pragma unroll
+            for (int e = 0; e < 4; e++)
+                w4[e] = (uint32_t)f32_to_bf16(a[8 * q + 2 * e]) | ((uint32_t)f32_to_bf16(a[8 * q + 2 * e + 1]) << 16);
+            ((uint4*)p)[q] = make_uint4(w4[0], w4[1], w4[2], w4[3]);
+        }
+    } else if constexpr (sizeof(T) == 4 && N % 4 == 0) {
+#pragma unroll
+        for (int q = 0; q < N / 4; q++) ((float4*)p)[q] = make_float4(a[4 * q], a[4 * q + 1], a[4 * q + 2], a[4 * q + 3]);
+    } else {
+#pragma unroll
+        for (int i = 0; i < N; i++) st(p + i, a[i]);
+    }
+}
+
+template <int CIN, int COUT, typename TI, typename TO>
+__global__ void __launch_bounds__(kNB) k_conv_fwd_t(const TI* __restrict__ in, const uint16_t* __restrict__ w,
+                                                   const float* __restrict__ bias, int relu, int B, int Z, int Y, int X,
+                                                   TO* __restrict__ out)
+{
+    __shared__ float ws[27 * COUT * CIN];
+    for (int i = threadIdx.x; i < 27 * COUT * CIN; i += kNB) ws[i] = bf16_to_f32(w[i]);
+    __syncthreads();
+    const long nvox = (long)B * Z * Y * X;
+    const long v = (long)blockIdx.x * kNB + threadIdx.x;
+    if (v >= nvox) return;
+    const int x = (int)(v % X);
+    long r = v / X;
+    const int y = (int)(r % Y);
+    r /= Y;
+    const int z = (int)(r % Z);
+    const int b = (int)(r / Z);
+    float acc[COUT];
+#pragma unroll
+    for (int o = 0; o < COUT; o++) acc[o] = bias[o];
+    int t = 0;
+    for (int dz = -1; dz <= 1; dz++)
+        for (int dy = -1; dy <= 1; dy++)
+            for (int dx = -1; dx <= 1; dx++, t++) {
+                const int zz = z + dz, yy = y + dy, xx = x + dx;
+                if (zz < 0 || zz >= Z || yy < 0 || yy >= Y || xx < 0 || xx >= X) continue;
+                float a[CIN];
+                ld_vec<CIN>(in + ((((long)b * Z + zz) * Y + yy) * X + xx) * CIN, a);
+                const float* wt = ws + t * COUT * CIN;
+#pragma unroll
+                for (int i = 0; i < CIN; i++)
+#pragma unroll
+                    for (int o = 0; o < COUT; o++) acc[o] = fmaf(wt[o * CIN + i], a[i], acc[o]);
+            }
+    if (relu) {
+#pragma unroll
+        for (int o = 0; o < COUT; o++) acc[o] = fmaxf(acc[o], 0.0f);
+    }
+    st_vec<COUT>(out + v * COUT, acc);
+}
+
 // Data gradient: gin[v][i] = sum_taps sum_o w[t][o][i] * gout[v - tap][o].
 __global__ void __launch_bounds__(kNB) k_conv_bwd_data(const float* __restrict__ gout, int cout,
                                                       const uint16_t* __restrict__ w, int cin, int B, int Z, int Y, int X,
@@ -263,13 +362,16 @@ __global__ void k_to_bf16(const float* __restrict__ a, uint16_t* __restrict__ b,
 }
 
 // ------------------------------------------------------------------ 16 -> 16 layer on the matrix cores
-// One wavefront computes 16 consecutive voxels along x (rows of the MFMA) times
-// the 16 output channels (columns), accumulating the 27 taps as 27
-// v_mfma_f32_16x16x16 bf16 products with K = 16 input channels.  Operand
+// A wavefront computes tiles of 16 consecutive voxels along x (rows of the
+// MFMA) times the 16 output channels (columns), accumulating the 27 taps as 27
+// v_mfma_f32_16x16x16 bf16 products with K = 16 input channels; it keeps the
+// weights of all taps in registers across kMfmaTilesPerWave tiles and loads a
+// tile's 27 input fragments before its first product.  Operand
 // layout of the 16x16x16 MFMA: lane l supplies A[row l%16][k 4(l/16)..+3] and
 // B[k 4(l/16)..+3][col l%16], and receives D[rows 4(l/16)..+3][col l%16].
 typedef short v4s __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
+constexpr int kMfmaTilesPerWave = 4;  // consecutive 16-voxel tiles per wavefront
 
 __global__ void __launch_bounds__(kNB) k_conv16_mfma(const uint16_t* __restrict__ in, const uint16_t* __restrict__ w,
                                                     const float* __restrict__ bias, int relu, int B, int Z, int Y,
@@ -278,37 +380,45 @@ __global__ void __launch_bounds__(kNB) k_conv16_mfma(const uint16_t* __restrict_
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int tiles_x = (X + 15) / 16;
-    const long tile = (long)blockIdx.x * (kNB / 64) + wave;
     const long ntiles = (long)B * Z * Y * tiles_x;
-    if (tile >= ntiles) return;
-    const int tx = (int)(tile % tiles_x);
-    long r = tile / tiles_x;
-    const int y = (int)(r % Y);
-    r /= Y;
-    const int z = (int)(r % Z);
-    const int b = (int)(r / Z);
     const int row = lane & 15;   // voxel within the tile (A row) / output channel (B, D column)
     const int kq = lane >> 4;    // which 4 of the 16 input channels
-    const int x = tx * 16 + row;
-    v4f acc = {0.f, 0.f, 0.f, 0.f};
-    int t = 0;
-    for (int dz = -1; dz <= 1; dz++)
-        for (int dy = -1; dy <= 1; dy++)
-            for (int dx = -1; dx <= 1; dx++, t++) {
-                const int zz = z + dz, yy = y + dy, xx = x + dx;
-                v4s a = {0, 0, 0, 0};
-                if (zz >= 0 && zz < Z && yy >= 0 && yy < Y && xx >= 0 && xx < X)
-                    a = *(const v4s*)(in + ((((long)b * Z + zz) * Y + yy) * X + xx) * 16 + 4 * kq);
-                const v4s bw = *(const v4s*)(w + (t * 16 + row) * 16 + 4 * kq);
-                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bw, acc, 0, 0, 0);
-            }
+    // the B operands of all 27 taps stay in registers for the wave's tiles
+    v4s bw[27];
+#pragma unroll
+    for (int t = 0; t < 27; t++) bw[t] = *(const v4s*)(w + (t * 16 + row) * 16 + 4 * kq);
     const float bo = bias[row];
-    for (int q = 0; q < 4; q++) {
-        const int xo = tx * 16 + 4 * kq + q;
-        if (xo >= X) continue;
-        float v = acc[q] + bo;
-        if (relu) v = fmaxf(v, 0.0f);
-        out[((((long)b * Z + z) * Y + y) * X + xo) * 16 + row] = f32_to_bf16(v);
+    const long first = ((long)blockIdx.x * (kNB / 64) + wave) * kMfmaTilesPerWave;
+    for (int it = 0; it < kMfmaTilesPerWave; it++) {
+        const long tile = first + it;
+        if (tile >= ntiles) return;
+        const int tx = (int)(tile % tiles_x);
+        long r = tile / tiles_x;
+        const int y = (int)(r % Y);
+        r /= Y;
+        const int z = (int)(r % Z);
+        const int b = (int)(r / Z);
+        const int x = tx * 16 + row;
+        // every A operand of the tile is loaded before the first product
+        v4s a[27];
+#pragma unroll
+        for (int t = 0; t < 27; t++) {
+            const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
+            const int zz = z + dz, yy = y + dy, xx = x + dx;
+            a[t] = v4s{0, 0, 0, 0};
+            if (zz >= 0 && zz < Z && yy >= 0 && yy < Y && xx >= 0 && xx < X)
+                a[t] = *(const v4s*)(in + ((((long)b * Z + zz) * Y + yy) * X + xx) * 16 + 4 * kq);
+        }
+        v4f acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int t = 0; t < 27; t++) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[t], bw[t], acc, 0, 0, 0);
+        for (int q = 0; q < 4; q++) {
+            const int xo = tx * 16 + 4 * kq + q;
+            if (xo >= X) continue;
+            float v = acc[q] + bo;
+            if (relu) v = fmaxf(v, 0.0f);
+            out[((((long)b * Z + z) * Y + y) * X + xo) * 16 + row] = f32_to_bf16(v);
+        }
     }
 }
 
@@ -371,10 +481,29 @@ __global__ void __launch_bounds__(kNB) k_net_target(SGrid g, const double* __res
 // ------------------------------------------------------------------ launchers
 constexpr int kNetParts = 2048;  // blocks (partial sums) of the weight-gradient reduction
 
+// The network's layer shapes (2 -> 16, 16 -> 16, 16 -> 1) run on the
+// compile-time kernel; returns false for other shapes.
+template <typename TI, typename TO>
+static bool conv_fwd_fixed(hipStream_t st, const TI* in, int cin, const uint16_t* w, const float* bias, int cout, int relu,
+                    int B, int Z, int Y, int X, TO* out)
+{
+    const dim3 grid(cdiv((long)B * Z * Y * X, kNB));
+    if (cin == 2 && cout == 16)
+        hipLaunchKernelGGL((k_conv_fwd_t<2, 16, TI, TO>), grid, dim3(kNB), 0, st, in, w, bias, relu, B, Z, Y, X, out);
+    else if (cin == 16 && cout == 16)
+        hipLaunchKernelGGL((k_conv_fwd_t<16, 16, TI, TO>), grid, dim3(kNB), 0, st, in, w, bias, relu, B, Z, Y, X, out);
+    else if (cin == 16 && cout == 1)
+        hipLaunchKernelGGL((k_conv_fwd_t<16, 1, TI, TO>), grid, dim3(kNB), 0, st, in, w, bias, relu, B, Z, Y, X, out);
+    else
+        return false;
+    return true;
+}
+
 void net_conv_fwd_f32(hipStream_t st, const float* in, int cin, const uint16_t* w, const float* bias, int cout, int relu,
                       int B, int Z, int Y, int X, float* out)
 {
     long nv = (long)B * Z * Y * X;
+    if (conv_fwd_fixed(st, in, cin, w, bias, cout, relu, B, Z, Y, X, out)) return;
     hipLaunchKernelGGL((k_conv_fwd<float, float>), dim3(cdiv(nv, kNB)), dim3(kNB), 0, st, in, cin, w, bias, cout, relu, B,
                        Z, Y, X, out);
 }
@@ -383,6 +512,7 @@ void net_conv_fwd_bf16(hipStream_t st, const uint16_t* in, int cin, const uint16
                        int relu, int B, int Z, int Y, int X, uint16_t* out)
 {
     long nv = (long)B * Z * Y * X;
+    if (conv_fwd_fixed(st, in, cin, w, bias, cout, relu, B, Z, Y, X, out)) return;
     hipLaunchKernelGGL((k_conv_fwd<uint16_t, uint16_t>), dim3(cdiv(nv, kNB)), dim3(kNB), 0, st, in, cin, w, bias, cout,
                        relu, B, Z, Y, X, out);
 }
@@ -391,6 +521,7 @@ void net_conv_fwd_bf16_to_f32(hipStream_t st, const uint16_t* in, int cin, const
                               int cout, int relu, int B, int Z, int Y, int X, float* out)
 {
     long nv = (long)B * Z * Y * X;
+    if (conv_fwd_fixed(st, in, cin, w, bias, cout, relu, B, Z, Y, X, out)) return;
     hipLaunchKernelGGL((k_conv_fwd<uint16_t, float>), dim3(cdiv(nv, kNB)), dim3(kNB), 0, st, in, cin, w, bias, cout,
                        relu, B, Z, Y, X, out);
 }
@@ -399,8 +530,8 @@ void net_conv16_mfma(hipStream_t st, const uint16_t* in, const uint16_t* w, cons
                      int Y, int X, uint16_t* out)
 {
     long ntiles = (long)B * Z * Y * ((X + 15) / 16);
-    hipLaunchKernelGGL(k_conv16_mfma, dim3(cdiv(ntiles, kNB / 64)), dim3(kNB), 0, st, in, w, bias, relu, B, Z, Y, X,
-                       out);
+    hipLaunchKernelGGL(k_conv16_mfma, dim3(cdiv(ntiles, (kNB / 64) * kMfmaTilesPerWave)), dim3(kNB), 0, st, in, w, bias,
+                       relu, B, Z, Y, X, out);
 }
 
 void net_conv_bwd_data(hipStream_t st, const float* gout, int cout, const uint16_t* w, int cin, int B, int Z, int Y,

@@ -51,7 +51,8 @@ bool validate(const np_config* c, char* why, size_t nwhy)
         return fail("bad precision %d%s", c->precision, 0);
     if (c->guess != NP_GUESS_INTERP && c->guess != NP_GUESS_LEARNED) return fail("bad guess %d%s", c->guess, 0);
     if (c->guess == NP_GUESS_LEARNED && c->dim != 3) return fail("the learned guess is 3-D only (dim %d)%s", c->dim, 0);
-    if (c->inner_cycles < 1 || c->inner_cycles > 8) return fail("inner_cycles must be 1..8 (got %d)%s", c->inner_cycles, 0);
+    if (c->inner_cycles < 0 || c->inner_cycles > 8)
+        return fail("inner_cycles must be 0 (adaptive) or 1..8 (got %d)%s", c->inner_cycles, 0);
     return true;
 }
 
@@ -492,18 +493,42 @@ int dc_outer_sync(np_solver* s, int l, bool update, double factor, double rscale
 }
 
 // Inner cycles of one defect-correction step (extension of Sec. 2.3 with FP32
-// or FP16-stored inner cycles): inner_cycles low-precision V-cycles on the
-// scaled defect r'' = r / r_scale, the first one starting from the state the
-// outer pass left (e'' = 0, red points relaxed when n_pre > 0).
-int dc_inner(np_solver* s, int l)
+// or FP16-stored inner cycles): k low-precision V-cycles on the scaled defect
+// r'' = r / r_scale, the first one starting from the state the outer pass left
+// (e'' = 0, red points relaxed when n_pre > 0).
+int dc_inner(np_solver* s, int l, int k)
 {
     const np_config& c = s->cfg;
-    for (int it = 0; it < c.inner_cycles; it++) {
+    for (int it = 0; it < k; it++) {
         const bool red_done = it == 0 && c.n_pre > 0;
         int rc = c.precision == NP_PREC_FP16S_DC ? vcycle_lo<__half>(s, l, red_done) : vcycle_lo<float>(s, l, red_done);
         if (rc) return rc;
     }
     return NP_OK;
+}
+
+// Inner V-cycles of the next defect-correction step: inner_cycles, or with
+// NP_INNER_ADAPTIVE the number that the contraction per cycle rho measured on
+// the previous step says brings the residual r down to the target, between 1
+// and a maximum (an outer pass costs about as much as a V-cycle, so the
+// estimate is rounded down unless it is a quarter cycle past an integer).  The
+// maximum is 4 with FP32 storage and 3 with FP16 storage, whose rounding (2^-11
+// relative) starts to limit what one step gains after about three cycles of
+// contraction ~0.3.  Never runs past `limit` (a pinned count or the cap).
+constexpr double kAdaptiveRho0 = 0.3;
+
+int dc_cycles(const np_config& c, double r, double target, double rho, int q, int limit)
+{
+    int k = c.inner_cycles;
+    if (k == NP_INNER_ADAPTIVE) {
+        const int kmax = c.precision == NP_PREC_FP16S_DC ? 3 : 4;
+        double need = kmax;
+        if (r > target && target > 0.0) need = std::log(target / r) / std::log(rho);
+        k = (int)std::ceil(need - 0.25);
+        k = k < 1 ? 1 : (k > kmax ? kmax : k);
+    }
+    if (q + k > limit) k = limit - q > 1 ? limit - q : 1;
+    return k;
 }
 
 // End of a level's defect correction: the level's potential must live in a
@@ -839,6 +864,8 @@ int nested_poisson_solve(np_solver* s, const double* const* rho, const double* p
         const bool dc = c.precision != NP_PREC_FP64;
         bool have_defect = false;
         double r_scale = 1.0;
+        double rho = kAdaptiveRho0;
+        int outer = 0;
         if (dc) {
             // multigrid level 0 of the correction has a zero ghost layer; clear the
             // whole array once per level (it is shared by levels of other sizes)
@@ -865,9 +892,11 @@ int nested_poisson_solve(np_solver* s, const double* const* rho, const double* p
                     if (rc) return rc;
                     have_defect = true;
                 }
-                rc = dc_inner(s, l);
+                const int k = dc_cycles(c, r, c.tol * scale, rho, q, pinned ? s->fixed[l] : c.max_cycles);
+                rc = dc_inner(s, l, k);
                 if (rc) return rc;
-                q++;
+                q += k;
+                outer++;
                 // phi += h^2 r_scale e'', then the residual of the updated potential,
                 // scaled by the previous norm (the new one is not known until the pass ends)
                 double rprev = r > 0 ? r : 1.0;
@@ -875,6 +904,10 @@ int nested_poisson_solve(np_solver* s, const double* const* rho, const double* p
                 rc = dc_outer_sync(s, l, true, dx * dx * r_scale, 1.0 / rprev, &r);
                 if (rc) return rc;
                 r_scale = rprev;
+                if (r > 0.0 && r < rprev) {
+                    const double m = std::pow(r / rprev, 1.0 / k);
+                    rho = m < 0.02 ? 0.02 : (m > 0.95 ? 0.95 : m);
+                }
             } else {
                 rc = vcycle(s, l);
                 if (rc) return rc;
@@ -897,6 +930,7 @@ int nested_poisson_solve(np_solver* s, const double* const* rho, const double* p
             if (rc) return rc;
         }
         st.cycles[l] = q;
+        st.outer_steps[l] = outer;
         st.scale[l] = scale;
         st.initial_rel_residual[l] = s->hist[l].front();
         st.final_rel_residual[l] = scale > 0 ? r / scale : r;

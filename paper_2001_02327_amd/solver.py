@@ -64,6 +64,7 @@ class NestedPoissonSolver:
             total_ms=st.total_ms,
             learned_used=[st.learned_used[l] for l in range(L)],
             interp_rel_residual=[st.interp_rel_residual[l] for l in range(L)],
+            outer_steps=[st.outer_steps[l] for l in range(L)],
         )
         return self.last_stats
 

@@ -81,7 +81,9 @@ def test_dc_inner_cycles_and_stress(precision):
     for l in range(wl.geom.nlevels):
         err = np.abs(phi[l] - phi64[l]).max() / np.abs(phi64[l]).max()
         assert err <= 1e-8, (l, err)
-        assert st["cycles"][l] <= st64["cycles"][l]
+        # the stop test runs after every second V-cycle
+        assert st["cycles"][l] == 2 * st["outer_steps"][l]
+        assert st["cycles"][l] <= st64["cycles"][l] + 1
     e64 = _linf_force_error(wl, F64)
     assert abs(_linf_force_error(wl, F) - e64) <= 5e-3 * e64
 
@@ -133,3 +135,27 @@ def test_dc_ragged_levels_and_schedules(make, precision, n_pre, inner):
         err = np.abs(phi[l] - ref["phi"][l]).max() / np.abs(ref["phi"][l]).max()
         assert err <= 1e-8, (l, err, st["cycles"])
         assert st["final_rel_residual"][l] <= 1e-10
+
+
+@pytest.mark.parametrize("precision", ["fp32_dc", "fp16s_dc"])
+@pytest.mark.parametrize("wl", [W.c3_plummer_offset(64), W.c4_multi_plummer(11, N=32), W.paper2d(32)],
+                         ids=lambda w: w.name)
+def test_dc_adaptive_inner_cycles(wl, precision):
+    """Adaptive inner cycles: each step runs as many V-cycles (1..4, 1..3 with
+    FP16 storage) as the contraction measured so far says the stop test needs.
+    The answer is the FP64 solve's, the V-cycle count stays within two of it
+    (three with FP16 storage, whose rounding slows the last cycles), and the outer
+    steps (each an FP64 pass over the level) are fewer than the V-cycles."""
+    phi64, F64, st64 = _solve(wl)
+    phi, F, st = _solve(wl, precision=precision, inner_cycles="adaptive")
+    for l in range(wl.geom.nlevels):
+        err = np.abs(phi[l] - phi64[l]).max() / np.abs(phi64[l]).max()
+        assert err <= 1e-8, (l, err)
+        assert st["final_rel_residual"][l] <= 1e-10
+        assert st["cycles"][l] <= st64["cycles"][l] + (3 if precision == "fp16s_dc" else 2), (st["cycles"], st64["cycles"])
+        assert st["outer_steps"][l] <= st["cycles"][l] <= 4 * st["outer_steps"][l]
+        if st64["cycles"][l] >= 6:
+            assert st["outer_steps"][l] < st["cycles"][l]
+    assert st64["outer_steps"] == [0] * wl.geom.nlevels
+    e64 = _linf_force_error(wl, F64)
+    assert abs(_linf_force_error(wl, F) - e64) <= 5e-3 * e64
