@@ -226,10 +226,13 @@ size_t np_net_workspace_bytes(int cin, int cout, long nvox);
  * weights, FP32 accumulation; 1 <= cin, cout <= 16. */
 int np_net_conv3d_fwd(const float* in, int cin, const unsigned short* w_bf16, const float* bias, int cout, int relu,
                       int batch, int nz, int ny, int nx, float* out, void* stream);
-/* The 16 -> 16 layer on the matrix cores: bfloat16 activations in and out,
- * FP32 accumulation (v_mfma_f32_16x16x16 bf16); 8-byte aligned arrays. */
-int np_net_conv3d_fwd_mfma(const unsigned short* in_bf16, const unsigned short* w_bf16, const float* bias, int relu,
-                           int batch, int nz, int ny, int nx, unsigned short* out_bf16, void* stream);
+/* A layer of the network on the matrix cores (the inference path), for
+ * (cin, cout) = (2, 16), (16, 16) or (16, 1): bfloat16 activations in,
+ * bfloat16 out (cout 16) or FP32 out (cout 1), FP32 accumulation
+ * (v_mfma_f32_16x16x16 bf16); `in` aligned to 4 * cin bytes.  Other shapes:
+ * NP_EINVAL. */
+int np_net_conv3d_fwd_mfma(const unsigned short* in_bf16, int cin, const unsigned short* w_bf16, const float* bias,
+                           int cout, int relu, int batch, int nz, int ny, int nx, void* out, void* stream);
 /* gin = d loss / d in given gout = d loss / d out. */
 int np_net_conv3d_bwd_data(const float* gout, int cout, const unsigned short* w_bf16, int cin, int batch, int nz,
                            int ny, int nx, float* gin, void* stream);

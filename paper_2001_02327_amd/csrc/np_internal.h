@@ -106,8 +106,10 @@ void net_conv_fwd_bf16(hipStream_t st, const uint16_t* in, int cin, const uint16
                        int relu, int B, int Z, int Y, int X, uint16_t* out);
 void net_conv_fwd_bf16_to_f32(hipStream_t st, const uint16_t* in, int cin, const uint16_t* w, const float* bias,
                               int cout, int relu, int B, int Z, int Y, int X, float* out);
-void net_conv16_mfma(hipStream_t st, const uint16_t* in, const uint16_t* w, const float* bias, int relu, int B, int Z,
-                     int Y, int X, uint16_t* out);
+// matrix-core inference of a layer (cin, cout) in {(2, 16), (16, 16), (16, 1)}:
+// bfloat16 input, bfloat16 output (cout 16) or FP32 output (cout 1)
+void net_conv_mfma(hipStream_t st, const uint16_t* in, int cin, const uint16_t* w, const float* bias, int cout, int relu,
+                   int B, int Z, int Y, int X, void* out);
 void net_conv_bwd_data(hipStream_t st, const float* gout, int cout, const uint16_t* w, int cin, int B, int Z, int Y,
                        int X, float* gin);
 size_t net_bwd_weight_workspace(int cin, int cout);

@@ -561,9 +561,9 @@ int learned_guess(np_solver* s, int l, const double* rho_l, double fourpiG, doub
     const double dx = std::ldexp(c.dx0, -l);
     prof_begin(s, NP_KCLASS_GUESS);
     net_features_bf16(st, g, s->phi[l], s->f[l], 1.0 / fnorm, 1.0 / (dx * dx), s->net_x);
-    net_conv_fwd_bf16(st, s->net_x, 2, s->net_w[0], s->net_b[0], 16, 1, 1, m, m, m, s->net_a1);
-    net_conv16_mfma(st, s->net_a1, s->net_w[1], s->net_b[1], 1, 1, m, m, m, s->net_a2);
-    net_conv_fwd_bf16_to_f32(st, s->net_a2, 16, s->net_w[2], s->net_b[2], 1, 0, 1, m, m, m, s->net_out);
+    net_conv_mfma(st, s->net_x, 2, s->net_w[0], s->net_b[0], 16, 1, 1, m, m, m, s->net_a1);
+    net_conv_mfma(st, s->net_a1, 16, s->net_w[1], s->net_b[1], 16, 1, 1, m, m, m, s->net_a2);
+    net_conv_mfma(st, s->net_a2, 16, s->net_w[2], s->net_b[2], 1, 0, 1, m, m, m, s->net_out);
     net_apply(st, g, s->phi[l], s->net_out, fnorm * dx * dx);
     prof_end(s);
     HIPCHK(s, hipGetLastError());

@@ -5,8 +5,10 @@ oracle's own solve, and the solve with the learned guess.
 Tolerances: the FP32 kernels use bfloat16 weights, so the reference is given
 the same bfloat16-rounded weights and the remaining difference is FP32
 accumulation over at most 27 * 16 = 432 terms: 1e-5 relative to the output's
-max.  The matrix-core kernel also rounds activations to bfloat16 (8 bits of
-mantissa, relative 2^-9 per operand) and its output: 2e-2.
+max.  The matrix-core kernels (the inference path) take bfloat16 activations,
+so the reference gets the same rounded inputs and the products are exact; the
+16-channel outputs are rounded to bfloat16 (relative 2^-9): 2e-2; the FP32
+output of the last layer: 1e-5.
 """
 import os
 
@@ -81,25 +83,35 @@ def test_conv_forward_and_backward(ci, co, shape):
     assert np.abs(gb.cpu().numpy() - rgb).max() <= 1e-5 * np.abs(rgb).max()
 
 
-@pytest.mark.parametrize("shape", [(1, 4, 5, 16), (2, 3, 4, 21), (1, 5, 5, 37)])
-def test_conv16_matrix_cores(shape):
-    rng = np.random.default_rng(sum(shape))
+@pytest.mark.parametrize("ci,co", [(2, 16), (16, 16), (16, 1)])
+@pytest.mark.parametrize("shape", [(1, 4, 5, 16), (2, 3, 4, 21), (1, 5, 5, 37), (1, 9, 7, 33)])
+def test_layers_on_matrix_cores(shape, ci, co):
+    """The inference path of each layer (LDS-staged blocks of 16 x 4 x 4
+    voxels; the shapes give partial blocks on every axis)."""
+    rng = np.random.default_rng(sum(shape) + ci + co)
     B, Z, Y, X = shape
-    x = onet.bf16_round(rng.standard_normal((B, Z, Y, X, 16)))
-    w = onet.bf16_round(rng.standard_normal((27, 16, 16)) * 0.2)
-    b = rng.standard_normal(16) * 0.1
+    x = onet.bf16_round(rng.standard_normal((B, Z, Y, X, ci)))
+    w = onet.bf16_round(rng.standard_normal((27, co, ci)) * 0.2)
+    b = rng.standard_normal(co) * 0.1
     xd = _dev(_bf16_bits(x), torch.int16)
     wd = _dev(_bf16_bits(w), torch.int16)
     bd = _dev(b)
-    out = torch.empty((B, Z, Y, X, 16), dtype=torch.int16, device="cuda")
+    out = torch.empty((B, Z, Y, X, co), dtype=torch.int16 if co == 16 else torch.float32, device="cuda")
     for relu in (0, 1):
-        assert _lib.lib().np_net_conv3d_fwd_mfma(xd.data_ptr(), wd.data_ptr(), bd.data_ptr(), relu, B, Z, Y, X,
-                                                 out.data_ptr(), _st()) == 0
-        got = (out.cpu().numpy().view(np.uint16).astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+        assert _lib.lib().np_net_conv3d_fwd_mfma(xd.data_ptr(), ci, wd.data_ptr(), bd.data_ptr(), co, relu, B, Z, Y,
+                                                 X, out.data_ptr(), _st()) == 0
+        if co == 16:
+            got = (out.cpu().numpy().view(np.uint16).astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+        else:
+            got = out.cpu().numpy().astype(np.float64)
         ref = onet.conv_fwd(x, w, b)
         if relu:
             ref = np.maximum(ref, 0)
-        assert np.abs(got - ref).max() <= 2e-2 * np.abs(ref).max(), relu
+        # bfloat16 output rounding (2^-9 relative) for cout 16; FP32 accumulation otherwise
+        tol = 2e-2 if co == 16 else 1e-5
+        assert np.abs(got - ref).max() <= tol * np.abs(ref).max(), relu
+    assert _lib.lib().np_net_conv3d_fwd_mfma(xd.data_ptr(), 3, wd.data_ptr(), bd.data_ptr(), co, 0, B, Z, Y, X,
+                                             out.data_ptr(), _st()) == _lib.NP_EINVAL
 
 
 def test_training_step_matches_reference():
