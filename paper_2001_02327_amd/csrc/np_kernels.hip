@@ -216,6 +216,91 @@ __global__ void __launch_bounds__(kBlock) k_interface_fill(SGrid gc, const doubl
     ff[p] = v;
 }
 
+// 3-D form of k_interface_fill marching along the coarse z axis: a thread owns
+// one coarse column and a chunk of coarse planes, keeps the 3 x 3 x 3 coarse
+// potential around the current coarse cell in registers and writes the 8 fine
+// points whose interpolation parent is that cell (fine padded p = 2a + d,
+// d = 0, 1, for the a-th parent from offset + 1).  The right-hand side of the
+// inner layer (rare) is interpolated with direct loads.  Same values as
+// k_interface_fill.
+constexpr int kFillChunk = 8;
+
+__global__ void __launch_bounds__(kBlock) k_interface_fill3_zm(SGrid gc, const double* __restrict__ phic,
+                                                               const double* __restrict__ fc, SGrid gf, int nf,
+                                                               int offx, int offy, int offz,
+                                                               const double* __restrict__ rho, double fourpiG,
+                                                               double* __restrict__ phif, double* __restrict__ ff,
+                                                               int pblocks)
+{
+    const int Mq = (gf.nx + 1) / 2;  // parents per axis: fine padded points 0 .. nf + 3 in pairs
+    const long lb = xcd_block();
+    const int zc = (int)(lb / pblocks);
+    const long t = (lb - (long)zc * pblocks) * kBlock + threadIdx.x;
+    if (t >= (long)Mq * Mq) return;
+    const int a = (int)(t % Mq), b = (int)(t / Mq);
+    const int c0 = zc * kFillChunk, c1 = min(c0 + kFillChunk, Mq) - 1;
+    const int qi = offx + 1 + a, qj = offy + 1 + b;
+    const int last = gf.nx - 1;
+    double cv[3][3][3];  // [z][y][x]: coarse planes qk-1 .. qk+1, rows qj-1 .., columns qi-1 ..
+    auto load_plane = [&](int qk, double (&pl)[3][3]) {
+#pragma unroll
+        for (int y = 0; y < 3; y++)
+#pragma unroll
+            for (int x = 0; x < 3; x++) pl[y][x] = at<3>(phic, gc, qi - 1 + x, qj - 1 + y, qk);
+    };
+    load_plane(offz + c0, cv[0]);
+    load_plane(offz + c0 + 1, cv[1]);
+    const double w0 = 0.75, w1 = 0.25;
+    for (int cc = c0; cc <= c1; cc++) {
+        const int qk = offz + 1 + cc;
+        load_plane(qk + 1, cv[2]);
+#pragma unroll
+        for (int dz = 0; dz < 2; dz++) {
+            const int pk = 2 * cc + dz;
+            if (pk > last) continue;
+            const int zs = dz ? 2 : 0;  // side of the fine centre: -1 for d = 0, +1 for d = 1
+#pragma unroll
+            for (int dy = 0; dy < 2; dy++) {
+                const int pj = 2 * b + dy;
+                if (pj > last) continue;
+                const int ys = dy ? 2 : 0;
+#pragma unroll
+                for (int dx = 0; dx < 2; dx++) {
+                    const int pi = 2 * a + dx;
+                    if (pi > last) continue;
+                    const int xs = dx ? 2 : 0;
+                    const double y0 = w0 * cv[1][1][1] + w1 * cv[1][1][xs];
+                    const double y1 = w0 * cv[1][ys][1] + w1 * cv[1][ys][xs];
+                    const double z0 = w0 * y0 + w1 * y1;
+                    const double y2 = w0 * cv[zs][1][1] + w1 * cv[zs][1][xs];
+                    const double y3 = w0 * cv[zs][ys][1] + w1 * cv[zs][ys][xs];
+                    const double z1 = w0 * y2 + w1 * y3;
+                    const size_t p = pos<3, double>(gf, pi, pj, pk);
+                    phif[p] = w0 * z0 + w1 * z1;
+                    const bool outer = pi == 0 || pi == last || pj == 0 || pj == last || pk == 0 || pk == last;
+                    const bool omega = pi >= 2 && pi <= nf + 1 && pj >= 2 && pj <= nf + 1 && pk >= 2 && pk <= nf + 1;
+                    double v;
+                    if (outer) {
+                        v = 0.0;
+                    } else if (omega) {
+                        v = fourpiG * rho[((size_t)(pk - 2) * nf + (pj - 2)) * nf + (pi - 2)];
+                    } else {
+                        v = interp_tensor<3>(fc, gc, qi, qj, qk, dx ? 1 : -1, dy ? 1 : -1, dz ? 1 : -1);
+                    }
+                    ff[p] = v;
+                }
+            }
+        }
+#pragma unroll
+        for (int y = 0; y < 3; y++)
+#pragma unroll
+            for (int x = 0; x < 3; x++) {
+                cv[0][y][x] = cv[1][y][x];
+                cv[1][y][x] = cv[2][y][x];
+            }
+    }
+}
+
 // ------------------------------------------------------------------ forces
 // F = -grad Phi with the fourth-order central difference:
 // dPhi/dx = [8 (Phi_{i+1} - Phi_{i-1}) - (Phi_{i+2} - Phi_{i-2})] / (12 dx).
@@ -252,6 +337,56 @@ __global__ void __launch_bounds__(kBlock) k_forces(SGrid g, int n, double m12dx,
     fx[t] = d4<D>(phi, g, pi, pj, pk, 0, m12dx);
     fy[t] = d4<D>(phi, g, pi, pj, pk, 1, m12dx);
     if (D == 3) fz[t] = d4<D>(phi, g, pi, pj, pk, 2, m12dx);
+}
+
+// 3-D forces marching along z: a thread owns one column (i, j) of Omega and a
+// chunk of kForceChunk planes; the potential along its own column (planes
+// k-2 .. k+2) stays in registers for the z-derivative, and every load of the
+// chunk (x and y neighbours at distance 1 and 2, the column values) is issued
+// before the first difference.  Same arithmetic as k_forces.
+constexpr int kForceChunk = 4;
+
+__global__ void __launch_bounds__(kBlock) k_forces3_zm(SGrid g, int n, double m12dx, const double* __restrict__ phi,
+                                                       double* __restrict__ fx, double* __restrict__ fy,
+                                                       double* __restrict__ fz, int pblocks)
+{
+    const long lb = xcd_block();
+    const int zc = (int)(lb / pblocks);
+    const long t = (lb - (long)zc * pblocks) * kBlock + threadIdx.x;
+    if (t >= (long)n * n) return;
+    const int i = (int)(t % n), j = (int)(t / n);
+    const int k0 = zc * kForceChunk;
+    const int nk = min(kForceChunk, n - k0);
+    const int pi = i + 2, pj = j + 2;
+    double col[kForceChunk + 4];  // padded planes k0 .. k0 + nk + 3 of the column
+    double xm1[kForceChunk], xp1[kForceChunk], xm2[kForceChunk], xp2[kForceChunk];
+    double ym1[kForceChunk], yp1[kForceChunk], ym2[kForceChunk], yp2[kForceChunk];
+#pragma unroll
+    for (int q = 0; q < kForceChunk + 4; q++)
+        if (q < nk + 4) col[q] = at<3>(phi, g, pi, pj, k0 + q);
+#pragma unroll
+    for (int q = 0; q < kForceChunk; q++) {
+        if (q < nk) {
+            const int pk = k0 + q + 2;
+            xm1[q] = at<3>(phi, g, pi - 1, pj, pk);
+            xp1[q] = at<3>(phi, g, pi + 1, pj, pk);
+            xm2[q] = at<3>(phi, g, pi - 2, pj, pk);
+            xp2[q] = at<3>(phi, g, pi + 2, pj, pk);
+            ym1[q] = at<3>(phi, g, pi, pj - 1, pk);
+            yp1[q] = at<3>(phi, g, pi, pj + 1, pk);
+            ym2[q] = at<3>(phi, g, pi, pj - 2, pk);
+            yp2[q] = at<3>(phi, g, pi, pj + 2, pk);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < kForceChunk; q++) {
+        if (q < nk) {
+            const long o = ((long)(k0 + q) * n + j) * n + i;
+            fx[o] = (8.0 * (xp1[q] - xm1[q]) - (xp2[q] - xm2[q])) * m12dx;
+            fy[o] = (8.0 * (yp1[q] - ym1[q]) - (yp2[q] - ym2[q])) * m12dx;
+            fz[o] = (8.0 * (col[q + 3] - col[q + 1]) - (col[q + 4] - col[q])) * m12dx;
+        }
+    }
 }
 
 // Forces into F (d arrays of n^d) and the maximum change against the values
@@ -1593,6 +1728,13 @@ void launch_interface_fill(int dim, hipStream_t st, SGrid gc, const double* phic
                            int nf, int offx, int offy, int offz, const double* rho, double fourpiG, double* phif,
                            double* ff)
 {
+    if (dim == 3) {
+        const long Mq = (gf.nx + 1) / 2;
+        const int pblocks = ceil_div(Mq * Mq, kBlock);
+        hipLaunchKernelGGL(k_interface_fill3_zm, dim3(pblocks * ceil_div(Mq, kFillChunk)), dim3(kBlock), 0, st, gc, phic,
+                           fc, gf, nf, offx, offy, offz, rho, fourpiG, phif, ff, pblocks);
+        return;
+    }
     NP_DISPATCH(dim, k_interface_fill, dim3(ceil_div(npoints(gf), kBlock)), dim3(kBlock), st, gc, phic, fc, gf, nf,
                 offx, offy, offz, rho, fourpiG, phif, ff);
 }
@@ -1601,9 +1743,14 @@ void launch_forces(int dim, hipStream_t st, SGrid g, int n, double dx, const dou
                    double* fz)
 {
     double m12dx = -1.0 / (12.0 * dx);
-    Strip sp = make_strip(n, n, dim == 3 ? n : 1, 16);
-    long blocks = dim == 3 ? strip_blocks(sp) : ceil_div((long)n * n, kBlock);
-    NP_DISPATCH(dim, k_forces, dim3(blocks), dim3(kBlock), st, g, n, m12dx, phi, fx, fy, fz, sp);
+    if (dim == 3) {
+        const int pblocks = ceil_div((long)n * n, kBlock);
+        hipLaunchKernelGGL(k_forces3_zm, dim3(pblocks * ceil_div(n, kForceChunk)), dim3(kBlock), 0, st, g, n, m12dx,
+                           phi, fx, fy, fz, pblocks);
+        return;
+    }
+    Strip sp = make_strip(n, n, 1, 16);
+    NP_DISPATCH(dim, k_forces, dim3(ceil_div((long)n * n, kBlock)), dim3(kBlock), st, g, n, m12dx, phi, fx, fy, fz, sp);
 }
 
 void launch_force_delta(int dim, hipStream_t st, SGrid g, int n, double dx, const double* phi, double* F,
@@ -1650,6 +1797,8 @@ void launch_half_sweep(int dim, hipStream_t st, SGrid g, T* u, const T* f, int c
     const GRule<C> gr{xn1, (C)coef};
     if (dim == 3 && fine && sizeof(T) <= 4 && (g.hx % 2) == 0) {
         // 2- and 4-byte storage: two compact points per thread, paired loads
+        // (on the coarse levels, with the ghost rule, this form measured slower
+        // than k_smooth_zmarch3)
         long m = g.nx - 2;
         int pblocks = ceil_div((long)(g.hx / 2) * m, kBlock);
         int chunks = ceil_div(m, kZChunk);
