@@ -24,6 +24,11 @@ if ROOT not in sys.path:
 
 METRIC = "nested solve time at fixed Linf force error; smoother GB/s; plain vs mixed+learned"
 PEAK_HBM_GBS = 8000.0   # MI355X HBM3E peak
+# HBM bytes per level-0 half sweep at 514^3 measured with rocprofv3 (FETCH_SIZE x 2.0 +
+# WRITE_SIZE x 1.0, the factors a 1 GiB device copy and fill give) for the smoother
+# kernels of this source tree: k_smooth_zmarch3_pair<__half> (FP16 storage) and
+# k_smooth_zmarch3<double,0> (FP64).  Valid only for those kernels at that size.
+SMOOTHER_TRAFFIC = {("fp16s_dc", 514): 0.3055e9 + 0.1373e9, ("fp64", 514): 1.2516e9 + 0.5480e9}
 
 
 def log(*a):
@@ -269,7 +274,7 @@ def main():
             "peak": PEAK_HBM_GBS,
             "unit": "GB/s",
             "frac": round(sm["GBps"] / PEAK_HBM_GBS, 4),
-            "traffic": None,
+            "traffic": SMOOTHER_TRAFFIC.get((VARIANTS[best]["precision"], n[0] + 2)),
             "bytes_per_launch": sm["bytes_per_launch"],
             "avg_launch_us": sm["avg_launch_us"],
         },

@@ -1570,6 +1570,8 @@ __device__ __forceinline__ Pair<double> dc_pair(const DcIn<TL, UPD>& in, size_t 
     return v;
 }
 
+constexpr int kDcGroup = 2;  // planes of the DC pass whose loads are issued together (1, 2, 4 measured alike)
+
 template <typename TL, bool UPD>
 __global__ void __launch_bounds__(kBlock) k_dc_outer3_pair(SGrid g, DcIn<TL, UPD> in, double* __restrict__ pout,
                                                            const double* __restrict__ f, double inv_h2, double rscale,
@@ -1596,21 +1598,33 @@ __global__ void __launch_bounds__(kBlock) k_dc_outer3_pair(SGrid g, DcIn<TL, UPD
             below[c] = dc_pair(in, c * cs + (size_t)(k0 - 1) * plane + col);
             cur[c] = dc_pair(in, c * cs + (size_t)k0 * plane + col);
         }
-        for (int pk = k0; pk <= k1; pk++) {
+        // the loads of one plane: updated potential above and in the rows
+        // beside, the extra x-neighbour of each colour, and f
+        struct Plane {
+            Pair<double> above[2], ym[2], yp[2], fv[2];
+            double ex[2];
+        };
+        auto load = [&](int pk, Plane& d) {
             const size_t here = (size_t)pk * plane + col;
-            Pair<double> above[2] = {dc_pair(in, here + plane), dc_pair(in, cs + here + plane)};
-            Pair<double> ym[2], yp[2];
             for (int c = 0; c < 2; c++) {
-                ym[c] = dc_pair(in, c * cs + here - g.hx);
-                yp[c] = dc_pair(in, c * cs + here + g.hx);
+                d.above[c] = dc_pair(in, c * cs + here + plane);
+                d.ym[c] = dc_pair(in, c * cs + here - g.hx);
+                d.yp[c] = dc_pair(in, c * cs + here + g.hx);
+                d.fv[c] = *(const Pair<double>*)(f + c * cs + here);
+                // the extra x-neighbour of colour c's points (other colour o), inside
+                // the plane (neighbouring row at the row ends)
+                const int par = (c + pj + pk + 3) & 1;
+                d.ex[c] = in((c ^ 1) * cs + (par ? here + 2 : here - 1));
             }
+        };
+        auto step = [&](int pk, const Plane& d) {
+            const size_t here = (size_t)pk * plane + col;
             for (int c = 0; c < 2; c++) {
                 const int o = c ^ 1;
                 const int par = (c + pj + pk + 3) & 1;
                 const int pi0 = 2 * h0 + par;
                 const bool a0 = pi0 >= 1, a1 = pi0 + 2 <= g.nx - 2;
-                // the extra x-neighbour stays inside the plane (neighbouring row at the row ends)
-                const double ex = in(o * cs + (par ? here + 2 : here - 1));
+                const double ex = d.ex[c];
                 double xm0, xp0, xm1, xp1;
                 if (par) {
                     xm0 = cur[o].a;
@@ -1624,17 +1638,17 @@ __global__ void __launch_bounds__(kBlock) k_dc_outer3_pair(SGrid g, DcIn<TL, UPD
                     xp1 = cur[o].b;
                 }
                 double s0 = xm0 + xp0;
-                s0 = s0 + ym[o].a;
-                s0 = s0 + yp[o].a;
+                s0 = s0 + d.ym[o].a;
+                s0 = s0 + d.yp[o].a;
                 s0 = s0 + below[o].a;
-                s0 = s0 + above[o].a;
+                s0 = s0 + d.above[o].a;
                 double s1 = xm1 + xp1;
-                s1 = s1 + ym[o].b;
-                s1 = s1 + yp[o].b;
+                s1 = s1 + d.ym[o].b;
+                s1 = s1 + d.yp[o].b;
                 s1 = s1 + below[o].b;
-                s1 = s1 + above[o].b;
+                s1 = s1 + d.above[o].b;
                 const size_t self = c * cs + here;
-                const Pair<double> fv = *(const Pair<double>*)(f + self);
+                const Pair<double> fv = d.fv[c];
                 const double v0 = fv.a - (s0 - 6.0 * cur[c].a) * inv_h2;
                 const double v1 = fv.b - (s1 - 6.0 * cur[c].b) * inv_h2;
                 Pair<TL> rl, el;
@@ -1671,8 +1685,23 @@ __global__ void __launch_bounds__(kBlock) k_dc_outer3_pair(SGrid g, DcIn<TL, UPD
             }
             for (int c = 0; c < 2; c++) {
                 below[c] = cur[c];
-                cur[c] = above[c];
+                cur[c] = d.above[c];
             }
+        };
+        int pk = k0;
+        // groups of kDcGroup planes: every load of the group is issued before its
+        // first update
+        for (; pk + kDcGroup - 1 <= k1; pk += kDcGroup) {
+            Plane d[kDcGroup];
+#pragma unroll
+            for (int q = 0; q < kDcGroup; q++) load(pk + q, d[q]);
+#pragma unroll
+            for (int q = 0; q < kDcGroup; q++) step(pk + q, d[q]);
+        }
+        for (; pk <= k1; pk++) {
+            Plane d;
+            load(pk, d);
+            step(pk, d);
         }
     }
     block_max_to(best, maxbits);
