@@ -1178,36 +1178,43 @@ __global__ void __launch_bounds__(kBlock) k_prolong3_zm(const TC* __restrict__ e
     load_plane(K0 - 1, cv[0]);
     load_plane(K0, cv[1]);
     const C w0 = (C)0.75, w1 = (C)0.25;
-    for (int K = K0; K <= K1; K++) {
-        load_plane(K + 1, cv[2]);
+    // the loads of one coarse step K: the children's positions and current
+    // values, and the coarse plane K + 1
+    struct Step {
+        C pl[3][3];
+        size_t pos8[8];
+        bool live[8];
+        TF old[8];
+    };
+    auto load = [&](int K, Step& st) {
 #pragma unroll
-        for (int dz = 0; dz < 2; dz++) {
-            const int pk = 2 * K - 1 + dz;
-            if (pk > Nf) continue;
-            const int zs = 1 + (dz ? 1 : -1);
+        for (int c8 = 0; c8 < 8; c8++) {
+            const int dz = c8 >> 2, dy = (c8 >> 1) & 1, dx = c8 & 1;
+            const int pk = 2 * K - 1 + dz, pj = 2 * J - 1 + dy, pi = 2 * I - 1 + dx;
+            const int colour = (pi + pj + pk + 3) & 1;
+            st.live[c8] = pi <= Nf && pj <= Nf && pk <= Nf && !(black_only && colour == 0);
+            st.pos8[c8] = (size_t)colour * gf.cs + row_base(gf, pj, pk) + (pi >> 1);
+            if (st.live[c8]) st.old[c8] = u[st.pos8[c8]];
+        }
+        load_plane(K + 1, st.pl);
+    };
+    auto apply = [&](const Step& st) {
 #pragma unroll
-            for (int dy = 0; dy < 2; dy++) {
-                const int pj = 2 * J - 1 + dy;
-                if (pj > Nf) continue;
-                const int ys = 1 + (dy ? 1 : -1);
-                const size_t row = row_base(gf, pj, pk);
+        for (int y = 0; y < 3; y++)
 #pragma unroll
-                for (int dx = 0; dx < 2; dx++) {
-                    const int pi = 2 * I - 1 + dx;
-                    if (pi > Nf) continue;
-                    const int colour = (pi + pj + pk + 3) & 1;
-                    if (black_only && colour == 0) continue;
-                    const int xs = 1 + (dx ? 1 : -1);
-                    C y0 = w0 * cv[1][1][1] + w1 * cv[1][1][xs];
-                    C y1 = w0 * cv[1][ys][1] + w1 * cv[1][ys][xs];
-                    C v = w0 * y0 + w1 * y1;
-                    C y2 = w0 * cv[zs][1][1] + w1 * cv[zs][1][xs];
-                    C y3 = w0 * cv[zs][ys][1] + w1 * cv[zs][ys][xs];
-                    v = w0 * v + w1 * (w0 * y2 + w1 * y3);
-                    const size_t p = (size_t)colour * gf.cs + row + (pi >> 1);
-                    u[p] = (TF)((C)u[p] + v);
-                }
-            }
+            for (int x = 0; x < 3; x++) cv[2][y][x] = st.pl[y][x];
+#pragma unroll
+        for (int c8 = 0; c8 < 8; c8++) {
+            if (!st.live[c8]) continue;
+            const int dz = c8 >> 2, dy = (c8 >> 1) & 1, dx = c8 & 1;
+            const int zs = 1 + (dz ? 1 : -1), ys = 1 + (dy ? 1 : -1), xs = 1 + (dx ? 1 : -1);
+            C y0 = w0 * cv[1][1][1] + w1 * cv[1][1][xs];
+            C y1 = w0 * cv[1][ys][1] + w1 * cv[1][ys][xs];
+            C v = w0 * y0 + w1 * y1;
+            C y2 = w0 * cv[zs][1][1] + w1 * cv[zs][1][xs];
+            C y3 = w0 * cv[zs][ys][1] + w1 * cv[zs][ys][xs];
+            v = w0 * v + w1 * (w0 * y2 + w1 * y3);
+            u[st.pos8[c8]] = (TF)((C)st.old[c8] + v);
         }
 #pragma unroll
         for (int y = 0; y < 3; y++)
@@ -1216,6 +1223,20 @@ __global__ void __launch_bounds__(kBlock) k_prolong3_zm(const TC* __restrict__ e
                 cv[0][y][x] = cv[1][y][x];
                 cv[1][y][x] = cv[2][y][x];
             }
+    };
+    // two coarse steps at a time: all loads of both before the first correction
+    int K = K0;
+    for (; K + 1 <= K1; K += 2) {
+        Step s0, s1;
+        load(K, s0);
+        load(K + 1, s1);
+        apply(s0);
+        apply(s1);
+    }
+    if (K <= K1) {
+        Step s0;
+        load(K, s0);
+        apply(s0);
     }
 }
 
@@ -1248,13 +1269,38 @@ __device__ __forceinline__ int box_size(int N)
     return D == 3 ? Q * Q * Q : Q * Q;
 }
 
+// q = a / N and a % N for 0 <= a < 2^22 through a float reciprocal (rN = 1/N,
+// loop-invariant) corrected by one step, instead of an integer division
+__device__ __forceinline__ int divmod_small(int a, int N, float rN, int& rem)
+{
+    int q = (int)((float)a * rN);
+    int r = a - q * N;
+    if (r < 0) {
+        q--;
+        r += N;
+    } else if (r >= N) {
+        q++;
+        r -= N;
+    }
+    rem = r;
+    return q;
+}
+
 template <int D>
 __device__ __forceinline__ void tail_point(int t, int N, int& i, int& j, int& k)
 {
-    i = 1 + t % N;
-    const int r = t / N;
-    j = 1 + (D == 3 ? r % N : r);
-    k = D == 3 ? 1 + r / N : 0;
+    const float rN = 1.0f / (float)N;
+    int ri;
+    const int r = divmod_small(t, N, rN, ri);
+    i = 1 + ri;
+    if (D == 3) {
+        int rj;
+        k = 1 + divmod_small(r, N, rN, rj);
+        j = 1 + rj;
+    } else {
+        j = 1 + r;
+        k = 0;
+    }
 }
 
 template <int D, typename C>
