@@ -1616,6 +1616,7 @@ __device__ __forceinline__ Pair<double> dc_pair(const DcIn<TL, UPD>& in, size_t 
     return v;
 }
 
+constexpr int kDcChunk = 4;  // planes per thread of the paired DC pass (2, 4, 8, 16, 32 measured: 4 best)
 constexpr int kDcGroup = 2;  // planes of the DC pass whose loads are issued together (1, 2, 4 measured alike)
 
 template <typename TL, bool UPD>
@@ -1634,8 +1635,8 @@ __global__ void __launch_bounds__(kBlock) k_dc_outer3_pair(SGrid g, DcIn<TL, UPD
     if (t < (long)hp_n * m) {
         const int h0 = 2 * (int)(t % hp_n);
         const int pj = 1 + (int)(t / hp_n);
-        const int k0 = 1 + zc * kNormChunk;
-        const int k1 = min(k0 + kNormChunk - 1, m);
+        const int k0 = 1 + zc * kDcChunk;
+        const int k1 = min(k0 + kDcChunk - 1, m);
         const size_t plane = (size_t)g.nx * g.hx;
         const size_t col = (size_t)pj * g.hx + h0;
         const size_t cs = g.cs;
@@ -2004,7 +2005,7 @@ void launch_dc_outer(int dim, hipStream_t st, SGrid g, const double* phi_in, con
     if (dim == 3 && g.hx % 2 == 0 && g.cs % 2 == 0) {
         long m = g.nx - 2;
         int pblocks = ceil_div((long)(g.hx / 2) * m, kBlock);
-        dim3 grid(pblocks * ceil_div(m, kNormChunk));
+        dim3 grid(pblocks * ceil_div(m, kDcChunk));
         if (upd)
             hipLaunchKernelGGL((k_dc_outer3_pair<TL, true>), grid, dim3(kBlock), 0, st, g,
                                DcIn<TL, true>{phi_in, e_in, factor}, phi_out, f, inv_h2, rscale, r, e_out, first_red,
