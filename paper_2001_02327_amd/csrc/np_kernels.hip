@@ -486,7 +486,7 @@ __global__ void __launch_bounds__(kBlock) k_norm(SGrid g, const double* __restri
 // k_smooth_fine3: a thread owns compact (h, pj), treats the red and the black
 // point of that position on every plane of its chunk, and keeps both colours'
 // values at pk-1, pk, pk+1 of its column in registers.
-constexpr int kNormChunk = 8;
+constexpr int kNormChunk = 8;  // 2, 4, 16 measured slower (more blocks, more atomics)
 
 __global__ void __launch_bounds__(kBlock) k_resid_norm3(SGrid g, const double* __restrict__ u,
                                                         const double* __restrict__ f, double inv_h2, int pblocks,
@@ -668,8 +668,10 @@ __global__ void __launch_bounds__(kBlock) k_smooth_fine(T* __restrict__ u, const
 // over the flattened (pj, h) plane fastest, so the blocks resident on one XCD
 // cover adjacent rows of the same planes and the y-neighbour rows come from
 // its L2.
-constexpr int kZChunk = 8;
-constexpr int kZGroup = 8;  // planes whose loads are issued together (divides kZChunk)
+// planes per thread on multigrid level 0 and on the coarse levels (4/4, 8/8,
+// 8/4, 4/2, 4/1 measured at 514^3: 4/4 best)
+constexpr int kZChunk0 = 4;
+constexpr int kZChunk1 = 4;
 
 // TAG 0: level 0 (ghost layer in memory); TAG 1: coarse levels, whose ghost
 // values come from the rule (GRule) where a boundary point reads them.
@@ -681,6 +683,8 @@ __global__ void __launch_bounds__(kBlock) k_smooth_zmarch3(T* __restrict__ u, co
 {
     using C = typename Compute<T>::type;
     constexpr bool RULE = TAG == 1;
+    constexpr int kZChunk = TAG == 0 ? kZChunk0 : kZChunk1;
+    constexpr int kZGroup = kZChunk;  // planes whose loads are issued together
     const int m = g.nx - 2;
     const long lb = xcd_block();
     const int zc = (int)(lb / pblocks);
@@ -806,6 +810,7 @@ __global__ void __launch_bounds__(kBlock) k_smooth_zmarch3_pair(T* __restrict__ 
     if (t >= (long)hp_n * m) return;
     const int h0 = 2 * (int)(t % hp_n);
     const int pj = 1 + (int)(t / hp_n);
+    constexpr int kZChunk = kZChunk0;
     const int k0 = 1 + zc * kZChunk;
     const int k1 = min(k0 + kZChunk - 1, m);
     const size_t plane = (size_t)g.nx * g.hx;
@@ -858,7 +863,7 @@ __global__ void __launch_bounds__(kBlock) k_smooth_zmarch3_pair(T* __restrict__ 
     auto extra = [&](int pk, size_t here) -> C { return (C)o[((colour + pj + pk + 3) & 1) ? here + 2 : here - 1]; };
     if (k1 - k0 + 1 == kZChunk) {
         // a full chunk: every load of its planes is issued before the first
-        // update, so that each wave keeps ~40 loads in flight
+        // update, so that each wave keeps ~20 loads in flight
         Pair<T> ab[kZChunk], ym[kZChunk], yp[kZChunk], fv[kZChunk];
         C ex[kZChunk];
 #pragma unroll
@@ -1877,7 +1882,7 @@ void launch_half_sweep(int dim, hipStream_t st, SGrid g, T* u, const T* f, int c
         // than k_smooth_zmarch3)
         long m = g.nx - 2;
         int pblocks = ceil_div((long)(g.hx / 2) * m, kBlock);
-        int chunks = ceil_div(m, kZChunk);
+        int chunks = ceil_div(m, kZChunk0);
         hipLaunchKernelGGL((k_smooth_zmarch3_pair<T>), dim3(pblocks * chunks), dim3(kBlock), 0, st, u, f, g, colour,
                            (C)h2, inv2d, pblocks);
         return;
@@ -1887,7 +1892,7 @@ void launch_half_sweep(int dim, hipStream_t st, SGrid g, T* u, const T* f, int c
         // coarse-level one (TAG 1) so that profiles separate them
         long m = g.nx - 2;
         int pblocks = ceil_div((long)g.hx * m, kBlock);
-        int chunks = ceil_div(m, kZChunk);
+        int chunks = ceil_div(m, fine ? kZChunk0 : kZChunk1);
         if (fine)
             hipLaunchKernelGGL((k_smooth_zmarch3<T, 0>), dim3(pblocks * chunks), dim3(kBlock), 0, st, u, f, g, colour,
                                (C)h2, inv2d, pblocks, gr);
