@@ -370,38 +370,36 @@ typedef short v4s __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 // Matrix-core convolution with the input block staged in LDS (the inference
-// path of all three layers).  A workgroup computes a 16 (x) x 4 (y) x 4 (z)
-// block of output voxels: it copies the 18 x 6 x 6 input voxels around the
-// block (zero outside the volume) into LDS once, and each of its 4 wavefronts
-// produces 4 rows of 16 voxels, taking the A operand of every tap from LDS, so
-// that an input voxel is read from memory about 2.5 times instead of 27.  The
+// path of all three layers).  A workgroup loads its weights once and then runs
+// a contiguous range of 16 (x) x 4 (y) x 4 (z) blocks of output voxels: for
+// each it copies the 18 x 6 x 6 input voxels around the block (zero outside the
+// volume) into LDS, and each of its 4 wavefronts produces 4 rows of 16 voxels,
+// taking the A operand of every tap from LDS, so that an input voxel is read
+// from memory about 2.5 times instead of 27.  The
 // K dimension of the products: CIN = 16, one tap's 16 channels per MFMA (27
 // products, in tap order); CIN = 2, (tap, channel) pairs,
 // 16 per MFMA (4 products, taps past 27 zero).  COUT = 1 pads the weight
 // columns with zeros and writes FP32; COUT = 16 writes bfloat16.
 constexpr int kCTx = 16, kCTy = 4, kCTz = 4;
+constexpr long kConvWorkgroups = 2048;
 
 template <int CIN, int COUT, typename TO>
 __global__ void __launch_bounds__(256) k_conv_mfma_lds(const uint16_t* __restrict__ in, const uint16_t* __restrict__ w,
                                                       const float* __restrict__ bias, int relu, int B, int Z, int Y,
-                                                      int X, TO* __restrict__ out)
+                                                      int X, TO* __restrict__ out, long per_block)
 {
     constexpr int SX = kCTx + 2, SY = kCTy + 2, SZ = kCTz + 2, NV = SX * SY * SZ;
     constexpr int NMF = CIN == 16 ? 27 : 4;
-    __shared__ __align__(16) uint16_t tile[NV * CIN];
+    // LDS stride per voxel in bfloat16 elements: 16 channels padded to 24 so that
+    // the 16 voxels of an A-operand read fall into different banks
+    constexpr int VS = CIN == 16 ? 24 : 2;
+    __shared__ __align__(16) uint16_t tile[NV * VS];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int row = lane & 15, kq = lane >> 4;
     const int ntx = (X + kCTx - 1) / kCTx, nty = (Y + kCTy - 1) / kCTy, ntz = (Z + kCTz - 1) / kCTz;
-    long bid = blockIdx.x;
-    const int bx = (int)(bid % ntx);
-    bid /= ntx;
-    const int by = (int)(bid % nty);
-    bid /= nty;
-    const int bz = (int)(bid % ntz);
-    const int b = (int)(bid / ntz);
-    if (b >= B) return;
-    const int x0 = bx * kCTx, y0 = by * kCTy, z0 = bz * kCTz;
-    // weights of the lane's B operand for every product
+    const long ntiles = (long)B * ntz * nty * ntx;
+    // weights of the lane's B operand for every product (once per workgroup,
+    // which then runs a contiguous range of output blocks)
     v4s bw[NMF];
 #pragma unroll
     for (int sI = 0; sI < NMF; sI++) {
@@ -418,85 +416,98 @@ __global__ void __launch_bounds__(256) k_conv_mfma_lds(const uint16_t* __restric
             bw[sI][e] = (row < COUT && t < 27) ? (short)w[(t * COUT + row) * CIN + c] : (short)0;
         }
     }
-    // stage the input block
-    for (int v = threadIdx.x; v < NV; v += 256) {
-        const int lx = v % SX, ly = (v / SX) % SY, lz = v / (SX * SY);
-        const int gx = x0 - 1 + lx, gy = y0 - 1 + ly, gz = z0 - 1 + lz;
-        const bool inside = gx >= 0 && gx < X && gy >= 0 && gy < Y && gz >= 0 && gz < Z;
-        const uint16_t* src = in + ((((long)b * Z + gz) * Y + gy) * X + gx) * CIN;
-        if (CIN == 16) {
-            uint4 q0 = make_uint4(0, 0, 0, 0), q1 = q0;
-            if (inside) {
-                q0 = ((const uint4*)src)[0];
-                q1 = ((const uint4*)src)[1];
-            }
-            ((uint4*)(tile + v * 16))[0] = q0;
-            ((uint4*)(tile + v * 16))[1] = q1;
-        } else {
-            ((uint32_t*)tile)[v] = inside ? *(const uint32_t*)src : 0u;
-        }
-    }
-    __syncthreads();
     const float bo = row < COUT ? bias[row] : 0.0f;
-    // A operand of product sI for the wave's output row it (rows of 16 voxels
-    // at (y0 + ly, z0 + lz)); rows outside the volume read zeros and are not stored
-    auto afrag = [&](int it, int sI) -> v4s {
-        const int rid = wave * 4 + it;
-        const int ly = rid % kCTy, lz = rid / kCTy;
-        if (CIN == 16) {
-            const int dz = sI / 9, dy = (sI / 3) % 3, dx = sI % 3;
-            const int lv = ((lz + dz) * SY + (ly + dy)) * SX + (row + dx);
-            return *(const v4s*)(tile + lv * 16 + 4 * kq);
+    const long first = (long)blockIdx.x * per_block;
+    const long last = first + per_block < ntiles ? first + per_block : ntiles;
+    for (long bid = first; bid < last; bid++) {
+        long rem = bid;
+        const int bx = (int)(rem % ntx);
+        rem /= ntx;
+        const int by = (int)(rem % nty);
+        rem /= nty;
+        const int bz = (int)(rem % ntz);
+        const int b = (int)(rem / ntz);
+        const int x0 = bx * kCTx, y0 = by * kCTy, z0 = bz * kCTz;
+        __syncthreads();  // the previous block's operands have been read
+        // stage the input block
+        for (int v = threadIdx.x; v < NV; v += 256) {
+            const int lx = v % SX, ly = (v / SX) % SY, lz = v / (SX * SY);
+            const int gx = x0 - 1 + lx, gy = y0 - 1 + ly, gz = z0 - 1 + lz;
+            const bool inside = gx >= 0 && gx < X && gy >= 0 && gy < Y && gz >= 0 && gz < Z;
+            const uint16_t* src = in + ((((long)b * Z + gz) * Y + gy) * X + gx) * CIN;
+            if (CIN == 16) {
+                uint4 q0 = make_uint4(0, 0, 0, 0), q1 = q0;
+                if (inside) {
+                    q0 = ((const uint4*)src)[0];
+                    q1 = ((const uint4*)src)[1];
+                }
+                ((uint4*)(tile + v * VS))[0] = q0;
+                ((uint4*)(tile + v * VS))[1] = q1;
+            } else {
+                ((uint32_t*)tile)[v] = inside ? *(const uint32_t*)src : 0u;
+            }
         }
-        short e4[4] = {0, 0, 0, 0};
-#pragma unroll
-        for (int h = 0; h < 2; h++) {
-            const int t = 8 * sI + 2 * kq + h;
-            if (t < 27) {
-                const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;
+        __syncthreads();
+        // A operand of product sI for the wave's output row it (rows of 16 voxels
+        // at (y0 + ly, z0 + lz)); rows outside the volume read zeros and are not stored
+        auto afrag = [&](int it, int sI) -> v4s {
+            const int rid = wave * 4 + it;
+            const int ly = rid % kCTy, lz = rid / kCTy;
+            if (CIN == 16) {
+                const int dz = sI / 9, dy = (sI / 3) % 3, dx = sI % 3;
                 const int lv = ((lz + dz) * SY + (ly + dy)) * SX + (row + dx);
-                const uint32_t pr = ((const uint32_t*)tile)[lv];
-                e4[2 * h] = (short)(pr & 0xffffu);
-                e4[2 * h + 1] = (short)(pr >> 16);
+                return *(const v4s*)(tile + lv * VS + 4 * kq);
             }
-        }
-        return v4s{e4[0], e4[1], e4[2], e4[3]};
-    };
-    auto store = [&](int it, const v4f& acc) {
-        const int rid = wave * 4 + it;
-        const int y = y0 + rid % kCTy, z = z0 + rid / kCTy;
-        if (y >= Y || z >= Z) return;
-        // lane holds D[voxels 4 kq .. 4 kq + 3][channel row]
-        const long base = (((long)b * Z + z) * Y + y) * X;
-        for (int q = 0; q < 4; q++) {
-            const int x = x0 + 4 * kq + q;
-            if (x >= X || row >= COUT) continue;
-            float v = acc[q] + bo;
-            if (relu) v = fmaxf(v, 0.0f);
-            st(out + (base + x) * COUT + row, v);
-        }
-    };
-    // two rows at a time on two independent accumulation chains; the A
-    // operands of a plane of taps (9 products) are read before its products
-    for (int p = 0; p < 4; p += 2) {
-        v4f acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = acc0;
-        constexpr int G = CIN == 16 ? 9 : NMF;
-#pragma unroll
-        for (int g0 = 0; g0 < NMF; g0 += G) {
-            v4s a0[G], a1[G];
-#pragma unroll
-            for (int q = 0; q < G; q++) {
-                a0[q] = afrag(p, g0 + q);
-                a1[q] = afrag(p + 1, g0 + q);
+            short e4[4] = {0, 0, 0, 0};
+    #pragma unroll
+            for (int h = 0; h < 2; h++) {
+                const int t = 8 * sI + 2 * kq + h;
+                if (t < 27) {
+                    const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;
+                    const int lv = ((lz + dz) * SY + (ly + dy)) * SX + (row + dx);
+                    const uint32_t pr = ((const uint32_t*)tile)[lv];
+                    e4[2 * h] = (short)(pr & 0xffffu);
+                    e4[2 * h + 1] = (short)(pr >> 16);
+                }
             }
-#pragma unroll
-            for (int q = 0; q < G; q++) {
-                acc0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0[q], bw[g0 + q], acc0, 0, 0, 0);
-                acc1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1[q], bw[g0 + q], acc1, 0, 0, 0);
+            return v4s{e4[0], e4[1], e4[2], e4[3]};
+        };
+        auto store = [&](int it, const v4f& acc) {
+            const int rid = wave * 4 + it;
+            const int y = y0 + rid % kCTy, z = z0 + rid / kCTy;
+            if (y >= Y || z >= Z) return;
+            // lane holds D[voxels 4 kq .. 4 kq + 3][channel row]
+            const long base = (((long)b * Z + z) * Y + y) * X;
+            for (int q = 0; q < 4; q++) {
+                const int x = x0 + 4 * kq + q;
+                if (x >= X || row >= COUT) continue;
+                float v = acc[q] + bo;
+                if (relu) v = fmaxf(v, 0.0f);
+                st(out + (base + x) * COUT + row, v);
             }
+        };
+        // two rows at a time on two independent accumulation chains; the A
+        // operands of a plane of taps (9 products) are read before its products
+        for (int p = 0; p < 4; p += 2) {
+            v4f acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = acc0;
+            constexpr int G = CIN == 16 ? 9 : NMF;
+    #pragma unroll
+            for (int g0 = 0; g0 < NMF; g0 += G) {
+                v4s a0[G], a1[G];
+    #pragma unroll
+                for (int q = 0; q < G; q++) {
+                    a0[q] = afrag(p, g0 + q);
+                    a1[q] = afrag(p + 1, g0 + q);
+                }
+    #pragma unroll
+                for (int q = 0; q < G; q++) {
+                    acc0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0[q], bw[g0 + q], acc0, 0, 0, 0);
+                    acc1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1[q], bw[g0 + q], acc1, 0, 0, 0);
+                }
+            }
+            store(p, acc0);
+            store(p + 1, acc1);
         }
-        store(p, acc0);
-        store(p + 1, acc1);
     }
 }
 
@@ -607,17 +618,19 @@ void net_conv_fwd_bf16_to_f32(hipStream_t st, const uint16_t* in, int cin, const
 void net_conv_mfma(hipStream_t st, const uint16_t* in, int cin, const uint16_t* w, const float* bias, int cout, int relu,
                    int B, int Z, int Y, int X, void* out)
 {
-    const long blocks = (long)B * ((Z + kCTz - 1) / kCTz) * ((Y + kCTy - 1) / kCTy) * ((X + kCTx - 1) / kCTx);
-    const dim3 grid((unsigned)blocks);
+    const long tiles = (long)B * ((Z + kCTz - 1) / kCTz) * ((Y + kCTy - 1) / kCTy) * ((X + kCTx - 1) / kCTx);
+    // persistent workgroups, each over a contiguous range of output blocks
+    const long per = (tiles + kConvWorkgroups - 1) / kConvWorkgroups;
+    const dim3 grid((unsigned)((tiles + per - 1) / per));
     if (cin == 16 && cout == 16)
         hipLaunchKernelGGL((k_conv_mfma_lds<16, 16, uint16_t>), grid, dim3(256), 0, st, in, w, bias, relu, B, Z, Y, X,
-                           (uint16_t*)out);
+                           (uint16_t*)out, per);
     else if (cin == 2 && cout == 16)
         hipLaunchKernelGGL((k_conv_mfma_lds<2, 16, uint16_t>), grid, dim3(256), 0, st, in, w, bias, relu, B, Z, Y, X,
-                           (uint16_t*)out);
+                           (uint16_t*)out, per);
     else if (cin == 16 && cout == 1)
         hipLaunchKernelGGL((k_conv_mfma_lds<16, 1, float>), grid, dim3(256), 0, st, in, w, bias, relu, B, Z, Y, X,
-                           (float*)out);
+                           (float*)out, per);
 }
 
 void net_conv_bwd_data(hipStream_t st, const float* gout, int cout, const uint16_t* w, int cin, int B, int Z, int Y,
