@@ -812,6 +812,37 @@ __global__ void __launch_bounds__(kBlock) k_half_sweep(T* __restrict__ u, const 
     half_sweep_body<D, T, true>(u, f, g, colour, h2, inv2d, gr);
 }
 
+// FP32 sums of FP16 halves of packed 32-bit words in one v_fma_mix_f32 each
+// (h * 1.0 + s with the FP16 operand converted exactly inside the instruction):
+// the same single rounding as a conversion followed by an FP32 add, one
+// instruction instead of two.  H selects the low (0) or high (1) half.
+template <int H>
+__device__ __forceinline__ float mix_add(float s, uint32_t w)
+{
+    float r;
+    if constexpr (H == 0)
+        asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel_hi:[1,0,0]" : "=v"(r) : "v"(w), "v"(s));
+    else
+        asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "=v"(r) : "v"(w), "v"(s));
+    return r;
+}
+
+// half HA of a plus half HB of b, both FP16, summed in FP32
+template <int HA, int HB>
+__device__ __forceinline__ float mix_add2(uint32_t a, uint32_t b)
+{
+    float r;
+    if constexpr (HA == 0 && HB == 1)
+        asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel:[0,0,1] op_sel_hi:[1,0,1]" : "=v"(r) : "v"(a), "v"(b));
+    else if constexpr (HA == 1 && HB == 0)
+        asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,1]" : "=v"(r) : "v"(a), "v"(b));
+    else if constexpr (HA == 0 && HB == 0)
+        asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel_hi:[1,0,1]" : "=v"(r) : "v"(a), "v"(b));
+    else
+        asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel:[1,0,1] op_sel_hi:[1,0,1]" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
 // Paired form of the level-0 z-march for 2- and 4-byte storage: a thread owns
 // the two compact points h0 = 2 hp and h0 + 1 of a row and moves them with
 // one 2-element load or store; the extra x-neighbour (h0 - 1 or h0 + 2) is a
@@ -831,12 +862,12 @@ __global__ void __launch_bounds__(kBlock) k_smooth_zmarch3_pair(T* __restrict__ 
     using C = typename Compute<T>::type;
     const int m = g.nx - 2;
     const int hp_n = g.hx >> 1;
-    const long lb = xcd_block();
-    const int zc = (int)(lb / pblocks);
-    const long t = (lb - (long)zc * pblocks) * kBlock + threadIdx.x;
-    if (t >= (long)hp_n * m) return;
-    const int h0 = 2 * (int)(t % hp_n);
-    const int pj = 1 + (int)(t / hp_n);
+    const int lb = (int)xcd_block();
+    const int zc = lb / pblocks;
+    const int t = (lb - zc * pblocks) * kBlock + (int)threadIdx.x;
+    if (t >= hp_n * m) return;
+    const int h0 = 2 * (t % hp_n);
+    const int pj = 1 + t / hp_n;
     constexpr int kZChunk = kZChunk0;
     const int k0 = 1 + zc * kZChunk;
     const int k1 = min(k0 + kZChunk - 1, m);
@@ -847,7 +878,8 @@ __global__ void __launch_bounds__(kBlock) k_smooth_zmarch3_pair(T* __restrict__ 
     const T* __restrict__ fc = f + (size_t)colour * g.cs;
     Pair<T> below = *(const Pair<T>*)(o + (size_t)(k0 - 1) * plane + col);
     Pair<T> cur = *(const Pair<T>*)(o + (size_t)k0 * plane + col);
-    auto step = [&](int pk, const Pair<T>& above, const Pair<T>& ym, const Pair<T>& yp, const Pair<T>& fv, C ex) {
+    auto step = [&](int pk, const Pair<T>& above, const Pair<T>& ym, const Pair<T>& yp, const Pair<T>& fv, T exh) {
+        const C ex = (C)exh;
         const size_t here = (size_t)pk * plane + col;
         const int par = (colour + pj + pk + 3) & 1;
         C xm0, xp0, xm1, xp1;
@@ -862,16 +894,36 @@ __global__ void __launch_bounds__(kBlock) k_smooth_zmarch3_pair(T* __restrict__ 
             xm1 = (C)cur.a;
             xp1 = (C)cur.b;
         }
-        C s0 = xm0 + xp0;
-        s0 = s0 + (C)ym.a;
-        s0 = s0 + (C)yp.a;
-        s0 = s0 + (C)below.a;
-        s0 = s0 + (C)above.a;
-        C s1 = xm1 + xp1;
-        s1 = s1 + (C)ym.b;
-        s1 = s1 + (C)yp.b;
-        s1 = s1 + (C)below.b;
-        s1 = s1 + (C)above.b;
+        C s0, s1;
+        if constexpr (sizeof(T) == 2) {
+            // the same sums on the packed FP16 words: x-neighbours are the
+            // point's compact partner and the extra value (one rounding each)
+            const uint32_t c = __builtin_bit_cast(uint32_t, cur);
+            const uint32_t xw = __builtin_bit_cast(uint16_t, exh);
+            s0 = mix_add2<0, 1>(c, par ? c : (xw << 16));  // a + (par ? b : extra)
+            s1 = mix_add2<1, 0>(c, par ? xw : c);          // b + (par ? extra : a)
+            const uint32_t wym = __builtin_bit_cast(uint32_t, ym), wyp = __builtin_bit_cast(uint32_t, yp);
+            const uint32_t wbl = __builtin_bit_cast(uint32_t, below), wab = __builtin_bit_cast(uint32_t, above);
+            s0 = mix_add<0>(s0, wym);
+            s0 = mix_add<0>(s0, wyp);
+            s0 = mix_add<0>(s0, wbl);
+            s0 = mix_add<0>(s0, wab);
+            s1 = mix_add<1>(s1, wym);
+            s1 = mix_add<1>(s1, wyp);
+            s1 = mix_add<1>(s1, wbl);
+            s1 = mix_add<1>(s1, wab);
+        } else {
+            s0 = xm0 + xp0;
+            s0 = s0 + (C)ym.a;
+            s0 = s0 + (C)yp.a;
+            s0 = s0 + (C)below.a;
+            s0 = s0 + (C)above.a;
+            s1 = xm1 + xp1;
+            s1 = s1 + (C)ym.b;
+            s1 = s1 + (C)yp.b;
+            s1 = s1 + (C)below.b;
+            s1 = s1 + (C)above.b;
+        }
         Pair<T> r;
         r.a = (T)((s0 - h2 * (C)fv.a) * inv2d);
         r.b = (T)((s1 - h2 * (C)fv.b) * inv2d);
@@ -887,12 +939,12 @@ __global__ void __launch_bounds__(kBlock) k_smooth_zmarch3_pair(T* __restrict__ 
         cur = above;
     };
     // the extra x-neighbour stays inside the plane (neighbouring row at the row ends)
-    auto extra = [&](int pk, size_t here) -> C { return (C)o[((colour + pj + pk + 3) & 1) ? here + 2 : here - 1]; };
+    auto extra = [&](int pk, size_t here) -> T { return o[((colour + pj + pk + 3) & 1) ? here + 2 : here - 1]; };
     if (k1 - k0 + 1 == kZChunk) {
         // a full chunk: every load of its planes is issued before the first
         // update, so that each wave keeps ~20 loads in flight
         Pair<T> ab[kZChunk], ym[kZChunk], yp[kZChunk], fv[kZChunk];
-        C ex[kZChunk];
+        T ex[kZChunk];
 #pragma unroll
         for (int q = 0; q < kZChunk; q++) {
             const size_t here = (size_t)(k0 + q) * plane + col;
@@ -1057,6 +1109,98 @@ __global__ void __launch_bounds__(kBlock) k_restrict3_zm(const TF* __restrict__ 
                     s = s + yp;
                     s = s + zm;
                     s = s + zp;
+                    sum += fv[dz][dy][dx] - (s - (C)6 * uc) * inv_h2;
+                }
+            }
+        }
+        const size_t q = pos<3, TC>(gc, I, J, K);
+        fc[q] = (TC)(sum * ((C)0.125 * out_scale));
+        ec[q] = (TC)0;
+#pragma unroll
+        for (int r = 0; r < 2; r++)
+#pragma unroll
+            for (int c = 0; c < 2; c++) pc[r][c] = p2[1 + r][1 + c];
+#pragma unroll
+        for (int r = 0; r < 4; r++)
+#pragma unroll
+            for (int c = 0; c < 4; c++) p1[r][c] = p3[r][c];
+    }
+}
+
+// Residual and restriction out of multigrid level 0 (ghost layer in memory),
+// the z-march of k_restrict3_zm (thread per coarse column (I, J), a chunk of
+// coarse planes, the 12-point cross of each fine plane loaded once) with every
+// address split into a uniform part and one per-lane offset: the fine points a
+// thread reads are (2I - 2 + c, 2J - 2 + r, k), whose colour
+// (c + r + k + 1) & 1 and in-plane offset r hx + (c >> 1) beyond the lane's
+// base (2J - 2) hx + I - 1 are the same for every lane of the block (the chunk,
+// hence k, is uniform).  So each load is a scalar pointer plus the lane's fixed
+// byte offset, with no per-load address arithmetic.  Same arithmetic in the
+// same order as k_restrict3_zm.  Requires N_f = 2 N_c (every child active) and
+// arrays of fewer than 2^31 bytes.
+template <typename TF, typename TC>
+__global__ void __launch_bounds__(kBlock) k_restrict3_l0(const TF* __restrict__ u, const TF* __restrict__ f, SGrid gf,
+                                                          typename Compute<TC>::type inv_h2,
+                                                          typename Compute<TC>::type out_scale, SGrid gc,
+                                                          TC* __restrict__ fc, TC* __restrict__ ec, int pblocks, int kch)
+{
+    using C = typename Compute<TC>::type;
+    const int Nc = gc.nx - 2;
+    const int lb = (int)xcd_block();
+    const int zc = lb / pblocks;
+    const int t = (lb - zc * pblocks) * kBlock + (int)threadIdx.x;
+    if (t >= Nc * Nc) return;
+    const int I = 1 + t % Nc, J = 1 + t / Nc;
+    const int K0 = 1 + zc * kch;
+    const int K1 = min(K0 + kch - 1, Nc);
+    const unsigned boff = (unsigned)(((2 * J - 2) * gf.hx + (I - 1)) * (int)sizeof(TF));
+    const size_t fplane = (size_t)gf.nx * gf.hx;
+    // value at (2I - 2 + c, 2J - 2 + r, k) of array a
+    auto ld = [&](const TF* __restrict__ a, int c, int r, int k) -> C {
+        const TF* p = a + (size_t)k * fplane + (((c + r + k + 1) & 1) ? gf.cs : 0) + (size_t)r * gf.hx + (c >> 1);
+        return (C) * (const TF*)((const char*)p + boff);
+    };
+    // cross of fine plane k: P[r][c] = u(2I-2+c, 2J-2+r, k); the corners are not loaded
+    auto load_cross = [&](int k, C (&P)[4][4]) {
+#pragma unroll
+        for (int r = 0; r < 4; r++)
+#pragma unroll
+            for (int c = 0; c < 4; c++) {
+                if ((r == 0 || r == 3) && (c == 0 || c == 3)) continue;
+                P[r][c] = ld(u, c, r, k);
+            }
+    };
+    C pc[2][2];  // centres of the plane below the current pair
+#pragma unroll
+    for (int r = 0; r < 2; r++)
+#pragma unroll
+        for (int c = 0; c < 2; c++) pc[r][c] = ld(u, 1 + c, 1 + r, 2 * K0 - 2);
+    C p1[4][4], p2[4][4], p3[4][4];
+    load_cross(2 * K0 - 1, p1);
+    for (int K = K0; K <= K1; K++) {
+        load_cross(2 * K, p2);
+        load_cross(2 * K + 1, p3);
+        C fv[2][2][2];
+#pragma unroll
+        for (int dz = 0; dz < 2; dz++)
+#pragma unroll
+            for (int dy = 0; dy < 2; dy++)
+#pragma unroll
+                for (int dx = 0; dx < 2; dx++) fv[dz][dy][dx] = ld(f, 1 + dx, 1 + dy, 2 * K - 1 + dz);
+        C sum = 0;
+#pragma unroll
+        for (int dz = 0; dz < 2; dz++) {
+#pragma unroll
+            for (int dy = 0; dy < 2; dy++) {
+#pragma unroll
+                for (int dx = 0; dx < 2; dx++) {
+                    const C(&P)[4][4] = dz ? p2 : p1;
+                    const C uc = P[1 + dy][1 + dx];
+                    C s = P[1 + dy][dx] + P[1 + dy][2 + dx];
+                    s = s + P[dy][1 + dx];
+                    s = s + P[2 + dy][1 + dx];
+                    s = s + (dz ? p1[1 + dy][1 + dx] : pc[dy][dx]);
+                    s = s + (dz ? p3[1 + dy][1 + dx] : p2[1 + dy][1 + dx]);
                     sum += fv[dz][dy][dx] - (s - (C)6 * uc) * inv_h2;
                 }
             }
@@ -1269,6 +1413,141 @@ __global__ void __launch_bounds__(kBlock) k_prolong3_zm(const TC* __restrict__ e
         Step s0;
         load(K, s0);
         apply(s0);
+    }
+}
+
+// Prolongation into the black points of multigrid level 0 (the red ones are
+// left alone: a red half sweep that reads only black values follows), paired
+// form: a thread owns the compact pair (h0, h0 + 1) of one fine row pj and a
+// chunk of coarse planes.  The two black points of the pair in any fine plane
+// have their x parents and neighbours among the coarse columns h0 .. h0 + 2,
+// and every fine point of row pj has the same y parent and neighbour, so a
+// coarse plane contributes 2 x 3 values (rule applied where they are ghosts).
+// Per coarse plane and row the four x-interpolants the pair can need are
+// formed once (which column is parent and which neighbour depends only on the
+// parity of the fine plane); each coarse plane K then corrects the pair in
+// fine planes 2K - 1 and 2K with one paired load and store each.  Per point
+// the arithmetic is that of k_prolong3_zm (same products, same order).  The
+// chunk's plane index is uniform over the block, so plane bases are scalar and
+// each lane keeps fixed 32-bit offsets inside a plane.  Requires an even row
+// length hx and arrays of fewer than 2^31 elements.
+constexpr int kProlongPairChunk = 4;
+
+template <typename TC, typename TF, int KCH>
+__global__ void __launch_bounds__(kBlock) k_prolong3_pair(const TC* __restrict__ e, SGrid gc, TF* __restrict__ u,
+                                                           SGrid gf, GRule<typename Compute<TC>::type> gr, int pblocks)
+{
+    using C = typename Compute<TC>::type;
+    const int Nc = gc.nx - 2, Nf = gf.nx - 2;
+    const int Mq = (Nf + 1) >> 1;  // coarse parents per axis
+    const int hp_n = gf.hx >> 1;
+    const int lb = (int)xcd_block();
+    const int zc = lb / pblocks;
+    const int t = (lb - zc * pblocks) * kBlock + (int)threadIdx.x;
+    if (t >= hp_n * Nf) return;
+    const int h0 = 2 * (t % hp_n);
+    const int pj = 1 + t / hp_n;
+    const int K0 = 1 + zc * KCH;
+    const int nk = min(KCH, Mq - K0 + 1);
+    const int qj = (pj + 1) >> 1, sj = (pj & 1) ? -1 : 1;
+    const AxisNb<C> my[2] = {axis_nb_clamped(qj, Nc, gr), axis_nb_clamped(qj + sj, Nc, gr)};
+    AxisNb<C> mx[3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) mx[a] = axis_nb_clamped(h0 + a, Nc, gr);
+    const bool edge = my[0].ghost || my[1].ghost || mx[0].ghost || mx[2].ghost;
+    // offsets inside a coarse plane of slot (y, x) for an even / odd plane index
+    // (the colour of a coarse point flips with the plane's parity)
+    unsigned off[2][2][3];
+#pragma unroll
+    for (int y = 0; y < 2; y++)
+#pragma unroll
+        for (int x = 0; x < 3; x++) {
+            const unsigned o = (unsigned)(my[y].q * gc.hx + (mx[x].q >> 1));
+            const int c0 = (mx[x].q + my[y].q + 3) & 1;  // colour on an even plane
+            off[0][y][x] = o + (c0 ? (unsigned)gc.cs : 0u);
+            off[1][y][x] = o + (c0 ? 0u : (unsigned)gc.cs);
+        }
+    const size_t cplane = (size_t)gc.nx * gc.hx;
+    const C w0 = (C)0.75, w1 = (C)0.25;
+    // par0: parity term of the black points in the odd fine plane 2K - 1
+    // (pi = 2 h + par); the even plane 2K has the other one
+    const bool par0 = ((pj + 1) & 1) != 0;
+    // X[z][d][b][y]: x-interpolant of coarse plane K0 - 1 + z, row y, for the
+    // pair point b in the fine plane of parity d (0: 2K - 1, 1: 2K)
+    C X[KCH + 2][2][2][2];
+#pragma unroll
+    for (int z = 0; z < KCH + 2; z++) {
+        if (z <= nk + 1) {
+            const AxisNb<C> mz = axis_nb_clamped(K0 - 1 + z, Nc, gr);
+            const TC* __restrict__ ep = e + (size_t)mz.q * cplane;
+            C cv[2][3];
+#pragma unroll
+            for (int y = 0; y < 2; y++)
+#pragma unroll
+                for (int x = 0; x < 3; x++) cv[y][x] = (C)ep[(mz.q & 1) ? off[1][y][x] : off[0][y][x]];
+            if (edge || mz.ghost) {
+#pragma unroll
+                for (int y = 0; y < 2; y++)
+#pragma unroll
+                    for (int x = 0; x < 3; x++) {
+                        C v = cv[y][x];
+                        if (mx[x].ghost) v = mx[x].fac * v;
+                        if (my[y].ghost) v = my[y].fac * v;
+                        if (mz.ghost) v = mz.fac * v;
+                        cv[y][x] = v;
+                    }
+            }
+#pragma unroll
+            for (int y = 0; y < 2; y++) {
+                // par = 1: point 0 has parent column 1 and neighbour 0, point 1
+                // parent 2 and neighbour 1; par = 0: (0, 1) and (1, 2)
+                const C A = par0 ? cv[y][1] : cv[y][0], B = par0 ? cv[y][0] : cv[y][1];
+                const C P = par0 ? cv[y][2] : cv[y][1], Q = par0 ? cv[y][1] : cv[y][2];
+                X[z][0][0][y] = w0 * A + w1 * B;
+                X[z][1][0][y] = w0 * B + w1 * A;
+                X[z][0][1][y] = w0 * P + w1 * Q;
+                X[z][1][1][y] = w0 * Q + w1 * P;
+            }
+        }
+    }
+    const size_t fplane = (size_t)gf.nx * gf.hx;
+    const unsigned row = (unsigned)(pj * gf.hx + h0);
+    TF* __restrict__ ub = u + gf.cs;  // black colour array
+    Pair<TF> old[KCH][2];
+#pragma unroll
+    for (int z = 0; z < KCH; z++)
+#pragma unroll
+        for (int d = 0; d < 2; d++) {
+            const int pk = 2 * (K0 + z) - 1 + d;
+            if (z < nk && pk <= Nf) old[z][d] = *(const Pair<TF>*)(ub + (size_t)pk * fplane + row);
+        }
+#pragma unroll
+    for (int z = 0; z < KCH; z++) {
+#pragma unroll
+        for (int d = 0; d < 2; d++) {
+            const int pk = 2 * (K0 + z) - 1 + d;
+            if (z >= nk || pk > Nf) continue;
+            const int zs = d ? z + 2 : z;  // the z neighbour: plane K + 1 or K - 1
+            C r[2];
+#pragma unroll
+            for (int b = 0; b < 2; b++) {
+                C v = w0 * X[z + 1][d][b][0] + w1 * X[z + 1][d][b][1];
+                r[b] = w0 * v + w1 * (w0 * X[zs][d][b][0] + w1 * X[zs][d][b][1]);
+            }
+            const Pair<TF> o = old[z][d];
+            Pair<TF> nv;
+            nv.a = (TF)((C)o.a + r[0]);
+            nv.b = (TF)((C)o.b + r[1]);
+            const int pi0 = 2 * h0 + (d ? !par0 : par0);
+            const bool a0 = pi0 >= 1, a1 = pi0 + 2 <= Nf;
+            TF* q = ub + (size_t)pk * fplane + row;
+            if (a0 && a1) {
+                *(Pair<TF>*)q = nv;
+            } else {
+                if (a0) q[0] = nv.a;
+                if (a1) q[1] = nv.b;
+            }
+        }
     }
 }
 
@@ -1953,6 +2232,12 @@ void launch_resid_restrict(int dim, hipStream_t st, SGrid gf, const TF* u, const
         const int kch = Nc >= 128 ? 4 : 1;
         const int pblocks = ceil_div(Nc * Nc, kBlock);
         const dim3 zgrid(pblocks * ceil_div(Nc, kch));
+        if (!rule && gf.nx - 2 == 2 * Nc && 2 * gf.cs * sizeof(TF) < (1ull << 31)) {
+            // multigrid level 0: uniform addressing
+            hipLaunchKernelGGL((k_restrict3_l0<TF, TC>), zgrid, dim3(kBlock), 0, st, u, f, gf, (C)inv_h2, (C)out_scale,
+                               gc, fc, ec, pblocks, kch);
+            return;
+        }
         if (rule)
             hipLaunchKernelGGL((k_restrict3_zm<TF, TC, true>), zgrid, dim3(kBlock), 0, st, u, f, gf, (C)inv_h2,
                                (C)out_scale, gc, fc, ec, gr, pblocks, kch);
@@ -1976,6 +2261,15 @@ void launch_prolong_add(int dim, hipStream_t st, SGrid gc, const TC* ec, SGrid g
     using C = typename Compute<TC>::type;
     const GRule<C> gr{xn1, (C)coef};
     dim3 grid(ceil_div(ncompact_active(dim, gf), kBlock));
+    if (dim == 3 && black_only && (gf.hx % 2) == 0 && 2 * gf.cs < (1ull << 31) && 2 * gc.cs < (1ull << 31)) {
+        // paired form: one paired load and store per fine plane and pair
+        const long Mq = (gf.nx - 1) / 2;
+        const int pblocks = ceil_div((long)(gf.hx / 2) * (gf.nx - 2), kBlock);
+        const int chunks = ceil_div(Mq, kProlongPairChunk);
+        hipLaunchKernelGGL((k_prolong3_pair<TC, TF, kProlongPairChunk>), dim3(pblocks * chunks), dim3(kBlock), 0, st,
+                           ec, gc, u, gf, gr, pblocks);
+        return;
+    }
     if (dim == 3) {
         const long Mq = (gf.nx - 1) / 2;  // ceil(N_f / 2) coarse parents per axis
         // 8 coarse planes per thread on large grids, 2 on small ones (there the
