@@ -47,20 +47,14 @@ inline Strip make_strip(int nxa, int nya, int nza, int nstrip)
     return s;
 }
 
-inline long strip_blocks(const Strip& s)
-{
-    long nstrip = (s.nya + s.R - 1) / s.R;
-    return nstrip * s.nza * s.B;
-}
-
 __device__ __forceinline__ bool strip_point(const Strip& s, int& x, int& y, int& z)
 {
-    const long lb = xcd_block();
-    const long per = (long)s.nza * s.B;
-    const int st = (int)(lb / per);
-    const long rem = lb - st * per;
-    z = (int)(rem / s.B);
-    const int blk = (int)(rem - (long)z * s.B);
+    const int lb = (int)xcd_block();
+    const int per = s.nza * s.B;
+    const int st = lb / per;
+    const int rem = lb - st * per;
+    z = rem / s.B;
+    const int blk = rem - z * s.B;
     const int tin = blk * kBlock + threadIdx.x;
     const int rr = tin / s.nxa;
     x = tin - rr * s.nxa;
@@ -233,9 +227,9 @@ __global__ void __launch_bounds__(kBlock) k_interface_fill3_zm(SGrid gc, const d
                                                                int pblocks)
 {
     const int Mq = (gf.nx + 1) / 2;  // parents per axis: fine padded points 0 .. nf + 3 in pairs
-    const long lb = xcd_block();
-    const int zc = (int)(lb / pblocks);
-    const long t = (lb - (long)zc * pblocks) * kBlock + threadIdx.x;
+    const int lb = (int)xcd_block();
+    const int zc = lb / pblocks;
+    const int t = (lb - zc * pblocks) * kBlock + (int)threadIdx.x;
     if (t >= (long)Mq * Mq) return;
     const int a = (int)(t % Mq), b = (int)(t / Mq);
     const int c0 = zc * kFillChunk, c1 = min(c0 + kFillChunk, Mq) - 1;
@@ -357,9 +351,9 @@ __global__ void __launch_bounds__(kBlock) k_forces3_zm(SGrid g, int n, double m1
     constexpr int R = kForceRows;
     constexpr int KC = kForceChunk;
     const int nrb = (n + R - 1) / R;
-    const long lb = xcd_block();
-    const int zc = (int)(lb / pblocks);
-    const long t = (lb - (long)zc * pblocks) * kBlock + threadIdx.x;
+    const int lb = (int)xcd_block();
+    const int zc = lb / pblocks;
+    const int t = (lb - zc * pblocks) * kBlock + (int)threadIdx.x;
     if (t >= (long)n * nrb) return;
     const int i = (int)(t % n), j0 = R * (int)(t / n);
     const int k0 = zc * KC;
@@ -520,9 +514,9 @@ __global__ void __launch_bounds__(kBlock) k_resid_norm3(SGrid g, const double* _
                                                         unsigned long long* maxbits)
 {
     const int m = g.nx - 2;
-    const long lb = xcd_block();
-    const int zc = (int)(lb / pblocks);
-    const long t = (lb - (long)zc * pblocks) * kBlock + threadIdx.x;
+    const int lb = (int)xcd_block();
+    const int zc = lb / pblocks;
+    const int t = (lb - zc * pblocks) * kBlock + (int)threadIdx.x;
     unsigned long long best = 0;
     if (t < (long)g.hx * m) {
         const int h = (int)(t % g.hx);
@@ -713,9 +707,9 @@ __global__ void __launch_bounds__(kBlock) k_smooth_zmarch3(T* __restrict__ u, co
     constexpr int kZChunk = TAG == 0 ? kZChunk0 : kZChunk1;
     constexpr int kZGroup = kZChunk;  // planes whose loads are issued together
     const int m = g.nx - 2;
-    const long lb = xcd_block();
-    const int zc = (int)(lb / pblocks);
-    const long t = (lb - (long)zc * pblocks) * kBlock + threadIdx.x;
+    const int lb = (int)xcd_block();
+    const int zc = lb / pblocks;
+    const int t = (lb - zc * pblocks) * kBlock + (int)threadIdx.x;
     if (t >= (long)g.hx * m) return;
     const int h = (int)(t % g.hx);
     const int pj = 1 + (int)(t / g.hx);
@@ -1037,9 +1031,9 @@ __global__ void __launch_bounds__(kBlock) k_restrict3_zm(const TF* __restrict__ 
 {
     using C = typename Compute<TC>::type;
     const int Nc = gc.nx - 2, Nf = gf.nx - 2;
-    const long lb = xcd_block();
-    const int zc = (int)(lb / pblocks);
-    const long t = (lb - (long)zc * pblocks) * kBlock + threadIdx.x;
+    const int lb = (int)xcd_block();
+    const int zc = lb / pblocks;
+    const int t = (lb - zc * pblocks) * kBlock + (int)threadIdx.x;
     if (t >= (long)Nc * Nc) return;
     const int I = 1 + (int)(t % Nc), J = 1 + (int)(t / Nc);
     const int K0 = 1 + zc * kch;
@@ -1324,9 +1318,9 @@ __global__ void __launch_bounds__(kBlock) k_prolong3_zm(const TC* __restrict__ e
     using C = typename Compute<TC>::type;
     const int Nc = gc.nx - 2, Nf = gf.nx - 2;
     const int Mq = (Nf + 1) >> 1;  // coarse parents per axis
-    const long lb = xcd_block();
-    const int zc = (int)(lb / pblocks);
-    const long t = (lb - (long)zc * pblocks) * kBlock + threadIdx.x;
+    const int lb = (int)xcd_block();
+    const int zc = lb / pblocks;
+    const int t = (lb - zc * pblocks) * kBlock + (int)threadIdx.x;
     if (t >= (long)Mq * Mq) return;
     const int I = 1 + (int)(t % Mq), J = 1 + (int)(t / Mq);
     const int K0 = 1 + zc * kch;
@@ -1861,9 +1855,9 @@ __global__ void __launch_bounds__(kBlock) k_dc_outer3(SGrid g, DcIn<TL, UPD> in,
                                                       unsigned long long* maxbits)
 {
     const int m = g.nx - 2;
-    const long lb = xcd_block();
-    const int zc = (int)(lb / pblocks);
-    const long t = (lb - (long)zc * pblocks) * kBlock + threadIdx.x;
+    const int lb = (int)xcd_block();
+    const int zc = lb / pblocks;
+    const int t = (lb - zc * pblocks) * kBlock + (int)threadIdx.x;
     unsigned long long best = 0;
     if (t < (long)g.hx * m) {
         const int h = (int)(t % g.hx);
@@ -1939,13 +1933,13 @@ __global__ void __launch_bounds__(kBlock) k_dc_outer3_pair(SGrid g, DcIn<TL, UPD
 {
     const int m = g.nx - 2;
     const int hp_n = g.hx >> 1;
-    const long lb = xcd_block();
-    const int zc = (int)(lb / pblocks);
-    const long t = (lb - (long)zc * pblocks) * kBlock + threadIdx.x;
+    const int lb = (int)xcd_block();
+    const int zc = lb / pblocks;
+    const int t = (lb - zc * pblocks) * kBlock + (int)threadIdx.x;
     unsigned long long best = 0;
-    if (t < (long)hp_n * m) {
-        const int h0 = 2 * (int)(t % hp_n);
-        const int pj = 1 + (int)(t / hp_n);
+    if (t < hp_n * m) {
+        const int h0 = 2 * (t % hp_n);
+        const int pj = 1 + t / hp_n;
         const int k0 = 1 + zc * kDcChunk;
         const int k1 = min(k0 + kDcChunk - 1, m);
         const size_t plane = (size_t)g.nx * g.hx;
