@@ -23,7 +23,9 @@ struct SGrid {
     int nx;     // padded points per axis
     int hx;     // compact points per row and colour
     int nz;     // nx in 3-D, 1 in 2-D
-    size_t cs;  // elements per colour array
+    size_t ps;  // elements per plane of one colour: nx rows of hx, rounded up to a
+                // multiple of 128 in 3-D so that every plane starts 256-byte aligned
+    size_t cs;  // elements per colour array (nz planes)
 };
 
 inline SGrid make_grid(int dim, int nx)
@@ -32,7 +34,9 @@ inline SGrid make_grid(int dim, int nx)
     g.nx = nx;
     g.hx = (nx + 1) / 2;
     g.nz = dim == 3 ? nx : 1;
-    g.cs = (size_t)g.hx * nx * g.nz;
+    g.ps = (size_t)g.hx * nx;
+    if (dim == 3) g.ps = (g.ps + 127) / 128 * 128;
+    g.cs = g.ps * g.nz;
     return g;
 }
 

@@ -70,7 +70,7 @@ __device__ __forceinline__ int colour_of(int pi, int pj, int pk)
 
 __device__ __forceinline__ size_t row_base(const SGrid& g, int pj, int pk)
 {
-    return ((size_t)pk * g.nx + pj) * g.hx;
+    return (size_t)pk * g.ps + (size_t)pj * g.hx;
 }
 
 template <int D, typename T>
@@ -459,7 +459,7 @@ __global__ void __launch_bounds__(kBlock) k_norm(SGrid g, const double* __restri
     int m = g.nx - 2;
     long total = (long)g.hx * m * (D == 3 ? m : 1);
     long stride = (long)gridDim.x * kBlock;
-    size_t ny = (size_t)g.hx, nz = (size_t)g.nx * g.hx;
+    size_t ny = (size_t)g.hx, nz = g.ps;
     unsigned long long best = 0;
     for (long t = xcd_block() * kBlock + threadIdx.x; t < total; t += stride) {
         int h = (int)(t % g.hx);
@@ -523,7 +523,7 @@ __global__ void __launch_bounds__(kBlock) k_resid_norm3(SGrid g, const double* _
         const int pj = 1 + (int)(t / g.hx);
         const int k0 = 1 + zc * kNormChunk;
         const int k1 = min(k0 + kNormChunk - 1, m);
-        const size_t plane = (size_t)g.nx * g.hx;
+        const size_t plane = g.ps;
         const size_t col = (size_t)pj * g.hx + h;
         const double* __restrict__ a[2] = {u, u + g.cs};
         double below[2], cur[2];
@@ -645,7 +645,7 @@ __device__ __forceinline__ void half_sweep_body(T* __restrict__ u, const T* __re
     if (pi < 1 || pi > g.nx - 2) return;
     const T* __restrict__ o = u + (size_t)(colour ^ 1) * g.cs;
     size_t row = row_base(g, pj, pk);
-    size_t ny = (size_t)g.hx, nz = (size_t)g.nx * g.hx;
+    size_t ny = (size_t)g.hx, nz = g.ps;
     size_t self = (size_t)colour * g.cs + row + h;
     C xm = (C)o[row + ((pi - 1) >> 1)], xp = (C)o[row + ((pi + 1) >> 1)];
     C ym = (C)o[row - ny + h], yp = (C)o[row + ny + h];
@@ -715,7 +715,7 @@ __global__ void __launch_bounds__(kBlock) k_smooth_zmarch3(T* __restrict__ u, co
     const int pj = 1 + (int)(t / g.hx);
     const int k0 = 1 + zc * kZChunk;
     const int k1 = min(k0 + kZChunk - 1, m);
-    const size_t plane = (size_t)g.nx * g.hx;
+    const size_t plane = g.ps;
     const size_t col = (size_t)pj * g.hx + h;  // offset of (h, pj) inside a plane
     const T* __restrict__ o = u + (size_t)(colour ^ 1) * g.cs;
     T* __restrict__ uc = u + (size_t)colour * g.cs;
@@ -855,17 +855,20 @@ __global__ void __launch_bounds__(kBlock) k_smooth_zmarch3_pair(T* __restrict__ 
 {
     using C = typename Compute<T>::type;
     const int m = g.nx - 2;
-    const int hp_n = g.hx >> 1;
     const int lb = (int)xcd_block();
     const int zc = lb / pblocks;
     const int t = (lb - zc * pblocks) * kBlock + (int)threadIdx.x;
-    if (t >= hp_n * m) return;
-    const int h0 = 2 * (t % hp_n);
-    const int pj = 1 + t / hp_n;
+    // flat pair index over the whole (padded) plane: each wave covers 128
+    // consecutive compact elements, an aligned segment; the ghost rows and the
+    // plane padding have no work
+    const int q = 2 * t;
+    const int pj = q / g.hx;
+    const int h0 = q - pj * g.hx;
+    if (pj < 1 || pj > m) return;
     constexpr int kZChunk = kZChunk0;
     const int k0 = 1 + zc * kZChunk;
     const int k1 = min(k0 + kZChunk - 1, m);
-    const size_t plane = (size_t)g.nx * g.hx;
+    const size_t plane = g.ps;
     const size_t col = (size_t)pj * g.hx + h0;
     const T* __restrict__ o = u + (size_t)(colour ^ 1) * g.cs;
     T* __restrict__ uc = u + (size_t)colour * g.cs;
@@ -1148,7 +1151,7 @@ __global__ void __launch_bounds__(kBlock) k_restrict3_l0(const TF* __restrict__ 
     const int K0 = 1 + zc * kch;
     const int K1 = min(K0 + kch - 1, Nc);
     const unsigned boff = (unsigned)(((2 * J - 2) * gf.hx + (I - 1)) * (int)sizeof(TF));
-    const size_t fplane = (size_t)gf.nx * gf.hx;
+    const size_t fplane = gf.ps;
     // value at (2I - 2 + c, 2J - 2 + r, k) of array a
     auto ld = [&](const TF* __restrict__ a, int c, int r, int k) -> C {
         const TF* p = a + (size_t)k * fplane + (((c + r + k + 1) & 1) ? gf.cs : 0) + (size_t)r * gf.hx + (c >> 1);
@@ -1434,13 +1437,14 @@ __global__ void __launch_bounds__(kBlock) k_prolong3_pair(const TC* __restrict__
     using C = typename Compute<TC>::type;
     const int Nc = gc.nx - 2, Nf = gf.nx - 2;
     const int Mq = (Nf + 1) >> 1;  // coarse parents per axis
-    const int hp_n = gf.hx >> 1;
     const int lb = (int)xcd_block();
     const int zc = lb / pblocks;
     const int t = (lb - zc * pblocks) * kBlock + (int)threadIdx.x;
-    if (t >= hp_n * Nf) return;
-    const int h0 = 2 * (t % hp_n);
-    const int pj = 1 + t / hp_n;
+    // flat pair index over the whole (padded) fine plane: aligned wave segments
+    const int q0 = 2 * t;
+    const int pj = q0 / gf.hx;
+    const int h0 = q0 - pj * gf.hx;
+    if (pj < 1 || pj > Nf) return;
     const int K0 = 1 + zc * KCH;
     const int nk = min(KCH, Mq - K0 + 1);
     const int qj = (pj + 1) >> 1, sj = (pj & 1) ? -1 : 1;
@@ -1461,7 +1465,7 @@ __global__ void __launch_bounds__(kBlock) k_prolong3_pair(const TC* __restrict__
             off[0][y][x] = o + (c0 ? (unsigned)gc.cs : 0u);
             off[1][y][x] = o + (c0 ? 0u : (unsigned)gc.cs);
         }
-    const size_t cplane = (size_t)gc.nx * gc.hx;
+    const size_t cplane = gc.ps;
     const C w0 = (C)0.75, w1 = (C)0.25;
     // par0: parity term of the black points in the odd fine plane 2K - 1
     // (pi = 2 h + par); the even plane 2K has the other one
@@ -1504,7 +1508,7 @@ __global__ void __launch_bounds__(kBlock) k_prolong3_pair(const TC* __restrict__
             }
         }
     }
-    const size_t fplane = (size_t)gf.nx * gf.hx;
+    const size_t fplane = gf.ps;
     const unsigned row = (unsigned)(pj * gf.hx + h0);
     TF* __restrict__ ub = u + gf.cs;  // black colour array
     Pair<TF> old[KCH][2];
@@ -1812,7 +1816,7 @@ __global__ void __launch_bounds__(kBlock) k_dc_outer(SGrid g, DcIn<TL, UPD> in, 
     int m = g.nx - 2;
     long total = (long)g.hx * m * (D == 3 ? m : 1);
     long stride = (long)gridDim.x * kBlock;
-    size_t ny = (size_t)g.hx, nz = (size_t)g.nx * g.hx;
+    size_t ny = (size_t)g.hx, nz = g.ps;
     unsigned long long best = 0;
     for (long t = xcd_block() * kBlock + threadIdx.x; t < total; t += stride) {
         int h = (int)(t % g.hx);
@@ -1864,7 +1868,7 @@ __global__ void __launch_bounds__(kBlock) k_dc_outer3(SGrid g, DcIn<TL, UPD> in,
         const int pj = 1 + (int)(t / g.hx);
         const int k0 = 1 + zc * kNormChunk;
         const int k1 = min(k0 + kNormChunk - 1, m);
-        const size_t plane = (size_t)g.nx * g.hx;
+        const size_t plane = g.ps;
         const size_t col = (size_t)pj * g.hx + h;
         const size_t cs = g.cs;
         double below[2], cur[2];
@@ -1932,17 +1936,18 @@ __global__ void __launch_bounds__(kBlock) k_dc_outer3_pair(SGrid g, DcIn<TL, UPD
                                                            unsigned long long* maxbits)
 {
     const int m = g.nx - 2;
-    const int hp_n = g.hx >> 1;
     const int lb = (int)xcd_block();
     const int zc = lb / pblocks;
     const int t = (lb - zc * pblocks) * kBlock + (int)threadIdx.x;
     unsigned long long best = 0;
-    if (t < hp_n * m) {
-        const int h0 = 2 * (t % hp_n);
-        const int pj = 1 + t / hp_n;
+    // flat pair index over the whole (padded) plane, as in k_smooth_zmarch3_pair
+    const int q = 2 * t;
+    const int pj = q / g.hx;
+    const int h0 = q - pj * g.hx;
+    if (pj >= 1 && pj <= m) {
         const int k0 = 1 + zc * kDcChunk;
         const int k1 = min(k0 + kDcChunk - 1, m);
-        const size_t plane = (size_t)g.nx * g.hx;
+        const size_t plane = g.ps;
         const size_t col = (size_t)pj * g.hx + h0;
         const size_t cs = g.cs;
         Pair<double> below[2], cur[2];
@@ -2181,7 +2186,7 @@ void launch_half_sweep(int dim, hipStream_t st, SGrid g, T* u, const T* f, int c
         // (on the coarse levels, with the ghost rule, this form measured slower
         // than k_smooth_zmarch3)
         long m = g.nx - 2;
-        int pblocks = ceil_div((long)(g.hx / 2) * m, kBlock);
+        int pblocks = ceil_div((long)(g.ps / 2), kBlock);
         int chunks = ceil_div(m, kZChunk0);
         hipLaunchKernelGGL((k_smooth_zmarch3_pair<T>), dim3(pblocks * chunks), dim3(kBlock), 0, st, u, f, g, colour,
                            (C)h2, inv2d, pblocks);
@@ -2258,7 +2263,7 @@ void launch_prolong_add(int dim, hipStream_t st, SGrid gc, const TC* ec, SGrid g
     if (dim == 3 && black_only && (gf.hx % 2) == 0 && 2 * gf.cs < (1ull << 31) && 2 * gc.cs < (1ull << 31)) {
         // paired form: one paired load and store per fine plane and pair
         const long Mq = (gf.nx - 1) / 2;
-        const int pblocks = ceil_div((long)(gf.hx / 2) * (gf.nx - 2), kBlock);
+        const int pblocks = ceil_div((long)(gf.ps / 2), kBlock);
         const int chunks = ceil_div(Mq, kProlongPairChunk);
         hipLaunchKernelGGL((k_prolong3_pair<TC, TF, kProlongPairChunk>), dim3(pblocks * chunks), dim3(kBlock), 0, st,
                            ec, gc, u, gf, gr, pblocks);
@@ -2324,7 +2329,7 @@ void launch_dc_outer(int dim, hipStream_t st, SGrid g, const double* phi_in, con
     const bool upd = e_in != nullptr;
     if (dim == 3 && g.hx % 2 == 0 && g.cs % 2 == 0) {
         long m = g.nx - 2;
-        int pblocks = ceil_div((long)(g.hx / 2) * m, kBlock);
+        int pblocks = ceil_div((long)(g.ps / 2), kBlock);
         dim3 grid(pblocks * ceil_div(m, kDcChunk));
         if (upd)
             hipLaunchKernelGGL((k_dc_outer3_pair<TL, true>), grid, dim3(kBlock), 0, st, g,

@@ -527,7 +527,7 @@ __global__ void __launch_bounds__(kNB) k_net_features(SGrid g, const double* __r
     const int j = (int)((v / m) % m) + 1;
     const int k = (int)(v / ((long)m * m)) + 1;
     auto at = [&](const double* a, int pi, int pj, int pk) {
-        return a[(size_t)((pi + pj + pk + 3) & 1) * g.cs + ((size_t)pk * g.nx + pj) * g.hx + (pi >> 1)];
+        return a[(size_t)((pi + pj + pk + 3) & 1) * g.cs + ((size_t)pk * g.ps + (size_t)pj * g.hx) + (pi >> 1)];
     };
     const double lap = (at(phi, i - 1, j, k) + at(phi, i + 1, j, k) + at(phi, i, j - 1, k) + at(phi, i, j + 1, k) +
                         at(phi, i, j, k - 1) + at(phi, i, j, k + 1) - 6.0 * at(phi, i, j, k)) * inv_h2;
@@ -547,7 +547,7 @@ __global__ void __launch_bounds__(kNB) k_net_apply(SGrid g, double* __restrict__
     const int i = (int)(v % m) + 1;
     const int j = (int)((v / m) % m) + 1;
     const int k = (int)(v / ((long)m * m)) + 1;
-    phi[(size_t)((i + j + k + 3) & 1) * g.cs + ((size_t)k * g.nx + j) * g.hx + (i >> 1)] += s * (double)out[v];
+    phi[(size_t)((i + j + k + 3) & 1) * g.cs + ((size_t)k * g.ps + (size_t)j * g.hx) + (i >> 1)] += s * (double)out[v];
 }
 
 // target = (phi_a - phi_b) * inv_s on Gamma
@@ -561,7 +561,7 @@ __global__ void __launch_bounds__(kNB) k_net_target(SGrid g, const double* __res
     const int i = (int)(v % m) + 1;
     const int j = (int)((v / m) % m) + 1;
     const int k = (int)(v / ((long)m * m)) + 1;
-    const size_t p = (size_t)((i + j + k + 3) & 1) * g.cs + ((size_t)k * g.nx + j) * g.hx + (i >> 1);
+    const size_t p = (size_t)((i + j + k + 3) & 1) * g.cs + ((size_t)k * g.ps + (size_t)j * g.hx) + (i >> 1);
     t[v] = (float)((pa[p] - pb[p]) * inv_s);
 }
 
