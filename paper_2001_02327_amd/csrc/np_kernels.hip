@@ -518,9 +518,11 @@ __global__ void __launch_bounds__(kBlock) k_resid_norm3(SGrid g, const double* _
     const int zc = lb / pblocks;
     const int t = (lb - zc * pblocks) * kBlock + (int)threadIdx.x;
     unsigned long long best = 0;
-    if (t < (long)g.hx * m) {
-        const int h = (int)(t % g.hx);
-        const int pj = 1 + (int)(t / g.hx);
+    // flat index over the whole (padded) plane: aligned wave segments; the ghost
+    // rows and the padding have no work
+    const int pj = t / g.hx;
+    const int h = t - pj * g.hx;
+    if (pj >= 1 && pj <= m) {
         const int k0 = 1 + zc * kNormChunk;
         const int k1 = min(k0 + kNormChunk - 1, m);
         const size_t plane = g.ps;
@@ -710,9 +712,10 @@ __global__ void __launch_bounds__(kBlock) k_smooth_zmarch3(T* __restrict__ u, co
     const int lb = (int)xcd_block();
     const int zc = lb / pblocks;
     const int t = (lb - zc * pblocks) * kBlock + (int)threadIdx.x;
-    if (t >= (long)g.hx * m) return;
-    const int h = (int)(t % g.hx);
-    const int pj = 1 + (int)(t / g.hx);
+    // flat index over the whole (padded) plane: aligned wave segments
+    const int pj = t / g.hx;
+    const int h = t - pj * g.hx;
+    if (pj < 1 || pj > m) return;
     const int k0 = 1 + zc * kZChunk;
     const int k1 = min(k0 + kZChunk - 1, m);
     const size_t plane = g.ps;
@@ -1863,9 +1866,11 @@ __global__ void __launch_bounds__(kBlock) k_dc_outer3(SGrid g, DcIn<TL, UPD> in,
     const int zc = lb / pblocks;
     const int t = (lb - zc * pblocks) * kBlock + (int)threadIdx.x;
     unsigned long long best = 0;
-    if (t < (long)g.hx * m) {
-        const int h = (int)(t % g.hx);
-        const int pj = 1 + (int)(t / g.hx);
+    // flat index over the whole (padded) plane: aligned wave segments; the ghost
+    // rows and the padding have no work
+    const int pj = t / g.hx;
+    const int h = t - pj * g.hx;
+    if (pj >= 1 && pj <= m) {
         const int k0 = 1 + zc * kNormChunk;
         const int k1 = min(k0 + kNormChunk - 1, m);
         const size_t plane = g.ps;
@@ -2157,7 +2162,7 @@ void launch_norm(int dim, hipStream_t st, SGrid g, const double* u, const double
 {
     if (dim == 3 && mode == 0) {
         long m = g.nx - 2;
-        int pblocks = ceil_div((long)g.hx * m, kBlock);
+        int pblocks = ceil_div((long)g.ps, kBlock);
         int chunks = ceil_div(m, kNormChunk);
         hipLaunchKernelGGL(k_resid_norm3, dim3(pblocks * chunks), dim3(kBlock), 0, st, g, u, f, inv_h2, pblocks,
                            maxbits);
@@ -2196,7 +2201,7 @@ void launch_half_sweep(int dim, hipStream_t st, SGrid g, T* u, const T* f, int c
         // z-march; the level-0 instance (TAG 0) is kept apart from the
         // coarse-level one (TAG 1) so that profiles separate them
         long m = g.nx - 2;
-        int pblocks = ceil_div((long)g.hx * m, kBlock);
+        int pblocks = ceil_div((long)g.ps, kBlock);
         int chunks = ceil_div(m, fine ? kZChunk0 : kZChunk1);
         if (fine)
             hipLaunchKernelGGL((k_smooth_zmarch3<T, 0>), dim3(pblocks * chunks), dim3(kBlock), 0, st, u, f, g, colour,
@@ -2343,7 +2348,7 @@ void launch_dc_outer(int dim, hipStream_t st, SGrid g, const double* phi_in, con
     }
     if (dim == 3) {
         long m = g.nx - 2;
-        int pblocks = ceil_div((long)g.hx * m, kBlock);
+        int pblocks = ceil_div((long)g.ps, kBlock);
         dim3 grid(pblocks * ceil_div(m, kNormChunk));
         if (upd)
             hipLaunchKernelGGL((k_dc_outer3<TL, true>), grid, dim3(kBlock), 0, st, g, DcIn<TL, true>{phi_in, e_in, factor},
