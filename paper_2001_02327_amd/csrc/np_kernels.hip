@@ -25,6 +25,18 @@ __device__ __forceinline__ long xcd_block()
     return x * q + (x < r ? x : r) + k;
 }
 
+// Consecutive level-0 kernels of a V-cycle run their z-chunks in alternating
+// directions (rev: the logical block order reversed), so that each starts on
+// the planes the previous one touched last, which the memory-side cache still
+// holds.  The direction changes the order of the work only, never its result.
+constexpr bool kAlternateZ = true;
+
+__device__ __forceinline__ int zmarch_block(int rev)
+{
+    const int lb = (int)xcd_block();
+    return (kAlternateZ && rev) ? (int)gridDim.x - 1 - lb : lb;
+}
+
 // Strip ordering of a 3-D box of points (x fastest): the y range is cut into
 // strips of R rows and logical blocks run over (strip, z, block of the strip
 // plane).  With the XCD-contiguous numbering above, every XCD walks whole
@@ -709,7 +721,7 @@ __global__ void __launch_bounds__(kBlock) k_smooth_zmarch3(T* __restrict__ u, co
     constexpr int kZChunk = TAG == 0 ? kZChunk0 : kZChunk1;
     constexpr int kZGroup = kZChunk;  // planes whose loads are issued together
     const int m = g.nx - 2;
-    const int lb = (int)xcd_block();
+    const int lb = zmarch_block(TAG == 0 ? colour : 0);  // level 0: red half sweeps up, black down
     const int zc = lb / pblocks;
     const int t = (lb - zc * pblocks) * kBlock + (int)threadIdx.x;
     // flat index over the whole (padded) plane: aligned wave segments
@@ -858,7 +870,7 @@ __global__ void __launch_bounds__(kBlock) k_smooth_zmarch3_pair(T* __restrict__ 
 {
     using C = typename Compute<T>::type;
     const int m = g.nx - 2;
-    const int lb = (int)xcd_block();
+    const int lb = zmarch_block(colour);  // red half sweeps up, black down
     const int zc = lb / pblocks;
     const int t = (lb - zc * pblocks) * kBlock + (int)threadIdx.x;
     // flat pair index over the whole (padded) plane: each wave covers 128
@@ -1440,7 +1452,7 @@ __global__ void __launch_bounds__(kBlock) k_prolong3_pair(const TC* __restrict__
     using C = typename Compute<TC>::type;
     const int Nc = gc.nx - 2, Nf = gf.nx - 2;
     const int Mq = (Nf + 1) >> 1;  // coarse parents per axis
-    const int lb = (int)xcd_block();
+    const int lb = zmarch_block(1);  // after the restriction, which runs up
     const int zc = lb / pblocks;
     const int t = (lb - zc * pblocks) * kBlock + (int)threadIdx.x;
     // flat pair index over the whole (padded) fine plane: aligned wave segments
