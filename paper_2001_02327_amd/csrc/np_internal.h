@@ -45,11 +45,15 @@ inline SGrid make_grid(int dim, int nx)
 // caller (the runtime) before any launch.
 
 // FP64 level operators (nested-level arrays, multigrid level 0)
+// fmax: device slot, zeroed by the caller, that receives the bit pattern of
+// max |f| over the level (atomic maximum)
 void launch_level0_init(int dim, hipStream_t st, SGrid g, const double* rho0, const double* phi_outer,
-                        double fourpiG, double* phi, double* f);
+                        double fourpiG, double* phi, double* f, unsigned long long* fmax);
+// fmax (may be null): device slot, zeroed by the caller, that receives the bit
+// pattern of max |f| over the level (atomic maximum)
 void launch_interface_fill(int dim, hipStream_t st, SGrid gc, const double* phic, const double* fc, SGrid gf,
                            int nf, int offx, int offy, int offz, const double* rho, double fourpiG, double* phif,
-                           double* ff);
+                           double* ff, unsigned long long* fmax);
 void launch_forces(int dim, hipStream_t st, SGrid g, int n, double dx, const double* phi, double* fx, double* fy,
                    double* fz);
 void launch_force_delta(int dim, hipStream_t st, SGrid g, int n, double dx, const double* phi, double* F,

@@ -132,30 +132,39 @@ __device__ __forceinline__ unsigned long long abs_bits(double a)
 // Level 0: potential = caller's outer layer on the ring, zero on Gamma^0;
 // right-hand side = 4 pi G rho on Gamma^0 (caller gives Omega^0 plus its inner
 // layer, (n+2)^d points).
+// Also reduces max |f| into *fmax (grid-stride loop, one atomic per block).
+constexpr int kInitBlocks = 16384;
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_level0_init(SGrid g, const double* __restrict__ rho0,
                                                         const double* __restrict__ phi_outer, double fourpiG,
-                                                        double* __restrict__ phi, double* __restrict__ f)
+                                                        double* __restrict__ phi, double* __restrict__ f,
+                                                        unsigned long long* fmax)
 {
-    long t = xcd_block() * kBlock + threadIdx.x;
-    long total = (long)g.nx * g.nx * g.nz;
-    if (t >= total) return;
-    int pi = (int)(t % g.nx);
-    long r = t / g.nx;
-    int pj = (int)(r % g.nx);
-    int pk = (int)(r / g.nx);
-    int last = g.nx - 1;
-    bool ring = pi == 0 || pi == last || pj == 0 || pj == last || (D == 3 && (pk == 0 || pk == last));
-    size_t p = pos<D, double>(g, pi, pj, pk);
-    if (ring) {
-        phi[p] = phi_outer[t];
-        f[p] = 0.0;
-    } else {
-        int m = g.nx - 2;
-        size_t ri = D == 3 ? (((size_t)(pk - 1) * m + (pj - 1)) * m + (pi - 1)) : ((size_t)(pj - 1) * m + (pi - 1));
-        phi[p] = 0.0;
-        f[p] = fourpiG * rho0[ri];
+    const long total = (long)g.nx * g.nx * g.nz;
+    const long stride = (long)gridDim.x * kBlock;
+    const int last = g.nx - 1;
+    unsigned long long best = 0;
+    for (long t = xcd_block() * kBlock + threadIdx.x; t < total; t += stride) {
+        int pi = (int)(t % g.nx);
+        long r = t / g.nx;
+        int pj = (int)(r % g.nx);
+        int pk = (int)(r / g.nx);
+        bool ring = pi == 0 || pi == last || pj == 0 || pj == last || (D == 3 && (pk == 0 || pk == last));
+        size_t p = pos<D, double>(g, pi, pj, pk);
+        if (ring) {
+            phi[p] = phi_outer[t];
+            f[p] = 0.0;
+        } else {
+            int m = g.nx - 2;
+            size_t ri = D == 3 ? (((size_t)(pk - 1) * m + (pj - 1)) * m + (pi - 1)) : ((size_t)(pj - 1) * m + (pi - 1));
+            const double v = fourpiG * rho0[ri];
+            phi[p] = 0.0;
+            f[p] = v;
+            const unsigned long long b = abs_bits(v);
+            best = b > best ? b : best;
+        }
     }
+    block_max_to(best, fmax);
 }
 
 // Interpolation weight pair along one axis for fine padded index p of a
@@ -192,11 +201,12 @@ __global__ void __launch_bounds__(kBlock) k_interface_fill(SGrid gc, const doubl
                                                            const double* __restrict__ fc, SGrid gf, int nf, int offx,
                                                            int offy, int offz, const double* __restrict__ rho,
                                                            double fourpiG, double* __restrict__ phif,
-                                                           double* __restrict__ ff)
+                                                           double* __restrict__ ff, unsigned long long* fmax)
 {
     long t = xcd_block() * kBlock + threadIdx.x;
     long total = (long)gf.nx * gf.nx * gf.nz;
-    if (t >= total) return;
+    unsigned long long best = 0;
+    if (t < total) {
     int pi = (int)(t % gf.nx);
     long r = t / gf.nx;
     int pj = (int)(r % gf.nx);
@@ -220,6 +230,9 @@ __global__ void __launch_bounds__(kBlock) k_interface_fill(SGrid gc, const doubl
         v = interp_tensor<D>(fc, gc, qi, qj, qk, si, sj, sk);
     }
     ff[p] = v;
+    best = abs_bits(v);
+    }
+    if (fmax) block_max_to(best, fmax);
 }
 
 // 3-D form of k_interface_fill marching along the coarse z axis: a thread owns
@@ -236,13 +249,14 @@ __global__ void __launch_bounds__(kBlock) k_interface_fill3_zm(SGrid gc, const d
                                                                int offx, int offy, int offz,
                                                                const double* __restrict__ rho, double fourpiG,
                                                                double* __restrict__ phif, double* __restrict__ ff,
-                                                               int pblocks)
+                                                               int pblocks, unsigned long long* fmax)
 {
     const int Mq = (gf.nx + 1) / 2;  // parents per axis: fine padded points 0 .. nf + 3 in pairs
     const int lb = (int)xcd_block();
     const int zc = lb / pblocks;
     const int t = (lb - zc * pblocks) * kBlock + (int)threadIdx.x;
-    if (t >= (long)Mq * Mq) return;
+    unsigned long long best = 0;  // max |f| written (the outer layer's 0 does not raise it)
+    if (t < Mq * Mq) {
     const int a = (int)(t % Mq), b = (int)(t / Mq);
     const int c0 = zc * kFillChunk, c1 = min(c0 + kFillChunk, Mq) - 1;
     const int qi = offx + 1 + a, qj = offy + 1 + b;
@@ -294,6 +308,8 @@ __global__ void __launch_bounds__(kBlock) k_interface_fill3_zm(SGrid gc, const d
                         v = interp_tensor<3>(fc, gc, qi, qj, qk, dx ? 1 : -1, dy ? 1 : -1, dz ? 1 : -1);
                     }
                     ff[p] = v;
+                    const unsigned long long bv = abs_bits(v);
+                    best = bv > best ? bv : best;
                 }
             }
         }
@@ -305,6 +321,8 @@ __global__ void __launch_bounds__(kBlock) k_interface_fill3_zm(SGrid gc, const d
                 cv[1][y][x] = cv[2][y][x];
             }
     }
+    }
+    if (fmax) block_max_to(best, fmax);
 }
 
 // ------------------------------------------------------------------ forces
@@ -2121,25 +2139,26 @@ static long ncompact_active(int dim, const SGrid& g)
 }
 
 void launch_level0_init(int dim, hipStream_t st, SGrid g, const double* rho0, const double* phi_outer,
-                        double fourpiG, double* phi, double* f)
+                        double fourpiG, double* phi, double* f, unsigned long long* fmax)
 {
-    NP_DISPATCH(dim, k_level0_init, dim3(ceil_div(npoints(g), kBlock)), dim3(kBlock), st, g, rho0, phi_outer, fourpiG,
-                phi, f);
+    int blocks = ceil_div(npoints(g), kBlock);
+    if (blocks > kInitBlocks) blocks = kInitBlocks;
+    NP_DISPATCH(dim, k_level0_init, dim3(blocks), dim3(kBlock), st, g, rho0, phi_outer, fourpiG, phi, f, fmax);
 }
 
 void launch_interface_fill(int dim, hipStream_t st, SGrid gc, const double* phic, const double* fc, SGrid gf,
                            int nf, int offx, int offy, int offz, const double* rho, double fourpiG, double* phif,
-                           double* ff)
+                           double* ff, unsigned long long* fmax)
 {
     if (dim == 3) {
         const long Mq = (gf.nx + 1) / 2;
         const int pblocks = ceil_div(Mq * Mq, kBlock);
         hipLaunchKernelGGL(k_interface_fill3_zm, dim3(pblocks * ceil_div(Mq, kFillChunk)), dim3(kBlock), 0, st, gc, phic,
-                           fc, gf, nf, offx, offy, offz, rho, fourpiG, phif, ff, pblocks);
+                           fc, gf, nf, offx, offy, offz, rho, fourpiG, phif, ff, pblocks, fmax);
         return;
     }
     NP_DISPATCH(dim, k_interface_fill, dim3(ceil_div(npoints(gf), kBlock)), dim3(kBlock), st, gc, phic, fc, gf, nf,
-                offx, offy, offz, rho, fourpiG, phif, ff);
+                offx, offy, offz, rho, fourpiG, phif, ff, fmax);
 }
 
 void launch_forces(int dim, hipStream_t st, SGrid g, int n, double dx, const double* phi, double* fx, double* fy,

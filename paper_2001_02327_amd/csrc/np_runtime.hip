@@ -580,7 +580,7 @@ int learned_guess(np_solver* s, int l, const double* rho_l, double fourpiG, doub
     }
     // fallback: restore the interpolated guess
     launch_interface_fill(c.dim, st, s->lg[l - 1], s->phi[l - 1], s->f[l - 1], g, c.n[l], c.offset[l][0],
-                          c.offset[l][1], c.offset[l][2], rho_l, fourpiG, s->phi[l], s->f[l]);
+                          c.offset[l][1], c.offset[l][2], rho_l, fourpiG, s->phi[l], s->f[l], nullptr);
     HIPCHK(s, hipGetLastError());
     return NP_OK;
 }
@@ -823,18 +823,22 @@ int nested_poisson_solve(np_solver* s, const double* const* rho, const double* p
         auto t0 = std::chrono::steady_clock::now();
         s->hist[l].clear();
         prof_begin(s, NP_KCLASS_FILL);
+        // the fill also reduces max |f| into slot 2
+        launch_set_u64(s->stream, s->d_bits + 2, 1, 0ULL);
         if (l == 0) {
-            launch_level0_init(d, s->stream, s->lg[0], rho[0], phi_outer, fourpiG, s->phi[0], s->f[0]);
+            launch_level0_init(d, s->stream, s->lg[0], rho[0], phi_outer, fourpiG, s->phi[0], s->f[0], s->d_bits + 2);
         } else {
             launch_interface_fill(d, s->stream, s->lg[l - 1], s->phi[l - 1], s->f[l - 1], s->lg[l], c.n[l],
                                   c.offset[l][0], c.offset[l][1], d == 3 ? c.offset[l][2] : 0, rho[l], fourpiG,
-                                  s->phi[l], s->f[l]);
+                                  s->phi[l], s->f[l], s->d_bits + 2);
         }
         prof_end(s);
         HIPCHK(s, hipGetLastError());
-        double fnorm = 0.0;
-        int rc = norm_sync(s, l, 1, &fnorm);
-        if (rc) return rc;
+        HIPCHK(s, hipMemcpyAsync(s->h_bits + 2, s->d_bits + 2, sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                                 s->stream));
+        HIPCHK(s, hipStreamSynchronize(s->stream));
+        const double fnorm = bits_to_double(s->h_bits[2]);
+        int rc = NP_OK;
         if (!std::isfinite(fnorm)) return set_err(s, NP_ENONFINITE, "level %d: non-finite density", l);
         double scale = fnorm;
         if (!(scale > 0.0)) {
@@ -1047,7 +1051,7 @@ int nested_poisson_guess_features(np_solver* s, int level, float* x, float* targ
     double dx = std::ldexp(c.dx0, -l);
     double fourpiG = 4.0 * M_PI * c.G;
     launch_interface_fill(c.dim, s->stream, s->lg[l - 1], s->phi[l - 1], s->f[l - 1], s->lg[l], c.n[l], c.offset[l][0],
-                          c.offset[l][1], c.offset[l][2], s->f[l], 0.0, s->feat_phi, s->feat_f);
+                          c.offset[l][1], c.offset[l][2], s->f[l], 0.0, s->feat_phi, s->feat_f, nullptr);
     double fnorm = 0.0;
     int rc = norm_sync(s, l, 1, &fnorm);
     if (rc) return rc;
