@@ -270,10 +270,25 @@ __global__ void __launch_bounds__(kBlock) k_interface_fill3_zm(SGrid gc, const d
     };
     load_plane(offz + c0, cv[0]);
     load_plane(offz + c0 + 1, cv[1]);
+    load_plane(offz + c0 + 2, cv[2]);
     const double w0 = 0.75, w1 = 0.25;
     for (int cc = c0; cc <= c1; cc++) {
         const int qk = offz + 1 + cc;
-        load_plane(qk + 1, cv[2]);
+        // issued before this step's arithmetic: the next step's coarse plane and
+        // the density of this step's children inside Omega
+        double nxt[3][3];
+        if (cc < c1) load_plane(qk + 2, nxt);
+        double rv[2][2][2];
+#pragma unroll
+        for (int dz = 0; dz < 2; dz++)
+#pragma unroll
+            for (int dy = 0; dy < 2; dy++)
+#pragma unroll
+                for (int dx = 0; dx < 2; dx++) {
+                    const int pi = 2 * a + dx, pj = 2 * b + dy, pk = 2 * cc + dz;
+                    const bool omega = pi >= 2 && pi <= nf + 1 && pj >= 2 && pj <= nf + 1 && pk >= 2 && pk <= nf + 1;
+                    rv[dz][dy][dx] = omega ? rho[((size_t)(pk - 2) * nf + (pj - 2)) * nf + (pi - 2)] : 0.0;
+                }
 #pragma unroll
         for (int dz = 0; dz < 2; dz++) {
             const int pk = 2 * cc + dz;
@@ -303,7 +318,7 @@ __global__ void __launch_bounds__(kBlock) k_interface_fill3_zm(SGrid gc, const d
                     if (outer) {
                         v = 0.0;
                     } else if (omega) {
-                        v = fourpiG * rho[((size_t)(pk - 2) * nf + (pj - 2)) * nf + (pi - 2)];
+                        v = fourpiG * rv[dz][dy][dx];
                     } else {
                         v = interp_tensor<3>(fc, gc, qi, qj, qk, dx ? 1 : -1, dy ? 1 : -1, dz ? 1 : -1);
                     }
@@ -319,6 +334,7 @@ __global__ void __launch_bounds__(kBlock) k_interface_fill3_zm(SGrid gc, const d
             for (int x = 0; x < 3; x++) {
                 cv[0][y][x] = cv[1][y][x];
                 cv[1][y][x] = cv[2][y][x];
+                cv[2][y][x] = nxt[y][x];
             }
     }
     }
