@@ -740,6 +740,7 @@ __global__ void __launch_bounds__(kBlock) k_smooth_fine(T* __restrict__ u, const
 // planes per thread on multigrid level 0 and on the coarse levels (4/4, 8/8,
 // 8/4, 4/2, 4/1 measured at 514^3: 4/4 best)
 constexpr int kZChunk0 = 4;
+constexpr bool kDppExtra = true;  // FP16 pair sweep: extra x-neighbour from the adjacent lane
 constexpr int kZChunk1 = 4;
 
 // TAG 0: level 0 (ghost layer in memory); TAG 1: coarse levels, whose ghost
@@ -991,6 +992,35 @@ __global__ void __launch_bounds__(kBlock) k_smooth_zmarch3_pair(T* __restrict__ 
         // update, so that each wave keeps ~20 loads in flight
         Pair<T> ab[kZChunk], ym[kZChunk], yp[kZChunk], fv[kZChunk];
         T ex[kZChunk];
+        if constexpr (sizeof(T) == 2 && kDppExtra) {
+            // FP16: the extra x-neighbour of plane pk is a half of the neighbouring
+            // lane's pair in the same plane (flat numbering: lane - 1 holds slots
+            // h0 - 2, h0 - 1 and lane + 1 slots h0 + 2, h0 + 3), moved across lanes
+            // with a DPP wave shift; only the wave's edge lanes, whose neighbour is
+            // in another wave, load it
+            const int lane = (int)(threadIdx.x & 63);
+#pragma unroll
+            for (int q = 0; q < kZChunk; q++) {
+                const size_t here = (size_t)(k0 + q) * plane + col;
+                ab[q] = *(const Pair<T>*)(o + here + plane);
+                ym[q] = *(const Pair<T>*)(o + here - g.hx);
+                yp[q] = *(const Pair<T>*)(o + here + g.hx);
+                fv[q] = *(const Pair<T>*)(fc + here);
+                const int par = (colour + pj + k0 + q + 3) & 1;
+                if (par ? lane == 63 : lane == 0) ex[q] = extra(k0 + q, here);
+            }
+#pragma unroll
+            for (int q = 0; q < kZChunk; q++) {
+                const int par = (colour + pj + k0 + q + 3) & 1;
+                const int w = (int)__builtin_bit_cast(uint32_t, cur);
+                const uint32_t wl = (uint32_t)__builtin_amdgcn_update_dpp(0, w, 0x138, 0xf, 0xf, false);  // lane - 1
+                const uint32_t wr = (uint32_t)__builtin_amdgcn_update_dpp(0, w, 0x130, 0xf, 0xf, false);  // lane + 1
+                const uint16_t xv = par ? (uint16_t)(wr & 0xffffu) : (uint16_t)(wl >> 16);
+                const T e = (par ? lane == 63 : lane == 0) ? ex[q] : __builtin_bit_cast(T, xv);
+                step(k0 + q, ab[q], ym[q], yp[q], fv[q], e);
+            }
+            return;
+        }
 #pragma unroll
         for (int q = 0; q < kZChunk; q++) {
             const size_t here = (size_t)(k0 + q) * plane + col;
