@@ -887,6 +887,17 @@ __device__ __forceinline__ float mix_add2(uint32_t a, uint32_t b)
     return r;
 }
 
+// Value of the previous (lane - 1) and next (lane + 1) lane of the wave by a
+// DPP wave shift; lane 0 (previous) and lane 63 (next) get 0.
+__device__ __forceinline__ unsigned dpp_prev(unsigned v)
+{
+    return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x138, 0xf, 0xf, false);  // wave_shr:1
+}
+__device__ __forceinline__ unsigned dpp_next(unsigned v)
+{
+    return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x130, 0xf, 0xf, false);  // wave_shl:1
+}
+
 // Paired form of the level-0 z-march for 2- and 4-byte storage: a thread owns
 // the two compact points h0 = 2 hp and h0 + 1 of a row and moves them with
 // one 2-element load or store; the extra x-neighbour (h0 - 1 or h0 + 2) is a
@@ -1012,10 +1023,8 @@ __global__ void __launch_bounds__(kBlock) k_smooth_zmarch3_pair(T* __restrict__ 
 #pragma unroll
             for (int q = 0; q < kZChunk; q++) {
                 const int par = (colour + pj + k0 + q + 3) & 1;
-                const int w = (int)__builtin_bit_cast(uint32_t, cur);
-                const uint32_t wl = (uint32_t)__builtin_amdgcn_update_dpp(0, w, 0x138, 0xf, 0xf, false);  // lane - 1
-                const uint32_t wr = (uint32_t)__builtin_amdgcn_update_dpp(0, w, 0x130, 0xf, 0xf, false);  // lane + 1
-                const uint16_t xv = par ? (uint16_t)(wr & 0xffffu) : (uint16_t)(wl >> 16);
+                const unsigned w = __builtin_bit_cast(uint32_t, cur);
+                const uint16_t xv = par ? (uint16_t)(dpp_next(w) & 0xffffu) : (uint16_t)(dpp_prev(w) >> 16);
                 const T e = (par ? lane == 63 : lane == 0) ? ex[q] : __builtin_bit_cast(T, xv);
                 step(k0 + q, ab[q], ym[q], yp[q], fv[q], e);
             }
