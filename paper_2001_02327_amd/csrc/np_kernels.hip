@@ -37,6 +37,31 @@ __device__ __forceinline__ int zmarch_block(int rev)
     return (kAlternateZ && rev) ? (int)gridDim.x - 1 - lb : lb;
 }
 
+// Value of the previous (lane - 1) and next (lane + 1) lane of the wave by a
+// DPP wave shift; lane 0 (previous) and lane 63 (next) get 0.
+__device__ __forceinline__ unsigned dpp_prev(unsigned v)
+{
+    return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x138, 0xf, 0xf, false);  // wave_shr:1
+}
+__device__ __forceinline__ unsigned dpp_next(unsigned v)
+{
+    return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x130, 0xf, 0xf, false);  // wave_shl:1
+}
+__device__ __forceinline__ float dpp_prev(float x) { return __uint_as_float(dpp_prev(__float_as_uint(x))); }
+__device__ __forceinline__ float dpp_next(float x) { return __uint_as_float(dpp_next(__float_as_uint(x))); }
+__device__ __forceinline__ double dpp_prev(double x)
+{
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, x);
+    const unsigned long long lo = dpp_prev((unsigned)b), hi = dpp_prev((unsigned)(b >> 32));
+    return __builtin_bit_cast(double, lo | (hi << 32));
+}
+__device__ __forceinline__ double dpp_next(double x)
+{
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, x);
+    const unsigned long long lo = dpp_next((unsigned)b), hi = dpp_next((unsigned)(b >> 32));
+    return __builtin_bit_cast(double, lo | (hi << 32));
+}
+
 // Strip ordering of a 3-D box of points (x fastest): the y range is cut into
 // strips of R rows and logical blocks run over (strip, z, block of the strip
 // plane).  With the XCD-contiguous numbering above, every XCD walks whole
@@ -777,6 +802,14 @@ __global__ void __launch_bounds__(kBlock) k_smooth_zmarch3(T* __restrict__ u, co
     // first update so that each wave keeps many loads in flight.  Loads at
     // inactive (ghost) positions stay inside the arrays: h-1 / h+1 fall in the
     // neighbouring row of the same plane and f covers the whole padded grid.
+    // level 0: the other colour's x-neighbour that is not the thread's own compact
+    // slot (h + 1 for par 1, h - 1 for par 0) is the adjacent lane's value of the
+    // same plane (flat numbering), moved by a DPP wave shift; only the wave's edge
+    // lanes load it.  Lanes of other rows are used only for ghost points.  (On
+    // the coarse levels the exchange measured slower and every lane loads.)
+    constexpr bool XDPP = TAG == 0;
+    const int lane = (int)(threadIdx.x & 63);
+    const auto own_load = [&](int par) { return !XDPP || (par ? lane == 63 : lane == 0); };
     for (; pk + kZGroup - 1 <= k1; pk += kZGroup) {
         C ab[kZGroup], xo[kZGroup], ym[kZGroup], yp[kZGroup], fv[kZGroup];
 #pragma unroll
@@ -784,7 +817,7 @@ __global__ void __launch_bounds__(kBlock) k_smooth_zmarch3(T* __restrict__ u, co
             const size_t here = (size_t)(pk + q) * plane + col;
             const int par = (colour + pj + pk + q + 3) & 1;
             ab[q] = (C)o[here + plane];
-            xo[q] = (C)o[par ? here + 1 : here - 1];
+            if (own_load(par)) xo[q] = (C)o[par ? here + 1 : here - 1];
             ym[q] = (C)o[here - g.hx];
             yp[q] = (C)o[here + g.hx];
             fv[q] = (C)fc[here];
@@ -794,6 +827,10 @@ __global__ void __launch_bounds__(kBlock) k_smooth_zmarch3(T* __restrict__ u, co
             const size_t here = (size_t)(pk + q) * plane + col;
             const int par = (colour + pj + pk + q + 3) & 1;
             const int pi = 2 * h + par;
+            if constexpr (XDPP) {
+                const C nb = par ? dpp_next(cur) : dpp_prev(cur);
+                if (!own_load(par)) xo[q] = nb;
+            }
             if (pi >= 1 && pi <= g.nx - 2) {
                 C xm = par ? cur : xo[q];
                 C xp = par ? xo[q] : cur;
@@ -885,17 +922,6 @@ __device__ __forceinline__ float mix_add2(uint32_t a, uint32_t b)
     else
         asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel:[1,0,1] op_sel_hi:[1,0,1]" : "=v"(r) : "v"(a), "v"(b));
     return r;
-}
-
-// Value of the previous (lane - 1) and next (lane + 1) lane of the wave by a
-// DPP wave shift; lane 0 (previous) and lane 63 (next) get 0.
-__device__ __forceinline__ unsigned dpp_prev(unsigned v)
-{
-    return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x138, 0xf, 0xf, false);  // wave_shr:1
-}
-__device__ __forceinline__ unsigned dpp_next(unsigned v)
-{
-    return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x130, 0xf, 0xf, false);  // wave_shl:1
 }
 
 // Paired form of the level-0 z-march for 2- and 4-byte storage: a thread owns
