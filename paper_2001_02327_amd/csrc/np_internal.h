@@ -75,10 +75,13 @@ template <typename T>
 void launch_half_sweep(int dim, hipStream_t st, SGrid g, T* u, const T* f, int colour, double h2, int fine, int xn1,
                        double coef);
 // fine grid of type TF, coarse of type TC; the coarse right-hand side is
-// multiplied by out_scale; rule != 0: the fine grid is a level L >= 1
+// multiplied by out_scale; rule != 0: the fine grid is a level L >= 1.  The
+// coarse correction is cleared, or with seed_h2 > 0 (the coarse level's h^2)
+// set to the result of its first red half sweep from zero, which the caller
+// then does not launch
 template <typename TF, typename TC>
 void launch_resid_restrict(int dim, hipStream_t st, SGrid gf, const TF* u, const TF* f, double inv_h2, double out_scale,
-                           SGrid gc, TC* fc, TC* ec, int rule, int xn1, double coef);
+                           SGrid gc, TC* fc, TC* ec, int rule, int xn1, double coef, double seed_h2);
 // black_only != 0 corrects only the black points; (xn1, coef): the coarse level's rule
 template <typename TC, typename TF>
 void launch_prolong_add(int dim, hipStream_t st, SGrid gc, const TC* ec, SGrid gf, TF* u, int black_only, int xn1,

@@ -1076,6 +1076,22 @@ __global__ void __launch_bounds__(kBlock) k_smooth_zmarch3_pair(T* __restrict__ 
     }
 }
 
+// Coarse right-hand side and correction of one coarse point.  With seed_h2 > 0
+// the correction is not cleared but set to the result of the coarse level's
+// first red half sweep from zero, (0 - h^2 f) / (2d) on red points (black
+// neighbours and rule ghosts are all zero then), in the sweep's arithmetic, so
+// that sweep is not launched; black points get 0.
+template <int D, typename TC, typename C>
+__device__ __forceinline__ void coarse_out(TC* __restrict__ fc, TC* __restrict__ ec, size_t q, int I, int J, int K, C val,
+                                           C seed_h2, C inv2d)
+{
+    const TC fv = (TC)val;
+    fc[q] = fv;
+    TC e = (TC)0;
+    if (seed_h2 > (C)0 && colour_of<D>(I, J, K) == 0) e = (TC)(((C)0 - seed_h2 * (C)fv) * inv2d);
+    ec[q] = e;
+}
+
 // Residual r = f - lap(u) on the 2^d children of each coarse active point and
 // their mean (eqn:restriction2D/3D) into the coarse right-hand side, times
 // out_scale (1 except below a scaled level-0 defect problem); children beyond
@@ -1087,7 +1103,9 @@ __global__ void __launch_bounds__(kBlock) k_resid_restrict(const TF* __restrict_
                                                            typename Compute<TC>::type inv_h2,
                                                            typename Compute<TC>::type out_scale, SGrid gc,
                                                            TC* __restrict__ fc, TC* __restrict__ ec,
-                                                           GRule<typename Compute<TC>::type> gr)
+                                                           GRule<typename Compute<TC>::type> gr,
+                                                           typename Compute<TC>::type seed_h2,
+                                                           typename Compute<TC>::type inv2d)
 {
     using C = typename Compute<TC>::type;
     int Nc = gc.nx - 2, Nf = gf.nx - 2;
@@ -1127,8 +1145,7 @@ __global__ void __launch_bounds__(kBlock) k_resid_restrict(const TF* __restrict_
                 sum += (C)at<D>(f, gf, i, j, k) - (s - (C)(2 * D) * uc) * inv_h2;
             }
     size_t pc = pos<D, TC>(gc, I, J, K);
-    fc[pc] = (TC)(sum * ((C)(D == 3 ? 0.125 : 0.25) * out_scale));
-    ec[pc] = (TC)0;
+    coarse_out<D, TC, C>(fc, ec, pc, I, J, K, sum * ((C)(D == 3 ? 0.125 : 0.25) * out_scale), seed_h2, inv2d);
 }
 
 // 3-D restriction marching along the coarse z axis: a thread owns one coarse
@@ -1144,7 +1161,9 @@ __global__ void __launch_bounds__(kBlock) k_restrict3_zm(const TF* __restrict__ 
                                                          typename Compute<TC>::type inv_h2,
                                                          typename Compute<TC>::type out_scale, SGrid gc,
                                                          TC* __restrict__ fc, TC* __restrict__ ec,
-                                                         GRule<typename Compute<TC>::type> gr, int pblocks, int kch)
+                                                         GRule<typename Compute<TC>::type> gr, int pblocks, int kch,
+                                                         typename Compute<TC>::type seed_h2,
+                                                         typename Compute<TC>::type inv2d)
 {
     using C = typename Compute<TC>::type;
     const int Nc = gc.nx - 2, Nf = gf.nx - 2;
@@ -1225,8 +1244,7 @@ __global__ void __launch_bounds__(kBlock) k_restrict3_zm(const TF* __restrict__ 
             }
         }
         const size_t q = pos<3, TC>(gc, I, J, K);
-        fc[q] = (TC)(sum * ((C)0.125 * out_scale));
-        ec[q] = (TC)0;
+        coarse_out<3, TC, C>(fc, ec, q, I, J, K, sum * ((C)0.125 * out_scale), seed_h2, inv2d);
 #pragma unroll
         for (int r = 0; r < 2; r++)
 #pragma unroll
@@ -1253,7 +1271,9 @@ template <typename TF, typename TC>
 __global__ void __launch_bounds__(kBlock) k_restrict3_l0(const TF* __restrict__ u, const TF* __restrict__ f, SGrid gf,
                                                           typename Compute<TC>::type inv_h2,
                                                           typename Compute<TC>::type out_scale, SGrid gc,
-                                                          TC* __restrict__ fc, TC* __restrict__ ec, int pblocks, int kch)
+                                                          TC* __restrict__ fc, TC* __restrict__ ec, int pblocks, int kch,
+                                                          typename Compute<TC>::type seed_h2,
+                                                          typename Compute<TC>::type inv2d)
 {
     using C = typename Compute<TC>::type;
     const int Nc = gc.nx - 2;
@@ -1317,8 +1337,7 @@ __global__ void __launch_bounds__(kBlock) k_restrict3_l0(const TF* __restrict__ 
             }
         }
         const size_t q = pos<3, TC>(gc, I, J, K);
-        fc[q] = (TC)(sum * ((C)0.125 * out_scale));
-        ec[q] = (TC)0;
+        coarse_out<3, TC, C>(fc, ec, q, I, J, K, sum * ((C)0.125 * out_scale), seed_h2, inv2d);
 #pragma unroll
         for (int r = 0; r < 2; r++)
 #pragma unroll
@@ -2335,9 +2354,10 @@ void launch_half_sweep(int dim, hipStream_t st, SGrid g, T* u, const T* f, int c
 
 template <typename TF, typename TC>
 void launch_resid_restrict(int dim, hipStream_t st, SGrid gf, const TF* u, const TF* f, double inv_h2, double out_scale,
-                           SGrid gc, TC* fc, TC* ec, int rule, int xn1, double coef)
+                           SGrid gc, TC* fc, TC* ec, int rule, int xn1, double coef, double seed_h2)
 {
     using C = typename Compute<TC>::type;
+    const C sh2 = (C)seed_h2, inv2d = (C)(1.0 / (2.0 * dim));
     long Nc = gc.nx - 2;
     long total = dim == 3 ? Nc * Nc * Nc : Nc * Nc;
     dim3 grid(ceil_div(total, kBlock));
@@ -2351,22 +2371,22 @@ void launch_resid_restrict(int dim, hipStream_t st, SGrid gf, const TF* u, const
         if (!rule && gf.nx - 2 == 2 * Nc && 2 * gf.cs * sizeof(TF) < (1ull << 31)) {
             // multigrid level 0: uniform addressing
             hipLaunchKernelGGL((k_restrict3_l0<TF, TC>), zgrid, dim3(kBlock), 0, st, u, f, gf, (C)inv_h2, (C)out_scale,
-                               gc, fc, ec, pblocks, kch);
+                               gc, fc, ec, pblocks, kch, sh2, inv2d);
             return;
         }
         if (rule)
             hipLaunchKernelGGL((k_restrict3_zm<TF, TC, true>), zgrid, dim3(kBlock), 0, st, u, f, gf, (C)inv_h2,
-                               (C)out_scale, gc, fc, ec, gr, pblocks, kch);
+                               (C)out_scale, gc, fc, ec, gr, pblocks, kch, sh2, inv2d);
         else
             hipLaunchKernelGGL((k_restrict3_zm<TF, TC, false>), zgrid, dim3(kBlock), 0, st, u, f, gf, (C)inv_h2,
-                               (C)out_scale, gc, fc, ec, gr, pblocks, kch);
+                               (C)out_scale, gc, fc, ec, gr, pblocks, kch, sh2, inv2d);
     } else {
         if (rule)
             hipLaunchKernelGGL((k_resid_restrict<2, TF, TC, true>), grid, dim3(kBlock), 0, st, u, f, gf, (C)inv_h2,
-                               (C)out_scale, gc, fc, ec, gr);
+                               (C)out_scale, gc, fc, ec, gr, sh2, inv2d);
         else
             hipLaunchKernelGGL((k_resid_restrict<2, TF, TC, false>), grid, dim3(kBlock), 0, st, u, f, gf, (C)inv_h2,
-                               (C)out_scale, gc, fc, ec, gr);
+                               (C)out_scale, gc, fc, ec, gr, sh2, inv2d);
     }
 }
 
@@ -2497,11 +2517,11 @@ template void launch_half_sweep<double>(int, hipStream_t, SGrid, double*, const 
 template void launch_half_sweep<float>(int, hipStream_t, SGrid, float*, const float*, int, double, int, int, double);
 template void launch_half_sweep<__half>(int, hipStream_t, SGrid, __half*, const __half*, int, double, int, int, double);
 template void launch_resid_restrict<double, double>(int, hipStream_t, SGrid, const double*, const double*, double,
-                                                    double, SGrid, double*, double*, int, int, double);
+                                                    double, SGrid, double*, double*, int, int, double, double);
 template void launch_resid_restrict<float, float>(int, hipStream_t, SGrid, const float*, const float*, double, double,
-                                                  SGrid, float*, float*, int, int, double);
+                                                  SGrid, float*, float*, int, int, double, double);
 template void launch_resid_restrict<__half, float>(int, hipStream_t, SGrid, const __half*, const __half*, double,
-                                                   double, SGrid, float*, float*, int, int, double);
+                                                   double, SGrid, float*, float*, int, int, double, double);
 template void launch_prolong_add<double, double>(int, hipStream_t, SGrid, const double*, SGrid, double*, int, int, double);
 template void launch_prolong_add<float, float>(int, hipStream_t, SGrid, const float*, SGrid, float*, int, int, double);
 template void launch_prolong_add<float, __half>(int, hipStream_t, SGrid, const float*, SGrid, __half*, int, int, double);

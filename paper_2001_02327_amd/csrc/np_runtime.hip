@@ -275,10 +275,10 @@ MGView<T> mg_view(const np_solver* s, int l, T* const* mu, T* const* mf)
 // level's rule (Sec. 2.4), evaluated by the kernels where they read it; that is
 // the same as refreshing it before each half sweep.
 template <typename T>
-void coarse_sweep(const np_solver* s, int l, const MGView<T>& v, int L, hipStream_t st)
+void coarse_sweep(const np_solver* s, int l, const MGView<T>& v, int L, hipStream_t st, int first_colour = 0)
 {
     const int d = s->cfg.dim;
-    for (int colour = 0; colour < 2; colour++)
+    for (int colour = first_colour; colour < 2; colour++)
         launch_half_sweep<T>(d, st, v.g[L], v.u[L], v.f[L], colour, v.h[L] * v.h[L], 0, s->plan.xn_is_one[l][L],
                              s->plan.ghost_coef[l][L]);
 }
@@ -326,17 +326,21 @@ void coarse_part(const np_solver* s, int l, const MGView<T>& v, hipStream_t st)
         tail(1);
         return;
     }
-    for (int it = 0; it < c.n_pre; it++) coarse_sweep(s, l, v, 1, st);
+    // the restriction into a level that the tail does not take has already done
+    // that level's first red half sweep (seeded correction)
+    for (int it = 0; it < c.n_pre; it++) coarse_sweep(s, l, v, 1, st, it == 0 ? 1 : 0);
     int L = 1;
     while (s->plan.N[l][L] > 1) {
+        const bool seed = c.n_pre > 0 && L + 1 != Lt;
         launch_resid_restrict<T, T>(d, st, v.g[L], v.u[L], v.f[L], 1.0 / (v.h[L] * v.h[L]), 1.0, v.g[L + 1], v.f[L + 1],
-                                    v.u[L + 1], 1, s->plan.xn_is_one[l][L], s->plan.ghost_coef[l][L]);
+                                    v.u[L + 1], 1, s->plan.xn_is_one[l][L], s->plan.ghost_coef[l][L],
+                                    seed ? v.h[L + 1] * v.h[L + 1] : 0.0);
         if (L + 1 == Lt) {
             tail(Lt);
             L = Lt;
             break;
         }
-        for (int it = 0; it < c.n_pre; it++) coarse_sweep(s, l, v, L + 1, st);
+        for (int it = 0; it < c.n_pre; it++) coarse_sweep(s, l, v, L + 1, st, it == 0 ? 1 : 0);
         L++;
     }
     while (L > 1) {
@@ -393,8 +397,12 @@ int vcycle_t(np_solver* s, int l, T0* u0, const T0* f0, double h2_0, double inv_
         }
     };
     for (int it = 0; it < c.n_pre; it++) sweep0();
+    // the restriction does multigrid level 1's first red half sweep unless the
+    // coarse tail starts at level 1 (coarse_part then skips it)
+    const bool seed1 = c.n_pre > 0 && tail_level(s, l, sizeof(TC)) != 1;
     prof_begin(s, NP_KCLASS_RESTRICT);
-    launch_resid_restrict<T0, TC>(d, st, v.g[0], u0, f0, inv_h2_0, out_scale_0, v.g[1], v.f[1], v.u[1], 0, 0, 0.0);
+    launch_resid_restrict<T0, TC>(d, st, v.g[0], u0, f0, inv_h2_0, out_scale_0, v.g[1], v.f[1], v.u[1], 0, 0, 0.0,
+                                  seed1 ? v.h[1] * v.h[1] : 0.0);
     prof_end(s);
     prof_begin(s, NP_KCLASS_COARSE);
     int rc = run_coarse(s, l, v, exec);
