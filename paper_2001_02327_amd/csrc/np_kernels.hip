@@ -2063,7 +2063,9 @@ __device__ __forceinline__ Pair<double> dc_pair(const DcIn<TL, UPD>& in, size_t 
 constexpr int kDcChunk = 8;  // planes per thread of the paired DC pass (aligned layout: 2, 4, 8 give 1.02, 0.93, 0.91 ms)
 constexpr int kDcGroup = 2;  // planes of the DC pass whose loads are issued together (1, 2, 4 measured alike)
 
-template <typename TL, bool UPD>
+// OUT = false: only the max norm of the residual (the stop test's residual
+// pass), no outputs.
+template <typename TL, bool UPD, bool OUT = true>
 __global__ void __launch_bounds__(kBlock) k_dc_outer3_pair(SGrid g, DcIn<TL, UPD> in, double* __restrict__ pout,
                                                            const double* __restrict__ f, double inv_h2, double rscale,
                                                            TL* __restrict__ r, TL* __restrict__ eout, int first_red,
@@ -2153,23 +2155,29 @@ __global__ void __launch_bounds__(kBlock) k_dc_outer3_pair(SGrid g, DcIn<TL, UPD
                 }
                 if (a0 && a1) {
                     if (UPD) *(Pair<double>*)(pout + self) = cur[c];
-                    *(Pair<TL>*)(r + self) = rl;
-                    *(Pair<TL>*)(eout + self) = el;
+                    if (OUT) {
+                        *(Pair<TL>*)(r + self) = rl;
+                        *(Pair<TL>*)(eout + self) = el;
+                    }
                     unsigned long long b0 = abs_bits(v0), b1 = abs_bits(v1);
                     b0 = b1 > b0 ? b1 : b0;
                     best = b0 > best ? b0 : best;
                 } else {
                     if (a0) {
                         if (UPD) pout[self] = cur[c].a;
-                        r[self] = rl.a;
-                        eout[self] = el.a;
+                        if (OUT) {
+                            r[self] = rl.a;
+                            eout[self] = el.a;
+                        }
                         unsigned long long b0 = abs_bits(v0);
                         best = b0 > best ? b0 : best;
                     }
                     if (a1) {
                         if (UPD) pout[self + 1] = cur[c].b;
-                        r[self + 1] = rl.b;
-                        eout[self + 1] = el.b;
+                        if (OUT) {
+                            r[self + 1] = rl.b;
+                            eout[self + 1] = el.b;
+                        }
                         unsigned long long b1 = abs_bits(v1);
                         best = b1 > best ? b1 : best;
                     }
@@ -2291,6 +2299,15 @@ void launch_export(int dim, hipStream_t st, SGrid g, const double* a, double* ou
 void launch_norm(int dim, hipStream_t st, SGrid g, const double* u, const double* f, double inv_h2, int mode,
                  unsigned long long* maxbits)
 {
+    if (dim == 3 && mode == 0 && g.hx % 2 == 0) {
+        // the paired DC pass without outputs: same residual, same order of operations
+        const long m = g.nx - 2;
+        const int pblocks = ceil_div((long)(g.ps / 2), kBlock);
+        hipLaunchKernelGGL((k_dc_outer3_pair<float, false, false>), dim3(pblocks * ceil_div(m, kDcChunk)), dim3(kBlock), 0,
+                           st, g, DcIn<float, false>{u, nullptr, 0.0}, nullptr, f, inv_h2, 0.0, nullptr, nullptr, 0, 0.0f,
+                           0.0f, pblocks, maxbits);
+        return;
+    }
     if (dim == 3 && mode == 0) {
         long m = g.nx - 2;
         int pblocks = ceil_div((long)g.ps, kBlock);
