@@ -25,6 +25,12 @@ __device__ __forceinline__ long xcd_block()
     return x * q + (x < r ? x : r) + k;
 }
 
+// Two consecutive elements moved by one load or store of twice the width.
+template <typename T>
+struct alignas(2 * sizeof(T)) Pair {
+    T a, b;
+};
+
 // Consecutive level-0 kernels of a V-cycle run their z-chunks in alternating
 // directions (rev: the logical block order reversed), so that each starts on
 // the planes the previous one touched last, which the memory-side cache still
@@ -362,6 +368,142 @@ __global__ void __launch_bounds__(kBlock) k_interface_fill3_zm(SGrid gc, const d
                 cv[2][y][x] = nxt[y][x];
             }
     }
+    }
+    if (fmax) block_max_to(best, fmax);
+}
+
+// 3-D coarse-to-fine fill in the paired form of the level-0 kernels: a thread
+// owns the compact pair (h0, h0 + 1) of one fine row pj in both colours (the
+// four fine points x = 2 h0 .. 2 h0 + 3), numbered flat over the padded plane
+// (aligned waves), and a chunk of fine-plane pairs (2c + 2, 2c + 3), which share
+// the coarse parent plane.  Their parents and neighbours lie among the coarse
+// columns offx + h0 .. offx + h0 + 3 of two coarse rows; per coarse plane the
+// four x-interpolants of each row are formed once.  Potential and right-hand
+// side go out as paired stores, the density comes in 16-byte loads.  Same
+// values, in the same order of operations, as k_interface_fill.  Requires an
+// even row length hx and a coarse array of fewer than 2^31 elements.
+constexpr int kFillPairChunk = 4;  // fine-plane pairs per thread
+
+__global__ void __launch_bounds__(kBlock) k_interface_fill3_pair(SGrid gc, const double* __restrict__ phic,
+                                                                 const double* __restrict__ fc, SGrid gf, int nf,
+                                                                 int offx, int offy, int offz,
+                                                                 const double* __restrict__ rho, double fourpiG,
+                                                                 double* __restrict__ phif, double* __restrict__ ff,
+                                                                 int pblocks, unsigned long long* fmax)
+{
+    const int nx = gf.nx, last = nx - 1;
+    const int lb = (int)xcd_block();
+    const int zc = lb / pblocks;
+    const int t = (lb - zc * pblocks) * kBlock + (int)threadIdx.x;
+    const int q = 2 * t;
+    const int pj = q / gf.hx;
+    const int h0 = q - pj * gf.hx;
+    unsigned long long best = 0;  // max |f| written (the outer layer's 0 does not raise it)
+    if (pj < nx) {
+        const int c0 = -1 + zc * kFillPairChunk;
+        const int c1 = min(c0 + kFillPairChunk, nx / 2 - 1);  // pairs c0 .. c1 - 1
+        const int fyy = pj - 2;
+        const int qy = offy + 2 + (fyy >> 1), sy = (fyy & 1) ? 1 : -1;
+        const int cxb = offx + h0;  // coarse columns cxb .. cxb + 3
+        // offsets inside a coarse plane of (row y, column x) for an even / odd plane index
+        unsigned off[2][2][4];
+#pragma unroll
+        for (int y = 0; y < 2; y++)
+#pragma unroll
+            for (int x = 0; x < 4; x++) {
+                const int cyv = y ? qy + sy : qy, cxv = cxb + x;
+                const unsigned o = (unsigned)(cyv * gc.hx + (cxv >> 1));
+                const bool ce = ((cxv + cyv + 3) & 1) != 0;  // colour on an even plane
+                off[0][y][x] = o + (ce ? (unsigned)gc.cs : 0u);
+                off[1][y][x] = o + (ce ? 0u : (unsigned)gc.cs);
+            }
+        const double w0 = 0.75, w1 = 0.25;
+        // X[y][a]: x-interpolant of coarse plane qz, row y (parent, side), for the fine point 2 h0 + a
+        auto load_X = [&](int qz, double (&X)[2][4]) {
+            const double* __restrict__ cp = phic + (size_t)qz * gc.ps;
+            double cv[2][4];
+#pragma unroll
+            for (int y = 0; y < 2; y++)
+#pragma unroll
+                for (int x = 0; x < 4; x++) cv[y][x] = cp[(qz & 1) ? off[1][y][x] : off[0][y][x]];
+#pragma unroll
+            for (int y = 0; y < 2; y++) {
+                X[y][0] = w0 * cv[y][1] + w1 * cv[y][0];
+                X[y][1] = w0 * cv[y][1] + w1 * cv[y][2];
+                X[y][2] = w0 * cv[y][2] + w1 * cv[y][1];
+                X[y][3] = w0 * cv[y][2] + w1 * cv[y][3];
+            }
+        };
+        double Xm[2][4], X0[2][4], Xp[2][4];  // coarse planes qk - 1, qk, qk + 1
+        load_X(offz + 1 + c0, Xm);
+        load_X(offz + 2 + c0, X0);
+        load_X(offz + 3 + c0, Xp);
+        const bool yomega = pj >= 2 && pj <= nf + 1;
+        const size_t prow = (size_t)pj * gf.hx + h0;
+        for (int c = c0; c < c1; c++) {
+            const int qk = offz + 2 + c;
+            double Xn[2][4];
+            if (c + 1 < c1) load_X(qk + 2, Xn);
+#pragma unroll
+            for (int d = 0; d < 2; d++) {
+                const int p = 2 * c + 2 + d;  // fine plane; its side coarse plane is qk - 1 (d = 0) or qk + 1
+                const bool omega_row = yomega && p >= 2 && p <= nf + 1;
+                double rv[4] = {0.0, 0.0, 0.0, 0.0};
+                if (omega_row) {
+                    const int x0 = 2 * h0 - 2;  // natural x of the pair's first point
+                    const double* __restrict__ rr = rho + ((size_t)(p - 2) * nf + (pj - 2)) * nf;
+                    if (x0 >= 0 && x0 + 1 <= nf - 1) {
+                        const Pair<double> v = *(const Pair<double>*)(rr + x0);
+                        rv[0] = v.a;
+                        rv[1] = v.b;
+                    }
+                    if (x0 + 2 >= 0 && x0 + 3 <= nf - 1) {
+                        const Pair<double> v = *(const Pair<double>*)(rr + x0 + 2);
+                        rv[2] = v.a;
+                        rv[3] = v.b;
+                    }
+                }
+                double ph[4], fv[4];
+#pragma unroll
+                for (int a = 0; a < 4; a++) {
+                    const double(&S)[2][4] = d ? Xp : Xm;
+                    const double z0 = w0 * X0[0][a] + w1 * X0[1][a];
+                    const double z1 = w0 * S[0][a] + w1 * S[1][a];
+                    ph[a] = w0 * z0 + w1 * z1;
+                    const int pi = 2 * h0 + a;
+                    const bool outer = pi == 0 || pi == last || pj == 0 || pj == last || p == 0 || p == last;
+                    const bool omega = omega_row && pi >= 2 && pi <= nf + 1;
+                    double v;
+                    if (outer) {
+                        v = 0.0;
+                    } else if (omega) {
+                        v = fourpiG * rv[a];
+                    } else {
+                        v = interp_tensor<3>(fc, gc, offx + 1 + h0 + (a >> 1), qy, qk, (a & 1) ? 1 : -1, sy,
+                                             d ? 1 : -1);
+                    }
+                    fv[a] = v;
+                    const unsigned long long bv = abs_bits(v);
+                    best = bv > best ? bv : best;
+                }
+                // colour of the even-x points 2 h0, 2 h0 + 2 in this row and plane
+                const int ce = (pj + p + 1) & 1;
+                const size_t base = (size_t)p * gf.ps + prow;
+                Pair<double> pe{ph[0], ph[2]}, po{ph[1], ph[3]}, fe{fv[0], fv[2]}, fo{fv[1], fv[3]};
+                *(Pair<double>*)(phif + (size_t)ce * gf.cs + base) = pe;
+                *(Pair<double>*)(phif + (size_t)(ce ^ 1) * gf.cs + base) = po;
+                *(Pair<double>*)(ff + (size_t)ce * gf.cs + base) = fe;
+                *(Pair<double>*)(ff + (size_t)(ce ^ 1) * gf.cs + base) = fo;
+            }
+#pragma unroll
+            for (int y = 0; y < 2; y++)
+#pragma unroll
+                for (int x = 0; x < 4; x++) {
+                    Xm[y][x] = X0[y][x];
+                    X0[y][x] = Xp[y][x];
+                    Xp[y][x] = Xn[y][x];
+                }
+        }
     }
     if (fmax) block_max_to(best, fmax);
 }
@@ -930,11 +1072,6 @@ __device__ __forceinline__ float mix_add2(uint32_t a, uint32_t b)
 // single load.  Same arithmetic, in the same order, as k_smooth_zmarch3.
 // Requires an even row length hx (so pairs never straddle rows and stay
 // aligned).
-template <typename T>
-struct alignas(2 * sizeof(T)) Pair {
-    T a, b;
-};
-
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_smooth_zmarch3_pair(T* __restrict__ u, const T* __restrict__ f, SGrid g,
                                                                 int colour, typename Compute<T>::type h2,
@@ -2258,6 +2395,13 @@ void launch_interface_fill(int dim, hipStream_t st, SGrid gc, const double* phic
                            int nf, int offx, int offy, int offz, const double* rho, double fourpiG, double* phif,
                            double* ff, unsigned long long* fmax)
 {
+    if (dim == 3 && gf.hx % 2 == 0 && 2 * gc.cs < (1ull << 31)) {
+        const int pblocks = ceil_div((long)(gf.ps / 2), kBlock);
+        const int chunks = ceil_div(gf.nx / 2, kFillPairChunk);
+        hipLaunchKernelGGL(k_interface_fill3_pair, dim3(pblocks * chunks), dim3(kBlock), 0, st, gc, phic, fc, gf, nf, offx,
+                           offy, offz, rho, fourpiG, phif, ff, pblocks, fmax);
+        return;
+    }
     if (dim == 3) {
         const long Mq = (gf.nx + 1) / 2;
         const int pblocks = ceil_div(Mq * Mq, kBlock);
