@@ -1072,12 +1072,24 @@ __device__ __forceinline__ float mix_add2(uint32_t a, uint32_t b)
 // single load.  Same arithmetic, in the same order, as k_smooth_zmarch3.
 // Requires an even row length hx (so pairs never straddle rows and stay
 // aligned).
-template <typename T>
+// SEED: the first black half sweep of a defect-correction step whose red points
+// hold the result of a red half sweep from zero, e = (0 - h2 r) / (2d), which is
+// not stored: the red values are formed from the defect f (red) here, in the
+// same arithmetic (its ghost layer is zero, as is the correction's).
+template <typename T, bool SEED = false>
 __global__ void __launch_bounds__(kBlock) k_smooth_zmarch3_pair(T* __restrict__ u, const T* __restrict__ f, SGrid g,
                                                                 int colour, typename Compute<T>::type h2,
                                                                 typename Compute<T>::type inv2d, int pblocks)
 {
     using C = typename Compute<T>::type;
+    const auto sv = [&](T v) -> T { return SEED ? (T)(((C)0 - h2 * (C)v) * inv2d) : v; };
+    const auto sp = [&](Pair<T> v) -> Pair<T> {
+        if (SEED) {
+            v.a = sv(v.a);
+            v.b = sv(v.b);
+        }
+        return v;
+    };
     const int m = g.nx - 2;
     const int lb = zmarch_block(colour);  // red half sweeps up, black down
     const int zc = lb / pblocks;
@@ -1094,11 +1106,11 @@ __global__ void __launch_bounds__(kBlock) k_smooth_zmarch3_pair(T* __restrict__ 
     const int k1 = min(k0 + kZChunk - 1, m);
     const size_t plane = g.ps;
     const size_t col = (size_t)pj * g.hx + h0;
-    const T* __restrict__ o = u + (size_t)(colour ^ 1) * g.cs;
+    const T* __restrict__ o = (SEED ? f : u) + (size_t)(colour ^ 1) * g.cs;
     T* __restrict__ uc = u + (size_t)colour * g.cs;
     const T* __restrict__ fc = f + (size_t)colour * g.cs;
-    Pair<T> below = *(const Pair<T>*)(o + (size_t)(k0 - 1) * plane + col);
-    Pair<T> cur = *(const Pair<T>*)(o + (size_t)k0 * plane + col);
+    Pair<T> below = sp(*(const Pair<T>*)(o + (size_t)(k0 - 1) * plane + col));
+    Pair<T> cur = sp(*(const Pair<T>*)(o + (size_t)k0 * plane + col));
     auto step = [&](int pk, const Pair<T>& above, const Pair<T>& ym, const Pair<T>& yp, const Pair<T>& fv, T exh) {
         const C ex = (C)exh;
         const size_t here = (size_t)pk * plane + col;
@@ -1160,7 +1172,7 @@ __global__ void __launch_bounds__(kBlock) k_smooth_zmarch3_pair(T* __restrict__ 
         cur = above;
     };
     // the extra x-neighbour stays inside the plane (neighbouring row at the row ends)
-    auto extra = [&](int pk, size_t here) -> T { return o[((colour + pj + pk + 3) & 1) ? here + 2 : here - 1]; };
+    auto extra = [&](int pk, size_t here) -> T { return sv(o[((colour + pj + pk + 3) & 1) ? here + 2 : here - 1]); };
     if (k1 - k0 + 1 == kZChunk) {
         // a full chunk: every load of its planes is issued before the first
         // update, so that each wave keeps ~20 loads in flight
@@ -1176,9 +1188,9 @@ __global__ void __launch_bounds__(kBlock) k_smooth_zmarch3_pair(T* __restrict__ 
 #pragma unroll
             for (int q = 0; q < kZChunk; q++) {
                 const size_t here = (size_t)(k0 + q) * plane + col;
-                ab[q] = *(const Pair<T>*)(o + here + plane);
-                ym[q] = *(const Pair<T>*)(o + here - g.hx);
-                yp[q] = *(const Pair<T>*)(o + here + g.hx);
+                ab[q] = sp(*(const Pair<T>*)(o + here + plane));
+                ym[q] = sp(*(const Pair<T>*)(o + here - g.hx));
+                yp[q] = sp(*(const Pair<T>*)(o + here + g.hx));
                 fv[q] = *(const Pair<T>*)(fc + here);
                 const int par = (colour + pj + k0 + q + 3) & 1;
                 if (par ? lane == 63 : lane == 0) ex[q] = extra(k0 + q, here);
@@ -1196,9 +1208,9 @@ __global__ void __launch_bounds__(kBlock) k_smooth_zmarch3_pair(T* __restrict__ 
 #pragma unroll
         for (int q = 0; q < kZChunk; q++) {
             const size_t here = (size_t)(k0 + q) * plane + col;
-            ab[q] = *(const Pair<T>*)(o + here + plane);
-            ym[q] = *(const Pair<T>*)(o + here - g.hx);
-            yp[q] = *(const Pair<T>*)(o + here + g.hx);
+            ab[q] = sp(*(const Pair<T>*)(o + here + plane));
+            ym[q] = sp(*(const Pair<T>*)(o + here - g.hx));
+            yp[q] = sp(*(const Pair<T>*)(o + here + g.hx));
             fv[q] = *(const Pair<T>*)(fc + here);
             ex[q] = extra(k0 + q, here);
         }
@@ -1208,8 +1220,8 @@ __global__ void __launch_bounds__(kBlock) k_smooth_zmarch3_pair(T* __restrict__ 
     }
     for (int pk = k0; pk <= k1; pk++) {
         const size_t here = (size_t)pk * plane + col;
-        step(pk, *(const Pair<T>*)(o + here + plane), *(const Pair<T>*)(o + here - g.hx),
-             *(const Pair<T>*)(o + here + g.hx), *(const Pair<T>*)(fc + here), extra(pk, here));
+        step(pk, sp(*(const Pair<T>*)(o + here + plane)), sp(*(const Pair<T>*)(o + here - g.hx)),
+             sp(*(const Pair<T>*)(o + here + g.hx)), *(const Pair<T>*)(fc + here), extra(pk, here));
     }
 }
 
@@ -2201,7 +2213,8 @@ constexpr int kDcChunk = 8;  // planes per thread of the paired DC pass (aligned
 constexpr int kDcGroup = 2;  // planes of the DC pass whose loads are issued together (1, 2, 4 measured alike)
 
 // OUT = false: only the max norm of the residual (the stop test's residual
-// pass), no outputs.
+// pass), no outputs.  eout == nullptr: the next correction's start is not
+// stored (its first black half sweep forms the red values from r).
 template <typename TL, bool UPD, bool OUT = true>
 __global__ void __launch_bounds__(kBlock) k_dc_outer3_pair(SGrid g, DcIn<TL, UPD> in, double* __restrict__ pout,
                                                            const double* __restrict__ f, double inv_h2, double rscale,
@@ -2294,7 +2307,7 @@ __global__ void __launch_bounds__(kBlock) k_dc_outer3_pair(SGrid g, DcIn<TL, UPD
                     if (UPD) *(Pair<double>*)(pout + self) = cur[c];
                     if (OUT) {
                         *(Pair<TL>*)(r + self) = rl;
-                        *(Pair<TL>*)(eout + self) = el;
+                        if (eout) *(Pair<TL>*)(eout + self) = el;
                     }
                     unsigned long long b0 = abs_bits(v0), b1 = abs_bits(v1);
                     b0 = b1 > b0 ? b1 : b0;
@@ -2304,7 +2317,7 @@ __global__ void __launch_bounds__(kBlock) k_dc_outer3_pair(SGrid g, DcIn<TL, UPD
                         if (UPD) pout[self] = cur[c].a;
                         if (OUT) {
                             r[self] = rl.a;
-                            eout[self] = el.a;
+                            if (eout) eout[self] = el.a;
                         }
                         unsigned long long b0 = abs_bits(v0);
                         best = b0 > best ? b0 : best;
@@ -2313,7 +2326,7 @@ __global__ void __launch_bounds__(kBlock) k_dc_outer3_pair(SGrid g, DcIn<TL, UPD
                         if (UPD) pout[self + 1] = cur[c].b;
                         if (OUT) {
                             r[self + 1] = rl.b;
-                            eout[self + 1] = el.b;
+                            if (eout) eout[self + 1] = el.b;
                         }
                         unsigned long long b1 = abs_bits(v1);
                         best = b1 > best ? b1 : best;
@@ -2513,6 +2526,17 @@ void launch_half_sweep(int dim, hipStream_t st, SGrid g, T* u, const T* f, int c
     }
 }
 
+template <typename T>
+void launch_half_sweep_seeded(hipStream_t st, SGrid g, T* u, const T* f, double h2)
+{
+    using C = typename Compute<T>::type;
+    const long m = g.nx - 2;
+    const int pblocks = ceil_div((long)(g.ps / 2), kBlock);
+    const int chunks = ceil_div(m, kZChunk0);
+    hipLaunchKernelGGL((k_smooth_zmarch3_pair<T, true>), dim3(pblocks * chunks), dim3(kBlock), 0, st, u, f, g, 1, (C)h2,
+                       (C)(1.0 / 6.0), pblocks);
+}
+
 template <typename TF, typename TC>
 void launch_resid_restrict(int dim, hipStream_t st, SGrid gf, const TF* u, const TF* f, double inv_h2, double out_scale,
                            SGrid gc, TC* fc, TC* ec, int rule, int xn1, double coef, double seed_h2)
@@ -2677,6 +2701,8 @@ void launch_copy_ghosts(int dim, hipStream_t st, SGrid g, const double* src, dou
 template void launch_half_sweep<double>(int, hipStream_t, SGrid, double*, const double*, int, double, int, int, double);
 template void launch_half_sweep<float>(int, hipStream_t, SGrid, float*, const float*, int, double, int, int, double);
 template void launch_half_sweep<__half>(int, hipStream_t, SGrid, __half*, const __half*, int, double, int, int, double);
+template void launch_half_sweep_seeded<float>(hipStream_t, SGrid, float*, const float*, double);
+template void launch_half_sweep_seeded<__half>(hipStream_t, SGrid, __half*, const __half*, double);
 template void launch_resid_restrict<double, double>(int, hipStream_t, SGrid, const double*, const double*, double,
                                                     double, SGrid, double*, double*, int, int, double, double);
 template void launch_resid_restrict<float, float>(int, hipStream_t, SGrid, const float*, const float*, double, double,

@@ -383,17 +383,24 @@ int run_coarse(np_solver* s, int l, const MGView<T>& v, hipGraphExec_t* exec)
 // defect-correction outer pass) and the cycle starts with black.
 template <typename T0, typename TC>
 int vcycle_t(np_solver* s, int l, T0* u0, const T0* f0, double h2_0, double inv_h2_0, double out_scale_0,
-             const MGView<TC>& v, hipGraphExec_t* exec, bool red_done = false)
+             const MGView<TC>& v, hipGraphExec_t* exec, bool red_done = false, bool red_unstored = false)
 {
     const np_config& c = s->cfg;
     const int d = c.dim;
     hipStream_t st = s->stream;
     auto sweep0 = [&]() {
         for (int colour = red_done ? 1 : 0; colour < 2; colour++) {
-            red_done = false;
             prof_begin(s, NP_KCLASS_SMOOTH);
-            launch_half_sweep<T0>(d, st, v.g[0], u0, f0, colour, h2_0, 1, 0, 0.0);
+            bool seeded = false;
+            if constexpr (sizeof(T0) <= 4) {
+                if (red_done && red_unstored) {
+                    launch_half_sweep_seeded<T0>(st, v.g[0], u0, f0, h2_0);
+                    seeded = true;
+                }
+            }
+            if (!seeded) launch_half_sweep<T0>(d, st, v.g[0], u0, f0, colour, h2_0, 1, 0, 0.0);
             prof_end(s);
+            red_done = false;
         }
     };
     for (int it = 0; it < c.n_pre; it++) sweep0();
@@ -430,13 +437,23 @@ int vcycle(np_solver* s, int l)
 // L e'' = r'' (L = h^2 lap, the integer stencil, r'' = r / ||r||) in low
 // precision TL, with FP32 coarse levels: the coarse right-hand side is
 // R(r'' - L e'') / h^2, in the same units as e''.
+// Whether the outer pass leaves the next correction's start unstored: its
+// first black half sweep then forms the red values (the red half sweep from
+// zero) from the defect.  Needs a red half sweep to follow that black one
+// before anything reads red (n_pre >= 2) and the paired level-0 sweep.
+bool dc_seed_black(const np_solver* s, int l)
+{
+    const np_config& c = s->cfg;
+    return c.precision != NP_PREC_FP64 && c.dim == 3 && c.n_pre >= 2 && (s->lg[l].hx % 2) == 0;
+}
+
 template <typename TL>
 int vcycle_lo(np_solver* s, int l, bool red_done)
 {
     MGView<float> v = mg_view<float>(s, l, s->mg_u32, s->mg_f32);
     double h = v.h[0];
     return vcycle_t<TL, float>(s, l, (TL*)s->e_lo, (const TL*)s->r_lo, 1.0, 1.0, 1.0 / (h * h), v, s->coarse_exec32,
-                               red_done);
+                               red_done, red_done && dc_seed_black(s, l));
 }
 
 // Queue a norm into slot `slot` and return it (host-synchronous).
@@ -477,7 +494,7 @@ int dc_outer_sync(np_solver* s, int l, bool update, double factor, double rscale
     double dx = std::ldexp(c.dx0, -l);
     int first_red = c.n_pre > 0;
     void* e_in = update ? s->e_lo : nullptr;
-    void* e_out = update ? s->e_nx : s->e_lo;
+    void* e_out = dc_seed_black(s, l) ? nullptr : (update ? s->e_nx : s->e_lo);
     double* p_out = update ? s->phi_alt : nullptr;
     launch_set_u64(s->stream, s->d_bits, 1, 0ULL);
     prof_begin(s, NP_KCLASS_DC);
@@ -884,6 +901,9 @@ int nested_poisson_solve(np_solver* s, const double* const* rho, const double* p
             size_t esz = c.precision == NP_PREC_FP16S_DC ? sizeof(__half) : sizeof(float);
             HIPCHK(s, hipMemsetAsync(s->e_lo, 0, 2 * s->lg[l].cs * esz, s->stream));
             HIPCHK(s, hipMemsetAsync(s->e_nx, 0, 2 * s->lg[l].cs * esz, s->stream));
+            // the defect's ghost layer stands in for the correction's (zero) where
+            // a black half sweep forms the red values from the defect
+            if (dc_seed_black(s, l)) HIPCHK(s, hipMemsetAsync(s->r_lo, 0, 2 * s->lg[l].cs * esz, s->stream));
             // the outer pass writes only active points of the other potential
             // buffer: give it this level's fixed ghost layer
             launch_copy_ghosts(c.dim, s->stream, s->lg[l], s->phi[l], s->phi_alt);
