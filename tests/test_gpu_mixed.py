@@ -111,20 +111,30 @@ def _ragged_levels_3d():
     return W.Workload("ragged3d_16_8_12", g, W.Plummer([(1.0, 0.1, (0.02, -0.03, 0.01))]))
 
 
+def _odd_rows_3d():
+    # n = 22: 13 compact points per row (odd), so level 0 takes the unpaired
+    # outer pass, which always stores the next correction's start; level 1
+    # (n = 12, 8 per row) the paired one
+    g = W.Geometry(dim=3, n=[22, 12], off=[(0, 0, 0), (5, 4, 6)], lo0=(-0.5, -0.5, -0.5), dx0=1.0 / 22)
+    return W.Workload("odd_rows3d_22_12", g, W.Plummer([(1.0, 0.09, (0.03, 0.01, -0.02))]))
+
+
 def _ragged_levels_2d():
     g = W.Geometry(dim=2, n=[30, 14, 6], off=[(0, 0, 0), (5, 9, 0), (3, 2, 0)], lo0=(-0.5, -0.5, 0.0),
                    dx0=1.0 / 30, G=1.0)
     return W.Workload("ragged2d_30_14_6", g, W.Gaussian(0.15, 1.0))
 
 
-@pytest.mark.parametrize("n_pre,inner", [(2, 1), (0, 1), (1, 2), (2, 3)])
+@pytest.mark.parametrize("n_pre,inner", [(2, 1), (0, 1), (1, 2), (2, 3), (3, 2)])
 @pytest.mark.parametrize("precision", ["fp32_dc", "fp16s_dc"])
-@pytest.mark.parametrize("make", [_ragged_levels_3d, _ragged_levels_2d], ids=["3d", "2d"])
+@pytest.mark.parametrize("make", [_ragged_levels_3d, _odd_rows_3d, _ragged_levels_2d], ids=["3d", "3d_odd_rows", "2d"])
 def test_dc_ragged_levels_and_schedules(make, precision, n_pre, inner):
     """Levels of different sizes, with and without pre-smoothing (the outer
     pass then starts the correction at zero instead of relaxing its red
-    points) and with several inner cycles: the FP64 outer iteration still
-    reaches the oracle's converged solution."""
+    points; with two or more pre-sweeps on even rows that start is not stored
+    and the first black half sweep forms it from the defect) and with several
+    inner cycles: the FP64 outer iteration still reaches the oracle's
+    converged solution."""
     wl = make()
     rho, po = W.make_inputs(wl.geom, wl.prob)
     ref = core.solve(wl.geom, [r.numpy() for r in rho], po.numpy(), tol=1e-13, max_cycles=200, n_pre=n_pre,
