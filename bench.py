@@ -26,9 +26,9 @@ METRIC = "nested solve time at fixed Linf force error; smoother GB/s; plain vs m
 PEAK_HBM_GBS = 8000.0   # MI355X HBM3E peak
 # HBM bytes per level-0 half sweep at 514^3 measured with rocprofv3 (FETCH_SIZE x 2.0 +
 # WRITE_SIZE x 1.0, the factors a 1 GiB device copy and fill give) for the smoother
-# kernel of this source tree: k_smooth_zmarch3_pair<__half> (FP16 storage).  Valid only
-# for that kernel at that size.
-SMOOTHER_TRAFFIC = {("fp16s_dc", 514): 0.2917e9 + 0.1363e9}
+# kernels of this source tree: k_smooth_zmarch3_pair<__half> (FP16 storage) and
+# k_smooth_zmarch3<double> (FP64).  Valid only for those kernels at that size.
+SMOOTHER_TRAFFIC = {("fp16s_dc", 514): 0.2908e9 + 0.1363e9, ("fp64", 514): 1.3696e9 + 0.5453e9}
 
 
 def log(*a):
