@@ -59,7 +59,7 @@ extern "C" {
 #define NP_ENODEV (-8)      /* no HIP device available */
 
 /* stop rules (Sec. 2.3 step 14 and Sec. 3.1) */
-#define NP_STOP_RESIDUAL 0    /* ||f - lap Phi||_inf <= tol * ||f||_inf on the patch and its inner layer */
+#define NP_STOP_RESIDUAL 0    /* ||f - lap Phi||_inf <= tol * ||f||_inf over the relaxed points */
 #define NP_STOP_FORCE_DELTA 1 /* max over the patch of |F^q - F^{q-1}| < tol (the paper's rule) */
 
 /* arithmetic of the V-cycles */
@@ -71,6 +71,13 @@ extern "C" {
 /* initial guess of levels l >= 1 */
 #define NP_GUESS_INTERP 0  /* interpolated from level l-1 (Sec. 2.4) */
 #define NP_GUESS_LEARNED 1 /* interpolated guess plus the correction predicted by the conv net */
+
+/* buffer zone of levels l >= 1 (Sec. 2.1 and Sec. 4, Fig. 4) */
+#define NP_BUFFER_RELAXED 0 /* the paper's method: the inner buffer layer is relaxed with the patch */
+#define NP_BUFFER_INTERP 1  /* comparison scheme of Sec. 4: both buffer layers keep the potential
+                               interpolated from level l-1 and only Omega^l is relaxed (the inner
+                               layer is its Dirichlet data); FP64, interpolated guess and the
+                               residual stop rule only */
 
 typedef struct np_config {
     int dim;                        /* 2 or 3 */
@@ -90,15 +97,17 @@ typedef struct np_config {
                                        storage), as many as the contraction measured so far
                                        says the stop test needs */
     int guess;                      /* NP_GUESS_* */
+    int buffer;                     /* NP_BUFFER_* */
 } np_config;
 
 /* Fills `cfg` with the paper's solver settings (N_pre = 2, N_post = 1,
  * Sec. 3) and tol = 1e-10, max_cycles = 50, FP64, residual stop,
- * interpolated guess.  Geometry fields are zeroed. */
+ * interpolated guess, relaxed buffer.  Geometry fields are zeroed. */
 void nested_poisson_default_config(np_config* cfg);
 
 /* Multigrid hierarchy of one patch (Sec. 2.2): N^0 = n + 2 (patch plus its
- * inner buffer layer), N^L = round(N^0 / 2^L) with halves rounded up, until
+ * inner buffer layer; N^0 = n on levels l >= 1 with NP_BUFFER_INTERP, where
+ * the patch alone is relaxed), N^L = round(N^0 / 2^L) with halves rounded up, until
  * N^L = 1.  For L >= 1, right-ghost rule of Sec. 2.4: xn_is_one[L] is 1 when
  * the right-most active centre sits exactly at x_MG = 1 (ghost = -e_{N-1}),
  * otherwise ghost = ghost_coef[L] * e_N, the value at x_N + h^L of the line

@@ -32,6 +32,7 @@ class OrcConfig(ctypes.Structure):
         ("max_cycles", ctypes.c_int),
         ("stop_rule", ctypes.c_int),
         ("ghost_literal", ctypes.c_int),
+        ("buffer_interp", ctypes.c_int),
     ]
 
 
@@ -162,7 +163,8 @@ def vcycle_patch(dim, h0, u, f, n_pre=2, n_post=1, literal=False):
 STATUS = {0: "ok", -1: "invalid", -2: "nonfinite", -3: "not converged", -4: "diverged"}
 
 
-def make_config(geom, n_pre=2, n_post=1, tol=1e-10, max_cycles=50, stop_rule=0, ghost_literal=False):
+def make_config(geom, n_pre=2, n_post=1, tol=1e-10, max_cycles=50, stop_rule=0, ghost_literal=False,
+                buffer_interp=False):
     c = OrcConfig()
     c.dim = geom.dim
     c.nlevels = geom.nlevels
@@ -177,6 +179,7 @@ def make_config(geom, n_pre=2, n_post=1, tol=1e-10, max_cycles=50, stop_rule=0, 
     c.max_cycles = max_cycles
     c.stop_rule = stop_rule
     c.ghost_literal = int(ghost_literal)
+    c.buffer_interp = int(buffer_interp)
     return c
 
 
@@ -187,6 +190,8 @@ def validate(geom):
 
 def solve(geom, rho, phi_outer, fixed_cycles=None, **kw):
     """Nested solve.  rho[0]: (n0+2)^d, rho[l>=1]: n_l^d, phi_outer: (n0+4)^d.
+    buffer_interp=True: the comparison scheme of Sec. 4 on levels l >= 1 (both
+    buffer layers interpolated from level l-1, only Omega^l relaxed).
 
     Returns dict(phi=[padded arrays], cycles, final_rel, hist, status)."""
     cfg = make_config(geom, **kw)

@@ -11,6 +11,9 @@ For each level l in order (one-way scheme, Sec. 2.1):
     caller's density (l = 0);
   * operator: the 5-/7-point Laplacian (eqn:Laplacian2D/3D) with the outer
     layer moved to the right-hand side.
+With buffer_interp (the comparison scheme of Sec. 4, levels l >= 1) the
+unknowns are the cells of Omega^l alone and the inner buffer layer keeps the
+interpolant of Phi^{l-1}, as Dirichlet data next to the outer layer's.
 The interpolation is evaluated from physical cell-centre coordinates (the
 bilinear/trilinear formula of Appendix A at the fine centre), not from index
 tables, so it is an independent route to the same weights.  The linear system
@@ -90,7 +93,7 @@ def _boundary_term(d, phi_padded, h):
     return b / (h * h)
 
 
-def solve(geom, rho, phi_outer):
+def solve(geom, rho, phi_outer, buffer_interp=False):
     """Exact nested solution.  Returns (phi_padded list, f_padded list)."""
     d = geom.dim
     fourpiG = 4 * math.pi * geom.G
@@ -109,11 +112,19 @@ def solve(geom, rho, phi_outer):
             phi[...] = _interp(geom, l, phis[l - 1], -2, n + 4)
             f[(slice(1, n + 3),) * d] = _interp(geom, l, fs[l - 1], -1, n + 2)
             f[core] = fourpiG * np.asarray(rho[l])
-        m = n + 2
-        A = _laplacian_system(d, m, h)
-        rhs = f[(slice(1, n + 3),) * d] - _boundary_term(d, phi, h)
-        x = spla.spsolve(A, rhs.reshape(-1))
-        phi[(slice(1, n + 3),) * d] = x.reshape((m,) * d)
+        if l > 0 and buffer_interp:
+            # unknowns on Omega^l; the inner layer is the boundary of the sub-box
+            sub = phi[(slice(1, n + 3),) * d]
+            A = _laplacian_system(d, n, h)
+            rhs = f[core] - _boundary_term(d, sub, h)
+            x = spla.spsolve(A, rhs.reshape(-1))
+            phi[core] = x.reshape((n,) * d)
+        else:
+            m = n + 2
+            A = _laplacian_system(d, m, h)
+            rhs = f[(slice(1, n + 3),) * d] - _boundary_term(d, phi, h)
+            x = spla.spsolve(A, rhs.reshape(-1))
+            phi[(slice(1, n + 3),) * d] = x.reshape((m,) * d)
         phis.append(phi)
         fs.append(f)
     return phis, fs

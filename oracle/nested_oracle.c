@@ -44,6 +44,8 @@ typedef struct {
     int max_cycles;
     int stop_rule;              /* 0: ||r||_inf <= tol*||f||_inf ; 1: max|F^q - F^{q-1}| < tol */
     int ghost_literal;          /* 1: use the right-ghost factor exactly as printed (negative tests) */
+    int buffer_interp;          /* 1: comparison scheme of Sec. 4 on levels l >= 1: both buffer layers
+                                   keep the interpolated potential and only Omega^l is relaxed */
 } orc_config;
 
 /* ------------------------------------------------------------------ */
@@ -419,6 +421,7 @@ int orc_validate(const orc_config *cfg)
         }
     }
     if (!(cfg->dx0 > 0.0)) return -1;
+    if (cfg->buffer_interp && cfg->stop_rule != 0) return -1;
     return 0;
 }
 
@@ -479,15 +482,45 @@ int orc_solve(const orc_config *cfg, const double *const *rho, const double *phi
             orc_interface_fill(d, cfg->n[l - 1], phi[l - 1], fl[l - 1], n, cfg->off[l], rho[l], fourpiG, u0, f0);
         }
 
+        /* The relaxed domain: Gamma^l (N^0 = n + 2) with the outer buffer layer
+         * as its ghost layer, which is the level array itself; or, for the
+         * comparison scheme of Sec. 4 (Fig. 4: the buffer values come from the
+         * coarse level by linear interpolation), Omega^l alone (N^0 = n) in an
+         * array of its own whose ghost layer is the interpolated inner buffer
+         * layer.  Its active values go back into the level array afterwards. */
+        int interp_buffer = l > 0 && cfg->buffer_interp;
+        int N0 = interp_buffer ? n : n + 2;
+        int Ps = N0 + 2;
+        size_t ms = npts(d, Ps);
+        double *us = u0, *fs = f0;
+        if (interp_buffer) {
+            us = malloc(ms * sizeof(double));
+            fs = malloc(ms * sizeof(double));
+            if (!us || !fs) {
+                free(us);
+                free(fs);
+                status = -1;
+                goto done;
+            }
+            int kmax = d == 3 ? Ps - 1 : 0;
+            for (int k = 0; k <= kmax; k++)
+                for (int j = 0; j < Ps; j++)
+                    for (int i = 0; i < Ps; i++) {
+                        size_t src = idx3(P, i + 1, j + 1, d == 3 ? k + 1 : 0);
+                        us[idx3(Ps, i, j, k)] = u0[src];
+                        fs[idx3(Ps, i, j, k)] = f0[src];
+                    }
+        }
+
         orc_mg m;
         memset(&m, 0, sizeof m);
         m.dim = d;
-        m.N0 = n + 2;
+        m.N0 = N0;
         m.literal = cfg->ghost_literal;
         m.nmg = orc_plan(m.N0, m.N, ORC_MAXMG);
         if (m.nmg < 1) { status = -1; goto done; }
-        m.u[0] = u0;
-        m.f[0] = f0;
+        m.u[0] = us;
+        m.f[0] = fs;
         int oom = 0;
         for (int L = 0; L < m.nmg; L++) {
             m.h[L] = dx * ldexp(1.0, L);
@@ -503,17 +536,17 @@ int orc_solve(const orc_config *cfg, const double *const *rho, const double *phi
 
         /* reference scale of the stop test: ||f||_inf over Gamma^l, or, for a
          * zero density, the residual of the zero potential */
-        double scale = orc_active_absmax(d, m.N[0], f0);
+        double scale = orc_active_absmax(d, m.N[0], fs);
         if (!(scale > 0.0) && !oom) {
-            double *z = malloc(m0 * sizeof(double));
+            double *z = malloc(ms * sizeof(double));
             if (!z) oom = 1;
             else {
-                memcpy(z, u0, m0 * sizeof(double));
-                int kmin = d == 3 ? 1 : 0, kmax = d == 3 ? P - 2 : 0;
+                memcpy(z, us, ms * sizeof(double));
+                int kmin = d == 3 ? 1 : 0, kmax = d == 3 ? Ps - 2 : 0;
                 for (int k = kmin; k <= kmax; k++)
-                    for (int j = 1; j <= P - 2; j++)
-                        for (int i = 1; i <= P - 2; i++) z[idx3(P, i, j, k)] = 0.0;
-                scale = orc_residual_norm(d, m.N[0], m.h[0], z, f0);
+                    for (int j = 1; j <= Ps - 2; j++)
+                        for (int i = 1; i <= Ps - 2; i++) z[idx3(Ps, i, j, k)] = 0.0;
+                scale = orc_residual_norm(d, m.N[0], m.h[0], z, fs);
                 free(z);
             }
         }
@@ -531,7 +564,7 @@ int orc_solve(const orc_config *cfg, const double *const *rho, const double *phi
         double r = 0.0;
         if (oom) lvl_status = -1;
         else {
-            r = orc_residual_norm(d, m.N[0], m.h[0], u0, f0);
+            r = orc_residual_norm(d, m.N[0], m.h[0], us, fs);
             double r0 = r;
             double *hl = hist ? hist + (size_t)l * (cfg->max_cycles + 1) : NULL;
             if (hl) hl[0] = scale > 0 ? r / scale : r;
@@ -546,7 +579,7 @@ int orc_solve(const orc_config *cfg, const double *const *rho, const double *phi
                 if (q >= cfg->max_cycles) { lvl_status = -3; break; }
                 vcycle(&m, cfg->n_pre, cfg->n_post);
                 q++;
-                r = orc_residual_norm(d, m.N[0], m.h[0], u0, f0);
+                r = orc_residual_norm(d, m.N[0], m.h[0], us, fs);
                 if (hl && q <= cfg->max_cycles) hl[q] = scale > 0 ? r / scale : r;
                 if (!isfinite(r)) { lvl_status = -2; break; }
                 if (r0 > 0 && r > 1e3 * r0) { lvl_status = -4; break; }
@@ -557,6 +590,14 @@ int orc_solve(const orc_config *cfg, const double *const *rho, const double *phi
                     if (dF < cfg->tol) break;
                 }
             }
+        }
+        if (interp_buffer) {
+            int kmin = d == 3 ? 1 : 0, kmax = d == 3 ? n : 0;
+            for (int k = kmin; k <= kmax; k++)
+                for (int j = 1; j <= n; j++)
+                    for (int i = 1; i <= n; i++) u0[idx3(P, i + 1, j + 1, d == 3 ? k + 1 : 0)] = us[idx3(Ps, i, j, k)];
+            free(us);
+            free(fs);
         }
         cycles[l] = q;
         final_rel[l] = scale > 0 ? r / scale : r;

@@ -26,6 +26,7 @@ NP_ENODEV = -8
 STOP_RULES = {"residual": 0, "force_delta": 1}
 PRECISIONS = {"fp64": 0, "fp32_dc": 1, "fp16s_dc": 2}
 GUESSES = {"interp": 0, "learned": 1}
+BUFFERS = {"relaxed": 0, "interp": 1}
 
 
 class NpConfig(ctypes.Structure):
@@ -44,6 +45,7 @@ class NpConfig(ctypes.Structure):
         ("precision", ctypes.c_int),
         ("inner_cycles", ctypes.c_int),
         ("guess", ctypes.c_int),
+        ("buffer", ctypes.c_int),
     ]
 
 
@@ -139,7 +141,7 @@ class NestedPoissonError(RuntimeError):
 
 
 def make_config(geom, n_pre=2, n_post=1, tol=1e-10, max_cycles=50, stop_rule="residual", precision="fp64",
-                inner_cycles=1, guess="interp"):
+                inner_cycles=1, guess="interp", buffer="relaxed"):
     """np_config from a geometry (attributes dim, n, off, dx0, G) and solver settings."""
     c = NpConfig()
     lib().nested_poisson_default_config(ctypes.byref(c))
@@ -159,6 +161,7 @@ def make_config(geom, n_pre=2, n_post=1, tol=1e-10, max_cycles=50, stop_rule="re
     c.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     c.inner_cycles = 0 if inner_cycles == "adaptive" else int(inner_cycles)
     c.guess = GUESSES[guess] if isinstance(guess, str) else int(guess)
+    c.buffer = BUFFERS[buffer] if isinstance(buffer, str) else int(buffer)
     return c
 
 

@@ -113,6 +113,10 @@ void launch_dc_outer(int dim, hipStream_t st, SGrid g, const double* phi_in, con
                      unsigned long long* maxbits);
 // ghost layer of a nested-level array copied from src to dst
 void launch_copy_ghosts(int dim, hipStream_t st, SGrid g, const double* src, double* dst);
+// dst(p) = src(p + shift) for the points p of grid gd with lo <= p_a <= hi on
+// every axis (padded indices of each grid; the caller keeps p + shift inside gs)
+void launch_copy_box(int dim, hipStream_t st, SGrid gs, const double* src, SGrid gd, double* dst, int lo, int hi,
+                     int shift);
 
 // learned initial guess network (np_net.hip); activations channel-last,
 // weights bfloat16 [27][cout][cin]

@@ -2380,6 +2380,23 @@ __global__ void __launch_bounds__(kBlock) k_copy_ghosts(SGrid g, const double* _
     dst[i] = src[i];
 }
 
+// dst(p) = src(p + shift) over the box lo <= p_a <= hi of grid gd (colour and
+// compact position taken in each grid's own padded indices): moves the relaxed
+// domain of a level between the level array and an array of its own
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_copy_box(SGrid gs, const double* __restrict__ src, SGrid gd,
+                                                     double* __restrict__ dst, int lo, int w, int shift)
+{
+    const long t = (long)blockIdx.x * kBlock + threadIdx.x;
+    const long total = D == 3 ? (long)w * w * w : (long)w * w;
+    if (t >= total) return;
+    const int i = lo + (int)(t % w);
+    const long r = t / w;
+    const int j = lo + (int)(r % w);
+    const int k = D == 3 ? lo + (int)(r / w) : 0;
+    dst[pos<D, double>(gd, i, j, k)] = at<D>(src, gs, i + shift, j + shift, D == 3 ? k + shift : 0);
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
@@ -2696,6 +2713,19 @@ void launch_copy_ghosts(int dim, hipStream_t st, SGrid g, const double* src, dou
         hipLaunchKernelGGL((k_copy_ghosts<3>), grid, dim3(kBlock), 0, st, g, src, dst);
     else
         hipLaunchKernelGGL((k_copy_ghosts<2>), grid, dim3(kBlock), 0, st, g, src, dst);
+}
+
+void launch_copy_box(int dim, hipStream_t st, SGrid gs, const double* src, SGrid gd, double* dst, int lo, int hi,
+                     int shift)
+{
+    const long w = hi - lo + 1;
+    if (w <= 0) return;
+    const long total = dim == 3 ? w * w * w : w * w;
+    dim3 grid(ceil_div(total, kBlock));
+    if (dim == 3)
+        hipLaunchKernelGGL((k_copy_box<3>), grid, dim3(kBlock), 0, st, gs, src, gd, dst, lo, (int)w, shift);
+    else
+        hipLaunchKernelGGL((k_copy_box<2>), grid, dim3(kBlock), 0, st, gs, src, gd, dst, lo, (int)w, shift);
 }
 
 template void launch_half_sweep<double>(int, hipStream_t, SGrid, double*, const double*, int, double, int, int, double);

@@ -22,12 +22,15 @@ namespace {
 // 4, patches on whole coarse cells with one coarse cell of margin.
 bool validate(const np_config* c, char* why, size_t nwhy)
 {
-    auto fail = [&](const char* fmt, int a, int b) {
-        snprintf(why, nwhy, fmt, a, b);
+    auto fail = [&](const char* fmt, auto... args) {
+        if constexpr (sizeof...(args) == 0)
+            snprintf(why, nwhy, "%s", fmt);
+        else
+            snprintf(why, nwhy, fmt, args...);
         return false;
     };
-    if (!c) return fail("null config%s", 0, 0);
-    if (c->dim != 2 && c->dim != 3) return fail("dim must be 2 or 3 (got %d)", c->dim, 0);
+    if (!c) return fail("null config");
+    if (c->dim != 2 && c->dim != 3) return fail("dim must be 2 or 3 (got %d)", c->dim);
     if (c->nlevels < 1 || c->nlevels > NP_MAX_LEVELS) return fail("nlevels must be 1..%d (got %d)", NP_MAX_LEVELS, c->nlevels);
     for (int l = 0; l < c->nlevels; l++) {
         int n = c->n[l];
@@ -40,19 +43,24 @@ bool validate(const np_config* c, char* why, size_t nwhy)
                 return fail("level %d: offset leaves less than one coarse cell of margin on axis %d", l, a);
         }
     }
-    if (!(c->dx0 > 0.0) || !std::isfinite(c->dx0)) return fail("dx0 must be positive%s", 0, 0);
-    if (!std::isfinite(c->G)) return fail("G must be finite%s", 0, 0);
+    if (!(c->dx0 > 0.0) || !std::isfinite(c->dx0)) return fail("dx0 must be positive");
+    if (!std::isfinite(c->G)) return fail("G must be finite");
     if (c->n_pre < 0 || c->n_pre > 16 || c->n_post < 0 || c->n_post > 16)
         return fail("n_pre/n_post must be 0..16 (got %d, %d)", c->n_pre, c->n_post);
-    if (!(c->tol > 0.0)) return fail("tol must be positive%s", 0, 0);
+    if (!(c->tol > 0.0)) return fail("tol must be positive");
     if (c->max_cycles < 1 || c->max_cycles > NP_MAX_CYCLES) return fail("max_cycles must be 1..%d (got %d)", NP_MAX_CYCLES, c->max_cycles);
-    if (c->stop_rule != NP_STOP_RESIDUAL && c->stop_rule != NP_STOP_FORCE_DELTA) return fail("bad stop_rule %d%s", c->stop_rule, 0);
+    if (c->stop_rule != NP_STOP_RESIDUAL && c->stop_rule != NP_STOP_FORCE_DELTA) return fail("bad stop_rule %d", c->stop_rule);
     if (c->precision != NP_PREC_FP64 && c->precision != NP_PREC_FP32_DC && c->precision != NP_PREC_FP16S_DC)
-        return fail("bad precision %d%s", c->precision, 0);
-    if (c->guess != NP_GUESS_INTERP && c->guess != NP_GUESS_LEARNED) return fail("bad guess %d%s", c->guess, 0);
-    if (c->guess == NP_GUESS_LEARNED && c->dim != 3) return fail("the learned guess is 3-D only (dim %d)%s", c->dim, 0);
+        return fail("bad precision %d", c->precision);
+    if (c->guess != NP_GUESS_INTERP && c->guess != NP_GUESS_LEARNED) return fail("bad guess %d", c->guess);
+    if (c->guess == NP_GUESS_LEARNED && c->dim != 3) return fail("the learned guess is 3-D only (dim %d)", c->dim);
     if (c->inner_cycles < 0 || c->inner_cycles > 8)
-        return fail("inner_cycles must be 0 (adaptive) or 1..8 (got %d)%s", c->inner_cycles, 0);
+        return fail("inner_cycles must be 0 (adaptive) or 1..8 (got %d)", c->inner_cycles);
+    if (c->buffer != NP_BUFFER_RELAXED && c->buffer != NP_BUFFER_INTERP) return fail("bad buffer %d", c->buffer);
+    if (c->buffer == NP_BUFFER_INTERP &&
+        (c->precision != NP_PREC_FP64 || c->guess != NP_GUESS_INTERP || c->stop_rule != NP_STOP_RESIDUAL))
+        return fail("the interpolated buffer runs with FP64, the interpolated guess and the residual stop "
+                    "rule only");
     return true;
 }
 
@@ -99,14 +107,19 @@ bool plan_in_bounds(const np_plan* p, int l)
     return true;
 }
 
+// N^0 of nested level l: the patch and its inner buffer layer, or the patch
+// alone where the buffer keeps its interpolated values (levels l >= 1)
+int level_N0(const np_config* c, int l) { return (l > 0 && c->buffer == NP_BUFFER_INTERP) ? c->n[l] : c->n[l] + 2; }
+
 int make_plan(const np_config* c, np_plan* p)
 {
     memset(p, 0, sizeof(*p));
     for (int l = 0; l < c->nlevels; l++) {
-        int m = plan_levels(c->n[l] + 2, p->N[l]);
+        const int N0 = level_N0(c, l);
+        int m = plan_levels(N0, p->N[l]);
         if (m < 2) return NP_EINVAL;
         p->nmg[l] = m;
-        for (int L = 1; L < m; L++) ghost_rule(c->n[l] + 2, L, p->N[l][L], &p->xn_is_one[l][L], &p->ghost_coef[l][L]);
+        for (int L = 1; L < m; L++) ghost_rule(N0, L, p->N[l][L], &p->xn_is_one[l][L], &p->ghost_coef[l][L]);
         if (!plan_in_bounds(p, l)) return NP_EINVAL;
     }
     return NP_OK;
@@ -181,6 +194,11 @@ struct np_solver {
     // training-feature scratch (interpolated guess of one level), on demand
     double* feat_phi = nullptr;
     double* feat_f = nullptr;
+    // NP_BUFFER_INTERP: the relaxed domain of a level l >= 1 (Omega^l, its ghost
+    // layer the inner buffer layer), (n + 2)^d colour-split, sized for the largest level
+    SGrid ag[NP_MAX_LEVELS];
+    double* ab_phi = nullptr;
+    double* ab_f = nullptr;
 };
 
 namespace {
@@ -610,6 +628,38 @@ int learned_guess(np_solver* s, int l, const double* rho_l, double fourpiG, doub
     return NP_OK;
 }
 
+// NP_BUFFER_INTERP on a level l >= 1: for the duration of the level's solve
+// the level's grid and arrays are those of the relaxed domain (Omega^l, whose
+// ghost layer is the interpolated inner buffer layer), so the V-cycle and norm
+// code runs unchanged on it; the level's own storage comes back on scope exit.
+struct RelaxedDomain {
+    np_solver* s;
+    int l;
+    bool on;
+    SGrid g{};
+    double* phi = nullptr;
+    double* f = nullptr;
+    RelaxedDomain(np_solver* s_, int l_, bool on_) : s(s_), l(l_), on(on_)
+    {
+        if (!on) return;
+        g = s->lg[l];
+        phi = s->phi[l];
+        f = s->f[l];
+        s->lg[l] = s->ag[l];
+        s->phi[l] = s->ab_phi;
+        s->f[l] = s->ab_f;
+    }
+    ~RelaxedDomain()
+    {
+        if (!on) return;
+        s->lg[l] = g;
+        s->phi[l] = phi;
+        s->f[l] = f;
+    }
+    RelaxedDomain(const RelaxedDomain&) = delete;
+    RelaxedDomain& operator=(const RelaxedDomain&) = delete;
+};
+
 void free_all(np_solver* s)
 {
     for (int l = 0; l < NP_MAX_LEVELS; l++) {
@@ -653,6 +703,9 @@ void free_all(np_solver* s)
     s->net_x = s->net_a1 = s->net_a2 = nullptr;
     s->net_out = nullptr;
     s->feat_phi = s->feat_f = nullptr;
+    if (s->ab_phi) (void)hipFree(s->ab_phi);
+    if (s->ab_f) (void)hipFree(s->ab_f);
+    s->ab_phi = s->ab_f = nullptr;
     if (s->force_scratch) (void)hipFree(s->force_scratch);
     if (s->d_bits) (void)hipFree(s->d_bits);
     if (s->h_bits) (void)hipHostFree(s->h_bits);
@@ -690,6 +743,7 @@ void nested_poisson_default_config(np_config* c)
     c->precision = NP_PREC_FP64;
     c->inner_cycles = 1;
     c->guess = NP_GUESS_INTERP;
+    c->buffer = NP_BUFFER_RELAXED;
 }
 
 int nested_poisson_plan(const np_config* cfg, np_plan* out)
@@ -756,6 +810,15 @@ int nested_poisson_create(const np_config* cfg, void* hip_stream, np_solver** ou
             rc = alloc_dev(s, (void**)&s->mg_u[L], best * sizeof(double));
             if (rc == NP_OK) rc = alloc_dev(s, (void**)&s->mg_f[L], best * sizeof(double));
         }
+    }
+    if (rc == NP_OK && cfg->buffer == NP_BUFFER_INTERP && cfg->nlevels > 1) {
+        size_t best = 0;
+        for (int l = 1; l < cfg->nlevels; l++) {
+            s->ag[l] = make_grid(d, cfg->n[l] + 2);
+            if (2 * s->ag[l].cs > best) best = 2 * s->ag[l].cs;
+        }
+        rc = alloc_dev(s, (void**)&s->ab_phi, best * sizeof(double));
+        if (rc == NP_OK) rc = alloc_dev(s, (void**)&s->ab_f, best * sizeof(double));
     }
     if (rc == NP_OK && dc) {
         size_t best = 0;
@@ -866,6 +929,21 @@ int nested_poisson_solve(np_solver* s, const double* const* rho, const double* p
         int rc = NP_OK;
         if (!std::isfinite(fnorm)) return set_err(s, NP_ENONFINITE, "level %d: non-finite density", l);
         double scale = fnorm;
+        // comparison scheme: Omega^l alone is relaxed, with the interpolated inner
+        // buffer layer as its Dirichlet data; its |f| sets the stop test's scale
+        const bool interp_buffer = l > 0 && c.buffer == NP_BUFFER_INTERP;
+        if (interp_buffer) {
+            prof_begin(s, NP_KCLASS_FILL);
+            launch_copy_box(d, s->stream, s->lg[l], s->phi[l], s->ag[l], s->ab_phi, 0, c.n[l] + 1, 1);
+            launch_copy_box(d, s->stream, s->lg[l], s->f[l], s->ag[l], s->ab_f, 0, c.n[l] + 1, 1);
+            prof_end(s);
+            HIPCHK(s, hipGetLastError());
+        }
+        RelaxedDomain dom(s, l, interp_buffer);
+        if (interp_buffer) {
+            rc = norm_sync(s, l, 1, &scale);
+            if (rc) return rc;
+        }
         if (!(scale > 0.0)) {
             rc = norm_sync(s, l, 2, &scale);
             if (rc) return rc;
@@ -960,6 +1038,13 @@ int nested_poisson_solve(np_solver* s, const double* const* rho, const double* p
         if (dc) {
             rc = dc_settle(s, l);
             if (rc) return rc;
+        }
+        if (interp_buffer) {
+            // the relaxed values back into Omega^l of the level's array
+            prof_begin(s, NP_KCLASS_FILL);
+            launch_copy_box(d, s->stream, s->lg[l], s->phi[l], dom.g, dom.phi, 2, c.n[l] + 1, -1);
+            prof_end(s);
+            HIPCHK(s, hipGetLastError());
         }
         st.cycles[l] = q;
         st.outer_steps[l] = outer;

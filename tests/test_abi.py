@@ -61,6 +61,21 @@ def test_host_plan_matches_oracle(wl):
                 assert p["coef"][L] == c  # same rational, one rounding
 
 
+@pytest.mark.parametrize("wl", [W.c2_plummer(128), W.paper2d(64), W.c5_two_plummer(512)], ids=lambda w: w.name)
+def test_host_plan_interp_buffer(wl):
+    """With the interpolated buffer, levels l >= 1 plan their hierarchy from
+    N^0 = n (Omega^l alone), level 0 from n + 2 as before."""
+    plan = _lib.plan(_lib.make_config(wl.geom, buffer="interp"))
+    for l, p in enumerate(plan):
+        N0 = wl.geom.n[l] + (2 if l == 0 else 0)
+        assert p["N"] == core.plan(N0)
+        for L in range(1, len(p["N"])):
+            one, c = core.ghost_rule(N0, L, p["N"][L])
+            assert bool(p["xn_is_one"][L]) == one
+            if not one:
+                assert p["coef"][L] == c
+
+
 def _bad(**kw):
     g = W.centred_geometry(3, 3, 16, 0.5, 1.0)
     cfg = _lib.make_config(g)
@@ -77,7 +92,8 @@ def _bad(**kw):
 @pytest.mark.parametrize("kw", [
     dict(dim=4), dict(nlevels=0), dict(nlevels=9), dict(n=(1, 7)), dict(n=(0, 2)), dict(off=(1, 0, 0)),
     dict(off=(2, 2, 9)), dict(dx0=0.0), dict(tol=-1.0), dict(max_cycles=0), dict(max_cycles=100000),
-    dict(n_pre=-1), dict(stop_rule=7), dict(inner_cycles=-1), dict(inner_cycles=9),
+    dict(n_pre=-1), dict(stop_rule=7), dict(inner_cycles=-1), dict(inner_cycles=9), dict(buffer=2),
+    dict(buffer=1, precision=1), dict(buffer=1, precision=2), dict(buffer=1, guess=1), dict(buffer=1, stop_rule=1),
 ], ids=lambda k: ",".join("%s=%s" % kv for kv in k.items()))
 def test_invalid_geometry_rejected_before_any_device_call(kw):
     cfg = _bad(**kw)

@@ -206,3 +206,57 @@ def test_plummer_128_full_parity():
     assert res["status"] == 0
     phi_g, F_g, st, _ = gpu_solve(wl, fixed=res["cycles"])
     assert_parity(wl, phi_g, F_g, res, F_o)
+
+
+# ------------------------------------------------ comparison scheme of Sec. 4
+INTERP_BUFFER = [W.paper2d(16), W.paper3d(16), W.c2_plummer(16), W.c3_plummer_offset(16), _ragged3d(), _ragged2d(),
+                 _minimal()]
+
+
+@pytest.mark.parametrize("wl", INTERP_BUFFER, ids=lambda w: w.name)
+def test_interp_buffer_parity(wl):
+    """Both buffer layers of levels l >= 1 interpolated and only Omega^l
+    relaxed (its own hierarchy from N^0 = n): same cycle counts as the oracle's
+    stop, potentials and forces to the FP64 bars."""
+    res, F_o = oracle_solve(wl, buffer_interp=True)
+    assert res["status"] == 0
+    phi_g, F_g, st, _ = gpu_solve(wl, fixed=res["cycles"], buffer="interp")
+    assert_parity(wl, phi_g, F_g, res, F_o)
+    phi_s, F_s, st_s, _ = gpu_solve(wl, buffer="interp")
+    for l in range(wl.geom.nlevels):
+        assert abs(st_s["cycles"][l] - res["cycles"][l]) <= 1
+        assert st_s["final_rel_residual"][l] <= 1e-10
+    if st_s["cycles"] == res["cycles"]:
+        assert_parity(wl, phi_s, F_s, res, F_o)
+
+
+@pytest.mark.parametrize("wl", [W.paper2d(16), _ragged3d()], ids=lambda w: w.name)
+def test_interp_buffer_cycle_by_cycle(wl):
+    """0, 1 and 2 cycles per level with the interpolated buffer: the copies into
+    and out of the relaxed domain and every V-cycle kernel on it agree."""
+    L = wl.geom.nlevels
+    for k in range(3):
+        fixed = [k] * L
+        res, F_o = oracle_solve(wl, fixed=fixed, buffer_interp=True)
+        phi_g, F_g, st, _ = gpu_solve(wl, fixed=fixed, buffer="interp")
+        assert_parity(wl, phi_g, F_g, res, F_o)
+
+
+def test_interp_buffer_reuse_and_level0():
+    """Two solves on one handle are identical; level 0 equals the relaxed
+    scheme's bit for bit (the buffer mode concerns levels l >= 1 only)."""
+    wl = W.c4_multi_plummer(11, N=32)
+    dev = torch.device("cuda")
+    rho, po = _inputs(wl, dev)
+    s = NestedPoissonSolver(wl.geom, buffer="interp")
+    s.solve(rho, po)
+    a = [s.potential(l).clone() for l in range(3)]
+    s.solve(rho, po)
+    b = [s.potential(l).clone() for l in range(3)]
+    s.close()
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+    s = NestedPoissonSolver(wl.geom)
+    s.solve(rho, po)
+    assert torch.equal(s.potential(0), a[0])
+    s.close()
