@@ -11,11 +11,18 @@
  * forces F = -grad(Phi) with the fourth-order central difference
  * (Eqn:force_evaluation).
  *
- * Geometry (Sec. 2.1).  Level l is a cube (square in 2-D) of n[l] cells per
- * axis with cell size dx0 / 2^l.  For l >= 1 its lower corner lies
- * offset[l][a] cells of level l-1 above the lower corner of level l-1 along
- * axis a; it must keep at least one coarse cell of margin on every side:
- *     1 <= offset[l][a]  and  offset[l][a] + n[l]/2 <= n[l-1] - 1.
+ * Geometry (Sec. 2.1).  The entries l = 0 .. nlevels-1 ("levels") are
+ * patches: entry 0 is the base level; every other entry l is refined out of
+ * its parent p = parent[l] (0 <= p < l), with cell size dx_p / 2, so the cell
+ * size of entry l is dx0 / 2^depth(l).  nested_poisson_default_config sets
+ * parent[l] = l - 1, the paper's stack of one patch per level; a tree gives
+ * several disjoint patches per level (the patch-based setting of Sec. 4).
+ * Entry l is a cube (square in 2-D) of n[l] cells per axis whose lower corner
+ * lies offset[l][a] cells of p above p's lower corner along axis a; it must
+ * keep at least one coarse cell of margin on every side:
+ *     1 <= offset[l][a]  and  offset[l][a] + n[l]/2 <= n[p] - 1,
+ * and patches with the same parent must not overlap.  Patches are solved in
+ * entry order, each from its converged parent (one-way scheme).
  * Each level carries a two-cell buffer.  Its padded array has n[l] + 4
  * points per axis: index 0 and n+3 are the outer buffer layer (Dirichlet
  * potential), 1 and n+2 the inner buffer layer (relaxed together with the
@@ -43,7 +50,7 @@
 extern "C" {
 #endif
 
-#define NP_MAX_LEVELS 8   /* nested refinement levels per solver */
+#define NP_MAX_LEVELS 16  /* nested patches (entries) per solver */
 #define NP_MAX_MG 32      /* multigrid levels per patch */
 #define NP_MAX_CYCLES 200 /* cap on max_cycles */
 
@@ -69,13 +76,13 @@ extern "C" {
 #define NP_INNER_ADAPTIVE 0 /* inner_cycles: chosen per step from the measured contraction */
 
 /* initial guess of levels l >= 1 */
-#define NP_GUESS_INTERP 0  /* interpolated from level l-1 (Sec. 2.4) */
+#define NP_GUESS_INTERP 0  /* interpolated from the parent patch (Sec. 2.4) */
 #define NP_GUESS_LEARNED 1 /* interpolated guess plus the correction predicted by the conv net */
 
 /* buffer zone of levels l >= 1 (Sec. 2.1 and Sec. 4, Fig. 4) */
 #define NP_BUFFER_RELAXED 0 /* the paper's method: the inner buffer layer is relaxed with the patch */
 #define NP_BUFFER_INTERP 1  /* comparison scheme of Sec. 4: both buffer layers keep the potential
-                               interpolated from level l-1 and only Omega^l is relaxed (the inner
+                               interpolated from the parent and only Omega^l is relaxed (the inner
                                layer is its Dirichlet data); FP64, interpolated guess and the
                                residual stop rule only */
 
@@ -83,7 +90,7 @@ typedef struct np_config {
     int dim;                        /* 2 or 3 */
     int nlevels;                    /* 1..NP_MAX_LEVELS */
     int n[NP_MAX_LEVELS];           /* cells per axis of level l: even, >= 4 */
-    int offset[NP_MAX_LEVELS][3];   /* l >= 1: corner offset in cells of level l-1 (see above) */
+    int offset[NP_MAX_LEVELS][3];   /* l >= 1: corner offset in cells of the parent (see above) */
     double dx0;                     /* cell size of level 0, > 0 */
     double G;                       /* gravitational constant */
     int n_pre;                      /* pre-smoothing sweeps (the paper uses 2), 0..16 */
@@ -98,11 +105,13 @@ typedef struct np_config {
                                        says the stop test needs */
     int guess;                      /* NP_GUESS_* */
     int buffer;                     /* NP_BUFFER_* */
+    int parent[NP_MAX_LEVELS];      /* l >= 1: the entry patch l is refined out of, 0 <= parent[l] < l */
 } np_config;
 
 /* Fills `cfg` with the paper's solver settings (N_pre = 2, N_post = 1,
  * Sec. 3) and tol = 1e-10, max_cycles = 50, FP64, residual stop,
- * interpolated guess, relaxed buffer.  Geometry fields are zeroed. */
+ * interpolated guess, relaxed buffer, parent[l] = l - 1.  The other
+ * geometry fields are zeroed. */
 void nested_poisson_default_config(np_config* cfg);
 
 /* Multigrid hierarchy of one patch (Sec. 2.2): N^0 = n + 2 (patch plus its
@@ -135,11 +144,11 @@ int nested_poisson_create(const np_config* cfg, void* hip_stream, np_solver** ou
 /* Nested solve (Sec. 2.1 one-way scheme, Sec. 2.3 V-cycle).
  *   rho[0]    : (n0+2)^d density of level 0 including its inner buffer layer
  *   rho[l>=1] : n_l^d density of level l (the inner buffer layer of l >= 1
- *               gets the density interpolated from level l-1)
+ *               gets the density interpolated from its parent)
  *   phi_outer : (n0+4)^d; only the outer layer is read (Dirichlet data of
  *               level 0)
  * Level 0 starts from Phi = 0; level l >= 1 from the potential interpolated
- * from level l-1 (plus the learned correction with NP_GUESS_LEARNED).
+ * from its parent (plus the learned correction with NP_GUESS_LEARNED).
  * Returns after the last stop test of the finest level (host-synchronous).
  * `stats` may be NULL.  Errors: NP_EINVAL, NP_ENONFINITE, NP_ENOTCONV (the
  * cap was hit on some level; results are valid), NP_EDIVERGED, NP_EHIP. */

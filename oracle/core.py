@@ -11,7 +11,7 @@ import numpy as np
 
 from . import build as _build
 
-MAXLEV = 8
+MAXLEV = 16
 MAXMG = 32
 
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -33,6 +33,7 @@ class OrcConfig(ctypes.Structure):
         ("stop_rule", ctypes.c_int),
         ("ghost_literal", ctypes.c_int),
         ("buffer_interp", ctypes.c_int),
+        ("parent", ctypes.c_int * MAXLEV),
     ]
 
 
@@ -180,6 +181,9 @@ def make_config(geom, n_pre=2, n_post=1, tol=1e-10, max_cycles=50, stop_rule=0, 
     c.stop_rule = stop_rule
     c.ghost_literal = int(ghost_literal)
     c.buffer_interp = int(buffer_interp)
+    parent = getattr(geom, "parent", None)
+    for l in range(geom.nlevels):
+        c.parent[l] = int(parent[l]) if parent is not None else l - 1
     return c
 
 

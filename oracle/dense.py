@@ -1,19 +1,20 @@
 """Direct solve of the nested discrete system: the plain definition of the
 fixed point the multigrid iteration converges to (test infrastructure).
 
-For each level l in order (one-way scheme, Sec. 2.1):
+For each level (patch) l in order (one-way scheme, Sec. 2.1; the parent of
+patch l is l-1 for the stack of one patch per level, geom.parent[l] for a tree):
   * unknowns: Phi at the centres of Gamma^l = Omega^l plus its inner buffer
     layer ((n_l+2)^d cells);
   * Dirichlet data at the outer buffer layer: the caller's potential for
-    l = 0, the multilinear interpolant of Phi^{l-1} for l >= 1;
+    l = 0, the multilinear interpolant of the parent's Phi for l >= 1;
   * right-hand side 4 pi G rho on Omega^l, and on the inner buffer layer the
-    multilinear interpolant of level l-1's right-hand side (l >= 1) or the
+    multilinear interpolant of the parent's right-hand side (l >= 1) or the
     caller's density (l = 0);
   * operator: the 5-/7-point Laplacian (eqn:Laplacian2D/3D) with the outer
     layer moved to the right-hand side.
 With buffer_interp (the comparison scheme of Sec. 4, levels l >= 1) the
 unknowns are the cells of Omega^l alone and the inner buffer layer keeps the
-interpolant of Phi^{l-1}, as Dirichlet data next to the outer layer's.
+interpolant of the parent's Phi, as Dirichlet data next to the outer layer's.
 The interpolation is evaluated from physical cell-centre coordinates (the
 bilinear/trilinear formula of Appendix A at the fine centre), not from index
 tables, so it is an independent route to the same weights.  The linear system
@@ -26,13 +27,19 @@ import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
 
+def _parent(geom, l):
+    return geom.parent[l] if getattr(geom, "parent", None) is not None else l - 1
+
+
 def _interp(geom, l, coarse_padded, first, count):
-    """Multilinear interpolation of a padded level-(l-1) array at the centres of
-    level-l cells first..first+count-1 along every axis (index -2 = outer layer)."""
+    """Multilinear interpolation of the padded array of patch l's parent at the
+    centres of patch-l cells first..first+count-1 along every axis (index -2 =
+    outer layer)."""
     d = geom.dim
-    lo_c = geom.lo(l - 1)
+    p = _parent(geom, l)
+    lo_c = geom.lo(p)
     lo_f = geom.lo(l)
-    dxc, dxf = geom.dx(l - 1), geom.dx(l)
+    dxc, dxf = geom.dx(p), geom.dx(l)
     idx = []
     wts = []
     for a in range(d):
@@ -109,8 +116,9 @@ def solve(geom, rho, phi_outer, buffer_interp=False):
             phi[...] = np.asarray(phi_outer)
             f[(slice(1, n + 3),) * d] = fourpiG * np.asarray(rho[0])
         else:
-            phi[...] = _interp(geom, l, phis[l - 1], -2, n + 4)
-            f[(slice(1, n + 3),) * d] = _interp(geom, l, fs[l - 1], -1, n + 2)
+            p = _parent(geom, l)
+            phi[...] = _interp(geom, l, phis[p], -2, n + 4)
+            f[(slice(1, n + 3),) * d] = _interp(geom, l, fs[p], -1, n + 2)
             f[core] = fourpiG * np.asarray(rho[l])
         if l > 0 and buffer_interp:
             # unknowns on Omega^l; the inner layer is the boundary of the sub-box

@@ -27,7 +27,7 @@
 #include <stdlib.h>
 #include <string.h>
 
-#define ORC_MAXLEV 8   /* nested levels */
+#define ORC_MAXLEV 16  /* nested patches (entries) */
 #define ORC_MAXMG 32   /* multigrid levels per patch */
 
 /* ------------------------------------------------------------------ */
@@ -36,7 +36,7 @@ typedef struct {
     int dim;                    /* 2 or 3 */
     int nlevels;                /* number of nested levels */
     int n[ORC_MAXLEV];          /* cells per axis of Omega^l */
-    int off[ORC_MAXLEV][3];     /* l>=1: lower corner of Omega^l, in cells of level l-1 */
+    int off[ORC_MAXLEV][3];     /* l>=1: lower corner of Omega^l, in cells of its parent */
     double dx0;                 /* cell size of level 0 */
     double G;                   /* gravitational constant */
     int n_pre, n_post;          /* smoothing counts (Sec. 3: 2 and 1) */
@@ -46,7 +46,21 @@ typedef struct {
     int ghost_literal;          /* 1: use the right-ghost factor exactly as printed (negative tests) */
     int buffer_interp;          /* 1: comparison scheme of Sec. 4 on levels l >= 1: both buffer layers
                                    keep the interpolated potential and only Omega^l is relaxed */
+    int parent[ORC_MAXLEV];     /* l>=1: the patch Omega^l is refined out of (earlier entry); the
+                                   stack of Sec. 2.1 has parent[l] = l-1, a tree gives several
+                                   disjoint patches per level */
 } orc_config;
+
+/* refinement depth of entry l: number of parent links down to the base level */
+static int depth_of(const orc_config *cfg, int l)
+{
+    int k = 0;
+    while (l > 0) {
+        l = cfg->parent[l];
+        k++;
+    }
+    return k;
+}
 
 /* ------------------------------------------------------------------ */
 static size_t idx3(int Q, int i, int j, int k) { return ((size_t)k * Q + j) * Q + i; }
@@ -415,9 +429,22 @@ int orc_validate(const orc_config *cfg)
     for (int l = 0; l < cfg->nlevels; l++) {
         if (cfg->n[l] < 4 || (cfg->n[l] & 1)) return -1;
         if (l == 0) continue;
+        int p = cfg->parent[l];
+        if (p < 0 || p >= l) return -1;
         for (int a = 0; a < cfg->dim; a++) {
             int o = cfg->off[l][a];
-            if (o < 1 || o + cfg->n[l] / 2 > cfg->n[l - 1] - 1) return -1;
+            if (o < 1 || o + cfg->n[l] / 2 > cfg->n[p] - 1) return -1;
+        }
+        /* siblings (same parent) must not overlap */
+        for (int m = 1; m < l; m++) {
+            if (cfg->parent[m] != p) continue;
+            int apart = 0;
+            for (int a = 0; a < cfg->dim; a++) {
+                int lo1 = cfg->off[l][a], hi1 = lo1 + cfg->n[l] / 2;
+                int lo2 = cfg->off[m][a], hi2 = lo2 + cfg->n[m] / 2;
+                if (hi1 <= lo2 || hi2 <= lo1) apart = 1;
+            }
+            if (!apart) return -1;
         }
     }
     if (!(cfg->dx0 > 0.0)) return -1;
@@ -461,7 +488,7 @@ int orc_solve(const orc_config *cfg, const double *const *rho, const double *phi
     for (int l = 0; l < cfg->nlevels; l++) {
         int n = cfg->n[l];
         int P = n + 4;
-        double dx = ldexp(cfg->dx0, -l);
+        double dx = ldexp(cfg->dx0, -depth_of(cfg, l));
         size_t m0 = npts(d, P);
         double *f0 = fl[l];
         double *u0 = phi[l];
@@ -479,7 +506,8 @@ int orc_solve(const orc_config *cfg, const double *const *rho, const double *phi
                         f0[c] = fourpiG * rho[0][ri];
                     }
         } else {
-            orc_interface_fill(d, cfg->n[l - 1], phi[l - 1], fl[l - 1], n, cfg->off[l], rho[l], fourpiG, u0, f0);
+            int p = cfg->parent[l];
+            orc_interface_fill(d, cfg->n[p], phi[p], fl[p], n, cfg->off[l], rho[l], fourpiG, u0, f0);
         }
 
         /* The relaxed domain: Gamma^l (N^0 = n + 2) with the outer buffer layer

@@ -9,14 +9,20 @@ centres.  No division by |Omega| (the paper's domains have unit measure).
 import numpy as np
 
 
+def _children(geom, l):
+    parent = getattr(geom, "parent", None)
+    return [m for m in range(1, geom.nlevels) if (parent[m] if parent is not None else m - 1) == l]
+
+
 def uncovered_mask(geom, l):
-    """Boolean n_l^d mask of Omega^l cells not covered by Omega^{l+1}."""
+    """Boolean n_l^d mask of the cells of patch l not covered by a finer patch
+    refined out of it (Omega^{l+1} for the stack of one patch per level)."""
     n = geom.n[l]
     shp = (n,) * geom.dim
     m = np.ones(shp, dtype=bool)
-    if l + 1 < geom.nlevels:
-        o = geom.off[l + 1]
-        h = geom.n[l + 1] // 2
+    for c in _children(geom, l):
+        o = geom.off[c]
+        h = geom.n[c] // 2
         sl = tuple(slice(o[a], o[a] + h) for a in reversed(range(geom.dim)))  # [k, j, i]
         m[sl] = False
     return m

@@ -10,7 +10,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libnested_poisson.so")
 
-NP_MAX_LEVELS = 8
+NP_MAX_LEVELS = 16
 NP_MAX_MG = 32
 
 NP_OK = 0
@@ -46,6 +46,7 @@ class NpConfig(ctypes.Structure):
         ("inner_cycles", ctypes.c_int),
         ("guess", ctypes.c_int),
         ("buffer", ctypes.c_int),
+        ("parent", ctypes.c_int * NP_MAX_LEVELS),
     ]
 
 
@@ -162,6 +163,10 @@ def make_config(geom, n_pre=2, n_post=1, tol=1e-10, max_cycles=50, stop_rule="re
     c.inner_cycles = 0 if inner_cycles == "adaptive" else int(inner_cycles)
     c.guess = GUESSES[guess] if isinstance(guess, str) else int(guess)
     c.buffer = BUFFERS[buffer] if isinstance(buffer, str) else int(buffer)
+    parent = getattr(geom, "parent", None)
+    if parent is not None:
+        for l, p in enumerate(parent):
+            c.parent[l] = int(p)
     return c
 
 

@@ -37,10 +37,23 @@ bool validate(const np_config* c, char* why, size_t nwhy)
         if (n < 4 || (n & 1)) return fail("level %d: n must be even and >= 4 (got %d)", l, n);
         if (n > 1 << 14) return fail("level %d: n too large (%d)", l, n);
         if (l == 0) continue;
+        const int p = c->parent[l];
+        if (p < 0 || p >= l) return fail("level %d: parent %d must name an earlier entry", l, p);
         for (int a = 0; a < c->dim; a++) {
             int o = c->offset[l][a];
-            if (o < 1 || o + n / 2 > c->n[l - 1] - 1)
+            if (o < 1 || o + n / 2 > c->n[p] - 1)
                 return fail("level %d: offset leaves less than one coarse cell of margin on axis %d", l, a);
+        }
+        // patches refined out of the same parent do not overlap
+        for (int m = 1; m < l; m++) {
+            if (c->parent[m] != p) continue;
+            bool overlap = true;
+            for (int a = 0; a < c->dim; a++) {
+                const int lo1 = c->offset[l][a], hi1 = lo1 + n / 2;
+                const int lo2 = c->offset[m][a], hi2 = lo2 + c->n[m] / 2;
+                if (hi1 <= lo2 || hi2 <= lo1) overlap = false;
+            }
+            if (overlap) return fail("levels %d and %d: patches of the same parent overlap", m, l);
         }
     }
     if (!(c->dx0 > 0.0) || !std::isfinite(c->dx0)) return fail("dx0 must be positive");
@@ -110,6 +123,18 @@ bool plan_in_bounds(const np_plan* p, int l)
 // N^0 of nested level l: the patch and its inner buffer layer, or the patch
 // alone where the buffer keeps its interpolated values (levels l >= 1)
 int level_N0(const np_config* c, int l) { return (l > 0 && c->buffer == NP_BUFFER_INTERP) ? c->n[l] : c->n[l] + 2; }
+
+// refinement depth of entry l (0 for the base level) and its cell size dx0 / 2^depth
+int level_depth(const np_config* c, int l)
+{
+    int k = 0;
+    while (l > 0) {
+        l = c->parent[l];
+        k++;
+    }
+    return k;
+}
+double level_dx(const np_config* c, int l) { return std::ldexp(c->dx0, -level_depth(c, l)); }
 
 int make_plan(const np_config* c, np_plan* p)
 {
@@ -279,7 +304,7 @@ MGView<T> mg_view(const np_solver* s, int l, T* const* mu, T* const* mf)
 {
     MGView<T> v;
     v.nmg = s->plan.nmg[l];
-    double dx = std::ldexp(s->cfg.dx0, -l);
+    double dx = level_dx(&s->cfg, l);
     for (int L = 0; L < v.nmg; L++) {
         v.u[L] = L == 0 ? nullptr : mu[L];
         v.f[L] = L == 0 ? nullptr : mf[L];
@@ -477,7 +502,7 @@ int vcycle_lo(np_solver* s, int l, bool red_done)
 // Queue a norm into slot `slot` and return it (host-synchronous).
 int norm_sync(np_solver* s, int l, int mode, double* out)
 {
-    double dx = std::ldexp(s->cfg.dx0, -l);
+    double dx = level_dx(&s->cfg, l);
     launch_set_u64(s->stream, s->d_bits, 1, 0ULL);
     prof_begin(s, NP_KCLASS_NORM);
     launch_norm(s->cfg.dim, s->stream, s->lg[l], s->phi[l], s->f[l], 1.0 / (dx * dx), mode, s->d_bits);
@@ -491,7 +516,7 @@ int norm_sync(np_solver* s, int l, int mode, double* out)
 
 int force_delta_sync(np_solver* s, int l, double* out)
 {
-    double dx = std::ldexp(s->cfg.dx0, -l);
+    double dx = level_dx(&s->cfg, l);
     launch_set_u64(s->stream, s->d_bits + 1, 1, 0ULL);
     launch_force_delta(s->cfg.dim, s->stream, s->lg[l], s->cfg.n[l], dx, s->phi[l], s->force_scratch, s->d_bits + 1);
     HIPCHK(s, hipGetLastError());
@@ -509,7 +534,7 @@ int force_delta_sync(np_solver* s, int l, double* out)
 int dc_outer_sync(np_solver* s, int l, bool update, double factor, double rscale, double* out)
 {
     const np_config& c = s->cfg;
-    double dx = std::ldexp(c.dx0, -l);
+    double dx = level_dx(&c, l);
     int first_red = c.n_pre > 0;
     void* e_in = update ? s->e_lo : nullptr;
     void* e_out = dc_seed_black(s, l) ? nullptr : (update ? s->e_nx : s->e_lo);
@@ -601,7 +626,7 @@ int learned_guess(np_solver* s, int l, const double* rho_l, double fourpiG, doub
     hipStream_t st = s->stream;
     SGrid g = s->lg[l];
     const int m = g.nx - 2;
-    const double dx = std::ldexp(c.dx0, -l);
+    const double dx = level_dx(&c, l);
     prof_begin(s, NP_KCLASS_GUESS);
     net_features_bf16(st, g, s->phi[l], s->f[l], 1.0 / fnorm, 1.0 / (dx * dx), s->net_x);
     net_conv_mfma(st, s->net_x, 2, s->net_w[0], s->net_b[0], 16, 1, 1, m, m, m, s->net_a1);
@@ -622,7 +647,7 @@ int learned_guess(np_solver* s, int l, const double* rho_l, double fourpiG, doub
         return NP_OK;
     }
     // fallback: restore the interpolated guess
-    launch_interface_fill(c.dim, st, s->lg[l - 1], s->phi[l - 1], s->f[l - 1], g, c.n[l], c.offset[l][0],
+    launch_interface_fill(c.dim, st, s->lg[c.parent[l]], s->phi[c.parent[l]], s->f[c.parent[l]], g, c.n[l], c.offset[l][0],
                           c.offset[l][1], c.offset[l][2], rho_l, fourpiG, s->phi[l], s->f[l], nullptr);
     HIPCHK(s, hipGetLastError());
     return NP_OK;
@@ -744,6 +769,7 @@ void nested_poisson_default_config(np_config* c)
     c->inner_cycles = 1;
     c->guess = NP_GUESS_INTERP;
     c->buffer = NP_BUFFER_RELAXED;
+    for (int l = 0; l < NP_MAX_LEVELS; l++) c->parent[l] = l - 1;
 }
 
 int nested_poisson_plan(const np_config* cfg, np_plan* out)
@@ -916,7 +942,7 @@ int nested_poisson_solve(np_solver* s, const double* const* rho, const double* p
         if (l == 0) {
             launch_level0_init(d, s->stream, s->lg[0], rho[0], phi_outer, fourpiG, s->phi[0], s->f[0], s->d_bits + 2);
         } else {
-            launch_interface_fill(d, s->stream, s->lg[l - 1], s->phi[l - 1], s->f[l - 1], s->lg[l], c.n[l],
+            launch_interface_fill(d, s->stream, s->lg[c.parent[l]], s->phi[c.parent[l]], s->f[c.parent[l]], s->lg[l], c.n[l],
                                   c.offset[l][0], c.offset[l][1], d == 3 ? c.offset[l][2] : 0, rho[l], fourpiG,
                                   s->phi[l], s->f[l], s->d_bits + 2);
         }
@@ -1010,7 +1036,7 @@ int nested_poisson_solve(np_solver* s, const double* const* rho, const double* p
                 // phi += h^2 r_scale e'', then the residual of the updated potential,
                 // scaled by the previous norm (the new one is not known until the pass ends)
                 double rprev = r > 0 ? r : 1.0;
-                double dx = std::ldexp(c.dx0, -l);
+                double dx = level_dx(&c, l);
                 rc = dc_outer_sync(s, l, true, dx * dx * r_scale, 1.0 / rprev, &r);
                 if (rc) return rc;
                 r_scale = rprev;
@@ -1086,7 +1112,7 @@ int nested_poisson_forces(np_solver* s, int level, double* fx, double* fy, doubl
     if (!s->solved) return set_err(s, NP_ESTATE, "forces requested before a successful solve");
     HIPCHK(s, hipSetDevice(s->device));
     prof_begin(s, NP_KCLASS_FORCES);
-    launch_forces(s->cfg.dim, s->stream, s->lg[level], s->cfg.n[level], std::ldexp(s->cfg.dx0, -level),
+    launch_forces(s->cfg.dim, s->stream, s->lg[level], s->cfg.n[level], level_dx(&s->cfg, level),
                   s->phi[level], fx, fy, fz);
     prof_end(s);
     HIPCHK(s, hipGetLastError());
@@ -1161,9 +1187,9 @@ int nested_poisson_guess_features(np_solver* s, int level, float* x, float* targ
     // the density of the patch itself does not enter Phi_interp, so the level's own
     // right-hand side serves as the density argument (only f_tmp's patch part uses it)
     const int l = level;
-    double dx = std::ldexp(c.dx0, -l);
+    double dx = level_dx(&c, l);
     double fourpiG = 4.0 * M_PI * c.G;
-    launch_interface_fill(c.dim, s->stream, s->lg[l - 1], s->phi[l - 1], s->f[l - 1], s->lg[l], c.n[l], c.offset[l][0],
+    launch_interface_fill(c.dim, s->stream, s->lg[c.parent[l]], s->phi[c.parent[l]], s->f[c.parent[l]], s->lg[l], c.n[l], c.offset[l][0],
                           c.offset[l][1], c.offset[l][2], s->f[l], 0.0, s->feat_phi, s->feat_f, nullptr);
     double fnorm = 0.0;
     int rc = norm_sync(s, l, 1, &fnorm);

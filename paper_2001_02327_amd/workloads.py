@@ -24,7 +24,7 @@ from __future__ import annotations
 
 import math
 from dataclasses import dataclass, field
-from typing import List, Sequence, Tuple
+from typing import List, Optional, Sequence, Tuple
 
 import numpy as np
 import torch
@@ -39,20 +39,37 @@ class Geometry:
     lo0: Tuple[float, float, float]   # physical lower corner of Omega^0
     dx0: float
     G: float = 1.0
+    # l >= 1: the entry patch l is refined out of (an earlier one); None = the
+    # stack of one patch per level (parent l - 1); a tree gives several
+    # disjoint patches per level, off[l] counted in cells of the parent
+    parent: Optional[List[int]] = None
 
     @property
     def nlevels(self) -> int:
         return len(self.n)
 
+    def par(self, l: int) -> int:
+        return self.parent[l] if self.parent is not None else l - 1
+
+    def depth(self, l: int) -> int:
+        k = 0
+        while l > 0:
+            l = self.par(l)
+            k += 1
+        return k
+
+    def children(self, l: int) -> List[int]:
+        return [m for m in range(1, self.nlevels) if self.par(m) == l]
+
     def dx(self, l: int) -> float:
-        return self.dx0 / (1 << l)
+        return self.dx0 / (1 << self.depth(l))
 
     def lo(self, l: int) -> Tuple[float, ...]:
-        x = list(self.lo0[: self.dim])
-        for ll in range(1, l + 1):
-            for a in range(self.dim):
-                x[a] += self.off[ll][a] * self.dx(ll - 1)
-        return tuple(x)
+        if l == 0:
+            return tuple(self.lo0[: self.dim])
+        p = self.par(l)
+        base = self.lo(p)
+        return tuple(base[a] + self.off[l][a] * self.dx(p) for a in range(self.dim))
 
     def centres(self, l: int, first: int, count: int, device="cpu"):
         """Per-axis cell-centre coordinates for Omega^l cell indices first..first+count-1
@@ -72,8 +89,11 @@ class Geometry:
         return x, y
 
     def describe(self) -> dict:
-        return dict(dim=self.dim, n=list(self.n), off=[list(o) for o in self.off], lo0=list(self.lo0[: self.dim]),
-                    dx0=self.dx0, G=self.G)
+        d = dict(dim=self.dim, n=list(self.n), off=[list(o) for o in self.off], lo0=list(self.lo0[: self.dim]),
+                 dx0=self.dx0, G=self.G)
+        if self.parent is not None:
+            d["parent"] = list(self.parent)
+        return d
 
 
 def centred_geometry(dim: int, nlevels: int, N: int, half_width0: float, G: float) -> Geometry:
@@ -216,6 +236,41 @@ class Gaussian(Problem):
         return tuple(2 * xi / self.s ** 2 * ph for xi in x)
 
 
+class GaussianSum(Problem):
+    """Manufactured Phi = sum_k A_k exp(-|x - c_k|^2 / s_k^2) in 2-D or 3-D;
+    4 pi G rho = lap(Phi) = sum_k A_k exp(.) (4 r_k^2 / s_k^4 - 2d / s_k^2)."""
+
+    def __init__(self, terms: Sequence[Tuple[float, float, Sequence[float]]], G: float = 1.0):
+        self.terms = [(float(A), float(s), tuple(float(c) for c in cen)) for A, s, cen in terms]
+        self.G = G
+
+    def _each(self, x):
+        for A, s, c in self.terms:
+            dx = [x[i] - c[i] for i in range(len(x))]
+            r2 = sum(v * v for v in dx)
+            yield A, s, dx, r2, A * torch.exp(-r2 / s ** 2)
+
+    def phi(self, *x):
+        out = torch.zeros_like(x[0])
+        for _, _, _, _, g in self._each(x):
+            out = out + g
+        return out
+
+    def rho(self, *x):
+        d = len(x)
+        out = torch.zeros_like(x[0])
+        for _, s, _, r2, g in self._each(x):
+            out = out + g * (4 * r2 / s ** 4 - 2 * d / s ** 2)
+        return out / (4 * math.pi * self.G)
+
+    def force(self, *x):
+        out = [torch.zeros_like(x[0]) for _ in x]
+        for _, s, dx, _, g in self._each(x):
+            for i in range(len(x)):
+                out[i] = out[i] + 2 * dx[i] / s ** 2 * g
+        return tuple(out)
+
+
 class Linear(Problem):
     """rho = 0, Phi = a.x + b: the interpolation and the Laplacian are exact on it."""
 
@@ -338,3 +393,41 @@ def paper3d(N: int, nlevels: int = 3) -> Workload:
     p = Paper3D(1.0, 0.25)
     g = centred_geometry(3, nlevels, N, 0.5, p.G)
     return Workload("paper3d_%d" % N, g, p)
+
+
+def two_patch_geometry(dim: int, N: int, grandchild_order: str = "last") -> Geometry:
+    """A tree of patches on [-1, 1]^d: the base level (N cells per axis), two
+    disjoint children of N/2 cells (each covering N/4 parent cells, width 1/2)
+    centred at x = -1/2 and x = +1/2, and one grandchild of N/2 cells centred
+    inside the first child.  Entry order [base, A, B, AA] ("last") or
+    [base, A, AA, B] ("middle")."""
+    if N % 8:
+        raise ValueError("N must be a multiple of 8")
+    q = N // 8
+    A = (q, 3 * q, 3 * q)
+    B = (5 * q, 3 * q, 3 * q)
+    AA = (q, q, q)
+    if grandchild_order == "last":
+        off, parent = [(0, 0, 0), A, B, AA], [-1, 0, 0, 1]
+    else:
+        off, parent = [(0, 0, 0), A, AA, B], [-1, 0, 1, 0]
+    if dim == 2:
+        off = [(o[0], o[1], 0) for o in off]
+    return Geometry(dim=dim, n=[N, N // 2, N // 2, N // 2], off=off, lo0=(-1.0, -1.0, -1.0), dx0=2.0 / N,
+                    parent=parent)
+
+
+def two_patch_2d(N: int = 64, grandchild_order: str = "last") -> Workload:
+    """Two manufactured Gaussian sources at (-1/2, 0) and (1/2, 0), each under
+    its own refined patch (a tree: two patches on level 1, one on level 2)."""
+    g = two_patch_geometry(2, N, grandchild_order)
+    return Workload("two_patch_2d_%d_%s" % (N, grandchild_order), g,
+                    GaussianSum([(1.0, 0.12, (-0.5, 0.0)), (0.6, 0.2, (0.5, 0.0))]))
+
+
+def two_patch_3d(N: int = 64, grandchild_order: str = "last") -> Workload:
+    """Two Plummer spheres (M = 1, a = 0.1 at (-1/2, 0, 0); M = 0.5, a = 0.06 at
+    (1/2, 0, 0)), each under its own refined patch (tree as in two_patch_2d)."""
+    g = two_patch_geometry(3, N, grandchild_order)
+    return Workload("two_patch_3d_%d_%s" % (N, grandchild_order), g,
+                    Plummer([(1.0, 0.1, (-0.5, 0.0, 0.0)), (0.5, 0.06, (0.5, 0.0, 0.0))]))

@@ -129,3 +129,50 @@ def test_plan_accepts_every_even_patch_size():
         g = W.Geometry(dim=3, n=[n], off=[(0, 0, 0)], lo0=(0, 0, 0), dx0=1.0)
         cfg = _lib.make_config(g)
         assert _lib.lib().nested_poisson_plan(ctypes.byref(cfg), ctypes.byref(_lib.NpPlan())) == 0, n
+
+
+def _tree_cfg(parent=None, off=None):
+    g = W.two_patch_geometry(3, 32)
+    cfg = _lib.make_config(g)
+    if parent is not None:
+        for l, p in enumerate(parent):
+            cfg.parent[l] = p
+    if off is not None:
+        l, o = off
+        for a in range(3):
+            cfg.offset[l][a] = o[a]
+    return cfg
+
+
+def test_default_parents_are_the_stack():
+    cfg = _lib.NpConfig()
+    _lib.lib().nested_poisson_default_config(ctypes.byref(cfg))
+    assert [cfg.parent[l] for l in range(_lib.NP_MAX_LEVELS)] == list(range(-1, _lib.NP_MAX_LEVELS - 1))
+
+
+def test_patch_tree_plans_and_validates_like_the_oracle():
+    cfg = _tree_cfg()
+    assert _lib.lib().nested_poisson_plan(ctypes.byref(cfg), ctypes.byref(_lib.NpPlan())) == 0
+    assert core.validate(W.two_patch_geometry(3, 32))
+    plan = _lib.plan(cfg)
+    assert [p["N"][0] for p in plan] == [34, 18, 18, 18]
+
+
+@pytest.mark.parametrize("bad", [
+    dict(parent=[-1, 0, 2, 1]),            # parent not an earlier entry
+    dict(parent=[-1, -1, 0, 1]),           # negative parent
+    dict(parent=[-1, 0, 0, 0], off=(3, (5, 13, 13))),  # grandchild moved under the base, onto patch A
+    dict(off=(2, (6, 10, 12))),            # patch B moved onto patch A
+    dict(off=(3, (1, 1, 9))),              # grandchild beyond its parent's margin
+], ids=["later_parent", "negative_parent", "overlap_base", "overlap_sibling", "margin"])
+def test_invalid_patch_trees_rejected(bad):
+    cfg = _tree_cfg(**bad)
+    assert _lib.lib().nested_poisson_plan(ctypes.byref(cfg), ctypes.byref(_lib.NpPlan())) == _lib.NP_EINVAL
+    g = W.two_patch_geometry(3, 32)
+    if "parent" in bad:
+        g.parent = bad["parent"]
+    if "off" in bad:
+        l, o = bad["off"]
+        g.off = list(g.off)
+        g.off[l] = o
+    assert not core.validate(g)

@@ -51,7 +51,8 @@ def _linf_force_error(wl, F):
     return norms.composite_norms(wl.geom, errs)[2]
 
 
-CASES = [W.c2_plummer(32), W.paper2d(32), W.c3_plummer_offset(32), W.c4_multi_plummer(7, N=32), W.paper3d(16)]
+CASES = [W.c2_plummer(32), W.paper2d(32), W.c3_plummer_offset(32), W.c4_multi_plummer(7, N=32), W.paper3d(16),
+         W.two_patch_3d(32), W.two_patch_2d(32, "middle")]
 
 
 @pytest.mark.parametrize("precision", ["fp32_dc", "fp16s_dc"])

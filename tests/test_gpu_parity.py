@@ -260,3 +260,43 @@ def test_interp_buffer_reuse_and_level0():
     s.solve(rho, po)
     assert torch.equal(s.potential(0), a[0])
     s.close()
+
+
+# ------------------------------------------------ several patches per level
+TREES = [W.two_patch_2d(32), W.two_patch_2d(32, "middle"), W.two_patch_3d(16), W.two_patch_3d(32, "middle")]
+
+
+@pytest.mark.parametrize("wl", TREES, ids=lambda w: w.name)
+def test_patch_tree_parity(wl):
+    """A tree of patches (two on level 1, one on level 2): with the oracle's
+    cycle counts and with the stop rule, potentials and forces of every patch
+    agree with the oracle."""
+    res, F_o = oracle_solve(wl)
+    assert res["status"] == 0
+    phi_g, F_g, st, _ = gpu_solve(wl, fixed=res["cycles"])
+    assert_parity(wl, phi_g, F_g, res, F_o)
+    phi_s, F_s, st_s, _ = gpu_solve(wl)
+    for l in range(wl.geom.nlevels):
+        assert abs(st_s["cycles"][l] - res["cycles"][l]) <= 1
+        assert st_s["final_rel_residual"][l] <= 1e-10
+    if st_s["cycles"] == res["cycles"]:
+        assert_parity(wl, phi_s, F_s, res, F_o)
+
+
+def test_patch_tree_paths_match_stacks():
+    """Each root-to-leaf path of the tree, solved on the GPU as a stack of one
+    patch per level, gives the tree's potentials bit for bit."""
+    wl = W.two_patch_3d(32)
+    g = wl.geom
+    phi_t, _, st_t, _ = gpu_solve(wl)
+    dev = torch.device("cuda")
+    rho, po = _inputs(wl, dev)
+    for path in ([0, 1, 3], [0, 2]):
+        chain = W.Geometry(dim=3, n=[g.n[l] for l in path], off=[g.off[l] for l in path], lo0=g.lo0, dx0=g.dx0,
+                           G=g.G)
+        s = NestedPoissonSolver(chain)
+        st = s.solve([rho[l] for l in path], po)
+        for k, l in enumerate(path):
+            assert torch.equal(s.potential(k).cpu(), torch.from_numpy(phi_t[l])), (path, l)
+            assert st["cycles"][k] == st_t["cycles"][l]
+        s.close()

@@ -272,3 +272,85 @@ def test_relaxed_buffer_lowers_the_interface_force_error():
             assert i >= 1.25 * r, (N, errs[N, False], errs[N, True])
     for a, b in zip(errs[32, True], errs[64, True]):
         assert 3.0 <= a / b <= 5.0, (errs[32, True], errs[64, True])
+
+
+# ------------------------------------------------ several patches per level
+def _chain_of(geom, path):
+    """The stack of one patch per level made of the entries `path` of a tree."""
+    return W.Geometry(dim=geom.dim, n=[geom.n[l] for l in path], off=[geom.off[l] for l in path], lo0=geom.lo0,
+                      dx0=geom.dx0, G=geom.G)
+
+
+@pytest.mark.parametrize("wl", [W.two_patch_2d(16), W.two_patch_2d(16, "middle"), W.two_patch_3d(8)],
+                         ids=lambda w: w.name)
+def test_patch_tree_reaches_the_direct_solution(wl):
+    """Two disjoint patches on level 1 and one on level 2: every patch converges
+    to the direct solution of its own discrete system, whose buffer data come
+    from its parent (interpolated from coordinates in the direct solve)."""
+    rho, po = _inputs(wl)
+    res = core.solve(wl.geom, rho, po, tol=1e-13, max_cycles=80)
+    assert res["status"] in (0, -3)
+    ex, _ = dense.solve(wl.geom, rho, po)
+    for l in range(wl.geom.nlevels):
+        err = np.abs(res["phi"][l] - ex[l]).max() / np.abs(ex[l]).max()
+        assert err < 1e-11, (l, err)
+
+
+@pytest.mark.parametrize("wl", [W.two_patch_2d(16), W.two_patch_3d(8, "middle")], ids=lambda w: w.name)
+def test_sibling_patches_are_independent(wl):
+    """One-way scheme: a patch depends only on its ancestors, so each root-to-
+    leaf path of the tree, solved as a stack of one patch per level, gives the
+    same potentials bit for bit."""
+    g = wl.geom
+    rho, po = _inputs(wl)
+    tree = core.solve(g, rho, po, tol=1e-12, max_cycles=60)
+    leaves = [l for l in range(g.nlevels) if not g.children(l)]
+    for leaf in leaves:
+        path = [leaf]
+        while path[-1] > 0:
+            path.append(g.par(path[-1]))
+        path = path[::-1]
+        chain = _chain_of(g, path)
+        res = core.solve(chain, [rho[l] for l in path], po, tol=1e-12, max_cycles=60)
+        for k, l in enumerate(path):
+            assert np.array_equal(res["phi"][k], tree["phi"][l]), (leaf, l)
+            assert res["cycles"][k] == tree["cycles"][l]
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_patch_tree_linear_potential_exact(dim):
+    """rho = 0, Phi = a.x + b on the tree: every patch reproduces Phi and F = -a."""
+    g = W.two_patch_geometry(dim, 16)
+    prob = W.Linear([0.7, -1.3, 0.4][:dim], 2.0)
+    rho, po = W.make_inputs(g, prob)
+    res = core.solve(g, [r.numpy() for r in rho], po.numpy(), tol=1e-13, max_cycles=60)
+    assert res["status"] == 0
+    for l in range(g.nlevels):
+        x = g.mesh(l, -2, g.n[l] + 4)
+        np.testing.assert_allclose(res["phi"][l], prob.phi(*x).numpy(), rtol=0, atol=2e-11)
+        F = core.forces(dim, g.dx(l), res["phi"][l])
+        for a in range(dim):
+            np.testing.assert_allclose(F[a], -prob.g[a], rtol=0, atol=1e-9)
+
+
+def test_patch_tree_second_order():
+    """Second order of the composite force and potential errors on the 2-D tree
+    under grid doubling (each point counted on the finest patch covering it)."""
+    out = []
+    for N in (32, 64, 128):
+        wl = W.two_patch_2d(N)
+        g, prob = wl.geom, wl.prob
+        rho, po = _inputs(wl)
+        res = core.solve(g, rho, po, tol=1e-12, max_cycles=80)
+        assert res["status"] == 0
+        ef, ep = [], []
+        for l in range(g.nlevels):
+            F = core.forces(2, g.dx(l), res["phi"][l])
+            x = g.mesh(l, 0, g.n[l])
+            Fa = [a.numpy() for a in prob.force(*x)]
+            ef.append(np.hypot(F[0] - Fa[0], F[1] - Fa[1]))
+            ep.append(res["phi"][l][2:-2, 2:-2] - prob.phi(*x).numpy())
+        out.append((norms.composite_norms(g, ef), norms.composite_norms(g, ep)))
+    for (fa, pa), (fb, pb) in zip(out[:-1], out[1:]):
+        for x, y in list(zip(fa, fb)) + list(zip(pa, pb)):
+            assert norms.order(x, y) > 1.75, (fa, fb, pa, pb)
