@@ -45,15 +45,20 @@ def workload(name, N):
         return W.c3_plummer_offset(N=N)
     if name == "paper3d":
         return W.paper3d(N)
+    if name == "two_patch":
+        # a tree: base level of N^3 cells, two disjoint (N/2)^3 patches on level 1
+        # around two Plummer spheres, one (N/2)^3 patch on level 2
+        return W.two_patch_3d(N)
     raise SystemExit("unknown workload %s" % name)
 
 
-def linf_force_error(solver, wl, F):
+def linf_force_error(solver, wl, Fs):
     """Composite max |F_num - F_analytic| over the cells of each level not covered by a finer one."""
     import torch
     geom = wl.geom
     worst = 0.0
     for l in range(geom.nlevels):
+        F = Fs[l]
         solver.forces(l, out=F)
         x = geom.mesh(l, 0, geom.n[l], device=F[0].device)
         Fa = wl.prob.force(*x)
@@ -61,21 +66,22 @@ def linf_force_error(solver, wl, F):
         for a in range(geom.dim):
             e += (F[a] - Fa[a]) ** 2
         e = e.sqrt()
-        if l + 1 < geom.nlevels:
-            o, h = geom.off[l + 1], geom.n[l + 1] // 2
+        for c in geom.children(l):
+            o, h = geom.off[c], geom.n[c] // 2
             e[o[2]:o[2] + h, o[1]:o[1] + h, o[0]:o[0] + h] = 0.0
         worst = max(worst, float(e.max()))
         del x, Fa, e
     return worst
 
 
-def edge_force_error(solver, wl, F, width=2):
+def edge_force_error(solver, wl, Fs, width=2):
     """Per refined level l >= 1: max |F_num - F_analytic| over the cells within
     `width` cells of the edge of Omega^l (next to the coarse-fine interface)."""
     import torch
     geom = wl.geom
     out = []
     for l in range(1, geom.nlevels):
+        F = Fs[l]
         solver.forces(l, out=F)
         x = geom.mesh(l, 0, geom.n[l], device=F[0].device)
         Fa = wl.prob.force(*x)
@@ -90,29 +96,40 @@ def edge_force_error(solver, wl, F, width=2):
     return out
 
 
-def cpu_baseline(wl, rho0, phi_outer, cycles_total, sample_cycles):
-    """The oracle's V(2,1) cycle on level 0 of the workload, timed on the host;
-    scaled to one nested solve by the total cycle count of the GPU solve (all
-    levels have the same size)."""
+def cpu_baseline(wl, rho, phi_outer, cycles_per_level, sample_cycles):
+    """The oracle's V(2,1) cycle on multigrid level 0 of each patch size of the
+    workload, timed on the host and scaled to one nested solve by the cycle
+    count of every patch in the GPU solve."""
     import numpy as np
     from oracle import core
     g = wl.geom
-    n = g.n[0]
-    P = n + 4
-    u = np.ascontiguousarray(phi_outer.cpu().numpy())
-    u[1:-1, 1:-1, 1:-1] = 0.0
-    f = np.zeros_like(u)
-    f[1:-1, 1:-1, 1:-1] = 4 * math.pi * g.G * rho0.cpu().numpy()
-    core.vcycle_patch(3, g.dx0, u, f)  # first touch of the pages
-    t0 = time.perf_counter()
-    for _ in range(sample_cycles):
-        core.vcycle_patch(3, g.dx0, u, f)
-    t = (time.perf_counter() - t0) / sample_cycles
-    ms_per_solve = t * 1e3 * cycles_total
+    t_of = {}
+    for l in range(g.nlevels):
+        n = g.n[l]
+        if n in t_of:
+            continue
+        P = n + 4
+        if l == 0:
+            u = np.ascontiguousarray(phi_outer.cpu().numpy())
+            u[1:-1, 1:-1, 1:-1] = 0.0
+            f = np.zeros_like(u)
+            f[1:-1, 1:-1, 1:-1] = 4 * math.pi * g.G * rho[0].cpu().numpy()
+        else:
+            u = np.zeros((P,) * 3)
+            f = np.zeros_like(u)
+            f[2:-2, 2:-2, 2:-2] = 4 * math.pi * g.G * rho[l].cpu().numpy()
+        core.vcycle_patch(3, g.dx(l), u, f)  # first touch of the pages
+        t0 = time.perf_counter()
+        for _ in range(sample_cycles):
+            core.vcycle_patch(3, g.dx(l), u, f)
+        t_of[n] = (time.perf_counter() - t0) / sample_cycles
+        del u, f
+    ms_per_solve = sum(t_of[g.n[l]] * 1e3 * cycles_per_level[l] for l in range(g.nlevels))
+    sizes = ", ".join("%d^3 active cells at %.4f s" % (n + 2, t) for n, t in t_of.items())
     return dict(value=ms_per_solve, unit="ms/solve", cores=core.num_threads(), kind="oracle",
-                sample="%d V(2,1) cycle(s) of level 0 (%d^3 active cells, padded %d^3) timed at %.3f s each, "
-                       "scaled by the %d cycles of one nested solve; setup, interface fills and forces not included"
-                       % (sample_cycles, n + 2, P, t, cycles_total))
+                sample="%d V(2,1) cycle(s) of multigrid level 0 per patch size (%s each), scaled by the cycles "
+                       "of every patch in one nested solve (%d in all); setup, interface fills and forces not "
+                       "included" % (sample_cycles, sizes, sum(cycles_per_level)))
 
 
 def copy_calibration():
@@ -139,7 +156,7 @@ VARIANTS = {
 ELEM = {"fp64": 8, "fp32_dc": 4, "fp16s_dc": 2}
 
 
-def run_variant(name, wl, rho, phi_outer, F, steps, warmup, inner_cycles):
+def run_variant(name, wl, rho, phi_outer, Fs, steps, warmup, inner_cycles):
     """Warm-up, then `steps` timed steps (solve + forces on every level) with the
     level-0 smoother timed by HIP events inside the library."""
     import torch
@@ -156,7 +173,7 @@ def run_variant(name, wl, rho, phi_outer, F, steps, warmup, inner_cycles):
     def step():
         st = solver.solve(rho, phi_outer)
         for l in range(geom.nlevels):
-            solver.forces(l, out=F)
+            solver.forces(l, out=Fs[l])
         return st
 
     for i in range(warmup):
@@ -185,8 +202,8 @@ def run_variant(name, wl, rho, phi_outer, F, steps, warmup, inner_cycles):
     half_sweep_bytes = 1.5 * elem * N0 ** geom.dim
     sm_count, sm_ms = prof["smooth"]
     sm_avg_ms = sm_ms / max(sm_count, 1)
-    linf = linf_force_error(solver, wl, F)
-    edge = edge_force_error(solver, wl, F)
+    linf = linf_force_error(solver, wl, Fs)
+    edge = edge_force_error(solver, wl, Fs)
     solver.close()
     log(name, "ms/solve %.2f  Linf force error %.6e" % (ms, linf))
     return dict(
@@ -197,8 +214,9 @@ def run_variant(name, wl, rho, phi_outer, F, steps, warmup, inner_cycles):
         learned_kept=stats[-1]["learned_used"],
         linf_force_error=linf,
         edge_force_error_per_level=edge,
-        smoother=dict(elem_bytes=elem, bytes_per_launch=half_sweep_bytes, avg_launch_us=round(sm_avg_ms * 1e3, 2),
-                      GBps=round(half_sweep_bytes / (sm_avg_ms * 1e-3) / 1e9, 1)),
+        smoother=(dict(elem_bytes=elem, bytes_per_launch=half_sweep_bytes, avg_launch_us=round(sm_avg_ms * 1e3, 2),
+                       GBps=round(half_sweep_bytes / (sm_avg_ms * 1e-3) / 1e9, 1)) if len(set(geom.n)) == 1 else
+                  dict(elem_bytes=elem, avg_launch_us=round(sm_avg_ms * 1e3, 2))),
         kernels={k: dict(launches=c, ms_per_step=round(m / steps, 3), avg_us=(round(1e3 * m / c, 2) if c else None))
                  for k, (c, m) in prof.items()},
     )
@@ -250,11 +268,16 @@ def main():
     log("workload", wl.name, geom.describe())
     rho, phi_outer = W.make_inputs(geom, wl.prob, device=dev)
     n = geom.n
-    if len(set(n)) != 1:
-        raise SystemExit("bench workloads use the same cell count on every level")
-    F = [torch.empty((n[0],) * geom.dim, dtype=torch.float64, device=dev) for _ in range(geom.dim)]
+    # the smoother roofline and the CPU baseline assume one grid size for every
+    # multigrid level 0; a workload with patches of several sizes reports neither
+    uniform = len(set(n)) == 1
+    Fs = {}
+    for l in range(geom.nlevels):
+        if n[l] not in Fs:
+            Fs[n[l]] = [torch.empty((n[l],) * geom.dim, dtype=torch.float64, device=dev) for _ in range(geom.dim)]
+    Fs = [Fs[n[l]] for l in range(geom.nlevels)]
 
-    res = {v: run_variant(v, wl, rho, phi_outer, F, args.steps, args.warmup, args.inner_cycles) for v in names}
+    res = {v: run_variant(v, wl, rho, phi_outer, Fs, args.steps, args.warmup, args.inner_cycles) for v in names}
 
     # headline: the fastest variant whose Linf force error matches the first
     # (plain) variant's within 0.5 %
@@ -265,10 +288,9 @@ def main():
     b = res[best]
 
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and geom.dim == 3:
         log("timing the CPU oracle on a sample ...")
-        cyc_total = sum(res[names[0]]["cycles_per_level"])
-        cpu = cpu_baseline(wl, rho[0], phi_outer, cyc_total, args.cpu_sample_cycles)
+        cpu = cpu_baseline(wl, rho, phi_outer, res[names[0]]["cycles_per_level"], args.cpu_sample_cycles)
         log("cpu baseline", cpu)
 
     sm = b["smoother"]
@@ -288,13 +310,13 @@ def main():
         "config": {
             "workload": wl.name,
             "levels": geom.nlevels,
-            "cells_per_level": "%d^%d" % (n[0], geom.dim),
+            "cells_per_level": ("%d^%d" % (n[0], geom.dim)) if uniform else ["%d^%d" % (m, geom.dim) for m in n],
             "variant": best,
             "stop": "||r||_inf <= 1e-10 ||f||_inf per level",
             "step": "nested solve + forces on every level",
             "inner_cycles": args.inner_cycles,
         },
-        "roofline": {
+        "roofline": None if not uniform else {
             "bound": "hbm",
             "kernel": "level-0 red-black half sweep of variant %s (%d-byte storage)" % (best, sm["elem_bytes"]),
             "achieved": sm["GBps"],
