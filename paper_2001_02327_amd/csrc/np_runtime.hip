@@ -200,6 +200,10 @@ struct np_solver {
     void* e_lo = nullptr;
     void* e_nx = nullptr;
     void* r_lo = nullptr;
+    // padded points per axis of the grid whose ghost layers in e_lo, e_nx and
+    // r_lo are known to be zero (no kernel writes a ghost point of these
+    // arrays; -1: not cleared yet)
+    int lo_ghost_nx = -1;
     size_t lo_bytes = 0;
     double* phi_alt = nullptr;
     size_t alt_cap = 0;
@@ -1000,14 +1004,19 @@ int nested_poisson_solve(np_solver* s, const double* const* rho, const double* p
         double rho = kAdaptiveRho0;
         int outer = 0;
         if (dc) {
-            // multigrid level 0 of the correction has a zero ghost layer; clear the
-            // whole array once per level (it is shared by levels of other sizes)
-            size_t esz = c.precision == NP_PREC_FP16S_DC ? sizeof(__half) : sizeof(float);
-            HIPCHK(s, hipMemsetAsync(s->e_lo, 0, 2 * s->lg[l].cs * esz, s->stream));
-            HIPCHK(s, hipMemsetAsync(s->e_nx, 0, 2 * s->lg[l].cs * esz, s->stream));
-            // the defect's ghost layer stands in for the correction's (zero) where
-            // a black half sweep forms the red values from the defect
-            if (dc_seed_black(s, l)) HIPCHK(s, hipMemsetAsync(s->r_lo, 0, 2 * s->lg[l].cs * esz, s->stream));
+            // multigrid level 0 of the correction has a zero ghost layer, and the
+            // defect's ghost layer stands in for it where a black half sweep forms
+            // the red values from the defect.  The arrays are shared by the levels:
+            // cleared whole when this level's grid differs from the one they were
+            // last cleared for (every kernel writes their active points only, and
+            // each active point is written before it is read within a level)
+            if (s->lg[l].nx != s->lo_ghost_nx) {
+                size_t esz = c.precision == NP_PREC_FP16S_DC ? sizeof(__half) : sizeof(float);
+                HIPCHK(s, hipMemsetAsync(s->e_lo, 0, 2 * s->lg[l].cs * esz, s->stream));
+                HIPCHK(s, hipMemsetAsync(s->e_nx, 0, 2 * s->lg[l].cs * esz, s->stream));
+                HIPCHK(s, hipMemsetAsync(s->r_lo, 0, 2 * s->lg[l].cs * esz, s->stream));
+                s->lo_ghost_nx = s->lg[l].nx;
+            }
             // the outer pass writes only active points of the other potential
             // buffer: give it this level's fixed ghost layer
             launch_copy_ghosts(c.dim, s->stream, s->lg[l], s->phi[l], s->phi_alt);

@@ -170,3 +170,28 @@ def test_dc_adaptive_inner_cycles(wl, precision):
     assert st64["outer_steps"] == [0] * wl.geom.nlevels
     e64 = _linf_force_error(wl, F64)
     assert abs(_linf_force_error(wl, F) - e64) <= 5e-3 * e64
+
+
+@pytest.mark.parametrize("precision", ["fp32_dc", "fp16s_dc"])
+def test_dc_repeat_solves_identical(precision):
+    """The low-precision arrays are shared by the levels and cleared only when
+    the grid size changes: two solves on one handle (levels of sizes 16, 8, 8,
+    12, so the arrays are reused across equal sizes and cleared between
+    different ones) and a solve on a fresh handle agree bit for bit."""
+    g = W.Geometry(dim=3, n=[16, 8, 8, 12], off=[(0, 0, 0), (4, 4, 4), (1, 1, 1), (1, 1, 1)],
+                   lo0=(-0.5, -0.5, -0.5), dx0=1.0 / 16)
+    wl = W.Workload("sizes_16_8_8_12", g, W.Plummer([(1.0, 0.1, (0.01, -0.02, 0.03))]))
+    dev = torch.device("cuda")
+    rho, po = W.make_inputs(wl.geom, wl.prob, device=dev)
+    s = NestedPoissonSolver(wl.geom, precision=precision, inner_cycles="adaptive")
+    s.solve(rho, po)
+    a = [s.potential(l).clone() for l in range(g.nlevels)]
+    s.solve(rho, po)
+    b = [s.potential(l).clone() for l in range(g.nlevels)]
+    s.close()
+    s = NestedPoissonSolver(wl.geom, precision=precision, inner_cycles="adaptive")
+    s.solve(rho, po)
+    c = [s.potential(l).clone() for l in range(g.nlevels)]
+    s.close()
+    for x, y, z in zip(a, b, c):
+        assert torch.equal(x, y) and torch.equal(x, z)
