@@ -87,3 +87,46 @@ def test_converged_solve_at_514(problem, settings):
         del F, Fo
         f_prev, phi_prev = f, phi
     s.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp16s_dc"])
+def test_single_patch_1020(precision):
+    """The largest patch tested: one level of 1020^3 cells, 1022^3 points on
+    multigrid level 0 and 2^30 points in its two colour arrays (8.6 GB per FP64
+    array), where the level-0 restriction takes its generic form (the arrays
+    pass 2^31 bytes).  The stop criterion, recomputed by the oracle in FP64
+    over every active point, holds, and the forces equal the oracle's stencil
+    on sampled blocks (corners, edges, interior)."""
+    n = 1020
+    g = W.Geometry(dim=3, n=[n], off=[(0, 0, 0)], lo0=(-1.0, -1.0, -1.0), dx0=2.0 / n)
+    prob = W.Plummer([(1.0, 0.1, (0.013, -0.021, 0.007))])
+    print("case: single patch 1020^3, %s" % precision, flush=True)
+    dev = torch.device("cuda")
+    settings = dict(precision=precision, inner_cycles="adaptive") if precision != "fp64" else {}
+    s = NestedPoissonSolver(g, **settings)
+    rho, po = W.make_inputs(g, prob, device=dev)
+    st = s.solve(rho, po)
+    del po
+    assert st["final_rel_residual"][0] <= 1e-10
+    phi = s.potential(0).cpu().numpy()
+    f = np.zeros_like(phi)
+    f[1:-1, 1:-1, 1:-1] = 4 * math.pi * g.G * rho[0].cpu().numpy()
+    del rho
+    fmax = np.abs(f).max()
+    rnorm = core.residual_norm(3, g.dx0, phi, f)
+    print("%d V-cycles, ||r|| / ||f|| = %.3e (library %.3e)" % (st["cycles"][0], rnorm / fmax,
+                                                               st["final_rel_residual"][0]), flush=True)
+    assert rnorm <= 1e-10 * fmax * (1 + 1e-4)
+    del f
+    F = s.forces(0)
+    B = 16
+    for k0, j0, i0 in [(0, 0, 0), (n - B, n - B, n - B), (0, n - B, 500), (501, 300, 700)]:
+        sub = np.ascontiguousarray(phi[k0:k0 + B + 4, j0:j0 + B + 4, i0:i0 + B + 4])
+        Fo = core.forces(3, g.dx0, sub)
+        fscale = max(np.abs(a).max() for a in Fo)
+        for ax in range(3):
+            Fg = F[ax][k0:k0 + B, j0:j0 + B, i0:i0 + B].cpu().numpy()
+            e = np.abs(Fg - Fo[ax]).max() / fscale
+            assert e <= 1e-11, ((k0, j0, i0), ax, e)
+    del F
+    s.close()
