@@ -7,9 +7,10 @@ already resident in HBM.  Default workload: two Plummer spheres (M = 1,
 a = 0.03 at the origin; M = 0.3, a = 0.015 at (0.2, 0, 0)), 5 nested levels
 of 512^3 cells, level k covering [-2^-k, 2^-k]^3, FP64.
 
-Prints one JSON line (rank 0): time per nested solve, the roofline of the
-level-0 smoother measured with HIP events inside the timed steps, the force
-error against the closed form, and the CPU oracle timed on a bounded sample.
+Prints one JSON line (rank 0): time per nested solve (timed steps with no
+per-kernel events), the roofline of the level-0 smoother measured with the
+library's HIP events over a second pass of the same steps, the force error
+against the closed form, and the CPU oracle timed on a bounded sample.
 """
 import argparse
 import json
@@ -179,8 +180,7 @@ def run_variant(name, wl, rho, phi_outer, Fs, steps, warmup, inner_cycles, stop_
     for i in range(warmup):
         st = step()
         log(name, "warmup", i, "cycles", st["cycles"], "ms %.1f" % st["total_ms"])
-    torch.cuda.synchronize()
-    solver.set_profiling(True)
+    # timed region: `steps` steps as a caller runs them (no per-kernel events)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -193,6 +193,18 @@ def run_variant(name, wl, rho, phi_outer, Fs, steps, warmup, inner_cycles, stop_
     torch.cuda.synchronize()
     wall_ms = (time.perf_counter() - t0) * 1e3
     ms = e0.elapsed_time(e1) / steps
+    # the same steps again with the library's HIP events around every kernel class
+    # (per-kernel averages for the roofline line; the events leave a gap of ~10 us
+    # before every kernel launched outside the coarse-level graph, so this pass is
+    # slower and is reported beside the headline, not as it)
+    solver.set_profiling(True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for i in range(steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_profiled = e0.elapsed_time(e1) / steps
     prof = solver.profile()
     solver.set_profiling(False)
     N0 = geom.n[0] + 2
@@ -209,6 +221,7 @@ def run_variant(name, wl, rho, phi_outer, Fs, steps, warmup, inner_cycles, stop_
     return dict(
         ms_per_solve=round(ms, 3),
         wall_ms_per_step=round(wall_ms / steps, 3),
+        ms_per_solve_with_kernel_events=round(ms_profiled, 3),
         cycles_per_level=stats[-1]["cycles"],
         outer_steps_per_level=stats[-1]["outer_steps"],
         learned_kept=stats[-1]["learned_used"],
