@@ -300,3 +300,31 @@ def test_patch_tree_paths_match_stacks():
             assert torch.equal(s.potential(k).cpu(), torch.from_numpy(phi_t[l])), (path, l)
             assert st["cycles"][k] == st_t["cycles"][l]
         s.close()
+
+
+def test_patch_tree_with_interp_buffer():
+    """The two extensions together: a tree of patches solved with both buffer
+    layers interpolated (each patch from its own parent) agrees with the oracle."""
+    wl = W.two_patch_3d(16, "middle")
+    res, F_o = oracle_solve(wl, buffer_interp=True)
+    assert res["status"] == 0
+    phi_g, F_g, st, _ = gpu_solve(wl, fixed=res["cycles"], buffer="interp")
+    assert_parity(wl, phi_g, F_g, res, F_o)
+
+
+def test_patch_tree_force_change_stop():
+    """The paper's force-change stop rule on a tree, FP64 and FP16-storage
+    defect correction: cycle counts within one of the oracle's, and the FP16
+    path reaches the oracle's potential to the defect-correction bar."""
+    wl = W.two_patch_2d(32)
+    res, F_o = oracle_solve(wl, stop_rule=1)
+    assert res["status"] == 0
+    phi_g, F_g, st, _ = gpu_solve(wl, stop_rule="force_delta")
+    for l in range(wl.geom.nlevels):
+        assert abs(st["cycles"][l] - res["cycles"][l]) <= 1
+    if st["cycles"] == res["cycles"]:
+        assert_parity(wl, phi_g, F_g, res, F_o)
+    phi_h, _, st_h, _ = gpu_solve(wl, stop_rule="force_delta", precision="fp16s_dc", inner_cycles="adaptive")
+    for l in range(wl.geom.nlevels):
+        err = np.abs(phi_h[l] - res["phi"][l]).max() / np.abs(res["phi"][l]).max()
+        assert err <= 1e-8, (l, err)
