@@ -106,11 +106,18 @@ int launch_coarse_tail(int dim, hipStream_t st, int nlev, const int* N, const do
 // defect correction, one fused outer pass: phi_out = phi_in + factor * e_in
 // (no update and no write of phi_out when e_in is null), r = (f - lap phi_out)
 // * rscale in low precision (+ its FP64 max norm into maxbits), and the next
-// correction e_out: zero, or with first_red the first red half sweep from zero
+// correction e_out (not written when null): zero, or with first_red the first
+// red half sweep from zero
 template <typename TL>
 void launch_dc_outer(int dim, hipStream_t st, SGrid g, const double* phi_in, const TL* e_in, double factor,
                      double* phi_out, const double* f, double inv_h2, double rscale, TL* r, TL* e_out, int first_red,
                      unsigned long long* maxbits);
+// r = (TL)(r32 * rscale) on the active points (r32: f - lap phi in FP32 from a
+// pass of launch_dc_outer<float> with rscale 1), and the next correction's start
+// into e_out (may be null) as launch_dc_outer writes it
+template <typename TL>
+void launch_dc_scale(int dim, hipStream_t st, SGrid g, const float* r32, double rscale, TL* r, TL* e_out,
+                     int first_red);
 // ghost layer of a nested-level array copied from src to dst
 void launch_copy_ghosts(int dim, hipStream_t st, SGrid g, const double* src, double* dst);
 // dst(p) = src(p + shift) for the points p of grid gd with lo <= p_a <= hi on

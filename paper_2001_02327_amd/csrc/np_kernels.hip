@@ -2086,7 +2086,34 @@ __device__ __forceinline__ void dc_out(size_t self, int colour, double v, double
     r[self] = rl;
     TL e0 = (TL)0.0f;
     if (colour == 0 && first_red) e0 = (TL)((0.0f - h2l * (float)rl) * inv2d);
-    eout[self] = e0;
+    if (eout) eout[self] = e0;
+}
+
+// r'' = r32 * rscale on the active points of a level (r32: f - lap phi kept in
+// FP32 by the level's first residual pass), rounded through FP32 as the outer
+// pass rounds, and the next correction's start as the outer pass writes it (the
+// red half sweep from zero on red points, zero on black) when e is not null
+template <int D, typename TL>
+__global__ void __launch_bounds__(kBlock) k_dc_scale(SGrid g, const float* __restrict__ r32, double rscale,
+                                                     TL* __restrict__ r, TL* __restrict__ e, int first_red,
+                                                     float h2l, float inv2d)
+{
+    const int m = g.nx - 2;
+    const long total = (long)g.hx * m * (D == 3 ? m : 1);
+    const long stride = (long)gridDim.x * kBlock;
+    for (long t = xcd_block() * kBlock + threadIdx.x; t < total; t += stride) {
+        const int h = (int)(t % g.hx);
+        const long rr = t / g.hx;
+        const int pj = 1 + (int)(rr % m);
+        const int pk = D == 3 ? 1 + (int)(rr / m) : 0;
+        const size_t row = row_base(g, pj, pk);
+        for (int c = 0; c < 2; c++) {
+            const int pi = 2 * h + ((c + pj + pk + D) & 1);
+            if (pi < 1 || pi > g.nx - 2) continue;
+            const size_t self = (size_t)c * g.cs + row + h;
+            dc_out<TL>(self, c, (double)r32[self], rscale, r, e, first_red, h2l, inv2d);
+        }
+    }
 }
 
 template <int D, typename TL, bool UPD>
@@ -2704,6 +2731,23 @@ void launch_dc_outer(int dim, hipStream_t st, SGrid g, const double* phi_in, con
                            DcIn<TL, false>{phi_in, nullptr, 0.0}, phi_out, f, inv_h2, rscale, r, e_out, first_red, h2l,
                            inv2d, maxbits);
 }
+
+template <typename TL>
+void launch_dc_scale(int dim, hipStream_t st, SGrid g, const float* r32, double rscale, TL* r, TL* e_out,
+                     int first_red)
+{
+    const float h2l = 1.0f, inv2d = (float)(1.0 / (2.0 * dim));
+    int blocks = ceil_div(ncompact_active(dim, g), kBlock);
+    if (blocks > 16384) blocks = 16384;
+    if (dim == 3)
+        hipLaunchKernelGGL((k_dc_scale<3, TL>), dim3(blocks), dim3(kBlock), 0, st, g, r32, rscale, r, e_out, first_red,
+                           h2l, inv2d);
+    else
+        hipLaunchKernelGGL((k_dc_scale<2, TL>), dim3(blocks), dim3(kBlock), 0, st, g, r32, rscale, r, e_out, first_red,
+                           h2l, inv2d);
+}
+template void launch_dc_scale<float>(int, hipStream_t, SGrid, const float*, double, float*, float*, int);
+template void launch_dc_scale<__half>(int, hipStream_t, SGrid, const float*, double, __half*, __half*, int);
 
 void launch_copy_ghosts(int dim, hipStream_t st, SGrid g, const double* src, double* dst)
 {

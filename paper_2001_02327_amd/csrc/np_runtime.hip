@@ -204,6 +204,9 @@ struct np_solver {
     // r_lo are known to be zero (no kernel writes a ghost point of these
     // arrays; -1: not cleared yet)
     int lo_ghost_nx = -1;
+    // f - lap phi of a level's starting potential in FP32 (active points), from
+    // which its first scaled defect is formed
+    float* r32 = nullptr;
     size_t lo_bytes = 0;
     double* phi_alt = nullptr;
     size_t alt_cap = 0;
@@ -564,6 +567,44 @@ int dc_outer_sync(np_solver* s, int l, bool update, double factor, double rscale
     return NP_OK;
 }
 
+// The level's starting residual for the defect correction: one pass of the
+// outer kernel without update that keeps f - lap phi in FP32 (r32) and returns
+// its max norm, so that the first scaled defect needs no second pass over phi
+// and f (dc_scale_defect).
+int dc_first_residual(np_solver* s, int l, double* out)
+{
+    const np_config& c = s->cfg;
+    double dx = level_dx(&c, l);
+    launch_set_u64(s->stream, s->d_bits, 1, 0ULL);
+    prof_begin(s, NP_KCLASS_NORM);
+    launch_dc_outer<float>(c.dim, s->stream, s->lg[l], s->phi[l], nullptr, 0.0, nullptr, s->f[l], 1.0 / (dx * dx), 1.0,
+                           s->r32, nullptr, 0, s->d_bits);
+    prof_end(s);
+    HIPCHK(s, hipGetLastError());
+    HIPCHK(s, hipMemcpyAsync(s->h_bits, s->d_bits, sizeof(unsigned long long), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    *out = bits_to_double(s->h_bits[0]);
+    return NP_OK;
+}
+
+// The first defect of a level from r32: r'' = r32 * rscale and the next
+// correction's start, as the outer pass without update writes them.
+int dc_scale_defect(np_solver* s, int l, double rscale)
+{
+    const np_config& c = s->cfg;
+    void* e_out = dc_seed_black(s, l) ? nullptr : s->e_lo;
+    prof_begin(s, NP_KCLASS_DC);
+    if (c.precision == NP_PREC_FP16S_DC)
+        launch_dc_scale<__half>(c.dim, s->stream, s->lg[l], s->r32, rscale, (__half*)s->r_lo, (__half*)e_out,
+                                c.n_pre > 0);
+    else
+        launch_dc_scale<float>(c.dim, s->stream, s->lg[l], s->r32, rscale, (float*)s->r_lo, (float*)e_out,
+                               c.n_pre > 0);
+    prof_end(s);
+    HIPCHK(s, hipGetLastError());
+    return NP_OK;
+}
+
 // Inner cycles of one defect-correction step (extension of Sec. 2.3 with FP32
 // or FP16-stored inner cycles): k low-precision V-cycles on the scaled defect
 // r'' = r / r_scale, the first one starting from the state the outer pass left
@@ -717,6 +758,8 @@ void free_all(np_solver* s)
     if (s->e_lo) (void)hipFree(s->e_lo);
     if (s->e_nx) (void)hipFree(s->e_nx);
     if (s->r_lo) (void)hipFree(s->r_lo);
+    if (s->r32) (void)hipFree(s->r32);
+    s->r32 = nullptr;
     if (s->phi_alt) (void)hipFree(s->phi_alt);
     s->e_lo = s->e_nx = s->r_lo = nullptr;
     s->phi_alt = nullptr;
@@ -859,6 +902,7 @@ int nested_poisson_create(const np_config* cfg, void* hip_stream, np_solver** ou
         rc = alloc_dev(s, &s->e_lo, s->lo_bytes);
         if (rc == NP_OK) rc = alloc_dev(s, &s->e_nx, s->lo_bytes);
         if (rc == NP_OK) rc = alloc_dev(s, &s->r_lo, s->lo_bytes);
+        if (rc == NP_OK) rc = alloc_dev(s, (void**)&s->r32, best * sizeof(float));
         s->alt_cap = best * sizeof(double);
         if (rc == NP_OK) rc = alloc_dev(s, (void**)&s->phi_alt, s->alt_cap);
     }
@@ -979,8 +1023,13 @@ int nested_poisson_solve(np_solver* s, const double* const* rho, const double* p
             if (rc) return rc;
             if (!std::isfinite(scale)) return set_err(s, NP_ENONFINITE, "level %d: non-finite boundary data", l);
         }
+        // with the defect correction the starting residual pass also keeps
+        // f - lap phi in FP32, the source of the level's first scaled defect
+        // (unless the learned guess changes phi after it)
+        const bool dc = c.precision != NP_PREC_FP64;
+        const bool r32_start = dc && c.guess != NP_GUESS_LEARNED;
         double r = 0.0;
-        rc = norm_sync(s, l, 0, &r);
+        rc = r32_start ? dc_first_residual(s, l, &r) : norm_sync(s, l, 0, &r);
         if (rc) return rc;
         st.interp_rel_residual[l] = scale > 0 ? r / scale : r;
         if (l > 0 && c.guess == NP_GUESS_LEARNED) {
@@ -998,7 +1047,6 @@ int nested_poisson_solve(np_solver* s, const double* const* rho, const double* p
         int q = 0;
         int lvl = NP_OK;
         // defect correction: r_lo holds (f - lap phi) / r_scale for the current phi
-        const bool dc = c.precision != NP_PREC_FP64;
         bool have_defect = false;
         double r_scale = 1.0;
         double rho = kAdaptiveRho0;
@@ -1033,7 +1081,8 @@ int nested_poisson_solve(np_solver* s, const double* const* rho, const double* p
                 if (!have_defect) {
                     double same = 0.0;
                     r_scale = r > 0 ? r : 1.0;
-                    rc = dc_outer_sync(s, l, false, 0.0, 1.0 / r_scale, &same);
+                    rc = r32_start ? dc_scale_defect(s, l, 1.0 / r_scale)
+                                   : dc_outer_sync(s, l, false, 0.0, 1.0 / r_scale, &same);
                     if (rc) return rc;
                     have_defect = true;
                 }
