@@ -185,6 +185,7 @@ struct np_solver {
     bool prof = false;
     std::vector<hipEvent_t> ev;  // pairs (start, stop)
     std::vector<int> ev_cls;
+    std::vector<int> ev_n;  // kernel launches inside each interval
     int ev_used = 0;
     int cur_cls = 0;
     long prof_count[NP_NKCLASS] = {};
@@ -264,7 +265,7 @@ int prof_flush(np_solver* s)
         HIPCHK(s, hipEventElapsedTime(&ms, s->ev[i], s->ev[i + 1]));
         int c = s->ev_cls[i / 2];
         s->prof_ms[c] += ms;
-        s->prof_count[c] += 1;
+        s->prof_count[c] += s->ev_n[i / 2];
     }
     s->ev_used = 0;
     return NP_OK;
@@ -278,11 +279,14 @@ void prof_begin(np_solver* s, int cls)
     (void)hipEventRecord(s->ev[s->ev_used], s->stream);
 }
 
-void prof_end(np_solver* s)
+// closes the interval opened by prof_begin; it held `launches` kernels of the
+// class (back to back on the stream), whose average duration the profile reports
+void prof_end(np_solver* s, int launches = 1)
 {
     if (!s->prof) return;
     (void)hipEventRecord(s->ev[s->ev_used + 1], s->stream);
     s->ev_cls[s->ev_used / 2] = s->cur_cls;
+    s->ev_n[s->ev_used / 2] = launches;
     s->ev_used += 2;
 }
 
@@ -291,6 +295,7 @@ void prof_release(np_solver* s)
     for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
     s->ev.clear();
     s->ev_cls.clear();
+    s->ev_n.clear();
     s->ev_used = 0;
     s->prof = false;
 }
@@ -438,9 +443,12 @@ int vcycle_t(np_solver* s, int l, T0* u0, const T0* f0, double h2_0, double inv_
     const np_config& c = s->cfg;
     const int d = c.dim;
     hipStream_t st = s->stream;
+    // the half sweeps of one smoothing step run back to back: one profiling
+    // interval over all of them (launch count recorded), so the per-launch
+    // average carries no event overhead between the sweeps
+    int nsweep = 0;
     auto sweep0 = [&]() {
         for (int colour = red_done ? 1 : 0; colour < 2; colour++) {
-            prof_begin(s, NP_KCLASS_SMOOTH);
             bool seeded = false;
             if constexpr (sizeof(T0) <= 4) {
                 if (red_done && red_unstored) {
@@ -449,11 +457,18 @@ int vcycle_t(np_solver* s, int l, T0* u0, const T0* f0, double h2_0, double inv_
                 }
             }
             if (!seeded) launch_half_sweep<T0>(d, st, v.g[0], u0, f0, colour, h2_0, 1, 0, 0.0);
-            prof_end(s);
+            nsweep++;
             red_done = false;
         }
     };
-    for (int it = 0; it < c.n_pre; it++) sweep0();
+    auto smooth0 = [&](int sweeps) {
+        if (sweeps <= 0) return;
+        nsweep = 0;
+        prof_begin(s, NP_KCLASS_SMOOTH);
+        for (int it = 0; it < sweeps; it++) sweep0();
+        prof_end(s, nsweep);
+    };
+    smooth0(c.n_pre);
     // the restriction does multigrid level 1's first red half sweep unless the
     // coarse tail starts at level 1 (coarse_part then skips it)
     const bool seed1 = c.n_pre > 0 && tail_level(s, l, sizeof(TC)) != 1;
@@ -471,7 +486,7 @@ int vcycle_t(np_solver* s, int l, T0* u0, const T0* f0, double h2_0, double inv_
     launch_prolong_add<TC, T0>(d, st, v.g[1], v.u[1], v.g[0], u0, c.n_post > 0, s->plan.xn_is_one[l][1],
                                s->plan.ghost_coef[l][1]);
     prof_end(s);
-    for (int it = 0; it < c.n_post; it++) sweep0();
+    smooth0(c.n_post);
     return NP_OK;
 }
 
@@ -1281,6 +1296,7 @@ int nested_poisson_set_profiling(np_solver* s, int enable)
         const int pool = 4096;
         s->ev.resize(pool);
         s->ev_cls.resize(pool / 2);
+        s->ev_n.resize(pool / 2);
         for (int i = 0; i < pool; i++) {
             if (hipEventCreate(&s->ev[i]) != hipSuccess) {
                 s->ev.resize(i);
