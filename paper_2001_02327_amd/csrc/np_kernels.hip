@@ -31,6 +31,19 @@ struct alignas(2 * sizeof(T)) Pair {
     T a, b;
 };
 
+// Stores marked non-temporal, for FP64 data written once and not read again
+// before much more than the caches hold has passed through them (the updated
+// potential of the defect-correction pass, the forces, the coarse-to-fine
+// fill): they then do not displace what the next kernels read.
+__device__ __forceinline__ void store_nt(double* p, double v) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void store_nt(Pair<double>* p, const Pair<double>& v)
+{
+    typedef double d2_t __attribute__((ext_vector_type(2)));
+    const d2_t x = {v.a, v.b};
+    __builtin_nontemporal_store(x, (d2_t*)p);
+}
+constexpr bool kFillNt = true;  // non-temporal stores in the level setup kernels as well
+
 // Consecutive level-0 kernels of a V-cycle run their z-chunks in alternating
 // directions (rev: the logical block order reversed), so that each starts on
 // the planes the previous one touched last, which the memory-side cache still
@@ -189,8 +202,13 @@ __global__ void __launch_bounds__(kBlock) k_level0_init(SGrid g, const double* _
             int m = g.nx - 2;
             size_t ri = D == 3 ? (((size_t)(pk - 1) * m + (pj - 1)) * m + (pi - 1)) : ((size_t)(pj - 1) * m + (pi - 1));
             const double v = fourpiG * rho0[ri];
-            phi[p] = 0.0;
-            f[p] = v;
+            if (kFillNt) {
+                store_nt(phi + p, 0.0);
+                store_nt(f + p, v);
+            } else {
+                phi[p] = 0.0;
+                f[p] = v;
+            }
             const unsigned long long b = abs_bits(v);
             best = b > best ? b : best;
         }
@@ -490,10 +508,17 @@ __global__ void __launch_bounds__(kBlock) k_interface_fill3_pair(SGrid gc, const
                 const int ce = (pj + p + 1) & 1;
                 const size_t base = (size_t)p * gf.ps + prow;
                 Pair<double> pe{ph[0], ph[2]}, po{ph[1], ph[3]}, fe{fv[0], fv[2]}, fo{fv[1], fv[3]};
-                *(Pair<double>*)(phif + (size_t)ce * gf.cs + base) = pe;
-                *(Pair<double>*)(phif + (size_t)(ce ^ 1) * gf.cs + base) = po;
-                *(Pair<double>*)(ff + (size_t)ce * gf.cs + base) = fe;
-                *(Pair<double>*)(ff + (size_t)(ce ^ 1) * gf.cs + base) = fo;
+                if (kFillNt) {
+                    store_nt((Pair<double>*)(phif + (size_t)ce * gf.cs + base), pe);
+                    store_nt((Pair<double>*)(phif + (size_t)(ce ^ 1) * gf.cs + base), po);
+                    store_nt((Pair<double>*)(ff + (size_t)ce * gf.cs + base), fe);
+                    store_nt((Pair<double>*)(ff + (size_t)(ce ^ 1) * gf.cs + base), fo);
+                } else {
+                    *(Pair<double>*)(phif + (size_t)ce * gf.cs + base) = pe;
+                    *(Pair<double>*)(phif + (size_t)(ce ^ 1) * gf.cs + base) = po;
+                    *(Pair<double>*)(ff + (size_t)ce * gf.cs + base) = fe;
+                    *(Pair<double>*)(ff + (size_t)(ce ^ 1) * gf.cs + base) = fo;
+                }
             }
 #pragma unroll
             for (int y = 0; y < 2; y++)
@@ -615,9 +640,9 @@ __global__ void __launch_bounds__(kBlock) k_forces3_zm(SGrid g, int n, double m1
                 if (j0 + r >= n) continue;
                 const long o = ((long)(k0 + q) * n + (j0 + r)) * n + i;
                 const int w = r + 2;
-                fx[o] = (8.0 * (xp1[r][q] - xm1[r][q]) - (xp2[r][q] - xm2[r][q])) * m12dx;
-                fy[o] = (8.0 * (yv(w + 1, q) - yv(w - 1, q)) - (yv(w + 2, q) - yv(w - 2, q))) * m12dx;
-                fz[o] = (8.0 * (col[r][q + 3] - col[r][q + 1]) - (col[r][q + 4] - col[r][q])) * m12dx;
+                store_nt(fx + o, (8.0 * (xp1[r][q] - xm1[r][q]) - (xp2[r][q] - xm2[r][q])) * m12dx);
+                store_nt(fy + o, (8.0 * (yv(w + 1, q) - yv(w - 1, q)) - (yv(w + 2, q) - yv(w - 2, q))) * m12dx);
+                store_nt(fz + o, (8.0 * (col[r][q + 3] - col[r][q + 1]) - (col[r][q + 4] - col[r][q])) * m12dx);
             }
         }
     }
@@ -2331,7 +2356,7 @@ __global__ void __launch_bounds__(kBlock) k_dc_outer3_pair(SGrid g, DcIn<TL, UPD
                     el.b = (TL)((0.0f - h2l * (float)rl.b) * inv2d);
                 }
                 if (a0 && a1) {
-                    if (UPD) *(Pair<double>*)(pout + self) = cur[c];
+                    if (UPD) store_nt((Pair<double>*)(pout + self), cur[c]);
                     if (OUT) {
                         *(Pair<TL>*)(r + self) = rl;
                         if (eout) *(Pair<TL>*)(eout + self) = el;
@@ -2341,7 +2366,7 @@ __global__ void __launch_bounds__(kBlock) k_dc_outer3_pair(SGrid g, DcIn<TL, UPD
                     best = b0 > best ? b0 : best;
                 } else {
                     if (a0) {
-                        if (UPD) pout[self] = cur[c].a;
+                        if (UPD) store_nt(pout + self, cur[c].a);
                         if (OUT) {
                             r[self] = rl.a;
                             if (eout) eout[self] = el.a;
@@ -2350,7 +2375,7 @@ __global__ void __launch_bounds__(kBlock) k_dc_outer3_pair(SGrid g, DcIn<TL, UPD
                         best = b0 > best ? b0 : best;
                     }
                     if (a1) {
-                        if (UPD) pout[self + 1] = cur[c].b;
+                        if (UPD) store_nt(pout + self + 1, cur[c].b);
                         if (OUT) {
                             r[self + 1] = rl.b;
                             if (eout) eout[self + 1] = el.b;
