@@ -43,6 +43,15 @@ __device__ __forceinline__ void store_nt(Pair<double>* p, const Pair<double>& v)
     __builtin_nontemporal_store(x, (d2_t*)p);
 }
 constexpr bool kFillNt = true;  // non-temporal stores in the level setup kernels as well
+// load of FP64 data read once and not again soon (the right-hand side in the
+// defect-correction pass)
+__device__ __forceinline__ Pair<double> load_nt(const Pair<double>* p)
+{
+    typedef double d2_t __attribute__((ext_vector_type(2)));
+    const d2_t x = __builtin_nontemporal_load((const d2_t*)p);
+    return Pair<double>{x.x, x.y};
+}
+constexpr bool kDcLoadNt = true;
 
 // Consecutive level-0 kernels of a V-cycle run their z-chunks in alternating
 // directions (rev: the logical block order reversed), so that each starts on
@@ -2306,7 +2315,8 @@ __global__ void __launch_bounds__(kBlock) k_dc_outer3_pair(SGrid g, DcIn<TL, UPD
                 d.above[c] = dc_pair(in, c * cs + here + plane);
                 d.ym[c] = dc_pair(in, c * cs + here - g.hx);
                 d.yp[c] = dc_pair(in, c * cs + here + g.hx);
-                d.fv[c] = *(const Pair<double>*)(f + c * cs + here);
+                d.fv[c] = kDcLoadNt ? load_nt((const Pair<double>*)(f + c * cs + here))
+                                    : *(const Pair<double>*)(f + c * cs + here);
                 // the extra x-neighbour of colour c's points (other colour o), inside
                 // the plane (neighbouring row at the row ends)
                 const int par = (c + pj + pk + 3) & 1;
