@@ -114,7 +114,8 @@ void launch_dc_outer(int dim, hipStream_t st, SGrid g, const double* phi_in, con
                      unsigned long long* maxbits);
 // r = (TL)(r32 * rscale) on the active points (r32: f - lap phi in FP32 from a
 // pass of launch_dc_outer<float> with rscale 1), and the next correction's start
-// into e_out (may be null) as launch_dc_outer writes it
+// into e_out (may be null) as launch_dc_outer writes it.  In 3-D the whole
+// arrays are scaled: r32 must be zero at every point that is not active
 template <typename TL>
 void launch_dc_scale(int dim, hipStream_t st, SGrid g, const float* r32, double rscale, TL* r, TL* e_out,
                      int first_red);

@@ -2767,11 +2767,50 @@ void launch_dc_outer(int dim, hipStream_t st, SGrid g, const double* phi_in, con
                            inv2d, maxbits);
 }
 
+// k_dc_scale over whole arrays, 8 consecutive elements per thread: with r32
+// zero at every point that is not active (cleared with the level's other
+// low-precision arrays; the residual pass writes active points only) the
+// ghost points of r and e come out zero, as the point-wise form leaves them.
+// Needs cs a multiple of 8 (3-D planes are padded to 128 elements).
+template <typename TL>
+__global__ void __launch_bounds__(kBlock) k_dc_scale_flat(long n8, size_t cs, const float* __restrict__ r32,
+                                                          double rscale, TL* __restrict__ r, TL* __restrict__ e,
+                                                          int first_red, float h2l, float inv2d)
+{
+    const long stride = (long)gridDim.x * kBlock;
+    for (long t = xcd_block() * kBlock + threadIdx.x; t < n8; t += stride) {
+        const size_t i = (size_t)t * 8;
+        const int colour = i < cs ? 0 : 1;
+        const float4 a = *(const float4*)(r32 + i);
+        const float4 b = *(const float4*)(r32 + i + 4);
+        const float v[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+        TL rl[8], el[8];
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+            rl[k] = (TL)(float)((double)v[k] * rscale);
+            el[k] = (colour == 0 && first_red) ? (TL)((0.0f - h2l * (float)rl[k]) * inv2d) : (TL)0.0f;
+        }
+#pragma unroll
+        for (int k = 0; k < 8; k += 2) {
+            *(Pair<TL>*)(r + i + k) = Pair<TL>{rl[k], rl[k + 1]};
+            if (e) *(Pair<TL>*)(e + i + k) = Pair<TL>{el[k], el[k + 1]};
+        }
+    }
+}
+
 template <typename TL>
 void launch_dc_scale(int dim, hipStream_t st, SGrid g, const float* r32, double rscale, TL* r, TL* e_out,
                      int first_red)
 {
     const float h2l = 1.0f, inv2d = (float)(1.0 / (2.0 * dim));
+    if (dim == 3 && g.cs % 8 == 0) {
+        const long n8 = (long)(2 * g.cs / 8);
+        int blocks = ceil_div(n8, kBlock);
+        if (blocks > 16384) blocks = 16384;
+        hipLaunchKernelGGL((k_dc_scale_flat<TL>), dim3(blocks), dim3(kBlock), 0, st, n8, g.cs, r32, rscale, r, e_out,
+                           first_red, h2l, inv2d);
+        return;
+    }
     int blocks = ceil_div(ncompact_active(dim, g), kBlock);
     if (blocks > 16384) blocks = 16384;
     if (dim == 3)

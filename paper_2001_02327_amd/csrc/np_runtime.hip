@@ -205,9 +205,11 @@ struct np_solver {
     // r_lo are known to be zero (no kernel writes a ghost point of these
     // arrays; -1: not cleared yet)
     int lo_ghost_nx = -1;
-    // f - lap phi of a level's starting potential in FP32 (active points), from
-    // which its first scaled defect is formed
+    // f - lap phi of a level's starting potential in FP32 (active points; zero
+    // elsewhere, cleared when the grid changes: r32_nx), from which its first
+    // scaled defect is formed
     float* r32 = nullptr;
+    int r32_nx = -1;
     size_t lo_bytes = 0;
     double* phi_alt = nullptr;
     size_t alt_cap = 0;
@@ -590,6 +592,10 @@ int dc_first_residual(np_solver* s, int l, double* out)
 {
     const np_config& c = s->cfg;
     double dx = level_dx(&c, l);
+    if (s->lg[l].nx != s->r32_nx) {
+        HIPCHK(s, hipMemsetAsync(s->r32, 0, 2 * s->lg[l].cs * sizeof(float), s->stream));
+        s->r32_nx = s->lg[l].nx;
+    }
     launch_set_u64(s->stream, s->d_bits, 1, 0ULL);
     prof_begin(s, NP_KCLASS_NORM);
     launch_dc_outer<float>(c.dim, s->stream, s->lg[l], s->phi[l], nullptr, 0.0, nullptr, s->f[l], 1.0 / (dx * dx), 1.0,
