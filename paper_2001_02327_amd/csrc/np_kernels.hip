@@ -11,6 +11,11 @@ namespace np {
 namespace {
 
 constexpr int kBlock = 256;
+// block sizes measured per kernel at 514^3 (128 / 256 / 512 threads): the paired
+// level-0 half sweep 92.8 / 84.3 / 82.5 us, the forces 1217 / 1248 / 2805 us;
+// every other kernel is fastest at kBlock
+constexpr int kSmoothPairBlock = 512;
+constexpr int kForceBlock = 128;
 
 __host__ __device__ inline int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }
 
@@ -591,7 +596,7 @@ __global__ void __launch_bounds__(kBlock) k_forces(SGrid g, int n, double m12dx,
 constexpr int kForceChunk = 8;
 constexpr int kForceRows = 4;
 
-__global__ void __launch_bounds__(kBlock) k_forces3_zm(SGrid g, int n, double m12dx, const double* __restrict__ phi,
+__global__ void __launch_bounds__(kForceBlock) k_forces3_zm(SGrid g, int n, double m12dx, const double* __restrict__ phi,
                                                        double* __restrict__ fx, double* __restrict__ fy,
                                                        double* __restrict__ fz, int pblocks)
 {
@@ -600,7 +605,7 @@ __global__ void __launch_bounds__(kBlock) k_forces3_zm(SGrid g, int n, double m1
     const int nrb = (n + R - 1) / R;
     const int lb = (int)xcd_block();
     const int zc = lb / pblocks;
-    const int t = (lb - zc * pblocks) * kBlock + (int)threadIdx.x;
+    const int t = (lb - zc * pblocks) * kForceBlock + (int)threadIdx.x;
     if (t >= (long)n * nrb) return;
     const int i = (int)(t % n), j0 = R * (int)(t / n);
     const int k0 = zc * KC;
@@ -1111,7 +1116,7 @@ __device__ __forceinline__ float mix_add2(uint32_t a, uint32_t b)
 // not stored: the red values are formed from the defect f (red) here, in the
 // same arithmetic (its ghost layer is zero, as is the correction's).
 template <typename T, bool SEED = false>
-__global__ void __launch_bounds__(kBlock) k_smooth_zmarch3_pair(T* __restrict__ u, const T* __restrict__ f, SGrid g,
+__global__ void __launch_bounds__(kSmoothPairBlock) k_smooth_zmarch3_pair(T* __restrict__ u, const T* __restrict__ f, SGrid g,
                                                                 int colour, typename Compute<T>::type h2,
                                                                 typename Compute<T>::type inv2d, int pblocks)
 {
@@ -1127,7 +1132,7 @@ __global__ void __launch_bounds__(kBlock) k_smooth_zmarch3_pair(T* __restrict__ 
     const int m = g.nx - 2;
     const int lb = zmarch_block(colour);  // red half sweeps up, black down
     const int zc = lb / pblocks;
-    const int t = (lb - zc * pblocks) * kBlock + (int)threadIdx.x;
+    const int t = (lb - zc * pblocks) * kSmoothPairBlock + (int)threadIdx.x;
     // flat pair index over the whole (padded) plane: each wave covers 128
     // consecutive compact elements, an aligned segment; the ghost rows and the
     // plane padding have no work
@@ -2510,9 +2515,9 @@ void launch_forces(int dim, hipStream_t st, SGrid g, int n, double dx, const dou
 {
     double m12dx = -1.0 / (12.0 * dx);
     if (dim == 3) {
-        const int pblocks = ceil_div((long)n * ((n + kForceRows - 1) / kForceRows), kBlock);
-        hipLaunchKernelGGL(k_forces3_zm, dim3(pblocks * ceil_div(n, kForceChunk)), dim3(kBlock), 0, st, g, n, m12dx,
-                           phi, fx, fy, fz, pblocks);
+        const int pblocks = ceil_div((long)n * ((n + kForceRows - 1) / kForceRows), kForceBlock);
+        hipLaunchKernelGGL(k_forces3_zm, dim3(pblocks * ceil_div(n, kForceChunk)), dim3(kForceBlock), 0, st, g, n,
+                           m12dx, phi, fx, fy, fz, pblocks);
         return;
     }
     Strip sp = make_strip(n, n, 1, 16);
@@ -2575,10 +2580,10 @@ void launch_half_sweep(int dim, hipStream_t st, SGrid g, T* u, const T* f, int c
         // (on the coarse levels, with the ghost rule, this form measured slower
         // than k_smooth_zmarch3)
         long m = g.nx - 2;
-        int pblocks = ceil_div((long)(g.ps / 2), kBlock);
+        int pblocks = ceil_div((long)(g.ps / 2), kSmoothPairBlock);
         int chunks = ceil_div(m, kZChunk0);
-        hipLaunchKernelGGL((k_smooth_zmarch3_pair<T>), dim3(pblocks * chunks), dim3(kBlock), 0, st, u, f, g, colour,
-                           (C)h2, inv2d, pblocks);
+        hipLaunchKernelGGL((k_smooth_zmarch3_pair<T>), dim3(pblocks * chunks), dim3(kSmoothPairBlock), 0, st, u, f, g,
+                           colour, (C)h2, inv2d, pblocks);
         return;
     }
     if (dim == 3 && (fine || g.nx >= 34)) {
@@ -2610,10 +2615,10 @@ void launch_half_sweep_seeded(hipStream_t st, SGrid g, T* u, const T* f, double 
 {
     using C = typename Compute<T>::type;
     const long m = g.nx - 2;
-    const int pblocks = ceil_div((long)(g.ps / 2), kBlock);
+    const int pblocks = ceil_div((long)(g.ps / 2), kSmoothPairBlock);
     const int chunks = ceil_div(m, kZChunk0);
-    hipLaunchKernelGGL((k_smooth_zmarch3_pair<T, true>), dim3(pblocks * chunks), dim3(kBlock), 0, st, u, f, g, 1, (C)h2,
-                       (C)(1.0 / 6.0), pblocks);
+    hipLaunchKernelGGL((k_smooth_zmarch3_pair<T, true>), dim3(pblocks * chunks), dim3(kSmoothPairBlock), 0, st, u, f,
+                       g, 1, (C)h2, (C)(1.0 / 6.0), pblocks);
 }
 
 template <typename TF, typename TC>
