@@ -29,7 +29,7 @@ PEAK_HBM_GBS = 8000.0   # MI355X HBM3E peak
 # WRITE_SIZE x 1.0, the factors a 1 GiB device copy and fill give) for the smoother
 # kernels of this source tree: k_smooth_zmarch3_pair<__half> (FP16 storage) and
 # k_smooth_zmarch3<double> (FP64).  Valid only for those kernels at that size.
-SMOOTHER_TRAFFIC = {("fp16s_dc", 514): 0.2908e9 + 0.1363e9, ("fp64", 514): 1.3696e9 + 0.5453e9}
+SMOOTHER_TRAFFIC = {("fp16s_dc", 514): 0.2896e9 + 0.1363e9, ("fp64", 514): 1.3711e9 + 0.5453e9}
 
 
 def log(*a):
