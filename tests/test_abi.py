@@ -90,7 +90,7 @@ def _bad(**kw):
 
 
 @pytest.mark.parametrize("kw", [
-    dict(dim=4), dict(nlevels=0), dict(nlevels=9), dict(n=(1, 7)), dict(n=(0, 2)), dict(off=(1, 0, 0)),
+    dict(dim=4), dict(nlevels=0), dict(nlevels=9), dict(nlevels=17), dict(n=(1, 7)), dict(n=(0, 2)), dict(off=(1, 0, 0)),
     dict(off=(2, 2, 9)), dict(dx0=0.0), dict(tol=-1.0), dict(max_cycles=0), dict(max_cycles=100000),
     dict(n_pre=-1), dict(stop_rule=7), dict(inner_cycles=-1), dict(inner_cycles=9), dict(buffer=2),
     dict(buffer=1, precision=1), dict(buffer=1, precision=2), dict(buffer=1, guess=1), dict(buffer=1, stop_rule=1),

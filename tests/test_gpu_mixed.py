@@ -73,6 +73,24 @@ def test_dc_reaches_fp64_solution(wl, precision):
 
 
 @pytest.mark.parametrize("precision", ["fp32_dc", "fp16s_dc"])
+def test_dc_maximum_depth(precision):
+    """Sixteen nested 8^3 levels around a Plummer core 2^-13 wide: the
+    right-hand side grows ~4^l down the stack, which the per-level defect
+    scaling must absorb; every level reaches the converged FP64 solution."""
+    g = W.centred_geometry(3, 16, 8, 0.5, 1.0)
+    wl = W.Workload("deepest3d_16x8", g, W.Plummer([(1.0, 0.5 ** 13, (0.0, 0.0, 0.0))]))
+    rho, po = W.make_inputs(g, wl.prob)
+    ref = core.solve(g, [r.numpy() for r in rho], po.numpy(), tol=1e-13, max_cycles=120)
+    _, _, st64 = _solve(wl)
+    phi, _, st = _solve(wl, precision=precision)
+    for l in range(16):
+        err = np.abs(phi[l] - ref["phi"][l]).max() / np.abs(ref["phi"][l]).max()
+        assert err <= 1e-8, (l, err)
+        assert st["final_rel_residual"][l] <= 1e-10
+        assert st["cycles"][l] <= st64["cycles"][l] + 2, (st["cycles"], st64["cycles"])
+
+
+@pytest.mark.parametrize("precision", ["fp32_dc", "fp16s_dc"])
 def test_dc_inner_cycles_and_stress(precision):
     """Two inner cycles per step; the offset a = 0.02 Plummer puts ||4 pi G rho||
     near 3.7e5, beyond FP16 range unless the defect is scaled."""

@@ -208,6 +208,32 @@ def test_plummer_128_full_parity():
     assert_parity(wl, phi_g, F_g, res, F_o)
 
 
+def _deepest(dim):
+    # the largest number of levels a solve takes: 16 patches of 8^d, each half
+    # its parent's width, around a Plummer core of the finest level's size
+    g = W.centred_geometry(dim, 16, 8, 0.5, 1.0)
+    if dim == 2:
+        terms = [(1.0, 0.5 ** k, (0.0, 0.0)) for k in (2, 5, 8, 11, 14)]
+        return W.Workload("deepest2d_16x8", g, W.GaussianSum(terms))
+    return W.Workload("deepest3d_16x8", g, W.Plummer([(1.0, 0.5 ** 13, (0.0, 0.0, 0.0))]))
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_maximum_depth_parity(dim):
+    """Sixteen nested levels (the library's limit, 2^15 between the coarsest
+    and finest spacing): cycle counts of the stop rule within one of the
+    oracle's, and at the oracle's counts potentials and forces to the FP64 bars."""
+    wl = _deepest(dim)
+    res, F_o = oracle_solve(wl)
+    assert res["status"] == 0
+    phi_g, F_g, st, _ = gpu_solve(wl, fixed=res["cycles"])
+    assert_parity(wl, phi_g, F_g, res, F_o)
+    _, _, st_s, _ = gpu_solve(wl)
+    for l in range(16):
+        assert abs(st_s["cycles"][l] - res["cycles"][l]) <= 1
+        assert st_s["final_rel_residual"][l] <= 1e-10
+
+
 # ------------------------------------------------ comparison scheme of Sec. 4
 INTERP_BUFFER = [W.paper2d(16), W.paper3d(16), W.c2_plummer(16), W.c3_plummer_offset(16), _ragged3d(), _ragged2d(),
                  _minimal()]
