@@ -121,6 +121,33 @@ def test_dc_zero_density_and_force_rule():
         assert np.abs(phi[l] - phi64[l]).max() / np.abs(phi64[l]).max() <= 1e-8
 
 
+@pytest.mark.parametrize("precision", ["fp32_dc", "fp16s_dc"])
+def test_dc_single_level_minimal_patch_and_linear(precision):
+    """Degenerate shapes: one level only (no interface), the minimal patch
+    (8^3 base with a 4^3 child: hierarchies 8, 4, 2, 1 and 4, 2, 1), both to
+    the converged FP64 solution; and a linear potential with zero density,
+    which the discrete operator reproduces exactly, to FP64 rounding."""
+    single = W.Workload("single3d_16", W.Geometry(dim=3, n=[16], off=[(0, 0, 0)], lo0=(-0.5, -0.5, -0.5),
+                                                   dx0=1.0 / 16), W.Plummer([(1.0, 0.15, (0.03, 0.0, -0.02))]))
+    minimal = W.Workload("minimal3d_8_4", W.Geometry(dim=3, n=[8, 4], off=[(0, 0, 0), (2, 2, 2)],
+                                                     lo0=(-0.5, -0.5, -0.5), dx0=1.0 / 8),
+                         W.Plummer([(1.0, 0.2, (0.0, 0.0, 0.0))]))
+    for wl in (single, minimal):
+        rho, po = W.make_inputs(wl.geom, wl.prob)
+        ref = core.solve(wl.geom, [r.numpy() for r in rho], po.numpy(), tol=1e-13, max_cycles=120)
+        phi, _, st = _solve(wl, precision=precision)
+        for l in range(wl.geom.nlevels):
+            err = np.abs(phi[l] - ref["phi"][l]).max() / np.abs(ref["phi"][l]).max()
+            assert err <= 1e-8, (wl.name, l, err)
+            assert st["final_rel_residual"][l] <= 1e-10
+    geom = W.centred_geometry(3, 3, 16, 0.5, 1.0)
+    wl = W.Workload("linear", geom, W.Linear([0.7, -1.3, 0.4], 2.0))
+    phi, _, st = _solve(wl, precision=precision, tol=1e-12, max_cycles=80)
+    for l in range(geom.nlevels):
+        x = geom.mesh(l, -2, geom.n[l] + 4)
+        np.testing.assert_allclose(phi[l], wl.prob.phi(*x).numpy(), rtol=0, atol=1e-9)
+
+
 def _ragged_levels_3d():
     # level sizes 16, 8, 12: the spare potential buffer of the defect correction
     # is larger than levels 1 and 2, so an odd number of outer passes there
