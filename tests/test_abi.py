@@ -176,3 +176,18 @@ def test_invalid_patch_trees_rejected(bad):
         g.off = list(g.off)
         g.off[l] = o
     assert not core.validate(g)
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """Without the built HIP library every entry point raises (no CPU fallback)."""
+    from paper_2001_02327_amd.solver import NestedPoissonSolver
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "absent.so"))
+    monkeypatch.setattr(_lib, "_lib", None)
+    with pytest.raises(RuntimeError, match="not built"):
+        _lib.lib()
+    g = W.centred_geometry(3, 2, 16, 0.5, 1.0)
+    with pytest.raises(RuntimeError, match="not built"):
+        _lib.plan(_lib.make_config(g))
+    # the solver refuses too (here, without a device, before it reaches the library)
+    with pytest.raises(RuntimeError):
+        NestedPoissonSolver(g)
