@@ -257,8 +257,8 @@ def main():
         args.inner_cycles = int(args.inner_cycles)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: the nested solve has no multi-GPU path in this build "
-              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        print("bench.py measures one GPU: the nested solve runs on one device, with no multi-GPU "
+              "path (--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
     import torch

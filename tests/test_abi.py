@@ -191,3 +191,15 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     # the solver refuses too (here, without a device, before it reaches the library)
     with pytest.raises(RuntimeError):
         NestedPoissonSolver(g)
+
+
+def test_bench_refuses_several_gpus():
+    """bench.py measures one GPU and says so for --gpus N > 1 (before touching a device)."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and "--gpus 2" in r.stderr

@@ -193,7 +193,7 @@ def _solve(wl, theta=None, **kw):
     return phi, st
 
 
-def test_learned_guess_is_judged_by_multigrid():
+def test_learned_guess_is_checked_by_multigrid():
     """Untrained or broken weights never change the answer: the V-cycles reach
     the same tolerance, and a guess that is worse than the interpolant (NaN
     weights here) is discarded."""
