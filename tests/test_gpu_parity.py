@@ -234,6 +234,18 @@ def test_maximum_depth_parity(dim):
         assert st_s["final_rel_residual"][l] <= 1e-10
 
 
+@pytest.mark.parametrize("dim", [2, 3])
+def test_maximum_depth_interp_buffer(dim):
+    """The comparison scheme of Sec. 4 over sixteen nested levels (each level
+    l >= 1 relaxes only Omega^l = 8^d cells between interpolated buffer layers):
+    potentials and forces to the FP64 bars at the oracle's cycle counts."""
+    wl = _deepest(dim)
+    res, F_o = oracle_solve(wl, buffer_interp=True)
+    assert res["status"] == 0
+    phi_g, F_g, st, _ = gpu_solve(wl, fixed=res["cycles"], buffer="interp")
+    assert_parity(wl, phi_g, F_g, res, F_o)
+
+
 # ------------------------------------------------ comparison scheme of Sec. 4
 INTERP_BUFFER = [W.paper2d(16), W.paper3d(16), W.c2_plummer(16), W.c3_plummer_offset(16), _ragged3d(), _ragged2d(),
                  _minimal()]
