@@ -123,6 +123,21 @@ def test_force_change_stop_rule(wl):
         assert_parity(wl, phi_g, F_g, res, F_o)
 
 
+@pytest.mark.parametrize("wl", [W.paper2d(1024), W.paper3d(128)], ids=lambda w: w.name)
+def test_paper_problems_largest_sizes(wl):
+    """The paper's 2-D problem at its largest N (4 levels of 1024^2, finest
+    spacing 1/8192) and its 3-D problem at N = 128, under the paper's own
+    force-change rule: full-array parity at the oracle's cycle counts, and the
+    GPU's own stop within one cycle of the oracle's on every level."""
+    res, F_o = oracle_solve(wl, stop_rule=1)
+    assert res["status"] == 0
+    phi_g, F_g, _, _ = gpu_solve(wl, fixed=res["cycles"])
+    assert_parity(wl, phi_g, F_g, res, F_o)
+    _, _, st, _ = gpu_solve(wl, stop_rule="force_delta")
+    for l in range(wl.geom.nlevels):
+        assert abs(st["cycles"][l] - res["cycles"][l]) <= 1, (st["cycles"], res["cycles"])
+
+
 @pytest.mark.parametrize("wl", [W.paper2d(16), W.paper3d(8), _ragged3d()], ids=lambda w: w.name)
 def test_cycle_by_cycle(wl):
     """After 0, 1, 2 and 3 cycles on level 0 (and the interface fill alone on
