@@ -33,6 +33,26 @@ def test_multigrid_reaches_the_direct_solution(wl):
 
 
 @pytest.mark.parametrize("dim", [2, 3])
+def test_sixteen_levels_reach_the_direct_solution(dim):
+    """The deepest nesting a solve takes (16 levels of 8^d, spacings from 1/8 to
+    2^-18): level offsets, spacings and interpolation weights stay right down
+    the stack (the direct solve interpolates from physical coordinates)."""
+    g = W.centred_geometry(dim, 16, 8, 0.5, 1.0)
+    if dim == 2:
+        prob = W.GaussianSum([(1.0, 0.5 ** k, (0.0, 0.0)) for k in (2, 5, 8, 11, 14)])
+    else:
+        prob = W.Plummer([(1.0, 0.5 ** 13, (0.0, 0.0, 0.0))])
+    wl = W.Workload("deepest", g, prob)
+    rho, po = _inputs(wl)
+    res = core.solve(g, rho, po, tol=1e-13, max_cycles=80)
+    assert res["status"] in (0, -3)
+    ex, _ = dense.solve(g, rho, po)
+    for l in range(16):
+        err = np.abs(res["phi"][l] - ex[l]).max() / np.abs(ex[l]).max()
+        assert err < 1e-11, (l, err)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
 def test_linear_potential_is_exact_on_every_level(dim):
     """rho = 0, Phi = a.x + b: interpolation (App. A) and the Laplacian are exact,
     so every level reproduces Phi at its centres and F = -a everywhere; the
