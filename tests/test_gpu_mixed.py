@@ -148,6 +148,19 @@ def test_dc_single_level_minimal_patch_and_linear(precision):
         np.testing.assert_allclose(phi[l], wl.prob.phi(*x).numpy(), rtol=0, atol=1e-9)
 
 
+@pytest.mark.parametrize("precision", ["fp32_dc", "fp16s_dc"])
+def test_dc_paper2d_largest_size(precision):
+    """The paper's 2-D problem at N = 1024 (finest spacing 1/8192) under its
+    force-change rule: the defect correction reaches the FP64 solve's
+    potential on every level."""
+    wl = W.paper2d(1024)
+    phi64, _, _ = _solve(wl, stop_rule="force_delta")
+    phi, _, _ = _solve(wl, precision=precision, stop_rule="force_delta")
+    for l in range(wl.geom.nlevels):
+        err = np.abs(phi[l] - phi64[l]).max() / np.abs(phi64[l]).max()
+        assert err <= 1e-8, (l, err)
+
+
 def _ragged_levels_3d():
     # level sizes 16, 8, 12: the spare potential buffer of the defect correction
     # is larger than levels 1 and 2, so an odd number of outer passes there
