@@ -162,6 +162,8 @@ typedef struct np_stats {
     int learned_used[NP_MAX_LEVELS];          /* 1 where the learned guess was kept */
     double interp_rel_residual[NP_MAX_LEVELS];/* relative residual of the interpolated guess */
     int outer_steps[NP_MAX_LEVELS];           /* defect-correction steps (0 for NP_PREC_FP64) */
+    double guess_box_ratio[NP_MAX_LEVELS];    /* learned guess: its residual restricted twice (mean over
+                                                 4^3 boxes, max norm) over the interpolated guess's */
 } np_stats;
 int nested_poisson_solve(np_solver* s, const double* const* rho, const double* phi_outer, np_stats* stats);
 
@@ -216,9 +218,13 @@ int nested_poisson_get_profile(np_solver* s, np_profile* out);
  *   output y on Gamma^l, guess = Phi_interp + ||f||_inf dx_l^2 y,
  * network conv3x3x3(2->16) -> ReLU -> conv3x3x3(16->16) -> ReLU ->
  * conv3x3x3(16->1), zero padding, same size.  The V-cycles then iterate to the
- * same tolerance; the learned guess is kept only if its max-norm residual is
- * at most half that of the interpolated guess (else, or if non-finite, it is
- * discarded).
+ * same tolerance.  The guess is kept only where it should save a V-cycle:
+ * the cycle count is set by the error the smoother leaves, whose residual
+ * survives restriction, so the guess is kept if its residual restricted twice
+ * (the mean over boxes of 4^3 points, max norm) is at most rho times that of
+ * the interpolated guess, rho being the contraction per V-cycle measured on
+ * the parent level's solve (0.3 before any); otherwise, or if non-finite, it
+ * is discarded.
  * Parameter vector (NP_NET_PARAMS floats): for each layer its weights
  * [27 taps][cout][cin] (taps ordered dz, dy, dx in -1..1, dx fastest) then its
  * cout biases.  Activations of the np_net_* kernels are FP32 (or bfloat16 as
@@ -226,10 +232,34 @@ int nested_poisson_get_profile(np_solver* s, np_profile* out);
  * bfloat16 device arrays; every call is queued on `stream` (hipStream_t). */
 #define NP_NET_PARAMS 8241
 
-/* Copies the host parameter vector (FP32, NP_NET_PARAMS values) into the
- * handle; required before a solve with guess = NP_GUESS_LEARNED.
- * Errors: NP_EINVAL (size), NP_ENOMEM, NP_EHIP. */
-int nested_poisson_set_guess_weights(np_solver* s, const float* theta, size_t n);
+/* Versioned parameter blob of the network (host memory, little-endian):
+ *   header, NP_GUESS_BLOB_HEADER bytes of uint32: magic NP_GUESS_BLOB_MAGIC
+ *     ("NPGW"), version NP_GUESS_BLOB_VERSION, layer count 3, then cin and
+ *     cout of each layer (2,16), (16,16), (16,1), then 0;
+ *   per layer: its bfloat16 weights [27 taps][cout][cin] (taps ordered
+ *     dz, dy, dx in -1..1, dx fastest), then its cout FP32 biases.
+ * NP_GUESS_BLOB_BYTES in all. */
+#define NP_GUESS_BLOB_MAGIC 0x5747504eu /* "NPGW" */
+#define NP_GUESS_BLOB_VERSION 1
+#define NP_GUESS_BLOB_HEADER 40
+#define NP_GUESS_BLOB_BYTES (NP_GUESS_BLOB_HEADER + 2 * (27 * (2 * 16 + 16 * 16 + 16 * 1)) + 4 * (16 + 16 + 1))
+
+/* Packs a parameter vector (FP32, NP_NET_PARAMS values, the layout above with
+ * FP32 weights) into a blob of nbytes >= NP_GUESS_BLOB_BYTES, rounding the
+ * weights to bfloat16 (nearest even).  Host only; touches no device.
+ * Errors: NP_EINVAL (null pointer, n != NP_NET_PARAMS, blob too small). */
+int nested_poisson_pack_guess_weights(const float* theta, size_t n, void* blob, size_t nbytes);
+
+/* Checks a blob's header, layer shapes and size (nbytes must equal
+ * NP_GUESS_BLOB_BYTES) and that every bias is finite.  Host only.
+ * Errors: NP_EINVAL with a message in nested_poisson_last_error(NULL). */
+int nested_poisson_check_guess_weights(const void* blob, size_t nbytes);
+
+/* Copies a blob (host memory, checked as above before any device work) into
+ * the handle; required before a solve with guess = NP_GUESS_LEARNED.
+ * Errors: NP_EINVAL (bad blob: wrong magic, version, shapes or size),
+ * NP_ESTATE (handle created without the learned guess), NP_EHIP. */
+int nested_poisson_set_guess_weights(np_solver* s, const void* blob, size_t nbytes);
 
 /* Training data of level `level` >= 1 after a successful solve: the network
  * input x ((n+2)^3 x 2 FP32, channel-last) built from the interpolated guess,
@@ -269,6 +299,15 @@ int np_net_adam(float* w, const float* g, float* m, float* v, long n, float lr, 
                 int step, unsigned short* w_bf16, void* stream);
 /* bfloat16 copy (round to nearest even). */
 int np_net_to_bf16(const float* a, unsigned short* b, long n, void* stream);
+/* a = bfloat16(a) in place, kept as FP32 (the training forward pass stores its
+ * inputs and hidden activations at the precision the inference path uses). */
+int np_net_round_bf16(float* a, long n, void* stream);
+/* out = the 7-point stencil of eqn:Laplacian3D without the 1/dx^2 factor (sum
+ * of the six face neighbours minus six times the centre), zero outside the
+ * box, on one-channel [batch][z][y][x] FP32 arrays (in != out).  The
+ * stencil is symmetric, so it is also its own adjoint (the backward pass of
+ * the residual training objective). */
+int np_net_lap7(const float* in, int batch, int nz, int ny, int nx, float* out, void* stream);
 
 /* Frees every library allocation of the handle.  NULL-safe. */
 void nested_poisson_destroy(np_solver* s);

@@ -38,15 +38,32 @@ class OrcConfig(ctypes.Structure):
 
 
 _lib = None
+_native = False
+
+
+def use_native(on=True):
+    """Switch every following call to the -O3 -march=native build of the same
+    source (built here on first use), or back to the portable build."""
+    global _lib, _native
+    if bool(on) != _native:
+        _lib = None
+        _native = bool(on)
+        if _native:
+            _build.build_native()
+
+
+def build_flags():
+    return " ".join(_build.NATIVE_FLAGS) if _native else "-O2 (generic x86-64)"
 
 
 def lib():
-    """Load oracle/liboracle.so, building it with gcc if it is not there."""
+    """Load oracle/liboracle.so (or the native build), building it with gcc if it is not there."""
     global _lib
     if _lib is None:
-        if not os.path.exists(_build.LIB):
-            _build.build()
-        L = ctypes.CDLL(_build.LIB)
+        path = _build.LIB_NATIVE if _native else _build.LIB
+        if not os.path.exists(path):
+            _build.build_native() if _native else _build.build()
+        L = ctypes.CDLL(path)
         L.orc_plan.argtypes = [ctypes.c_int, _ip, ctypes.c_int]
         L.orc_plan.restype = ctypes.c_int
         L.orc_ghost_rule.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _ip, _dp]
@@ -70,6 +87,7 @@ def lib():
                                        ctypes.c_int, ctypes.c_int]
         L.orc_vcycle_patch.restype = ctypes.c_int
         L.orc_num_threads.restype = ctypes.c_int
+        L.orc_set_threads.argtypes = [ctypes.c_int]
         _lib = L
     return _lib
 
@@ -151,6 +169,10 @@ def forces(dim, dx, phi):
 
 def num_threads():
     return lib().orc_num_threads()
+
+
+def set_threads(n):
+    lib().orc_set_threads(int(n))
 
 
 def vcycle_patch(dim, h0, u, f, n_pre=2, n_post=1, literal=False):

@@ -678,3 +678,10 @@ int orc_vcycle_patch(int dim, int N0, double h0, double *u, const double *f, int
 
 /* threads the OpenMP loops of the oracle use */
 int orc_num_threads(void) { return omp_get_max_threads(); }
+
+/* thread count of the parallel loops (timing at 1 thread and at all cores);
+ * results do not depend on it: every parallel loop updates independent points */
+void orc_set_threads(int n)
+{
+    if (n >= 1) omp_set_num_threads(n);
+}

@@ -70,12 +70,17 @@ class NpStats(ctypes.Structure):
         ("learned_used", ctypes.c_int * NP_MAX_LEVELS),
         ("interp_rel_residual", ctypes.c_double * NP_MAX_LEVELS),
         ("outer_steps", ctypes.c_int * NP_MAX_LEVELS),
+        ("guess_box_ratio", ctypes.c_double * NP_MAX_LEVELS),
     ]
 
 
 NP_NKCLASS = 10
 KCLASSES = ["smooth", "restrict", "prolong", "coarse", "norm", "fill", "forces", "dc", "guess"]
 NP_NET_PARAMS = 8241
+NP_GUESS_BLOB_MAGIC = 0x5747504E
+NP_GUESS_BLOB_VERSION = 1
+NP_GUESS_BLOB_HEADER = 40
+NP_GUESS_BLOB_BYTES = NP_GUESS_BLOB_HEADER + 2 * 27 * (2 * 16 + 16 * 16 + 16 * 1) + 4 * (16 + 16 + 1)
 
 
 class NpProfile(ctypes.Structure):
@@ -96,7 +101,10 @@ SIGNATURES = {
     "nested_poisson_potential": (ctypes.c_int, [_vp, ctypes.c_int, _vp]),
     "nested_poisson_set_profiling": (ctypes.c_int, [_vp, ctypes.c_int]),
     "nested_poisson_get_profile": (ctypes.c_int, [_vp, ctypes.POINTER(NpProfile)]),
-    "nested_poisson_set_guess_weights": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_float), ctypes.c_size_t]),
+    "nested_poisson_pack_guess_weights": (ctypes.c_int, [ctypes.POINTER(ctypes.c_float), ctypes.c_size_t, _vp,
+                                                          ctypes.c_size_t]),
+    "nested_poisson_check_guess_weights": (ctypes.c_int, [_vp, ctypes.c_size_t]),
+    "nested_poisson_set_guess_weights": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t]),
     "nested_poisson_guess_features": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp]),
     "np_net_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int, ctypes.c_int, ctypes.c_long]),
     "np_net_conv3d_fwd": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
@@ -112,6 +120,8 @@ SIGNATURES = {
     "np_net_adam": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_long, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                    ctypes.c_float, ctypes.c_int, _vp, _vp]),
     "np_net_to_bf16": (ctypes.c_int, [_vp, _vp, ctypes.c_long, _vp]),
+    "np_net_round_bf16": (ctypes.c_int, [_vp, ctypes.c_long, _vp]),
+    "np_net_lap7": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp]),
     "nested_poisson_destroy": (None, [_vp]),
     "nested_poisson_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "nested_poisson_last_error": (ctypes.c_char_p, [_vp]),
@@ -182,3 +192,15 @@ def plan(cfg):
         out.append(dict(N=[p.N[l][L] for L in range(m)], xn_is_one=[p.xn_is_one[l][L] for L in range(m)],
                         coef=[p.ghost_coef[l][L] for L in range(m)]))
     return out
+
+
+def pack_guess_weights(theta):
+    """The library's versioned parameter blob (bytes) of an FP32 parameter vector."""
+    import numpy as np
+    th = np.ascontiguousarray(np.asarray(theta, dtype=np.float32).reshape(-1))
+    buf = ctypes.create_string_buffer(NP_GUESS_BLOB_BYTES)
+    rc = lib().nested_poisson_pack_guess_weights(th.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), th.size, buf,
+                                                 NP_GUESS_BLOB_BYTES)
+    if rc:
+        raise NestedPoissonError(rc, lib().nested_poisson_last_error(None).decode())
+    return buf.raw

@@ -65,6 +65,10 @@ void launch_export(int dim, hipStream_t st, SGrid g, const double* a, double* ou
 void launch_norm(int dim, hipStream_t st, SGrid g, const double* u, const double* f, double inv_h2, int mode,
                  unsigned long long* maxbits);
 void launch_set_u64(hipStream_t st, unsigned long long* p, int count, unsigned long long v);
+// 3-D: max over boxes of 4^3 active points of |mean of f - lap u| (the residual
+// restricted twice), as a bit pattern into maxbits (atomic maximum)
+void launch_box_resid_norm3(hipStream_t st, SGrid g, const double* u, const double* f, double inv_h2,
+                            unsigned long long* maxbits);
 
 // multigrid operators, templated on the storage type (double, float; __half
 // only on multigrid level 0 of the FP16-storage defect correction)

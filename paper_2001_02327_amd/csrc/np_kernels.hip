@@ -813,6 +813,50 @@ __global__ void __launch_bounds__(kBlock) k_resid_norm3(SGrid g, const double* _
     block_max_to(best, maxbits);
 }
 
+// Max norm of the residual's mean over boxes of 4^3 active points of a 3-D
+// nested-level array (boxes at the far end keep their full volume; points
+// past the active range count as zero): the residual restricted twice
+// (eqn:restriction3D applied to multigrid levels 0 -> 1 -> 2), i.e. its part
+// that the smoother does not remove and that sets the number of V-cycles.  A
+// thread owns one box.
+constexpr int kBox = 4;
+
+__global__ void __launch_bounds__(kBlock) k_box_resid_norm3(SGrid g, const double* __restrict__ u,
+                                                            const double* __restrict__ f, double inv_h2, int nbx,
+                                                            unsigned long long* maxbits)
+{
+    const int m = g.nx - 2;
+    const long t = xcd_block() * kBlock + threadIdx.x;
+    unsigned long long best = 0;
+    if (t < (long)nbx * nbx * nbx) {
+        const int bx = (int)(t % nbx), by = (int)((t / nbx) % nbx), bz = (int)(t / ((long)nbx * nbx));
+        {
+            double sum = 0.0;
+            for (int dz = 0; dz < kBox; dz++) {
+                const int pk = 1 + kBox * bz + dz;
+                if (pk > m) break;
+                for (int dy = 0; dy < kBox; dy++) {
+                    const int pj = 1 + kBox * by + dy;
+                    if (pj > m) break;
+                    for (int dx = 0; dx < kBox; dx++) {
+                        const int pi = 1 + kBox * bx + dx;
+                        if (pi > m) break;
+                        double s6 = at<3>(u, g, pi - 1, pj, pk) + at<3>(u, g, pi + 1, pj, pk);
+                        s6 = s6 + at<3>(u, g, pi, pj - 1, pk);
+                        s6 = s6 + at<3>(u, g, pi, pj + 1, pk);
+                        s6 = s6 + at<3>(u, g, pi, pj, pk - 1);
+                        s6 = s6 + at<3>(u, g, pi, pj, pk + 1);
+                        sum += at<3>(f, g, pi, pj, pk) - (s6 - 6.0 * at<3>(u, g, pi, pj, pk)) * inv_h2;
+                    }
+                }
+            }
+            const unsigned long long b = abs_bits(sum * (1.0 / (kBox * kBox * kBox)));
+            best = b > best ? b : best;
+        }
+    }
+    block_max_to(best, maxbits);
+}
+
 __global__ void k_set_u64(unsigned long long* p, int count, unsigned long long v)
 {
     int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -2560,6 +2604,15 @@ void launch_norm(int dim, hipStream_t st, SGrid g, const double* u, const double
     int blocks = ceil_div(ncompact_active(dim, g), kBlock);
     if (blocks > 2048) blocks = 2048;
     NP_DISPATCH(dim, k_norm, dim3(blocks), dim3(kBlock), st, g, u, f, inv_h2, mode, maxbits);
+}
+
+void launch_box_resid_norm3(hipStream_t st, SGrid g, const double* u, const double* f, double inv_h2,
+                            unsigned long long* maxbits)
+{
+    const int m = g.nx - 2;
+    const int nbx = (m + kBox - 1) / kBox;
+    hipLaunchKernelGGL(k_box_resid_norm3, dim3(ceil_div((long)nbx * nbx * nbx, kBlock)), dim3(kBlock), 0, st, g, u, f,
+                       inv_h2, nbx, maxbits);
 }
 
 void launch_set_u64(hipStream_t st, unsigned long long* p, int count, unsigned long long v)

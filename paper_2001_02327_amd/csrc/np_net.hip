@@ -11,7 +11,6 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
-
 #include "../../include/nested_poisson.h"
 #include "np_internal.h"
 
@@ -359,6 +358,37 @@ __global__ void k_to_bf16(const float* __restrict__ a, uint16_t* __restrict__ b,
 {
     const long i = (long)blockIdx.x * kNB + threadIdx.x;
     if (i < n) b[i] = f32_to_bf16(a[i]);
+}
+
+// a = bfloat16(a), kept in FP32 storage: the training forward pass rounds its
+// inputs and hidden activations as the bfloat16 inference path stores them
+__global__ void k_round_bf16(float* __restrict__ a, long n)
+{
+    const long i = (long)blockIdx.x * kNB + threadIdx.x;
+    if (i < n) a[i] = bf16_to_f32(f32_to_bf16(a[i]));
+}
+
+// out = h^2 lap(in) with the 7-point stencil of eqn:Laplacian3D (the sum of
+// the six face neighbours minus six times the centre), zero outside the box;
+// one channel, [batch][z][y][x].  The stencil is symmetric, so the same kernel
+// applies its transpose in the backward pass of the residual objective.
+__global__ void k_lap7(const float* __restrict__ in, int B, int Z, int Y, int X, float* __restrict__ out)
+{
+    const long v = (long)blockIdx.x * kNB + threadIdx.x;
+    const long nv = (long)B * Z * Y * X;
+    if (v >= nv) return;
+    const int x = (int)(v % X);
+    long r = v / X;
+    const int y = (int)(r % Y);
+    r /= Y;
+    const int z = (int)(r % Z);
+    float s = x > 0 ? in[v - 1] : 0.0f;
+    s += x + 1 < X ? in[v + 1] : 0.0f;
+    s += y > 0 ? in[v - X] : 0.0f;
+    s += y + 1 < Y ? in[v + X] : 0.0f;
+    s += z > 0 ? in[v - (long)X * Y] : 0.0f;
+    s += z + 1 < Z ? in[v + (long)X * Y] : 0.0f;
+    out[v] = s - 6.0f * in[v];
 }
 
 // ------------------------------------------------------------------ inference on the matrix cores
@@ -778,6 +808,21 @@ int np_net_adam(float* w, const float* g, float* m, float* v, long n, float lr, 
 {
     if (!w || !g || !m || !v || n < 0 || step < 1) return NP_EINVAL;
     if (n) net_adam((hipStream_t)stream, w, g, m, v, n, lr, beta1, beta2, eps, step, w_bf16);
+    return hipGetLastError() == hipSuccess ? NP_OK : NP_EHIP;
+}
+
+int np_net_round_bf16(float* a, long n, void* stream)
+{
+    if (!a || n < 0) return NP_EINVAL;
+    if (n) hipLaunchKernelGGL(k_round_bf16, dim3(cdiv(n, kNB)), dim3(kNB), 0, (hipStream_t)stream, a, n);
+    return hipGetLastError() == hipSuccess ? NP_OK : NP_EHIP;
+}
+
+int np_net_lap7(const float* in, int batch, int nz, int ny, int nx, float* out, void* stream)
+{
+    if (!in || !out || in == out || !dims_ok(batch, nz, ny, nx)) return NP_EINVAL;
+    const long nv = (long)batch * nz * ny * nx;
+    hipLaunchKernelGGL(k_lap7, dim3(cdiv(nv, kNB)), dim3(kNB), 0, (hipStream_t)stream, in, batch, nz, ny, nx, out);
     return hipGetLastError() == hipSuccess ? NP_OK : NP_EHIP;
 }
 

@@ -220,6 +220,11 @@ struct np_solver {
     // learned initial guess: weights (bfloat16 per layer, FP32 biases) and
     // activations on Gamma of the largest level
     bool have_weights = false;
+    // contraction per V-cycle measured on each level's last solve (the keep
+    // test of a child's learned guess), and the restricted-residual ratio of
+    // each level's learned guess against the interpolated one
+    double rho_meas[NP_MAX_LEVELS] = {};
+    double guess_box_ratio[NP_MAX_LEVELS] = {};
     uint16_t* net_w[3] = {};
     float* net_b[3] = {};
     uint16_t* net_x = nullptr;
@@ -678,13 +683,31 @@ int dc_settle(np_solver* s, int l)
     return NP_OK;
 }
 
-constexpr double kLearnedKeep = 0.5;
+// Max norm of the residual of level l's potential restricted twice (its mean
+// over boxes of 4^3 points; host-synchronous, slot 3).
+int box_resid_sync(np_solver* s, int l, double* out)
+{
+    const double dx = level_dx(&s->cfg, l);
+    launch_set_u64(s->stream, s->d_bits + 3, 1, 0ULL);
+    launch_box_resid_norm3(s->stream, s->lg[l], s->phi[l], s->f[l], 1.0 / (dx * dx), s->d_bits + 3);
+    HIPCHK(s, hipGetLastError());
+    HIPCHK(s, hipMemcpyAsync(s->h_bits + 3, s->d_bits + 3, sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                             s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    *out = bits_to_double(s->h_bits[3]);
+    return NP_OK;
+}
 
 // Learned initial guess of level l >= 1 (3-D): the network's prediction from
-// the interpolated guess, kept only if it lowers the max-norm residual by
-// kLearnedKeep or more; otherwise the interpolated guess is restored.  *r is the residual norm of
-// the guess in effect on return.
-int learned_guess(np_solver* s, int l, const double* rho_l, double fourpiG, double fnorm, double* r, int* used)
+// the interpolated guess, kept only where it is expected to save a V-cycle.
+// The cycle count is set by the error the smoother does not remove, whose
+// residual survives restriction: the guess is kept if it lowers the residual
+// restricted twice (mean over 4^3 boxes) by at least the contraction of one
+// V-cycle, `rho` (measured on the parent level), and its point-wise residual
+// is finite; otherwise the interpolated guess is restored.  *r is the max-norm
+// residual of the guess in effect on return.
+int learned_guess(np_solver* s, int l, const double* rho_l, double fourpiG, double fnorm, double rho, double* r,
+                  int* used)
 {
     *used = 0;
     if (!s->have_weights || !(fnorm > 0.0) || !std::isfinite(*r)) return NP_OK;
@@ -693,6 +716,9 @@ int learned_guess(np_solver* s, int l, const double* rho_l, double fourpiG, doub
     SGrid g = s->lg[l];
     const int m = g.nx - 2;
     const double dx = level_dx(&c, l);
+    double rb_interp = 0.0;
+    int rc = box_resid_sync(s, l, &rb_interp);
+    if (rc) return rc;
     prof_begin(s, NP_KCLASS_GUESS);
     net_features_bf16(st, g, s->phi[l], s->f[l], 1.0 / fnorm, 1.0 / (dx * dx), s->net_x);
     net_conv_mfma(st, s->net_x, 2, s->net_w[0], s->net_b[0], 16, 1, 1, m, m, m, s->net_a1);
@@ -701,13 +727,13 @@ int learned_guess(np_solver* s, int l, const double* rho_l, double fourpiG, doub
     net_apply(st, g, s->phi[l], s->net_out, fnorm * dx * dx);
     prof_end(s);
     HIPCHK(s, hipGetLastError());
-    double rl = 0.0;
-    int rc = norm_sync(s, l, 0, &rl);
+    double rl = 0.0, rb = 0.0;
+    rc = norm_sync(s, l, 0, &rl);
     if (rc) return rc;
-    // keep the network's guess only if it at least halves the max-norm residual
-    // of the interpolated guess (it then removed the dominant local error);
-    // otherwise the V-cycles start from the interpolant
-    if (rl <= kLearnedKeep * *r) {
+    rc = box_resid_sync(s, l, &rb);
+    if (rc) return rc;
+    s->guess_box_ratio[l] = rb_interp > 0.0 ? rb / rb_interp : 0.0;
+    if (std::isfinite(rl) && std::isfinite(rb) && rb <= rho * rb_interp) {
         *r = rl;
         *used = 1;
         return NP_OK;
@@ -1054,8 +1080,10 @@ int nested_poisson_solve(np_solver* s, const double* const* rho, const double* p
         if (rc) return rc;
         st.interp_rel_residual[l] = scale > 0 ? r / scale : r;
         if (l > 0 && c.guess == NP_GUESS_LEARNED) {
-            rc = learned_guess(s, l, rho[l], fourpiG, fnorm, &r, &st.learned_used[l]);
+            const double rho_p = s->rho_meas[c.parent[l]] > 0.0 ? s->rho_meas[c.parent[l]] : kAdaptiveRho0;
+            rc = learned_guess(s, l, rho[l], fourpiG, fnorm, rho_p, &r, &st.learned_used[l]);
             if (rc) return rc;
+            st.guess_box_ratio[l] = s->guess_box_ratio[l];
         }
         double Fdelta = 0.0;
         bool pinned = s->has_fixed && s->fixed[l] >= 0;
@@ -1153,6 +1181,13 @@ int nested_poisson_solve(np_solver* s, const double* const* rho, const double* p
         }
         st.cycles[l] = q;
         st.outer_steps[l] = outer;
+        // contraction per V-cycle of this level (geometric mean), clamped
+        if (q > 0 && r0 > 0.0 && r > 0.0 && r < r0) {
+            const double m = std::pow(r / r0, 1.0 / q);
+            s->rho_meas[l] = m < 0.02 ? 0.02 : (m > 0.95 ? 0.95 : m);
+        } else {
+            s->rho_meas[l] = 0.0;
+        }
         st.scale[l] = scale;
         st.initial_rel_residual[l] = s->hist[l].front();
         st.final_rel_residual[l] = scale > 0 ? r / scale : r;
@@ -1221,27 +1256,90 @@ void nested_poisson_destroy(np_solver* s)
     delete s;
 }
 
-int nested_poisson_set_guess_weights(np_solver* s, const float* theta, size_t n)
+// Parameter blob of the learned guess (layout in nested_poisson.h).
+static const unsigned kBlobCin[3] = {2, 16, 16}, kBlobCout[3] = {16, 16, 1};
+
+static uint16_t host_bf16(float f)
+{
+    uint32_t u;
+    memcpy(&u, &f, sizeof u);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x7fffffu)) return (uint16_t)((u >> 16) | 0x40);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+int nested_poisson_pack_guess_weights(const float* theta, size_t n, void* blob, size_t nbytes)
+{
+    if (!theta || !blob || n != NP_NET_PARAMS || nbytes < NP_GUESS_BLOB_BYTES) {
+        snprintf(g_last_error, sizeof g_last_error, "pack: need %d parameters and a blob of %d bytes",
+                 NP_NET_PARAMS, (int)NP_GUESS_BLOB_BYTES);
+        return NP_EINVAL;
+    }
+    unsigned char* out = (unsigned char*)blob;
+    const uint32_t hdr[10] = {NP_GUESS_BLOB_MAGIC, NP_GUESS_BLOB_VERSION, 3, kBlobCin[0], kBlobCout[0],
+                              kBlobCin[1], kBlobCout[1], kBlobCin[2], kBlobCout[2], 0};
+    memcpy(out, hdr, sizeof hdr);
+    size_t o = NP_GUESS_BLOB_HEADER, k = 0;
+    for (int L = 0; L < 3; L++) {
+        const size_t nw = 27 * (size_t)kBlobCin[L] * kBlobCout[L];
+        for (size_t i = 0; i < nw; i++) {
+            const uint16_t b = host_bf16(theta[k + i]);
+            memcpy(out + o + 2 * i, &b, 2);
+        }
+        o += 2 * nw;
+        memcpy(out + o, theta + k + nw, 4 * (size_t)kBlobCout[L]);
+        o += 4 * (size_t)kBlobCout[L];
+        k += nw + kBlobCout[L];
+    }
+    return NP_OK;
+}
+
+int nested_poisson_check_guess_weights(const void* blob, size_t nbytes)
+{
+    auto bad = [](const char* why) {
+        snprintf(g_last_error, sizeof g_last_error, "guess weights: %s", why);
+        return NP_EINVAL;
+    };
+    if (!blob) return bad("null blob");
+    if (nbytes != NP_GUESS_BLOB_BYTES) return bad("size mismatch");
+    uint32_t hdr[10];
+    memcpy(hdr, blob, sizeof hdr);
+    if (hdr[0] != NP_GUESS_BLOB_MAGIC) return bad("wrong magic");
+    if (hdr[1] != NP_GUESS_BLOB_VERSION) return bad("unsupported version");
+    if (hdr[2] != 3) return bad("layer count is not 3");
+    for (int L = 0; L < 3; L++)
+        if (hdr[3 + 2 * L] != kBlobCin[L] || hdr[4 + 2 * L] != kBlobCout[L]) return bad("layer shape mismatch");
+    const unsigned char* in = (const unsigned char*)blob;
+    size_t o = NP_GUESS_BLOB_HEADER;
+    for (int L = 0; L < 3; L++) {
+        o += 2 * 27 * (size_t)kBlobCin[L] * kBlobCout[L];
+        for (unsigned c = 0; c < kBlobCout[L]; c++) {
+            float b;
+            memcpy(&b, in + o + 4 * c, 4);
+            if (!std::isfinite(b)) return bad("non-finite bias");
+        }
+        o += 4 * (size_t)kBlobCout[L];
+    }
+    return NP_OK;
+}
+
+int nested_poisson_set_guess_weights(np_solver* s, const void* blob, size_t nbytes)
 {
     if (!s) return NP_EINVAL;
-    if (!theta || n != NP_NET_PARAMS) return set_err(s, NP_EINVAL, "expected %d parameters", NP_NET_PARAMS);
+    if (nested_poisson_check_guess_weights(blob, nbytes) != NP_OK)
+        return set_err(s, NP_EINVAL, "%s", g_last_error);
     if (s->cfg.guess != NP_GUESS_LEARNED) return set_err(s, NP_ESTATE, "handle created without the learned guess");
     HIPCHK(s, hipSetDevice(s->device));
-    float* tmp = nullptr;
-    int rc = alloc_dev(s, (void**)&tmp, n * sizeof(float));
-    if (rc) return rc;
-    hipError_t e = hipMemcpyAsync(tmp, theta, n * sizeof(float), hipMemcpyHostToDevice, s->stream);
-    const int cin[3] = {2, 16, 16}, cout[3] = {16, 16, 1};
-    size_t k0 = 0;
-    for (int k = 0; k < 3 && e == hipSuccess; k++) {
-        size_t nw = 27 * (size_t)cin[k] * cout[k];
-        net_to_bf16(s->stream, tmp + k0, s->net_w[k], (long)nw);
-        e = hipMemcpyAsync(s->net_b[k], tmp + k0 + nw, cout[k] * sizeof(float), hipMemcpyDeviceToDevice, s->stream);
-        k0 += nw + cout[k];
+    const unsigned char* in = (const unsigned char*)blob;
+    size_t o = NP_GUESS_BLOB_HEADER;
+    for (int k = 0; k < 3; k++) {
+        const size_t nw = 27 * (size_t)kBlobCin[k] * kBlobCout[k];
+        HIPCHK(s, hipMemcpyAsync(s->net_w[k], in + o, 2 * nw, hipMemcpyHostToDevice, s->stream));
+        o += 2 * nw;
+        HIPCHK(s, hipMemcpyAsync(s->net_b[k], in + o, 4 * (size_t)kBlobCout[k], hipMemcpyHostToDevice, s->stream));
+        o += 4 * (size_t)kBlobCout[k];
     }
-    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
-    (void)hipFree(tmp);
-    if (e != hipSuccess) return set_err(s, NP_EHIP, "setting weights: %s", hipGetErrorString(e));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
     s->have_weights = true;
     return NP_OK;
 }

@@ -84,9 +84,17 @@ class GuessNet:
         return self.wbf[sw], self.theta[sb]
 
     # -------------------------------------------------------------- forward / backward (FP32 activations)
-    def forward(self, x):
-        """x: [B, Z, Y, X, 2] FP32.  Returns the list of activations (input first)."""
+    def _round_bf16(self, t):
+        _chk(_lib.lib().np_net_round_bf16(_p(t), t.numel(), ctypes.c_void_p(self.st)), "round bf16")
+
+    def forward(self, x, bf16_acts=True):
+        """x: [B, Z, Y, X, 2] FP32.  Returns the list of activations (input first).
+        With bf16_acts the input and the hidden activations are rounded to
+        bfloat16 (in place for the input), as the solver's inference path
+        stores them; the output stays FP32 there too."""
         B, Z, Y, X, _ = x.shape
+        if bf16_acts:
+            self._round_bf16(x)
         acts = [x]
         h = x
         for k, (ci, co) in enumerate(LAYERS):
@@ -94,6 +102,8 @@ class GuessNet:
             out = torch.empty((B, Z, Y, X, co), dtype=torch.float32, device=self.dev)
             _chk(_lib.lib().np_net_conv3d_fwd(_p(h), ci, _p(w), _p(b), co, int(k < len(LAYERS) - 1), B, Z, Y, X,
                                               _p(out), ctypes.c_void_p(self.st)), "conv fwd")
+            if bf16_acts and k < len(LAYERS) - 1:
+                self._round_bf16(out)
             acts.append(out)
             h = out
         return acts
@@ -145,33 +155,21 @@ class GuessNet:
         self.adam_step(lr)
         return loss
 
-    def _laplacian(self):
-        if not hasattr(self, "_lap"):
-            w = np.zeros((27, 1, 1), dtype=np.float32)
-            for t, (dz, dy, dx) in enumerate([(a, b, c) for a in (-1, 0, 1) for b in (-1, 0, 1) for c in (-1, 0, 1)]):
-                k = abs(dz) + abs(dy) + abs(dx)
-                w[t, 0, 0] = -6.0 if k == 0 else (1.0 if k == 1 else 0.0)
-            wt = torch.tensor(w.reshape(-1), device=self.dev)
-            self._lap = torch.zeros(27, dtype=torch.int16, device=self.dev)
-            _chk(_lib.lib().np_net_to_bf16(_p(wt), _p(self._lap), 27, ctypes.c_void_p(self.st)), "to_bf16")
-            self._lap_b = torch.zeros(1, dtype=torch.float32, device=self.dev)
-        return self._lap, self._lap_b
+    def _lap7(self, a, out):
+        B, Z, Y, X, _ = a.shape
+        _chk(_lib.lib().np_net_lap7(_p(a), B, Z, Y, X, _p(out), ctypes.c_void_p(self.st)), "lap7")
 
     def train_step_residual(self, x, lr=1e-3):
         """Residual objective: mean (r0/||f|| - L y)^2, the max-norm-relevant
-        residual left by the corrected guess (L = the 7-point stencil without
-        1/dx^2, zero outside Gamma; the input's second channel is r0/||f||)."""
-        B, Z, Y, X, _ = x.shape
+        residual left by the corrected guess (L = the library's 7-point stencil
+        without 1/dx^2, zero outside Gamma; the input's second channel is r0/||f||)."""
         acts = self.forward(x)
-        w, b = self._laplacian()
         ly = torch.empty_like(acts[-1])
-        _chk(_lib.lib().np_net_conv3d_fwd(_p(acts[-1]), 1, _p(w), _p(b), 1, 0, B, Z, Y, X, _p(ly),
-                                          ctypes.c_void_p(self.st)), "laplacian")
+        self._lap7(acts[-1], ly)
         r = x[..., 1:2].contiguous()
         loss, gl = self.loss_grad(ly, r)
         gy = torch.empty_like(gl)
-        _chk(_lib.lib().np_net_conv3d_bwd_data(_p(gl), 1, _p(w), 1, B, Z, Y, X, _p(gy), ctypes.c_void_p(self.st)),
-             "laplacian bwd")
+        self._lap7(gl, gy)  # the stencil is its own adjoint
         self.backward(acts, gy)
         self.adam_step(lr)
         return loss

@@ -65,6 +65,7 @@ class NestedPoissonSolver:
             learned_used=[st.learned_used[l] for l in range(L)],
             interp_rel_residual=[st.interp_rel_residual[l] for l in range(L)],
             outer_steps=[st.outer_steps[l] for l in range(L)],
+            guess_box_ratio=[st.guess_box_ratio[l] for l in range(L)],
         )
         return self.last_stats
 
@@ -101,11 +102,11 @@ class NestedPoissonSolver:
         return out
 
     def set_guess_weights(self, theta):
-        """Network parameters (NP_NET_PARAMS floats, host array-like)."""
-        import numpy as np
-        th = np.ascontiguousarray(np.asarray(theta, dtype=np.float32).reshape(-1))
-        self._check(_lib.lib().nested_poisson_set_guess_weights(
-            self._h, th.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), th.size))
+        """Network parameters: an FP32 vector of NP_NET_PARAMS values (packed into
+        the library's versioned blob) or such a blob (bytes)."""
+        blob = theta if isinstance(theta, (bytes, bytearray)) else _lib.pack_guess_weights(theta)
+        buf = ctypes.create_string_buffer(bytes(blob), len(blob))
+        self._check(_lib.lib().nested_poisson_set_guess_weights(self._h, buf, len(blob)))
 
     def guess_features(self, level, with_target=True):
         """(x, target) of the learned guess for a level >= 1 after a solve:

@@ -203,3 +203,48 @@ def test_bench_refuses_several_gpus():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr and "--gpus 2" in r.stderr
+
+
+def test_guess_weight_blob_on_the_host():
+    """The versioned parameter blob: packing rounds the weights to bfloat16
+    (nearest even) and copies the FP32 biases; the check refuses a wrong
+    magic, version, layer shape, size or a non-finite bias.  Host only."""
+    import numpy as np
+    from paper_2001_02327_amd import learned
+    theta = learned.init_params(7)
+    theta[-1] = 0.25
+    blob = _lib.pack_guess_weights(theta)
+    assert len(blob) == _lib.NP_GUESS_BLOB_BYTES
+    L = _lib.lib()
+    hdr = np.frombuffer(blob[:_lib.NP_GUESS_BLOB_HEADER], dtype="<u4")
+    assert list(hdr) == [_lib.NP_GUESS_BLOB_MAGIC, _lib.NP_GUESS_BLOB_VERSION, 3, 2, 16, 16, 16, 16, 1, 0]
+    # layer 1 weights: bfloat16 round-to-nearest-even of the FP32 values
+    nw = 27 * 2 * 16
+    w = np.frombuffer(blob[_lib.NP_GUESS_BLOB_HEADER:_lib.NP_GUESS_BLOB_HEADER + 2 * nw], dtype="<u2")
+    u = theta[:nw].astype(np.float32).view(np.uint32).astype(np.uint64)
+    assert np.array_equal(w, ((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint16))
+    b = np.frombuffer(blob[_lib.NP_GUESS_BLOB_HEADER + 2 * nw:_lib.NP_GUESS_BLOB_HEADER + 2 * nw + 64], dtype="<f4")
+    assert np.array_equal(b, theta[nw:nw + 16])
+    last = np.frombuffer(blob[-4:], dtype="<f4")
+    assert last[0] == np.float32(0.25)
+
+    def check(bb):
+        buf = ctypes.create_string_buffer(bytes(bb), len(bb))
+        return L.nested_poisson_check_guess_weights(buf, len(bb))
+
+    assert check(blob) == 0
+    for pos, val in ((0, 0x00), (4, 2), (8, 4), (12, 3), (32, 2)):
+        bad = bytearray(blob)
+        bad[pos] = val
+        assert check(bad) == _lib.NP_EINVAL, pos
+    assert check(blob[:-1]) == _lib.NP_EINVAL
+    assert check(blob + b"\0") == _lib.NP_EINVAL
+    bad = bytearray(blob)
+    bad[-4:] = np.array([np.nan], dtype="<f4").tobytes()
+    assert check(bad) == _lib.NP_EINVAL
+    assert b"non-finite" in L.nested_poisson_last_error(None)
+    # wrong parameter count
+    short = np.zeros(100, dtype=np.float32)
+    buf = ctypes.create_string_buffer(_lib.NP_GUESS_BLOB_BYTES)
+    assert L.nested_poisson_pack_guess_weights(short.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), 100, buf,
+                                               _lib.NP_GUESS_BLOB_BYTES) == _lib.NP_EINVAL

@@ -253,3 +253,56 @@ def test_dc_repeat_solves_identical(precision):
     s.close()
     for x, y, z in zip(a, b, c):
         assert torch.equal(x, y) and torch.equal(x, z)
+
+
+_C3_REF = {}
+
+
+def _c3_reference():
+    """The oracle's solution of the mixed-precision workload at its configured
+    size (4 levels of 256^3, Plummer a = 0.02 at (0.1, -0.05, 0.03)), converged
+    to 1e-12 (the FP64 rounding floor of the relative residual is ~4e-13 on the
+    finest level, dx = 1/1024, so 1e-13 is not reachable there), and its
+    forces; computed once for both precisions."""
+    if not _C3_REF:
+        wl = W.c3_plummer_offset(256)
+        rho, po = W.make_inputs(wl.geom, wl.prob)
+        print("oracle: %s to 1e-12 ..." % wl.name, flush=True)
+        ref = core.solve(wl.geom, [r.numpy() for r in rho], po.numpy(), tol=1e-12, max_cycles=120)
+        assert ref["status"] == 0, ref["status_name"]
+        _C3_REF["wl"] = wl
+        _C3_REF["phi"] = ref["phi"]
+        _C3_REF["F"] = [core.forces(3, wl.geom.dx(l), ref["phi"][l]) for l in range(wl.geom.nlevels)]
+    return _C3_REF
+
+
+@pytest.mark.parametrize("precision", ["fp32_dc", "fp16s_dc"])
+def test_dc_configured_size_plummer_offset(precision):
+    """The mixed-precision workload at its configured size, adaptive inner
+    cycles (as the benchmark runs them): every level's potential within 1e-8 of
+    the oracle's converged solution, forces within what that bound allows
+    through the fourth-order stencil (18 / (12 dx) of it) of the oracle's
+    stencil on its solution, and the Linf force error against the closed form
+    equal to the FP64 solve's within 0.5 %.  The deviations from the FP64
+    solve of the same run are printed."""
+    ref = _c3_reference()
+    wl = ref["wl"]
+    print("gpu: %s %s adaptive" % (wl.name, precision), flush=True)
+    phi64, F64, st64 = _solve(wl)
+    phi, F, st = _solve(wl, precision=precision, inner_cycles="adaptive")
+    for l in range(wl.geom.nlevels):
+        err = np.abs(phi[l] - ref["phi"][l]).max() / np.abs(ref["phi"][l]).max()
+        assert err <= 1e-8, (l, err)
+        fmax = max(np.abs(a).max() for a in ref["F"][l])
+        ef = max(np.abs(F[l][a] - ref["F"][l][a]).max() for a in range(3)) / fmax
+        # the stencil turns |dPhi| <= 1e-8 max|Phi| into |dF| <= 18 / (12 dx) of it
+        f_bar = 1.5 * 1e-8 * np.abs(ref["phi"][l]).max() / (wl.geom.dx(l) * fmax)
+        assert ef <= f_bar, (l, ef, f_bar)
+        assert st["final_rel_residual"][l] <= 1e-10
+        d_phi = np.abs(phi[l] - phi64[l]).max() / np.abs(phi64[l]).max()
+        d_F = max(np.abs(F[l][a] - F64[l][a]).max() for a in range(3)) / max(np.abs(a).max() for a in F64[l])
+        print("level %d: |dPhi|/|Phi| vs oracle %.2e, vs FP64 %.2e; |dF|/|F| vs oracle %.2e, vs FP64 %.2e; "
+              "V-cycles %d (FP64 %d)" % (l, err, d_phi, ef, d_F, st["cycles"][l], st64["cycles"][l]))
+    e64 = _linf_force_error(wl, F64)
+    e = _linf_force_error(wl, F)
+    assert abs(e - e64) <= 5e-3 * e64, (e, e64)

@@ -122,7 +122,7 @@ def test_training_step_matches_reference():
     net = learned.GuessNet(theta)
     x = rng.standard_normal((1, 6, 5, 7, 2)).astype(np.float32)
     t = rng.standard_normal((1, 6, 5, 7, 1)).astype(np.float32)
-    acts = net.forward(_dev(x))
+    acts = net.forward(_dev(x), bf16_acts=False)
     loss, gy = net.loss_grad(acts[-1], _dev(t))
     net.backward(acts, gy)
     parts = list(_split(theta))
@@ -137,6 +137,92 @@ def test_training_step_matches_reference():
     net.adam_step(lr=1e-2)
     rth, _, _ = onet.adam(before, g.astype(np.float64), np.zeros_like(before), np.zeros_like(before), 1, lr=1e-2)
     assert np.abs(net.theta.cpu().numpy() - rth).max() <= 1e-6
+
+
+def test_training_forward_rounds_like_inference():
+    """With bfloat16 activations (the default of the training forward pass) the
+    FP32 kernels see the values the matrix-core inference path stores: inputs
+    and hidden activations rounded to bfloat16.  Given the committed weights
+    (or a seeded initialisation) the two paths then differ only by the FP32
+    summation order and the rare bfloat16 rounding it flips."""
+    theta = learned.load_weights() if os.path.exists(learned.DEFAULT_WEIGHTS) else learned.init_params(4)
+    net = learned.GuessNet(theta)
+    rng = np.random.default_rng(11)
+    B, Z, Y, X = 1, 9, 10, 37
+    x = rng.standard_normal((B, Z, Y, X, 2)).astype(np.float32)
+    xd = _dev(x)
+    acts = net.forward(xd)  # rounds xd in place
+    y_train = acts[-1].cpu().numpy().astype(np.float64)
+    # the inference path: bfloat16 input, three matrix-core layers
+    L = _lib.lib()
+    xb = _dev(_bf16_bits(x), torch.int16)
+    a1 = torch.empty((B, Z, Y, X, 16), dtype=torch.int16, device="cuda")
+    a2 = torch.empty_like(a1)
+    y = torch.empty((B, Z, Y, X, 1), dtype=torch.float32, device="cuda")
+    h = xb
+    for k, (ci, co) in enumerate(learned.LAYERS):
+        w, b = net._w(k)
+        out = (a1, a2, y)[k]
+        assert L.np_net_conv3d_fwd_mfma(h.data_ptr(), ci, w.data_ptr(), b.data_ptr(), co, int(k < 2), B, Z, Y, X,
+                                        out.data_ptr(), _st()) == 0
+        h = out
+    y_inf = y.cpu().numpy().astype(np.float64)
+    # the rounded training input is exactly the inference input
+    assert np.array_equal(_bf16_bits(xd.cpu().numpy()), _bf16_bits(x))
+    scale = np.abs(y_inf).max()
+    diff = np.abs(y_train - y_inf)
+    print("training forward vs inference path: max %.3e, mean %.3e (relative to max |y| %.3e)"
+          % (diff.max() / scale, diff.mean() / scale, scale))
+    assert diff.max() <= 2e-2 * scale
+    assert diff.mean() <= 1e-3 * scale
+
+
+def test_lap7_and_residual_objective():
+    """np_net_lap7 is the 7-point stencil with zero outside the box (checked
+    against shifted copies in FP64) and its own adjoint (<L a, b> = <a, L b>)."""
+    rng = np.random.default_rng(12)
+    B, Z, Y, X = 2, 5, 6, 71
+    a = rng.standard_normal((B, Z, Y, X, 1))
+    b = rng.standard_normal((B, Z, Y, X, 1))
+    L = _lib.lib()
+    ad, bd = _dev(a), _dev(b)
+    la, lb = torch.empty_like(ad), torch.empty_like(bd)
+    assert L.np_net_lap7(ad.data_ptr(), B, Z, Y, X, la.data_ptr(), _st()) == 0
+    assert L.np_net_lap7(bd.data_ptr(), B, Z, Y, X, lb.data_ptr(), _st()) == 0
+    p = np.pad(a[..., 0], ((0, 0), (1, 1), (1, 1), (1, 1)))
+    ref = (p[:, :-2, 1:-1, 1:-1] + p[:, 2:, 1:-1, 1:-1] + p[:, 1:-1, :-2, 1:-1] + p[:, 1:-1, 2:, 1:-1]
+           + p[:, 1:-1, 1:-1, :-2] + p[:, 1:-1, 1:-1, 2:] - 6.0 * a[..., 0])
+    got = la.cpu().numpy()[..., 0].astype(np.float64)
+    assert np.abs(got - ref).max() <= 1e-5 * np.abs(ref).max()
+    lhs = float((la.double() * bd.double()).sum())
+    rhs = float((ad.double() * lb.double()).sum())
+    assert lhs == pytest.approx(rhs, rel=1e-5)
+    assert L.np_net_lap7(ad.data_ptr(), B, Z, Y, X, ad.data_ptr(), _st()) == _lib.NP_EINVAL
+
+
+def test_guess_weights_blob_is_versioned():
+    """set_guess_weights takes the versioned blob only: a wrong magic, version,
+    shape or size is rejected before any device work, and the packed blob of
+    the committed parameters round-trips (the learned solve runs)."""
+    theta = learned.init_params(2)
+    blob = bytearray(_lib.pack_guess_weights(theta))
+    wl = W.c4_multi_plummer(200001, N=16)
+    s = NestedPoissonSolver(wl.geom, guess="learned")
+    bad_version = bytearray(blob)
+    bad_version[4] = 2
+    bad_magic = bytearray(blob)
+    bad_magic[0] ^= 0xFF
+    bad_shape = bytearray(blob)
+    bad_shape[12] = 3
+    for bad in (bad_version, bad_magic, bad_shape, blob[:-4]):
+        with pytest.raises(_lib.NestedPoissonError) as ei:
+            s.set_guess_weights(bytes(bad))
+        assert ei.value.code == _lib.NP_EINVAL
+    s.set_guess_weights(bytes(blob))
+    rho, po = W.make_inputs(wl.geom, wl.prob, device="cuda")
+    st = s.solve(rho, po)
+    assert st["status"] == 0
+    s.close()
 
 
 def _split(theta):
@@ -211,31 +297,38 @@ def test_learned_guess_is_checked_by_multigrid():
 
 
 @pytest.mark.skipif(not os.path.exists(learned.DEFAULT_WEIGHTS), reason="no trained weights in the tree")
-def test_trained_network_gain():
-    """What the trained network buys on held-out seeds (3 levels of 128^3).
-
-    Measured (and recorded in the design notes): the network leaves the
-    initial max-norm residual of the refined levels essentially unchanged and
-    costs 0-2 extra V-cycles where its guess is kept; the cycle count to 1e-10
-    is set by the slowly converging mode of the iteration (contraction ~0.29),
-    which a local correction does not reach.  The test pins that the answer is
-    the plain solve's, that a kept guess never starts from a larger residual,
-    and that the cost stays within two cycles per level (a guess is kept only
-    when it halves the initial residual)."""
+@pytest.mark.parametrize("precision", ["fp64", "fp16s_dc"])
+def test_trained_network_gain(precision):
+    """What the trained network buys on held-out seeds (3 levels of 128^3 of
+    the seeded multi-Plummer workload): the V-cycles and the host time of the
+    refined levels with and without it, printed.  Measured: it buys nothing.
+    Its guess lowers the residual restricted twice to 0.13-0.38 of the
+    interpolated guess's, yet the refined levels need 99 instead of 95
+    V-cycles in FP64: neither the point-wise nor the restricted residual of the
+    starting guess predicts the cycle count.  Pinned: the answer is the plain
+    solve's, a kept guess passed the keep test, and the loss stays within two
+    V-cycles per level."""
     theta = learned.load_weights()
+    kw = dict(precision=precision, inner_cycles="adaptive") if precision != "fp64" else {}
     tot0 = tot1 = kept = 0
+    ms0 = ms1 = 0.0
+    ratios = []
     for seed in (200000, 200002, 200003, 200005):
         wl = W.c4_multi_plummer(seed, N=128)
-        phi0, st0 = _solve(wl)
-        phi1, st1 = _solve(wl, theta, guess="learned")
+        phi0, st0 = _solve(wl, **kw)
+        phi1, st1 = _solve(wl, theta, guess="learned", **kw)
         tot0 += sum(st0["cycles"][1:])
         tot1 += sum(st1["cycles"][1:])
+        ms0 += sum(st0["level_ms"][1:])
+        ms1 += sum(st1["level_ms"][1:])
         kept += sum(st1["learned_used"][1:])
+        ratios += st1["guess_box_ratio"][1:]
+        for l in range(wl.geom.nlevels):
+            assert np.abs(phi1[l] - phi0[l]).max() <= 1e-8 * np.abs(phi0[l]).max()
         for l in range(1, wl.geom.nlevels):
             assert st1["cycles"][l] <= st0["cycles"][l] + 2
             if st1["learned_used"][l]:
-                assert st1["initial_rel_residual"][l] <= 0.5 * st1["interp_rel_residual"][l]
-        for l in range(wl.geom.nlevels):
-            assert np.abs(phi1[l] - phi0[l]).max() <= 1e-8 * np.abs(phi0[l]).max()
-    print("refined-level V-cycles on 4 held-out seeds: interpolated guess %d, learned guess %d "
-          "(kept on %d of 8 levels)" % (tot0, tot1, kept))
+                assert st1["guess_box_ratio"][l] <= 0.95
+    print("%s, refined levels of 4 held-out seeds: V-cycles %d (interpolated guess) vs %d (learned, kept on %d of "
+          "8 levels); host time %.1f vs %.1f ms; restricted-residual ratios %s"
+          % (precision, tot0, tot1, kept, ms0, ms1, ", ".join("%.2f" % x for x in ratios)))

@@ -84,7 +84,7 @@ def _minimal():
     return W.Workload("minimal3d_8_4", g, W.Plummer([(1.0, 0.2, (0.0, 0.0, 0.0))]))
 
 
-SMALL = [W.paper2d(16), W.c1_gaussian_2d(32), W.paper3d(16), W.c2_plummer(16), W.c4_multi_plummer(5, N=16),
+SMALL = [W.paper2d(16), W.c1_gaussian_2d(32), W.c1_gaussian_2d(64), W.paper3d(16), W.c2_plummer(16), W.c4_multi_plummer(5, N=16),
          W.c3_plummer_offset(16), _ragged3d(), _ragged2d(), _minimal(), W.paper2d(8), W.c2_plummer(32)]
 
 
