@@ -293,6 +293,19 @@ int np_net_relu_bwd(const float* act, float* grad, long n, void* stream);
  * (mask may be NULL = all ones). */
 int np_net_mse(const float* pred, const float* target, const float* mask, long n, float count, float* grad,
                float* loss, float* workspace, size_t workspace_bytes, void* stream);
+/* np_net_mse without the workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, serving loops):
+ * the partial sums live in a static device array of the library, so the
+ * call allocates nothing.  n <= NP_NET_MSE_NOALLOC_MAX (2^28 values, 4 MiB
+ * of partials held by each device the library runs on until the process
+ * ends); larger n: NP_EINVAL with a message in nested_poisson_last_error(NULL).
+ * Every call on a device shares that device's array: calls that overlap on
+ * one device (different streams or threads) race and must be serialised by
+ * the caller.  Same results as np_net_mse.  NP_ENODEV / NP_EHIP if the
+ * device's copy of the array cannot be located. */
+#define NP_NET_MSE_NOALLOC_MAX (1L << 28)
+int np_net_mse_noalloc(const float* pred, const float* target, const float* mask, long n, float count, float* grad,
+                       float* loss, void* stream);
 /* Adam with bias correction (step >= 1) on FP32 master weights; refreshes the
  * bfloat16 copy when w_bf16 is not NULL. */
 int np_net_adam(float* w, const float* g, float* m, float* v, long n, float lr, float beta1, float beta2, float eps,

@@ -77,6 +77,7 @@ class NpStats(ctypes.Structure):
 NP_NKCLASS = 10
 KCLASSES = ["smooth", "restrict", "prolong", "coarse", "norm", "fill", "forces", "dc", "guess"]
 NP_NET_PARAMS = 8241
+NP_NET_MSE_NOALLOC_MAX = 1 << 28
 NP_GUESS_BLOB_MAGIC = 0x5747504E
 NP_GUESS_BLOB_VERSION = 1
 NP_GUESS_BLOB_HEADER = 40
@@ -117,6 +118,7 @@ SIGNATURES = {
                                                 ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
     "np_net_relu_bwd": (ctypes.c_int, [_vp, _vp, ctypes.c_long, _vp]),
     "np_net_mse": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_long, ctypes.c_float, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
+    "np_net_mse_noalloc": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_long, ctypes.c_float, _vp, _vp, _vp]),
     "np_net_adam": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_long, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                    ctypes.c_float, ctypes.c_int, _vp, _vp]),
     "np_net_to_bf16": (ctypes.c_int, [_vp, _vp, ctypes.c_long, _vp]),

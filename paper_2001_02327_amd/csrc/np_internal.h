@@ -40,6 +40,9 @@ inline SGrid make_grid(int dim, int nx)
     return g;
 }
 
+// message returned by nested_poisson_last_error(NULL) on the calling thread
+void set_last_error(const char* msg);
+
 // ------------------------------------------------------------------ launches
 // All launches are asynchronous on `st`.  Grids and sizes are checked by the
 // caller (the runtime) before any launch.

@@ -11,6 +11,9 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <cstdio>
+#include <mutex>
+
 #include "../../include/nested_poisson.h"
 #include "np_internal.h"
 
@@ -800,6 +803,59 @@ int np_net_mse(const float* pred, const float* target, const float* mask, long n
     if (!pred || !target || !grad || !loss || !workspace || n < 1 || !(count > 0)) return NP_EINVAL;
     if (workspace_bytes < net_mse_workspace(n)) return NP_EINVAL;
     net_mse((hipStream_t)stream, pred, target, mask, n, count, grad, workspace, loss);
+    return hipGetLastError() == hipSuccess ? NP_OK : NP_EHIP;
+}
+
+// Partial sums of np_net_mse_noalloc: one file-scope device array, never
+// allocated at run time.  Each device holds its own copy at its own address,
+// looked up once per device (hipGetSymbolAddress) and kept in mse_scratch_dev;
+// host code uses only those addresses, never the array's name.
+static __device__ __align__(256) float scratch[NP_NET_MSE_NOALLOC_MAX / 256];
+static float* mse_scratch_dev[64];
+static std::mutex mse_scratch_mu;
+
+static int mse_scratch(float** out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+        (void)hipGetLastError();
+        set_last_error("np_net_mse_noalloc: no current HIP device (or device index >= 64)");
+        return NP_ENODEV;
+    }
+    std::lock_guard<std::mutex> lock(mse_scratch_mu);
+    if (!mse_scratch_dev[dev]) {
+        float* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress((void**)&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            char msg[160];
+            snprintf(msg, sizeof msg, "np_net_mse_noalloc: hipGetSymbolAddress: %s", hipGetErrorString(e));
+            set_last_error(msg);
+            return NP_EHIP;
+        }
+        mse_scratch_dev[dev] = p;
+    }
+    *out = mse_scratch_dev[dev];
+    return NP_OK;
+}
+
+int np_net_mse_noalloc(const float* pred, const float* target, const float* mask, long n, float count, float* grad,
+                       float* loss, void* stream)
+{
+    if (!pred || !target || !grad || !loss || n < 1 || !(count > 0)) return NP_EINVAL;
+    if (n > NP_NET_MSE_NOALLOC_MAX) {
+        char msg[160];
+        snprintf(msg, sizeof msg, "np_net_mse_noalloc: n = %ld exceeds the maximum %ld", n,
+                 (long)NP_NET_MSE_NOALLOC_MAX);
+        set_last_error(msg);
+        return NP_EINVAL;
+    }
+    float* part = nullptr;
+    const int rc = mse_scratch(&part);
+    if (rc) return rc;
+    // every partial k_sum reads (blocks 0 .. ceil(n/256) - 1) is written by k_mse
+    // first, so nothing needs clearing between calls
+    net_mse((hipStream_t)stream, pred, target, mask, n, count, grad, part, loss);
     return hipGetLastError() == hipSuccess ? NP_OK : NP_EHIP;
 }
 

@@ -161,6 +161,10 @@ thread_local char g_last_error[256] = "";
 
 }  // namespace
 
+namespace np {
+void set_last_error(const char* msg) { snprintf(g_last_error, sizeof g_last_error, "%s", msg); }
+}  // namespace np
+
 // ------------------------------------------------------------------ handle
 struct np_solver {
     np_config cfg;
