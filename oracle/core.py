@@ -22,7 +22,7 @@ class OrcConfig(ctypes.Structure):
     _fields_ = [
         ("dim", ctypes.c_int),
         ("nlevels", ctypes.c_int),
-        ("n", ctypes.c_int * MAXLEV),
+        ("n", (ctypes.c_int * 3) * MAXLEV),
         ("off", (ctypes.c_int * 3) * MAXLEV),
         ("dx0", ctypes.c_double),
         ("G", ctypes.c_double),
@@ -64,26 +64,29 @@ def lib():
         if not os.path.exists(path):
             _build.build_native() if _native else _build.build()
         L = ctypes.CDLL(path)
+        _i3 = ctypes.POINTER(ctypes.c_int)
         L.orc_plan.argtypes = [ctypes.c_int, _ip, ctypes.c_int]
         L.orc_plan.restype = ctypes.c_int
+        L.orc_plan3.argtypes = [ctypes.c_int, _i3, _ip, ctypes.c_int]
+        L.orc_plan3.restype = ctypes.c_int
+        L.orc_plan_stable.argtypes = [ctypes.c_int, _i3, _ip, ctypes.c_int]
+        L.orc_plan_stable.restype = ctypes.c_int
         L.orc_ghost_rule.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _ip, _dp]
-        L.orc_ghost_fill.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int]
-        L.orc_rb_sweep.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
-                                   _dp, _dp, ctypes.c_int]
-        L.orc_residual.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp, _dp, _dp]
-        L.orc_residual_norm.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp, _dp]
+        L.orc_ghost_fill.argtypes = [ctypes.c_int, _i3, ctypes.c_int, _i3, _dp, ctypes.c_int]
+        L.orc_rb_sweep.argtypes = [ctypes.c_int, _i3, ctypes.c_int, _i3, ctypes.c_double, _dp, _dp, ctypes.c_int]
+        L.orc_residual.argtypes = [ctypes.c_int, _i3, ctypes.c_double, _dp, _dp, _dp]
+        L.orc_residual_norm.argtypes = [ctypes.c_int, _i3, ctypes.c_double, _dp, _dp]
         L.orc_residual_norm.restype = ctypes.c_double
-        L.orc_restrict.argtypes = [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int, _dp]
-        L.orc_prolong_add.argtypes = [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int, _dp]
-        L.orc_interface_fill.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, ctypes.c_int, _ip, _dp,
-                                         ctypes.c_double, _dp, _dp]
-        L.orc_forces.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp, _dp, _dp, _dp]
+        L.orc_restrict.argtypes = [ctypes.c_int, _i3, _dp, _i3, _dp]
+        L.orc_prolong_add.argtypes = [ctypes.c_int, _i3, _dp, _i3, _dp]
+        L.orc_interface_fill.argtypes = [ctypes.c_int, _i3, _dp, _dp, _i3, _i3, _dp, ctypes.c_double, _dp, _dp]
+        L.orc_forces.argtypes = [ctypes.c_int, _i3, ctypes.c_double, _dp, _dp, _dp, _dp]
         L.orc_validate.argtypes = [ctypes.POINTER(OrcConfig)]
         L.orc_validate.restype = ctypes.c_int
         L.orc_solve.argtypes = [ctypes.POINTER(OrcConfig), ctypes.POINTER(_dp), _dp, ctypes.POINTER(_dp), _ip,
                                 _ip, _dp, _dp]
         L.orc_solve.restype = ctypes.c_int
-        L.orc_vcycle_patch.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp, _dp, ctypes.c_int,
+        L.orc_vcycle_patch.argtypes = [ctypes.c_int, _i3, ctypes.c_double, _dp, _dp, ctypes.c_int,
                                        ctypes.c_int, ctypes.c_int]
         L.orc_vcycle_patch.restype = ctypes.c_int
         L.orc_num_threads.restype = ctypes.c_int
@@ -97,18 +100,50 @@ def _p(a):
     return a.ctypes.data_as(_dp)
 
 
-def _shape(dim, Q):
-    return (Q, Q, Q) if dim == 3 else (Q, Q)
+def _i3(v):
+    """Three ints (x, y, z) for the C side; missing axes are 1."""
+    v = list(v) + [1] * (3 - len(v))
+    return (ctypes.c_int * 3)(*[int(x) for x in v])
+
+
+def _act(dim, a, pad):
+    """Active points per axis (x, y[, z]) of an array [k, j, i] with `pad` ghost layers."""
+    return tuple(a.shape[dim - 1 - ax] - 2 * pad for ax in range(dim))
+
+
+def _ax(dim, v):
+    """An int (the same on every axis) or a per-axis sequence, as a tuple."""
+    return tuple(v) if isinstance(v, (tuple, list)) else (int(v),) * dim
 
 
 # ---------------------------------------------------------------- operators
 def plan(N0):
-    """Active cells per axis of every multigrid level (Sec. 2.2)."""
+    """Active cells per axis of every multigrid level of a cube (Sec. 2.2)."""
     buf = (ctypes.c_int * MAXMG)()
     m = lib().orc_plan(int(N0), buf, MAXMG)
     if m < 1:
         raise ValueError("bad N0")
     return [buf[i] for i in range(m)]
+
+
+def plan3(dim, N0):
+    """Per-axis hierarchy of a box with N0 = (x, y[, z]) cells: one tuple per
+    multigrid level, ending on the first level with one cell along some axis."""
+    buf = (ctypes.c_int * (3 * MAXMG))()
+    m = lib().orc_plan3(dim, _i3(N0), buf, MAXMG)
+    if m < 1:
+        raise ValueError("bad N0")
+    return [tuple(buf[3 * L + a] for a in range(dim)) for L in range(m)]
+
+
+def plan_stable(dim, N0):
+    """False when some level's right-ghost gain |c_L| / (2d) exceeds the
+    bound the oracle accepts (such hierarchies are refused)."""
+    buf = (ctypes.c_int * (3 * MAXMG))()
+    m = lib().orc_plan3(dim, _i3(N0), buf, MAXMG)
+    if m < 1:
+        raise ValueError("bad N0")
+    return bool(lib().orc_plan_stable(dim, _i3(N0), buf, m))
 
 
 def ghost_rule(N0, L, N, literal=False):
@@ -119,51 +154,53 @@ def ghost_rule(N0, L, N, literal=False):
 
 
 def ghost_fill(dim, N0, L, e, literal=False):
-    N = e.shape[0] - 2
-    lib().orc_ghost_fill(dim, N0, L, N, _p(e), int(literal))
+    lib().orc_ghost_fill(dim, _i3(_ax(dim, N0)), L, _i3(_act(dim, e, 1)), _p(e), int(literal))
 
 
 def rb_sweep(dim, N0, L, h, u, f, literal=False):
-    N = u.shape[0] - 2
-    lib().orc_rb_sweep(dim, N0, L, N, h, _p(u), _p(f), int(literal))
+    lib().orc_rb_sweep(dim, _i3(_ax(dim, N0)), L, _i3(_act(dim, u, 1)), h, _p(u), _p(f), int(literal))
 
 
 def residual(dim, h, u, f):
     r = np.zeros_like(u)
-    lib().orc_residual(dim, u.shape[0] - 2, h, _p(u), _p(f), _p(r))
+    lib().orc_residual(dim, _i3(_act(dim, u, 1)), h, _p(u), _p(f), _p(r))
     return r
 
 
 def residual_norm(dim, h, u, f):
-    return lib().orc_residual_norm(dim, u.shape[0] - 2, h, _p(u), _p(f))
+    return lib().orc_residual_norm(dim, _i3(_act(dim, u, 1)), h, _p(u), _p(f))
 
 
 def restrict(dim, r, Nc):
-    fc = np.zeros(_shape(dim, Nc + 2))
-    lib().orc_restrict(dim, r.shape[0] - 2, _p(r), Nc, _p(fc))
+    Nc = _ax(dim, Nc)
+    fc = np.zeros(tuple(v + 2 for v in reversed(Nc)))
+    lib().orc_restrict(dim, _i3(_act(dim, r, 1)), _p(r), _i3(Nc), _p(fc))
     return fc
 
 
 def prolong_add(dim, ec, uf):
-    lib().orc_prolong_add(dim, ec.shape[0] - 2, _p(ec), uf.shape[0] - 2, _p(uf))
+    lib().orc_prolong_add(dim, _i3(_act(dim, ec, 1)), _p(ec), _i3(_act(dim, uf, 1)), _p(uf))
 
 
 def interface_fill(dim, phic, fc, nf, off, rho, fourpiG):
-    """Coarse-to-fine fill of a level l >= 1: returns (phi_f, f_f), padded."""
-    phif = np.zeros(_shape(dim, nf + 4))
+    """Coarse-to-fine fill of a level l >= 1 (nf: cells per axis, an int or
+    a tuple): returns (phi_f, f_f), padded."""
+    nf = _ax(dim, nf)
+    phif = np.zeros(tuple(v + 4 for v in reversed(nf)))
     ff = np.zeros_like(phif)
     offa = (ctypes.c_int * 3)(*(list(off) + [0] * (3 - len(off))))
     rho = np.ascontiguousarray(rho, dtype=np.float64)
-    lib().orc_interface_fill(dim, phic.shape[0] - 4, _p(phic), _p(fc), nf, offa, _p(rho), fourpiG, _p(phif), _p(ff))
+    lib().orc_interface_fill(dim, _i3(_act(dim, phic, 2)), _p(phic), _p(fc), _i3(nf), offa, _p(rho), fourpiG,
+                             _p(phif), _p(ff))
     return phif, ff
 
 
 def forces(dim, dx, phi):
     """F = -grad(Phi) on Omega of a padded level array (fourth-order stencil)."""
-    n = phi.shape[0] - 4
-    shp = (n, n, n) if dim == 3 else (n, n)
+    n = _act(dim, phi, 2)
+    shp = tuple(reversed(n))
     fx, fy, fz = np.zeros(shp), np.zeros(shp), np.zeros(shp if dim == 3 else (1,))
-    lib().orc_forces(dim, n, dx, _p(phi), _p(fx), _p(fy), _p(fz))
+    lib().orc_forces(dim, _i3(n), dx, _p(phi), _p(fx), _p(fy), _p(fz))
     return (fx, fy, fz) if dim == 3 else (fx, fy)
 
 
@@ -176,8 +213,7 @@ def set_threads(n):
 
 
 def vcycle_patch(dim, h0, u, f, n_pre=2, n_post=1, literal=False):
-    N0 = u.shape[0] - 2
-    rc = lib().orc_vcycle_patch(dim, N0, h0, _p(u), _p(f), n_pre, n_post, int(literal))
+    rc = lib().orc_vcycle_patch(dim, _i3(_act(dim, u, 1)), h0, _p(u), _p(f), n_pre, n_post, int(literal))
     if rc:
         raise RuntimeError("vcycle_patch failed")
 
@@ -192,7 +228,9 @@ def make_config(geom, n_pre=2, n_post=1, tol=1e-10, max_cycles=50, stop_rule=0, 
     c.dim = geom.dim
     c.nlevels = geom.nlevels
     for l in range(geom.nlevels):
-        c.n[l] = geom.n[l]
+        e = list(geom.ext(l)) + [1] * (3 - geom.dim)
+        for a in range(3):
+            c.n[l][a] = int(e[a])
         for a in range(3):
             c.off[l][a] = geom.off[l][a] if a < len(geom.off[l]) else 0
     c.dx0 = geom.dx0
@@ -215,7 +253,8 @@ def validate(geom):
 
 
 def solve(geom, rho, phi_outer, fixed_cycles=None, **kw):
-    """Nested solve.  rho[0]: (n0+2)^d, rho[l>=1]: n_l^d, phi_outer: (n0+4)^d.
+    """Nested solve.  rho[0]: n0_a + 2 per axis, rho[l>=1]: n_l,a per axis,
+    phi_outer: n0_a + 4 per axis ([k, j, i] arrays).
     buffer_interp=True: the comparison scheme of Sec. 4 on levels l >= 1 (both
     buffer layers interpolated from level l-1, only Omega^l relaxed).
 
@@ -225,7 +264,7 @@ def solve(geom, rho, phi_outer, fixed_cycles=None, **kw):
     nl = geom.nlevels
     rho = [np.ascontiguousarray(r, dtype=np.float64) for r in rho]
     phi_outer = np.ascontiguousarray(phi_outer, dtype=np.float64)
-    phi = [np.zeros(_shape(d, geom.n[l] + 4)) for l in range(nl)]
+    phi = [np.zeros(geom.shape(l, 2)) for l in range(nl)]
     rho_p = (_dp * nl)(*[_p(r) for r in rho])
     phi_p = (_dp * nl)(*[_p(a) for a in phi])
     fixed = None

@@ -33,9 +33,11 @@ def _parent(geom, l):
 
 def _interp(geom, l, coarse_padded, first, count):
     """Multilinear interpolation of the padded array of patch l's parent at the
-    centres of patch-l cells first..first+count-1 along every axis (index -2 =
-    outer layer)."""
+    centres of patch-l cells first..first+count_a-1 along each axis a (index
+    -2 = outer layer); `count` is one count per axis (x, y[, z]) or an int."""
     d = geom.dim
+    if not isinstance(count, (tuple, list)):
+        count = (count,) * d
     p = _parent(geom, l)
     lo_c = geom.lo(p)
     lo_f = geom.lo(l)
@@ -43,14 +45,14 @@ def _interp(geom, l, coarse_padded, first, count):
     idx = []
     wts = []
     for a in range(d):
-        i = np.arange(first, first + count)
+        i = np.arange(first, first + count[a])
         x = lo_f[a] + (i + 0.5) * dxf
         t = (x - lo_c[a]) / dxc - 0.5          # continuous coarse cell index
         il = np.floor(t).astype(int)
         w = t - il
         idx.append(il + 2)                      # padded coarse index
         wts.append(w)
-    out = np.zeros((count,) * d)
+    out = np.zeros(tuple(reversed(count)))
     for corner in range(1 << d):
         sel = [(corner >> a) & 1 for a in range(d)]
         # weights along each axis
@@ -67,25 +69,31 @@ def _interp(geom, l, coarse_padded, first, count):
 
 
 def _laplacian_system(d, m, h):
-    """Sparse matrix of the m^d-cell Laplacian with homogeneous Dirichlet data
-    outside (the boundary values are added to the right-hand side separately)."""
-    one = np.ones(m)
-    T = sp.diags([one[:-1], -2 * one, one[:-1]], [-1, 0, 1], shape=(m, m))
-    I = sp.identity(m)
+    """Sparse matrix of the Laplacian on m = (m_x, m_y[, m_z]) cells with
+    homogeneous Dirichlet data outside (the boundary values are added to the
+    right-hand side separately); unknowns in [k, j, i] order (x fastest)."""
+    def T(k):
+        one = np.ones(k)
+        return sp.diags([one[:-1], -2 * one, one[:-1]], [-1, 0, 1], shape=(k, k))
+
+    def I(k):
+        return sp.identity(k)
+
     if d == 2:
-        A = sp.kron(I, T) + sp.kron(T, I)
+        A = sp.kron(I(m[1]), T(m[0])) + sp.kron(T(m[1]), I(m[0]))
     else:
-        A = sp.kron(sp.kron(I, I), T) + sp.kron(sp.kron(I, T), I) + sp.kron(sp.kron(T, I), I)
+        A = (sp.kron(sp.kron(I(m[2]), I(m[1])), T(m[0])) + sp.kron(sp.kron(I(m[2]), T(m[1])), I(m[0]))
+             + sp.kron(sp.kron(T(m[2]), I(m[1])), I(m[0])))
     return (A / (h * h)).tocsc()
 
 
 def _boundary_term(d, phi_padded, h):
-    """Contribution of the outer-layer values to the Laplacian of each Gamma cell."""
-    P = phi_padded.shape[0]
-    m = P - 2
-    b = np.zeros((m,) * d)
+    """Contribution of the outer-layer values to the Laplacian of each cell
+    inside them (the array minus its outermost layer)."""
+    P = phi_padded.shape
+    b = np.zeros(tuple(v - 2 for v in P))
     ring = phi_padded.copy()
-    inner = (slice(1, P - 1),) * d
+    inner = tuple(slice(1, v - 1) for v in P)
     ring[inner] = 0.0
     # sum of the face neighbours that are outer-layer points
     for a in range(d):
@@ -93,9 +101,9 @@ def _boundary_term(d, phi_padded, h):
             sl = []
             for ax in range(d):
                 if ax == a:
-                    sl.append(slice(1 + s, P - 1 + s))
+                    sl.append(slice(1 + s, P[ax] - 1 + s))
                 else:
-                    sl.append(slice(1, P - 1))
+                    sl.append(slice(1, P[ax] - 1))
             b += ring[tuple(sl)]
     return b / (h * h)
 
@@ -106,33 +114,33 @@ def solve(geom, rho, phi_outer, buffer_interp=False):
     fourpiG = 4 * math.pi * geom.G
     phis, fs = [], []
     for l in range(geom.nlevels):
-        n = geom.n[l]
-        P = n + 4
+        n = geom.ext(l)                       # cells per axis (x, y[, z])
         h = geom.dx(l)
-        phi = np.zeros((P,) * d)
-        f = np.zeros((P,) * d)
-        core = (slice(2, n + 2),) * d
+        phi = np.zeros(geom.shape(l, 2))
+        f = np.zeros(geom.shape(l, 2))
+        core = tuple(slice(2, v + 2) for v in reversed(n))
+        gam = tuple(slice(1, v + 3) for v in reversed(n))
         if l == 0:
             phi[...] = np.asarray(phi_outer)
-            f[(slice(1, n + 3),) * d] = fourpiG * np.asarray(rho[0])
+            f[gam] = fourpiG * np.asarray(rho[0])
         else:
             p = _parent(geom, l)
-            phi[...] = _interp(geom, l, phis[p], -2, n + 4)
-            f[(slice(1, n + 3),) * d] = _interp(geom, l, fs[p], -1, n + 2)
+            phi[...] = _interp(geom, l, phis[p], -2, tuple(v + 4 for v in n))
+            f[gam] = _interp(geom, l, fs[p], -1, tuple(v + 2 for v in n))
             f[core] = fourpiG * np.asarray(rho[l])
         if l > 0 and buffer_interp:
             # unknowns on Omega^l; the inner layer is the boundary of the sub-box
-            sub = phi[(slice(1, n + 3),) * d]
+            sub = phi[gam]
             A = _laplacian_system(d, n, h)
             rhs = f[core] - _boundary_term(d, sub, h)
             x = spla.spsolve(A, rhs.reshape(-1))
-            phi[core] = x.reshape((n,) * d)
+            phi[core] = x.reshape(tuple(reversed(n)))
         else:
-            m = n + 2
+            m = tuple(v + 2 for v in n)
             A = _laplacian_system(d, m, h)
-            rhs = f[(slice(1, n + 3),) * d] - _boundary_term(d, phi, h)
+            rhs = f[gam] - _boundary_term(d, phi, h)
             x = spla.spsolve(A, rhs.reshape(-1))
-            phi[(slice(1, n + 3),) * d] = x.reshape((m,) * d)
+            phi[gam] = x.reshape(tuple(reversed(m)))
         phis.append(phi)
         fs.append(f)
     return phis, fs
@@ -141,15 +149,14 @@ def solve(geom, rho, phi_outer, buffer_interp=False):
 def forces(dim, dx, phi):
     """F = -grad(Phi) on Omega from a padded array, fourth-order central
     difference (Eqn:force_evaluation), written with array slices."""
-    P = phi.shape[0]
-    n = P - 4
+    P = phi.shape
     out = []
     for a in range(dim):
         ax = dim - 1 - a  # numpy axis of physical axis a ([k, j, i] order)
 
         def sh(off):
-            sl = [slice(2, n + 2)] * dim
-            sl[ax] = slice(2 + off, n + 2 + off)
+            sl = [slice(2, v - 2) for v in P]
+            sl[ax] = slice(2 + off, P[ax] - 2 + off)
             return phi[tuple(sl)]
 
         g = 8.0 * (sh(1) - sh(-1)) - (sh(2) - sh(-2))

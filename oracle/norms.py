@@ -15,15 +15,13 @@ def _children(geom, l):
 
 
 def uncovered_mask(geom, l):
-    """Boolean n_l^d mask of the cells of patch l not covered by a finer patch
+    """Boolean mask (shape of Omega^l) of the cells of patch l not covered by a finer patch
     refined out of it (Omega^{l+1} for the stack of one patch per level)."""
-    n = geom.n[l]
-    shp = (n,) * geom.dim
-    m = np.ones(shp, dtype=bool)
+    m = np.ones(geom.shape(l), dtype=bool)
     for c in _children(geom, l):
         o = geom.off[c]
-        h = geom.n[c] // 2
-        sl = tuple(slice(o[a], o[a] + h) for a in reversed(range(geom.dim)))  # [k, j, i]
+        h = [v // 2 for v in geom.ext(c)]
+        sl = tuple(slice(o[a], o[a] + h[a]) for a in reversed(range(geom.dim)))  # [k, j, i]
         m[sl] = False
     return m
 

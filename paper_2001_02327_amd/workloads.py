@@ -34,7 +34,8 @@ import torch
 @dataclass
 class Geometry:
     dim: int
-    n: List[int]                      # cells per axis of Omega^l
+    n: List                           # cells of Omega^l: an int (the same along every
+                                      # axis) or a tuple per axis (x, y[, z])
     off: List[Tuple[int, int, int]]   # l >= 1: corner offset in coarse cells (off[0] unused)
     lo0: Tuple[float, float, float]   # physical lower corner of Omega^0
     dx0: float
@@ -47,6 +48,22 @@ class Geometry:
     @property
     def nlevels(self) -> int:
         return len(self.n)
+
+    def ext(self, l: int) -> Tuple[int, ...]:
+        """Cells of Omega^l along x, y[, z]."""
+        n = self.n[l]
+        if isinstance(n, (tuple, list)):
+            assert len(n) == self.dim
+            return tuple(int(v) for v in n)
+        return (int(n),) * self.dim
+
+    @property
+    def cubic(self) -> bool:
+        return all(len(set(self.ext(l))) == 1 for l in range(self.nlevels))
+
+    def shape(self, l: int, pad: int = 0) -> Tuple[int, ...]:
+        """Array shape [k, j, i] of Omega^l with `pad` extra cells on every side."""
+        return tuple(v + 2 * pad for v in reversed(self.ext(l)))
 
     def par(self, l: int) -> int:
         return self.parent[l] if self.parent is not None else l - 1
@@ -71,15 +88,24 @@ class Geometry:
         base = self.lo(p)
         return tuple(base[a] + self.off[l][a] * self.dx(p) for a in range(self.dim))
 
-    def centres(self, l: int, first: int, count: int, device="cpu"):
+    def centres(self, l: int, first: int, count, device="cpu"):
         """Per-axis cell-centre coordinates for Omega^l cell indices first..first+count-1
-        (index -2 = outer buffer layer, -1 = inner buffer layer)."""
+        (index -2 = outer buffer layer, -1 = inner buffer layer); `count` is an
+        int or one count per axis."""
         lo = self.lo(l)
         dx = self.dx(l)
-        i = torch.arange(first, first + count, dtype=torch.float64, device=device)
-        return [lo[a] + (i + 0.5) * dx for a in range(self.dim)]
+        cnt = tuple(count) if isinstance(count, (tuple, list)) else (count,) * self.dim
+        out = []
+        for a in range(self.dim):
+            i = torch.arange(first, first + cnt[a], dtype=torch.float64, device=device)
+            out.append(lo[a] + (i + 0.5) * dx)
+        return out
 
-    def mesh(self, l: int, first: int, count: int, device="cpu"):
+    def mesh_pad(self, l: int, pad: int = 0, device="cpu"):
+        """Coordinate arrays of Omega^l with `pad` cells on every side."""
+        return self.mesh(l, -pad, tuple(v + 2 * pad for v in self.ext(l)), device)
+
+    def mesh(self, l: int, first: int, count, device="cpu"):
         """Coordinate arrays (x, y[, z]) broadcast to [k, j, i] shape."""
         ax = self.centres(l, first, count, device)
         if self.dim == 3:
@@ -89,7 +115,8 @@ class Geometry:
         return x, y
 
     def describe(self) -> dict:
-        d = dict(dim=self.dim, n=list(self.n), off=[list(o) for o in self.off], lo0=list(self.lo0[: self.dim]),
+        d = dict(dim=self.dim, n=[list(v) if isinstance(v, (tuple, list)) else v for v in self.n],
+                 off=[list(o) for o in self.off], lo0=list(self.lo0[: self.dim]),
                  dx0=self.dx0, G=self.G)
         if self.parent is not None:
             d["parent"] = list(self.parent)
@@ -309,19 +336,15 @@ class Quadratic(Problem):
 def make_inputs(geom: Geometry, prob: Problem, device="cpu"):
     """Caller inputs of a nested solve.
 
-    rho[0]   : (n0+2)^d   Omega^0 plus its inner buffer layer
-    rho[l>=1]: n_l^d      Omega^l
-    phi_outer: (n0+4)^d   closed-form potential (only its outer layer is used)
+    rho[0]   : n0_a + 2 per axis   Omega^0 plus its inner buffer layer
+    rho[l>=1]: n_l,a per axis      Omega^l
+    phi_outer: n0_a + 4 per axis   closed-form potential (only its outer layer is used)
     """
     rho = []
     for l in range(geom.nlevels):
-        n = geom.n[l]
-        if l == 0:
-            x = geom.mesh(0, -1, n + 2, device)
-        else:
-            x = geom.mesh(l, 0, n, device)
+        x = geom.mesh_pad(l, 1 if l == 0 else 0, device)
         rho.append(prob.rho(*x).contiguous())
-    x = geom.mesh(0, -2, geom.n[0] + 4, device)
+    x = geom.mesh_pad(0, 2, device)
     phi_outer = prob.phi(*x).contiguous()
     return rho, phi_outer
 
@@ -431,3 +454,44 @@ def two_patch_3d(N: int = 64, grandchild_order: str = "last") -> Workload:
     g = two_patch_geometry(3, N, grandchild_order)
     return Workload("two_patch_3d_%d_%s" % (N, grandchild_order), g,
                     Plummer([(1.0, 0.1, (-0.5, 0.0, 0.0)), (0.5, 0.06, (0.5, 0.0, 0.0))]))
+
+
+def box_geometry(dim: int, n0, n1, off1, n2=None, off2=None, dx0: float = 1.0 / 32) -> Geometry:
+    """Non-cubic nested patches (Sec. 2.1 gives the cell counts per direction;
+    the cells stay cubes): base level of n0 = (nx, ny[, nz]) cells with its
+    lower corner at the origin, a patch of n1 cells whose corner sits off1
+    base cells in, and optionally a patch of n2 cells inside that one."""
+    n = [tuple(n0), tuple(n1)]
+    off = [(0, 0, 0), tuple(off1) + (0,) * (3 - dim)]
+    if n2 is not None:
+        n.append(tuple(n2))
+        off.append(tuple(off2) + (0,) * (3 - dim))
+    return Geometry(dim=dim, n=n, off=off, lo0=(0.0, 0.0, 0.0), dx0=dx0, G=1.0)
+
+
+def box_plummer_3d(scale: int = 1) -> Workload:
+    """A 3-D stack of non-cubic patches around a Plummer sphere (M = 1,
+    a = 0.12): base 64 x 32 x 46 cells of 1/32, a 46 x 22 x 30 patch from
+    base cell (8, 4, 8), a 30 x 16 x 22 patch inside it from (6, 3, 4);
+    `scale` multiplies every cell count (and divides the spacing).  The counts
+    keep every right-ghost gain of their hierarchies small at scales 1-8."""
+    k = scale
+    g = box_geometry(3, (64 * k, 32 * k, 46 * k), (46 * k, 22 * k, 30 * k), (8 * k, 4 * k, 8 * k),
+                     (30 * k, 16 * k, 22 * k), (6 * k, 3 * k, 4 * k), dx0=1.0 / (32 * k))
+    c = g.lo(2)
+    e = g.ext(2)
+    centre = tuple(c[a] + 0.5 * e[a] * g.dx(2) for a in range(3))
+    return Workload("box_plummer_3d_%d" % k, g, Plummer([(1.0, 0.12, centre)]))
+
+
+def box_gaussian_2d(scale: int = 1) -> Workload:
+    """A 2-D stack of non-cubic patches around a manufactured Gaussian
+    (s = 0.15): base 64 x 32 cells of 1/32, a 42 x 26 patch from base cell
+    (10, 2), a 26 x 16 patch inside it from (8, 5); `scale` as above."""
+    k = scale
+    g = box_geometry(2, (64 * k, 32 * k), (42 * k, 26 * k), (10 * k, 2 * k), (26 * k, 16 * k), (8 * k, 5 * k),
+                     dx0=1.0 / (32 * k))
+    c = g.lo(2)
+    e = g.ext(2)
+    centre = tuple(c[a] + 0.5 * e[a] * g.dx(2) for a in range(2))
+    return Workload("box_gaussian_2d_%d" % k, g, GaussianSum([(1.0, 0.15, centre)]))
