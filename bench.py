@@ -74,6 +74,10 @@ def workload(name, N):
         # a tree: base level of N^3 cells, two disjoint (N/2)^3 patches on level 1
         # around two Plummer spheres, one (N/2)^3 patch on level 2
         return W.two_patch_3d(N)
+    if name == "box":
+        # non-cubic patches: the box stack 64 x 32 x 46 / 46 x 22 x 30 / 30 x 16 x 22
+        # scaled by N / 64 (N = 512: 512 x 256 x 368 base)
+        return W.box_plummer_3d(max(1, N // 64))
     raise SystemExit("unknown workload %s" % name)
 
 
@@ -85,15 +89,15 @@ def linf_force_error(solver, wl, Fs):
     for l in range(geom.nlevels):
         F = Fs[l]
         solver.forces(l, out=F)
-        x = geom.mesh(l, 0, geom.n[l], device=F[0].device)
+        x = geom.mesh_pad(l, 0, device=F[0].device)
         Fa = wl.prob.force(*x)
         e = torch.zeros_like(F[0])
         for a in range(geom.dim):
             e += (F[a] - Fa[a]) ** 2
         e = e.sqrt()
         for c in geom.children(l):
-            o, h = geom.off[c], geom.n[c] // 2
-            e[o[2]:o[2] + h, o[1]:o[1] + h, o[0]:o[0] + h] = 0.0
+            o, h = geom.off[c], [v // 2 for v in geom.ext(c)]
+            e[o[2]:o[2] + h[2], o[1]:o[1] + h[1], o[0]:o[0] + h[0]] = 0.0
         worst = max(worst, float(e.max()))
         del x, Fa, e
     return worst
@@ -108,14 +112,13 @@ def edge_force_error(solver, wl, Fs, width=2):
     for l in range(1, geom.nlevels):
         F = Fs[l]
         solver.forces(l, out=F)
-        x = geom.mesh(l, 0, geom.n[l], device=F[0].device)
+        x = geom.mesh_pad(l, 0, device=F[0].device)
         Fa = wl.prob.force(*x)
         e = torch.zeros_like(F[0])
         for a in range(geom.dim):
             e += (F[a] - Fa[a]) ** 2
         e = e.sqrt()
-        n = geom.n[l]
-        e[(slice(width, n - width),) * geom.dim] = 0.0
+        e[tuple(slice(width, v - width) for v in geom.shape(l))] = 0.0
         out.append(float(e.max()))
         del x, Fa, e
     return out
@@ -147,17 +150,16 @@ def cpu_baseline(wl, rho, phi_outer, cycles_per_level, sample_cycles, small_N=12
     nthreads = core.num_threads()
     t_all, t_one = {}, {}
     for l in range(g.nlevels):
-        n = g.n[l]
+        n = g.ext(l)
         if n in t_all:
             continue
-        P = n + 4
         if l == 0:
             u = np.ascontiguousarray(phi_outer.cpu().numpy())
             u[1:-1, 1:-1, 1:-1] = 0.0
             f = np.zeros_like(u)
             f[1:-1, 1:-1, 1:-1] = 4 * math.pi * g.G * rho[0].cpu().numpy()
         else:
-            u = np.zeros((P,) * 3)
+            u = np.zeros(g.shape(l, 2))
             f = np.zeros_like(u)
             f[2:-2, 2:-2, 2:-2] = 4 * math.pi * g.G * rho[l].cpu().numpy()
         core.set_threads(nthreads)
@@ -172,10 +174,10 @@ def cpu_baseline(wl, rho, phi_outer, cycles_per_level, sample_cycles, small_N=12
         t_one[n] = time.perf_counter() - t0
         core.set_threads(nthreads)
         del u, f
-    ms_all = sum(t_all[g.n[l]] * 1e3 * cycles_per_level[l] for l in range(g.nlevels))
-    ms_one = sum(t_one[g.n[l]] * 1e3 * cycles_per_level[l] for l in range(g.nlevels))
-    sizes = ", ".join("%d^3 active cells at %.4f s (%d threads) / %.3f s (1 thread)" % (n + 2, t_all[n], nthreads,
-                                                                                       t_one[n]) for n in t_all)
+    ms_all = sum(t_all[g.ext(l)] * 1e3 * cycles_per_level[l] for l in range(g.nlevels))
+    ms_one = sum(t_one[g.ext(l)] * 1e3 * cycles_per_level[l] for l in range(g.nlevels))
+    sizes = ", ".join("%s active cells at %.4f s (%d threads) / %.3f s (1 thread)"
+                      % ("x".join(str(v + 2) for v in n), t_all[n], nthreads, t_one[n]) for n in t_all)
     # one complete nested solve (fills, V-cycles to the stop rule, forces) at a small size
     small = workload_small(wl, small_N)
     full = None
@@ -215,6 +217,8 @@ def workload_small(wl, N):
         return W.c2_plummer(N=N)
     if name.startswith("paper3d"):
         return W.paper3d(N)
+    if name.startswith("box_plummer_3d"):
+        return W.box_plummer_3d(1)
     return None
 
 
@@ -327,11 +331,10 @@ def run_variant(name, wl, rho, phi_outer, Fs, steps, warmup, inner_cycles, stop_
     ms_profiled = e0.elapsed_time(e1) / steps
     prof = solver.profile()
     solver.set_profiling(False)
-    N0 = geom.n[0] + 2
     # algorithmic bytes of one level-0 half sweep: read the other colour, read f of
     # this colour, write this colour: 1.5 elements per grid point (both colours counted)
     elem = ELEM[v["precision"]]
-    half_sweep_bytes = 1.5 * elem * N0 ** geom.dim
+    half_sweep_bytes = 1.5 * elem * math.prod(v + 2 for v in geom.ext(0))
     sm_count, sm_ms = prof["smooth"]
     sm_avg_ms = sm_ms / max(sm_count, 1)
     linf = linf_force_error(solver, wl, Fs)
@@ -355,7 +358,8 @@ def run_variant(name, wl, rho, phi_outer, Fs, steps, warmup, inner_cycles, stop_
         deviation_from_fp64=dev,
         edge_force_error_per_level=edge,
         smoother=(dict(elem_bytes=elem, bytes_per_launch=half_sweep_bytes, avg_launch_us=round(sm_avg_ms * 1e3, 2),
-                       GBps=round(half_sweep_bytes / (sm_avg_ms * 1e-3) / 1e9, 1)) if len(set(geom.n)) == 1 else
+                       GBps=round(half_sweep_bytes / (sm_avg_ms * 1e-3) / 1e9, 1))
+                  if len(set(geom.ext(l) for l in range(geom.nlevels))) == 1 else
                   dict(elem_bytes=elem, avg_launch_us=round(sm_avg_ms * 1e3, 2))),
         kernels={k: dict(launches=c, ms_per_step=round(m / steps, 3), avg_us=(round(1e3 * m / c, 2) if c else None))
                  for k, (c, m) in prof.items()},
@@ -413,12 +417,13 @@ def main():
     n = geom.n
     # the smoother roofline and the CPU baseline assume one grid size for every
     # multigrid level 0; a workload with patches of several sizes reports neither
-    uniform = len(set(n)) == 1
+    uniform = len(set(geom.ext(l) for l in range(geom.nlevels))) == 1
     Fs = {}
     for l in range(geom.nlevels):
-        if n[l] not in Fs:
-            Fs[n[l]] = [torch.empty((n[l],) * geom.dim, dtype=torch.float64, device=dev) for _ in range(geom.dim)]
-    Fs = [Fs[n[l]] for l in range(geom.nlevels)]
+        e = geom.ext(l)
+        if e not in Fs:
+            Fs[e] = [torch.empty(geom.shape(l), dtype=torch.float64, device=dev) for _ in range(geom.dim)]
+    Fs = [Fs[geom.ext(l)] for l in range(geom.nlevels)]
 
     if args.stop == "force_delta":
         names = [v for v in names if VARIANTS[v].get("buffer", "relaxed") == "relaxed"]  # residual stop only there
@@ -472,7 +477,9 @@ def main():
         "config": {
             "workload": wl.name,
             "levels": geom.nlevels,
-            "cells_per_level": ("%d^%d" % (n[0], geom.dim)) if uniform else ["%d^%d" % (m, geom.dim) for m in n],
+            "cells_per_level": (("%d^%d" % (n[0], geom.dim)) if geom.cubic else "x".join(map(str, geom.ext(0))))
+            if uniform else [("%d^%d" % (m, geom.dim)) if not isinstance(m, (tuple, list)) else "x".join(map(str, m))
+                             for m in n],
             "variant": best,
             "stop": ("||r||_inf <= 1e-10 ||f||_inf per level" if args.stop == "residual" else
                      "max |F^q - F^(q-1)| < 1e-10 per level"),
@@ -486,7 +493,7 @@ def main():
             "peak": PEAK_HBM_GBS,
             "unit": "GB/s",
             "frac": round(sm["GBps"] / PEAK_HBM_GBS, 4),
-            "traffic": measured_traffic(VARIANTS[best]["precision"], n[0] + 2),
+            "traffic": measured_traffic(VARIANTS[best]["precision"], geom.ext(0)[0] + 2) if geom.cubic else None,
             "traffic_source": os.path.relpath(PMC_SUMMARY, ROOT),
             "kernel_source_sha": kernel_source_sha(),
             "bytes_per_launch": sm["bytes_per_launch"],

@@ -17,17 +17,19 @@
  * size of entry l is dx0 / 2^depth(l).  nested_poisson_default_config sets
  * parent[l] = l - 1, the paper's stack of one patch per level; a tree gives
  * several disjoint patches per level (the patch-based setting of Sec. 4).
- * Entry l is a cube (square in 2-D) of n[l] cells per axis whose lower corner
- * lies offset[l][a] cells of p above p's lower corner along axis a; it must
- * keep at least one coarse cell of margin on every side:
- *     1 <= offset[l][a]  and  offset[l][a] + n[l]/2 <= n[p] - 1,
+ * Entry l is a box of n_a = extent[l][a] cells along axis a (Sec. 2.1 gives
+ * the cell counts per direction; the cells are cubes), or a cube (square in
+ * 2-D) of n[l] cells per axis when extent[l][0] is 0.  Its lower corner lies
+ * offset[l][a] cells of p above p's lower corner along axis a; it must keep
+ * at least one coarse cell of margin on every side:
+ *     1 <= offset[l][a]  and  offset[l][a] + n_a/2 <= n_a(p) - 1,
  * and patches with the same parent must not overlap.  Patches are solved in
  * entry order, each from its converged parent (one-way scheme).
- * Each level carries a two-cell buffer.  Its padded array has n[l] + 4
- * points per axis: index 0 and n+3 are the outer buffer layer (Dirichlet
- * potential), 1 and n+2 the inner buffer layer (relaxed together with the
- * patch), 2..n+1 the patch itself.  Cell i of the patch is centred at
- * lo_l + (i + 1/2) dx_l.
+ * Each level carries a two-cell buffer.  Its padded array has n_a + 4
+ * points along axis a: index 0 and n_a+3 are the outer buffer layer
+ * (Dirichlet potential), 1 and n_a+2 the inner buffer layer (relaxed together
+ * with the patch), 2..n_a+1 the patch itself.  Cell i of the patch is centred
+ * at lo_l + (i + 1/2) dx_l.
  *
  * Memory.  Every array crossing this ABI is row-major with x fastest
  * ([k][j][i] in 3-D, [j][i] in 2-D), FP64, in DEVICE memory of the device
@@ -106,26 +108,36 @@ typedef struct np_config {
     int guess;                      /* NP_GUESS_* */
     int buffer;                     /* NP_BUFFER_* */
     int parent[NP_MAX_LEVELS];      /* l >= 1: the entry patch l is refined out of, 0 <= parent[l] < l */
+    int extent[NP_MAX_LEVELS][3];   /* cells of level l along x, y (, z): each even, >= 4; all zero:
+                                       n[l] along every axis */
 } np_config;
 
 /* Fills `cfg` with the paper's solver settings (N_pre = 2, N_post = 1,
  * Sec. 3) and tol = 1e-10, max_cycles = 50, FP64, residual stop,
  * interpolated guess, relaxed buffer, parent[l] = l - 1.  The other
- * geometry fields are zeroed. */
+ * geometry fields (extent included: cubic patches) are zeroed. */
 void nested_poisson_default_config(np_config* cfg);
 
-/* Multigrid hierarchy of one patch (Sec. 2.2): N^0 = n + 2 (patch plus its
- * inner buffer layer; N^0 = n on levels l >= 1 with NP_BUFFER_INTERP, where
- * the patch alone is relaxed), N^L = round(N^0 / 2^L) with halves rounded up, until
- * N^L = 1.  For L >= 1, right-ghost rule of Sec. 2.4: xn_is_one[L] is 1 when
- * the right-most active centre sits exactly at x_MG = 1 (ghost = -e_{N-1}),
- * otherwise ghost = ghost_coef[L] * e_N, the value at x_N + h^L of the line
- * through (x_N, e_N) that vanishes at x_MG = 1. */
+/* Multigrid hierarchy of one patch (Sec. 2.2), along each axis a: N^0_a =
+ * n_a + 2 (patch plus its inner buffer layer; N^0_a = n_a on levels l >= 1
+ * with NP_BUFFER_INTERP, where the patch alone is relaxed), N^L_a =
+ * round(N^0_a / 2^L) with halves rounded up (every axis doubles its mesh size,
+ * so the cells stay cubes); the hierarchy ends on the first level with one
+ * active cell along some axis (for a cube: N^L = 1).  For L >= 1, right-ghost
+ * rule of Sec. 2.4 per axis: xn_is_one[L][a] is 1 when the right-most active
+ * centre sits exactly at x_MG = 1 (ghost = -e_{N-1}), otherwise ghost =
+ * ghost_coef[L][a] * e_N, the value at x_N + h^L of the line through
+ * (x_N, e_N) that vanishes at x_MG = 1.  The ghost refresh is explicit, so an
+ * error at the last active cell returns amplified by ghost_coef / (2 dim);
+ * hierarchies where that gain exceeds NP_MAX_GHOST_GAIN (x_N just below 1,
+ * e.g. N^0 = 194 at L = 7 with ghost_coef = -63) make the V-cycle diverge and
+ * are refused (NP_EINVAL). */
+#define NP_MAX_GHOST_GAIN 6.0
 typedef struct np_plan {
-    int nmg[NP_MAX_LEVELS];                   /* multigrid levels of each nested level */
-    int N[NP_MAX_LEVELS][NP_MAX_MG];          /* active cells per axis */
-    int xn_is_one[NP_MAX_LEVELS][NP_MAX_MG];
-    double ghost_coef[NP_MAX_LEVELS][NP_MAX_MG];
+    int nmg[NP_MAX_LEVELS];                      /* multigrid levels of each nested level */
+    int N[NP_MAX_LEVELS][NP_MAX_MG][3];          /* active cells along x, y, z (z: 1 in 2-D) */
+    int xn_is_one[NP_MAX_LEVELS][NP_MAX_MG][3];
+    double ghost_coef[NP_MAX_LEVELS][NP_MAX_MG][3];
 } np_plan;
 
 /* Validates `cfg` and computes the hierarchy on the host; touches no device.
@@ -142,11 +154,12 @@ typedef struct np_solver np_solver;
 int nested_poisson_create(const np_config* cfg, void* hip_stream, np_solver** out);
 
 /* Nested solve (Sec. 2.1 one-way scheme, Sec. 2.3 V-cycle).
- *   rho[0]    : (n0+2)^d density of level 0 including its inner buffer layer
- *   rho[l>=1] : n_l^d density of level l (the inner buffer layer of l >= 1
- *               gets the density interpolated from its parent)
- *   phi_outer : (n0+4)^d; only the outer layer is read (Dirichlet data of
- *               level 0)
+ *   rho[0]    : n_a(0) + 2 points per axis: density of level 0 including its
+ *               inner buffer layer
+ *   rho[l>=1] : n_a(l) points per axis: density of level l (the inner buffer
+ *               layer of l >= 1 gets the density interpolated from its parent)
+ *   phi_outer : n_a(0) + 4 points per axis; only the outer layer is read
+ *               (Dirichlet data of level 0)
  * Level 0 starts from Phi = 0; level l >= 1 from the potential interpolated
  * from its parent (plus the learned correction with NP_GUESS_LEARNED).
  * Returns after the last stop test of the finest level (host-synchronous).
@@ -177,14 +190,15 @@ int nested_poisson_set_fixed_cycles(np_solver* s, const int* cycles);
  * returns their count (or a negative error). */
 int nested_poisson_history(const np_solver* s, int level, double* out, int cap);
 
-/* F = -grad(Phi) on the n_l^d cells of level `level` (Eqn:force_evaluation),
- * written to device arrays fx, fy (and fz in 3-D; ignored in 2-D), each n_l^d.
+/* F = -grad(Phi) on the cells of level `level` (Eqn:force_evaluation),
+ * written to device arrays fx, fy (and fz in 3-D; ignored in 2-D), each of
+ * the level's shape (n_z x n_y x n_x, x fastest).
  * Queued on the handle's stream; does not synchronise.
  * Errors: NP_EINVAL (level out of range, null pointer), NP_ESTATE (no solve). */
 int nested_poisson_forces(np_solver* s, int level, double* fx, double* fy, double* fz);
 
-/* Copies the padded (n_l+4)^d potential of `level` into the device array
- * `phi_padded` (both buffer layers included).  Queued on the stream.
+/* Copies the padded potential of `level` (n_a + 4 points per axis) into the
+ * device array `phi_padded` (both buffer layers included).  Queued on the stream.
  * Errors: as nested_poisson_forces. */
 int nested_poisson_potential(np_solver* s, int level, double* phi_padded);
 
@@ -262,9 +276,10 @@ int nested_poisson_check_guess_weights(const void* blob, size_t nbytes);
 int nested_poisson_set_guess_weights(np_solver* s, const void* blob, size_t nbytes);
 
 /* Training data of level `level` >= 1 after a successful solve: the network
- * input x ((n+2)^3 x 2 FP32, channel-last) built from the interpolated guess,
- * and target = (Phi_converged - Phi_interp) / (||f||_inf dx_l^2) ((n+2)^3 FP32,
- * may be NULL).  Device arrays.  Errors: NP_EINVAL, NP_ESTATE, NP_ENOMEM. */
+ * input x ((n_z+2) x (n_y+2) x (n_x+2) x 2 FP32, channel-last) built from the
+ * interpolated guess, and target = (Phi_converged - Phi_interp) /
+ * (||f||_inf dx_l^2) (one value per point of Gamma^l, FP32, may be NULL).
+ * Device arrays.  Errors: NP_EINVAL, NP_ESTATE, NP_ENOMEM. */
 int nested_poisson_guess_features(np_solver* s, int level, float* x, float* target);
 
 /* Workspace (bytes) needed by np_net_conv3d_bwd_weight for (cin, cout) and by

@@ -47,15 +47,16 @@ class NpConfig(ctypes.Structure):
         ("guess", ctypes.c_int),
         ("buffer", ctypes.c_int),
         ("parent", ctypes.c_int * NP_MAX_LEVELS),
+        ("extent", (ctypes.c_int * 3) * NP_MAX_LEVELS),
     ]
 
 
 class NpPlan(ctypes.Structure):
     _fields_ = [
         ("nmg", ctypes.c_int * NP_MAX_LEVELS),
-        ("N", (ctypes.c_int * NP_MAX_MG) * NP_MAX_LEVELS),
-        ("xn_is_one", (ctypes.c_int * NP_MAX_MG) * NP_MAX_LEVELS),
-        ("ghost_coef", (ctypes.c_double * NP_MAX_MG) * NP_MAX_LEVELS),
+        ("N", ((ctypes.c_int * 3) * NP_MAX_MG) * NP_MAX_LEVELS),
+        ("xn_is_one", ((ctypes.c_int * 3) * NP_MAX_MG) * NP_MAX_LEVELS),
+        ("ghost_coef", ((ctypes.c_double * 3) * NP_MAX_MG) * NP_MAX_LEVELS),
     ]
 
 
@@ -161,7 +162,12 @@ def make_config(geom, n_pre=2, n_post=1, tol=1e-10, max_cycles=50, stop_rule="re
     c.dim = int(geom.dim)
     c.nlevels = len(geom.n)
     for l, n in enumerate(geom.n):
-        c.n[l] = int(n)
+        if isinstance(n, (tuple, list)):
+            # a box: cells per axis (n[l] unused)
+            for a in range(3):
+                c.extent[l][a] = int(n[a]) if a < len(n) else 0
+        else:
+            c.n[l] = int(n)
         off = list(geom.off[l]) + [0, 0, 0]
         for a in range(3):
             c.offset[l][a] = int(off[a])
@@ -189,10 +195,12 @@ def plan(cfg):
     if rc:
         raise NestedPoissonError(rc, lib().nested_poisson_last_error(None).decode())
     out = []
+    d = cfg.dim
     for l in range(cfg.nlevels):
         m = p.nmg[l]
-        out.append(dict(N=[p.N[l][L] for L in range(m)], xn_is_one=[p.xn_is_one[l][L] for L in range(m)],
-                        coef=[p.ghost_coef[l][L] for L in range(m)]))
+        out.append(dict(N=[tuple(p.N[l][L][a] for a in range(d)) for L in range(m)],
+                        xn_is_one=[tuple(p.xn_is_one[l][L][a] for a in range(d)) for L in range(m)],
+                        coef=[tuple(p.ghost_coef[l][L][a] for a in range(d)) for L in range(m)]))
     return out
 
 

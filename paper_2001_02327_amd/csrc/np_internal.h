@@ -1,10 +1,10 @@
 // Internal declarations of the nested-grid multigrid library (gfx950).
 //
 // Storage: every grid (a nested level's padded array, or one multigrid level)
-// is a cube (square in 2-D) of nx points per axis in "colour-split" form: the
+// is a box of nx x ny x nz points (nz = 1 in 2-D) in "colour-split" form: the
 // red points (even sum of 0-based active indices) and the black points are
 // stored in two separate arrays, each holding hx = (nx+1)/2 points per row:
-//     value(pi, pj, pk) = a[c * cs + (pk * nx + pj) * hx + (pi >> 1)],
+//     value(pi, pj, pk) = a[c * cs + pk * ps + pj * hx + (pi >> 1)],
 //     c = (pi + pj + pk + dim) & 1          (0 = red),
 // with pi, pj, pk padded indices (0 = ghost / outer buffer layer).  A
 // red-black half sweep then reads one colour and writes the other with unit
@@ -20,25 +20,46 @@
 namespace np {
 
 struct SGrid {
-    int nx;     // padded points per axis
+    int nx;     // padded points along x
+    int ny;     // padded points along y
+    int nz;     // padded points along z (1 in 2-D)
     int hx;     // compact points per row and colour
-    int nz;     // nx in 3-D, 1 in 2-D
-    size_t ps;  // elements per plane of one colour: nx rows of hx, rounded up to a
+    size_t ps;  // elements per plane of one colour: ny rows of hx, rounded up to a
                 // multiple of 128 in 3-D so that every plane starts 256-byte aligned
     size_t cs;  // elements per colour array (nz planes)
 };
 
-inline SGrid make_grid(int dim, int nx)
+inline SGrid make_grid(int dim, int nx, int ny, int nz)
 {
     SGrid g;
     g.nx = nx;
+    g.ny = ny;
+    g.nz = dim == 3 ? nz : 1;
     g.hx = (nx + 1) / 2;
-    g.nz = dim == 3 ? nx : 1;
-    g.ps = (size_t)g.hx * nx;
+    g.ps = (size_t)g.hx * ny;
     if (dim == 3) g.ps = (g.ps + 127) / 128 * 128;
     g.cs = g.ps * g.nz;
     return g;
 }
+
+// a grid of n points along every axis
+inline SGrid make_grid(int dim, int n) { return make_grid(dim, n, n, n); }
+
+// padded points per axis as an array (x, y, z)
+inline void grid_extent(const SGrid& g, int* q)
+{
+    q[0] = g.nx;
+    q[1] = g.ny;
+    q[2] = g.nz;
+}
+
+// Right-ghost rule of a multigrid level L >= 1 (Sec. 2.4), one per axis:
+// xn1[a] = 1 when the last active centre along axis a sits at x_MG = 1, else
+// the ghost is coef[a] times the last active value.
+struct Rule3 {
+    int xn1[3];
+    double coef[3];
+};
 
 // message returned by nested_poisson_last_error(NULL) on the calling thread
 void set_last_error(const char* msg);
@@ -54,12 +75,14 @@ void launch_level0_init(int dim, hipStream_t st, SGrid g, const double* rho0, co
                         double fourpiG, double* phi, double* f, unsigned long long* fmax);
 // fmax (may be null): device slot, zeroed by the caller, that receives the bit
 // pattern of max |f| over the level (atomic maximum)
+// (gf is the fine level's padded grid: nf_a = gf.n_a - 4 cells per axis)
 void launch_interface_fill(int dim, hipStream_t st, SGrid gc, const double* phic, const double* fc, SGrid gf,
-                           int nf, int offx, int offy, int offz, const double* rho, double fourpiG, double* phif,
+                           int offx, int offy, int offz, const double* rho, double fourpiG, double* phif,
                            double* ff, unsigned long long* fmax);
-void launch_forces(int dim, hipStream_t st, SGrid g, int n, double dx, const double* phi, double* fx, double* fy,
+// forces on Omega (g.n_a - 4 cells per axis; arrays n_z x n_y x n_x)
+void launch_forces(int dim, hipStream_t st, SGrid g, double dx, const double* phi, double* fx, double* fy,
                    double* fz);
-void launch_force_delta(int dim, hipStream_t st, SGrid g, int n, double dx, const double* phi, double* F,
+void launch_force_delta(int dim, hipStream_t st, SGrid g, double dx, const double* phi, double* F,
                         unsigned long long* maxbits);
 void launch_export(int dim, hipStream_t st, SGrid g, const double* a, double* out);
 
@@ -77,10 +100,10 @@ void launch_box_resid_norm3(hipStream_t st, SGrid g, const double* u, const doub
 // only on multigrid level 0 of the FP16-storage defect correction)
 // fine != 0: the nested-level arrays (multigrid level 0, ghost layer in
 // memory); fine == 0: a multigrid level L >= 1 whose ghost values follow the
-// rule (xn1 = x_N is 1, coef = right coefficient) where they are read
+// rule of each axis where they are read
 template <typename T>
-void launch_half_sweep(int dim, hipStream_t st, SGrid g, T* u, const T* f, int colour, double h2, int fine, int xn1,
-                       double coef);
+void launch_half_sweep(int dim, hipStream_t st, SGrid g, T* u, const T* f, int colour, double h2, int fine,
+                       const Rule3& rule);
 // Black half sweep of a 3-D multigrid level 0 (even hx, 2- or 4-byte storage)
 // whose red points hold the red half sweep from zero, (0 - h2 f) / 6, unstored:
 // the red values are formed from f
@@ -93,22 +116,23 @@ void launch_half_sweep_seeded(hipStream_t st, SGrid g, T* u, const T* f, double 
 // then does not launch
 template <typename TF, typename TC>
 void launch_resid_restrict(int dim, hipStream_t st, SGrid gf, const TF* u, const TF* f, double inv_h2, double out_scale,
-                           SGrid gc, TC* fc, TC* ec, int rule, int xn1, double coef, double seed_h2);
-// black_only != 0 corrects only the black points; (xn1, coef): the coarse level's rule
+                           SGrid gc, TC* fc, TC* ec, int rule, const Rule3& fine_rule, double seed_h2);
+// black_only != 0 corrects only the black points; coarse_rule: the coarse level's rule
 template <typename TC, typename TF>
-void launch_prolong_add(int dim, hipStream_t st, SGrid gc, const TC* ec, SGrid gf, TF* u, int black_only, int xn1,
-                        double coef);
+void launch_prolong_add(int dim, hipStream_t st, SGrid gc, const TC* ec, SGrid gf, TF* u, int black_only,
+                        const Rule3& coarse_rule);
 
-// coarse tail: levels Lt .. Lt+nlev-1 of one V-cycle (N[a], spacing h[a], rule
-// xn1[a]/coef[a]; N[nlev-1] == 1) in one workgroup with the levels in LDS;
-// reads f and writes the correction u of level Lt (grid g0).  Returns -1
-// without launching when the levels do not fit (coarse_tail_lds_bytes).
+// coarse tail: levels Lt .. Lt+nlev-1 of one V-cycle (active points N[a][axis],
+// spacing h[a], rule[a]; the last level has one point along some axis) in one
+// workgroup with the levels in LDS; reads f and writes the correction u of
+// level Lt (grid g0).  Returns -1 without launching when the levels do not fit
+// (coarse_tail_lds_bytes).
 constexpr int kTailMaxLevels = 8;
 constexpr size_t kTailLdsBytes = 64 * 1024;
-size_t coarse_tail_lds_bytes(int dim, const int* N, int nlev, size_t esz);
+size_t coarse_tail_lds_bytes(int dim, const int (*N)[3], int nlev, size_t esz);
 template <typename T>
-int launch_coarse_tail(int dim, hipStream_t st, int nlev, const int* N, const double* h, const int* xn1,
-                       const double* coef, int n_pre, int n_post, SGrid g0, const T* f0, T* u0);
+int launch_coarse_tail(int dim, hipStream_t st, int nlev, const int (*N)[3], const double* h, const Rule3* rule,
+                       int n_pre, int n_post, SGrid g0, const T* f0, T* u0);
 
 // defect correction, one fused outer pass: phi_out = phi_in + factor * e_in
 // (no update and no write of phi_out when e_in is null), r = (f - lap phi_out)
@@ -128,10 +152,11 @@ void launch_dc_scale(int dim, hipStream_t st, SGrid g, const float* r32, double 
                      int first_red);
 // ghost layer of a nested-level array copied from src to dst
 void launch_copy_ghosts(int dim, hipStream_t st, SGrid g, const double* src, double* dst);
-// dst(p) = src(p + shift) for the points p of grid gd with lo <= p_a <= hi on
-// every axis (padded indices of each grid; the caller keeps p + shift inside gs)
-void launch_copy_box(int dim, hipStream_t st, SGrid gs, const double* src, SGrid gd, double* dst, int lo, int hi,
-                     int shift);
+// dst(p) = src(p + shift) for the points p of grid gd with lo <= p_a <= hi[a]
+// on every axis (padded indices of each grid; the caller keeps p + shift
+// inside gs)
+void launch_copy_box(int dim, hipStream_t st, SGrid gs, const double* src, SGrid gd, double* dst, int lo,
+                     const int* hi, int shift);
 
 // learned initial guess network (np_net.hip); activations channel-last,
 // weights bfloat16 [27][cout][cin]
@@ -157,7 +182,7 @@ void net_mse(hipStream_t st, const float* pred, const float* target, const float
 void net_adam(hipStream_t st, float* w, const float* g, float* m, float* v, long n, float lr, float b1, float b2,
               float eps, int step, uint16_t* wb);
 void net_to_bf16(hipStream_t st, const float* a, uint16_t* b, long n);
-// solver glue on a nested level's Gamma ((n+2)^3 points)
+// solver glue on a nested level's Gamma ((n_x+2) x (n_y+2) x (n_z+2) points)
 void net_features_bf16(hipStream_t st, SGrid g, const double* phi, const double* f, double inv_fnorm, double inv_h2,
                        uint16_t* x);
 void net_features_f32(hipStream_t st, SGrid g, const double* phi, const double* f, double inv_fnorm, double inv_h2,

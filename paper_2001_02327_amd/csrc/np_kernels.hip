@@ -198,23 +198,22 @@ __global__ void __launch_bounds__(kBlock) k_level0_init(SGrid g, const double* _
                                                         double* __restrict__ phi, double* __restrict__ f,
                                                         unsigned long long* fmax)
 {
-    const long total = (long)g.nx * g.nx * g.nz;
+    const long total = (long)g.nx * g.ny * g.nz;
     const long stride = (long)gridDim.x * kBlock;
-    const int last = g.nx - 1;
     unsigned long long best = 0;
     for (long t = xcd_block() * kBlock + threadIdx.x; t < total; t += stride) {
         int pi = (int)(t % g.nx);
         long r = t / g.nx;
-        int pj = (int)(r % g.nx);
-        int pk = (int)(r / g.nx);
-        bool ring = pi == 0 || pi == last || pj == 0 || pj == last || (D == 3 && (pk == 0 || pk == last));
+        int pj = (int)(r % g.ny);
+        int pk = (int)(r / g.ny);
+        bool ring = pi == 0 || pi == g.nx - 1 || pj == 0 || pj == g.ny - 1 || (D == 3 && (pk == 0 || pk == g.nz - 1));
         size_t p = pos<D, double>(g, pi, pj, pk);
         if (ring) {
             phi[p] = phi_outer[t];
             f[p] = 0.0;
         } else {
-            int m = g.nx - 2;
-            size_t ri = D == 3 ? (((size_t)(pk - 1) * m + (pj - 1)) * m + (pi - 1)) : ((size_t)(pj - 1) * m + (pi - 1));
+            const int mx = g.nx - 2, my = g.ny - 2;
+            size_t ri = D == 3 ? (((size_t)(pk - 1) * my + (pj - 1)) * mx + (pi - 1)) : ((size_t)(pj - 1) * mx + (pi - 1));
             const double v = fourpiG * rho0[ri];
             if (kFillNt) {
                 store_nt(phi + p, 0.0);
@@ -261,33 +260,33 @@ __device__ __forceinline__ double interp_tensor(const double* __restrict__ c, co
 // interpolated; Omega^l takes 4 pi G rho from the caller (n^d points).
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_interface_fill(SGrid gc, const double* __restrict__ phic,
-                                                           const double* __restrict__ fc, SGrid gf, int nf, int offx,
+                                                           const double* __restrict__ fc, SGrid gf, int offx,
                                                            int offy, int offz, const double* __restrict__ rho,
                                                            double fourpiG, double* __restrict__ phif,
                                                            double* __restrict__ ff, unsigned long long* fmax)
 {
     long t = xcd_block() * kBlock + threadIdx.x;
-    long total = (long)gf.nx * gf.nx * gf.nz;
+    long total = (long)gf.nx * gf.ny * gf.nz;
+    const int nfx = gf.nx - 4, nfy = gf.ny - 4, nfz = gf.nz - 4;
     unsigned long long best = 0;
     if (t < total) {
     int pi = (int)(t % gf.nx);
     long r = t / gf.nx;
-    int pj = (int)(r % gf.nx);
-    int pk = (int)(r / gf.nx);
+    int pj = (int)(r % gf.ny);
+    int pk = (int)(r / gf.ny);
     int qi, qj, qk = 0, si, sj, sk = 1;
     fine_to_coarse(pi, offx, qi, si);
     fine_to_coarse(pj, offy, qj, sj);
     if (D == 3) fine_to_coarse(pk, offz, qk, sk);
     size_t p = pos<D, double>(gf, pi, pj, pk);
     phif[p] = interp_tensor<D>(phic, gc, qi, qj, qk, si, sj, sk);
-    int last = gf.nx - 1;
-    bool outer = pi == 0 || pi == last || pj == 0 || pj == last || (D == 3 && (pk == 0 || pk == last));
-    bool omega = pi >= 2 && pi <= nf + 1 && pj >= 2 && pj <= nf + 1 && (D == 2 || (pk >= 2 && pk <= nf + 1));
+    bool outer = pi == 0 || pi == gf.nx - 1 || pj == 0 || pj == gf.ny - 1 || (D == 3 && (pk == 0 || pk == gf.nz - 1));
+    bool omega = pi >= 2 && pi <= nfx + 1 && pj >= 2 && pj <= nfy + 1 && (D == 2 || (pk >= 2 && pk <= nfz + 1));
     double v;
     if (outer) {
         v = 0.0;
     } else if (omega) {
-        size_t ri = D == 3 ? (((size_t)(pk - 2) * nf + (pj - 2)) * nf + (pi - 2)) : ((size_t)(pj - 2) * nf + (pi - 2));
+        size_t ri = D == 3 ? (((size_t)(pk - 2) * nfy + (pj - 2)) * nfx + (pi - 2)) : ((size_t)(pj - 2) * nfx + (pi - 2));
         v = fourpiG * rho[ri];
     } else {
         v = interp_tensor<D>(fc, gc, qi, qj, qk, si, sj, sk);
@@ -308,22 +307,23 @@ __global__ void __launch_bounds__(kBlock) k_interface_fill(SGrid gc, const doubl
 constexpr int kFillChunk = 8;
 
 __global__ void __launch_bounds__(kBlock) k_interface_fill3_zm(SGrid gc, const double* __restrict__ phic,
-                                                               const double* __restrict__ fc, SGrid gf, int nf,
+                                                               const double* __restrict__ fc, SGrid gf,
                                                                int offx, int offy, int offz,
                                                                const double* __restrict__ rho, double fourpiG,
                                                                double* __restrict__ phif, double* __restrict__ ff,
                                                                int pblocks, unsigned long long* fmax)
 {
-    const int Mq = (gf.nx + 1) / 2;  // parents per axis: fine padded points 0 .. nf + 3 in pairs
+    // parents per axis: fine padded points 0 .. n_a + 3 in pairs
+    const int Mx = (gf.nx + 1) / 2, My = (gf.ny + 1) / 2, Mz = (gf.nz + 1) / 2;
+    const int nfx = gf.nx - 4, nfy = gf.ny - 4, nfz = gf.nz - 4;
     const int lb = (int)xcd_block();
     const int zc = lb / pblocks;
     const int t = (lb - zc * pblocks) * kBlock + (int)threadIdx.x;
     unsigned long long best = 0;  // max |f| written (the outer layer's 0 does not raise it)
-    if (t < Mq * Mq) {
-    const int a = (int)(t % Mq), b = (int)(t / Mq);
-    const int c0 = zc * kFillChunk, c1 = min(c0 + kFillChunk, Mq) - 1;
+    if (t < Mx * My) {
+    const int a = (int)(t % Mx), b = (int)(t / Mx);
+    const int c0 = zc * kFillChunk, c1 = min(c0 + kFillChunk, Mz) - 1;
     const int qi = offx + 1 + a, qj = offy + 1 + b;
-    const int last = gf.nx - 1;
     double cv[3][3][3];  // [z][y][x]: coarse planes qk-1 .. qk+1, rows qj-1 .., columns qi-1 ..
     auto load_plane = [&](int qk, double (&pl)[3][3]) {
 #pragma unroll
@@ -349,23 +349,24 @@ __global__ void __launch_bounds__(kBlock) k_interface_fill3_zm(SGrid gc, const d
 #pragma unroll
                 for (int dx = 0; dx < 2; dx++) {
                     const int pi = 2 * a + dx, pj = 2 * b + dy, pk = 2 * cc + dz;
-                    const bool omega = pi >= 2 && pi <= nf + 1 && pj >= 2 && pj <= nf + 1 && pk >= 2 && pk <= nf + 1;
-                    rv[dz][dy][dx] = omega ? rho[((size_t)(pk - 2) * nf + (pj - 2)) * nf + (pi - 2)] : 0.0;
+                    const bool omega =
+                        pi >= 2 && pi <= nfx + 1 && pj >= 2 && pj <= nfy + 1 && pk >= 2 && pk <= nfz + 1;
+                    rv[dz][dy][dx] = omega ? rho[((size_t)(pk - 2) * nfy + (pj - 2)) * nfx + (pi - 2)] : 0.0;
                 }
 #pragma unroll
         for (int dz = 0; dz < 2; dz++) {
             const int pk = 2 * cc + dz;
-            if (pk > last) continue;
+            if (pk > gf.nz - 1) continue;
             const int zs = dz ? 2 : 0;  // side of the fine centre: -1 for d = 0, +1 for d = 1
 #pragma unroll
             for (int dy = 0; dy < 2; dy++) {
                 const int pj = 2 * b + dy;
-                if (pj > last) continue;
+                if (pj > gf.ny - 1) continue;
                 const int ys = dy ? 2 : 0;
 #pragma unroll
                 for (int dx = 0; dx < 2; dx++) {
                     const int pi = 2 * a + dx;
-                    if (pi > last) continue;
+                    if (pi > gf.nx - 1) continue;
                     const int xs = dx ? 2 : 0;
                     const double y0 = w0 * cv[1][1][1] + w1 * cv[1][1][xs];
                     const double y1 = w0 * cv[1][ys][1] + w1 * cv[1][ys][xs];
@@ -375,8 +376,10 @@ __global__ void __launch_bounds__(kBlock) k_interface_fill3_zm(SGrid gc, const d
                     const double z1 = w0 * y2 + w1 * y3;
                     const size_t p = pos<3, double>(gf, pi, pj, pk);
                     phif[p] = w0 * z0 + w1 * z1;
-                    const bool outer = pi == 0 || pi == last || pj == 0 || pj == last || pk == 0 || pk == last;
-                    const bool omega = pi >= 2 && pi <= nf + 1 && pj >= 2 && pj <= nf + 1 && pk >= 2 && pk <= nf + 1;
+                    const bool outer = pi == 0 || pi == gf.nx - 1 || pj == 0 || pj == gf.ny - 1 || pk == 0 ||
+                                       pk == gf.nz - 1;
+                    const bool omega =
+                        pi >= 2 && pi <= nfx + 1 && pj >= 2 && pj <= nfy + 1 && pk >= 2 && pk <= nfz + 1;
                     double v;
                     if (outer) {
                         v = 0.0;
@@ -417,13 +420,13 @@ __global__ void __launch_bounds__(kBlock) k_interface_fill3_zm(SGrid gc, const d
 constexpr int kFillPairChunk = 4;  // fine-plane pairs per thread
 
 __global__ void __launch_bounds__(kBlock) k_interface_fill3_pair(SGrid gc, const double* __restrict__ phic,
-                                                                 const double* __restrict__ fc, SGrid gf, int nf,
+                                                                 const double* __restrict__ fc, SGrid gf,
                                                                  int offx, int offy, int offz,
                                                                  const double* __restrict__ rho, double fourpiG,
                                                                  double* __restrict__ phif, double* __restrict__ ff,
                                                                  int pblocks, unsigned long long* fmax)
 {
-    const int nx = gf.nx, last = nx - 1;
+    const int nfx = gf.nx - 4, nfy = gf.ny - 4, nfz = gf.nz - 4;
     const int lb = (int)xcd_block();
     const int zc = lb / pblocks;
     const int t = (lb - zc * pblocks) * kBlock + (int)threadIdx.x;
@@ -431,9 +434,9 @@ __global__ void __launch_bounds__(kBlock) k_interface_fill3_pair(SGrid gc, const
     const int pj = q / gf.hx;
     const int h0 = q - pj * gf.hx;
     unsigned long long best = 0;  // max |f| written (the outer layer's 0 does not raise it)
-    if (pj < nx) {
+    if (pj < gf.ny) {
         const int c0 = -1 + zc * kFillPairChunk;
-        const int c1 = min(c0 + kFillPairChunk, nx / 2 - 1);  // pairs c0 .. c1 - 1
+        const int c1 = min(c0 + kFillPairChunk, gf.nz / 2 - 1);  // pairs c0 .. c1 - 1
         const int fyy = pj - 2;
         const int qy = offy + 2 + (fyy >> 1), sy = (fyy & 1) ? 1 : -1;
         const int cxb = offx + h0;  // coarse columns cxb .. cxb + 3
@@ -470,7 +473,7 @@ __global__ void __launch_bounds__(kBlock) k_interface_fill3_pair(SGrid gc, const
         load_X(offz + 1 + c0, Xm);
         load_X(offz + 2 + c0, X0);
         load_X(offz + 3 + c0, Xp);
-        const bool yomega = pj >= 2 && pj <= nf + 1;
+        const bool yomega = pj >= 2 && pj <= nfy + 1;
         const size_t prow = (size_t)pj * gf.hx + h0;
         for (int c = c0; c < c1; c++) {
             const int qk = offz + 2 + c;
@@ -479,17 +482,17 @@ __global__ void __launch_bounds__(kBlock) k_interface_fill3_pair(SGrid gc, const
 #pragma unroll
             for (int d = 0; d < 2; d++) {
                 const int p = 2 * c + 2 + d;  // fine plane; its side coarse plane is qk - 1 (d = 0) or qk + 1
-                const bool omega_row = yomega && p >= 2 && p <= nf + 1;
+                const bool omega_row = yomega && p >= 2 && p <= nfz + 1;
                 double rv[4] = {0.0, 0.0, 0.0, 0.0};
                 if (omega_row) {
                     const int x0 = 2 * h0 - 2;  // natural x of the pair's first point
-                    const double* __restrict__ rr = rho + ((size_t)(p - 2) * nf + (pj - 2)) * nf;
-                    if (x0 >= 0 && x0 + 1 <= nf - 1) {
+                    const double* __restrict__ rr = rho + ((size_t)(p - 2) * nfy + (pj - 2)) * nfx;
+                    if (x0 >= 0 && x0 + 1 <= nfx - 1) {
                         const Pair<double> v = *(const Pair<double>*)(rr + x0);
                         rv[0] = v.a;
                         rv[1] = v.b;
                     }
-                    if (x0 + 2 >= 0 && x0 + 3 <= nf - 1) {
+                    if (x0 + 2 >= 0 && x0 + 3 <= nfx - 1) {
                         const Pair<double> v = *(const Pair<double>*)(rr + x0 + 2);
                         rv[2] = v.a;
                         rv[3] = v.b;
@@ -503,8 +506,9 @@ __global__ void __launch_bounds__(kBlock) k_interface_fill3_pair(SGrid gc, const
                     const double z1 = w0 * S[0][a] + w1 * S[1][a];
                     ph[a] = w0 * z0 + w1 * z1;
                     const int pi = 2 * h0 + a;
-                    const bool outer = pi == 0 || pi == last || pj == 0 || pj == last || p == 0 || p == last;
-                    const bool omega = omega_row && pi >= 2 && pi <= nf + 1;
+                    const bool outer =
+                        pi == 0 || pi == gf.nx - 1 || pj == 0 || pj == gf.ny - 1 || p == 0 || p == gf.nz - 1;
+                    const bool omega = omega_row && pi >= 2 && pi <= nfx + 1;
                     double v;
                     if (outer) {
                         v = 0.0;
@@ -564,20 +568,21 @@ __device__ __forceinline__ double d4(const double* __restrict__ phi, const SGrid
 }
 
 template <int D>
-__global__ void __launch_bounds__(kBlock) k_forces(SGrid g, int n, double m12dx, const double* __restrict__ phi,
+__global__ void __launch_bounds__(kBlock) k_forces(SGrid g, double m12dx, const double* __restrict__ phi,
                                                    double* __restrict__ fx, double* __restrict__ fy,
                                                    double* __restrict__ fz, Strip sp)
 {
+    const int nx = g.nx - 4, ny = g.ny - 4;
     int i, j, k = 0;
     long t;
     if (D == 3) {
         if (!strip_point(sp, i, j, k)) return;
-        t = ((long)k * n + j) * n + i;
+        t = ((long)k * ny + j) * nx + i;
     } else {
         t = xcd_block() * kBlock + threadIdx.x;
-        if (t >= (long)n * n) return;
-        i = (int)(t % n);
-        j = (int)(t / n);
+        if (t >= (long)nx * ny) return;
+        i = (int)(t % nx);
+        j = (int)(t / nx);
     }
     int pi = i + 2, pj = j + 2, pk = D == 3 ? k + 2 : 0;
     fx[t] = d4<D>(phi, g, pi, pj, pk, 0, m12dx);
@@ -596,24 +601,25 @@ __global__ void __launch_bounds__(kBlock) k_forces(SGrid g, int n, double m12dx,
 constexpr int kForceChunk = 8;
 constexpr int kForceRows = 4;
 
-__global__ void __launch_bounds__(kForceBlock) k_forces3_zm(SGrid g, int n, double m12dx, const double* __restrict__ phi,
+__global__ void __launch_bounds__(kForceBlock) k_forces3_zm(SGrid g, double m12dx, const double* __restrict__ phi,
                                                        double* __restrict__ fx, double* __restrict__ fy,
                                                        double* __restrict__ fz, int pblocks)
 {
     constexpr int R = kForceRows;
     constexpr int KC = kForceChunk;
-    const int nrb = (n + R - 1) / R;
+    const int nx = g.nx - 4, ny = g.ny - 4, nz = g.nz - 4;
+    const int nrb = (ny + R - 1) / R;
     const int lb = (int)xcd_block();
     const int zc = lb / pblocks;
     const int t = (lb - zc * pblocks) * kForceBlock + (int)threadIdx.x;
-    if (t >= (long)n * nrb) return;
-    const int i = (int)(t % n), j0 = R * (int)(t / n);
+    if (t >= (long)nx * nrb) return;
+    const int i = (int)(t % nx), j0 = R * (int)(t / nx);
     const int k0 = zc * KC;
-    const int nk = min(KC, n - k0);
+    const int nk = min(KC, nz - k0);
     const int pi = i + 2;
     // padded rows j0 + 2 - 2 .. j0 + 2 + R + 1: the thread's rows and two on each side
     // (rows past the array are clamped; they are never differenced)
-    auto prow = [&](int q) { return min(j0 + q, n + 3); };  // q = 0 .. R + 3
+    auto prow = [&](int q) { return min(j0 + q, ny + 3); };  // q = 0 .. R + 3
     double col[R][KC + 4];  // padded planes k0 .. k0 + nk + 3 of each of the thread's rows
     double xm1[R][KC], xp1[R][KC], xm2[R][KC], xp2[R][KC];
     double yh[4][KC];       // rows j0, j0 + 1 (below) and j0 + R + 2, j0 + R + 3 (above), padded
@@ -651,8 +657,8 @@ __global__ void __launch_bounds__(kForceBlock) k_forces3_zm(SGrid g, int n, doub
         if (q < nk) {
 #pragma unroll
             for (int r = 0; r < R; r++) {
-                if (j0 + r >= n) continue;
-                const long o = ((long)(k0 + q) * n + (j0 + r)) * n + i;
+                if (j0 + r >= ny) continue;
+                const long o = ((long)(k0 + q) * ny + (j0 + r)) * nx + i;
                 const int w = r + 2;
                 store_nt(fx + o, (8.0 * (xp1[r][q] - xm1[r][q]) - (xp2[r][q] - xm2[r][q])) * m12dx);
                 store_nt(fy + o, (8.0 * (yv(w + 1, q) - yv(w - 1, q)) - (yv(w + 2, q) - yv(w - 2, q))) * m12dx);
@@ -665,17 +671,18 @@ __global__ void __launch_bounds__(kForceBlock) k_forces3_zm(SGrid g, int n, doub
 // Forces into F (d arrays of n^d) and the maximum change against the values
 // F held before (the stop rule of Sec. 3.1).
 template <int D>
-__global__ void __launch_bounds__(kBlock) k_force_delta(SGrid g, int n, double m12dx, const double* __restrict__ phi,
+__global__ void __launch_bounds__(kBlock) k_force_delta(SGrid g, double m12dx, const double* __restrict__ phi,
                                                         double* __restrict__ F, unsigned long long* maxbits)
 {
+    const int nx = g.nx - 4, ny = g.ny - 4, nz = D == 3 ? g.nz - 4 : 1;
     long t = xcd_block() * kBlock + threadIdx.x;
-    long total = D == 3 ? (long)n * n * n : (long)n * n;
+    long total = (long)nx * ny * nz;
     unsigned long long m = 0;
     if (t < total) {
-        int i = (int)(t % n);
-        long r = t / n;
-        int j = (int)(r % n);
-        int k = (int)(r / n);
+        int i = (int)(t % nx);
+        long r = t / nx;
+        int j = (int)(r % ny);
+        int k = (int)(r / ny);
         int pi = i + 2, pj = j + 2, pk = D == 3 ? k + 2 : 0;
         for (int ax = 0; ax < D; ax++) {
             double v = d4<D>(phi, g, pi, pj, pk, ax, m12dx);
@@ -692,12 +699,12 @@ template <int D>
 __global__ void __launch_bounds__(kBlock) k_export(SGrid g, const double* __restrict__ a, double* __restrict__ out)
 {
     long t = xcd_block() * kBlock + threadIdx.x;
-    long total = (long)g.nx * g.nx * g.nz;
+    long total = (long)g.nx * g.ny * g.nz;
     if (t >= total) return;
     int pi = (int)(t % g.nx);
     long r = t / g.nx;
-    int pj = (int)(r % g.nx);
-    int pk = (int)(r / g.nx);
+    int pj = (int)(r % g.ny);
+    int pk = (int)(r / g.ny);
     out[t] = at<D>(a, g, pi, pj, pk);
 }
 
@@ -708,16 +715,16 @@ template <int D>
 __global__ void __launch_bounds__(kBlock) k_norm(SGrid g, const double* __restrict__ u, const double* __restrict__ f,
                                                  double inv_h2, int mode, unsigned long long* maxbits)
 {
-    int m = g.nx - 2;
-    long total = (long)g.hx * m * (D == 3 ? m : 1);
+    const int my = g.ny - 2, mz = g.nz - 2;
+    long total = (long)g.hx * my * (D == 3 ? mz : 1);
     long stride = (long)gridDim.x * kBlock;
     size_t ny = (size_t)g.hx, nz = g.ps;
     unsigned long long best = 0;
     for (long t = xcd_block() * kBlock + threadIdx.x; t < total; t += stride) {
         int h = (int)(t % g.hx);
         long r = t / g.hx;
-        int pj = 1 + (int)(r % m);
-        int pk = D == 3 ? 1 + (int)(r / m) : 0;
+        int pj = 1 + (int)(r % my);
+        int pk = D == 3 ? 1 + (int)(r / my) : 0;
         size_t row = row_base(g, pj, pk);
         for (int c = 0; c < 2; c++) {
             int pi = 2 * h + ((c + pj + pk + D) & 1);
@@ -733,9 +740,9 @@ __global__ void __launch_bounds__(kBlock) k_norm(SGrid g, const double* __restri
                 if (pi - 1 == 0) s += o[row + ((pi - 1) >> 1)];
                 if (pi + 1 == g.nx - 1) s += o[row + ((pi + 1) >> 1)];
                 if (pj - 1 == 0) s += o[row - ny + h];
-                if (pj + 1 == g.nx - 1) s += o[row + ny + h];
+                if (pj + 1 == g.ny - 1) s += o[row + ny + h];
                 if (D == 3 && pk - 1 == 0) s += o[row - nz + h];
-                if (D == 3 && pk + 1 == g.nx - 1) s += o[row + nz + h];
+                if (D == 3 && pk + 1 == g.nz - 1) s += o[row + nz + h];
                 val = f[self] - s * inv_h2;
             } else {
                 double s = o[row + ((pi - 1) >> 1)];
@@ -765,7 +772,7 @@ __global__ void __launch_bounds__(kBlock) k_resid_norm3(SGrid g, const double* _
                                                         const double* __restrict__ f, double inv_h2, int pblocks,
                                                         unsigned long long* maxbits)
 {
-    const int m = g.nx - 2;
+    const int my = g.ny - 2, mz = g.nz - 2;
     const int lb = (int)xcd_block();
     const int zc = lb / pblocks;
     const int t = (lb - zc * pblocks) * kBlock + (int)threadIdx.x;
@@ -774,9 +781,9 @@ __global__ void __launch_bounds__(kBlock) k_resid_norm3(SGrid g, const double* _
     // rows and the padding have no work
     const int pj = t / g.hx;
     const int h = t - pj * g.hx;
-    if (pj >= 1 && pj <= m) {
+    if (pj >= 1 && pj <= my) {
         const int k0 = 1 + zc * kNormChunk;
-        const int k1 = min(k0 + kNormChunk - 1, m);
+        const int k1 = min(k0 + kNormChunk - 1, mz);
         const size_t plane = g.ps;
         const size_t col = (size_t)pj * g.hx + h;
         const double* __restrict__ a[2] = {u, u + g.cs};
@@ -822,25 +829,26 @@ __global__ void __launch_bounds__(kBlock) k_resid_norm3(SGrid g, const double* _
 constexpr int kBox = 4;
 
 __global__ void __launch_bounds__(kBlock) k_box_resid_norm3(SGrid g, const double* __restrict__ u,
-                                                            const double* __restrict__ f, double inv_h2, int nbx,
+                                                            const double* __restrict__ f, double inv_h2,
                                                             unsigned long long* maxbits)
 {
-    const int m = g.nx - 2;
+    const int mx = g.nx - 2, my = g.ny - 2, mz = g.nz - 2;
+    const int nbx = (mx + kBox - 1) / kBox, nby = (my + kBox - 1) / kBox, nbz = (mz + kBox - 1) / kBox;
     const long t = xcd_block() * kBlock + threadIdx.x;
     unsigned long long best = 0;
-    if (t < (long)nbx * nbx * nbx) {
-        const int bx = (int)(t % nbx), by = (int)((t / nbx) % nbx), bz = (int)(t / ((long)nbx * nbx));
+    if (t < (long)nbx * nby * nbz) {
+        const int bx = (int)(t % nbx), by = (int)((t / nbx) % nby), bz = (int)(t / ((long)nbx * nby));
         {
             double sum = 0.0;
             for (int dz = 0; dz < kBox; dz++) {
                 const int pk = 1 + kBox * bz + dz;
-                if (pk > m) break;
+                if (pk > mz) break;
                 for (int dy = 0; dy < kBox; dy++) {
                     const int pj = 1 + kBox * by + dy;
-                    if (pj > m) break;
+                    if (pj > my) break;
                     for (int dx = 0; dx < kBox; dx++) {
                         const int pi = 1 + kBox * bx + dx;
-                        if (pi > m) break;
+                        if (pi > mx) break;
                         double s6 = at<3>(u, g, pi - 1, pj, pk) + at<3>(u, g, pi + 1, pj, pk);
                         s6 = s6 + at<3>(u, g, pi, pj - 1, pk);
                         s6 = s6 + at<3>(u, g, pi, pj + 1, pk);
@@ -879,9 +887,15 @@ struct Compute<__half> { using type = float; };
 // which has the other colour, and neither changes before p's own update.
 template <typename C>
 struct GRule {
-    int xn1;
-    C coef;
+    int xn1[3];  // per axis: the last active centre sits at x_MG = 1
+    C coef[3];   // per axis: the right-ghost coefficient otherwise
 };
+
+template <typename C>
+GRule<C> grule(const Rule3& r)
+{
+    return GRule<C>{{r.xn1[0], r.xn1[1], r.xn1[2]}, {(C)r.coef[0], (C)r.coef[1], (C)r.coef[2]}};
+}
 
 // Value at padded point p of a level with a rule ghost layer (any point, ghost
 // along any number of axes).  Factors are applied per axis in x, y, z order.
@@ -889,18 +903,19 @@ template <int D, typename T, typename C>
 __device__ __forceinline__ C rule_at(const T* __restrict__ a, const SGrid& g, int pi, int pj, int pk,
                                      const GRule<C>& gr)
 {
-    const int N = g.nx - 2;
+    const int Na[3] = {g.nx - 2, g.ny - 2, g.nz - 2};
     int p[3] = {pi, pj, pk};
     C fac[3] = {(C)1, (C)1, (C)1};
     bool sc[3] = {false, false, false};
     for (int ax = 0; ax < D; ax++) {
+        const int N = Na[ax];
         if (p[ax] == 0) {
             p[ax] = 1;
             fac[ax] = (C)-1;
             sc[ax] = true;
         } else if (p[ax] == N + 1) {
-            p[ax] = gr.xn1 ? N - 1 : N;
-            fac[ax] = gr.xn1 ? (C)-1 : gr.coef;
+            p[ax] = gr.xn1[ax] ? N - 1 : N;
+            fac[ax] = gr.xn1[ax] ? (C)-1 : gr.coef[ax];
             sc[ax] = true;
         }
     }
@@ -911,13 +926,13 @@ __device__ __forceinline__ C rule_at(const T* __restrict__ a, const SGrid& g, in
 }
 
 // Face-ghost substitution for a 7-point stencil at active index q (1..N) along
-// one axis: the neighbour below (q = 1) is -self; the neighbour above (q = N)
+// axis ax: the neighbour below (q = 1) is -self; the neighbour above (q = N)
 // is -(the neighbour below) when x_N = 1, else coef * self.
 template <typename C>
-__device__ __forceinline__ void rule_pair(int q, int N, C self, C& lo, C& hi, const GRule<C>& gr)
+__device__ __forceinline__ void rule_pair(int q, int N, C self, C& lo, C& hi, const GRule<C>& gr, int ax)
 {
     if (q == 1) lo = -self;
-    if (q == N) hi = gr.xn1 ? -lo : gr.coef * self;
+    if (q == N) hi = gr.xn1[ax] ? -lo : gr.coef[ax] * self;
 }
 
 // Red-black Gauss-Seidel half sweep: u_c = (sum of the 2d neighbours - h^2 f_c) / (2d)
@@ -932,13 +947,13 @@ __device__ __forceinline__ void half_sweep_body(T* __restrict__ u, const T* __re
 {
     using C = typename Compute<T>::type;
     long t = xcd_block() * kBlock + threadIdx.x;
-    int m = g.nx - 2;
-    long total = (long)g.hx * m * (D == 3 ? m : 1);
+    const int my = g.ny - 2, mz = g.nz - 2;
+    long total = (long)g.hx * my * (D == 3 ? mz : 1);
     if (t >= total) return;
     int h = (int)(t % g.hx);
     long r = t / g.hx;
-    int pj = 1 + (int)(r % m);
-    int pk = D == 3 ? 1 + (int)(r / m) : 0;
+    int pj = 1 + (int)(r % my);
+    int pk = D == 3 ? 1 + (int)(r / my) : 0;
     int pi = 2 * h + ((colour + pj + pk + D) & 1);
     if (pi < 1 || pi > g.nx - 2) return;
     const T* __restrict__ o = u + (size_t)(colour ^ 1) * g.cs;
@@ -953,12 +968,12 @@ __device__ __forceinline__ void half_sweep_body(T* __restrict__ u, const T* __re
         zp = (C)o[row + nz + h];
     }
     if (RULE) {
-        const int N = g.nx - 2;
-        if (pi == 1 || pi == N || pj == 1 || pj == N || (D == 3 && (pk == 1 || pk == N))) {
+        const int Nx = g.nx - 2;
+        if (pi == 1 || pi == Nx || pj == 1 || pj == my || (D == 3 && (pk == 1 || pk == mz))) {
             const C me = (C)u[self];
-            rule_pair(pi, N, me, xm, xp, gr);
-            rule_pair(pj, N, me, ym, yp, gr);
-            if (D == 3) rule_pair(pk, N, me, zm, zp, gr);
+            rule_pair(pi, Nx, me, xm, xp, gr, 0);
+            rule_pair(pj, my, me, ym, yp, gr, 1);
+            if (D == 3) rule_pair(pk, mz, me, zm, zp, gr, 2);
         }
     }
     C s = xm + xp;
@@ -976,7 +991,7 @@ template <int D, typename T>
 __global__ void __launch_bounds__(kBlock) k_smooth_fine(T* __restrict__ u, const T* __restrict__ f, SGrid g, int colour,
                                                         typename Compute<T>::type h2, typename Compute<T>::type inv2d)
 {
-    half_sweep_body<D, T, false>(u, f, g, colour, h2, inv2d, GRule<typename Compute<T>::type>{0, 0});
+    half_sweep_body<D, T, false>(u, f, g, colour, h2, inv2d, GRule<typename Compute<T>::type>{});
 }
 
 // 3-D level-0 half sweep marching along z.  A thread owns one compact (h, pj)
@@ -1005,16 +1020,16 @@ __global__ void __launch_bounds__(kBlock) k_smooth_zmarch3(T* __restrict__ u, co
     constexpr bool RULE = TAG == 1;
     constexpr int kZChunk = TAG == 0 ? kZChunk0 : kZChunk1;
     constexpr int kZGroup = kZChunk;  // planes whose loads are issued together
-    const int m = g.nx - 2;
+    const int mx = g.nx - 2, my = g.ny - 2, mz = g.nz - 2;
     const int lb = zmarch_block(TAG == 0 ? colour : 0);  // level 0: red half sweeps up, black down
     const int zc = lb / pblocks;
     const int t = (lb - zc * pblocks) * kBlock + (int)threadIdx.x;
     // flat index over the whole (padded) plane: aligned wave segments
     const int pj = t / g.hx;
     const int h = t - pj * g.hx;
-    if (pj < 1 || pj > m) return;
+    if (pj < 1 || pj > my) return;
     const int k0 = 1 + zc * kZChunk;
-    const int k1 = min(k0 + kZChunk - 1, m);
+    const int k1 = min(k0 + kZChunk - 1, mz);
     const size_t plane = g.ps;
     const size_t col = (size_t)pj * g.hx + h;  // offset of (h, pj) inside a plane
     const T* __restrict__ o = u + (size_t)(colour ^ 1) * g.cs;
@@ -1056,17 +1071,17 @@ __global__ void __launch_bounds__(kBlock) k_smooth_zmarch3(T* __restrict__ u, co
                 const C nb = par ? dpp_next(cur) : dpp_prev(cur);
                 if (!own_load(par)) xo[q] = nb;
             }
-            if (pi >= 1 && pi <= g.nx - 2) {
+            if (pi >= 1 && pi <= mx) {
                 C xm = par ? cur : xo[q];
                 C xp = par ? xo[q] : cur;
                 C y0 = ym[q], y1 = yp[q], z0 = below, z1 = ab[q];
                 if (RULE) {
                     const int kk = pk + q;
-                    if (pi == 1 || pi == m || pj == 1 || pj == m || kk == 1 || kk == m) {
+                    if (pi == 1 || pi == mx || pj == 1 || pj == my || kk == 1 || kk == mz) {
                         const C me = (C)uc[here];
-                        rule_pair(pi, m, me, xm, xp, gr);
-                        rule_pair(pj, m, me, y0, y1, gr);
-                        rule_pair(kk, m, me, z0, z1, gr);
+                        rule_pair(pi, mx, me, xm, xp, gr, 0);
+                        rule_pair(pj, my, me, y0, y1, gr, 1);
+                        rule_pair(kk, mz, me, z0, z1, gr, 2);
                     }
                 }
                 C s = xm + xp;
@@ -1085,17 +1100,17 @@ __global__ void __launch_bounds__(kBlock) k_smooth_zmarch3(T* __restrict__ u, co
         C above = (C)o[here + plane];
         const int par = (colour + pj + pk + 3) & 1;  // pi = 2h + par
         const int pi = 2 * h + par;
-        if (pi >= 1 && pi <= g.nx - 2) {
+        if (pi >= 1 && pi <= mx) {
             // x-neighbours pi-1, pi+1: compact h-1 and h (par 0) or h and h+1 (par 1)
             C xm = par ? cur : (C)o[here - 1];
             C xp = par ? (C)o[here + 1] : cur;
             C y0 = (C)o[here - g.hx], y1 = (C)o[here + g.hx], z0 = below, z1 = above;
             if (RULE) {
-                if (pi == 1 || pi == m || pj == 1 || pj == m || pk == 1 || pk == m) {
+                if (pi == 1 || pi == mx || pj == 1 || pj == my || pk == 1 || pk == mz) {
                     const C me = (C)uc[here];
-                    rule_pair(pi, m, me, xm, xp, gr);
-                    rule_pair(pj, m, me, y0, y1, gr);
-                    rule_pair(pk, m, me, z0, z1, gr);
+                    rule_pair(pi, mx, me, xm, xp, gr, 0);
+                    rule_pair(pj, my, me, y0, y1, gr, 1);
+                    rule_pair(pk, mz, me, z0, z1, gr, 2);
                 }
             }
             C s = xm + xp;
@@ -1173,7 +1188,7 @@ __global__ void __launch_bounds__(kSmoothPairBlock) k_smooth_zmarch3_pair(T* __r
         }
         return v;
     };
-    const int m = g.nx - 2;
+    const int my = g.ny - 2, mz = g.nz - 2;
     const int lb = zmarch_block(colour);  // red half sweeps up, black down
     const int zc = lb / pblocks;
     const int t = (lb - zc * pblocks) * kSmoothPairBlock + (int)threadIdx.x;
@@ -1183,10 +1198,10 @@ __global__ void __launch_bounds__(kSmoothPairBlock) k_smooth_zmarch3_pair(T* __r
     const int q = 2 * t;
     const int pj = q / g.hx;
     const int h0 = q - pj * g.hx;
-    if (pj < 1 || pj > m) return;
+    if (pj < 1 || pj > my) return;
     constexpr int kZChunk = kZChunk0;
     const int k0 = 1 + zc * kZChunk;
-    const int k1 = min(k0 + kZChunk - 1, m);
+    const int k1 = min(k0 + kZChunk - 1, mz);
     const size_t plane = g.ps;
     const size_t col = (size_t)pj * g.hx + h0;
     const T* __restrict__ o = (SEED ? f : u) + (size_t)(colour ^ 1) * g.cs;
@@ -1340,20 +1355,21 @@ __global__ void __launch_bounds__(kBlock) k_resid_restrict(const TF* __restrict_
                                                            typename Compute<TC>::type inv2d)
 {
     using C = typename Compute<TC>::type;
-    int Nc = gc.nx - 2, Nf = gf.nx - 2;
+    const int Ncx = gc.nx - 2, Ncy = gc.ny - 2, Ncz = gc.nz - 2;
+    const int Nfx = gf.nx - 2, Nfy = gf.ny - 2, Nfz = gf.nz - 2;
     long t = xcd_block() * kBlock + threadIdx.x;
-    long total = D == 3 ? (long)Nc * Nc * Nc : (long)Nc * Nc;
+    long total = D == 3 ? (long)Ncx * Ncy * Ncz : (long)Ncx * Ncy;
     if (t >= total) return;
-    int I = 1 + (int)(t % Nc);
-    long r = t / Nc;
-    int J = 1 + (int)(r % Nc);
-    int K = D == 3 ? 1 + (int)(r / Nc) : 0;
+    int I = 1 + (int)(t % Ncx);
+    long r = t / Ncx;
+    int J = 1 + (int)(r % Ncy);
+    int K = D == 3 ? 1 + (int)(r / Ncy) : 0;
     C sum = 0;
     int k0 = D == 3 ? 2 * K - 1 : 0, k1 = D == 3 ? 2 * K : 0;
     for (int k = k0; k <= k1; k++)
         for (int j = 2 * J - 1; j <= 2 * J; j++)
             for (int i = 2 * I - 1; i <= 2 * I; i++) {
-                if (i > Nf || j > Nf || (D == 3 && k > Nf)) continue;
+                if (i > Nfx || j > Nfy || (D == 3 && k > Nfz)) continue;
                 C xm = (C)at<D>(u, gf, i - 1, j, k), xp = (C)at<D>(u, gf, i + 1, j, k);
                 C ym = (C)at<D>(u, gf, i, j - 1, k), yp = (C)at<D>(u, gf, i, j + 1, k);
                 C zm = 0, zp = 0;
@@ -1363,9 +1379,9 @@ __global__ void __launch_bounds__(kBlock) k_resid_restrict(const TF* __restrict_
                 }
                 C uc = (C)at<D>(u, gf, i, j, k);
                 if (RULE) {
-                    rule_pair(i, Nf, uc, xm, xp, gr);
-                    rule_pair(j, Nf, uc, ym, yp, gr);
-                    if (D == 3) rule_pair(k, Nf, uc, zm, zp, gr);
+                    rule_pair(i, Nfx, uc, xm, xp, gr, 0);
+                    rule_pair(j, Nfy, uc, ym, yp, gr, 1);
+                    if (D == 3) rule_pair(k, Nfz, uc, zm, zp, gr, 2);
                 }
                 C s = xm + xp;
                 s = s + ym;
@@ -1398,19 +1414,22 @@ __global__ void __launch_bounds__(kBlock) k_restrict3_zm(const TF* __restrict__ 
                                                          typename Compute<TC>::type inv2d)
 {
     using C = typename Compute<TC>::type;
-    const int Nc = gc.nx - 2, Nf = gf.nx - 2;
+    const int Ncx = gc.nx - 2, Ncy = gc.ny - 2, Ncz = gc.nz - 2;
+    const int Nfx = gf.nx - 2, Nfy = gf.ny - 2, Nfz = gf.nz - 2;
     const int lb = (int)xcd_block();
     const int zc = lb / pblocks;
     const int t = (lb - zc * pblocks) * kBlock + (int)threadIdx.x;
-    if (t >= (long)Nc * Nc) return;
-    const int I = 1 + (int)(t % Nc), J = 1 + (int)(t / Nc);
+    if (t >= (long)Ncx * Ncy) return;
+    const int I = 1 + (int)(t % Ncx), J = 1 + (int)(t / Ncx);
     const int K0 = 1 + zc * kch;
-    const int K1 = min(K0 + kch - 1, Nc);
-    auto cl = [&](int a) { return a > Nf + 1 ? Nf + 1 : a; };
+    const int K1 = min(K0 + kch - 1, Ncz);
+    auto clx = [&](int a) { return a > Nfx + 1 ? Nfx + 1 : a; };
+    auto cly = [&](int a) { return a > Nfy + 1 ? Nfy + 1 : a; };
+    auto cl = [&](int a) { return a > Nfz + 1 ? Nfz + 1 : a; };
     int xi[4], yj[4];
     for (int a = 0; a < 4; a++) {
-        xi[a] = cl(2 * I - 2 + a);
-        yj[a] = cl(2 * J - 2 + a);
+        xi[a] = clx(2 * I - 2 + a);
+        yj[a] = cly(2 * J - 2 + a);
     }
     // cross of fine plane k: P[r][c] = u(2I-2+c, 2J-2+r, k); the corners are not loaded
     auto load_cross = [&](int k, C (&P)[4][4]) {
@@ -1446,15 +1465,15 @@ __global__ void __launch_bounds__(kBlock) k_restrict3_zm(const TF* __restrict__ 
 #pragma unroll
         for (int dz = 0; dz < 2; dz++) {
             const int k = 2 * K - 1 + dz;
-            if (k > Nf) continue;
+            if (k > Nfz) continue;
 #pragma unroll
             for (int dy = 0; dy < 2; dy++) {
                 const int j = 2 * J - 1 + dy;
-                if (j > Nf) continue;
+                if (j > Nfy) continue;
 #pragma unroll
                 for (int dx = 0; dx < 2; dx++) {
                     const int i = 2 * I - 1 + dx;
-                    if (i > Nf) continue;
+                    if (i > Nfx) continue;
                     const C(&P)[4][4] = dz ? p2 : p1;
                     const C uc = P[1 + dy][1 + dx];
                     C xm = P[1 + dy][dx], xp = P[1 + dy][2 + dx];
@@ -1462,9 +1481,9 @@ __global__ void __launch_bounds__(kBlock) k_restrict3_zm(const TF* __restrict__ 
                     C zm = dz ? p1[1 + dy][1 + dx] : pc[dy][dx];
                     C zp = dz ? p3[1 + dy][1 + dx] : p2[1 + dy][1 + dx];
                     if (RULE) {
-                        rule_pair(i, Nf, uc, xm, xp, gr);
-                        rule_pair(j, Nf, uc, ym, yp, gr);
-                        rule_pair(k, Nf, uc, zm, zp, gr);
+                        rule_pair(i, Nfx, uc, xm, xp, gr, 0);
+                        rule_pair(j, Nfy, uc, ym, yp, gr, 1);
+                        rule_pair(k, Nfz, uc, zm, zp, gr, 2);
                     }
                     C s = xm + xp;
                     s = s + ym;
@@ -1497,8 +1516,8 @@ __global__ void __launch_bounds__(kBlock) k_restrict3_zm(const TF* __restrict__ 
 // base (2J - 2) hx + I - 1 are the same for every lane of the block (the chunk,
 // hence k, is uniform).  So each load is a scalar pointer plus the lane's fixed
 // byte offset, with no per-load address arithmetic.  Same arithmetic in the
-// same order as k_restrict3_zm.  Requires N_f = 2 N_c (every child active) and
-// arrays of fewer than 2^31 bytes.
+// same order as k_restrict3_zm.  Requires N_f = 2 N_c along every axis (every
+// child active) and arrays of fewer than 2^31 bytes.
 template <typename TF, typename TC>
 __global__ void __launch_bounds__(kBlock) k_restrict3_l0(const TF* __restrict__ u, const TF* __restrict__ f, SGrid gf,
                                                           typename Compute<TC>::type inv_h2,
@@ -1508,14 +1527,14 @@ __global__ void __launch_bounds__(kBlock) k_restrict3_l0(const TF* __restrict__ 
                                                           typename Compute<TC>::type inv2d)
 {
     using C = typename Compute<TC>::type;
-    const int Nc = gc.nx - 2;
+    const int Ncx = gc.nx - 2, Ncy = gc.ny - 2, Ncz = gc.nz - 2;
     const int lb = (int)xcd_block();
     const int zc = lb / pblocks;
     const int t = (lb - zc * pblocks) * kBlock + (int)threadIdx.x;
-    if (t >= Nc * Nc) return;
-    const int I = 1 + t % Nc, J = 1 + t / Nc;
+    if (t >= Ncx * Ncy) return;
+    const int I = 1 + t % Ncx, J = 1 + t / Ncx;
     const int K0 = 1 + zc * kch;
-    const int K1 = min(K0 + kch - 1, Nc);
+    const int K1 = min(K0 + kch - 1, Ncz);
     const unsigned boff = (unsigned)(((2 * J - 2) * gf.hx + (I - 1)) * (int)sizeof(TF));
     const size_t fplane = gf.ps;
     // value at (2I - 2 + c, 2J - 2 + r, k) of array a
@@ -1598,7 +1617,7 @@ struct AxisNb {
 };
 
 template <typename C>
-__device__ __forceinline__ AxisNb<C> axis_nb(int q, int N, const GRule<C>& gr)
+__device__ __forceinline__ AxisNb<C> axis_nb(int q, int N, const GRule<C>& gr, int ax)
 {
     AxisNb<C> a{q, (C)1, false};
     if (q == 0) {
@@ -1606,8 +1625,8 @@ __device__ __forceinline__ AxisNb<C> axis_nb(int q, int N, const GRule<C>& gr)
         a.fac = (C)-1;
         a.ghost = true;
     } else if (q == N + 1) {
-        a.q = gr.xn1 ? N - 1 : N;
-        a.fac = gr.xn1 ? (C)-1 : gr.coef;
+        a.q = gr.xn1[ax] ? N - 1 : N;
+        a.fac = gr.xn1[ax] ? (C)-1 : gr.coef[ax];
         a.ghost = true;
     }
     return a;
@@ -1618,26 +1637,26 @@ __global__ void __launch_bounds__(kBlock) k_prolong_add(const TC* __restrict__ e
                                                         int black_only, GRule<typename Compute<TC>::type> gr)
 {
     using C = typename Compute<TC>::type;
-    int m = gf.nx - 2;
+    const int my = gf.ny - 2, mz = gf.nz - 2;
     long t = xcd_block() * kBlock + threadIdx.x;
-    long total = (long)gf.hx * m * (D == 3 ? m : 1);
+    long total = (long)gf.hx * my * (D == 3 ? mz : 1);
     if (t >= total) return;
     int h = (int)(t % gf.hx);
     long r = t / gf.hx;
-    int pj = 1 + (int)(r % m);
-    int pk = D == 3 ? 1 + (int)(r / m) : 0;
+    int pj = 1 + (int)(r % my);
+    int pk = D == 3 ? 1 + (int)(r / my) : 0;
     const C w0 = (C)0.75, w1 = (C)0.25;
-    const int Nc = gc.nx - 2;
+    const int Ncx = gc.nx - 2, Ncy = gc.ny - 2, Ncz = gc.nz - 2;
     int qj = (pj + 1) >> 1, sj = (pj & 1) ? -1 : 1;
     int qk = D == 3 ? (pk + 1) >> 1 : 0, sk = (pk & 1) ? -1 : 1;
-    const AxisNb<C> pj_ = axis_nb(qj, Nc, gr), nj = axis_nb(qj + sj, Nc, gr);
+    const AxisNb<C> pj_ = axis_nb(qj, Ncy, gr, 1), nj = axis_nb(qj + sj, Ncy, gr, 1);
     const AxisNb<C> none{0, (C)1, false};
-    const AxisNb<C> pk_ = D == 3 ? axis_nb(qk, Nc, gr) : none, nk = D == 3 ? axis_nb(qk + sk, Nc, gr) : none;
+    const AxisNb<C> pk_ = D == 3 ? axis_nb(qk, Ncz, gr, 2) : none, nk = D == 3 ? axis_nb(qk + sk, Ncz, gr, 2) : none;
     for (int c = black_only; c < 2; c++) {
         int pi = 2 * h + ((c + pj + pk + D) & 1);
         if (pi < 1 || pi > gf.nx - 2) continue;
         int qi = (pi + 1) >> 1, si = (pi & 1) ? -1 : 1;
-        const AxisNb<C> pi_ = axis_nb(qi, Nc, gr), ni = axis_nb(qi + si, Nc, gr);
+        const AxisNb<C> pi_ = axis_nb(qi, Ncx, gr, 0), ni = axis_nb(qi + si, Ncx, gr, 0);
         // coarse value at (parent or neighbour) per axis, rule factors in x, y, z order
         auto E = [&](bool bx, bool by, bool bz) -> C {
             const AxisNb<C>& ax = bx ? ni : pi_;
@@ -1671,11 +1690,11 @@ __global__ void __launch_bounds__(kBlock) k_prolong_add(const TC* __restrict__ e
 // (a ghost parent with one active child).  Per child the arithmetic is that
 // of k_prolong_add.
 template <typename C>
-__device__ __forceinline__ AxisNb<C> axis_nb_clamped(int q, int N, const GRule<C>& gr)
+__device__ __forceinline__ AxisNb<C> axis_nb_clamped(int q, int N, const GRule<C>& gr, int ax)
 {
     // q = N + 2 only beside a ghost parent, on the side it has no child: any
     // in-bounds value serves
-    return axis_nb(q > N + 1 ? N + 1 : q, N, gr);
+    return axis_nb(q > N + 1 ? N + 1 : q, N, gr, ax);
 }
 
 template <typename TC, typename TF>
@@ -1684,24 +1703,26 @@ __global__ void __launch_bounds__(kBlock) k_prolong3_zm(const TC* __restrict__ e
                                                          int pblocks, int kch)
 {
     using C = typename Compute<TC>::type;
-    const int Nc = gc.nx - 2, Nf = gf.nx - 2;
-    const int Mq = (Nf + 1) >> 1;  // coarse parents per axis
+    const int Ncx = gc.nx - 2, Ncy = gc.ny - 2, Ncz = gc.nz - 2;
+    const int Nfx = gf.nx - 2, Nfy = gf.ny - 2, Nfz = gf.nz - 2;
+    // coarse parents per axis
+    const int Mx = (Nfx + 1) >> 1, My = (Nfy + 1) >> 1, Mz = (Nfz + 1) >> 1;
     const int lb = (int)xcd_block();
     const int zc = lb / pblocks;
     const int t = (lb - zc * pblocks) * kBlock + (int)threadIdx.x;
-    if (t >= (long)Mq * Mq) return;
-    const int I = 1 + (int)(t % Mq), J = 1 + (int)(t / Mq);
+    if (t >= (long)Mx * My) return;
+    const int I = 1 + (int)(t % Mx), J = 1 + (int)(t / Mx);
     const int K0 = 1 + zc * kch;
-    const int K1 = min(K0 + kch - 1, Mq);
+    const int K1 = min(K0 + kch - 1, Mz);
     AxisNb<C> mx[3], my[3];
     for (int a = 0; a < 3; a++) {
-        mx[a] = axis_nb_clamped(I - 1 + a, Nc, gr);
-        my[a] = axis_nb_clamped(J - 1 + a, Nc, gr);
+        mx[a] = axis_nb_clamped(I - 1 + a, Ncx, gr, 0);
+        my[a] = axis_nb_clamped(J - 1 + a, Ncy, gr, 1);
     }
     // coarse values, index [z][y][x] = plane K-1+z, row J-1+y, column I-1+x
     C cv[3][3][3];
     auto load_plane = [&](int kk, C (&pl)[3][3]) {
-        const AxisNb<C> mz = axis_nb_clamped(kk, Nc, gr);
+        const AxisNb<C> mz = axis_nb_clamped(kk, Ncz, gr, 2);
 #pragma unroll
         for (int y = 0; y < 3; y++)
 #pragma unroll
@@ -1730,7 +1751,7 @@ __global__ void __launch_bounds__(kBlock) k_prolong3_zm(const TC* __restrict__ e
             const int dz = c8 >> 2, dy = (c8 >> 1) & 1, dx = c8 & 1;
             const int pk = 2 * K - 1 + dz, pj = 2 * J - 1 + dy, pi = 2 * I - 1 + dx;
             const int colour = (pi + pj + pk + 3) & 1;
-            st.live[c8] = pi <= Nf && pj <= Nf && pk <= Nf && !(black_only && colour == 0);
+            st.live[c8] = pi <= Nfx && pj <= Nfy && pk <= Nfz && !(black_only && colour == 0);
             st.pos8[c8] = (size_t)colour * gf.cs + row_base(gf, pj, pk) + (pi >> 1);
             if (st.live[c8]) st.old[c8] = u[st.pos8[c8]];
         }
@@ -1800,8 +1821,9 @@ __global__ void __launch_bounds__(kBlock) k_prolong3_pair(const TC* __restrict__
                                                            SGrid gf, GRule<typename Compute<TC>::type> gr, int pblocks)
 {
     using C = typename Compute<TC>::type;
-    const int Nc = gc.nx - 2, Nf = gf.nx - 2;
-    const int Mq = (Nf + 1) >> 1;  // coarse parents per axis
+    const int Ncx = gc.nx - 2, Ncy = gc.ny - 2, Ncz = gc.nz - 2;
+    const int Nfx = gf.nx - 2, Nfy = gf.ny - 2, Nfz = gf.nz - 2;
+    const int Mz = (Nfz + 1) >> 1;  // coarse parents along z
     const int lb = zmarch_block(1);  // after the restriction, which runs up
     const int zc = lb / pblocks;
     const int t = (lb - zc * pblocks) * kBlock + (int)threadIdx.x;
@@ -1809,14 +1831,14 @@ __global__ void __launch_bounds__(kBlock) k_prolong3_pair(const TC* __restrict__
     const int q0 = 2 * t;
     const int pj = q0 / gf.hx;
     const int h0 = q0 - pj * gf.hx;
-    if (pj < 1 || pj > Nf) return;
+    if (pj < 1 || pj > Nfy) return;
     const int K0 = 1 + zc * KCH;
-    const int nk = min(KCH, Mq - K0 + 1);
+    const int nk = min(KCH, Mz - K0 + 1);
     const int qj = (pj + 1) >> 1, sj = (pj & 1) ? -1 : 1;
-    const AxisNb<C> my[2] = {axis_nb_clamped(qj, Nc, gr), axis_nb_clamped(qj + sj, Nc, gr)};
+    const AxisNb<C> my[2] = {axis_nb_clamped(qj, Ncy, gr, 1), axis_nb_clamped(qj + sj, Ncy, gr, 1)};
     AxisNb<C> mx[3];
 #pragma unroll
-    for (int a = 0; a < 3; a++) mx[a] = axis_nb_clamped(h0 + a, Nc, gr);
+    for (int a = 0; a < 3; a++) mx[a] = axis_nb_clamped(h0 + a, Ncx, gr, 0);
     const bool edge = my[0].ghost || my[1].ghost || mx[0].ghost || mx[2].ghost;
     // offsets inside a coarse plane of slot (y, x) for an even / odd plane index
     // (the colour of a coarse point flips with the plane's parity)
@@ -1841,7 +1863,7 @@ __global__ void __launch_bounds__(kBlock) k_prolong3_pair(const TC* __restrict__
 #pragma unroll
     for (int z = 0; z < KCH + 2; z++) {
         if (z <= nk + 1) {
-            const AxisNb<C> mz = axis_nb_clamped(K0 - 1 + z, Nc, gr);
+            const AxisNb<C> mz = axis_nb_clamped(K0 - 1 + z, Ncz, gr, 2);
             const TC* __restrict__ ep = e + (size_t)mz.q * cplane;
             C cv[2][3];
 #pragma unroll
@@ -1882,14 +1904,14 @@ __global__ void __launch_bounds__(kBlock) k_prolong3_pair(const TC* __restrict__
 #pragma unroll
         for (int d = 0; d < 2; d++) {
             const int pk = 2 * (K0 + z) - 1 + d;
-            if (z < nk && pk <= Nf) old[z][d] = *(const Pair<TF>*)(ub + (size_t)pk * fplane + row);
+            if (z < nk && pk <= Nfz) old[z][d] = *(const Pair<TF>*)(ub + (size_t)pk * fplane + row);
         }
 #pragma unroll
     for (int z = 0; z < KCH; z++) {
 #pragma unroll
         for (int d = 0; d < 2; d++) {
             const int pk = 2 * (K0 + z) - 1 + d;
-            if (z >= nk || pk > Nf) continue;
+            if (z >= nk || pk > Nfz) continue;
             const int zs = d ? z + 2 : z;  // the z neighbour: plane K + 1 or K - 1
             C r[2];
 #pragma unroll
@@ -1902,7 +1924,7 @@ __global__ void __launch_bounds__(kBlock) k_prolong3_pair(const TC* __restrict__
             nv.a = (TF)((C)o.a + r[0]);
             nv.b = (TF)((C)o.b + r[1]);
             const int pi0 = 2 * h0 + (d ? !par0 : par0);
-            const bool a0 = pi0 >= 1, a1 = pi0 + 2 <= Nf;
+            const bool a0 = pi0 >= 1, a1 = pi0 + 2 <= Nfx;
             TF* q = ub + (size_t)pk * fplane + row;
             if (a0 && a1) {
                 *(Pair<TF>*)q = nv;
@@ -1922,25 +1944,32 @@ __global__ void __launch_bounds__(kBlock) k_prolong3_pair(const TC* __restrict__
 // per-level kernels: n_pre sweeps on Lt; per level down, the restriction
 // (correction cleared) and n_pre sweeps; per level up, the prolongation and
 // n_post sweeps.  Each level lives in LDS in natural order (x fastest) on its
-// (N+2)^d box; the ghost slots are never written, the rule supplies their values.
+// box of N_a + 2 points per axis; the ghost slots are never written, the rule
+// supplies their values.
 constexpr int kTailThreads = 1024;
 
 template <typename C>
 struct TailParams {
-    int nlev;                   // levels Lt .. Lt + nlev - 1 (the last has N = 1)
-    int N[kTailMaxLevels];
-    int off[kTailMaxLevels];    // LDS element offset of level a's u; its f follows (N+2)^d later
+    int nlev;                   // levels Lt .. Lt + nlev - 1 (the last has one point along some axis)
+    int N[kTailMaxLevels][3];   // active points per axis
+    int off[kTailMaxLevels];    // LDS element offset of level a's u; its f follows one box later
     C h2[kTailMaxLevels];       // smoother factor (2^L h)^2
     C inv_h2[kTailMaxLevels];   // residual factor 1 / (2^L h)^2
     GRule<C> gr[kTailMaxLevels];
     int n_pre, n_post;
 };
 
+// points of a level's box in LDS ((N_x+2) x (N_y+2) [x (N_z+2)])
 template <int D>
-__device__ __forceinline__ int box_size(int N)
+__device__ __forceinline__ int box_size(const int* N)
 {
-    const int Q = N + 2;
-    return D == 3 ? Q * Q * Q : Q * Q;
+    return D == 3 ? (N[0] + 2) * (N[1] + 2) * (N[2] + 2) : (N[0] + 2) * (N[1] + 2);
+}
+
+template <int D>
+__device__ __forceinline__ int box_active(const int* N)
+{
+    return D == 3 ? N[0] * N[1] * N[2] : N[0] * N[1];
 }
 
 // q = a / N and a % N for 0 <= a < 2^22 through a float reciprocal (rN = 1/N,
@@ -1961,15 +1990,14 @@ __device__ __forceinline__ int divmod_small(int a, int N, float rN, int& rem)
 }
 
 template <int D>
-__device__ __forceinline__ void tail_point(int t, int N, int& i, int& j, int& k)
+__device__ __forceinline__ void tail_point(int t, const int* N, int& i, int& j, int& k)
 {
-    const float rN = 1.0f / (float)N;
     int ri;
-    const int r = divmod_small(t, N, rN, ri);
+    const int r = divmod_small(t, N[0], 1.0f / (float)N[0], ri);
     i = 1 + ri;
     if (D == 3) {
         int rj;
-        k = 1 + divmod_small(r, N, rN, rj);
+        k = 1 + divmod_small(r, N[1], 1.0f / (float)N[1], rj);
         j = 1 + rj;
     } else {
         j = 1 + r;
@@ -1977,24 +2005,31 @@ __device__ __forceinline__ void tail_point(int t, int N, int& i, int& j, int& k)
     }
 }
 
-template <int D, typename C>
-__device__ __forceinline__ void tail_sweep(C* U, const C* F, int N, C h2, C inv2d, const GRule<C>& gr, int colour)
+// element index of (i, j, k) in a level box with active points N
+__device__ __forceinline__ int box_idx(const int* N, int i, int j, int k)
 {
-    const int Q = N + 2, total = D == 3 ? N * N * N : N * N;
+    return (k * (N[1] + 2) + j) * (N[0] + 2) + i;
+}
+
+template <int D, typename C>
+__device__ __forceinline__ void tail_sweep(C* U, const C* F, const int* N, C h2, C inv2d, const GRule<C>& gr,
+                                           int colour)
+{
+    const int Qx = N[0] + 2, Qxy = Qx * (N[1] + 2), total = box_active<D>(N);
     for (int t = threadIdx.x; t < total; t += kTailThreads) {
         int i, j, k;
         tail_point<D>(t, N, i, j, k);
         if (((i + j + k + D) & 1) != colour) continue;
-        const int idx = (k * Q + j) * Q + i;
-        C xm = U[idx - 1], xp = U[idx + 1], ym = U[idx - Q], yp = U[idx + Q], zm = 0, zp = 0;
+        const int idx = box_idx(N, i, j, k);
+        C xm = U[idx - 1], xp = U[idx + 1], ym = U[idx - Qx], yp = U[idx + Qx], zm = 0, zp = 0;
         if (D == 3) {
-            zm = U[idx - Q * Q];
-            zp = U[idx + Q * Q];
+            zm = U[idx - Qxy];
+            zp = U[idx + Qxy];
         }
         const C me = U[idx];
-        rule_pair(i, N, me, xm, xp, gr);
-        rule_pair(j, N, me, ym, yp, gr);
-        if (D == 3) rule_pair(k, N, me, zm, zp, gr);
+        rule_pair(i, N[0], me, xm, xp, gr, 0);
+        rule_pair(j, N[1], me, ym, yp, gr, 1);
+        if (D == 3) rule_pair(k, N[2], me, zm, zp, gr, 2);
         C s = xm + xp;
         s = s + ym;
         s = s + yp;
@@ -2007,10 +2042,10 @@ __device__ __forceinline__ void tail_sweep(C* U, const C* F, int N, C h2, C inv2
 }
 
 template <int D, typename C>
-__device__ __forceinline__ void tail_restrict(const C* U, const C* F, int Nf, C inv_h2, const GRule<C>& gr, C* Uc,
-                                              C* Fc, int Nc)
+__device__ __forceinline__ void tail_restrict(const C* U, const C* F, const int* Nf, C inv_h2, const GRule<C>& gr,
+                                              C* Uc, C* Fc, const int* Nc)
 {
-    const int Qf = Nf + 2, Qc = Nc + 2, total = D == 3 ? Nc * Nc * Nc : Nc * Nc;
+    const int Qx = Nf[0] + 2, Qxy = Qx * (Nf[1] + 2), total = box_active<D>(Nc);
     for (int t = threadIdx.x; t < total; t += kTailThreads) {
         int I, J, K;
         tail_point<D>(t, Nc, I, J, K);
@@ -2019,17 +2054,17 @@ __device__ __forceinline__ void tail_restrict(const C* U, const C* F, int Nf, C 
         for (int k = k0; k <= k1; k++)
             for (int j = 2 * J - 1; j <= 2 * J; j++)
                 for (int i = 2 * I - 1; i <= 2 * I; i++) {
-                    if (i > Nf || j > Nf || (D == 3 && k > Nf)) continue;
-                    const int idx = (k * Qf + j) * Qf + i;
-                    C xm = U[idx - 1], xp = U[idx + 1], ym = U[idx - Qf], yp = U[idx + Qf], zm = 0, zp = 0;
+                    if (i > Nf[0] || j > Nf[1] || (D == 3 && k > Nf[2])) continue;
+                    const int idx = box_idx(Nf, i, j, k);
+                    C xm = U[idx - 1], xp = U[idx + 1], ym = U[idx - Qx], yp = U[idx + Qx], zm = 0, zp = 0;
                     if (D == 3) {
-                        zm = U[idx - Qf * Qf];
-                        zp = U[idx + Qf * Qf];
+                        zm = U[idx - Qxy];
+                        zp = U[idx + Qxy];
                     }
                     const C uc = U[idx];
-                    rule_pair(i, Nf, uc, xm, xp, gr);
-                    rule_pair(j, Nf, uc, ym, yp, gr);
-                    if (D == 3) rule_pair(k, Nf, uc, zm, zp, gr);
+                    rule_pair(i, Nf[0], uc, xm, xp, gr, 0);
+                    rule_pair(j, Nf[1], uc, ym, yp, gr, 1);
+                    if (D == 3) rule_pair(k, Nf[2], uc, zm, zp, gr, 2);
                     C s = xm + xp;
                     s = s + ym;
                     s = s + yp;
@@ -2039,16 +2074,16 @@ __device__ __forceinline__ void tail_restrict(const C* U, const C* F, int Nf, C 
                     }
                     sum += F[idx] - (s - (C)(2 * D) * uc) * inv_h2;
                 }
-        const int pc = (K * Qc + J) * Qc + I;
+        const int pc = box_idx(Nc, I, J, K);
         Fc[pc] = sum * ((C)(D == 3 ? 0.125 : 0.25) * (C)1);
         Uc[pc] = (C)0;
     }
 }
 
 template <int D, typename C>
-__device__ __forceinline__ void tail_prolong(const C* Ue, int Nc, const GRule<C>& gr, C* U, int Nf)
+__device__ __forceinline__ void tail_prolong(const C* Ue, const int* Nc, const GRule<C>& gr, C* U, const int* Nf)
 {
-    const int Qc = Nc + 2, Qf = Nf + 2, total = D == 3 ? Nf * Nf * Nf : Nf * Nf;
+    const int total = box_active<D>(Nf);
     const C w0 = (C)0.75, w1 = (C)0.25;
     const AxisNb<C> none{0, (C)1, false};
     for (int t = threadIdx.x; t < total; t += kTailThreads) {
@@ -2057,14 +2092,15 @@ __device__ __forceinline__ void tail_prolong(const C* Ue, int Nc, const GRule<C>
         const int qi = (i + 1) >> 1, si = (i & 1) ? -1 : 1;
         const int qj = (j + 1) >> 1, sj = (j & 1) ? -1 : 1;
         const int qk = D == 3 ? (k + 1) >> 1 : 0, sk = (k & 1) ? -1 : 1;
-        const AxisNb<C> pi_ = axis_nb(qi, Nc, gr), ni = axis_nb(qi + si, Nc, gr);
-        const AxisNb<C> pj_ = axis_nb(qj, Nc, gr), nj = axis_nb(qj + sj, Nc, gr);
-        const AxisNb<C> pk_ = D == 3 ? axis_nb(qk, Nc, gr) : none, nk = D == 3 ? axis_nb(qk + sk, Nc, gr) : none;
+        const AxisNb<C> pi_ = axis_nb(qi, Nc[0], gr, 0), ni = axis_nb(qi + si, Nc[0], gr, 0);
+        const AxisNb<C> pj_ = axis_nb(qj, Nc[1], gr, 1), nj = axis_nb(qj + sj, Nc[1], gr, 1);
+        const AxisNb<C> pk_ = D == 3 ? axis_nb(qk, Nc[2], gr, 2) : none;
+        const AxisNb<C> nk = D == 3 ? axis_nb(qk + sk, Nc[2], gr, 2) : none;
         auto E = [&](bool bx, bool by, bool bz) -> C {
             const AxisNb<C>& ax = bx ? ni : pi_;
             const AxisNb<C>& ay = by ? nj : pj_;
             const AxisNb<C>& az = bz ? nk : pk_;
-            C v = Ue[(az.q * Qc + ay.q) * Qc + ax.q];
+            C v = Ue[box_idx(Nc, ax.q, ay.q, az.q)];
             if (ax.ghost) v = ax.fac * v;
             if (ay.ghost) v = ay.fac * v;
             if (az.ghost) v = az.fac * v;
@@ -2078,7 +2114,7 @@ __device__ __forceinline__ void tail_prolong(const C* Ue, int Nc, const GRule<C>
             C y3 = w0 * E(false, true, true) + w1 * E(true, true, true);
             v = w0 * v + w1 * (w0 * y2 + w1 * y3);
         }
-        const int idx = (k * Qf + j) * Qf + i;
+        const int idx = box_idx(Nf, i, j, k);
         U[idx] = U[idx] + v;
     }
 }
@@ -2099,13 +2135,14 @@ __global__ void __launch_bounds__(kTailThreads) k_coarse_tail(TailParams<C> P, S
         }
     };
     {
-        const int N = P.N[0], Q = N + 2, total = D == 3 ? N * N * N : N * N;
+        const int* N = P.N[0];
+        const int total = box_active<D>(N);
         C* u = U(0);
         C* f = F(0);
         for (int t = threadIdx.x; t < total; t += kTailThreads) {
             int i, j, k;
             tail_point<D>(t, N, i, j, k);
-            const int idx = (k * Q + j) * Q + i;
+            const int idx = box_idx(N, i, j, k);
             f[idx] = fg[pos<D, C>(g0, i, j, k)];
             u[idx] = (C)0;
         }
@@ -2126,12 +2163,13 @@ __global__ void __launch_bounds__(kTailThreads) k_coarse_tail(TailParams<C> P, S
         a--;
     }
     {
-        const int N = P.N[0], Q = N + 2, total = D == 3 ? N * N * N : N * N;
+        const int* N = P.N[0];
+        const int total = box_active<D>(N);
         const C* u = U(0);
         for (int t = threadIdx.x; t < total; t += kTailThreads) {
             int i, j, k;
             tail_point<D>(t, N, i, j, k);
-            ug[pos<D, C>(g0, i, j, k)] = u[(k * Q + j) * Q + i];
+            ug[pos<D, C>(g0, i, j, k)] = u[box_idx(N, i, j, k)];
         }
     }
 }
@@ -2181,14 +2219,14 @@ __global__ void __launch_bounds__(kBlock) k_dc_scale(SGrid g, const float* __res
                                                      TL* __restrict__ r, TL* __restrict__ e, int first_red,
                                                      float h2l, float inv2d)
 {
-    const int m = g.nx - 2;
-    const long total = (long)g.hx * m * (D == 3 ? m : 1);
+    const int my = g.ny - 2, mz = g.nz - 2;
+    const long total = (long)g.hx * my * (D == 3 ? mz : 1);
     const long stride = (long)gridDim.x * kBlock;
     for (long t = xcd_block() * kBlock + threadIdx.x; t < total; t += stride) {
         const int h = (int)(t % g.hx);
         const long rr = t / g.hx;
-        const int pj = 1 + (int)(rr % m);
-        const int pk = D == 3 ? 1 + (int)(rr / m) : 0;
+        const int pj = 1 + (int)(rr % my);
+        const int pk = D == 3 ? 1 + (int)(rr / my) : 0;
         const size_t row = row_base(g, pj, pk);
         for (int c = 0; c < 2; c++) {
             const int pi = 2 * h + ((c + pj + pk + D) & 1);
@@ -2205,16 +2243,16 @@ __global__ void __launch_bounds__(kBlock) k_dc_outer(SGrid g, DcIn<TL, UPD> in, 
                                                      TL* __restrict__ r, TL* __restrict__ eout, int first_red,
                                                      float h2l, float inv2d, unsigned long long* maxbits)
 {
-    int m = g.nx - 2;
-    long total = (long)g.hx * m * (D == 3 ? m : 1);
+    const int my = g.ny - 2, mz = g.nz - 2;
+    long total = (long)g.hx * my * (D == 3 ? mz : 1);
     long stride = (long)gridDim.x * kBlock;
     size_t ny = (size_t)g.hx, nz = g.ps;
     unsigned long long best = 0;
     for (long t = xcd_block() * kBlock + threadIdx.x; t < total; t += stride) {
         int h = (int)(t % g.hx);
         long rr = t / g.hx;
-        int pj = 1 + (int)(rr % m);
-        int pk = D == 3 ? 1 + (int)(rr / m) : 0;
+        int pj = 1 + (int)(rr % my);
+        int pk = D == 3 ? 1 + (int)(rr / my) : 0;
         size_t row = row_base(g, pj, pk);
         for (int c = 0; c < 2; c++) {
             int pi = 2 * h + ((c + pj + pk + D) & 1);
@@ -2250,7 +2288,7 @@ __global__ void __launch_bounds__(kBlock) k_dc_outer3(SGrid g, DcIn<TL, UPD> in,
                                                       float h2l, float inv2d, int pblocks,
                                                       unsigned long long* maxbits)
 {
-    const int m = g.nx - 2;
+    const int my = g.ny - 2, mz = g.nz - 2;
     const int lb = (int)xcd_block();
     const int zc = lb / pblocks;
     const int t = (lb - zc * pblocks) * kBlock + (int)threadIdx.x;
@@ -2259,9 +2297,9 @@ __global__ void __launch_bounds__(kBlock) k_dc_outer3(SGrid g, DcIn<TL, UPD> in,
     // rows and the padding have no work
     const int pj = t / g.hx;
     const int h = t - pj * g.hx;
-    if (pj >= 1 && pj <= m) {
+    if (pj >= 1 && pj <= my) {
         const int k0 = 1 + zc * kNormChunk;
-        const int k1 = min(k0 + kNormChunk - 1, m);
+        const int k1 = min(k0 + kNormChunk - 1, mz);
         const size_t plane = g.ps;
         const size_t col = (size_t)pj * g.hx + h;
         const size_t cs = g.cs;
@@ -2332,7 +2370,7 @@ __global__ void __launch_bounds__(kBlock) k_dc_outer3_pair(SGrid g, DcIn<TL, UPD
                                                            float h2l, float inv2d, int pblocks,
                                                            unsigned long long* maxbits)
 {
-    const int m = g.nx - 2;
+    const int my = g.ny - 2, mz = g.nz - 2;
     const int lb = (int)xcd_block();
     const int zc = lb / pblocks;
     const int t = (lb - zc * pblocks) * kBlock + (int)threadIdx.x;
@@ -2341,9 +2379,9 @@ __global__ void __launch_bounds__(kBlock) k_dc_outer3_pair(SGrid g, DcIn<TL, UPD
     const int q = 2 * t;
     const int pj = q / g.hx;
     const int h0 = q - pj * g.hx;
-    if (pj >= 1 && pj <= m) {
+    if (pj >= 1 && pj <= my) {
         const int k0 = 1 + zc * kDcChunk;
-        const int k1 = min(k0 + kDcChunk - 1, m);
+        const int k1 = min(k0 + kDcChunk - 1, mz);
         const size_t plane = g.ps;
         const size_t col = (size_t)pj * g.hx + h0;
         const size_t cs = g.cs;
@@ -2473,19 +2511,20 @@ __global__ void __launch_bounds__(kBlock) k_dc_outer3_pair(SGrid g, DcIn<TL, UPD
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_copy_ghosts(SGrid g, const double* __restrict__ src, double* __restrict__ dst)
 {
-    int Q = g.nx;
+    const int Q[3] = {g.nx, g.ny, g.nz};
     int t = blockIdx.x * kBlock + threadIdx.x;
-    int per = D == 3 ? Q * Q : Q;
-    if (t >= per) return;
     int face = blockIdx.y;
     int axis = face >> 1, side = face & 1;
+    const int a1 = D == 3 ? (axis + 1) % 3 : (axis ^ 1), a2 = (axis + 2) % 3;
+    int per = D == 3 ? Q[a1] * Q[a2] : Q[a1];
+    if (t >= per) return;
     int p[3] = {0, 0, 0};
-    p[axis] = side ? Q - 1 : 0;
+    p[axis] = side ? Q[axis] - 1 : 0;
     if (D == 3) {
-        p[(axis + 1) % 3] = t % Q;
-        p[(axis + 2) % 3] = t / Q;
+        p[a1] = t % Q[a1];
+        p[a2] = t / Q[a1];
     } else {
-        p[axis ^ 1] = t;
+        p[a1] = t;
     }
     size_t i = pos<D, double>(g, p[0], p[1], D == 3 ? p[2] : 0);
     dst[i] = src[i];
@@ -2496,15 +2535,16 @@ __global__ void __launch_bounds__(kBlock) k_copy_ghosts(SGrid g, const double* _
 // domain of a level between the level array and an array of its own
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_copy_box(SGrid gs, const double* __restrict__ src, SGrid gd,
-                                                     double* __restrict__ dst, int lo, int w, int shift)
+                                                     double* __restrict__ dst, int lo, int wx, int wy, int wz,
+                                                     int shift)
 {
     const long t = (long)blockIdx.x * kBlock + threadIdx.x;
-    const long total = D == 3 ? (long)w * w * w : (long)w * w;
+    const long total = D == 3 ? (long)wx * wy * wz : (long)wx * wy;
     if (t >= total) return;
-    const int i = lo + (int)(t % w);
-    const long r = t / w;
-    const int j = lo + (int)(r % w);
-    const int k = D == 3 ? lo + (int)(r / w) : 0;
+    const int i = lo + (int)(t % wx);
+    const long r = t / wx;
+    const int j = lo + (int)(r % wy);
+    const int k = D == 3 ? lo + (int)(r / wy) : 0;
     dst[pos<D, double>(gd, i, j, k)] = at<D>(src, gs, i + shift, j + shift, D == 3 ? k + shift : 0);
 }
 
@@ -2517,11 +2557,10 @@ __global__ void __launch_bounds__(kBlock) k_copy_box(SGrid gs, const double* __r
         else hipLaunchKernelGGL((KERNEL<2>), (grid), (block), 0, (st), __VA_ARGS__);           \
     } while (0)
 
-static long npoints(const SGrid& g) { return (long)g.nx * g.nx * g.nz; }
+static long npoints(const SGrid& g) { return (long)g.nx * g.ny * g.nz; }
 static long ncompact_active(int dim, const SGrid& g)
 {
-    long m = g.nx - 2;
-    return (long)g.hx * m * (dim == 3 ? m : 1);
+    return (long)g.hx * (g.ny - 2) * (dim == 3 ? g.nz - 2 : 1);
 }
 
 void launch_level0_init(int dim, hipStream_t st, SGrid g, const double* rho0, const double* phi_outer,
@@ -2533,47 +2572,48 @@ void launch_level0_init(int dim, hipStream_t st, SGrid g, const double* rho0, co
 }
 
 void launch_interface_fill(int dim, hipStream_t st, SGrid gc, const double* phic, const double* fc, SGrid gf,
-                           int nf, int offx, int offy, int offz, const double* rho, double fourpiG, double* phif,
+                           int offx, int offy, int offz, const double* rho, double fourpiG, double* phif,
                            double* ff, unsigned long long* fmax)
 {
     if (dim == 3 && gf.hx % 2 == 0 && 2 * gc.cs < (1ull << 31)) {
         const int pblocks = ceil_div((long)(gf.ps / 2), kBlock);
-        const int chunks = ceil_div(gf.nx / 2, kFillPairChunk);
-        hipLaunchKernelGGL(k_interface_fill3_pair, dim3(pblocks * chunks), dim3(kBlock), 0, st, gc, phic, fc, gf, nf, offx,
+        const int chunks = ceil_div(gf.nz / 2, kFillPairChunk);
+        hipLaunchKernelGGL(k_interface_fill3_pair, dim3(pblocks * chunks), dim3(kBlock), 0, st, gc, phic, fc, gf, offx,
                            offy, offz, rho, fourpiG, phif, ff, pblocks, fmax);
         return;
     }
     if (dim == 3) {
-        const long Mq = (gf.nx + 1) / 2;
-        const int pblocks = ceil_div(Mq * Mq, kBlock);
-        hipLaunchKernelGGL(k_interface_fill3_zm, dim3(pblocks * ceil_div(Mq, kFillChunk)), dim3(kBlock), 0, st, gc, phic,
-                           fc, gf, nf, offx, offy, offz, rho, fourpiG, phif, ff, pblocks, fmax);
+        const long Mx = (gf.nx + 1) / 2, My = (gf.ny + 1) / 2, Mz = (gf.nz + 1) / 2;
+        const int pblocks = ceil_div(Mx * My, kBlock);
+        hipLaunchKernelGGL(k_interface_fill3_zm, dim3(pblocks * ceil_div(Mz, kFillChunk)), dim3(kBlock), 0, st, gc, phic,
+                           fc, gf, offx, offy, offz, rho, fourpiG, phif, ff, pblocks, fmax);
         return;
     }
-    NP_DISPATCH(dim, k_interface_fill, dim3(ceil_div(npoints(gf), kBlock)), dim3(kBlock), st, gc, phic, fc, gf, nf,
+    NP_DISPATCH(dim, k_interface_fill, dim3(ceil_div(npoints(gf), kBlock)), dim3(kBlock), st, gc, phic, fc, gf,
                 offx, offy, offz, rho, fourpiG, phif, ff, fmax);
 }
 
-void launch_forces(int dim, hipStream_t st, SGrid g, int n, double dx, const double* phi, double* fx, double* fy,
+void launch_forces(int dim, hipStream_t st, SGrid g, double dx, const double* phi, double* fx, double* fy,
                    double* fz)
 {
     double m12dx = -1.0 / (12.0 * dx);
+    const long nx = g.nx - 4, ny = g.ny - 4, nz = g.nz - 4;
     if (dim == 3) {
-        const int pblocks = ceil_div((long)n * ((n + kForceRows - 1) / kForceRows), kForceBlock);
-        hipLaunchKernelGGL(k_forces3_zm, dim3(pblocks * ceil_div(n, kForceChunk)), dim3(kForceBlock), 0, st, g, n,
+        const int pblocks = ceil_div(nx * ((ny + kForceRows - 1) / kForceRows), kForceBlock);
+        hipLaunchKernelGGL(k_forces3_zm, dim3(pblocks * ceil_div(nz, kForceChunk)), dim3(kForceBlock), 0, st, g,
                            m12dx, phi, fx, fy, fz, pblocks);
         return;
     }
-    Strip sp = make_strip(n, n, 1, 16);
-    NP_DISPATCH(dim, k_forces, dim3(ceil_div((long)n * n, kBlock)), dim3(kBlock), st, g, n, m12dx, phi, fx, fy, fz, sp);
+    Strip sp = make_strip((int)nx, (int)ny, 1, 16);
+    NP_DISPATCH(dim, k_forces, dim3(ceil_div(nx * ny, kBlock)), dim3(kBlock), st, g, m12dx, phi, fx, fy, fz, sp);
 }
 
-void launch_force_delta(int dim, hipStream_t st, SGrid g, int n, double dx, const double* phi, double* F,
+void launch_force_delta(int dim, hipStream_t st, SGrid g, double dx, const double* phi, double* F,
                         unsigned long long* maxbits)
 {
-    long total = dim == 3 ? (long)n * n * n : (long)n * n;
+    long total = (long)(g.nx - 4) * (g.ny - 4) * (dim == 3 ? g.nz - 4 : 1);
     double m12dx = -1.0 / (12.0 * dx);
-    NP_DISPATCH(dim, k_force_delta, dim3(ceil_div(total, kBlock)), dim3(kBlock), st, g, n, m12dx, phi, F, maxbits);
+    NP_DISPATCH(dim, k_force_delta, dim3(ceil_div(total, kBlock)), dim3(kBlock), st, g, m12dx, phi, F, maxbits);
 }
 
 void launch_export(int dim, hipStream_t st, SGrid g, const double* a, double* out)
@@ -2586,17 +2626,17 @@ void launch_norm(int dim, hipStream_t st, SGrid g, const double* u, const double
 {
     if (dim == 3 && mode == 0 && g.hx % 2 == 0) {
         // the paired DC pass without outputs: same residual, same order of operations
-        const long m = g.nx - 2;
+        const long mz = g.nz - 2;
         const int pblocks = ceil_div((long)(g.ps / 2), kBlock);
-        hipLaunchKernelGGL((k_dc_outer3_pair<float, false, false>), dim3(pblocks * ceil_div(m, kDcChunk)), dim3(kBlock), 0,
+        hipLaunchKernelGGL((k_dc_outer3_pair<float, false, false>), dim3(pblocks * ceil_div(mz, kDcChunk)), dim3(kBlock), 0,
                            st, g, DcIn<float, false>{u, nullptr, 0.0}, nullptr, f, inv_h2, 0.0, nullptr, nullptr, 0, 0.0f,
                            0.0f, pblocks, maxbits);
         return;
     }
     if (dim == 3 && mode == 0) {
-        long m = g.nx - 2;
+        long mz = g.nz - 2;
         int pblocks = ceil_div((long)g.ps, kBlock);
-        int chunks = ceil_div(m, kNormChunk);
+        int chunks = ceil_div(mz, kNormChunk);
         hipLaunchKernelGGL(k_resid_norm3, dim3(pblocks * chunks), dim3(kBlock), 0, st, g, u, f, inv_h2, pblocks,
                            maxbits);
         return;
@@ -2609,10 +2649,9 @@ void launch_norm(int dim, hipStream_t st, SGrid g, const double* u, const double
 void launch_box_resid_norm3(hipStream_t st, SGrid g, const double* u, const double* f, double inv_h2,
                             unsigned long long* maxbits)
 {
-    const int m = g.nx - 2;
-    const int nbx = (m + kBox - 1) / kBox;
-    hipLaunchKernelGGL(k_box_resid_norm3, dim3(ceil_div((long)nbx * nbx * nbx, kBlock)), dim3(kBlock), 0, st, g, u, f,
-                       inv_h2, nbx, maxbits);
+    const long nb = (long)((g.nx - 2 + kBox - 1) / kBox) * ((g.ny - 2 + kBox - 1) / kBox) *
+                    ((g.nz - 2 + kBox - 1) / kBox);
+    hipLaunchKernelGGL(k_box_resid_norm3, dim3(ceil_div(nb, kBlock)), dim3(kBlock), 0, st, g, u, f, inv_h2, maxbits);
 }
 
 void launch_set_u64(hipStream_t st, unsigned long long* p, int count, unsigned long long v)
@@ -2621,30 +2660,30 @@ void launch_set_u64(hipStream_t st, unsigned long long* p, int count, unsigned l
 }
 
 template <typename T>
-void launch_half_sweep(int dim, hipStream_t st, SGrid g, T* u, const T* f, int colour, double h2, int fine, int xn1,
-                       double coef)
+void launch_half_sweep(int dim, hipStream_t st, SGrid g, T* u, const T* f, int colour, double h2, int fine,
+                       const Rule3& rule)
 {
     using C = typename Compute<T>::type;
     dim3 grid(ceil_div(ncompact_active(dim, g), kBlock));
     C inv2d = (C)(1.0 / (2.0 * dim));
-    const GRule<C> gr{xn1, (C)coef};
+    const GRule<C> gr = grule<C>(rule);
     if (dim == 3 && fine && sizeof(T) <= 4 && (g.hx % 2) == 0) {
         // 2- and 4-byte storage: two compact points per thread, paired loads
         // (on the coarse levels, with the ghost rule, this form measured slower
         // than k_smooth_zmarch3)
-        long m = g.nx - 2;
+        long mz = g.nz - 2;
         int pblocks = ceil_div((long)(g.ps / 2), kSmoothPairBlock);
-        int chunks = ceil_div(m, kZChunk0);
+        int chunks = ceil_div(mz, kZChunk0);
         hipLaunchKernelGGL((k_smooth_zmarch3_pair<T>), dim3(pblocks * chunks), dim3(kSmoothPairBlock), 0, st, u, f, g,
                            colour, (C)h2, inv2d, pblocks);
         return;
     }
-    if (dim == 3 && (fine || g.nx >= 34)) {
+    if (dim == 3 && (fine || g.nz >= 34)) {
         // z-march; the level-0 instance (TAG 0) is kept apart from the
         // coarse-level one (TAG 1) so that profiles separate them
-        long m = g.nx - 2;
+        long mz = g.nz - 2;
         int pblocks = ceil_div((long)g.ps, kBlock);
-        int chunks = ceil_div(m, fine ? kZChunk0 : kZChunk1);
+        int chunks = ceil_div(mz, fine ? kZChunk0 : kZChunk1);
         if (fine)
             hipLaunchKernelGGL((k_smooth_zmarch3<T, 0>), dim3(pblocks * chunks), dim3(kBlock), 0, st, u, f, g, colour,
                                (C)h2, inv2d, pblocks, gr);
@@ -2667,30 +2706,31 @@ template <typename T>
 void launch_half_sweep_seeded(hipStream_t st, SGrid g, T* u, const T* f, double h2)
 {
     using C = typename Compute<T>::type;
-    const long m = g.nx - 2;
+    const long mz = g.nz - 2;
     const int pblocks = ceil_div((long)(g.ps / 2), kSmoothPairBlock);
-    const int chunks = ceil_div(m, kZChunk0);
+    const int chunks = ceil_div(mz, kZChunk0);
     hipLaunchKernelGGL((k_smooth_zmarch3_pair<T, true>), dim3(pblocks * chunks), dim3(kSmoothPairBlock), 0, st, u, f,
                        g, 1, (C)h2, (C)(1.0 / 6.0), pblocks);
 }
 
 template <typename TF, typename TC>
 void launch_resid_restrict(int dim, hipStream_t st, SGrid gf, const TF* u, const TF* f, double inv_h2, double out_scale,
-                           SGrid gc, TC* fc, TC* ec, int rule, int xn1, double coef, double seed_h2)
+                           SGrid gc, TC* fc, TC* ec, int rule, const Rule3& fine_rule, double seed_h2)
 {
     using C = typename Compute<TC>::type;
     const C sh2 = (C)seed_h2, inv2d = (C)(1.0 / (2.0 * dim));
-    long Nc = gc.nx - 2;
-    long total = dim == 3 ? Nc * Nc * Nc : Nc * Nc;
+    const long Ncx = gc.nx - 2, Ncy = gc.ny - 2, Ncz = gc.nz - 2;
+    long total = dim == 3 ? Ncx * Ncy * Ncz : Ncx * Ncy;
     dim3 grid(ceil_div(total, kBlock));
-    const GRule<C> gr{xn1, (C)coef};
+    const GRule<C> gr = grule<C>(fine_rule);
     if (dim == 3) {
         // z-march: 4 coarse planes per thread on large grids, 1 on small ones
         // (there the column count alone does not fill the chip)
-        const int kch = Nc >= 128 ? 4 : 1;
-        const int pblocks = ceil_div(Nc * Nc, kBlock);
-        const dim3 zgrid(pblocks * ceil_div(Nc, kch));
-        if (!rule && gf.nx - 2 == 2 * Nc && 2 * gf.cs * sizeof(TF) < (1ull << 31)) {
+        const int kch = Ncx * Ncy >= 128 * 128 ? 4 : 1;
+        const int pblocks = ceil_div(Ncx * Ncy, kBlock);
+        const dim3 zgrid(pblocks * ceil_div(Ncz, kch));
+        if (!rule && gf.nx - 2 == 2 * Ncx && gf.ny - 2 == 2 * Ncy && gf.nz - 2 == 2 * Ncz &&
+            2 * gf.cs * sizeof(TF) < (1ull << 31)) {
             // multigrid level 0: uniform addressing
             hipLaunchKernelGGL((k_restrict3_l0<TF, TC>), zgrid, dim3(kBlock), 0, st, u, f, gf, (C)inv_h2, (C)out_scale,
                                gc, fc, ec, pblocks, kch, sh2, inv2d);
@@ -2713,49 +2753,53 @@ void launch_resid_restrict(int dim, hipStream_t st, SGrid gf, const TF* u, const
 }
 
 template <typename TC, typename TF>
-void launch_prolong_add(int dim, hipStream_t st, SGrid gc, const TC* ec, SGrid gf, TF* u, int black_only, int xn1,
-                        double coef)
+void launch_prolong_add(int dim, hipStream_t st, SGrid gc, const TC* ec, SGrid gf, TF* u, int black_only,
+                        const Rule3& coarse_rule)
 {
     using C = typename Compute<TC>::type;
-    const GRule<C> gr{xn1, (C)coef};
+    const GRule<C> gr = grule<C>(coarse_rule);
     dim3 grid(ceil_div(ncompact_active(dim, gf), kBlock));
     if (dim == 3 && black_only && (gf.hx % 2) == 0 && 2 * gf.cs < (1ull << 31) && 2 * gc.cs < (1ull << 31)) {
         // paired form: one paired load and store per fine plane and pair
-        const long Mq = (gf.nx - 1) / 2;
+        const long Mz = (gf.nz - 1) / 2;
         const int pblocks = ceil_div((long)(gf.ps / 2), kBlock);
-        const int chunks = ceil_div(Mq, kProlongPairChunk);
+        const int chunks = ceil_div(Mz, kProlongPairChunk);
         hipLaunchKernelGGL((k_prolong3_pair<TC, TF, kProlongPairChunk>), dim3(pblocks * chunks), dim3(kBlock), 0, st,
                            ec, gc, u, gf, gr, pblocks);
         return;
     }
     if (dim == 3) {
-        const long Mq = (gf.nx - 1) / 2;  // ceil(N_f / 2) coarse parents per axis
+        // ceil(N_f / 2) coarse parents per axis
+        const long Mx = (gf.nx - 1) / 2, My = (gf.ny - 1) / 2, Mz = (gf.nz - 1) / 2;
         // 8 coarse planes per thread on large grids, 2 on small ones (there the
         // column count alone does not fill the chip)
-        const int kch = Mq >= 200 ? 8 : 2;
-        const int pblocks = ceil_div(Mq * Mq, kBlock);
-        const int chunks = ceil_div(Mq, kch);
+        const int kch = Mx * My >= 200 * 200 ? 8 : 2;
+        const int pblocks = ceil_div(Mx * My, kBlock);
+        const int chunks = ceil_div(Mz, kch);
         hipLaunchKernelGGL((k_prolong3_zm<TC, TF>), dim3(pblocks * chunks), dim3(kBlock), 0, st, ec, gc, u, gf,
                            black_only, gr, pblocks, kch);
     } else
         hipLaunchKernelGGL((k_prolong_add<2, TC, TF>), grid, dim3(kBlock), 0, st, ec, gc, u, gf, black_only, gr);
 }
 
-size_t coarse_tail_lds_bytes(int dim, const int* N, int nlev, size_t esz)
+static size_t tail_box(int dim, const int* N)
+{
+    const size_t qx = (size_t)N[0] + 2, qy = (size_t)N[1] + 2, qz = (size_t)N[2] + 2;
+    return dim == 3 ? qx * qy * qz : qx * qy;
+}
+
+size_t coarse_tail_lds_bytes(int dim, const int (*N)[3], int nlev, size_t esz)
 {
     size_t e = 0;
-    for (int a = 0; a < nlev; a++) {
-        size_t Q = (size_t)N[a] + 2;
-        e += 2 * (dim == 3 ? Q * Q * Q : Q * Q);
-    }
+    for (int a = 0; a < nlev; a++) e += 2 * tail_box(dim, N[a]);
     return e * esz;
 }
 
 template <typename T>
-int launch_coarse_tail(int dim, hipStream_t st, int nlev, const int* N, const double* h, const int* xn1,
-                       const double* coef, int n_pre, int n_post, SGrid g0, const T* f0, T* u0)
+int launch_coarse_tail(int dim, hipStream_t st, int nlev, const int (*N)[3], const double* h, const Rule3* rule,
+                       int n_pre, int n_post, SGrid g0, const T* f0, T* u0)
 {
-    if (nlev < 1 || nlev > kTailMaxLevels || N[nlev - 1] != 1) return -1;
+    if (nlev < 1 || nlev > kTailMaxLevels) return -1;
     const size_t bytes = coarse_tail_lds_bytes(dim, N, nlev, sizeof(T));
     if (bytes > kTailLdsBytes) return -1;
     TailParams<T> P{};
@@ -2764,13 +2808,12 @@ int launch_coarse_tail(int dim, hipStream_t st, int nlev, const int* N, const do
     P.n_post = n_post;
     int off = 0;
     for (int a = 0; a < nlev; a++) {
-        P.N[a] = N[a];
+        for (int ax = 0; ax < 3; ax++) P.N[a][ax] = ax < dim ? N[a][ax] : 0;
         P.off[a] = off;
-        const int Q = N[a] + 2;
-        off += 2 * (dim == 3 ? Q * Q * Q : Q * Q);
+        off += 2 * (int)tail_box(dim, N[a]);
         P.h2[a] = (T)(h[a] * h[a]);
         P.inv_h2[a] = (T)(1.0 / (h[a] * h[a]));
-        P.gr[a] = GRule<T>{xn1[a], (T)coef[a]};
+        P.gr[a] = grule<T>(rule[a]);
     }
     if (dim == 3)
         hipLaunchKernelGGL((k_coarse_tail<3, T>), dim3(1), dim3(kTailThreads), bytes, st, P, g0, f0, u0);
@@ -2787,9 +2830,9 @@ void launch_dc_outer(int dim, hipStream_t st, SGrid g, const double* phi_in, con
     const float h2l = 1.0f, inv2d = (float)(1.0 / (2.0 * dim));
     const bool upd = e_in != nullptr;
     if (dim == 3 && g.hx % 2 == 0 && g.cs % 2 == 0) {
-        long m = g.nx - 2;
+        long mz = g.nz - 2;
         int pblocks = ceil_div((long)(g.ps / 2), kBlock);
-        dim3 grid(pblocks * ceil_div(m, kDcChunk));
+        dim3 grid(pblocks * ceil_div(mz, kDcChunk));
         if (upd)
             hipLaunchKernelGGL((k_dc_outer3_pair<TL, true>), grid, dim3(kBlock), 0, st, g,
                                DcIn<TL, true>{phi_in, e_in, factor}, phi_out, f, inv_h2, rscale, r, e_out, first_red,
@@ -2801,9 +2844,9 @@ void launch_dc_outer(int dim, hipStream_t st, SGrid g, const double* phi_in, con
         return;
     }
     if (dim == 3) {
-        long m = g.nx - 2;
+        long mz = g.nz - 2;
         int pblocks = ceil_div((long)g.ps, kBlock);
-        dim3 grid(pblocks * ceil_div(m, kNormChunk));
+        dim3 grid(pblocks * ceil_div(mz, kNormChunk));
         if (upd)
             hipLaunchKernelGGL((k_dc_outer3<TL, true>), grid, dim3(kBlock), 0, st, g, DcIn<TL, true>{phi_in, e_in, factor},
                                phi_out, f, inv_h2, rscale, r, e_out, first_red, h2l, inv2d, pblocks, maxbits);
@@ -2883,7 +2926,9 @@ template void launch_dc_scale<__half>(int, hipStream_t, SGrid, const float*, dou
 
 void launch_copy_ghosts(int dim, hipStream_t st, SGrid g, const double* src, double* dst)
 {
-    int per = dim == 3 ? g.nx * g.nx : g.nx;
+    // the largest face
+    const int m = g.nx > g.ny ? (g.nx > g.nz ? g.nx : g.nz) : (g.ny > g.nz ? g.ny : g.nz);
+    int per = dim == 3 ? m * m : m;
     dim3 grid(ceil_div(per, kBlock), 2 * dim);
     if (dim == 3)
         hipLaunchKernelGGL((k_copy_ghosts<3>), grid, dim3(kBlock), 0, st, g, src, dst);
@@ -2891,37 +2936,41 @@ void launch_copy_ghosts(int dim, hipStream_t st, SGrid g, const double* src, dou
         hipLaunchKernelGGL((k_copy_ghosts<2>), grid, dim3(kBlock), 0, st, g, src, dst);
 }
 
-void launch_copy_box(int dim, hipStream_t st, SGrid gs, const double* src, SGrid gd, double* dst, int lo, int hi,
-                     int shift)
+void launch_copy_box(int dim, hipStream_t st, SGrid gs, const double* src, SGrid gd, double* dst, int lo,
+                     const int* hi, int shift)
 {
-    const long w = hi - lo + 1;
-    if (w <= 0) return;
-    const long total = dim == 3 ? w * w * w : w * w;
-    dim3 grid(ceil_div(total, kBlock));
+    const long wx = hi[0] - lo + 1, wy = hi[1] - lo + 1, wz = dim == 3 ? hi[2] - lo + 1 : 1;
+    if (wx <= 0 || wy <= 0 || wz <= 0) return;
+    dim3 grid(ceil_div(wx * wy * wz, kBlock));
     if (dim == 3)
-        hipLaunchKernelGGL((k_copy_box<3>), grid, dim3(kBlock), 0, st, gs, src, gd, dst, lo, (int)w, shift);
+        hipLaunchKernelGGL((k_copy_box<3>), grid, dim3(kBlock), 0, st, gs, src, gd, dst, lo, (int)wx, (int)wy, (int)wz,
+                           shift);
     else
-        hipLaunchKernelGGL((k_copy_box<2>), grid, dim3(kBlock), 0, st, gs, src, gd, dst, lo, (int)w, shift);
+        hipLaunchKernelGGL((k_copy_box<2>), grid, dim3(kBlock), 0, st, gs, src, gd, dst, lo, (int)wx, (int)wy, 1,
+                           shift);
 }
 
-template void launch_half_sweep<double>(int, hipStream_t, SGrid, double*, const double*, int, double, int, int, double);
-template void launch_half_sweep<float>(int, hipStream_t, SGrid, float*, const float*, int, double, int, int, double);
-template void launch_half_sweep<__half>(int, hipStream_t, SGrid, __half*, const __half*, int, double, int, int, double);
+template void launch_half_sweep<double>(int, hipStream_t, SGrid, double*, const double*, int, double, int, const Rule3&);
+template void launch_half_sweep<float>(int, hipStream_t, SGrid, float*, const float*, int, double, int, const Rule3&);
+template void launch_half_sweep<__half>(int, hipStream_t, SGrid, __half*, const __half*, int, double, int,
+                                        const Rule3&);
 template void launch_half_sweep_seeded<float>(hipStream_t, SGrid, float*, const float*, double);
 template void launch_half_sweep_seeded<__half>(hipStream_t, SGrid, __half*, const __half*, double);
 template void launch_resid_restrict<double, double>(int, hipStream_t, SGrid, const double*, const double*, double,
-                                                    double, SGrid, double*, double*, int, int, double, double);
+                                                    double, SGrid, double*, double*, int, const Rule3&, double);
 template void launch_resid_restrict<float, float>(int, hipStream_t, SGrid, const float*, const float*, double, double,
-                                                  SGrid, float*, float*, int, int, double, double);
+                                                  SGrid, float*, float*, int, const Rule3&, double);
 template void launch_resid_restrict<__half, float>(int, hipStream_t, SGrid, const __half*, const __half*, double,
-                                                   double, SGrid, float*, float*, int, int, double, double);
-template void launch_prolong_add<double, double>(int, hipStream_t, SGrid, const double*, SGrid, double*, int, int, double);
-template void launch_prolong_add<float, float>(int, hipStream_t, SGrid, const float*, SGrid, float*, int, int, double);
-template void launch_prolong_add<float, __half>(int, hipStream_t, SGrid, const float*, SGrid, __half*, int, int, double);
-template int launch_coarse_tail<float>(int, hipStream_t, int, const int*, const double*, const int*, const double*,
-                                       int, int, SGrid, const float*, float*);
-template int launch_coarse_tail<double>(int, hipStream_t, int, const int*, const double*, const int*, const double*,
-                                        int, int, SGrid, const double*, double*);
+                                                   double, SGrid, float*, float*, int, const Rule3&, double);
+template void launch_prolong_add<double, double>(int, hipStream_t, SGrid, const double*, SGrid, double*, int,
+                                                 const Rule3&);
+template void launch_prolong_add<float, float>(int, hipStream_t, SGrid, const float*, SGrid, float*, int, const Rule3&);
+template void launch_prolong_add<float, __half>(int, hipStream_t, SGrid, const float*, SGrid, __half*, int,
+                                                const Rule3&);
+template int launch_coarse_tail<float>(int, hipStream_t, int, const int (*)[3], const double*, const Rule3*, int, int,
+                                       SGrid, const float*, float*);
+template int launch_coarse_tail<double>(int, hipStream_t, int, const int (*)[3], const double*, const Rule3*, int,
+                                        int, SGrid, const double*, double*);
 template void launch_dc_outer<float>(int, hipStream_t, SGrid, const double*, const float*, double, double*,
                                      const double*, double, double, float*, float*, int, unsigned long long*);
 template void launch_dc_outer<__half>(int, hipStream_t, SGrid, const double*, const __half*, double, double*,

@@ -552,13 +552,13 @@ __global__ void __launch_bounds__(kNB) k_net_features(SGrid g, const double* __r
                                                      const double* __restrict__ f, double inv_fnorm, double inv_h2,
                                                      TA* __restrict__ x)
 {
-    const int m = g.nx - 2;
-    const long nv = (long)m * m * m;
+    const int mx = g.nx - 2, my = g.ny - 2, mz = g.nz - 2;
+    const long nv = (long)mx * my * mz;
     const long v = (long)blockIdx.x * kNB + threadIdx.x;
     if (v >= nv) return;
-    const int i = (int)(v % m) + 1;
-    const int j = (int)((v / m) % m) + 1;
-    const int k = (int)(v / ((long)m * m)) + 1;
+    const int i = (int)(v % mx) + 1;
+    const int j = (int)((v / mx) % my) + 1;
+    const int k = (int)(v / ((long)mx * my)) + 1;
     auto at = [&](const double* a, int pi, int pj, int pk) {
         return a[(size_t)((pi + pj + pk + 3) & 1) * g.cs + ((size_t)pk * g.ps + (size_t)pj * g.hx) + (pi >> 1)];
     };
@@ -573,13 +573,13 @@ __global__ void __launch_bounds__(kNB) k_net_features(SGrid g, const double* __r
 __global__ void __launch_bounds__(kNB) k_net_apply(SGrid g, double* __restrict__ phi, const float* __restrict__ out,
                                                   double s)
 {
-    const int m = g.nx - 2;
-    const long nv = (long)m * m * m;
+    const int mx = g.nx - 2, my = g.ny - 2, mz = g.nz - 2;
+    const long nv = (long)mx * my * mz;
     const long v = (long)blockIdx.x * kNB + threadIdx.x;
     if (v >= nv) return;
-    const int i = (int)(v % m) + 1;
-    const int j = (int)((v / m) % m) + 1;
-    const int k = (int)(v / ((long)m * m)) + 1;
+    const int i = (int)(v % mx) + 1;
+    const int j = (int)((v / mx) % my) + 1;
+    const int k = (int)(v / ((long)mx * my)) + 1;
     phi[(size_t)((i + j + k + 3) & 1) * g.cs + ((size_t)k * g.ps + (size_t)j * g.hx) + (i >> 1)] += s * (double)out[v];
 }
 
@@ -587,13 +587,13 @@ __global__ void __launch_bounds__(kNB) k_net_apply(SGrid g, double* __restrict__
 __global__ void __launch_bounds__(kNB) k_net_target(SGrid g, const double* __restrict__ pa,
                                                    const double* __restrict__ pb, double inv_s, float* __restrict__ t)
 {
-    const int m = g.nx - 2;
-    const long nv = (long)m * m * m;
+    const int mx = g.nx - 2, my = g.ny - 2, mz = g.nz - 2;
+    const long nv = (long)mx * my * mz;
     const long v = (long)blockIdx.x * kNB + threadIdx.x;
     if (v >= nv) return;
-    const int i = (int)(v % m) + 1;
-    const int j = (int)((v / m) % m) + 1;
-    const int k = (int)(v / ((long)m * m)) + 1;
+    const int i = (int)(v % mx) + 1;
+    const int j = (int)((v / mx) % my) + 1;
+    const int k = (int)(v / ((long)mx * my)) + 1;
     const size_t p = (size_t)((i + j + k + 3) & 1) * g.cs + ((size_t)k * g.ps + (size_t)j * g.hx) + (i >> 1);
     t[v] = (float)((pa[p] - pb[p]) * inv_s);
 }
@@ -713,29 +713,29 @@ void net_to_bf16(hipStream_t st, const float* a, uint16_t* b, long n)
 void net_features_bf16(hipStream_t st, SGrid g, const double* phi, const double* f, double inv_fnorm, double inv_h2,
                        uint16_t* x)
 {
-    long m = g.nx - 2;
-    hipLaunchKernelGGL((k_net_features<uint16_t>), dim3(cdiv(m * m * m, kNB)), dim3(kNB), 0, st, g, phi, f, inv_fnorm,
+    const long nvox = (long)(g.nx - 2) * (g.ny - 2) * (g.nz - 2);
+    hipLaunchKernelGGL((k_net_features<uint16_t>), dim3(cdiv(nvox, kNB)), dim3(kNB), 0, st, g, phi, f, inv_fnorm,
                        inv_h2, x);
 }
 
 void net_features_f32(hipStream_t st, SGrid g, const double* phi, const double* f, double inv_fnorm, double inv_h2,
                       float* x)
 {
-    long m = g.nx - 2;
-    hipLaunchKernelGGL((k_net_features<float>), dim3(cdiv(m * m * m, kNB)), dim3(kNB), 0, st, g, phi, f, inv_fnorm,
+    const long nvox = (long)(g.nx - 2) * (g.ny - 2) * (g.nz - 2);
+    hipLaunchKernelGGL((k_net_features<float>), dim3(cdiv(nvox, kNB)), dim3(kNB), 0, st, g, phi, f, inv_fnorm,
                        inv_h2, x);
 }
 
 void net_apply(hipStream_t st, SGrid g, double* phi, const float* out, double s)
 {
-    long m = g.nx - 2;
-    hipLaunchKernelGGL(k_net_apply, dim3(cdiv(m * m * m, kNB)), dim3(kNB), 0, st, g, phi, out, s);
+    const long nvox = (long)(g.nx - 2) * (g.ny - 2) * (g.nz - 2);
+    hipLaunchKernelGGL(k_net_apply, dim3(cdiv(nvox, kNB)), dim3(kNB), 0, st, g, phi, out, s);
 }
 
 void net_target(hipStream_t st, SGrid g, const double* pa, const double* pb, double inv_s, float* t)
 {
-    long m = g.nx - 2;
-    hipLaunchKernelGGL(k_net_target, dim3(cdiv(m * m * m, kNB)), dim3(kNB), 0, st, g, pa, pb, inv_s, t);
+    const long nvox = (long)(g.nx - 2) * (g.ny - 2) * (g.nz - 2);
+    hipLaunchKernelGGL(k_net_target, dim3(cdiv(nvox, kNB)), dim3(kNB), 0, st, g, pa, pb, inv_s, t);
 }
 
 }  // namespace np

@@ -18,6 +18,14 @@ using namespace np;
 namespace {
 
 // ------------------------------------------------------------------ planning
+// Cells of level l along axis a (Sec. 2.1: counts per direction; a cube when
+// the per-axis extents are not given).
+int level_n(const np_config* c, int l, int a)
+{
+    if (a >= c->dim) return 1;
+    return c->extent[l][0] > 0 ? c->extent[l][a] : c->n[l];
+}
+
 // Validation of the nested geometry (Sec. 2.1): even cell counts of at least
 // 4, patches on whole coarse cells with one coarse cell of margin.
 bool validate(const np_config* c, char* why, size_t nwhy)
@@ -33,15 +41,17 @@ bool validate(const np_config* c, char* why, size_t nwhy)
     if (c->dim != 2 && c->dim != 3) return fail("dim must be 2 or 3 (got %d)", c->dim);
     if (c->nlevels < 1 || c->nlevels > NP_MAX_LEVELS) return fail("nlevels must be 1..%d (got %d)", NP_MAX_LEVELS, c->nlevels);
     for (int l = 0; l < c->nlevels; l++) {
-        int n = c->n[l];
-        if (n < 4 || (n & 1)) return fail("level %d: n must be even and >= 4 (got %d)", l, n);
-        if (n > 1 << 14) return fail("level %d: n too large (%d)", l, n);
+        for (int a = 0; a < c->dim; a++) {
+            const int n = level_n(c, l, a);
+            if (n < 4 || (n & 1)) return fail("level %d: cells along axis %d must be even and >= 4 (got %d)", l, a, n);
+            if (n > 1 << 14) return fail("level %d: too many cells along axis %d (%d)", l, a, n);
+        }
         if (l == 0) continue;
         const int p = c->parent[l];
         if (p < 0 || p >= l) return fail("level %d: parent %d must name an earlier entry", l, p);
         for (int a = 0; a < c->dim; a++) {
             int o = c->offset[l][a];
-            if (o < 1 || o + n / 2 > c->n[p] - 1)
+            if (o < 1 || o + level_n(c, l, a) / 2 > level_n(c, p, a) - 1)
                 return fail("level %d: offset leaves less than one coarse cell of margin on axis %d", l, a);
         }
         // patches refined out of the same parent do not overlap
@@ -49,8 +59,8 @@ bool validate(const np_config* c, char* why, size_t nwhy)
             if (c->parent[m] != p) continue;
             bool overlap = true;
             for (int a = 0; a < c->dim; a++) {
-                const int lo1 = c->offset[l][a], hi1 = lo1 + n / 2;
-                const int lo2 = c->offset[m][a], hi2 = lo2 + c->n[m] / 2;
+                const int lo1 = c->offset[l][a], hi1 = lo1 + level_n(c, l, a) / 2;
+                const int lo2 = c->offset[m][a], hi2 = lo2 + level_n(c, m, a) / 2;
                 if (hi1 <= lo2 || hi2 <= lo1) overlap = false;
             }
             if (overlap) return fail("levels %d and %d: patches of the same parent overlap", m, l);
@@ -77,15 +87,23 @@ bool validate(const np_config* c, char* why, size_t nwhy)
     return true;
 }
 
-// Sec. 2.2: N^0 = n + 2; N^L = round(N^0 / 2^L), halves up, until 1.
-int plan_levels(int N0, int* NL)
+// Sec. 2.2 along every axis: N^0_a = n_a + 2; N^L_a = round(N^0_a / 2^L),
+// halves up (the same doubling of h on every axis); the hierarchy ends on the
+// first level with one active cell along some axis.  NL[L][a]; returns the
+// number of levels.
+int plan_levels(int dim, const int* N0, int (*NL)[3])
 {
-    NL[0] = N0;
+    for (int a = 0; a < 3; a++) NL[0][a] = a < dim ? N0[a] : 1;
     int L = 0;
-    while (NL[L] > 1) {
+    for (;;) {
+        bool one = false;
+        for (int a = 0; a < dim; a++)
+            if (NL[L][a] <= 1) one = true;
+        if (one) break;
         if (L + 1 >= NP_MAX_MG) return -1;
         L++;
-        NL[L] = (int)(((long long)N0 + (1LL << (L - 1))) >> L);
+        for (int a = 0; a < 3; a++)
+            NL[L][a] = a < dim ? (int)(((long long)N0[a] + (1LL << (L - 1))) >> L) : 1;
     }
     return L + 1;
 }
@@ -103,26 +121,31 @@ void ghost_rule(int N0, int L, int N, int* one, double* coef)
     *coef = *one ? -1.0 : num / den;
 }
 
-// The kernels index coarse grids from fine ones; these bounds are what keeps
-// every access inside the padded arrays:
+// The kernels index coarse grids from fine ones; these bounds (per axis) are
+// what keeps every access inside the padded arrays:
 //   prolongation: fine active a in 1..Nf reads coarse ceil(a/2) and its
 //     neighbour towards a, so ceil(Nf/2) <= Nc + 1 and floor(Nf/2) <= Nc;
 //   restriction: coarse I in 1..Nc has children 2I-1, 2I <= Nf + 1;
 //   the x_N = 1 rule reads e_{N-1}, so N >= 2 there.
-bool plan_in_bounds(const np_plan* p, int l)
+bool plan_in_bounds(const np_plan* p, int l, int dim)
 {
-    for (int L = 0; L + 1 < p->nmg[l]; L++) {
-        int Nf = p->N[l][L], Nc = p->N[l][L + 1];
-        if ((Nf + 1) / 2 > Nc + 1 || Nf / 2 > Nc || 2 * Nc > Nf + 1) return false;
+    for (int a = 0; a < dim; a++) {
+        for (int L = 0; L + 1 < p->nmg[l]; L++) {
+            int Nf = p->N[l][L][a], Nc = p->N[l][L + 1][a];
+            if ((Nf + 1) / 2 > Nc + 1 || Nf / 2 > Nc || 2 * Nc > Nf + 1) return false;
+        }
+        for (int L = 1; L < p->nmg[l]; L++)
+            if (p->xn_is_one[l][L][a] && p->N[l][L][a] < 2) return false;
     }
-    for (int L = 1; L < p->nmg[l]; L++)
-        if (p->xn_is_one[l][L] && p->N[l][L] < 2) return false;
     return true;
 }
 
-// N^0 of nested level l: the patch and its inner buffer layer, or the patch
-// alone where the buffer keeps its interpolated values (levels l >= 1)
-int level_N0(const np_config* c, int l) { return (l > 0 && c->buffer == NP_BUFFER_INTERP) ? c->n[l] : c->n[l] + 2; }
+// N^0 of nested level l along axis a: the patch and its inner buffer layer, or
+// the patch alone where the buffer keeps its interpolated values (levels l >= 1)
+int level_N0(const np_config* c, int l, int a)
+{
+    return (l > 0 && c->buffer == NP_BUFFER_INTERP) ? level_n(c, l, a) : level_n(c, l, a) + 2;
+}
 
 // refinement depth of entry l (0 for the base level) and its cell size dx0 / 2^depth
 int level_depth(const np_config* c, int l)
@@ -136,16 +159,40 @@ int level_depth(const np_config* c, int l)
 }
 double level_dx(const np_config* c, int l) { return std::ldexp(c->dx0, -level_depth(c, l)); }
 
-int make_plan(const np_config* c, np_plan* p)
+// Returns NP_OK, or NP_EINVAL with the reason in `why`.
+int make_plan(const np_config* c, np_plan* p, char* why, size_t nwhy)
 {
     memset(p, 0, sizeof(*p));
+    const int d = c->dim;
     for (int l = 0; l < c->nlevels; l++) {
-        const int N0 = level_N0(c, l);
-        int m = plan_levels(N0, p->N[l]);
-        if (m < 2) return NP_EINVAL;
+        int N0[3];
+        for (int a = 0; a < 3; a++) N0[a] = a < d ? level_N0(c, l, a) : 1;
+        int m = plan_levels(d, N0, p->N[l]);
+        if (m < 2) {
+            snprintf(why, nwhy, "level %d: multigrid hierarchy too deep", l);
+            return NP_EINVAL;
+        }
         p->nmg[l] = m;
-        for (int L = 1; L < m; L++) ghost_rule(N0, L, p->N[l][L], &p->xn_is_one[l][L], &p->ghost_coef[l][L]);
-        if (!plan_in_bounds(p, l)) return NP_EINVAL;
+        for (int L = 1; L < m; L++)
+            for (int a = 0; a < 3; a++) {
+                if (a < d) {
+                    ghost_rule(N0[a], L, p->N[l][L][a], &p->xn_is_one[l][L][a], &p->ghost_coef[l][L][a]);
+                    if (!p->xn_is_one[l][L][a] && std::fabs(p->ghost_coef[l][L][a]) > NP_MAX_GHOST_GAIN * 2.0 * d) {
+                        snprintf(why, nwhy,
+                                 "level %d: right-ghost coefficient %.3g of multigrid level %d on axis %d exceeds "
+                                 "%g x 2d (the explicit ghost refresh would make the V-cycle diverge)",
+                                 l, p->ghost_coef[l][L][a], L, a, NP_MAX_GHOST_GAIN);
+                        return NP_EINVAL;
+                    }
+                } else {
+                    p->xn_is_one[l][L][a] = 0;
+                    p->ghost_coef[l][L][a] = 0.0;
+                }
+            }
+        if (!plan_in_bounds(p, l, d)) {
+            snprintf(why, nwhy, "level %d: multigrid hierarchy out of the kernels' index bounds", l);
+            return NP_EINVAL;
+        }
     }
     return NP_OK;
 }
@@ -205,15 +252,14 @@ struct np_solver {
     void* e_lo = nullptr;
     void* e_nx = nullptr;
     void* r_lo = nullptr;
-    // padded points per axis of the grid whose ghost layers in e_lo, e_nx and
-    // r_lo are known to be zero (no kernel writes a ghost point of these
-    // arrays; -1: not cleared yet)
-    int lo_ghost_nx = -1;
+    // the grid whose ghost layers in e_lo, e_nx and r_lo are known to be zero
+    // (no kernel writes a ghost point of these arrays; -1: not cleared yet)
+    SGrid lo_ghost_grid{-1, -1, -1, 0, 0, 0};
     // f - lap phi of a level's starting potential in FP32 (active points; zero
-    // elsewhere, cleared when the grid changes: r32_nx), from which its first
+    // elsewhere, cleared when the grid changes: r32_grid), from which its first
     // scaled defect is formed
     float* r32 = nullptr;
-    int r32_nx = -1;
+    SGrid r32_grid{-1, -1, -1, 0, 0, 0};
     size_t lo_bytes = 0;
     double* phi_alt = nullptr;
     size_t alt_cap = 0;
@@ -264,7 +310,30 @@ int set_err(np_solver* s, int code, const char* fmt, ...)
         if (e_ != hipSuccess) return set_err((s), NP_EHIP, "%s: %s", #call, hipGetErrorString(e_)); \
     } while (0)
 
-SGrid mg_grid(const np_solver* s, int l, int L) { return make_grid(s->cfg.dim, s->plan.N[l][L] + 2); }
+SGrid mg_grid(const np_solver* s, int l, int L)
+{
+    const int* N = s->plan.N[l][L];
+    return make_grid(s->cfg.dim, N[0] + 2, N[1] + 2, N[2] + 2);
+}
+
+// padded grid of nested level l (n_a + 4 points per axis)
+SGrid level_grid(const np_config* c, int l)
+{
+    return make_grid(c->dim, level_n(c, l, 0) + 4, level_n(c, l, 1) + 4, level_n(c, l, 2) + 4);
+}
+
+// right-ghost rule of multigrid level L of nested level l, per axis
+Rule3 rule_of(const np_solver* s, int l, int L)
+{
+    Rule3 r{};
+    for (int a = 0; a < 3; a++) {
+        r.xn1[a] = s->plan.xn_is_one[l][L][a];
+        r.coef[a] = s->plan.ghost_coef[l][L][a];
+    }
+    return r;
+}
+
+bool same_grid(const SGrid& a, const SGrid& b) { return a.nx == b.nx && a.ny == b.ny && a.nz == b.nz; }
 
 // Fold the recorded event pairs into the per-class totals (synchronises).
 int prof_flush(np_solver* s)
@@ -344,13 +413,13 @@ template <typename T>
 void coarse_sweep(const np_solver* s, int l, const MGView<T>& v, int L, hipStream_t st, int first_colour = 0)
 {
     const int d = s->cfg.dim;
+    const Rule3 rule = rule_of(s, l, L);
     for (int colour = first_colour; colour < 2; colour++)
-        launch_half_sweep<T>(d, st, v.g[L], v.u[L], v.f[L], colour, v.h[L] * v.h[L], 0, s->plan.xn_is_one[l][L],
-                             s->plan.ghost_coef[l][L]);
+        launch_half_sweep<T>(d, st, v.g[L], v.u[L], v.f[L], colour, v.h[L] * v.h[L], 0, rule);
 }
 
 // First multigrid level of the coarse tail of nested level l (the levels from
-// there to the one-point level fit in LDS together, elements of esz bytes),
+// there to the coarsest level fit in LDS together, elements of esz bytes),
 // or 0 if none does.
 int tail_level(const np_solver* s, int l, size_t esz)
 {
@@ -378,15 +447,14 @@ void coarse_part(const np_solver* s, int l, const MGView<T>& v, hipStream_t st)
     const int Lt = tail_level(s, l, sizeof(T));
     auto tail = [&](int L0) {
         const int nlev = s->plan.nmg[l] - L0;
-        int N[kTailMaxLevels], xn[kTailMaxLevels];
-        double h[kTailMaxLevels], coef[kTailMaxLevels];
+        double h[kTailMaxLevels];
+        Rule3 rules[kTailMaxLevels];
         for (int a = 0; a < nlev; a++) {
-            N[a] = s->plan.N[l][L0 + a];
-            xn[a] = s->plan.xn_is_one[l][L0 + a];
-            coef[a] = s->plan.ghost_coef[l][L0 + a];
+            rules[a] = rule_of(s, l, L0 + a);
             h[a] = v.h[L0 + a];
         }
-        launch_coarse_tail<T>(d, st, nlev, N, h, xn, coef, c.n_pre, c.n_post, v.g[L0], v.f[L0], v.u[L0]);
+        launch_coarse_tail<T>(d, st, nlev, &s->plan.N[l][L0], h, rules, c.n_pre, c.n_post, v.g[L0], v.f[L0],
+                              v.u[L0]);
     };
     if (Lt == 1) {
         tail(1);
@@ -396,11 +464,10 @@ void coarse_part(const np_solver* s, int l, const MGView<T>& v, hipStream_t st)
     // that level's first red half sweep (seeded correction)
     for (int it = 0; it < c.n_pre; it++) coarse_sweep(s, l, v, 1, st, it == 0 ? 1 : 0);
     int L = 1;
-    while (s->plan.N[l][L] > 1) {
+    while (L + 1 < s->plan.nmg[l]) {
         const bool seed = c.n_pre > 0 && L + 1 != Lt;
         launch_resid_restrict<T, T>(d, st, v.g[L], v.u[L], v.f[L], 1.0 / (v.h[L] * v.h[L]), 1.0, v.g[L + 1], v.f[L + 1],
-                                    v.u[L + 1], 1, s->plan.xn_is_one[l][L], s->plan.ghost_coef[l][L],
-                                    seed ? v.h[L + 1] * v.h[L + 1] : 0.0);
+                                    v.u[L + 1], 1, rule_of(s, l, L), seed ? v.h[L + 1] * v.h[L + 1] : 0.0);
         if (L + 1 == Lt) {
             tail(Lt);
             L = Lt;
@@ -410,8 +477,7 @@ void coarse_part(const np_solver* s, int l, const MGView<T>& v, hipStream_t st)
         L++;
     }
     while (L > 1) {
-        launch_prolong_add<T, T>(d, st, v.g[L], v.u[L], v.g[L - 1], v.u[L - 1], 0, s->plan.xn_is_one[l][L],
-                                 s->plan.ghost_coef[l][L]);
+        launch_prolong_add<T, T>(d, st, v.g[L], v.u[L], v.g[L - 1], v.u[L - 1], 0, rule_of(s, l, L));
         for (int it = 0; it < c.n_post; it++) coarse_sweep(s, l, v, L - 1, st);
         L--;
     }
@@ -467,7 +533,7 @@ int vcycle_t(np_solver* s, int l, T0* u0, const T0* f0, double h2_0, double inv_
                     seeded = true;
                 }
             }
-            if (!seeded) launch_half_sweep<T0>(d, st, v.g[0], u0, f0, colour, h2_0, 1, 0, 0.0);
+            if (!seeded) launch_half_sweep<T0>(d, st, v.g[0], u0, f0, colour, h2_0, 1, Rule3{});
             nsweep++;
             red_done = false;
         }
@@ -484,7 +550,7 @@ int vcycle_t(np_solver* s, int l, T0* u0, const T0* f0, double h2_0, double inv_
     // coarse tail starts at level 1 (coarse_part then skips it)
     const bool seed1 = c.n_pre > 0 && tail_level(s, l, sizeof(TC)) != 1;
     prof_begin(s, NP_KCLASS_RESTRICT);
-    launch_resid_restrict<T0, TC>(d, st, v.g[0], u0, f0, inv_h2_0, out_scale_0, v.g[1], v.f[1], v.u[1], 0, 0, 0.0,
+    launch_resid_restrict<T0, TC>(d, st, v.g[0], u0, f0, inv_h2_0, out_scale_0, v.g[1], v.f[1], v.u[1], 0, Rule3{},
                                   seed1 ? v.h[1] * v.h[1] : 0.0);
     prof_end(s);
     prof_begin(s, NP_KCLASS_COARSE);
@@ -494,8 +560,7 @@ int vcycle_t(np_solver* s, int l, T0* u0, const T0* f0, double h2_0, double inv_
     prof_begin(s, NP_KCLASS_PROLONG);
     // on level 0 (fixed ghost layer) the red corrections are dead when a
     // post-smoothing red half sweep follows: it reads only black points
-    launch_prolong_add<TC, T0>(d, st, v.g[1], v.u[1], v.g[0], u0, c.n_post > 0, s->plan.xn_is_one[l][1],
-                               s->plan.ghost_coef[l][1]);
+    launch_prolong_add<TC, T0>(d, st, v.g[1], v.u[1], v.g[0], u0, c.n_post > 0, rule_of(s, l, 1));
     prof_end(s);
     smooth0(c.n_post);
     return NP_OK;
@@ -551,7 +616,7 @@ int force_delta_sync(np_solver* s, int l, double* out)
 {
     double dx = level_dx(&s->cfg, l);
     launch_set_u64(s->stream, s->d_bits + 1, 1, 0ULL);
-    launch_force_delta(s->cfg.dim, s->stream, s->lg[l], s->cfg.n[l], dx, s->phi[l], s->force_scratch, s->d_bits + 1);
+    launch_force_delta(s->cfg.dim, s->stream, s->lg[l], dx, s->phi[l], s->force_scratch, s->d_bits + 1);
     HIPCHK(s, hipGetLastError());
     HIPCHK(s, hipMemcpyAsync(s->h_bits + 1, s->d_bits + 1, sizeof(unsigned long long), hipMemcpyDeviceToHost, s->stream));
     HIPCHK(s, hipStreamSynchronize(s->stream));
@@ -601,9 +666,9 @@ int dc_first_residual(np_solver* s, int l, double* out)
 {
     const np_config& c = s->cfg;
     double dx = level_dx(&c, l);
-    if (s->lg[l].nx != s->r32_nx) {
+    if (!same_grid(s->lg[l], s->r32_grid)) {
         HIPCHK(s, hipMemsetAsync(s->r32, 0, 2 * s->lg[l].cs * sizeof(float), s->stream));
-        s->r32_nx = s->lg[l].nx;
+        s->r32_grid = s->lg[l];
     }
     launch_set_u64(s->stream, s->d_bits, 1, 0ULL);
     prof_begin(s, NP_KCLASS_NORM);
@@ -718,16 +783,16 @@ int learned_guess(np_solver* s, int l, const double* rho_l, double fourpiG, doub
     const np_config& c = s->cfg;
     hipStream_t st = s->stream;
     SGrid g = s->lg[l];
-    const int m = g.nx - 2;
+    const int X = g.nx - 2, Y = g.ny - 2, Z = g.nz - 2;
     const double dx = level_dx(&c, l);
     double rb_interp = 0.0;
     int rc = box_resid_sync(s, l, &rb_interp);
     if (rc) return rc;
     prof_begin(s, NP_KCLASS_GUESS);
     net_features_bf16(st, g, s->phi[l], s->f[l], 1.0 / fnorm, 1.0 / (dx * dx), s->net_x);
-    net_conv_mfma(st, s->net_x, 2, s->net_w[0], s->net_b[0], 16, 1, 1, m, m, m, s->net_a1);
-    net_conv_mfma(st, s->net_a1, 16, s->net_w[1], s->net_b[1], 16, 1, 1, m, m, m, s->net_a2);
-    net_conv_mfma(st, s->net_a2, 16, s->net_w[2], s->net_b[2], 1, 0, 1, m, m, m, s->net_out);
+    net_conv_mfma(st, s->net_x, 2, s->net_w[0], s->net_b[0], 16, 1, 1, Z, Y, X, s->net_a1);
+    net_conv_mfma(st, s->net_a1, 16, s->net_w[1], s->net_b[1], 16, 1, 1, Z, Y, X, s->net_a2);
+    net_conv_mfma(st, s->net_a2, 16, s->net_w[2], s->net_b[2], 1, 0, 1, Z, Y, X, s->net_out);
     net_apply(st, g, s->phi[l], s->net_out, fnorm * dx * dx);
     prof_end(s);
     HIPCHK(s, hipGetLastError());
@@ -743,7 +808,7 @@ int learned_guess(np_solver* s, int l, const double* rho_l, double fourpiG, doub
         return NP_OK;
     }
     // fallback: restore the interpolated guess
-    launch_interface_fill(c.dim, st, s->lg[c.parent[l]], s->phi[c.parent[l]], s->f[c.parent[l]], g, c.n[l], c.offset[l][0],
+    launch_interface_fill(c.dim, st, s->lg[c.parent[l]], s->phi[c.parent[l]], s->f[c.parent[l]], g, c.offset[l][0],
                           c.offset[l][1], c.offset[l][2], rho_l, fourpiG, s->phi[l], s->f[l], nullptr);
     HIPCHK(s, hipGetLastError());
     return NP_OK;
@@ -874,11 +939,7 @@ int nested_poisson_plan(const np_config* cfg, np_plan* out)
 {
     if (!out) return NP_EINVAL;
     if (!validate(cfg, g_last_error, sizeof g_last_error)) return NP_EINVAL;
-    if (make_plan(cfg, out) != NP_OK) {
-        snprintf(g_last_error, sizeof g_last_error, "multigrid hierarchy too deep");
-        return NP_EINVAL;
-    }
-    return NP_OK;
+    return make_plan(cfg, out, g_last_error, sizeof g_last_error);
 }
 
 int nested_poisson_create(const np_config* cfg, void* hip_stream, np_solver** out)
@@ -889,7 +950,7 @@ int nested_poisson_create(const np_config* cfg, void* hip_stream, np_solver** ou
     np_solver* s = new (std::nothrow) np_solver();
     if (!s) return NP_ENOMEM;
     s->cfg = *cfg;
-    if (make_plan(cfg, &s->plan) != NP_OK) {
+    if (make_plan(cfg, &s->plan, g_last_error, sizeof g_last_error) != NP_OK) {
         delete s;
         return NP_EINVAL;
     }
@@ -907,14 +968,15 @@ int nested_poisson_create(const np_config* cfg, void* hip_stream, np_solver** ou
     s->stream = (hipStream_t)hip_stream;
     const int d = cfg->dim;
     int rc = NP_OK;
-    int maxn = 0;
+    size_t max_cells = 0;  // largest Omega^l
     for (int l = 0; l < cfg->nlevels && rc == NP_OK; l++) {
-        s->lg[l] = make_grid(d, cfg->n[l] + 4);
+        s->lg[l] = level_grid(cfg, l);
         size_t bytes = 2 * s->lg[l].cs * sizeof(double);
         rc = alloc_dev(s, (void**)&s->phi[l], bytes);
         if (rc == NP_OK) rc = alloc_dev(s, (void**)&s->f[l], bytes);
         s->phi_cap[l] = bytes;
-        if (cfg->n[l] > maxn) maxn = cfg->n[l];
+        const size_t cells = (size_t)level_n(cfg, l, 0) * level_n(cfg, l, 1) * level_n(cfg, l, 2);
+        if (cells > max_cells) max_cells = cells;
     }
     // multigrid scratch: per level L the largest grid over the nested levels,
     // FP64 for the plain solve, FP32 for the defect correction's inner cycles
@@ -923,7 +985,7 @@ int nested_poisson_create(const np_config* cfg, void* hip_stream, np_solver** ou
         size_t best = 0;
         for (int l = 0; l < cfg->nlevels; l++)
             if (L < s->plan.nmg[l]) {
-                size_t b = 2 * make_grid(d, s->plan.N[l][L] + 2).cs;
+                size_t b = 2 * mg_grid(s, l, L).cs;
                 if (b > best) best = b;
             }
         if (!best) break;
@@ -938,7 +1000,7 @@ int nested_poisson_create(const np_config* cfg, void* hip_stream, np_solver** ou
     if (rc == NP_OK && cfg->buffer == NP_BUFFER_INTERP && cfg->nlevels > 1) {
         size_t best = 0;
         for (int l = 1; l < cfg->nlevels; l++) {
-            s->ag[l] = make_grid(d, cfg->n[l] + 2);
+            s->ag[l] = make_grid(d, level_n(cfg, l, 0) + 2, level_n(cfg, l, 1) + 2, level_n(cfg, l, 2) + 2);
             if (2 * s->ag[l].cs > best) best = 2 * s->ag[l].cs;
         }
         rc = alloc_dev(s, (void**)&s->ab_phi, best * sizeof(double));
@@ -960,8 +1022,8 @@ int nested_poisson_create(const np_config* cfg, void* hip_stream, np_solver** ou
     if (rc == NP_OK && cfg->guess == NP_GUESS_LEARNED) {
         size_t vox = 0;
         for (int l = 1; l < cfg->nlevels; l++) {
-            size_t m = (size_t)cfg->n[l] + 2;
-            if (m * m * m > vox) vox = m * m * m;
+            const size_t m = ((size_t)level_n(cfg, l, 0) + 2) * (level_n(cfg, l, 1) + 2) * (level_n(cfg, l, 2) + 2);
+            if (m > vox) vox = m;
         }
         const int cin[3] = {2, 16, 16}, cout[3] = {16, 16, 1};
         for (int k = 0; k < 3 && rc == NP_OK; k++) {
@@ -975,10 +1037,8 @@ int nested_poisson_create(const np_config* cfg, void* hip_stream, np_solver** ou
             if (rc == NP_OK) rc = alloc_dev(s, (void**)&s->net_out, vox * sizeof(float));
         }
     }
-    if (rc == NP_OK && cfg->stop_rule == NP_STOP_FORCE_DELTA) {
-        size_t cells = (size_t)maxn * maxn * (d == 3 ? maxn : 1);
-        rc = alloc_dev(s, (void**)&s->force_scratch, (size_t)d * cells * sizeof(double));
-    }
+    if (rc == NP_OK && cfg->stop_rule == NP_STOP_FORCE_DELTA)
+        rc = alloc_dev(s, (void**)&s->force_scratch, (size_t)d * max_cells * sizeof(double));
     if (rc == NP_OK) rc = alloc_dev(s, (void**)&s->d_bits, 8 * sizeof(unsigned long long));
     if (rc == NP_OK && hipHostMalloc((void**)&s->h_bits, 8 * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
@@ -1041,7 +1101,7 @@ int nested_poisson_solve(np_solver* s, const double* const* rho, const double* p
         if (l == 0) {
             launch_level0_init(d, s->stream, s->lg[0], rho[0], phi_outer, fourpiG, s->phi[0], s->f[0], s->d_bits + 2);
         } else {
-            launch_interface_fill(d, s->stream, s->lg[c.parent[l]], s->phi[c.parent[l]], s->f[c.parent[l]], s->lg[l], c.n[l],
+            launch_interface_fill(d, s->stream, s->lg[c.parent[l]], s->phi[c.parent[l]], s->f[c.parent[l]], s->lg[l],
                                   c.offset[l][0], c.offset[l][1], d == 3 ? c.offset[l][2] : 0, rho[l], fourpiG,
                                   s->phi[l], s->f[l], s->d_bits + 2);
         }
@@ -1057,10 +1117,12 @@ int nested_poisson_solve(np_solver* s, const double* const* rho, const double* p
         // comparison scheme: Omega^l alone is relaxed, with the interpolated inner
         // buffer layer as its Dirichlet data; its |f| sets the stop test's scale
         const bool interp_buffer = l > 0 && c.buffer == NP_BUFFER_INTERP;
+        // last padded index of Omega^l in the relaxed domain's array, per axis
+        const int box_hi[3] = {level_n(&c, l, 0) + 1, level_n(&c, l, 1) + 1, level_n(&c, l, 2) + 1};
         if (interp_buffer) {
             prof_begin(s, NP_KCLASS_FILL);
-            launch_copy_box(d, s->stream, s->lg[l], s->phi[l], s->ag[l], s->ab_phi, 0, c.n[l] + 1, 1);
-            launch_copy_box(d, s->stream, s->lg[l], s->f[l], s->ag[l], s->ab_f, 0, c.n[l] + 1, 1);
+            launch_copy_box(d, s->stream, s->lg[l], s->phi[l], s->ag[l], s->ab_phi, 0, box_hi, 1);
+            launch_copy_box(d, s->stream, s->lg[l], s->f[l], s->ag[l], s->ab_f, 0, box_hi, 1);
             prof_end(s);
             HIPCHK(s, hipGetLastError());
         }
@@ -1111,12 +1173,12 @@ int nested_poisson_solve(np_solver* s, const double* const* rho, const double* p
             // cleared whole when this level's grid differs from the one they were
             // last cleared for (every kernel writes their active points only, and
             // each active point is written before it is read within a level)
-            if (s->lg[l].nx != s->lo_ghost_nx) {
+            if (!same_grid(s->lg[l], s->lo_ghost_grid)) {
                 size_t esz = c.precision == NP_PREC_FP16S_DC ? sizeof(__half) : sizeof(float);
                 HIPCHK(s, hipMemsetAsync(s->e_lo, 0, 2 * s->lg[l].cs * esz, s->stream));
                 HIPCHK(s, hipMemsetAsync(s->e_nx, 0, 2 * s->lg[l].cs * esz, s->stream));
                 HIPCHK(s, hipMemsetAsync(s->r_lo, 0, 2 * s->lg[l].cs * esz, s->stream));
-                s->lo_ghost_nx = s->lg[l].nx;
+                s->lo_ghost_grid = s->lg[l];
             }
             // the outer pass writes only active points of the other potential
             // buffer: give it this level's fixed ghost layer
@@ -1179,7 +1241,7 @@ int nested_poisson_solve(np_solver* s, const double* const* rho, const double* p
         if (interp_buffer) {
             // the relaxed values back into Omega^l of the level's array
             prof_begin(s, NP_KCLASS_FILL);
-            launch_copy_box(d, s->stream, s->lg[l], s->phi[l], dom.g, dom.phi, 2, c.n[l] + 1, -1);
+            launch_copy_box(d, s->stream, s->lg[l], s->phi[l], dom.g, dom.phi, 2, box_hi, -1);
             prof_end(s);
             HIPCHK(s, hipGetLastError());
         }
@@ -1230,8 +1292,7 @@ int nested_poisson_forces(np_solver* s, int level, double* fx, double* fy, doubl
     if (!s->solved) return set_err(s, NP_ESTATE, "forces requested before a successful solve");
     HIPCHK(s, hipSetDevice(s->device));
     prof_begin(s, NP_KCLASS_FORCES);
-    launch_forces(s->cfg.dim, s->stream, s->lg[level], s->cfg.n[level], level_dx(&s->cfg, level),
-                  s->phi[level], fx, fy, fz);
+    launch_forces(s->cfg.dim, s->stream, s->lg[level], level_dx(&s->cfg, level), s->phi[level], fx, fy, fz);
     prof_end(s);
     HIPCHK(s, hipGetLastError());
     return NP_OK;
@@ -1370,8 +1431,9 @@ int nested_poisson_guess_features(np_solver* s, int level, float* x, float* targ
     const int l = level;
     double dx = level_dx(&c, l);
     double fourpiG = 4.0 * M_PI * c.G;
-    launch_interface_fill(c.dim, s->stream, s->lg[c.parent[l]], s->phi[c.parent[l]], s->f[c.parent[l]], s->lg[l], c.n[l], c.offset[l][0],
-                          c.offset[l][1], c.offset[l][2], s->f[l], 0.0, s->feat_phi, s->feat_f, nullptr);
+    launch_interface_fill(c.dim, s->stream, s->lg[c.parent[l]], s->phi[c.parent[l]], s->f[c.parent[l]], s->lg[l],
+                          c.offset[l][0], c.offset[l][1], c.offset[l][2], s->f[l], 0.0, s->feat_phi, s->feat_f,
+                          nullptr);
     double fnorm = 0.0;
     int rc = norm_sync(s, l, 1, &fnorm);
     if (rc) return rc;

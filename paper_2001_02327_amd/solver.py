@@ -2,8 +2,8 @@
 
 Device memory comes from torch (ROCm) tensors; every step of the solve runs
 in the HIP library.  Inputs are float64 tensors on the solver's device,
-indexed [k, j, i] (x fastest):
-    rho[0]: (n0+2)^d, rho[l>=1]: n_l^d, phi_outer: (n0+4)^d.
+indexed [k, j, i] (x fastest), shapes per axis from the geometry:
+    rho[0]: n0_a + 2, rho[l>=1]: n_l,a, phi_outer: n0_a + 4.
 """
 import ctypes
 
@@ -18,7 +18,7 @@ class NestedPoissonSolver:
             raise RuntimeError("NestedPoissonSolver needs a HIP device")
         self.geom = geom
         self.dim = int(geom.dim)
-        self.n = [int(v) for v in geom.n]
+        self.n = list(geom.n)
         self.cfg = _lib.make_config(geom, **settings)
         self.device = torch.device("cuda", torch.cuda.current_device())
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
@@ -35,6 +35,12 @@ class NestedPoissonSolver:
             raise _lib.NestedPoissonError(rc, _lib.lib().nested_poisson_last_error(self._h).decode())
         return rc
 
+    def _shape(self, l, pad):
+        """[k, j, i] shape of level l's cells with `pad` extra cells on every side."""
+        n = self.n[l]
+        ext = tuple(n) if isinstance(n, (tuple, list)) else (int(n),) * self.dim
+        return tuple(v + 2 * pad for v in reversed(ext))
+
     def _tensor(self, t, shape, name):
         if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or t.device != self.device:
             raise TypeError("%s must be a float64 tensor on %s" % (name, self.device))
@@ -46,9 +52,9 @@ class NestedPoissonSolver:
         d = self.dim
         if len(rho) != len(self.n):
             raise ValueError("need one density array per level")
-        rho = [self._tensor(rho[0], (self.n[0] + 2,) * d, "rho[0]")] + \
-              [self._tensor(rho[l], (self.n[l],) * d, "rho[%d]" % l) for l in range(1, len(self.n))]
-        phi_outer = self._tensor(phi_outer, (self.n[0] + 4,) * d, "phi_outer")
+        rho = [self._tensor(rho[0], self._shape(0, 1), "rho[0]")] + \
+              [self._tensor(rho[l], self._shape(l, 0), "rho[%d]" % l) for l in range(1, len(self.n))]
+        phi_outer = self._tensor(phi_outer, self._shape(0, 2), "phi_outer")
         ptrs = (ctypes.c_void_p * len(rho))(*[r.data_ptr() for r in rho])
         st = _lib.NpStats()
         rc = _lib.lib().nested_poisson_solve(self._h, ptrs, ctypes.c_void_p(phi_outer.data_ptr()), ctypes.byref(st))
@@ -83,21 +89,22 @@ class NestedPoissonSolver:
         return [buf[i] for i in range(m)]
 
     def forces(self, level, out=None):
-        n, d = self.n[level], self.dim
+        d = self.dim
+        shp = self._shape(level, 0)
         if out is None:
-            out = [torch.empty((n,) * d, dtype=torch.float64, device=self.device) for _ in range(d)]
+            out = [torch.empty(shp, dtype=torch.float64, device=self.device) for _ in range(d)]
         for a, t in enumerate(out):
-            self._tensor(t, (n,) * d, "force[%d]" % a)
+            self._tensor(t, shp, "force[%d]" % a)
         fz = out[2].data_ptr() if d == 3 else None
         self._check(_lib.lib().nested_poisson_forces(self._h, level, ctypes.c_void_p(out[0].data_ptr()),
                                                      ctypes.c_void_p(out[1].data_ptr()), ctypes.c_void_p(fz)))
         return tuple(out)
 
     def potential(self, level, out=None):
-        n, d = self.n[level], self.dim
+        shp = self._shape(level, 2)
         if out is None:
-            out = torch.empty((n + 4,) * d, dtype=torch.float64, device=self.device)
-        self._tensor(out, (n + 4,) * d, "phi")
+            out = torch.empty(shp, dtype=torch.float64, device=self.device)
+        self._tensor(out, shp, "phi")
         self._check(_lib.lib().nested_poisson_potential(self._h, level, ctypes.c_void_p(out.data_ptr())))
         return out
 
@@ -110,10 +117,10 @@ class NestedPoissonSolver:
 
     def guess_features(self, level, with_target=True):
         """(x, target) of the learned guess for a level >= 1 after a solve:
-        x is (n+2)^3 x 2 channel-last, target (n+2)^3 (FP32 device tensors)."""
-        m = self.n[level] + 2
-        x = torch.empty((m, m, m, 2), dtype=torch.float32, device=self.device)
-        t = torch.empty((m, m, m), dtype=torch.float32, device=self.device) if with_target else None
+        x is Gamma^l's shape x 2 channel-last, target Gamma^l's shape (FP32 device tensors)."""
+        shp = self._shape(level, 1)
+        x = torch.empty(shp + (2,), dtype=torch.float32, device=self.device)
+        t = torch.empty(shp, dtype=torch.float32, device=self.device) if with_target else None
         self._check(_lib.lib().nested_poisson_guess_features(self._h, level, ctypes.c_void_p(x.data_ptr()),
                                                              ctypes.c_void_p(t.data_ptr() if t is not None else 0)))
         return x, t

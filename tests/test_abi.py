@@ -45,35 +45,50 @@ def test_library_links_no_oracle():
     assert "oracle" not in ldd
 
 
+def _check_plan(wl, interp_buffer=False):
+    cfg = _lib.make_config(wl.geom, buffer="interp" if interp_buffer else "relaxed")
+    plan = _lib.plan(cfg)
+    d = wl.geom.dim
+    for l, p in enumerate(plan):
+        N0 = tuple(v + (0 if (interp_buffer and l > 0) else 2) for v in wl.geom.ext(l))
+        assert p["N"] == core.plan3(d, N0)
+        for L in range(1, len(p["N"])):
+            for a in range(d):
+                one, c = core.ghost_rule(N0[a], L, p["N"][L][a])
+                assert bool(p["xn_is_one"][L][a]) == one
+                if not one:
+                    assert p["coef"][L][a] == c  # same rational, one rounding
+
+
 @pytest.mark.parametrize("wl", [W.c1_gaussian_2d(64), W.c2_plummer(128), W.c3_plummer_offset(256),
-                                W.c5_two_plummer(512), W.paper2d(1024), W.paper3d(10 * 4)],
+                                W.c5_two_plummer(512), W.paper2d(1024), W.paper3d(10 * 4), W.box_plummer_3d(1),
+                                W.box_plummer_3d(8), W.box_gaussian_2d(4)],
                          ids=lambda w: w.name)
 def test_host_plan_matches_oracle(wl):
-    cfg = _lib.make_config(wl.geom)
-    plan = _lib.plan(cfg)
-    for l, p in enumerate(plan):
-        N0 = wl.geom.n[l] + 2
-        assert p["N"] == core.plan(N0)
-        for L in range(1, len(p["N"])):
-            one, c = core.ghost_rule(N0, L, p["N"][L])
-            assert bool(p["xn_is_one"][L]) == one
-            if not one:
-                assert p["coef"][L] == c  # same rational, one rounding
+    _check_plan(wl)
 
 
-@pytest.mark.parametrize("wl", [W.c2_plummer(128), W.paper2d(64), W.c5_two_plummer(512)], ids=lambda w: w.name)
+@pytest.mark.parametrize("wl", [W.c2_plummer(128), W.paper2d(64), W.c5_two_plummer(512), W.box_plummer_3d(2)],
+                         ids=lambda w: w.name)
 def test_host_plan_interp_buffer(wl):
     """With the interpolated buffer, levels l >= 1 plan their hierarchy from
     N^0 = n (Omega^l alone), level 0 from n + 2 as before."""
-    plan = _lib.plan(_lib.make_config(wl.geom, buffer="interp"))
-    for l, p in enumerate(plan):
-        N0 = wl.geom.n[l] + (2 if l == 0 else 0)
-        assert p["N"] == core.plan(N0)
-        for L in range(1, len(p["N"])):
-            one, c = core.ghost_rule(N0, L, p["N"][L])
-            assert bool(p["xn_is_one"][L]) == one
-            if not one:
-                assert p["coef"][L] == c
+    _check_plan(wl, interp_buffer=True)
+
+
+def test_host_plan_refuses_steep_ghost_lines():
+    """A hierarchy whose right-ghost gain |c| / (2d) exceeds NP_MAX_GHOST_GAIN
+    (N^0 = 194: c = -63 on multigrid level 7) is refused with a message, as
+    the oracle refuses it; one just inside the bound is accepted."""
+    bad = W.box_geometry(2, (192, 200), (8, 16), (2, 4), dx0=1.0 / 16)
+    with pytest.raises(_lib.NestedPoissonError) as ei:
+        _lib.plan(_lib.make_config(bad))
+    assert ei.value.code == _lib.NP_EINVAL
+    assert "right-ghost coefficient" in str(ei.value)
+    assert not core.plan_stable(2, (194, 202))
+    ok = W.box_geometry(2, (196, 200), (8, 16), (2, 4), dx0=1.0 / 16)
+    _lib.plan(_lib.make_config(ok))
+    assert core.plan_stable(2, (198, 202))
 
 
 def _bad(**kw):
@@ -124,11 +139,23 @@ def test_null_handle_calls_are_safe():
 
 def test_plan_accepts_every_even_patch_size():
     """Every even n (so every N^0 = n + 2) plans within the index bounds the
-    kernels rely on (checked inside nested_poisson_plan)."""
+    kernels rely on (checked inside nested_poisson_plan), unless a level's
+    right-ghost gain is beyond the bound, exactly where the oracle refuses it
+    too (297 of the 2998 sizes, 192, 320, 384, ... among them; none of the
+    paper's or the benchmark's)."""
+    refused = []
     for n in range(4, 6000, 2):
         g = W.Geometry(dim=3, n=[n], off=[(0, 0, 0)], lo0=(0, 0, 0), dx0=1.0)
         cfg = _lib.make_config(g)
-        assert _lib.lib().nested_poisson_plan(ctypes.byref(cfg), ctypes.byref(_lib.NpPlan())) == 0, n
+        rc = _lib.lib().nested_poisson_plan(ctypes.byref(cfg), ctypes.byref(_lib.NpPlan()))
+        stable = core.plan_stable(3, (n + 2,) * 3)
+        assert (rc == 0) == stable, n
+        if rc:
+            assert b"right-ghost coefficient" in _lib.lib().nested_poisson_last_error(None), n
+            refused.append(n)
+    assert len(refused) == 297
+    for n in (16, 32, 64, 128, 256, 512, 1020, 1024):
+        assert n not in refused
 
 
 def _tree_cfg(parent=None, off=None):
@@ -155,7 +182,7 @@ def test_patch_tree_plans_and_validates_like_the_oracle():
     assert _lib.lib().nested_poisson_plan(ctypes.byref(cfg), ctypes.byref(_lib.NpPlan())) == 0
     assert core.validate(W.two_patch_geometry(3, 32))
     plan = _lib.plan(cfg)
-    assert [p["N"][0] for p in plan] == [34, 18, 18, 18]
+    assert [p["N"][0] for p in plan] == [(34, 34, 34)] + [(18, 18, 18)] * 3
 
 
 @pytest.mark.parametrize("bad", [

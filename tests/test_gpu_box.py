@@ -1,0 +1,146 @@
+"""Non-cubic patches on the GPU against the oracle (Sec. 2.1: cell counts per
+direction with cubic cells; Sec. 2.2: the hierarchy along each axis, ending on
+the first level with one cell along some axis; Sec. 2.4: the right-ghost rule
+of each axis).
+
+Bars as in test_gpu_parity (FP64: 1e-12 relative potential, 1e-11 forces, at
+the oracle's cycle counts) and test_gpu_mixed (defect correction: within 1e-8
+of the oracle's converged solution).  Cases: 2-D and 3-D stacks of boxes
+whose row lengths are multiples of 4 (paired kernels) and 2 mod 4 (unpaired
+ones), a thin box whose short axis reaches one cell early, the interpolated
+buffer, the force-change stop rule, cycle-by-cycle iterates and a tree.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import core
+from paper_2001_02327_amd import learned
+from paper_2001_02327_amd import workloads as W
+
+from test_gpu_parity import assert_parity, gpu_solve, oracle_solve
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need the MI355X"
+
+
+def _thin3d():
+    # 40 x 12 x 20 cells: y has N^0 = 14 -> 7, 4, 2, 1 and ends the hierarchy
+    # on level 4 while x and z still have 3 and 2 cells; a 16 x 8 x 12 patch
+    g = W.box_geometry(3, (40, 12, 20), (16, 8, 12), (10, 2, 4), dx0=1.0 / 20)
+    return W.Workload("thin3d_40x12x20", g, W.Plummer([(1.0, 0.15, (0.9, 0.3, 0.5))]))
+
+
+def _odd_rows3d():
+    # row lengths 2 mod 4 on every level (unpaired level-0 kernels)
+    g = W.box_geometry(3, (38, 22, 30), (18, 14, 26), (8, 3, 1), (10, 6, 14), (3, 3, 5), dx0=1.0 / 24)
+    c = g.lo(2)
+    e = g.ext(2)
+    centre = tuple(c[a] + 0.5 * e[a] * g.dx(2) for a in range(3))
+    return W.Workload("odd_rows3d", g, W.Plummer([(1.0, 0.08, centre)]))
+
+
+def _box_tree3d():
+    # a 48 x 32 x 40 base with two disjoint box children and a grandchild
+    g = W.Geometry(dim=3, n=[(48, 32, 40), (16, 12, 20), (12, 16, 8), (12, 8, 16)],
+                   off=[(0, 0, 0), (3, 4, 5), (30, 8, 6), (2, 2, 2)], lo0=(0.0, 0.0, 0.0), dx0=1.0 / 24,
+                   parent=[-1, 0, 0, 1])
+    def centre(l):
+        return tuple(g.lo(l)[a] + 0.5 * g.ext(l)[a] * g.dx(l) for a in range(3))
+    # one sphere under the grandchild, one under the second child
+    return W.Workload("box_tree3d", g, W.Plummer([(1.0, 0.06, centre(3)), (0.5, 0.08, centre(2))]))
+
+
+BOXES = [W.box_plummer_3d(1), W.box_gaussian_2d(1), W.box_gaussian_2d(2), _thin3d(), _odd_rows3d(),
+         _box_tree3d()]
+
+
+@pytest.mark.parametrize("wl", BOXES, ids=lambda w: w.name)
+def test_box_pinned_cycle_parity(wl):
+    print("box parity: %s %s" % (wl.name, [wl.geom.ext(l) for l in range(wl.geom.nlevels)]), flush=True)
+    res, F_o = oracle_solve(wl)
+    assert res["status"] == 0, res["status_name"]
+    phi_g, F_g, st, _ = gpu_solve(wl, fixed=res["cycles"])
+    assert st["cycles"] == res["cycles"]
+    assert_parity(wl, phi_g, F_g, res, F_o)
+    # and the GPU's own stop takes the oracle's cycle counts within one
+    _, _, st2, _ = gpu_solve(wl)
+    for l in range(wl.geom.nlevels):
+        assert abs(st2["cycles"][l] - res["cycles"][l]) <= 1
+        assert st2["final_rel_residual"][l] <= 1e-10
+
+
+@pytest.mark.parametrize("wl", [_odd_rows3d(), W.box_gaussian_2d(1)], ids=lambda w: w.name)
+def test_box_cycle_by_cycle(wl):
+    L = wl.geom.nlevels
+    for k in range(3):
+        fixed = [k] + [min(k, 1)] * (L - 1)
+        res, F_o = oracle_solve(wl, fixed=fixed)
+        phi_g, F_g, _, _ = gpu_solve(wl, fixed=fixed)
+        assert_parity(wl, phi_g, F_g, res, F_o)
+
+
+def test_box_large_3d_parity():
+    """The 3-D box stack at twice the size (128 x 64 x 92 base; the coarse
+    levels run through several-block kernels before the LDS tail)."""
+    wl = W.box_plummer_3d(2)
+    res, F_o = oracle_solve(wl)
+    assert res["status"] == 0
+    phi_g, F_g, _, _ = gpu_solve(wl, fixed=res["cycles"])
+    assert_parity(wl, phi_g, F_g, res, F_o)
+
+
+@pytest.mark.parametrize("wl", [W.box_plummer_3d(1), W.box_gaussian_2d(1)], ids=lambda w: w.name)
+def test_box_interp_buffer(wl):
+    res, F_o = oracle_solve(wl, buffer_interp=True)
+    assert res["status"] == 0
+    phi_g, F_g, _, _ = gpu_solve(wl, fixed=res["cycles"], buffer="interp")
+    assert_parity(wl, phi_g, F_g, res, F_o)
+
+
+def test_box_force_change_stop():
+    wl = W.box_plummer_3d(1)
+    res, F_o = oracle_solve(wl, stop_rule=1)
+    phi_g, F_g, st, _ = gpu_solve(wl, stop_rule="force_delta")
+    for l in range(wl.geom.nlevels):
+        assert abs(st["cycles"][l] - res["cycles"][l]) <= 1
+    if st["cycles"] == res["cycles"]:
+        assert_parity(wl, phi_g, F_g, res, F_o)
+
+
+@pytest.mark.parametrize("precision", ["fp32_dc", "fp16s_dc"])
+@pytest.mark.parametrize("wl", [W.box_plummer_3d(1), _odd_rows3d(), W.box_gaussian_2d(2), _box_tree3d()],
+                         ids=lambda w: w.name)
+def test_box_defect_correction(wl, precision):
+    rho, po = W.make_inputs(wl.geom, wl.prob)
+    ref = core.solve(wl.geom, [r.numpy() for r in rho], po.numpy(), tol=1e-12, max_cycles=150)
+    assert ref["status"] == 0
+    phi, _, st, _ = gpu_solve(wl, precision=precision, inner_cycles="adaptive")
+    for l in range(wl.geom.nlevels):
+        err = np.abs(phi[l] - ref["phi"][l]).max() / np.abs(ref["phi"][l]).max()
+        assert err <= 1e-8, (l, err)
+        assert st["final_rel_residual"][l] <= 1e-10
+
+
+def test_box_learned_guess_runs():
+    """The network runs on box levels (its convolutions take any extents);
+    the multigrid still reaches the plain solve's answer."""
+    wl = W.box_plummer_3d(1)
+    phi0, _, _, _ = gpu_solve(wl)
+    theta = learned.load_weights() if learned.os.path.exists(learned.DEFAULT_WEIGHTS) else learned.init_params(1)
+    import paper_2001_02327_amd.solver as S
+    rho, po = W.make_inputs(wl.geom, wl.prob, device="cuda")
+    s = S.NestedPoissonSolver(wl.geom, guess="learned")
+    s.set_guess_weights(theta)
+    st = s.solve(rho, po)
+    for l in range(wl.geom.nlevels):
+        phi = s.potential(l).cpu().numpy()
+        assert np.abs(phi - phi0[l]).max() <= 1e-8 * np.abs(phi0[l]).max()
+        assert st["final_rel_residual"][l] <= 1e-10
+    x, t = s.guess_features(1)
+    assert tuple(x.shape) == tuple(v + 2 for v in reversed(wl.geom.ext(1))) + (2,)
+    s.close()
