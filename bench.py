@@ -74,6 +74,10 @@ def workload(name, N):
         # a tree: base level of N^3 cells, two disjoint (N/2)^3 patches on level 1
         # around two Plummer spheres, one (N/2)^3 patch on level 2
         return W.two_patch_3d(N)
+    if name == "many":
+        # patch-based refinement: eight (N/4)^3 patches around Plummer spheres in a
+        # base of N^3 cells (N = 256: eight 64^3 children), batched per depth
+        return W.many_patches_3d(N, 2)
     if name == "box":
         # non-cubic patches: the box stack 64 x 32 x 46 / 46 x 22 x 30 / 30 x 16 x 22
         # scaled by N / 64 (N = 512: 512 x 256 x 368 base)
@@ -219,6 +223,8 @@ def workload_small(wl, N):
         return W.paper3d(N)
     if name.startswith("box_plummer_3d"):
         return W.box_plummer_3d(1)
+    if name.startswith("many_patches_3d"):
+        return W.many_patches_3d(64, 2)
     return None
 
 
@@ -243,6 +249,8 @@ VARIANTS = {
     "fp64+learned": dict(precision="fp64", guess="learned"),
     # the comparison scheme of Sec. 4: both buffer layers interpolated, Omega^l alone relaxed
     "fp64_interp_buffer": dict(precision="fp64", guess="interp", buffer="interp"),
+    # same-size patches of a depth one after another instead of batched
+    "fp64_sequential": dict(precision="fp64", guess="interp", batch=False),
 }
 ELEM = {"fp64": 8, "fp32_dc": 4, "fp16s_dc": 2}
 # largest max |F - F_fp64| / max |F_fp64| a variant may show to count as the
@@ -290,7 +298,7 @@ def run_variant(name, wl, rho, phi_outer, Fs, steps, warmup, inner_cycles, stop_
     geom = wl.geom
     v = VARIANTS[name]
     solver = NestedPoissonSolver(geom, precision=v["precision"], guess=v["guess"], inner_cycles=inner_cycles,
-                                 buffer=v.get("buffer", "relaxed"), stop_rule=stop_rule)
+                                 buffer=v.get("buffer", "relaxed"), stop_rule=stop_rule, batch=v.get("batch", True))
     if v["guess"] == "learned":
         solver.set_guess_weights(learned.load_weights())
     stream = torch.cuda.current_stream()

@@ -110,11 +110,16 @@ typedef struct np_config {
     int parent[NP_MAX_LEVELS];      /* l >= 1: the entry patch l is refined out of, 0 <= parent[l] < l */
     int extent[NP_MAX_LEVELS][3];   /* cells of level l along x, y (, z): each even, >= 4; all zero:
                                        n[l] along every axis */
+    int batch;                      /* 1 (default): patches of one refinement depth with the same
+                                       extents are solved together, one launch per operator over
+                                       all of them, each patch stopping at its own cycle count (FP64,
+                                       interpolated guess, relaxed buffer, residual stop rule;
+                                       otherwise one after another); 0: one after another */
 } np_config;
 
 /* Fills `cfg` with the paper's solver settings (N_pre = 2, N_post = 1,
  * Sec. 3) and tol = 1e-10, max_cycles = 50, FP64, residual stop,
- * interpolated guess, relaxed buffer, parent[l] = l - 1.  The other
+ * interpolated guess, relaxed buffer, parent[l] = l - 1, batch = 1.  The other
  * geometry fields (extent included: cubic patches) are zeroed. */
 void nested_poisson_default_config(np_config* cfg);
 

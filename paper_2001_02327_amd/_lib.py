@@ -48,6 +48,7 @@ class NpConfig(ctypes.Structure):
         ("buffer", ctypes.c_int),
         ("parent", ctypes.c_int * NP_MAX_LEVELS),
         ("extent", (ctypes.c_int * 3) * NP_MAX_LEVELS),
+        ("batch", ctypes.c_int),
     ]
 
 
@@ -155,7 +156,7 @@ class NestedPoissonError(RuntimeError):
 
 
 def make_config(geom, n_pre=2, n_post=1, tol=1e-10, max_cycles=50, stop_rule="residual", precision="fp64",
-                inner_cycles=1, guess="interp", buffer="relaxed"):
+                inner_cycles=1, guess="interp", buffer="relaxed", batch=True):
     """np_config from a geometry (attributes dim, n, off, dx0, G) and solver settings."""
     c = NpConfig()
     lib().nested_poisson_default_config(ctypes.byref(c))
@@ -181,6 +182,7 @@ def make_config(geom, n_pre=2, n_post=1, tol=1e-10, max_cycles=50, stop_rule="re
     c.inner_cycles = 0 if inner_cycles == "adaptive" else int(inner_cycles)
     c.guess = GUESSES[guess] if isinstance(guess, str) else int(guess)
     c.buffer = BUFFERS[buffer] if isinstance(buffer, str) else int(buffer)
+    c.batch = 1 if batch else 0
     parent = getattr(geom, "parent", None)
     if parent is not None:
         for l, p in enumerate(parent):

@@ -27,6 +27,13 @@ struct SGrid {
     size_t ps;  // elements per plane of one colour: ny rows of hx, rounded up to a
                 // multiple of 128 in 3-D so that every plane starts 256-byte aligned
     size_t cs;  // elements per colour array (nz planes)
+    // a batch of nb patches with identical grids (the multigrid kernels launch
+    // one grid row per patch, blockIdx.y): patch b's array starts b * bs
+    // elements after patch 0's, and act (device array, may be null) flags the
+    // patches still iterating; nb = 1, bs = 0, act = null for a single grid
+    int nb;
+    size_t bs;
+    const int* act;
 };
 
 inline SGrid make_grid(int dim, int nx, int ny, int nz)
@@ -39,6 +46,18 @@ inline SGrid make_grid(int dim, int nx, int ny, int nz)
     g.ps = (size_t)g.hx * ny;
     if (dim == 3) g.ps = (g.ps + 127) / 128 * 128;
     g.cs = g.ps * g.nz;
+    g.nb = 1;
+    g.bs = 0;
+    g.act = nullptr;
+    return g;
+}
+
+// the same grid over a batch of nb patches whose arrays lie 2 cs apart
+inline SGrid batched(SGrid g, int nb, const int* act)
+{
+    g.nb = nb;
+    g.bs = nb > 1 ? 2 * g.cs : 0;
+    g.act = nb > 1 ? act : nullptr;
     return g;
 }
 

@@ -132,6 +132,18 @@ __device__ __forceinline__ bool strip_point(const Strip& s, int& x, int& y, int&
     return rr < s.R && y < s.nya;
 }
 
+// Patch batches (SGrid::nb): a multigrid launch over nb patches of one grid
+// runs patch blockIdx.y; its arrays start blockIdx.y * bs elements in, and a
+// patch whose flag in act is 0 has stopped iterating: its blocks return at
+// once (a block-uniform exit, before any barrier).
+__device__ __forceinline__ bool batch_idle(const SGrid& g) { return g.act && !g.act[blockIdx.y]; }
+
+template <typename T>
+__device__ __forceinline__ T* batch_at(T* p, const SGrid& g)
+{
+    return p ? p + (size_t)blockIdx.y * g.bs : p;
+}
+
 template <int D>
 __device__ __forceinline__ int colour_of(int pi, int pj, int pk)
 {
@@ -715,6 +727,10 @@ template <int D>
 __global__ void __launch_bounds__(kBlock) k_norm(SGrid g, const double* __restrict__ u, const double* __restrict__ f,
                                                  double inv_h2, int mode, unsigned long long* maxbits)
 {
+    if (batch_idle(g)) return;
+    u = batch_at(u, g);
+    f = batch_at(f, g);
+    maxbits += blockIdx.y;
     const int my = g.ny - 2, mz = g.nz - 2;
     long total = (long)g.hx * my * (D == 3 ? mz : 1);
     long stride = (long)gridDim.x * kBlock;
@@ -772,6 +788,10 @@ __global__ void __launch_bounds__(kBlock) k_resid_norm3(SGrid g, const double* _
                                                         const double* __restrict__ f, double inv_h2, int pblocks,
                                                         unsigned long long* maxbits)
 {
+    if (batch_idle(g)) return;
+    u = batch_at(u, g);
+    f = batch_at(f, g);
+    maxbits += blockIdx.y;
     const int my = g.ny - 2, mz = g.nz - 2;
     const int lb = (int)xcd_block();
     const int zc = lb / pblocks;
@@ -946,6 +966,9 @@ __device__ __forceinline__ void half_sweep_body(T* __restrict__ u, const T* __re
                                                        GRule<typename Compute<T>::type> gr)
 {
     using C = typename Compute<T>::type;
+    if (batch_idle(g)) return;
+    u = batch_at(u, g);
+    f = batch_at(f, g);
     long t = xcd_block() * kBlock + threadIdx.x;
     const int my = g.ny - 2, mz = g.nz - 2;
     long total = (long)g.hx * my * (D == 3 ? mz : 1);
@@ -1020,6 +1043,9 @@ __global__ void __launch_bounds__(kBlock) k_smooth_zmarch3(T* __restrict__ u, co
     constexpr bool RULE = TAG == 1;
     constexpr int kZChunk = TAG == 0 ? kZChunk0 : kZChunk1;
     constexpr int kZGroup = kZChunk;  // planes whose loads are issued together
+    if (batch_idle(g)) return;
+    u = batch_at(u, g);
+    f = batch_at(f, g);
     const int mx = g.nx - 2, my = g.ny - 2, mz = g.nz - 2;
     const int lb = zmarch_block(TAG == 0 ? colour : 0);  // level 0: red half sweeps up, black down
     const int zc = lb / pblocks;
@@ -1188,6 +1214,9 @@ __global__ void __launch_bounds__(kSmoothPairBlock) k_smooth_zmarch3_pair(T* __r
         }
         return v;
     };
+    if (batch_idle(g)) return;
+    u = batch_at(u, g);
+    f = batch_at(f, g);
     const int my = g.ny - 2, mz = g.nz - 2;
     const int lb = zmarch_block(colour);  // red half sweeps up, black down
     const int zc = lb / pblocks;
@@ -1355,6 +1384,11 @@ __global__ void __launch_bounds__(kBlock) k_resid_restrict(const TF* __restrict_
                                                            typename Compute<TC>::type inv2d)
 {
     using C = typename Compute<TC>::type;
+    if (batch_idle(gf)) return;
+    u = batch_at(u, gf);
+    f = batch_at(f, gf);
+    fc = batch_at(fc, gc);
+    ec = batch_at(ec, gc);
     const int Ncx = gc.nx - 2, Ncy = gc.ny - 2, Ncz = gc.nz - 2;
     const int Nfx = gf.nx - 2, Nfy = gf.ny - 2, Nfz = gf.nz - 2;
     long t = xcd_block() * kBlock + threadIdx.x;
@@ -1414,6 +1448,11 @@ __global__ void __launch_bounds__(kBlock) k_restrict3_zm(const TF* __restrict__ 
                                                          typename Compute<TC>::type inv2d)
 {
     using C = typename Compute<TC>::type;
+    if (batch_idle(gf)) return;
+    u = batch_at(u, gf);
+    f = batch_at(f, gf);
+    fc = batch_at(fc, gc);
+    ec = batch_at(ec, gc);
     const int Ncx = gc.nx - 2, Ncy = gc.ny - 2, Ncz = gc.nz - 2;
     const int Nfx = gf.nx - 2, Nfy = gf.ny - 2, Nfz = gf.nz - 2;
     const int lb = (int)xcd_block();
@@ -1527,6 +1566,11 @@ __global__ void __launch_bounds__(kBlock) k_restrict3_l0(const TF* __restrict__ 
                                                           typename Compute<TC>::type inv2d)
 {
     using C = typename Compute<TC>::type;
+    if (batch_idle(gf)) return;
+    u = batch_at(u, gf);
+    f = batch_at(f, gf);
+    fc = batch_at(fc, gc);
+    ec = batch_at(ec, gc);
     const int Ncx = gc.nx - 2, Ncy = gc.ny - 2, Ncz = gc.nz - 2;
     const int lb = (int)xcd_block();
     const int zc = lb / pblocks;
@@ -1637,6 +1681,9 @@ __global__ void __launch_bounds__(kBlock) k_prolong_add(const TC* __restrict__ e
                                                         int black_only, GRule<typename Compute<TC>::type> gr)
 {
     using C = typename Compute<TC>::type;
+    if (batch_idle(gf)) return;
+    e = batch_at(e, gc);
+    u = batch_at(u, gf);
     const int my = gf.ny - 2, mz = gf.nz - 2;
     long t = xcd_block() * kBlock + threadIdx.x;
     long total = (long)gf.hx * my * (D == 3 ? mz : 1);
@@ -1703,6 +1750,9 @@ __global__ void __launch_bounds__(kBlock) k_prolong3_zm(const TC* __restrict__ e
                                                          int pblocks, int kch)
 {
     using C = typename Compute<TC>::type;
+    if (batch_idle(gf)) return;
+    e = batch_at(e, gc);
+    u = batch_at(u, gf);
     const int Ncx = gc.nx - 2, Ncy = gc.ny - 2, Ncz = gc.nz - 2;
     const int Nfx = gf.nx - 2, Nfy = gf.ny - 2, Nfz = gf.nz - 2;
     // coarse parents per axis
@@ -1821,6 +1871,9 @@ __global__ void __launch_bounds__(kBlock) k_prolong3_pair(const TC* __restrict__
                                                            SGrid gf, GRule<typename Compute<TC>::type> gr, int pblocks)
 {
     using C = typename Compute<TC>::type;
+    if (batch_idle(gf)) return;
+    e = batch_at(e, gc);
+    u = batch_at(u, gf);
     const int Ncx = gc.nx - 2, Ncy = gc.ny - 2, Ncz = gc.nz - 2;
     const int Nfx = gf.nx - 2, Nfy = gf.ny - 2, Nfz = gf.nz - 2;
     const int Mz = (Nfz + 1) >> 1;  // coarse parents along z
@@ -2124,6 +2177,9 @@ __global__ void __launch_bounds__(kTailThreads) k_coarse_tail(TailParams<C> P, S
                                                               C* __restrict__ ug)
 {
     extern __shared__ __align__(16) unsigned char tail_lds[];
+    if (batch_idle(g0)) return;
+    fg = batch_at(fg, g0);
+    ug = batch_at(ug, g0);
     C* const lds = reinterpret_cast<C*>(tail_lds);
     const C inv2d = (C)(1.0 / (2.0 * D));
     auto U = [&](int a) { return lds + P.off[a]; };
@@ -2370,6 +2426,14 @@ __global__ void __launch_bounds__(kBlock) k_dc_outer3_pair(SGrid g, DcIn<TL, UPD
                                                            float h2l, float inv2d, int pblocks,
                                                            unsigned long long* maxbits)
 {
+    if (batch_idle(g)) return;
+    in.p = batch_at(in.p, g);
+    if (UPD) in.e = batch_at(in.e, g);
+    pout = batch_at(pout, g);
+    f = batch_at(f, g);
+    r = batch_at(r, g);
+    eout = batch_at(eout, g);
+    maxbits += blockIdx.y;
     const int my = g.ny - 2, mz = g.nz - 2;
     const int lb = (int)xcd_block();
     const int zc = lb / pblocks;
@@ -2628,7 +2692,7 @@ void launch_norm(int dim, hipStream_t st, SGrid g, const double* u, const double
         // the paired DC pass without outputs: same residual, same order of operations
         const long mz = g.nz - 2;
         const int pblocks = ceil_div((long)(g.ps / 2), kBlock);
-        hipLaunchKernelGGL((k_dc_outer3_pair<float, false, false>), dim3(pblocks * ceil_div(mz, kDcChunk)), dim3(kBlock), 0,
+        hipLaunchKernelGGL((k_dc_outer3_pair<float, false, false>), dim3(pblocks * ceil_div(mz, kDcChunk), g.nb), dim3(kBlock), 0,
                            st, g, DcIn<float, false>{u, nullptr, 0.0}, nullptr, f, inv_h2, 0.0, nullptr, nullptr, 0, 0.0f,
                            0.0f, pblocks, maxbits);
         return;
@@ -2637,13 +2701,13 @@ void launch_norm(int dim, hipStream_t st, SGrid g, const double* u, const double
         long mz = g.nz - 2;
         int pblocks = ceil_div((long)g.ps, kBlock);
         int chunks = ceil_div(mz, kNormChunk);
-        hipLaunchKernelGGL(k_resid_norm3, dim3(pblocks * chunks), dim3(kBlock), 0, st, g, u, f, inv_h2, pblocks,
+        hipLaunchKernelGGL(k_resid_norm3, dim3(pblocks * chunks, g.nb), dim3(kBlock), 0, st, g, u, f, inv_h2, pblocks,
                            maxbits);
         return;
     }
     int blocks = ceil_div(ncompact_active(dim, g), kBlock);
     if (blocks > 2048) blocks = 2048;
-    NP_DISPATCH(dim, k_norm, dim3(blocks), dim3(kBlock), st, g, u, f, inv_h2, mode, maxbits);
+    NP_DISPATCH(dim, k_norm, dim3(blocks, g.nb), dim3(kBlock), st, g, u, f, inv_h2, mode, maxbits);
 }
 
 void launch_box_resid_norm3(hipStream_t st, SGrid g, const double* u, const double* f, double inv_h2,
@@ -2664,7 +2728,7 @@ void launch_half_sweep(int dim, hipStream_t st, SGrid g, T* u, const T* f, int c
                        const Rule3& rule)
 {
     using C = typename Compute<T>::type;
-    dim3 grid(ceil_div(ncompact_active(dim, g), kBlock));
+    dim3 grid(ceil_div(ncompact_active(dim, g), kBlock), g.nb);
     C inv2d = (C)(1.0 / (2.0 * dim));
     const GRule<C> gr = grule<C>(rule);
     if (dim == 3 && fine && sizeof(T) <= 4 && (g.hx % 2) == 0) {
@@ -2674,7 +2738,7 @@ void launch_half_sweep(int dim, hipStream_t st, SGrid g, T* u, const T* f, int c
         long mz = g.nz - 2;
         int pblocks = ceil_div((long)(g.ps / 2), kSmoothPairBlock);
         int chunks = ceil_div(mz, kZChunk0);
-        hipLaunchKernelGGL((k_smooth_zmarch3_pair<T>), dim3(pblocks * chunks), dim3(kSmoothPairBlock), 0, st, u, f, g,
+        hipLaunchKernelGGL((k_smooth_zmarch3_pair<T>), dim3(pblocks * chunks, g.nb), dim3(kSmoothPairBlock), 0, st, u, f, g,
                            colour, (C)h2, inv2d, pblocks);
         return;
     }
@@ -2685,10 +2749,10 @@ void launch_half_sweep(int dim, hipStream_t st, SGrid g, T* u, const T* f, int c
         int pblocks = ceil_div((long)g.ps, kBlock);
         int chunks = ceil_div(mz, fine ? kZChunk0 : kZChunk1);
         if (fine)
-            hipLaunchKernelGGL((k_smooth_zmarch3<T, 0>), dim3(pblocks * chunks), dim3(kBlock), 0, st, u, f, g, colour,
+            hipLaunchKernelGGL((k_smooth_zmarch3<T, 0>), dim3(pblocks * chunks, g.nb), dim3(kBlock), 0, st, u, f, g, colour,
                                (C)h2, inv2d, pblocks, gr);
         else
-            hipLaunchKernelGGL((k_smooth_zmarch3<T, 1>), dim3(pblocks * chunks), dim3(kBlock), 0, st, u, f, g, colour,
+            hipLaunchKernelGGL((k_smooth_zmarch3<T, 1>), dim3(pblocks * chunks, g.nb), dim3(kBlock), 0, st, u, f, g, colour,
                                (C)h2, inv2d, pblocks, gr);
         return;
     }
@@ -2709,7 +2773,7 @@ void launch_half_sweep_seeded(hipStream_t st, SGrid g, T* u, const T* f, double 
     const long mz = g.nz - 2;
     const int pblocks = ceil_div((long)(g.ps / 2), kSmoothPairBlock);
     const int chunks = ceil_div(mz, kZChunk0);
-    hipLaunchKernelGGL((k_smooth_zmarch3_pair<T, true>), dim3(pblocks * chunks), dim3(kSmoothPairBlock), 0, st, u, f,
+    hipLaunchKernelGGL((k_smooth_zmarch3_pair<T, true>), dim3(pblocks * chunks, g.nb), dim3(kSmoothPairBlock), 0, st, u, f,
                        g, 1, (C)h2, (C)(1.0 / 6.0), pblocks);
 }
 
@@ -2721,14 +2785,14 @@ void launch_resid_restrict(int dim, hipStream_t st, SGrid gf, const TF* u, const
     const C sh2 = (C)seed_h2, inv2d = (C)(1.0 / (2.0 * dim));
     const long Ncx = gc.nx - 2, Ncy = gc.ny - 2, Ncz = gc.nz - 2;
     long total = dim == 3 ? Ncx * Ncy * Ncz : Ncx * Ncy;
-    dim3 grid(ceil_div(total, kBlock));
+    dim3 grid(ceil_div(total, kBlock), gf.nb);
     const GRule<C> gr = grule<C>(fine_rule);
     if (dim == 3) {
         // z-march: 4 coarse planes per thread on large grids, 1 on small ones
         // (there the column count alone does not fill the chip)
         const int kch = Ncx * Ncy >= 128 * 128 ? 4 : 1;
         const int pblocks = ceil_div(Ncx * Ncy, kBlock);
-        const dim3 zgrid(pblocks * ceil_div(Ncz, kch));
+        const dim3 zgrid(pblocks * ceil_div(Ncz, kch), gf.nb);
         if (!rule && gf.nx - 2 == 2 * Ncx && gf.ny - 2 == 2 * Ncy && gf.nz - 2 == 2 * Ncz &&
             2 * gf.cs * sizeof(TF) < (1ull << 31)) {
             // multigrid level 0: uniform addressing
@@ -2758,13 +2822,13 @@ void launch_prolong_add(int dim, hipStream_t st, SGrid gc, const TC* ec, SGrid g
 {
     using C = typename Compute<TC>::type;
     const GRule<C> gr = grule<C>(coarse_rule);
-    dim3 grid(ceil_div(ncompact_active(dim, gf), kBlock));
+    dim3 grid(ceil_div(ncompact_active(dim, gf), kBlock), gf.nb);
     if (dim == 3 && black_only && (gf.hx % 2) == 0 && 2 * gf.cs < (1ull << 31) && 2 * gc.cs < (1ull << 31)) {
         // paired form: one paired load and store per fine plane and pair
         const long Mz = (gf.nz - 1) / 2;
         const int pblocks = ceil_div((long)(gf.ps / 2), kBlock);
         const int chunks = ceil_div(Mz, kProlongPairChunk);
-        hipLaunchKernelGGL((k_prolong3_pair<TC, TF, kProlongPairChunk>), dim3(pblocks * chunks), dim3(kBlock), 0, st,
+        hipLaunchKernelGGL((k_prolong3_pair<TC, TF, kProlongPairChunk>), dim3(pblocks * chunks, gf.nb), dim3(kBlock), 0, st,
                            ec, gc, u, gf, gr, pblocks);
         return;
     }
@@ -2776,7 +2840,7 @@ void launch_prolong_add(int dim, hipStream_t st, SGrid gc, const TC* ec, SGrid g
         const int kch = Mx * My >= 200 * 200 ? 8 : 2;
         const int pblocks = ceil_div(Mx * My, kBlock);
         const int chunks = ceil_div(Mz, kch);
-        hipLaunchKernelGGL((k_prolong3_zm<TC, TF>), dim3(pblocks * chunks), dim3(kBlock), 0, st, ec, gc, u, gf,
+        hipLaunchKernelGGL((k_prolong3_zm<TC, TF>), dim3(pblocks * chunks, gf.nb), dim3(kBlock), 0, st, ec, gc, u, gf,
                            black_only, gr, pblocks, kch);
     } else
         hipLaunchKernelGGL((k_prolong_add<2, TC, TF>), grid, dim3(kBlock), 0, st, ec, gc, u, gf, black_only, gr);
@@ -2816,9 +2880,9 @@ int launch_coarse_tail(int dim, hipStream_t st, int nlev, const int (*N)[3], con
         P.gr[a] = grule<T>(rule[a]);
     }
     if (dim == 3)
-        hipLaunchKernelGGL((k_coarse_tail<3, T>), dim3(1), dim3(kTailThreads), bytes, st, P, g0, f0, u0);
+        hipLaunchKernelGGL((k_coarse_tail<3, T>), dim3(1, g0.nb), dim3(kTailThreads), bytes, st, P, g0, f0, u0);
     else
-        hipLaunchKernelGGL((k_coarse_tail<2, T>), dim3(1), dim3(kTailThreads), bytes, st, P, g0, f0, u0);
+        hipLaunchKernelGGL((k_coarse_tail<2, T>), dim3(1, g0.nb), dim3(kTailThreads), bytes, st, P, g0, f0, u0);
     return 0;
 }
 
@@ -2832,7 +2896,7 @@ void launch_dc_outer(int dim, hipStream_t st, SGrid g, const double* phi_in, con
     if (dim == 3 && g.hx % 2 == 0 && g.cs % 2 == 0) {
         long mz = g.nz - 2;
         int pblocks = ceil_div((long)(g.ps / 2), kBlock);
-        dim3 grid(pblocks * ceil_div(mz, kDcChunk));
+        dim3 grid(pblocks * ceil_div(mz, kDcChunk), g.nb);
         if (upd)
             hipLaunchKernelGGL((k_dc_outer3_pair<TL, true>), grid, dim3(kBlock), 0, st, g,
                                DcIn<TL, true>{phi_in, e_in, factor}, phi_out, f, inv_h2, rscale, r, e_out, first_red,

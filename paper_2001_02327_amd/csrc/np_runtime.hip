@@ -1,6 +1,7 @@
 // Host runtime of the nested-grid multigrid solver: geometry validation,
 // multigrid planning, device storage, the V-cycle schedule and the C ABI
 // declared in include/nested_poisson.h.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -14,6 +15,14 @@
 #include "np_internal.h"
 
 using namespace np;
+
+// Entries solved together: patches of one refinement depth with the same
+// extents, whose V-cycles and stop-test norms run as one launch per operator
+// over the group (one grid row per patch), or a single entry.
+struct PatchGroup {
+    int n;
+    int member[NP_MAX_LEVELS];
+};
 
 namespace {
 
@@ -84,7 +93,18 @@ bool validate(const np_config* c, char* why, size_t nwhy)
         (c->precision != NP_PREC_FP64 || c->guess != NP_GUESS_INTERP || c->stop_rule != NP_STOP_RESIDUAL))
         return fail("the interpolated buffer runs with FP64, the interpolated guess and the residual stop "
                     "rule only");
+    if (c->batch != 0 && c->batch != 1) return fail("batch must be 0 or 1 (got %d)", c->batch);
     return true;
+}
+
+// Whether patches of one depth and extents are solved as one batch: with
+// batch = 1 in FP64, with the interpolated guess, the relaxed buffer and the
+// residual stop rule (their per-patch state is the potential, the right-hand
+// side and the stop test only).
+bool batching(const np_config* c)
+{
+    return c->batch == 1 && c->precision == NP_PREC_FP64 && c->guess == NP_GUESS_INTERP &&
+           c->buffer == NP_BUFFER_RELAXED && c->stop_rule == NP_STOP_RESIDUAL;
 }
 
 // Sec. 2.2 along every axis: N^0_a = n_a + 2; N^L_a = round(N^0_a / 2^L),
@@ -157,6 +177,45 @@ int level_depth(const np_config* c, int l)
     }
     return k;
 }
+
+// Solve order: with batching, the entries by depth (then index), grouped by
+// extents within a depth; every parent lies at a smaller depth, so it is
+// solved in an earlier group (one-way scheme).  Otherwise one entry per group
+// in entry order (a parent is always an earlier entry).
+int make_groups(const np_config* c, PatchGroup* g)
+{
+    int ng = 0;
+    if (!batching(c)) {
+        for (int l = 0; l < c->nlevels; l++) {
+            g[ng].n = 1;
+            g[ng].member[0] = l;
+            ng++;
+        }
+        return ng;
+    }
+    int maxd = 0;
+    for (int l = 0; l < c->nlevels; l++) maxd = std::max(maxd, level_depth(c, l));
+    for (int dep = 0; dep <= maxd; dep++) {
+        const int first = ng;
+        for (int l = 0; l < c->nlevels; l++) {
+            if (level_depth(c, l) != dep) continue;
+            int k = first;
+            for (; k < ng; k++) {
+                const int m = g[k].member[0];
+                bool same = true;
+                for (int a = 0; a < c->dim; a++)
+                    if (level_n(c, l, a) != level_n(c, m, a)) same = false;
+                if (same) break;
+            }
+            if (k == ng) {
+                g[ng].n = 0;
+                ng++;
+            }
+            g[k].member[g[k].n++] = l;
+        }
+    }
+    return ng;
+}
 double level_dx(const np_config* c, int l) { return std::ldexp(c->dx0, -level_depth(c, l)); }
 
 // Returns NP_OK, or NP_EINVAL with the reason in `why`.
@@ -213,9 +272,19 @@ void set_last_error(const char* msg) { snprintf(g_last_error, sizeof g_last_erro
 }  // namespace np
 
 // ------------------------------------------------------------------ handle
+// device reduction slots: 0 norm, 1 force change, 2 max |f| of a fill,
+// 3 restricted residual; kBatchSlot + b the norm of batch member b
+constexpr int kBatchSlot = 8;
+constexpr int kBitSlots = kBatchSlot + NP_MAX_LEVELS;
+
 struct np_solver {
     np_config cfg;
     np_plan plan;
+    int ngroups = 0;
+    PatchGroup groups[NP_MAX_LEVELS];
+    bool owns[NP_MAX_LEVELS] = {};  // phi[l] and f[l] own their allocation (else inside a group's)
+    int* d_act = nullptr;           // device flags of the batch members still iterating
+    int* h_act = nullptr;           // pinned host copy
     hipStream_t stream = nullptr;
     int device = 0;
     SGrid lg[NP_MAX_LEVELS];          // level grids (= multigrid level 0)
@@ -846,6 +915,146 @@ struct RelaxedDomain {
     RelaxedDomain& operator=(const RelaxedDomain&) = delete;
 };
 
+// A batch of patches (one depth, one set of extents; FP64, interpolated
+// guess, residual stop rule): each member is filled from its parent, then the
+// V-cycles and the stop-test norms run as one launch per operator over the
+// members still iterating (device flags d_act), each member stopping at its
+// own count, with the arithmetic of a single-patch solve.
+int solve_batch(np_solver* s, const PatchGroup& G, const double* const* rho, double fourpiG, np_stats& st,
+                int& status)
+{
+    const np_config& c = s->cfg;
+    const int d = c.dim;
+    const int n = G.n, m0 = G.member[0];
+    hipStream_t stm = s->stream;
+    auto t0 = std::chrono::steady_clock::now();
+    unsigned long long* slots = s->d_bits + kBatchSlot;
+    // the members' fills (each from its own parent), max |f| of member b into slot b
+    prof_begin(s, NP_KCLASS_FILL);
+    launch_set_u64(stm, slots, n, 0ULL);
+    for (int b = 0; b < n; b++) {
+        const int l = G.member[b];
+        s->hist[l].clear();
+        launch_interface_fill(d, stm, s->lg[c.parent[l]], s->phi[c.parent[l]], s->f[c.parent[l]], s->lg[l],
+                              c.offset[l][0], c.offset[l][1], d == 3 ? c.offset[l][2] : 0, rho[l], fourpiG, s->phi[l],
+                              s->f[l], slots + b);
+    }
+    prof_end(s, n);
+    HIPCHK(s, hipGetLastError());
+    HIPCHK(s, hipMemcpyAsync(s->h_bits + kBatchSlot, slots, n * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                             stm));
+    HIPCHK(s, hipStreamSynchronize(stm));
+    double scale[NP_MAX_LEVELS], r[NP_MAX_LEVELS], r0[NP_MAX_LEVELS];
+    int q[NP_MAX_LEVELS] = {}, lvl[NP_MAX_LEVELS] = {};
+    for (int b = 0; b < n; b++) {
+        scale[b] = bits_to_double(s->h_bits[kBatchSlot + b]);
+        if (!std::isfinite(scale[b])) return set_err(s, NP_ENONFINITE, "level %d: non-finite density", G.member[b]);
+    }
+    for (int b = 0; b < n; b++) {
+        if (scale[b] > 0.0) continue;
+        // zero density: the residual of the zero potential sets the scale
+        int rc = norm_sync(s, G.member[b], 2, &scale[b]);
+        if (rc) return rc;
+        if (!std::isfinite(scale[b]))
+            return set_err(s, NP_ENONFINITE, "level %d: non-finite boundary data", G.member[b]);
+    }
+    // the batch's grids: level 0 and the multigrid levels, one row per member
+    const double dx = level_dx(&c, m0);
+    MGView<double> v = mg_view<double>(s, m0, s->mg_u, s->mg_f);
+    for (int L = 0; L < v.nmg; L++) v.g[L] = batched(v.g[L], n, s->d_act);
+    const SGrid g0 = v.g[0];
+    // stop-test norms of the members still iterating into their slots
+    auto norms = [&](bool first) -> int {
+        launch_set_u64(stm, slots, n, 0ULL);
+        prof_begin(s, NP_KCLASS_NORM);
+        launch_norm(d, stm, g0, s->phi[m0], s->f[m0], 1.0 / (dx * dx), 0, slots);
+        prof_end(s);
+        HIPCHK(s, hipGetLastError());
+        HIPCHK(s, hipMemcpyAsync(s->h_bits + kBatchSlot, slots, n * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                                 stm));
+        HIPCHK(s, hipStreamSynchronize(stm));
+        for (int b = 0; b < n; b++)
+            if (first || s->h_act[b]) r[b] = bits_to_double(s->h_bits[kBatchSlot + b]);
+        return NP_OK;
+    };
+    // which members go on: the rule of a single-patch solve, member by member
+    auto update = [&]() -> bool {
+        bool any = false;
+        for (int b = 0; b < n; b++) {
+            if (!s->h_act[b]) continue;
+            const int l = G.member[b];
+            const bool pinned = s->has_fixed && s->fixed[l] >= 0;
+            bool go = true;
+            if (!std::isfinite(r[b])) {
+                lvl[b] = NP_ENONFINITE;
+                go = false;
+            } else if (q[b] > 0 && r0[b] > 0 && r[b] > 1e3 * r0[b]) {
+                lvl[b] = NP_EDIVERGED;
+                go = false;
+            } else if (pinned ? q[b] >= s->fixed[l] : r[b] <= c.tol * scale[b]) {
+                go = false;
+            } else if (q[b] >= c.max_cycles) {
+                lvl[b] = NP_ENOTCONV;
+                go = false;
+            }
+            s->h_act[b] = go ? 1 : 0;
+            any = any || go;
+        }
+        return any;
+    };
+    for (int b = 0; b < n; b++) s->h_act[b] = 1;
+    HIPCHK(s, hipMemcpyAsync(s->d_act, s->h_act, n * sizeof(int), hipMemcpyHostToDevice, stm));
+    int rc = norms(true);
+    if (rc) return rc;
+    for (int b = 0; b < n; b++) {
+        r0[b] = r[b];
+        s->hist[G.member[b]].push_back(scale[b] > 0 ? r[b] / scale[b] : r[b]);
+        st.interp_rel_residual[G.member[b]] = scale[b] > 0 ? r[b] / scale[b] : r[b];
+    }
+    bool any = update();
+    while (any) {
+        HIPCHK(s, hipMemcpyAsync(s->d_act, s->h_act, n * sizeof(int), hipMemcpyHostToDevice, stm));
+        rc = vcycle_t<double, double>(s, m0, s->phi[m0], s->f[m0], dx * dx, 1.0 / (dx * dx), 1.0, v,
+                                      s->coarse_exec);
+        if (rc) return rc;
+        HIPCHK(s, hipGetLastError());
+        for (int b = 0; b < n; b++) q[b] += s->h_act[b];
+        rc = norms(false);
+        if (rc) return rc;
+        for (int b = 0; b < n; b++)
+            if (s->h_act[b]) s->hist[G.member[b]].push_back(scale[b] > 0 ? r[b] / scale[b] : r[b]);
+        any = update();
+    }
+    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    for (int b = 0; b < n; b++) {
+        const int l = G.member[b];
+        st.cycles[l] = q[b];
+        st.outer_steps[l] = 0;
+        st.scale[l] = scale[b];
+        st.initial_rel_residual[l] = s->hist[l].front();
+        st.final_rel_residual[l] = scale[b] > 0 ? r[b] / scale[b] : r[b];
+        st.level_ms[l] = ms;
+        if (q[b] > 0 && r0[b] > 0.0 && r[b] > 0.0 && r[b] < r0[b]) {
+            const double m = std::pow(r[b] / r0[b], 1.0 / q[b]);
+            s->rho_meas[l] = m < 0.02 ? 0.02 : (m > 0.95 ? 0.95 : m);
+        } else {
+            s->rho_meas[l] = 0.0;
+        }
+    }
+    for (int b = 0; b < n; b++) {
+        const int l = G.member[b];
+        if (lvl[b] == NP_ENONFINITE || lvl[b] == NP_EDIVERGED)
+            return set_err(s, lvl[b], "level %d: %s after %d cycles", l,
+                           lvl[b] == NP_ENONFINITE ? "non-finite residual" : "residual diverged", q[b]);
+        if (lvl[b] == NP_ENOTCONV && status == NP_OK) {
+            status = NP_ENOTCONV;
+            set_err(s, NP_ENOTCONV, "level %d: not converged in %d cycles (rel. residual %.3e)", l, q[b],
+                    st.final_rel_residual[l]);
+        }
+    }
+    return NP_OK;
+}
+
 void free_all(np_solver* s)
 {
     for (int l = 0; l < NP_MAX_LEVELS; l++) {
@@ -855,10 +1064,17 @@ void free_all(np_solver* s)
     if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
     s->cap_stream = nullptr;
     for (int l = 0; l < NP_MAX_LEVELS; l++) {
-        if (s->phi[l]) (void)hipFree(s->phi[l]);
-        if (s->f[l]) (void)hipFree(s->f[l]);
+        if (s->owns[l]) {
+            if (s->phi[l]) (void)hipFree(s->phi[l]);
+            if (s->f[l]) (void)hipFree(s->f[l]);
+        }
+        s->owns[l] = false;
         s->phi[l] = s->f[l] = nullptr;
     }
+    if (s->d_act) (void)hipFree(s->d_act);
+    if (s->h_act) (void)hipHostFree(s->h_act);
+    s->d_act = nullptr;
+    s->h_act = nullptr;
     for (int L = 0; L < NP_MAX_MG; L++) {
         if (s->mg_u[L]) (void)hipFree(s->mg_u[L]);
         if (s->mg_f[L]) (void)hipFree(s->mg_f[L]);
@@ -932,6 +1148,7 @@ void nested_poisson_default_config(np_config* c)
     c->inner_cycles = 1;
     c->guess = NP_GUESS_INTERP;
     c->buffer = NP_BUFFER_RELAXED;
+    c->batch = 1;
     for (int l = 0; l < NP_MAX_LEVELS; l++) c->parent[l] = l - 1;
 }
 
@@ -969,25 +1186,39 @@ int nested_poisson_create(const np_config* cfg, void* hip_stream, np_solver** ou
     const int d = cfg->dim;
     int rc = NP_OK;
     size_t max_cells = 0;  // largest Omega^l
-    for (int l = 0; l < cfg->nlevels && rc == NP_OK; l++) {
+    s->ngroups = make_groups(cfg, s->groups);
+    for (int l = 0; l < cfg->nlevels; l++) {
         s->lg[l] = level_grid(cfg, l);
-        size_t bytes = 2 * s->lg[l].cs * sizeof(double);
-        rc = alloc_dev(s, (void**)&s->phi[l], bytes);
-        if (rc == NP_OK) rc = alloc_dev(s, (void**)&s->f[l], bytes);
-        s->phi_cap[l] = bytes;
         const size_t cells = (size_t)level_n(cfg, l, 0) * level_n(cfg, l, 1) * level_n(cfg, l, 2);
         if (cells > max_cells) max_cells = cells;
+    }
+    // the level arrays; a batch's members lie 2 cs apart in one allocation
+    for (int gi = 0; gi < s->ngroups && rc == NP_OK; gi++) {
+        const PatchGroup& G = s->groups[gi];
+        const int m0 = G.member[0];
+        const size_t bytes = 2 * s->lg[m0].cs * sizeof(double);
+        rc = alloc_dev(s, (void**)&s->phi[m0], G.n * bytes);
+        if (rc == NP_OK) rc = alloc_dev(s, (void**)&s->f[m0], G.n * bytes);
+        s->owns[m0] = true;
+        for (int b = 0; b < G.n && rc == NP_OK; b++) {
+            const int m = G.member[b];
+            s->phi[m] = s->phi[m0] + b * 2 * s->lg[m0].cs;
+            s->f[m] = s->f[m0] + b * 2 * s->lg[m0].cs;
+            s->phi_cap[m] = bytes;
+        }
     }
     // multigrid scratch: per level L the largest grid over the nested levels,
     // FP64 for the plain solve, FP32 for the defect correction's inner cycles
     const bool dc = cfg->precision != NP_PREC_FP64;
     for (int L = 1; L < NP_MAX_MG && rc == NP_OK; L++) {
         size_t best = 0;
-        for (int l = 0; l < cfg->nlevels; l++)
+        for (int gi = 0; gi < s->ngroups; gi++) {
+            const int l = s->groups[gi].member[0];
             if (L < s->plan.nmg[l]) {
-                size_t b = 2 * mg_grid(s, l, L).cs;
+                size_t b = 2 * mg_grid(s, l, L).cs * s->groups[gi].n;
                 if (b > best) best = b;
             }
+        }
         if (!best) break;
         if (dc) {
             rc = alloc_dev(s, (void**)&s->mg_u32[L], best * sizeof(float));
@@ -1039,10 +1270,16 @@ int nested_poisson_create(const np_config* cfg, void* hip_stream, np_solver** ou
     }
     if (rc == NP_OK && cfg->stop_rule == NP_STOP_FORCE_DELTA)
         rc = alloc_dev(s, (void**)&s->force_scratch, (size_t)d * max_cells * sizeof(double));
-    if (rc == NP_OK) rc = alloc_dev(s, (void**)&s->d_bits, 8 * sizeof(unsigned long long));
-    if (rc == NP_OK && hipHostMalloc((void**)&s->h_bits, 8 * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess) {
+    if (rc == NP_OK) rc = alloc_dev(s, (void**)&s->d_bits, kBitSlots * sizeof(unsigned long long));
+    if (rc == NP_OK && hipHostMalloc((void**)&s->h_bits, kBitSlots * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
         s->h_bits = nullptr;
+        rc = NP_ENOMEM;
+    }
+    if (rc == NP_OK) rc = alloc_dev(s, (void**)&s->d_act, NP_MAX_LEVELS * sizeof(int));
+    if (rc == NP_OK && hipHostMalloc((void**)&s->h_act, NP_MAX_LEVELS * sizeof(int), hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        s->h_act = nullptr;
         rc = NP_ENOMEM;
     }
     if (rc != NP_OK) {
@@ -1092,7 +1329,16 @@ int nested_poisson_solve(np_solver* s, const double* const* rho, const double* p
     s->solved = false;
     int status = NP_OK;
     auto t_all = std::chrono::steady_clock::now();
-    for (int l = 0; l < c.nlevels; l++) {
+    for (int gi = 0; gi < s->ngroups; gi++) {
+        if (s->groups[gi].n > 1) {
+            int rc = solve_batch(s, s->groups[gi], rho, fourpiG, st, status);
+            if (rc) {
+                if (stats) *stats = st;
+                return rc;
+            }
+            continue;
+        }
+        const int l = s->groups[gi].member[0];
         auto t0 = std::chrono::steady_clock::now();
         s->hist[l].clear();
         prof_begin(s, NP_KCLASS_FILL);

@@ -495,3 +495,62 @@ def box_gaussian_2d(scale: int = 1) -> Workload:
     e = g.ext(2)
     centre = tuple(c[a] + 0.5 * e[a] * g.dx(2) for a in range(2))
     return Workload("box_gaussian_2d_%d" % k, g, GaussianSum([(1.0, 0.15, centre)]))
+
+
+def many_patches_geometry(dim: int, N: int, k: int = 2, m: int = None, depth2: bool = False) -> Geometry:
+    """A base of N cells per axis on [-1, 1]^d with k^d disjoint children of m
+    cells each (default N/4, each covering m/2 base cells) centred in the k^d
+    cells of a regular split of the base; with depth2, the children carry one
+    grandchild of m cells at their centre each (a second depth of same-size
+    patches), as many as the 16 entries of a solver hold."""
+    m = m or N // 4
+    if N % (2 * k) or m % 4:
+        raise ValueError("N must be a multiple of 2k and m of 4")
+    span = N // k                 # base cells per split cell
+    half = m // 2                 # base cells a child covers
+    if half + 2 > span:
+        raise ValueError("children too large for the split")
+    n = [N]
+    off = [(0, 0, 0)]
+    parent = [-1]
+    idx = []
+    for c in range(k ** dim):
+        pos = [(c // k ** a) % k for a in range(dim)]
+        o = tuple(p * span + (span - half) // 2 for p in pos) + (0,) * (3 - dim)
+        n.append(m)
+        off.append(o)
+        parent.append(0)
+        idx.append(len(n) - 1)
+    if depth2:
+        for c in idx[:16 - len(n)]:
+            n.append(m)
+            off.append((m // 4,) * dim + (0,) * (3 - dim))
+            parent.append(c)
+    return Geometry(dim=dim, n=n, off=off, lo0=(-1.0, -1.0, -1.0), dx0=2.0 / N, parent=parent)
+
+
+def many_patches_3d(N: int = 256, k: int = 2, m: int = None, depth2: bool = False) -> Workload:
+    """k^3 same-size patches refined out of a base of N^3 cells (default: eight
+    64^3 children of a 256^3 base), each around a Plummer sphere at its centre
+    (M = 1, a = 0.04; the spheres' closed forms superposed)."""
+    g = many_patches_geometry(3, N, k, m, depth2)
+    cen = []
+    for l in range(1, g.nlevels):
+        if g.par(l) != 0:
+            continue
+        lo = g.lo(l)
+        cen.append(tuple(lo[a] + 0.5 * g.ext(l)[a] * g.dx(l) for a in range(3)))
+    return Workload("many_patches_3d_%d_k%d%s" % (N, k, "_d2" if depth2 else ""), g,
+                    Plummer([(1.0, 0.04, c) for c in cen]))
+
+
+def many_patches_2d(N: int = 128, k: int = 2, m: int = None, depth2: bool = False) -> Workload:
+    """The 2-D form: k^2 same-size patches around Gaussian sources (width 0.06)."""
+    g = many_patches_geometry(2, N, k, m, depth2)
+    terms = []
+    for l in range(1, g.nlevels):
+        if g.par(l) != 0:
+            continue
+        lo = g.lo(l)
+        terms.append((1.0, 0.06, tuple(lo[a] + 0.5 * g.ext(l)[a] * g.dx(l) for a in range(2))))
+    return Workload("many_patches_2d_%d_k%d%s" % (N, k, "_d2" if depth2 else ""), g, GaussianSum(terms))
