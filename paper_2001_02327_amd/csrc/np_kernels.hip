@@ -1906,6 +1906,36 @@ __global__ void __launch_bounds__(kBlock) k_prolong3_pair(const TC* __restrict__
             off[1][y][x] = o + (c0 ? 0u : (unsigned)gc.cs);
         }
     const size_t cplane = gc.ps;
+    const size_t fplane = gf.ps;
+    const unsigned row = (unsigned)(pj * gf.hx + h0);
+    TF* __restrict__ ub = u + gf.cs;  // black colour array
+    // Every load of the chunk is issued before the first use, with no branch
+    // between them (the planes past the chunk's end read clamped, in-bounds
+    // indices and feed no stored value): with the loads of each coarse plane
+    // behind a condition, each plane cost a full memory round trip.
+    // coarse planes K0 - 1 .. K0 + KCH (the index clamped to the ghost plane)
+    AxisNb<C> mzs[KCH + 2];
+    TC raw[KCH + 2][2][3];
+#pragma unroll
+    for (int z = 0; z < KCH + 2; z++) {
+        mzs[z] = axis_nb_clamped(K0 - 1 + z, Ncz, gr, 2);
+        const TC* __restrict__ ep = e + (size_t)mzs[z].q * cplane;
+        const bool odd = (mzs[z].q & 1) != 0;
+#pragma unroll
+        for (int y = 0; y < 2; y++)
+#pragma unroll
+            for (int x = 0; x < 3; x++) raw[z][y][x] = ep[odd ? off[1][y][x] : off[0][y][x]];
+    }
+    // fine black pairs of planes 2K - 1 and 2K (past the last active plane the
+    // ghost plane Nfz + 1 is read and nothing is stored)
+    Pair<TF> old[KCH][2];
+#pragma unroll
+    for (int z = 0; z < KCH; z++)
+#pragma unroll
+        for (int d = 0; d < 2; d++) {
+            const int pk = min(2 * (K0 + z) - 1 + d, Nfz + 1);
+            old[z][d] = *(const Pair<TF>*)(ub + (size_t)pk * fplane + row);
+        }
     const C w0 = (C)0.75, w1 = (C)0.25;
     // par0: parity term of the black points in the odd fine plane 2K - 1
     // (pi = 2 h + par); the even plane 2K has the other one
@@ -1915,50 +1945,36 @@ __global__ void __launch_bounds__(kBlock) k_prolong3_pair(const TC* __restrict__
     C X[KCH + 2][2][2][2];
 #pragma unroll
     for (int z = 0; z < KCH + 2; z++) {
-        if (z <= nk + 1) {
-            const AxisNb<C> mz = axis_nb_clamped(K0 - 1 + z, Ncz, gr, 2);
-            const TC* __restrict__ ep = e + (size_t)mz.q * cplane;
-            C cv[2][3];
+        const AxisNb<C>& mz = mzs[z];
+        C cv[2][3];
+#pragma unroll
+        for (int y = 0; y < 2; y++)
+#pragma unroll
+            for (int x = 0; x < 3; x++) cv[y][x] = (C)raw[z][y][x];
+        if (edge || mz.ghost) {
 #pragma unroll
             for (int y = 0; y < 2; y++)
 #pragma unroll
-                for (int x = 0; x < 3; x++) cv[y][x] = (C)ep[(mz.q & 1) ? off[1][y][x] : off[0][y][x]];
-            if (edge || mz.ghost) {
+                for (int x = 0; x < 3; x++) {
+                    C v = cv[y][x];
+                    if (mx[x].ghost) v = mx[x].fac * v;
+                    if (my[y].ghost) v = my[y].fac * v;
+                    if (mz.ghost) v = mz.fac * v;
+                    cv[y][x] = v;
+                }
+        }
 #pragma unroll
-                for (int y = 0; y < 2; y++)
-#pragma unroll
-                    for (int x = 0; x < 3; x++) {
-                        C v = cv[y][x];
-                        if (mx[x].ghost) v = mx[x].fac * v;
-                        if (my[y].ghost) v = my[y].fac * v;
-                        if (mz.ghost) v = mz.fac * v;
-                        cv[y][x] = v;
-                    }
-            }
-#pragma unroll
-            for (int y = 0; y < 2; y++) {
-                // par = 1: point 0 has parent column 1 and neighbour 0, point 1
-                // parent 2 and neighbour 1; par = 0: (0, 1) and (1, 2)
-                const C A = par0 ? cv[y][1] : cv[y][0], B = par0 ? cv[y][0] : cv[y][1];
-                const C P = par0 ? cv[y][2] : cv[y][1], Q = par0 ? cv[y][1] : cv[y][2];
-                X[z][0][0][y] = w0 * A + w1 * B;
-                X[z][1][0][y] = w0 * B + w1 * A;
-                X[z][0][1][y] = w0 * P + w1 * Q;
-                X[z][1][1][y] = w0 * Q + w1 * P;
-            }
+        for (int y = 0; y < 2; y++) {
+            // par = 1: point 0 has parent column 1 and neighbour 0, point 1
+            // parent 2 and neighbour 1; par = 0: (0, 1) and (1, 2)
+            const C A = par0 ? cv[y][1] : cv[y][0], B = par0 ? cv[y][0] : cv[y][1];
+            const C P = par0 ? cv[y][2] : cv[y][1], Q = par0 ? cv[y][1] : cv[y][2];
+            X[z][0][0][y] = w0 * A + w1 * B;
+            X[z][1][0][y] = w0 * B + w1 * A;
+            X[z][0][1][y] = w0 * P + w1 * Q;
+            X[z][1][1][y] = w0 * Q + w1 * P;
         }
     }
-    const size_t fplane = gf.ps;
-    const unsigned row = (unsigned)(pj * gf.hx + h0);
-    TF* __restrict__ ub = u + gf.cs;  // black colour array
-    Pair<TF> old[KCH][2];
-#pragma unroll
-    for (int z = 0; z < KCH; z++)
-#pragma unroll
-        for (int d = 0; d < 2; d++) {
-            const int pk = 2 * (K0 + z) - 1 + d;
-            if (z < nk && pk <= Nfz) old[z][d] = *(const Pair<TF>*)(ub + (size_t)pk * fplane + row);
-        }
 #pragma unroll
     for (int z = 0; z < KCH; z++) {
 #pragma unroll
