@@ -2025,6 +2025,8 @@ struct TailParams {
     C h2[kTailMaxLevels];       // smoother factor (2^L h)^2
     C inv_h2[kTailMaxLevels];   // residual factor 1 / (2^L h)^2
     GRule<C> gr[kTailMaxLevels];
+    float rN[kTailMaxLevels][3];  // 1 / N per axis (index decoding)
+    float rS[kTailMaxLevels];     // 1 / ((N_x + 1) / 2), the slots of one colour per row
     int n_pre, n_post;
 };
 
@@ -2059,14 +2061,14 @@ __device__ __forceinline__ int divmod_small(int a, int N, float rN, int& rem)
 }
 
 template <int D>
-__device__ __forceinline__ void tail_point(int t, const int* N, int& i, int& j, int& k)
+__device__ __forceinline__ void tail_point(int t, const int* N, const float* rN, int& i, int& j, int& k)
 {
     int ri;
-    const int r = divmod_small(t, N[0], 1.0f / (float)N[0], ri);
+    const int r = divmod_small(t, N[0], rN[0], ri);
     i = 1 + ri;
     if (D == 3) {
         int rj;
-        k = 1 + divmod_small(r, N[1], 1.0f / (float)N[1], rj);
+        k = 1 + divmod_small(r, N[1], rN[1], rj);
         j = 1 + rj;
     } else {
         j = 1 + r;
@@ -2080,15 +2082,30 @@ __device__ __forceinline__ int box_idx(const int* N, int i, int j, int k)
     return (k * (N[1] + 2) + j) * (N[0] + 2) + i;
 }
 
+// One half sweep; the threads run over the points of the colour only: row
+// (j, k) holds (N_x + 1) / 2 slots, slot s is i = i0 + 2 s with i0 = 1 or 2
+// by the row's parity (a slot past N_x has no point).
 template <int D, typename C>
-__device__ __forceinline__ void tail_sweep(C* U, const C* F, const int* N, C h2, C inv2d, const GRule<C>& gr,
-                                           int colour)
+__device__ __forceinline__ void tail_sweep(C* U, const C* F, const int* N, const float* rN, float rS, C h2, C inv2d,
+                                           const GRule<C>& gr, int colour)
 {
-    const int Qx = N[0] + 2, Qxy = Qx * (N[1] + 2), total = box_active<D>(N);
+    const int Qx = N[0] + 2, Qxy = Qx * (N[1] + 2);
+    const int hs = (N[0] + 1) >> 1;
+    const int total = hs * N[1] * (D == 3 ? N[2] : 1);
     for (int t = threadIdx.x; t < total; t += kTailThreads) {
-        int i, j, k;
-        tail_point<D>(t, N, i, j, k);
-        if (((i + j + k + D) & 1) != colour) continue;
+        int sl;
+        const int row = divmod_small(t, hs, rS, sl);
+        int j, k;
+        if (D == 3) {
+            int rj;
+            k = 1 + divmod_small(row, N[1], rN[1], rj);
+            j = 1 + rj;
+        } else {
+            j = 1 + row;
+            k = 0;
+        }
+        const int i = 1 + ((1 + j + k + D + colour) & 1) + 2 * sl;
+        if (i > N[0]) continue;
         const int idx = box_idx(N, i, j, k);
         C xm = U[idx - 1], xp = U[idx + 1], ym = U[idx - Qx], yp = U[idx + Qx], zm = 0, zp = 0;
         if (D == 3) {
@@ -2112,12 +2129,12 @@ __device__ __forceinline__ void tail_sweep(C* U, const C* F, const int* N, C h2,
 
 template <int D, typename C>
 __device__ __forceinline__ void tail_restrict(const C* U, const C* F, const int* Nf, C inv_h2, const GRule<C>& gr,
-                                              C* Uc, C* Fc, const int* Nc)
+                                              C* Uc, C* Fc, const int* Nc, const float* rNc)
 {
     const int Qx = Nf[0] + 2, Qxy = Qx * (Nf[1] + 2), total = box_active<D>(Nc);
     for (int t = threadIdx.x; t < total; t += kTailThreads) {
         int I, J, K;
-        tail_point<D>(t, Nc, I, J, K);
+        tail_point<D>(t, Nc, rNc, I, J, K);
         C sum = 0;
         const int k0 = D == 3 ? 2 * K - 1 : 0, k1 = D == 3 ? 2 * K : 0;
         for (int k = k0; k <= k1; k++)
@@ -2150,14 +2167,15 @@ __device__ __forceinline__ void tail_restrict(const C* U, const C* F, const int*
 }
 
 template <int D, typename C>
-__device__ __forceinline__ void tail_prolong(const C* Ue, const int* Nc, const GRule<C>& gr, C* U, const int* Nf)
+__device__ __forceinline__ void tail_prolong(const C* Ue, const int* Nc, const GRule<C>& gr, C* U, const int* Nf,
+                                             const float* rNf)
 {
     const int total = box_active<D>(Nf);
     const C w0 = (C)0.75, w1 = (C)0.25;
     const AxisNb<C> none{0, (C)1, false};
     for (int t = threadIdx.x; t < total; t += kTailThreads) {
         int i, j, k;
-        tail_point<D>(t, Nf, i, j, k);
+        tail_point<D>(t, Nf, rNf, i, j, k);
         const int qi = (i + 1) >> 1, si = (i & 1) ? -1 : 1;
         const int qj = (j + 1) >> 1, sj = (j & 1) ? -1 : 1;
         const int qk = D == 3 ? (k + 1) >> 1 : 0, sk = (k & 1) ? -1 : 1;
@@ -2202,7 +2220,7 @@ __global__ void __launch_bounds__(kTailThreads) k_coarse_tail(TailParams<C> P, S
     auto F = [&](int a) { return lds + P.off[a] + box_size<D>(P.N[a]); };
     auto sweep = [&](int a) {
         for (int colour = 0; colour < 2; colour++) {
-            tail_sweep<D, C>(U(a), F(a), P.N[a], P.h2[a], inv2d, P.gr[a], colour);
+            tail_sweep<D, C>(U(a), F(a), P.N[a], P.rN[a], P.rS[a], P.h2[a], inv2d, P.gr[a], colour);
             __syncthreads();
         }
     };
@@ -2213,7 +2231,7 @@ __global__ void __launch_bounds__(kTailThreads) k_coarse_tail(TailParams<C> P, S
         C* f = F(0);
         for (int t = threadIdx.x; t < total; t += kTailThreads) {
             int i, j, k;
-            tail_point<D>(t, N, i, j, k);
+            tail_point<D>(t, N, P.rN[0], i, j, k);
             const int idx = box_idx(N, i, j, k);
             f[idx] = fg[pos<D, C>(g0, i, j, k)];
             u[idx] = (C)0;
@@ -2223,13 +2241,13 @@ __global__ void __launch_bounds__(kTailThreads) k_coarse_tail(TailParams<C> P, S
     for (int it = 0; it < P.n_pre; it++) sweep(0);
     int a = 0;
     while (a + 1 < P.nlev) {
-        tail_restrict<D, C>(U(a), F(a), P.N[a], P.inv_h2[a], P.gr[a], U(a + 1), F(a + 1), P.N[a + 1]);
+        tail_restrict<D, C>(U(a), F(a), P.N[a], P.inv_h2[a], P.gr[a], U(a + 1), F(a + 1), P.N[a + 1], P.rN[a + 1]);
         __syncthreads();
         for (int it = 0; it < P.n_pre; it++) sweep(a + 1);
         a++;
     }
     while (a > 0) {
-        tail_prolong<D, C>(U(a), P.N[a], P.gr[a], U(a - 1), P.N[a - 1]);
+        tail_prolong<D, C>(U(a), P.N[a], P.gr[a], U(a - 1), P.N[a - 1], P.rN[a - 1]);
         __syncthreads();
         for (int it = 0; it < P.n_post; it++) sweep(a - 1);
         a--;
@@ -2240,7 +2258,7 @@ __global__ void __launch_bounds__(kTailThreads) k_coarse_tail(TailParams<C> P, S
         const C* u = U(0);
         for (int t = threadIdx.x; t < total; t += kTailThreads) {
             int i, j, k;
-            tail_point<D>(t, N, i, j, k);
+            tail_point<D>(t, N, P.rN[0], i, j, k);
             ug[pos<D, C>(g0, i, j, k)] = u[box_idx(N, i, j, k)];
         }
     }
@@ -2894,6 +2912,8 @@ int launch_coarse_tail(int dim, hipStream_t st, int nlev, const int (*N)[3], con
         P.h2[a] = (T)(h[a] * h[a]);
         P.inv_h2[a] = (T)(1.0 / (h[a] * h[a]));
         P.gr[a] = grule<T>(rule[a]);
+        for (int ax = 0; ax < 3; ax++) P.rN[a][ax] = ax < dim ? 1.0f / (float)N[a][ax] : 0.0f;
+        P.rS[a] = 1.0f / (float)((N[a][0] + 1) / 2);
     }
     if (dim == 3)
         hipLaunchKernelGGL((k_coarse_tail<3, T>), dim3(1, g0.nb), dim3(kTailThreads), bytes, st, P, g0, f0, u0);

@@ -276,10 +276,12 @@ def _c3_reference():
     return _C3_REF
 
 
+@pytest.mark.parametrize("n_pre", [2, 1], ids=["V21", "V11"])
 @pytest.mark.parametrize("precision", ["fp32_dc", "fp16s_dc"])
-def test_dc_configured_size_plummer_offset(precision):
+def test_dc_configured_size_plummer_offset(precision, n_pre):
     """The mixed-precision workload at its configured size, adaptive inner
-    cycles (as the benchmark runs them): every level's potential within 1e-8 of
+    cycles (as the benchmark runs them), with the paper's V(2,1) inner cycles
+    and with V(1,1) ones: every level's potential within 1e-8 of
     the oracle's converged solution, forces within what that bound allows
     through the fourth-order stencil (18 / (12 dx) of it) of the oracle's
     stencil on its solution, and the Linf force error against the closed form
@@ -287,9 +289,9 @@ def test_dc_configured_size_plummer_offset(precision):
     solve of the same run are printed."""
     ref = _c3_reference()
     wl = ref["wl"]
-    print("gpu: %s %s adaptive" % (wl.name, precision), flush=True)
+    print("gpu: %s %s adaptive, V(%d,1) inner cycles" % (wl.name, precision, n_pre), flush=True)
     phi64, F64, st64 = _solve(wl)
-    phi, F, st = _solve(wl, precision=precision, inner_cycles="adaptive")
+    phi, F, st = _solve(wl, precision=precision, inner_cycles="adaptive", n_pre=n_pre, n_post=1)
     for l in range(wl.geom.nlevels):
         err = np.abs(phi[l] - ref["phi"][l]).max() / np.abs(ref["phi"][l]).max()
         assert err <= 1e-8, (l, err)
