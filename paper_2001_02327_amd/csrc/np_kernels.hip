@@ -1644,6 +1644,157 @@ __global__ void __launch_bounds__(kBlock) k_restrict3_l0(const TF* __restrict__ 
     }
 }
 
+// Residual and restriction out of multigrid level 0 in the paired layout of
+// the level-0 sweeps.  A thread owns coarse row J (fine rows 2J - 1, 2J and
+// their neighbours 2J - 2, 2J + 1) and the compact pair (h0, h0 + 1) of those
+// rows, i.e. the fine points x = 2 h0 .. 2 h0 + 3 of both colours, and forms
+// the coarse points I = h0 + 1 and h0 + 2 (children x = 2 h0 + 1 .. 2 h0 + 4)
+// of a chunk of coarse planes.  Fine values come in paired loads; x = 2 h0 + 4
+// and 2 h0 + 5 are the first pair elements of the next lane, moved by a DPP
+// wave shift.  Lanes run over (J, pair) flat, 63 new pairs per wave: lane 63
+// repeats the next wave's lane 0 so that the shift has a source, and stores
+// nothing.  At a row's end the shifted values come from the next row; they
+// feed only I = N_c + 1, which is not stored.  Per child and in the sum over
+// children the arithmetic and order are those of k_restrict3_l0, with a
+// third of its memory instructions (the 2-byte loads of the FP16 form kept
+// the texture address unit busy).  Requires N_f = 2 N_c along every axis, an
+// even row length hx and arrays of fewer than 2^31 elements.  Used for 2-byte
+// storage: 206 -> 162 us at 514^3; the FP32 and FP64 forms (138 and 230 VGPRs)
+// measured slower than k_restrict3_l0 (325 vs 278 us, 597 vs 537 us).
+constexpr int kRestrictPairChunk = 4;  // coarse planes per thread
+
+template <typename T>
+__device__ __forceinline__ T next_first(const Pair<T>& p);
+template <>
+__device__ __forceinline__ __half next_first(const Pair<__half>& p)
+{
+    return __builtin_bit_cast(__half, (uint16_t)(dpp_next(__builtin_bit_cast(uint32_t, p)) & 0xffffu));
+}
+template <>
+__device__ __forceinline__ float next_first(const Pair<float>& p)
+{
+    return dpp_next(p.a);
+}
+template <>
+__device__ __forceinline__ double next_first(const Pair<double>& p)
+{
+    return dpp_next(p.a);
+}
+
+template <typename TF, typename TC>
+__global__ void __launch_bounds__(kBlock) k_restrict3_pair(const TF* __restrict__ u, const TF* __restrict__ f, SGrid gf,
+                                                            typename Compute<TC>::type inv_h2,
+                                                            typename Compute<TC>::type out_scale, SGrid gc,
+                                                            TC* __restrict__ fc, TC* __restrict__ ec, int pblocks,
+                                                            typename Compute<TC>::type seed_h2,
+                                                            typename Compute<TC>::type inv2d)
+{
+    using C = typename Compute<TC>::type;
+    if (batch_idle(gf)) return;
+    u = batch_at(u, gf);
+    f = batch_at(f, gf);
+    fc = batch_at(fc, gc);
+    ec = batch_at(ec, gc);
+    const int Ncx = gc.nx - 2, Ncy = gc.ny - 2, Ncz = gc.nz - 2;
+    const int lb = (int)xcd_block();
+    const int zc = lb / pblocks;
+    const int lane = (int)(threadIdx.x & 63);
+    const int w = (lb - zc * pblocks) * (kBlock / 64) + (int)(threadIdx.x >> 6);
+    const int e = 63 * w + lane;
+    const int P = gf.hx >> 1;  // pairs per fine row
+    const int J = 1 + e / P;
+    if (J > Ncy) return;
+    const int hp = e - (J - 1) * P;
+    const int h0 = 2 * hp;
+    const int K0 = 1 + zc * kRestrictPairChunk;
+    const int K1 = min(K0 + kRestrictPairChunk - 1, Ncz);
+    const size_t fplane = gf.ps;
+    const unsigned row0 = (unsigned)((2 * J - 2) * gf.hx + h0);
+    // v[m] = a(x = 2 h0 + m) for m = 0..5 in fine row 2J - 2 + r of plane z:
+    // x = 2 h0 + 2 i is in colour (y + z + 1) & 1 at compact h0 + i, the odd
+    // x in the other colour
+    auto seg = [&](const TF* __restrict__ a, int r, int z, C (&v)[6]) {
+        const int y = 2 * J - 2 + r;
+        const bool ca = ((y + z + 1) & 1) != 0;
+        const TF* __restrict__ pl = a + (size_t)z * fplane + (row0 + (unsigned)(r * gf.hx));
+        const Pair<TF> A = *(const Pair<TF>*)(pl + (ca ? gf.cs : 0));
+        const Pair<TF> B = *(const Pair<TF>*)(pl + (ca ? 0 : gf.cs));
+        v[0] = (C)A.a;
+        v[2] = (C)A.b;
+        v[4] = (C)next_first(A);
+        v[1] = (C)B.a;
+        v[3] = (C)B.b;
+        v[5] = (C)next_first(B);
+    };
+    // the residuals of fine plane z (rows 2J - 1 + dy, x = 2 h0 + 1 + j) added to
+    // the two coarse sums in the order dy, dx: c1, c2 the rows 2J - 1, 2J of the
+    // plane, y0, y3 the rows 2J - 2, 2J + 1, zm / zp rows 2J - 1, 2J of the
+    // planes below and above, f1, f2 the right-hand side
+    auto plane_sums = [&](const C (&zm)[2][6], const C (&c)[2][6], const C (&zp)[2][6], const C (&y0)[6],
+                          const C (&y3)[6], const C (&fr)[2][6], C& sa, C& sb) {
+#pragma unroll
+        for (int half = 0; half < 2; half++) {
+            C& sum = half ? sb : sa;
+#pragma unroll
+            for (int dy = 0; dy < 2; dy++) {
+#pragma unroll
+                for (int dx = 0; dx < 2; dx++) {
+                    const int m = 1 + 2 * half + dx;
+                    const C uc = c[dy][m];
+                    C s = c[dy][m - 1] + c[dy][m + 1];
+                    s = s + (dy ? c[0][m] : y0[m]);
+                    s = s + (dy ? y3[m] : c[1][m]);
+                    s = s + zm[dy][m];
+                    s = s + zp[dy][m];
+                    sum += fr[dy][m] - (s - (C)6 * uc) * inv_h2;
+                }
+            }
+        }
+    };
+    const C scale = (C)0.125 * out_scale;
+    const int I = h0 + 1;
+    const bool store_b = lane != 63 && I + 1 <= Ncx, store_a = lane != 63;
+    C lo[2][6], mid[2][6];  // rows 2J - 1, 2J of fine planes 2K - 2, 2K - 1
+#pragma unroll
+    for (int r = 0; r < 2; r++) {
+        seg(u, 1 + r, 2 * K0 - 2, lo[r]);
+        seg(u, 1 + r, 2 * K0 - 1, mid[r]);
+    }
+    auto step = [&](int K) {
+        C n1[2][6], n2[2][6], ya[6], yb[6], yc[6], yd[6], fa[2][6], fb[2][6];
+#pragma unroll
+        for (int r = 0; r < 2; r++) {
+            seg(u, 1 + r, 2 * K, n1[r]);
+            seg(u, 1 + r, 2 * K + 1, n2[r]);
+            seg(f, 1 + r, 2 * K - 1, fa[r]);
+            seg(f, 1 + r, 2 * K, fb[r]);
+        }
+        seg(u, 0, 2 * K - 1, ya);
+        seg(u, 3, 2 * K - 1, yb);
+        seg(u, 0, 2 * K, yc);
+        seg(u, 3, 2 * K, yd);
+        C sa = 0, sb = 0;
+        plane_sums(lo, mid, n1, ya, yb, fa, sa, sb);
+        plane_sums(mid, n1, n2, yc, yd, fb, sa, sb);
+        if (store_a) coarse_out<3, TC, C>(fc, ec, pos<3, TC>(gc, I, J, K), I, J, K, sa * scale, seed_h2, inv2d);
+        if (store_b)
+            coarse_out<3, TC, C>(fc, ec, pos<3, TC>(gc, I + 1, J, K), I + 1, J, K, sb * scale, seed_h2, inv2d);
+#pragma unroll
+        for (int r = 0; r < 2; r++)
+#pragma unroll
+            for (int m = 0; m < 6; m++) {
+                lo[r][m] = n1[r][m];
+                mid[r][m] = n2[r][m];
+            }
+    };
+    if (K1 - K0 + 1 == kRestrictPairChunk) {
+#pragma unroll
+        for (int i = 0; i < kRestrictPairChunk; i++) step(K0 + i);
+    } else {
+        for (int K = K0; K <= K1; K++) step(K);
+    }
+}
+
 // u += P(e) on the fine active points (eqn:prolongation2D/3D as the tensor
 // product of (3/4, 1/4) along each axis: the coarse parent ceil(p/2) weighs
 // 3/4, its neighbour on the side of the fine centre 1/4).  Each thread does
@@ -2827,6 +2978,18 @@ void launch_resid_restrict(int dim, hipStream_t st, SGrid gf, const TF* u, const
         const int kch = Ncx * Ncy >= 128 * 128 ? 4 : 1;
         const int pblocks = ceil_div(Ncx * Ncy, kBlock);
         const dim3 zgrid(pblocks * ceil_div(Ncz, kch), gf.nb);
+        if constexpr (sizeof(TF) == 2) {
+            if (!rule && gf.nx - 2 == 2 * Ncx && gf.ny - 2 == 2 * Ncy && gf.nz - 2 == 2 * Ncz && gf.hx % 2 == 0 &&
+                2 * gf.cs < (1ull << 31)) {
+                // multigrid level 0 in 2-byte storage, paired layout
+                const long waves = ceil_div((long)(gf.hx / 2) * Ncy, 63);
+                const int pb = ceil_div(waves, kBlock / 64);
+                const dim3 pgrid(pb * ceil_div(Ncz, kRestrictPairChunk), gf.nb);
+                hipLaunchKernelGGL((k_restrict3_pair<TF, TC>), pgrid, dim3(kBlock), 0, st, u, f, gf, (C)inv_h2,
+                                   (C)out_scale, gc, fc, ec, pb, sh2, inv2d);
+                return;
+            }
+        }
         if (!rule && gf.nx - 2 == 2 * Ncx && gf.ny - 2 == 2 * Ncy && gf.nz - 2 == 2 * Ncz &&
             2 * gf.cs * sizeof(TF) < (1ull << 31)) {
             // multigrid level 0: uniform addressing
