@@ -125,9 +125,9 @@ void launch_half_sweep(int dim, hipStream_t st, SGrid g, T* u, const T* f, int c
                        const Rule3& rule);
 // Black half sweep of a 3-D multigrid level 0 (even hx, 2- or 4-byte storage)
 // whose red points hold the red half sweep from zero, (0 - h2 f) / 6, unstored:
-// the red values are formed from f
+// the red values are formed from f (and stored into u with store_red)
 template <typename T>
-void launch_half_sweep_seeded(hipStream_t st, SGrid g, T* u, const T* f, double h2);
+void launch_half_sweep_seeded(hipStream_t st, SGrid g, T* u, const T* f, double h2, int store_red);
 // fine grid of type TF, coarse of type TC; the coarse right-hand side is
 // multiplied by out_scale; rule != 0: the fine grid is a level L >= 1.  The
 // coarse correction is cleared, or with seed_h2 > 0 (the coarse level's h^2)

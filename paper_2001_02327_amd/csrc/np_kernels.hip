@@ -1196,11 +1196,14 @@ __device__ __forceinline__ float mix_add2(uint32_t a, uint32_t b)
 // single load.  Same arithmetic, in the same order, as k_smooth_zmarch3.
 // Requires an even row length hx (so pairs never straddle rows and stay
 // aligned).
-// SEED: the first black half sweep of a defect-correction step whose red points
-// hold the result of a red half sweep from zero, e = (0 - h2 r) / (2d), which is
-// not stored: the red values are formed from the defect f (red) here, in the
-// same arithmetic (its ghost layer is zero, as is the correction's).
-template <typename T, bool SEED = false>
+// SEED (1 or 2): the first black half sweep of a defect-correction step whose
+// red points hold the result of a red half sweep from zero, e = (0 - h2 r) /
+// (2d), which is not stored: the red values are formed from the defect f (red)
+// here, in the same arithmetic (its ghost layer is zero, as is the
+// correction's).  With SEED = 2 they are also stored, for a restriction that
+// reads them next (one pre-smoothing sweep); with 1 a red half sweep rewrites
+// them first.
+template <typename T, int SEED = 0>
 __global__ void __launch_bounds__(kSmoothPairBlock) k_smooth_zmarch3_pair(T* __restrict__ u, const T* __restrict__ f, SGrid g,
                                                                 int colour, typename Compute<T>::type h2,
                                                                 typename Compute<T>::type inv2d, int pblocks)
@@ -1235,6 +1238,7 @@ __global__ void __launch_bounds__(kSmoothPairBlock) k_smooth_zmarch3_pair(T* __r
     const size_t col = (size_t)pj * g.hx + h0;
     const T* __restrict__ o = (SEED ? f : u) + (size_t)(colour ^ 1) * g.cs;
     T* __restrict__ uc = u + (size_t)colour * g.cs;
+    T* __restrict__ uo = u + (size_t)(colour ^ 1) * g.cs;  // written with SEED = 2 only
     const T* __restrict__ fc = f + (size_t)colour * g.cs;
     Pair<T> below = sp(*(const Pair<T>*)(o + (size_t)(k0 - 1) * plane + col));
     Pair<T> cur = sp(*(const Pair<T>*)(o + (size_t)k0 * plane + col));
@@ -1295,6 +1299,9 @@ __global__ void __launch_bounds__(kSmoothPairBlock) k_smooth_zmarch3_pair(T* __r
             if (a0) uc[here] = r.a;
             if (a1) uc[here + 1] = r.b;
         }
+        // the pair's red values formed from the defect (0 on its ghost columns,
+        // as the correction's ghost layer)
+        if (SEED == 2) *(Pair<T>*)(uo + here) = cur;
         below = cur;
         cur = above;
     };
@@ -2952,14 +2959,18 @@ void launch_half_sweep(int dim, hipStream_t st, SGrid g, T* u, const T* f, int c
 }
 
 template <typename T>
-void launch_half_sweep_seeded(hipStream_t st, SGrid g, T* u, const T* f, double h2)
+void launch_half_sweep_seeded(hipStream_t st, SGrid g, T* u, const T* f, double h2, int store_red)
 {
     using C = typename Compute<T>::type;
     const long mz = g.nz - 2;
     const int pblocks = ceil_div((long)(g.ps / 2), kSmoothPairBlock);
     const int chunks = ceil_div(mz, kZChunk0);
-    hipLaunchKernelGGL((k_smooth_zmarch3_pair<T, true>), dim3(pblocks * chunks, g.nb), dim3(kSmoothPairBlock), 0, st, u, f,
-                       g, 1, (C)h2, (C)(1.0 / 6.0), pblocks);
+    if (store_red)
+        hipLaunchKernelGGL((k_smooth_zmarch3_pair<T, 2>), dim3(pblocks * chunks, g.nb), dim3(kSmoothPairBlock), 0, st,
+                           u, f, g, 1, (C)h2, (C)(1.0 / 6.0), pblocks);
+    else
+        hipLaunchKernelGGL((k_smooth_zmarch3_pair<T, 1>), dim3(pblocks * chunks, g.nb), dim3(kSmoothPairBlock), 0, st,
+                           u, f, g, 1, (C)h2, (C)(1.0 / 6.0), pblocks);
 }
 
 template <typename TF, typename TC>
@@ -3217,8 +3228,8 @@ template void launch_half_sweep<double>(int, hipStream_t, SGrid, double*, const 
 template void launch_half_sweep<float>(int, hipStream_t, SGrid, float*, const float*, int, double, int, const Rule3&);
 template void launch_half_sweep<__half>(int, hipStream_t, SGrid, __half*, const __half*, int, double, int,
                                         const Rule3&);
-template void launch_half_sweep_seeded<float>(hipStream_t, SGrid, float*, const float*, double);
-template void launch_half_sweep_seeded<__half>(hipStream_t, SGrid, __half*, const __half*, double);
+template void launch_half_sweep_seeded<float>(hipStream_t, SGrid, float*, const float*, double, int);
+template void launch_half_sweep_seeded<__half>(hipStream_t, SGrid, __half*, const __half*, double, int);
 template void launch_resid_restrict<double, double>(int, hipStream_t, SGrid, const double*, const double*, double,
                                                     double, SGrid, double*, double*, int, const Rule3&, double);
 template void launch_resid_restrict<float, float>(int, hipStream_t, SGrid, const float*, const float*, double, double,

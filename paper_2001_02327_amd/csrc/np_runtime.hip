@@ -598,7 +598,8 @@ int vcycle_t(np_solver* s, int l, T0* u0, const T0* f0, double h2_0, double inv_
             bool seeded = false;
             if constexpr (sizeof(T0) <= 4) {
                 if (red_done && red_unstored) {
-                    launch_half_sweep_seeded<T0>(st, v.g[0], u0, f0, h2_0);
+                    // with one pre-smoothing sweep the restriction reads the red values next
+                    launch_half_sweep_seeded<T0>(st, v.g[0], u0, f0, h2_0, c.n_pre == 1);
                     seeded = true;
                 }
             }
@@ -649,12 +650,12 @@ int vcycle(np_solver* s, int l)
 // R(r'' - L e'') / h^2, in the same units as e''.
 // Whether the outer pass leaves the next correction's start unstored: its
 // first black half sweep then forms the red values (the red half sweep from
-// zero) from the defect.  Needs a red half sweep to follow that black one
-// before anything reads red (n_pre >= 2) and the paired level-0 sweep.
+// zero) from the defect, and stores them when no red half sweep follows that
+// black one (n_pre = 1).  Needs the paired level-0 sweep.
 bool dc_seed_black(const np_solver* s, int l)
 {
     const np_config& c = s->cfg;
-    return c.precision != NP_PREC_FP64 && c.dim == 3 && c.n_pre >= 2 && (s->lg[l].hx % 2) == 0;
+    return c.precision != NP_PREC_FP64 && c.dim == 3 && c.n_pre >= 1 && (s->lg[l].hx % 2) == 0;
 }
 
 template <typename TL>
