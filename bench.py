@@ -346,11 +346,19 @@ def run_variant(name, wl, rho, phi_outer, Fs, steps, warmup, inner_cycles, stop_
     prof = solver.profile()
     solver.set_profiling(False)
     # algorithmic bytes of one level-0 half sweep: read the other colour, read f of
-    # this colour, write this colour: 1.5 elements per grid point (both colours counted)
+    # this colour, write this colour: 1.5 elements per grid point (both colours counted).
+    # The seeded black half sweep of a defect-correction step reads the defect of
+    # both colours and writes black, and with one pre-smoothing sweep also the red
+    # start: 1.5 or 2 elements per point; it is timed as a class of its own.
     elem = ELEM[v["precision"]]
-    half_sweep_bytes = 1.5 * elem * math.prod(v + 2 for v in geom.ext(0))
+    npts = math.prod(v + 2 for v in geom.ext(0))
+    half_sweep_bytes = 1.5 * elem * npts
+    seeded_bytes = (2.0 if v.get("n_pre", 2) == 1 else 1.5) * elem * npts
     sm_count, sm_ms = prof["smooth"]
     sm_avg_ms = sm_ms / max(sm_count, 1)
+    sd_count, sd_ms = prof["seeded"]
+    seeded = (dict(launches=sd_count, bytes_per_launch=seeded_bytes, avg_launch_us=round(1e3 * sd_ms / sd_count, 2),
+                   GBps=round(seeded_bytes / (sd_ms / sd_count * 1e-3) / 1e9, 1)) if sd_count else None)
     linf = linf_force_error(solver, wl, Fs)
     edge = edge_force_error(solver, wl, Fs)
     dev = None
@@ -371,8 +379,9 @@ def run_variant(name, wl, rho, phi_outer, Fs, steps, warmup, inner_cycles, stop_
         linf_force_error=linf,
         deviation_from_fp64=dev,
         edge_force_error_per_level=edge,
-        smoother=(dict(elem_bytes=elem, bytes_per_launch=half_sweep_bytes, avg_launch_us=round(sm_avg_ms * 1e3, 2),
-                       GBps=round(half_sweep_bytes / (sm_avg_ms * 1e-3) / 1e9, 1))
+        smoother=(dict(elem_bytes=elem, launches=sm_count, bytes_per_launch=half_sweep_bytes,
+                       avg_launch_us=round(sm_avg_ms * 1e3, 2),
+                       GBps=round(half_sweep_bytes / (sm_avg_ms * 1e-3) / 1e9, 1), seeded=seeded)
                   if len(set(geom.ext(l) for l in range(geom.nlevels))) == 1 else
                   dict(elem_bytes=elem, avg_launch_us=round(sm_avg_ms * 1e3, 2))),
         kernels={k: dict(launches=c, ms_per_step=round(m / steps, 3), avg_us=(round(1e3 * m / c, 2) if c else None))

@@ -219,6 +219,8 @@ int nested_poisson_potential(np_solver* s, int level, double* phi_padded);
 #define NP_KCLASS_FORCES 6   /* force evaluation */
 #define NP_KCLASS_DC 7       /* FP64 residual / correction passes of the defect correction */
 #define NP_KCLASS_GUESS 8    /* learned initial guess (features, three convolutions, update) */
+#define NP_KCLASS_SEEDED 9   /* first black half sweep of a defect-correction step, which forms its red
+                              * neighbours from the defect (and stores them with one pre-smoothing sweep) */
 #define NP_NKCLASS 10
 typedef struct np_profile {
     long count[NP_NKCLASS]; /* launches (intervals) recorded */

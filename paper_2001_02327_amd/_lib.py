@@ -77,7 +77,7 @@ class NpStats(ctypes.Structure):
 
 
 NP_NKCLASS = 10
-KCLASSES = ["smooth", "restrict", "prolong", "coarse", "norm", "fill", "forces", "dc", "guess"]
+KCLASSES = ["smooth", "restrict", "prolong", "coarse", "norm", "fill", "forces", "dc", "guess", "seeded"]
 NP_NET_PARAMS = 8241
 NP_NET_MSE_NOALLOC_MAX = 1 << 28
 NP_GUESS_BLOB_MAGIC = 0x5747504E

@@ -592,6 +592,8 @@ int vcycle_t(np_solver* s, int l, T0* u0, const T0* f0, double h2_0, double inv_
     // the half sweeps of one smoothing step run back to back: one profiling
     // interval over all of them (launch count recorded), so the per-launch
     // average carries no event overhead between the sweeps
+    // (the seeded black half sweep, whose bytes differ, has an interval and a
+    // class of its own)
     int nsweep = 0;
     auto sweep0 = [&]() {
         for (int colour = red_done ? 1 : 0; colour < 2; colour++) {
@@ -599,21 +601,25 @@ int vcycle_t(np_solver* s, int l, T0* u0, const T0* f0, double h2_0, double inv_
             if constexpr (sizeof(T0) <= 4) {
                 if (red_done && red_unstored) {
                     // with one pre-smoothing sweep the restriction reads the red values next
+                    prof_begin(s, NP_KCLASS_SEEDED);
                     launch_half_sweep_seeded<T0>(st, v.g[0], u0, f0, h2_0, c.n_pre == 1);
+                    prof_end(s);
                     seeded = true;
                 }
             }
-            if (!seeded) launch_half_sweep<T0>(d, st, v.g[0], u0, f0, colour, h2_0, 1, Rule3{});
-            nsweep++;
+            if (!seeded) {
+                if (nsweep == 0) prof_begin(s, NP_KCLASS_SMOOTH);
+                launch_half_sweep<T0>(d, st, v.g[0], u0, f0, colour, h2_0, 1, Rule3{});
+                nsweep++;
+            }
             red_done = false;
         }
     };
     auto smooth0 = [&](int sweeps) {
         if (sweeps <= 0) return;
         nsweep = 0;
-        prof_begin(s, NP_KCLASS_SMOOTH);
         for (int it = 0; it < sweeps; it++) sweep0();
-        prof_end(s, nsweep);
+        if (nsweep) prof_end(s, nsweep);
     };
     smooth0(c.n_pre);
     // the restriction does multigrid level 1's first red half sweep unless the
