@@ -39,9 +39,10 @@ def kernel_source_sha():
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
-def measured_traffic(variant, n0):
-    """HBM bytes per launch of the level-0 half sweep of `variant` at n0^3 points
-    from the PMC summary, or None when it was taken on another kernel source."""
+def measured_traffic(variant, kind, n0):
+    """HBM bytes per launch of the level-0 smoothing kernel `kind` (smooth: half
+    sweep, full: full sweep) of `variant` at n0^3 points from the PMC summary, or
+    None when it was taken on another kernel source."""
     if not os.path.exists(PMC_SUMMARY):
         return None
     sha = kernel_source_sha()
@@ -51,7 +52,8 @@ def measured_traffic(variant, n0):
             if len(f) < 2 or f[0] != "traffic":
                 continue
             kv = dict(x.split("=", 1) for x in f[1:] if "=" in x)
-            if kv.get("variant") == variant and int(kv.get("points", 0)) == n0 and kv.get("source_sha") == sha:
+            if (kv.get("variant") == variant and kv.get("kind") == kind and int(kv.get("points", 0)) == n0
+                    and kv.get("source_sha") == sha):
                 return float(kv["bytes"])
     return None
 
@@ -345,20 +347,31 @@ def run_variant(name, wl, rho, phi_outer, Fs, steps, warmup, inner_cycles, stop_
     ms_profiled = e0.elapsed_time(e1) / steps
     prof = solver.profile()
     solver.set_profiling(False)
-    # algorithmic bytes of one level-0 half sweep: read the other colour, read f of
-    # this colour, write this colour: 1.5 elements per grid point (both colours counted).
-    # The seeded black half sweep of a defect-correction step reads the defect of
-    # both colours and writes black, and with one pre-smoothing sweep also the red
-    # start: 1.5 or 2 elements per point; it is timed as a class of its own.
+    # algorithmic bytes per grid point of multigrid level 0 (both colours counted),
+    # in elements e of the storage type, of each smoothing kernel class:
+    #   half sweep: read the other colour, read f of this colour, write this colour: 1.5 e;
+    #   seeded black half sweep of a defect-correction step: read the defect of both
+    #   colours, write black (and with one pre-smoothing sweep also the red start): 1.5 or 2 e;
+    #   full sweep (FP64, 3-D): read P's black points, f of both colours, write both
+    #   colours of Q: 2.5 e; the one that completes the stop test's residual also
+    #   reads P's red points: 3 e.
     elem = ELEM[v["precision"]]
     npts = math.prod(v + 2 for v in geom.ext(0))
-    half_sweep_bytes = 1.5 * elem * npts
-    seeded_bytes = (2.0 if v.get("n_pre", 2) == 1 else 1.5) * elem * npts
-    sm_count, sm_ms = prof["smooth"]
-    sm_avg_ms = sm_ms / max(sm_count, 1)
-    sd_count, sd_ms = prof["seeded"]
-    seeded = (dict(launches=sd_count, bytes_per_launch=seeded_bytes, avg_launch_us=round(1e3 * sd_ms / sd_count, 2),
-                   GBps=round(seeded_bytes / (sd_ms / sd_count * 1e-3) / 1e9, 1)) if sd_count else None)
+    per_point = dict(smooth=1.5, seeded=2.0 if v.get("n_pre", 2) == 1 else 1.5, full=2.5, full_res=3.0)
+    uniform = len(set(geom.ext(l) for l in range(geom.nlevels))) == 1
+    sweeps = {}
+    for cls, e in per_point.items():
+        cnt, ms_c = prof[cls]
+        if not cnt:
+            continue
+        avg = ms_c / cnt
+        d = dict(launches=cnt, avg_launch_us=round(avg * 1e3, 2), ms_per_step=round(ms_c / steps, 3))
+        if uniform:
+            d.update(bytes_per_launch=e * elem * npts, GBps=round(e * elem * npts / (avg * 1e-3) / 1e9, 1))
+        sweeps[cls] = d
+    # the roofline kernel: the smoothing class with the most device time
+    main_cls = max((c for c in ("smooth", "full") if c in sweeps), key=lambda c: sweeps[c]["ms_per_step"])
+    smoother = dict(sweeps[main_cls], kind=main_cls, elem_bytes=elem, classes=sweeps)
     linf = linf_force_error(solver, wl, Fs)
     edge = edge_force_error(solver, wl, Fs)
     dev = None
@@ -379,11 +392,7 @@ def run_variant(name, wl, rho, phi_outer, Fs, steps, warmup, inner_cycles, stop_
         linf_force_error=linf,
         deviation_from_fp64=dev,
         edge_force_error_per_level=edge,
-        smoother=(dict(elem_bytes=elem, launches=sm_count, bytes_per_launch=half_sweep_bytes,
-                       avg_launch_us=round(sm_avg_ms * 1e3, 2),
-                       GBps=round(half_sweep_bytes / (sm_avg_ms * 1e-3) / 1e9, 1), seeded=seeded)
-                  if len(set(geom.ext(l) for l in range(geom.nlevels))) == 1 else
-                  dict(elem_bytes=elem, avg_launch_us=round(sm_avg_ms * 1e3, 2))),
+        smoother=smoother,
         kernels={k: dict(launches=c, ms_per_step=round(m / steps, 3), avg_us=(round(1e3 * m / c, 2) if c else None))
                  for k, (c, m) in prof.items()},
     )
@@ -513,12 +522,15 @@ def main():
         },
         "roofline": None if not uniform else {
             "bound": "hbm",
-            "kernel": "level-0 red-black half sweep of variant %s (%d-byte storage)" % (best, sm["elem_bytes"]),
+            "kernel": "level-0 red-black %s of variant %s (%d-byte storage)"
+                      % ("half sweep" if sm["kind"] == "smooth" else "full sweep (one pass, two buffers)", best,
+                         sm["elem_bytes"]),
             "achieved": sm["GBps"],
             "peak": PEAK_HBM_GBS,
             "unit": "GB/s",
             "frac": round(sm["GBps"] / PEAK_HBM_GBS, 4),
-            "traffic": measured_traffic(VARIANTS[best]["precision"], geom.ext(0)[0] + 2) if geom.cubic else None,
+            "traffic": (measured_traffic(VARIANTS[best]["precision"], sm["kind"], geom.ext(0)[0] + 2) if geom.cubic
+                        else None),
             "traffic_source": os.path.relpath(PMC_SUMMARY, ROOT),
             "kernel_source_sha": kernel_source_sha(),
             "bytes_per_launch": sm["bytes_per_launch"],

@@ -88,6 +88,19 @@ extern "C" {
                                layer is its Dirichlet data); FP64, interpolated guess and the
                                residual stop rule only */
 
+/* How multigrid level 0 of a 3-D FP64 solve is smoothed (np_config.sweep).
+ * NP_SWEEP_FULL: each red-black sweep is one pass from the level's potential
+ * into a second buffer (the handle's; the buffers then trade roles), and the
+ * stop test's residual norm is taken inside the sweeps: over the black points
+ * by the last post-smoothing sweep, over the red points by the next cycle's
+ * first pre-smoothing sweep, which runs before the test and is dropped when
+ * the level stops (needs n_pre >= 1 and n_post >= 1, the relaxed buffer on
+ * levels l >= 1 and a level solved on its own; elsewhere the half sweeps run).
+ * NP_SWEEP_HALF: two half sweeps in place and a separate residual pass.  The
+ * iterates are the same in both. */
+#define NP_SWEEP_FULL 0
+#define NP_SWEEP_HALF 1
+
 typedef struct np_config {
     int dim;                        /* 2 or 3 */
     int nlevels;                    /* 1..NP_MAX_LEVELS */
@@ -115,6 +128,7 @@ typedef struct np_config {
                                        all of them, each patch stopping at its own cycle count (FP64,
                                        interpolated guess, relaxed buffer, residual stop rule;
                                        otherwise one after another); 0: one after another */
+    int sweep;                      /* NP_SWEEP_* (default NP_SWEEP_FULL) */
 } np_config;
 
 /* Fills `cfg` with the paper's solver settings (N_pre = 2, N_post = 1,
@@ -221,7 +235,9 @@ int nested_poisson_potential(np_solver* s, int level, double* phi_padded);
 #define NP_KCLASS_GUESS 8    /* learned initial guess (features, three convolutions, update) */
 #define NP_KCLASS_SEEDED 9   /* first black half sweep of a defect-correction step, which forms its red
                               * neighbours from the defect (and stores them with one pre-smoothing sweep) */
-#define NP_NKCLASS 10
+#define NP_KCLASS_FULL 10    /* full red-black sweeps of multigrid level 0 (NP_SWEEP_FULL) */
+#define NP_KCLASS_FULL_RES 11 /* the full sweep that also completes the stop test's residual norm */
+#define NP_NKCLASS 12
 typedef struct np_profile {
     long count[NP_NKCLASS]; /* launches (intervals) recorded */
     double ms[NP_NKCLASS];  /* summed device time */

@@ -27,6 +27,7 @@ STOP_RULES = {"residual": 0, "force_delta": 1}
 PRECISIONS = {"fp64": 0, "fp32_dc": 1, "fp16s_dc": 2}
 GUESSES = {"interp": 0, "learned": 1}
 BUFFERS = {"relaxed": 0, "interp": 1}
+SWEEPS = {"full": 0, "half": 1}
 
 
 class NpConfig(ctypes.Structure):
@@ -49,6 +50,7 @@ class NpConfig(ctypes.Structure):
         ("parent", ctypes.c_int * NP_MAX_LEVELS),
         ("extent", (ctypes.c_int * 3) * NP_MAX_LEVELS),
         ("batch", ctypes.c_int),
+        ("sweep", ctypes.c_int),
     ]
 
 
@@ -76,8 +78,9 @@ class NpStats(ctypes.Structure):
     ]
 
 
-NP_NKCLASS = 10
-KCLASSES = ["smooth", "restrict", "prolong", "coarse", "norm", "fill", "forces", "dc", "guess", "seeded"]
+NP_NKCLASS = 12
+KCLASSES = ["smooth", "restrict", "prolong", "coarse", "norm", "fill", "forces", "dc", "guess", "seeded", "full",
+            "full_res"]
 NP_NET_PARAMS = 8241
 NP_NET_MSE_NOALLOC_MAX = 1 << 28
 NP_GUESS_BLOB_MAGIC = 0x5747504E
@@ -156,7 +159,7 @@ class NestedPoissonError(RuntimeError):
 
 
 def make_config(geom, n_pre=2, n_post=1, tol=1e-10, max_cycles=50, stop_rule="residual", precision="fp64",
-                inner_cycles=1, guess="interp", buffer="relaxed", batch=True):
+                inner_cycles=1, guess="interp", buffer="relaxed", batch=True, sweep="full"):
     """np_config from a geometry (attributes dim, n, off, dx0, G) and solver settings."""
     c = NpConfig()
     lib().nested_poisson_default_config(ctypes.byref(c))
@@ -183,6 +186,7 @@ def make_config(geom, n_pre=2, n_post=1, tol=1e-10, max_cycles=50, stop_rule="re
     c.guess = GUESSES[guess] if isinstance(guess, str) else int(guess)
     c.buffer = BUFFERS[buffer] if isinstance(buffer, str) else int(buffer)
     c.batch = 1 if batch else 0
+    c.sweep = SWEEPS[sweep] if isinstance(sweep, str) else int(sweep)
     parent = getattr(geom, "parent", None)
     if parent is not None:
         for l, p in enumerate(parent):

@@ -128,6 +128,15 @@ void launch_half_sweep(int dim, hipStream_t st, SGrid g, T* u, const T* f, int c
 // the red values are formed from f (and stored into u with store_red)
 template <typename T>
 void launch_half_sweep_seeded(hipStream_t st, SGrid g, T* u, const T* f, double h2, int store_red);
+// One red-black sweep of a 3-D multigrid level 0 (ghost layer in memory) from
+// P into Q (Q's ghost layer must equal P's; P is not written).  mode bit 0:
+// max |f - lap P| over P's red points into maxbits; bit 1: max |f - lap Q| over
+// Q's black points (atomic maxima of the bit patterns; slot zeroed by the
+// caller).  rev: order of the z-chunks (cache reuse only)
+constexpr int kSweepResIn = 1, kSweepResOut = 2;
+template <typename T>
+void launch_full_sweep(hipStream_t st, SGrid g, const T* P, T* Q, const T* f, double h2, double inv_h2, int mode,
+                       int rev, unsigned long long* maxbits);
 // fine grid of type TF, coarse of type TC; the coarse right-hand side is
 // multiplied by out_scale; rule != 0: the fine grid is a level L >= 1.  The
 // coarse correction is cleared, or with seed_h2 > 0 (the coarse level's h^2)

@@ -198,6 +198,14 @@ __device__ __forceinline__ unsigned long long abs_bits(double a)
     return (unsigned long long)__double_as_longlong(fabs(a));
 }
 
+// Residual f - (s - 2d u) / h^2 at a point (s: the sum of its 2d neighbours)
+// with the rounding every residual-norm pass uses: one fused multiply-add
+// forms s - 2d u, a second f - (s - 2d u) inv_h2.
+__device__ __forceinline__ double resid(double f, double s, double u, double two_d, double inv_h2)
+{
+    return __fma_rn(-inv_h2, __fma_rn(-two_d, u, s), f);
+}
+
 // ------------------------------------------------------------------ level setup
 // Level 0: potential = caller's outer layer on the ring, zero on Gamma^0;
 // right-hand side = 4 pi G rho on Gamma^0 (caller gives Omega^0 plus its inner
@@ -769,7 +777,7 @@ __global__ void __launch_bounds__(kBlock) k_norm(SGrid g, const double* __restri
                     s = s + o[row - nz + h];
                     s = s + o[row + nz + h];
                 }
-                val = f[self] - (s - (2.0 * D) * u[self]) * inv_h2;
+                val = resid(f[self], s, u[self], 2.0 * D, inv_h2);
             }
             unsigned long long b = abs_bits(val);
             best = b > best ? b : best;
@@ -827,7 +835,7 @@ __global__ void __launch_bounds__(kBlock) k_resid_norm3(SGrid g, const double* _
                 s = s + a[o][here + g.hx];
                 s = s + below[o];
                 s = s + above[o];
-                double r = f[(size_t)c * g.cs + here] - (s - 6.0 * cur[c]) * inv_h2;
+                double r = resid(f[(size_t)c * g.cs + here], s, cur[c], 6.0, inv_h2);
                 unsigned long long b = abs_bits(r);
                 best = b > best ? b : best;
             }
@@ -1357,6 +1365,201 @@ __global__ void __launch_bounds__(kSmoothPairBlock) k_smooth_zmarch3_pair(T* __r
         step(pk, sp(*(const Pair<T>*)(o + here + plane)), sp(*(const Pair<T>*)(o + here - g.hx)),
              sp(*(const Pair<T>*)(o + here + g.hx)), *(const Pair<T>*)(fc + here), extra(pk, here));
     }
+}
+
+// ------------------------------------------------------------------ full sweep
+// One red-black sweep of multigrid level 0 of a 3-D level (ghost layer in
+// memory) in a single pass, from the potential P into a second array Q whose
+// ghost layer is P's: red points first, then black, each with the arithmetic
+// of the half sweeps above, so Q ends up holding what the two half sweeps in
+// place would leave (bit for bit).  The black update of a point reads the new
+// red values of the rows beside it, which belong to other threads, so a
+// thread relaxes the red points of its G rows and of one row on either side of
+// them, and of one plane beyond either end of its chunk of planes, and keeps
+// them in registers; it stores only its own.  The x-neighbour in the other
+// compact slot comes from the adjacent lane by a DPP shift; a wave owns the
+// kFsOwn columns between its first and its last lane, which only supply red
+// values to their neighbours.  No thread reads what another writes.
+// MODE & kFsResIn: also max |f - lap P| over the red points owned.  P's black
+// points are exact (their residual was taken by the black update of the sweep
+// that produced P, MODE & kFsResOut), so together they give P's residual norm,
+// with the operations of the residual pass (k_dc_outer3_pair) per point.
+constexpr int kFsBlock = 256;
+constexpr int kFsOwn = 62;   // columns a wave owns (lanes 1..62)
+constexpr int kFsRows = 3;   // rows per thread (1, 2, 3, 4 measured: 3 fastest)
+constexpr int kFsChunk = 16; // planes per thread
+constexpr int kFsResIn = kSweepResIn, kFsResOut = kSweepResOut;
+
+template <typename T, int G, int KCH, int MODE>
+__global__ void __launch_bounds__(kFsBlock) k_full_sweep3(const T* __restrict__ P, T* __restrict__ Q,
+                                                          const T* __restrict__ f, SGrid g, double h2, double inv2d,
+                                                          double inv_h2, int nrg, int wblocks, int rev,
+                                                          unsigned long long* maxbits)
+{
+    using C = typename Compute<T>::type;
+    constexpr int R = G + 2;  // rows whose red points the thread relaxes
+    const C h2c = (C)h2, inv2dc = (C)inv2d;
+    const int mx = g.nx - 2, my = g.ny - 2, mz = g.nz - 2;
+    const int lb = zmarch_block(rev);
+    const int zc = lb / wblocks;
+    const long wave = (long)(lb - zc * wblocks) * (kFsBlock / 64) + (threadIdx.x >> 6);
+    const int lane = (int)(threadIdx.x & 63);
+    const long total = (long)nrg * g.hx;
+    const long t = wave * kFsOwn + lane - 1;
+    const bool owner = lane >= 1 && lane <= kFsOwn && t >= 0 && t < total;
+    const long tc = t < 0 ? 0 : (t >= total ? total - 1 : t);
+    const int rg = (int)(tc / g.hx);
+    const int h = (int)(tc - (long)rg * g.hx);
+    const int j0 = 1 + G * rg;  // first own row
+    const int k0 = 1 + zc * KCH;
+    const int k1 = min(k0 + KCH - 1, mz);
+    const size_t cs = g.cs, ps = g.ps;
+    const int hm = h > 0 ? h - 1 : 0, hp = h + 1 < g.hx ? h + 1 : g.hx - 1;
+    // element offsets inside a plane (32-bit; plane bases are uniform) of the red
+    // rows j0-1 .. j0+G and of the rows j0-2 and j0+G+1 (rows clamped into the
+    // array: values of rows outside it are never used)
+    auto rowc = [&](int r) { return r < 0 ? 0 : (r > my + 1 ? my + 1 : r); };
+    auto planec = [&](int k) { return (size_t)(k < 0 ? 0 : (k > mz + 1 ? mz + 1 : k)) * ps; };
+    unsigned ro[R];
+#pragma unroll
+    for (int i = 0; i < R; i++) ro[i] = (unsigned)(rowc(j0 - 1 + i) * g.hx + h);
+    const unsigned ry0 = (unsigned)(rowc(j0 - 2) * g.hx + h), ry1 = (unsigned)(rowc(j0 + G + 1) * g.hx + h);
+    const int dm = hm - h, dp = hp - h;  // the other compact slot of the edge lanes
+    const T* __restrict__ Pr = P;
+    const T* __restrict__ Pb = P + cs;
+    const T* __restrict__ fr = f;
+    const T* __restrict__ fb = f + cs;
+    T* __restrict__ Qr = Q;
+    T* __restrict__ Qb = Q + cs;
+    C b0[R], b1[R];  // P's black values of the red rows at planes k - 1 and k
+    C rn[R];         // new red values at plane k - 1
+    C rp[G];         // new red values of the own rows at plane k - 2
+    {
+        const T* __restrict__ pa = Pb + planec(k0 - 2);
+        const T* __restrict__ pb = Pb + planec(k0 - 1);
+#pragma unroll
+        for (int i = 0; i < R; i++) {
+            b0[i] = (C)pa[ro[i]];
+            b1[i] = (C)pb[ro[i]];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < R; i++) rn[i] = (C)0;
+#pragma unroll
+    for (int i = 0; i < G; i++) rp[i] = (C)0;
+    unsigned long long best = 0;
+    // the loads of step k (red points of plane k, black points of plane k - 1),
+    // all issued before the step computes
+    struct Loads {
+        C ba[R], fv[R], ex[R], gh[R], fbv[G], prv[G], y0, y1;
+    };
+    auto load = [&](int k, Loads& L) {
+        const T* __restrict__ pbk = Pb + planec(k);
+        const T* __restrict__ pba = Pb + planec(k + 1);
+        const T* __restrict__ prk = Pr + planec(k);
+        const T* __restrict__ frk = fr + planec(k);
+        const T* __restrict__ fbk = fb + planec(k - 1);
+        const bool kact = k >= 1 && k <= mz;
+        L.y0 = (C)pbk[ry0];
+        L.y1 = (C)pbk[ry1];
+#pragma unroll
+        for (int i = 0; i < R; i++) {
+            const int r = j0 - 1 + i;
+            const int par = (r + k + 3) & 1;  // red point pi = 2h + par
+            const int pi = 2 * h + par;
+            L.ba[i] = (C)pba[ro[i]];
+            L.fv[i] = (C)frk[ro[i]];
+            L.ex[i] = (C)0;
+            if (par ? lane == 63 : lane == 0) L.ex[i] = (C)pbk[(int)ro[i] + (par ? dp : dm)];
+            L.gh[i] = (C)0;
+            const bool act = kact && r >= 1 && r <= my && pi >= 1 && pi <= mx;
+            if (!act) L.gh[i] = (C)prk[ro[i]];
+        }
+        const bool bstep = k - 1 >= k0;
+        const bool red_own = k >= k0 && k <= k1;
+#pragma unroll
+        for (int i = 0; i < G; i++) {
+            L.fbv[i] = bstep ? (C)fbk[ro[i + 1]] : (C)0;
+            L.prv[i] = ((MODE & kFsResIn) && red_own) ? (C)prk[ro[i + 1]] : (C)0;
+        }
+    };
+    auto step = [&](int k, const Loads& L) {
+        const size_t pk = planec(k), pkb = planec(k - 1);
+        const bool red_own = k >= k0 && k <= k1;
+        const bool bstep = k - 1 >= k0;
+        const bool kact = k >= 1 && k <= mz;
+        // red points of plane k
+        C rk[R];
+#pragma unroll
+        for (int i = 0; i < R; i++) {
+            const int r = j0 - 1 + i;
+            const int par = (r + k + 3) & 1;
+            const int pi = 2 * h + par;
+            const C sh = par ? dpp_next(b1[i]) : dpp_prev(b1[i]);
+            const C e = (par ? lane == 63 : lane == 0) ? L.ex[i] : sh;
+            const C xm = par ? b1[i] : e;
+            const C xp = par ? e : b1[i];
+            const C y0 = i == 0 ? L.y0 : b1[i - 1];
+            const C y1 = i == R - 1 ? L.y1 : b1[i + 1];
+            C s = xm + xp;
+            s = s + y0;
+            s = s + y1;
+            s = s + b0[i];
+            s = s + L.ba[i];
+            const bool act = kact && r >= 1 && r <= my && pi >= 1 && pi <= mx;
+            const T v = (T)((s - h2c * L.fv[i]) * inv2dc);
+            rk[i] = act ? (C)v : L.gh[i];
+            if (i >= 1 && i <= G && red_own && owner && act) {
+                (Qr + pk)[ro[i]] = v;
+                if (MODE & kFsResIn) {
+                    const double res = resid(L.fv[i], s, L.prv[i - 1], 6.0, inv_h2);
+                    const unsigned long long bb = abs_bits(res);
+                    best = bb > best ? bb : best;
+                }
+            }
+        }
+        // black points of plane k - 1
+        if (bstep) {
+#pragma unroll
+            for (int i = 0; i < G; i++) {
+                const int r = j0 + i;
+                const int kb = k - 1;
+                const int par = (r + kb + 4) & 1;
+                const int pi = 2 * h + par;
+                const C sh = par ? dpp_next(rn[i + 1]) : dpp_prev(rn[i + 1]);
+                const C xm = par ? rn[i + 1] : sh;
+                const C xp = par ? sh : rn[i + 1];
+                C s = xm + xp;
+                s = s + rn[i];
+                s = s + rn[i + 2];
+                s = s + rp[i];
+                s = s + rk[i + 1];
+                const T v = (T)((s - h2c * L.fbv[i]) * inv2dc);
+                if (owner && r <= my && pi >= 1 && pi <= mx) {
+                    (Qb + pkb)[ro[i + 1]] = v;
+                    if (MODE & kFsResOut) {
+                        const double res = resid(L.fbv[i], s, (C)v, 6.0, inv_h2);
+                        const unsigned long long bb = abs_bits(res);
+                        best = bb > best ? bb : best;
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < G; i++) rp[i] = rn[i + 1];
+#pragma unroll
+        for (int i = 0; i < R; i++) {
+            rn[i] = rk[i];
+            b0[i] = b1[i];
+            b1[i] = L.ba[i];
+        }
+    };
+    for (int k = k0 - 1; k <= k1 + 1; k++) {
+        Loads L;
+        load(k, L);
+        step(k, L);
+    }
+    if (MODE) block_max_to(best, maxbits);
 }
 
 // Coarse right-hand side and correction of one coarse point.  With seed_h2 > 0
@@ -2517,7 +2720,7 @@ __global__ void __launch_bounds__(kBlock) k_dc_outer(SGrid g, DcIn<TL, UPD> in, 
             }
             const double cen = in(self);
             if (UPD) pout[self] = cen;
-            double v = f[self] - (s - (2.0 * D) * cen) * inv_h2;
+            double v = resid(f[self], s, cen, 2.0 * D, inv_h2);
             dc_out<TL>(self, c, v, rscale, r, eout, first_red, h2l, inv2d);
             unsigned long long b = abs_bits(v);
             best = b > best ? b : best;
@@ -2574,7 +2777,7 @@ __global__ void __launch_bounds__(kBlock) k_dc_outer3(SGrid g, DcIn<TL, UPD> in,
                 s = s + above[o];
                 const size_t self = c * cs + here;
                 if (UPD) pout[self] = cur[c];
-                double v = f[self] - (s - 6.0 * cur[c]) * inv_h2;
+                double v = resid(f[self], s, cur[c], 6.0, inv_h2);
                 dc_out<TL>(self, c, v, rscale, r, eout, first_red, h2l, inv2d);
                 unsigned long long b = abs_bits(v);
                 best = b > best ? b : best;
@@ -2698,8 +2901,8 @@ __global__ void __launch_bounds__(kBlock) k_dc_outer3_pair(SGrid g, DcIn<TL, UPD
                 s1 = s1 + d.above[o].b;
                 const size_t self = c * cs + here;
                 const Pair<double> fv = d.fv[c];
-                const double v0 = fv.a - (s0 - 6.0 * cur[c].a) * inv_h2;
-                const double v1 = fv.b - (s1 - 6.0 * cur[c].b) * inv_h2;
+                const double v0 = resid(fv.a, s0, cur[c].a, 6.0, inv_h2);
+                const double v1 = resid(fv.b, s1, cur[c].b, 6.0, inv_h2);
                 Pair<TL> rl, el;
                 rl.a = (TL)(float)(v0 * rscale);
                 rl.b = (TL)(float)(v1 * rscale);
@@ -2973,6 +3176,28 @@ void launch_half_sweep_seeded(hipStream_t st, SGrid g, T* u, const T* f, double 
                            u, f, g, 1, (C)h2, (C)(1.0 / 6.0), pblocks);
 }
 
+template <typename T>
+void launch_full_sweep(hipStream_t st, SGrid g, const T* P, T* Q, const T* f, double h2, double inv_h2, int mode,
+                       int rev, unsigned long long* maxbits)
+{
+    const int my = g.ny - 2, mz = g.nz - 2;
+    const int nrg = ceil_div(my, kFsRows);
+    const long waves = ceil_div((long)nrg * g.hx, kFsOwn);
+    const int wblocks = ceil_div(waves, kFsBlock / 64);
+    const dim3 grid(wblocks * ceil_div(mz, kFsChunk));
+    const double inv2d = 1.0 / 6.0;
+#define NP_FS(M)                                                                                                    \
+    hipLaunchKernelGGL((k_full_sweep3<T, kFsRows, kFsChunk, M>), grid, dim3(kFsBlock), 0, st, P, Q, f, g, h2, inv2d, \
+                       inv_h2, nrg, wblocks, rev, maxbits)
+    switch (mode & 3) {
+    case 0: NP_FS(0); break;
+    case 1: NP_FS(1); break;
+    case 2: NP_FS(2); break;
+    default: NP_FS(3); break;
+    }
+#undef NP_FS
+}
+
 template <typename TF, typename TC>
 void launch_resid_restrict(int dim, hipStream_t st, SGrid gf, const TF* u, const TF* f, double inv_h2, double out_scale,
                            SGrid gc, TC* fc, TC* ec, int rule, const Rule3& fine_rule, double seed_h2)
@@ -3225,6 +3450,8 @@ void launch_copy_box(int dim, hipStream_t st, SGrid gs, const double* src, SGrid
 }
 
 template void launch_half_sweep<double>(int, hipStream_t, SGrid, double*, const double*, int, double, int, const Rule3&);
+template void launch_full_sweep<double>(hipStream_t, SGrid, const double*, double*, const double*, double, double, int,
+                                        int, unsigned long long*);
 template void launch_half_sweep<float>(int, hipStream_t, SGrid, float*, const float*, int, double, int, const Rule3&);
 template void launch_half_sweep<__half>(int, hipStream_t, SGrid, __half*, const __half*, int, double, int,
                                         const Rule3&);

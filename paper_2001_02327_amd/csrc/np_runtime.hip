@@ -94,6 +94,7 @@ bool validate(const np_config* c, char* why, size_t nwhy)
         return fail("the interpolated buffer runs with FP64, the interpolated guess and the residual stop "
                     "rule only");
     if (c->batch != 0 && c->batch != 1) return fail("batch must be 0 or 1 (got %d)", c->batch);
+    if (c->sweep != NP_SWEEP_FULL && c->sweep != NP_SWEEP_HALF) return fail("bad sweep %d", c->sweep);
     return true;
 }
 
@@ -332,6 +333,7 @@ struct np_solver {
     size_t lo_bytes = 0;
     double* phi_alt = nullptr;
     size_t alt_cap = 0;
+    int fs_rev = 0;  // z order of the next full sweep (alternates; cache reuse only)
     size_t phi_cap[NP_MAX_LEVELS] = {};
     float* mg_u32[NP_MAX_MG] = {};
     float* mg_f32[NP_MAX_MG] = {};
@@ -648,6 +650,89 @@ int vcycle(np_solver* s, int l)
     MGView<double> v = mg_view<double>(s, l, s->mg_u, s->mg_f);
     double h = v.h[0];
     return vcycle_t<double, double>(s, l, s->phi[l], s->f[l], h * h, 1.0 / (h * h), 1.0, v, s->coarse_exec);
+}
+
+// Whether nested level l (solved on its own) runs full sweeps on multigrid level 0.
+bool full_sweeps(const np_solver* s, int l)
+{
+    const np_config& c = s->cfg;
+    return c.dim == 3 && c.precision == NP_PREC_FP64 && c.sweep == NP_SWEEP_FULL && s->phi_alt && c.n_pre >= 1 &&
+           c.n_post >= 1 && !(l > 0 && c.buffer == NP_BUFFER_INTERP);
+}
+
+// One full sweep of level l's multigrid level 0 from the potential into the
+// spare buffer, which then becomes the potential (mode: kSweepRes* bits).
+void full_sweep(np_solver* s, int l, int mode)
+{
+    const double h = level_dx(&s->cfg, l);
+    launch_full_sweep<double>(s->stream, s->lg[l], s->phi[l], s->phi_alt, s->f[l], h * h, 1.0 / (h * h), mode,
+                              s->fs_rev, s->d_bits);
+    s->fs_rev ^= 1;
+    std::swap(s->phi[l], s->phi_alt);
+    std::swap(s->phi_cap[l], s->alt_cap);
+}
+
+// Plain FP64 V-cycle (Sec. 2.3 steps 2-13) with full sweeps on multigrid level
+// 0.  The last post-smoothing sweep takes the residual norm of its black points
+// into slot 0 (zeroed here); full_sweep_norm_sync completes it.  With
+// first_done the first pre-smoothing sweep has already run (by
+// full_sweep_norm_sync, its result in the spare buffer).
+int vcycle_full(np_solver* s, int l, bool first_done)
+{
+    const np_config& c = s->cfg;
+    const int d = c.dim;
+    hipStream_t st = s->stream;
+    MGView<double> v = mg_view<double>(s, l, s->mg_u, s->mg_f);
+    const double h = v.h[0];
+    int it = 0;
+    if (first_done) {
+        std::swap(s->phi[l], s->phi_alt);
+        std::swap(s->phi_cap[l], s->alt_cap);
+        it = 1;
+    }
+    if (it < c.n_pre) {
+        prof_begin(s, NP_KCLASS_FULL);
+        const int n = c.n_pre - it;
+        for (; it < c.n_pre; it++) full_sweep(s, l, 0);
+        prof_end(s, n);
+    }
+    const bool seed1 = tail_level(s, l, sizeof(double)) != 1;
+    prof_begin(s, NP_KCLASS_RESTRICT);
+    launch_resid_restrict<double, double>(d, st, v.g[0], s->phi[l], s->f[l], 1.0 / (h * h), 1.0, v.g[1], v.f[1],
+                                          v.u[1], 0, Rule3{}, seed1 ? v.h[1] * v.h[1] : 0.0);
+    prof_end(s);
+    prof_begin(s, NP_KCLASS_COARSE);
+    int rc = run_coarse(s, l, v, s->coarse_exec);
+    prof_end(s);
+    if (rc) return rc;
+    // the post-smoothing sweeps read only the black values: the prolongation
+    // corrects the black points
+    prof_begin(s, NP_KCLASS_PROLONG);
+    launch_prolong_add<double, double>(d, st, v.g[1], v.u[1], v.g[0], s->phi[l], 1, rule_of(s, l, 1));
+    prof_end(s);
+    launch_set_u64(st, s->d_bits, 1, 0ULL);
+    prof_begin(s, NP_KCLASS_FULL);
+    for (it = 0; it < c.n_post; it++) full_sweep(s, l, it == c.n_post - 1 ? kSweepResOut : 0);
+    prof_end(s, c.n_post);
+    return NP_OK;
+}
+
+// Completes the residual norm of the potential after vcycle_full: the next
+// cycle's first pre-smoothing sweep, into the spare buffer (the potential is
+// not replaced), also takes the norm over the red points (host-synchronous).
+int full_sweep_norm_sync(np_solver* s, int l, double* out)
+{
+    const double h = level_dx(&s->cfg, l);
+    prof_begin(s, NP_KCLASS_FULL_RES);
+    launch_full_sweep<double>(s->stream, s->lg[l], s->phi[l], s->phi_alt, s->f[l], h * h, 1.0 / (h * h), kSweepResIn,
+                              s->fs_rev, s->d_bits);
+    prof_end(s);
+    s->fs_rev ^= 1;
+    HIPCHK(s, hipGetLastError());
+    HIPCHK(s, hipMemcpyAsync(s->h_bits, s->d_bits, sizeof(unsigned long long), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    *out = bits_to_double(s->h_bits[0]);
+    return NP_OK;
 }
 
 // Inner V-cycle of the defect correction, on the scaled level-0 problem
@@ -1257,6 +1342,14 @@ int nested_poisson_create(const np_config* cfg, void* hip_stream, np_solver** ou
         s->alt_cap = best * sizeof(double);
         if (rc == NP_OK) rc = alloc_dev(s, (void**)&s->phi_alt, s->alt_cap);
     }
+    if (rc == NP_OK && !dc && d == 3 && cfg->sweep == NP_SWEEP_FULL && cfg->n_pre >= 1 && cfg->n_post >= 1) {
+        // the second potential buffer of the full sweeps
+        size_t best = 0;
+        for (int l = 0; l < cfg->nlevels; l++)
+            if (2 * s->lg[l].cs > best) best = 2 * s->lg[l].cs;
+        s->alt_cap = best * sizeof(double);
+        rc = alloc_dev(s, (void**)&s->phi_alt, s->alt_cap);
+    }
     if (rc == NP_OK && cfg->guess == NP_GUESS_LEARNED) {
         size_t vox = 0;
         for (int l = 1; l < cfg->nlevels; l++) {
@@ -1437,6 +1530,10 @@ int nested_poisson_solve(np_solver* s, const double* const* rho, const double* p
             // buffer: give it this level's fixed ghost layer
             launch_copy_ghosts(c.dim, s->stream, s->lg[l], s->phi[l], s->phi_alt);
         }
+        // full sweeps write the active points of the spare buffer: the same
+        const bool fs = !dc && full_sweeps(s, l);
+        bool first_done = false;  // the next cycle's first pre-smoothing sweep has run
+        if (fs) launch_copy_ghosts(c.dim, s->stream, s->lg[l], s->phi[l], s->phi_alt);
         for (;;) {
             if (!std::isfinite(r)) { lvl = NP_ENONFINITE; break; }
             if (pinned) {
@@ -1470,6 +1567,14 @@ int nested_poisson_solve(np_solver* s, const double* const* rho, const double* p
                     const double m = std::pow(r / rprev, 1.0 / k);
                     rho = m < 0.02 ? 0.02 : (m > 0.95 ? 0.95 : m);
                 }
+            } else if (fs) {
+                rc = vcycle_full(s, l, first_done);
+                if (rc) return rc;
+                HIPCHK(s, hipGetLastError());
+                q++;
+                rc = full_sweep_norm_sync(s, l, &r);
+                if (rc) return rc;
+                first_done = true;
             } else {
                 rc = vcycle(s, l);
                 if (rc) return rc;
@@ -1487,7 +1592,7 @@ int nested_poisson_solve(np_solver* s, const double* const* rho, const double* p
                 if (Fdelta < c.tol) break;
             }
         }
-        if (dc) {
+        if (dc || fs) {
             rc = dc_settle(s, l);
             if (rc) return rc;
         }
