@@ -29,7 +29,7 @@ PEAK_HBM_GBS = 8000.0   # MI355X HBM3E peak
 # committed under profiles/ (FETCH_SIZE and WRITE_SIZE scaled by a plain copy
 # kernel), recorded together with the SHA-256 of the kernel source it was taken
 # on; the figure is reported only while that source is unchanged.
-PMC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_level0_half_sweep_two_plummer_5x512.txt")
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "level0_kernels_two_plummer_5x512.txt")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2001_02327_amd", "csrc", "np_kernels.hip")
 
 
@@ -369,6 +369,15 @@ def run_variant(name, wl, rho, phi_outer, Fs, steps, warmup, inner_cycles, stop_
         if uniform:
             d.update(bytes_per_launch=e * elem * npts, GBps=round(e * elem * npts / (avg * 1e-3) / 1e9, 1))
         sweeps[cls] = d
+    # the defect-correction outer pass (mixed precision): reads phi (8), the
+    # correction e and f (8), writes the updated phi (8) and the next defect r,
+    # e and r in the storage type: 24 + 2 e bytes per point
+    dc_pass = None
+    cnt, ms_c = prof["dc"]
+    if cnt and uniform and elem < 8:
+        b = (24 + 2 * elem) * npts
+        dc_pass = dict(launches=cnt, avg_launch_us=round(ms_c / cnt * 1e3, 2), ms_per_step=round(ms_c / steps, 3),
+                       bytes_per_launch=b, GBps=round(b / (ms_c / cnt * 1e-3) / 1e9, 1))
     # the roofline kernel: the smoothing class with the most device time
     main_cls = max((c for c in ("smooth", "full") if c in sweeps), key=lambda c: sweeps[c]["ms_per_step"])
     smoother = dict(sweeps[main_cls], kind=main_cls, elem_bytes=elem, classes=sweeps)
@@ -393,6 +402,7 @@ def run_variant(name, wl, rho, phi_outer, Fs, steps, warmup, inner_cycles, stop_
         deviation_from_fp64=dev,
         edge_force_error_per_level=edge,
         smoother=smoother,
+        dc_pass=dc_pass,
         kernels={k: dict(launches=c, ms_per_step=round(m / steps, 3), avg_us=(round(1e3 * m / c, 2) if c else None))
                  for k, (c, m) in prof.items()},
     )
@@ -536,6 +546,10 @@ def main():
             "bytes_per_launch": sm["bytes_per_launch"],
             "avg_launch_us": sm["avg_launch_us"],
         },
+        # the largest kernel of a mixed-precision headline besides the smoother
+        "dc_pass_roofline": (None if not b.get("dc_pass") else
+                             dict(b["dc_pass"], peak=PEAK_HBM_GBS, unit="GB/s",
+                                  frac=round(b["dc_pass"]["GBps"] / PEAK_HBM_GBS, 4))),
         "cpu_baseline": cpu,
         "linf_force_error": b["linf_force_error"],
         "deviation_from_fp64": b["deviation_from_fp64"],

@@ -237,7 +237,8 @@ int nested_poisson_potential(np_solver* s, int level, double* phi_padded);
                               * neighbours from the defect (and stores them with one pre-smoothing sweep) */
 #define NP_KCLASS_FULL 10    /* full red-black sweeps of multigrid level 0 (NP_SWEEP_FULL) */
 #define NP_KCLASS_FULL_RES 11 /* the full sweep that also completes the stop test's residual norm */
-#define NP_NKCLASS 12
+#define NP_KCLASS_DC_SCALE 12 /* first scaled defect of a level from its starting residual */
+#define NP_NKCLASS 16
 typedef struct np_profile {
     long count[NP_NKCLASS]; /* launches (intervals) recorded */
     double ms[NP_NKCLASS];  /* summed device time */

@@ -78,9 +78,9 @@ class NpStats(ctypes.Structure):
     ]
 
 
-NP_NKCLASS = 12
+NP_NKCLASS = 16
 KCLASSES = ["smooth", "restrict", "prolong", "coarse", "norm", "fill", "forces", "dc", "guess", "seeded", "full",
-            "full_res"]
+            "full_res", "dc_scale"]
 NP_NET_PARAMS = 8241
 NP_NET_MSE_NOALLOC_MAX = 1 << 28
 NP_GUESS_BLOB_MAGIC = 0x5747504E

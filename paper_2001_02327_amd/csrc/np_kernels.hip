@@ -1036,7 +1036,7 @@ __global__ void __launch_bounds__(kBlock) k_smooth_fine(T* __restrict__ u, const
 // planes per thread on multigrid level 0 and on the coarse levels (4/4, 8/8,
 // 8/4, 4/2, 4/1 measured at 514^3: 4/4 best)
 constexpr int kZChunk0 = 4;
-constexpr bool kDppExtra = true;  // FP16 pair sweep: extra x-neighbour from the adjacent lane
+constexpr bool kDppExtra = true;  // pair sweep: extra x-neighbour from the adjacent lane
 constexpr int kZChunk1 = 4;
 
 // TAG 0: level 0 (ghost layer in memory); TAG 1: coarse levels, whose ghost
@@ -1320,8 +1320,8 @@ __global__ void __launch_bounds__(kSmoothPairBlock) k_smooth_zmarch3_pair(T* __r
         // update, so that each wave keeps ~20 loads in flight
         Pair<T> ab[kZChunk], ym[kZChunk], yp[kZChunk], fv[kZChunk];
         T ex[kZChunk];
-        if constexpr (sizeof(T) == 2 && kDppExtra) {
-            // FP16: the extra x-neighbour of plane pk is a half of the neighbouring
+        if constexpr (sizeof(T) <= 4 && kDppExtra) {
+            // the extra x-neighbour of plane pk is an element of the neighbouring
             // lane's pair in the same plane (flat numbering: lane - 1 holds slots
             // h0 - 2, h0 - 1 and lane + 1 slots h0 + 2, h0 + 3), moved across lanes
             // with a DPP wave shift; only the wave's edge lanes, whose neighbour is
@@ -1340,9 +1340,14 @@ __global__ void __launch_bounds__(kSmoothPairBlock) k_smooth_zmarch3_pair(T* __r
 #pragma unroll
             for (int q = 0; q < kZChunk; q++) {
                 const int par = (colour + pj + k0 + q + 3) & 1;
-                const unsigned w = __builtin_bit_cast(uint32_t, cur);
-                const uint16_t xv = par ? (uint16_t)(dpp_next(w) & 0xffffu) : (uint16_t)(dpp_prev(w) >> 16);
-                const T e = (par ? lane == 63 : lane == 0) ? ex[q] : __builtin_bit_cast(T, xv);
+                T xv;
+                if constexpr (sizeof(T) == 2) {
+                    const unsigned w = __builtin_bit_cast(uint32_t, cur);
+                    xv = __builtin_bit_cast(T, par ? (uint16_t)(dpp_next(w) & 0xffffu) : (uint16_t)(dpp_prev(w) >> 16));
+                } else {
+                    xv = par ? dpp_next(cur.a) : dpp_prev(cur.b);
+                }
+                const T e = (par ? lane == 63 : lane == 0) ? ex[q] : xv;
                 step(k0 + q, ab[q], ym[q], yp[q], fv[q], e);
             }
             return;

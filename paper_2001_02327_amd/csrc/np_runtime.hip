@@ -849,7 +849,7 @@ int dc_scale_defect(np_solver* s, int l, double rscale)
 {
     const np_config& c = s->cfg;
     void* e_out = dc_seed_black(s, l) ? nullptr : s->e_lo;
-    prof_begin(s, NP_KCLASS_DC);
+    prof_begin(s, NP_KCLASS_DC_SCALE);
     if (c.precision == NP_PREC_FP16S_DC)
         launch_dc_scale<__half>(c.dim, s->stream, s->lg[l], s->r32, rscale, (__half*)s->r_lo, (__half*)e_out,
                                 c.n_pre > 0);
