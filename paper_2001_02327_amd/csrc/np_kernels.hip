@@ -615,11 +615,15 @@ __global__ void __launch_bounds__(kBlock) k_forces(SGrid g, double m12dx, const 
 // (planes k-2 .. k+2) stays in registers for the z-derivative and serves the
 // y-derivatives of the neighbouring columns, so only two rows on each side are
 // loaded for y; every load of the chunk is issued before the first difference.
-// Same arithmetic as k_forces.
+// The x-neighbours i-2 .. i+2 are the adjacent lanes' column values, moved by DPP
+// shifts: a wave owns the kForceOwn columns between its two first and two last
+// lanes, which only supply values; at the ends of a row (the buffer columns) the
+// lanes load them.  Same arithmetic as k_forces.
 // planes and rows per thread: (8, 4) measured best of (4, 1), (4, 2), (2, 4), (4, 4),
-// (4, 8), (2, 8) at 512^3 (1.61 -> 1.28 ms)
+// (4, 8), (2, 8) at 512^3 (1.61 -> 1.28 ms, with every x-neighbour loaded)
 constexpr int kForceChunk = 8;
 constexpr int kForceRows = 4;
+constexpr int kForceOwn = 60;  // columns a wave owns (lanes 2..61)
 
 __global__ void __launch_bounds__(kForceBlock) k_forces3_zm(SGrid g, double m12dx, const double* __restrict__ phi,
                                                        double* __restrict__ fx, double* __restrict__ fy,
@@ -629,19 +633,23 @@ __global__ void __launch_bounds__(kForceBlock) k_forces3_zm(SGrid g, double m12d
     constexpr int KC = kForceChunk;
     const int nx = g.nx - 4, ny = g.ny - 4, nz = g.nz - 4;
     const int nrb = (ny + R - 1) / R;
+    const long total = (long)nx * nrb;
     const int lb = (int)xcd_block();
     const int zc = lb / pblocks;
-    const int t = (lb - zc * pblocks) * kForceBlock + (int)threadIdx.x;
-    if (t >= (long)nx * nrb) return;
-    const int i = (int)(t % nx), j0 = R * (int)(t / nx);
+    const long wave = (long)(lb - zc * pblocks) * (kForceBlock / 64) + (threadIdx.x >> 6);
+    const int lane = (int)(threadIdx.x & 63);
+    const long t = wave * kForceOwn + lane - 2;
+    const bool owner = lane >= 2 && lane < 2 + kForceOwn && t >= 0 && t < total;
+    const long tc = t < 0 ? 0 : (t >= total ? total - 1 : t);
+    const int i = (int)(tc % nx), j0 = R * (int)(tc / nx);
     const int k0 = zc * KC;
     const int nk = min(KC, nz - k0);
     const int pi = i + 2;
+    const bool xload = i < 2 || i >= nx - 2;  // an x-neighbour lies in the buffer columns
     // padded rows j0 + 2 - 2 .. j0 + 2 + R + 1: the thread's rows and two on each side
     // (rows past the array are clamped; they are never differenced)
     auto prow = [&](int q) { return min(j0 + q, ny + 3); };  // q = 0 .. R + 3
     double col[R][KC + 4];  // padded planes k0 .. k0 + nk + 3 of each of the thread's rows
-    double xm1[R][KC], xp1[R][KC], xm2[R][KC], xp2[R][KC];
     double yh[4][KC];       // rows j0, j0 + 1 (below) and j0 + R + 2, j0 + R + 3 (above), padded
 #pragma unroll
     for (int r = 0; r < R; r++)
@@ -652,14 +660,6 @@ __global__ void __launch_bounds__(kForceBlock) k_forces3_zm(SGrid g, double m12d
     for (int q = 0; q < KC; q++) {
         if (q < nk) {
             const int pk = k0 + q + 2;
-#pragma unroll
-            for (int r = 0; r < R; r++) {
-                const int pj = prow(r + 2);
-                xm1[r][q] = at<3>(phi, g, pi - 1, pj, pk);
-                xp1[r][q] = at<3>(phi, g, pi + 1, pj, pk);
-                xm2[r][q] = at<3>(phi, g, pi - 2, pj, pk);
-                xp2[r][q] = at<3>(phi, g, pi + 2, pj, pk);
-            }
             yh[0][q] = at<3>(phi, g, pi, prow(0), pk);
             yh[1][q] = at<3>(phi, g, pi, prow(1), pk);
             yh[2][q] = at<3>(phi, g, pi, prow(R + 2), pk);
@@ -677,10 +677,20 @@ __global__ void __launch_bounds__(kForceBlock) k_forces3_zm(SGrid g, double m12d
         if (q < nk) {
 #pragma unroll
             for (int r = 0; r < R; r++) {
-                if (j0 + r >= ny) continue;
+                const double c = col[r][q + 2];
+                double xm1 = dpp_prev(c), xp1 = dpp_next(c);
+                double xm2 = dpp_prev(xm1), xp2 = dpp_next(xp1);
+                if (xload) {
+                    const int pj = prow(r + 2), pk = k0 + q + 2;
+                    xm1 = at<3>(phi, g, pi - 1, pj, pk);
+                    xp1 = at<3>(phi, g, pi + 1, pj, pk);
+                    xm2 = at<3>(phi, g, pi - 2, pj, pk);
+                    xp2 = at<3>(phi, g, pi + 2, pj, pk);
+                }
+                if (!owner || j0 + r >= ny) continue;
                 const long o = ((long)(k0 + q) * ny + (j0 + r)) * nx + i;
                 const int w = r + 2;
-                store_nt(fx + o, (8.0 * (xp1[r][q] - xm1[r][q]) - (xp2[r][q] - xm2[r][q])) * m12dx);
+                store_nt(fx + o, (8.0 * (xp1 - xm1) - (xp2 - xm2)) * m12dx);
                 store_nt(fy + o, (8.0 * (yv(w + 1, q) - yv(w - 1, q)) - (yv(w + 2, q) - yv(w - 2, q))) * m12dx);
                 store_nt(fz + o, (8.0 * (col[r][q + 3] - col[r][q + 1]) - (col[r][q + 4] - col[r][q])) * m12dx);
             }
@@ -3063,7 +3073,8 @@ void launch_forces(int dim, hipStream_t st, SGrid g, double dx, const double* ph
     double m12dx = -1.0 / (12.0 * dx);
     const long nx = g.nx - 4, ny = g.ny - 4, nz = g.nz - 4;
     if (dim == 3) {
-        const int pblocks = ceil_div(nx * ((ny + kForceRows - 1) / kForceRows), kForceBlock);
+        const long waves = ceil_div(nx * ((ny + kForceRows - 1) / kForceRows), kForceOwn);
+        const int pblocks = ceil_div(waves, kForceBlock / 64);
         hipLaunchKernelGGL(k_forces3_zm, dim3(pblocks * ceil_div(nz, kForceChunk)), dim3(kForceBlock), 0, st, g,
                            m12dx, phi, fx, fy, fz, pblocks);
         return;
