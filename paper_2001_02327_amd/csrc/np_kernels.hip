@@ -1048,6 +1048,8 @@ __global__ void __launch_bounds__(kBlock) k_smooth_fine(T* __restrict__ u, const
 constexpr int kZChunk0 = 4;
 constexpr bool kDppExtra = true;  // pair sweep: extra x-neighbour from the adjacent lane
 constexpr int kZChunk1 = 4;
+constexpr int kZChunkSmall = 1;  // coarse levels of at most kSmallPlanes planes: more threads, shorter chains
+constexpr int kSmallPlanes = 64;
 
 // TAG 0: level 0 (ghost layer in memory); TAG 1: coarse levels, whose ghost
 // values come from the rule (GRule) where a boundary point reads them.
@@ -1058,8 +1060,8 @@ __global__ void __launch_bounds__(kBlock) k_smooth_zmarch3(T* __restrict__ u, co
                                                            GRule<typename Compute<T>::type> gr)
 {
     using C = typename Compute<T>::type;
-    constexpr bool RULE = TAG == 1;
-    constexpr int kZChunk = TAG == 0 ? kZChunk0 : kZChunk1;
+    constexpr bool RULE = TAG >= 1;
+    constexpr int kZChunk = TAG == 0 ? kZChunk0 : (TAG == 1 ? kZChunk1 : kZChunkSmall);
     constexpr int kZGroup = kZChunk;  // planes whose loads are issued together
     if (batch_idle(g)) return;
     u = batch_at(u, g);
@@ -3158,9 +3160,13 @@ void launch_half_sweep(int dim, hipStream_t st, SGrid g, T* u, const T* f, int c
         // coarse-level one (TAG 1) so that profiles separate them
         long mz = g.nz - 2;
         int pblocks = ceil_div((long)g.ps, kBlock);
-        int chunks = ceil_div(mz, fine ? kZChunk0 : kZChunk1);
+        const bool small = !fine && mz <= kSmallPlanes;
+        int chunks = ceil_div(mz, fine ? kZChunk0 : (small ? kZChunkSmall : kZChunk1));
         if (fine)
             hipLaunchKernelGGL((k_smooth_zmarch3<T, 0>), dim3(pblocks * chunks, g.nb), dim3(kBlock), 0, st, u, f, g, colour,
+                               (C)h2, inv2d, pblocks, gr);
+        else if (small)
+            hipLaunchKernelGGL((k_smooth_zmarch3<T, 2>), dim3(pblocks * chunks, g.nb), dim3(kBlock), 0, st, u, f, g, colour,
                                (C)h2, inv2d, pblocks, gr);
         else
             hipLaunchKernelGGL((k_smooth_zmarch3<T, 1>), dim3(pblocks * chunks, g.nb), dim3(kBlock), 0, st, u, f, g, colour,
@@ -3286,7 +3292,7 @@ void launch_prolong_add(int dim, hipStream_t st, SGrid gc, const TC* ec, SGrid g
         const long Mx = (gf.nx - 1) / 2, My = (gf.ny - 1) / 2, Mz = (gf.nz - 1) / 2;
         // 8 coarse planes per thread on large grids, 2 on small ones (there the
         // column count alone does not fill the chip)
-        const int kch = Mx * My >= 200 * 200 ? 8 : 2;
+        const int kch = Mx * My >= 200 * 200 ? 8 : (Mz <= kSmallPlanes / 2 ? 1 : 2);
         const int pblocks = ceil_div(Mx * My, kBlock);
         const int chunks = ceil_div(Mz, kch);
         hipLaunchKernelGGL((k_prolong3_zm<TC, TF>), dim3(pblocks * chunks, gf.nb), dim3(kBlock), 0, st, ec, gc, u, gf,
