@@ -109,6 +109,7 @@ def _bad(**kw):
     dict(off=(2, 2, 9)), dict(dx0=0.0), dict(tol=-1.0), dict(max_cycles=0), dict(max_cycles=100000),
     dict(n_pre=-1), dict(stop_rule=7), dict(inner_cycles=-1), dict(inner_cycles=9), dict(buffer=2),
     dict(buffer=1, precision=1), dict(buffer=1, precision=2), dict(buffer=1, guess=1), dict(buffer=1, stop_rule=1),
+    dict(sweep=2), dict(sweep=-1), dict(batch=2),
 ], ids=lambda k: ",".join("%s=%s" % kv for kv in k.items()))
 def test_invalid_geometry_rejected_before_any_device_call(kw):
     cfg = _bad(**kw)
@@ -275,3 +276,18 @@ def test_guess_weight_blob_on_the_host():
     buf = ctypes.create_string_buffer(_lib.NP_GUESS_BLOB_BYTES)
     assert L.nested_poisson_pack_guess_weights(short.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), 100, buf,
                                                _lib.NP_GUESS_BLOB_BYTES) == _lib.NP_EINVAL
+
+
+def test_profile_classes_match_the_header():
+    """The ctypes mirror of np_profile and the class names follow the header's
+    NP_KCLASS_* numbering (no device needed)."""
+    import re
+    hdr = open(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include",
+                            "nested_poisson.h")).read()
+    classes = {int(v): k for k, v in re.findall(r"#define NP_KCLASS_(\w+) (\d+)", hdr)}
+    n = int(re.search(r"#define NP_NKCLASS (\d+)", hdr).group(1))
+    assert n == _lib.NP_NKCLASS and len(classes) <= n
+    assert [classes[i].lower() for i in range(len(classes))] == _lib.KCLASSES
+    assert ctypes.sizeof(_lib.NpProfile) == n * (ctypes.sizeof(ctypes.c_long) + ctypes.sizeof(ctypes.c_double))
+    sweeps = dict(re.findall(r"#define NP_SWEEP_(\w+) (\d+)", hdr))
+    assert {k.lower(): int(v) for k, v in sweeps.items()} == _lib.SWEEPS
