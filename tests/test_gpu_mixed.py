@@ -41,6 +41,23 @@ def _solve(wl, **kw):
     return phi, F, st
 
 
+def _oracle_phi(wl, **kw):
+    """The oracle's potentials converged to 1e-13 (residual rule unless kw says
+    otherwise), on the CPU, from the same inputs."""
+    rho, po = W.make_inputs(wl.geom, wl.prob)
+    kw.setdefault("tol", 1e-13)
+    kw.setdefault("max_cycles", 120)
+    ref = core.solve(wl.geom, [r.numpy() for r in rho], po.numpy(), **kw)
+    assert ref["status"] == 0, ref["status_name"]
+    return ref["phi"]
+
+
+def _assert_close_to_oracle(wl, phi, ref, bar=1e-8):
+    for l in range(wl.geom.nlevels):
+        err = np.abs(phi[l] - ref[l]).max() / np.abs(ref[l]).max()
+        assert err <= bar, ("oracle", l, err)
+
+
 def _linf_force_error(wl, F):
     from oracle import norms
     errs = []
@@ -97,6 +114,7 @@ def test_dc_inner_cycles_and_stress(precision):
     wl = W.c3_plummer_offset(64)
     phi64, F64, st64 = _solve(wl)
     phi, F, st = _solve(wl, precision=precision, inner_cycles=2)
+    _assert_close_to_oracle(wl, phi, _oracle_phi(wl))
     for l in range(wl.geom.nlevels):
         err = np.abs(phi[l] - phi64[l]).max() / np.abs(phi64[l]).max()
         assert err <= 1e-8, (l, err)
@@ -156,6 +174,8 @@ def test_dc_paper2d_largest_size(precision):
     wl = W.paper2d(1024)
     phi64, _, _ = _solve(wl, stop_rule="force_delta")
     phi, _, _ = _solve(wl, precision=precision, stop_rule="force_delta")
+    # and the oracle's own solve under the same rule
+    _assert_close_to_oracle(wl, phi, _oracle_phi(wl, stop_rule=1, tol=1e-10))
     for l in range(wl.geom.nlevels):
         err = np.abs(phi[l] - phi64[l]).max() / np.abs(phi64[l]).max()
         assert err <= 1e-8, (l, err)
@@ -212,11 +232,14 @@ def test_dc_ragged_levels_and_schedules(make, precision, n_pre, inner):
 def test_dc_adaptive_inner_cycles(wl, precision):
     """Adaptive inner cycles: each step runs as many V-cycles (1..4, 1..3 with
     FP16 storage) as the contraction measured so far says the stop test needs.
-    The answer is the FP64 solve's, the V-cycle count stays within two of it
+    The answer is the oracle's converged solution and the FP64 solve's, the
+    V-cycle count stays within two of it
     (three with FP16 storage, whose rounding slows the last cycles), and the outer
     steps (each an FP64 pass over the level) are fewer than the V-cycles."""
     phi64, F64, st64 = _solve(wl)
     phi, F, st = _solve(wl, precision=precision, inner_cycles="adaptive")
+    # (1e-12: the finest level of the 3 x 32^3 multi-Plummer case cannot reach 1e-13 in FP64)
+    _assert_close_to_oracle(wl, phi, _oracle_phi(wl, tol=1e-12))
     for l in range(wl.geom.nlevels):
         err = np.abs(phi[l] - phi64[l]).max() / np.abs(phi64[l]).max()
         assert err <= 1e-8, (l, err)
