@@ -1579,6 +1579,217 @@ __global__ void __launch_bounds__(kFsBlock) k_full_sweep3(const T* __restrict__ 
     if (MODE) block_max_to(best, maxbits);
 }
 
+// Paired form of k_full_sweep3 (even row length hx): a lane owns the compact
+// points h0 = 2 hp and h0 + 1 of its rows, moves each pair with one 16-byte
+// access, and takes the compact slot past its pair (h0 - 1 or h0 + 2) from the
+// adjacent lane's pair; a wave owns the kFsOwn pairs between its first and
+// last lane.  Same arithmetic per point, in the same order, as the single form
+// and the paired half sweep.
+constexpr int kFsPairRows = 5;    // rows per thread (1..8 measured at 514^3: 5 fastest)
+constexpr int kFsPairChunk = 16;  // planes per thread
+
+template <typename T, int G, int KCH, int MODE>
+__global__ void __launch_bounds__(kFsBlock) k_full_sweep3_pair(const T* __restrict__ P, T* __restrict__ Q,
+                                                               const T* __restrict__ f, SGrid g, double h2,
+                                                               double inv2d, double inv_h2, int nrg, int wblocks,
+                                                               int rev, unsigned long long* maxbits)
+{
+    using C = typename Compute<T>::type;
+    using PT = Pair<T>;
+    constexpr int R = G + 2;
+    const C h2c = (C)h2, inv2dc = (C)inv2d;
+    const int mx = g.nx - 2, my = g.ny - 2, mz = g.nz - 2;
+    const int lb = zmarch_block(rev);
+    const int zc = lb / wblocks;
+    const long wave = (long)(lb - zc * wblocks) * (kFsBlock / 64) + (threadIdx.x >> 6);
+    const int lane = (int)(threadIdx.x & 63);
+    const int hp2 = g.hx / 2;  // pairs per row
+    const long total = (long)nrg * hp2;
+    const long t = wave * kFsOwn + lane - 1;
+    const bool owner = lane >= 1 && lane <= kFsOwn && t >= 0 && t < total;
+    const long tc = t < 0 ? 0 : (t >= total ? total - 1 : t);
+    const int rg = (int)(tc / hp2);
+    const int h0 = 2 * (int)(tc - (long)rg * hp2);
+    const int j0 = 1 + G * rg;
+    const int k0 = 1 + zc * KCH;
+    const int k1 = min(k0 + KCH - 1, mz);
+    const size_t cs = g.cs, ps = g.ps;
+    auto rowc = [&](int r) { return r < 0 ? 0 : (r > my + 1 ? my + 1 : r); };
+    auto planec = [&](int k) { return (size_t)(k < 0 ? 0 : (k > mz + 1 ? mz + 1 : k)) * ps; };
+    unsigned ro[R];
+#pragma unroll
+    for (int i = 0; i < R; i++) ro[i] = (unsigned)(rowc(j0 - 1 + i) * g.hx + h0);
+    const unsigned ry0 = (unsigned)(rowc(j0 - 2) * g.hx + h0), ry1 = (unsigned)(rowc(j0 + G + 1) * g.hx + h0);
+    const T* __restrict__ Pr = P;
+    const T* __restrict__ Pb = P + cs;
+    const T* __restrict__ fr = f;
+    const T* __restrict__ fb = f + cs;
+    T* __restrict__ Qr = Q;
+    T* __restrict__ Qb = Q + cs;
+    auto ldp = [](const T* p, unsigned o) { return *(const PT*)(p + o); };
+    PT b0[R], b1[R];  // P's black pairs of the red rows at planes k - 1 and k
+    PT rn[R];         // new red pairs at plane k - 1
+    PT rp[G];         // new red pairs of the own rows at plane k - 2
+    {
+        const T* pa = Pb + planec(k0 - 2);
+        const T* pb = Pb + planec(k0 - 1);
+#pragma unroll
+        for (int i = 0; i < R; i++) {
+            b0[i] = ldp(pa, ro[i]);
+            b1[i] = ldp(pb, ro[i]);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < R; i++) rn[i] = PT{(T)0, (T)0};
+#pragma unroll
+    for (int i = 0; i < G; i++) rp[i] = PT{(T)0, (T)0};
+    unsigned long long best = 0;
+    auto take = [&](unsigned long long b) { best = b > best ? b : best; };
+    for (int k = k0 - 1; k <= k1 + 1; k++) {
+        const T* __restrict__ pbk = Pb + planec(k);
+        const T* __restrict__ pba = Pb + planec(k + 1);
+        const T* __restrict__ prk = Pr + planec(k);
+        const T* __restrict__ frk = fr + planec(k);
+        const T* __restrict__ fbk = fb + planec(k - 1);
+        const bool kact = k >= 1 && k <= mz;
+        const bool red_own = k >= k0 && k <= k1;
+        const bool bstep = k - 1 >= k0;
+        // every load of the step first
+        PT ba[R], fv[R], gh[R], fbv[G], prv[G];
+        T ex[R];
+        const PT y0v = ldp(pbk, ry0), y1v = ldp(pbk, ry1);
+#pragma unroll
+        for (int i = 0; i < R; i++) {
+            const int r = j0 - 1 + i;
+            const int par = (r + k + 3) & 1;  // red points pi = 2 h0 + par, + 2
+            const int pi0 = 2 * h0 + par;
+            ba[i] = ldp(pba, ro[i]);
+            fv[i] = ldp(frk, ro[i]);
+            const bool ract = kact && r >= 1 && r <= my;
+            // the slot past the pair: the adjacent lane's, loaded by the wave's edge
+            // lanes only where the point reading it is active (so it lies in the row)
+            ex[i] = (T)0;
+            if (par ? (lane == 63 && ract && pi0 + 2 <= mx) : (lane == 0 && ract && pi0 >= 1))
+                ex[i] = pbk[(int)ro[i] + (par ? 2 : -1)];
+            gh[i] = PT{(T)0, (T)0};
+            if (!(ract && pi0 >= 1 && pi0 + 2 <= mx)) gh[i] = ldp(prk, ro[i]);
+        }
+#pragma unroll
+        for (int i = 0; i < G; i++) {
+            fbv[i] = bstep ? ldp(fbk, ro[i + 1]) : PT{(T)0, (T)0};
+            prv[i] = ((MODE & kFsResIn) && red_own) ? ldp(prk, ro[i + 1]) : PT{(T)0, (T)0};
+        }
+        // red points of plane k
+        PT rk[R];
+#pragma unroll
+        for (int i = 0; i < R; i++) {
+            const int r = j0 - 1 + i;
+            const int par = (r + k + 3) & 1;
+            const int pi0 = 2 * h0 + par;
+            const C nx = (C)dpp_next(b1[i].a), pv = (C)dpp_prev(b1[i].b);
+            const C e = (par ? lane == 63 : lane == 0) ? (C)ex[i] : (par ? nx : pv);
+            C xm0, xp0, xm1, xp1;
+            if (par) {
+                xm0 = (C)b1[i].a;
+                xp0 = (C)b1[i].b;
+                xm1 = (C)b1[i].b;
+                xp1 = e;
+            } else {
+                xm0 = e;
+                xp0 = (C)b1[i].a;
+                xm1 = (C)b1[i].a;
+                xp1 = (C)b1[i].b;
+            }
+            const PT y0 = i == 0 ? y0v : b1[i - 1];
+            const PT y1 = i == R - 1 ? y1v : b1[i + 1];
+            C s0 = xm0 + xp0;
+            s0 = s0 + (C)y0.a;
+            s0 = s0 + (C)y1.a;
+            s0 = s0 + (C)b0[i].a;
+            s0 = s0 + (C)ba[i].a;
+            C s1 = xm1 + xp1;
+            s1 = s1 + (C)y0.b;
+            s1 = s1 + (C)y1.b;
+            s1 = s1 + (C)b0[i].b;
+            s1 = s1 + (C)ba[i].b;
+            const bool ract = kact && r >= 1 && r <= my;
+            const bool a0 = ract && pi0 >= 1 && pi0 <= mx, a1 = ract && pi0 + 2 <= mx;
+            const T v0 = (T)((s0 - h2c * (C)fv[i].a) * inv2dc), v1 = (T)((s1 - h2c * (C)fv[i].b) * inv2dc);
+            rk[i].a = a0 ? v0 : gh[i].a;
+            rk[i].b = a1 ? v1 : gh[i].b;
+            if (i >= 1 && i <= G && red_own && owner) {
+                T* q = Qr + planec(k) + ro[i];
+                if (a0 && a1)
+                    *(PT*)q = PT{v0, v1};
+                else {
+                    if (a0) q[0] = v0;
+                    if (a1) q[1] = v1;
+                }
+                if (MODE & kFsResIn) {
+                    if (a0) take(abs_bits(resid((double)fv[i].a, (double)s0, (double)prv[i - 1].a, 6.0, inv_h2)));
+                    if (a1) take(abs_bits(resid((double)fv[i].b, (double)s1, (double)prv[i - 1].b, 6.0, inv_h2)));
+                }
+            }
+        }
+        // black points of plane k - 1
+        if (bstep) {
+#pragma unroll
+            for (int i = 0; i < G; i++) {
+                const int r = j0 + i;
+                const int kb = k - 1;
+                const int par = (r + kb + 4) & 1;
+                const int pi0 = 2 * h0 + par;
+                const PT cur = rn[i + 1];
+                const C nx = (C)dpp_next(cur.a), pv = (C)dpp_prev(cur.b);
+                C xm0, xp0, xm1, xp1;
+                if (par) {
+                    xm0 = (C)cur.a;
+                    xp0 = (C)cur.b;
+                    xm1 = (C)cur.b;
+                    xp1 = nx;
+                } else {
+                    xm0 = pv;
+                    xp0 = (C)cur.a;
+                    xm1 = (C)cur.a;
+                    xp1 = (C)cur.b;
+                }
+                C s0 = xm0 + xp0;
+                s0 = s0 + (C)rn[i].a;
+                s0 = s0 + (C)rn[i + 2].a;
+                s0 = s0 + (C)rp[i].a;
+                s0 = s0 + (C)rk[i + 1].a;
+                C s1 = xm1 + xp1;
+                s1 = s1 + (C)rn[i].b;
+                s1 = s1 + (C)rn[i + 2].b;
+                s1 = s1 + (C)rp[i].b;
+                s1 = s1 + (C)rk[i + 1].b;
+                const T v0 = (T)((s0 - h2c * (C)fbv[i].a) * inv2dc), v1 = (T)((s1 - h2c * (C)fbv[i].b) * inv2dc);
+                const bool a0 = owner && r <= my && pi0 >= 1 && pi0 <= mx, a1 = owner && r <= my && pi0 + 2 <= mx;
+                T* q = Qb + planec(kb) + ro[i + 1];
+                if (a0 && a1)
+                    *(PT*)q = PT{v0, v1};
+                else {
+                    if (a0) q[0] = v0;
+                    if (a1) q[1] = v1;
+                }
+                if (MODE & kFsResOut) {
+                    if (a0) take(abs_bits(resid((double)fbv[i].a, (double)s0, (double)v0, 6.0, inv_h2)));
+                    if (a1) take(abs_bits(resid((double)fbv[i].b, (double)s1, (double)v1, 6.0, inv_h2)));
+                }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < G; i++) rp[i] = rn[i + 1];
+#pragma unroll
+        for (int i = 0; i < R; i++) {
+            rn[i] = rk[i];
+            b0[i] = b1[i];
+            b1[i] = ba[i];
+        }
+    }
+    if (MODE) block_max_to(best, maxbits);
+}
+
 // Coarse right-hand side and correction of one coarse point.  With seed_h2 > 0
 // the correction is not cleared but set to the result of the coarse level's
 // first red half sweep from zero, (0 - h^2 f) / (2d) on red points (black
@@ -3203,11 +3414,28 @@ void launch_full_sweep(hipStream_t st, SGrid g, const T* P, T* Q, const T* f, do
                        int rev, unsigned long long* maxbits)
 {
     const int my = g.ny - 2, mz = g.nz - 2;
+    const double inv2d = 1.0 / 6.0;
+    if (g.hx % 2 == 0) {
+        const int nrg = ceil_div(my, kFsPairRows);
+        const long waves = ceil_div((long)nrg * (g.hx / 2), kFsOwn);
+        const int wblocks = ceil_div(waves, kFsBlock / 64);
+        const dim3 grid(wblocks * ceil_div(mz, kFsPairChunk));
+#define NP_FSP(M)                                                                                                      \
+    hipLaunchKernelGGL((k_full_sweep3_pair<T, kFsPairRows, kFsPairChunk, M>), grid, dim3(kFsBlock), 0, st, P, Q, f, g, h2, \
+                       inv2d, inv_h2, nrg, wblocks, rev, maxbits)
+        switch (mode & 3) {
+        case 0: NP_FSP(0); break;
+        case 1: NP_FSP(1); break;
+        case 2: NP_FSP(2); break;
+        default: NP_FSP(3); break;
+        }
+#undef NP_FSP
+        return;
+    }
     const int nrg = ceil_div(my, kFsRows);
     const long waves = ceil_div((long)nrg * g.hx, kFsOwn);
     const int wblocks = ceil_div(waves, kFsBlock / 64);
     const dim3 grid(wblocks * ceil_div(mz, kFsChunk));
-    const double inv2d = 1.0 / 6.0;
 #define NP_FS(M)                                                                                                    \
     hipLaunchKernelGGL((k_full_sweep3<T, kFsRows, kFsChunk, M>), grid, dim3(kFsBlock), 0, st, P, Q, f, g, h2, inv2d, \
                        inv_h2, nrg, wblocks, rev, maxbits)
