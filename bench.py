@@ -260,6 +260,9 @@ VARIANTS = {
     "fp64_interp_buffer": dict(precision="fp64", guess="interp", buffer="interp"),
     # same-size patches of a depth one after another instead of batched
     "fp64_sequential": dict(precision="fp64", guess="interp", batch=False),
+    # the headline's schedule with the last pre-smoothing black half sweep run
+    # inside the restriction (slower on MI355X; not in the default set)
+    "fp16s_dc_v11_fused": dict(precision="fp16s_dc", guess="interp", n_pre=1, n_post=1, sweep="fused"),
 }
 ELEM = {"fp64": 8, "fp32_dc": 4, "fp16s_dc": 2}
 # largest max |F - F_fp64| / max |F_fp64| a variant may show to count as the
@@ -308,7 +311,7 @@ def run_variant(name, wl, rho, phi_outer, Fs, steps, warmup, inner_cycles, stop_
     v = VARIANTS[name]
     solver = NestedPoissonSolver(geom, precision=v["precision"], guess=v["guess"], inner_cycles=inner_cycles,
                                  buffer=v.get("buffer", "relaxed"), stop_rule=stop_rule, batch=v.get("batch", True),
-                                 n_pre=v.get("n_pre", 2), n_post=v.get("n_post", 1))
+                                 n_pre=v.get("n_pre", 2), n_post=v.get("n_post", 1), sweep=v.get("sweep", "full"))
     if v["guess"] == "learned":
         solver.set_guess_weights(learned.load_weights())
     stream = torch.cuda.current_stream()
@@ -380,6 +383,17 @@ def run_variant(name, wl, rho, phi_outer, Fs, steps, warmup, inner_cycles, stop_
         b = (24 + 2 * elem) * npts
         dc_pass = dict(launches=cnt, avg_launch_us=round(ms_c / cnt * 1e3, 2), ms_per_step=round(ms_c / steps, 3),
                        bytes_per_launch=b, GBps=round(b / (ms_c / cnt * 1e-3) / 1e9, 1))
+    # the last pre-smoothing black half sweep fused with the restriction (2-byte
+    # storage): reads the red values (or the defect they are formed from) and f
+    # of both colours, writes the black values (and the formed red ones): 2 e per
+    # fine point, plus the coarse right-hand side and correction (2 x 4 B per
+    # coarse point): 1 B per fine point
+    black_restrict = None
+    cnt, ms_c = prof["black_restrict"]
+    if cnt and uniform:
+        b = (2 * elem + 1) * npts
+        black_restrict = dict(launches=cnt, avg_launch_us=round(ms_c / cnt * 1e3, 2), ms_per_step=round(ms_c / steps, 3),
+                              bytes_per_launch=b, GBps=round(b / (ms_c / cnt * 1e-3) / 1e9, 1))
     # the roofline kernel: the smoothing class with the most device time
     main_cls = max((c for c in ("smooth", "full") if c in sweeps), key=lambda c: sweeps[c]["ms_per_step"])
     smoother = dict(sweeps[main_cls], kind=main_cls, elem_bytes=elem, classes=sweeps)
@@ -405,6 +419,7 @@ def run_variant(name, wl, rho, phi_outer, Fs, steps, warmup, inner_cycles, stop_
         edge_force_error_per_level=edge,
         smoother=smoother,
         dc_pass=dc_pass,
+        black_restrict=black_restrict,
         kernels={k: dict(launches=c, ms_per_step=round(m / steps, 3), avg_us=(round(1e3 * m / c, 2) if c else None))
                  for k, (c, m) in prof.items()},
     )
@@ -552,6 +567,9 @@ def main():
         "dc_pass_roofline": (None if not b.get("dc_pass") else
                              dict(b["dc_pass"], peak=PEAK_HBM_GBS, unit="GB/s",
                                   frac=round(b["dc_pass"]["GBps"] / PEAK_HBM_GBS, 4))),
+        "black_restrict_roofline": (None if not b.get("black_restrict") else
+                                    dict(b["black_restrict"], peak=PEAK_HBM_GBS, unit="GB/s",
+                                         frac=round(b["black_restrict"]["GBps"] / PEAK_HBM_GBS, 4))),
         "cpu_baseline": cpu,
         "linf_force_error": b["linf_force_error"],
         "deviation_from_fp64": b["deviation_from_fp64"],

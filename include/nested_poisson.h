@@ -96,10 +96,16 @@ extern "C" {
  * first pre-smoothing sweep, which runs before the test and is dropped when
  * the level stops (needs n_pre >= 1 and n_post >= 1, the relaxed buffer on
  * levels l >= 1 and a level solved on its own; elsewhere the half sweeps run).
- * NP_SWEEP_HALF: two half sweeps in place and a separate residual pass.  The
- * iterates are the same in both. */
+ * NP_SWEEP_HALF: two half sweeps in place and a separate residual pass.
+ * NP_SWEEP_FUSED: as NP_SWEEP_FULL, and in the defect correction with 2-byte
+ * storage (3-D) the last pre-smoothing black half sweep of multigrid level 0
+ * runs inside the restriction that follows it (Sec. 2.3 steps 2-5 in one pass;
+ * needs N^0 = 2 N^1 along every axis and an odd N^1_x, elsewhere they run
+ * apart).  On MI355X this pass is slower than the two kernels it replaces, so
+ * it is not the default.  The iterates are the same in all three. */
 #define NP_SWEEP_FULL 0
 #define NP_SWEEP_HALF 1
+#define NP_SWEEP_FUSED 2
 
 typedef struct np_config {
     int dim;                        /* 2 or 3 */
@@ -238,6 +244,8 @@ int nested_poisson_potential(np_solver* s, int level, double* phi_padded);
 #define NP_KCLASS_FULL 10    /* full red-black sweeps of multigrid level 0 (NP_SWEEP_FULL) */
 #define NP_KCLASS_FULL_RES 11 /* the full sweep that also completes the stop test's residual norm */
 #define NP_KCLASS_DC_SCALE 12 /* first scaled defect of a level from its starting residual */
+#define NP_KCLASS_BLACK_RESTRICT 13 /* last pre-smoothing black half sweep of multigrid level 0 fused with
+                                     * the residual restriction (NP_SWEEP_FUSED, 2-byte storage) */
 #define NP_NKCLASS 16
 typedef struct np_profile {
     long count[NP_NKCLASS]; /* launches (intervals) recorded */

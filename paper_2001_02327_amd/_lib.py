@@ -27,7 +27,7 @@ STOP_RULES = {"residual": 0, "force_delta": 1}
 PRECISIONS = {"fp64": 0, "fp32_dc": 1, "fp16s_dc": 2}
 GUESSES = {"interp": 0, "learned": 1}
 BUFFERS = {"relaxed": 0, "interp": 1}
-SWEEPS = {"full": 0, "half": 1}
+SWEEPS = {"full": 0, "half": 1, "fused": 2}
 
 
 class NpConfig(ctypes.Structure):
@@ -80,7 +80,7 @@ class NpStats(ctypes.Structure):
 
 NP_NKCLASS = 16
 KCLASSES = ["smooth", "restrict", "prolong", "coarse", "norm", "fill", "forces", "dc", "guess", "seeded", "full",
-            "full_res", "dc_scale"]
+            "full_res", "dc_scale", "black_restrict"]
 NP_NET_PARAMS = 8241
 NP_NET_MSE_NOALLOC_MAX = 1 << 28
 NP_GUESS_BLOB_MAGIC = 0x5747504E

@@ -145,6 +145,15 @@ void launch_full_sweep(hipStream_t st, SGrid g, const T* P, T* Q, const T* f, do
 template <typename TF, typename TC>
 void launch_resid_restrict(int dim, hipStream_t st, SGrid gf, const TF* u, const TF* f, double inv_h2, double out_scale,
                            SGrid gc, TC* fc, TC* ec, int rule, const Rule3& fine_rule, double seed_h2);
+// Black half sweep of a 3-D multigrid level 0 in 2-byte storage followed by
+// the residual restriction of launch_resid_restrict (FP32 coarse level, fixed
+// ghost layer), in one pass, with the same results.  seed != 0: the red points
+// hold the red half sweep from zero, unstored; the red values are formed from f
+// and stored (as launch_half_sweep_seeded with store_red).  Applies where
+// black_restrict_fits: N_fine = 2 N_coarse along every axis, even hx
+bool black_restrict_fits(const SGrid& gf, const SGrid& gc);
+void launch_black_restrict(hipStream_t st, SGrid gf, __half* u, const __half* f, double h2, double inv_h2,
+                           double out_scale, SGrid gc, float* fc, float* ec, double seed_h2, int seed);
 // black_only != 0 corrects only the black points; coarse_rule: the coarse level's rule
 template <typename TC, typename TF>
 void launch_prolong_add(int dim, hipStream_t st, SGrid gc, const TC* ec, SGrid gf, TF* u, int black_only,

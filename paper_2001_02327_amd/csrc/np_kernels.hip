@@ -1210,6 +1210,16 @@ __device__ __forceinline__ float mix_add2(uint32_t a, uint32_t b)
     return r;
 }
 
+// Gauss-Seidel value of a point in storage type T from the sum s of its 2d
+// neighbours: (s - h^2 f) / (2d) in the compute type C, rounded to T, written
+// as k_smooth_zmarch3_pair writes it (there inline, so that the compiler keeps
+// building the pair in one register for a 4-byte store).
+template <typename T, typename C>
+__device__ __forceinline__ T gs_value(C s, T fv, C h2, C inv2d)
+{
+    return (T)((s - h2 * (C)fv) * inv2d);
+}
+
 // Paired form of the level-0 z-march for 2- and 4-byte storage: a thread owns
 // the two compact points h0 = 2 hp and h0 + 1 of a row and moves them with
 // one 2-element load or store; the extra x-neighbour (h0 - 1 or h0 + 2) is a
@@ -2119,15 +2129,91 @@ __device__ __forceinline__ double next_first(const Pair<double>& p)
     return dpp_next(p.a);
 }
 
+// One fine row of a pair of coarse points in packed FP16 words: x = 2 h0 + m
+// for m = 0..5 is the lower (m = 0, 1, 4, 5) or upper (m = 2, 3) half of A (even
+// x = 2 h0, 2 h0 + 2), B (odd x), An and Bn (the next lane's A and B: x =
+// 2 h0 + 4, 2 h0 + 5).  The residual arithmetic below takes the halves straight
+// from the words (v_fma_mix converts them exactly), so no value is converted on
+// its own.
+struct HRow {
+    uint32_t A, B, An, Bn;
+};
+__device__ __forceinline__ HRow hrow(uint32_t A, uint32_t B) { return HRow{A, B, dpp_next(A), dpp_next(B)}; }
+template <int M>
+__device__ __forceinline__ uint32_t hw(const HRow& r)
+{
+    return (M == 0 || M == 2) ? r.A : ((M == 1 || M == 3) ? r.B : (M == 4 ? r.An : r.Bn));
+}
+template <int M>
+constexpr int kHalfOf = (M == 2 || M == 3) ? 1 : 0;
+
+// c * (half H of w) + s, one rounding
+template <int H>
+__device__ __forceinline__ float mix_fma_w(uint32_t w, float c, float s)
+{
+    float r;
+    if constexpr (H == 0)
+        asm("v_fma_mix_f32 %0, %1, %2, %3 op_sel_hi:[1,0,0]" : "=v"(r) : "v"(w), "v"(c), "v"(s));
+    else
+        asm("v_fma_mix_f32 %0, %1, %2, %3 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "=v"(r) : "v"(w), "v"(c), "v"(s));
+    return r;
+}
+// c * t + (half H of w), one rounding
+template <int H>
+__device__ __forceinline__ float mix_fma_to(float c, float t, uint32_t w)
+{
+    float r;
+    if constexpr (H == 0)
+        asm("v_fma_mix_f32 %0, %1, %2, %3 op_sel_hi:[0,0,1]" : "=v"(r) : "v"(c), "v"(t), "v"(w));
+    else
+        asm("v_fma_mix_f32 %0, %1, %2, %3 op_sel:[0,0,1] op_sel_hi:[0,0,1]" : "=v"(r) : "v"(c), "v"(t), "v"(w));
+    return r;
+}
+
+// Residual f - lap u at x = 2 h0 + M of fine row 2J - 1 + DY: the neighbour
+// sum in the order x, y, z (one rounding per addition), then s - 6 u and f -
+// (s - 6 u) / h^2 as fused multiply-adds.  c: rows 2J - 1, 2J of the plane, y0,
+// y3: rows 2J - 2, 2J + 1, zm / zp: rows 2J - 1, 2J of the planes below and
+// above, fr: the right-hand side; m6 = -6, ninv_h2 = -1 / h^2.
+template <int M, int DY>
+__device__ __forceinline__ float resid_h(const HRow (&zm)[2], const HRow (&c)[2], const HRow (&zp)[2], const HRow& y0,
+                                         const HRow& y3, const HRow (&fr)[2], float m6, float ninv_h2)
+{
+    constexpr int H = kHalfOf<M>;
+    float s = mix_add2<kHalfOf<M - 1>, kHalfOf<M + 1>>(hw<M - 1>(c[DY]), hw<M + 1>(c[DY]));
+    s = mix_add<H>(s, hw<M>(DY ? c[0] : y0));
+    s = mix_add<H>(s, hw<M>(DY ? y3 : c[1]));
+    s = mix_add<H>(s, hw<M>(zm[DY]));
+    s = mix_add<H>(s, hw<M>(zp[DY]));
+    const float t = mix_fma_w<H>(hw<M>(c[DY]), m6, s);
+    return mix_fma_to<H>(ninv_h2, t, hw<M>(fr[DY]));
+}
+
+// The residuals of one fine plane of a pair of coarse points (rows 2J - 1 + dy,
+// x = 2 h0 + 1 + j) added to their two sums in the order dy, dx.
+__device__ __forceinline__ void pair_plane_sums(const HRow (&zm)[2], const HRow (&c)[2], const HRow (&zp)[2],
+                                                const HRow& y0, const HRow& y3, const HRow (&fr)[2], float m6,
+                                                float ninv_h2, float& sa, float& sb)
+{
+    sa = sa + resid_h<1, 0>(zm, c, zp, y0, y3, fr, m6, ninv_h2);
+    sa = sa + resid_h<2, 0>(zm, c, zp, y0, y3, fr, m6, ninv_h2);
+    sa = sa + resid_h<1, 1>(zm, c, zp, y0, y3, fr, m6, ninv_h2);
+    sa = sa + resid_h<2, 1>(zm, c, zp, y0, y3, fr, m6, ninv_h2);
+    sb = sb + resid_h<3, 0>(zm, c, zp, y0, y3, fr, m6, ninv_h2);
+    sb = sb + resid_h<4, 0>(zm, c, zp, y0, y3, fr, m6, ninv_h2);
+    sb = sb + resid_h<3, 1>(zm, c, zp, y0, y3, fr, m6, ninv_h2);
+    sb = sb + resid_h<4, 1>(zm, c, zp, y0, y3, fr, m6, ninv_h2);
+}
+
+// The paired restriction described above (FP16 fine level, FP32 coarse level).
 template <typename TF, typename TC>
 __global__ void __launch_bounds__(kBlock) k_restrict3_pair(const TF* __restrict__ u, const TF* __restrict__ f, SGrid gf,
-                                                            typename Compute<TC>::type inv_h2,
-                                                            typename Compute<TC>::type out_scale, SGrid gc,
+                                                            float inv_h2, float out_scale, SGrid gc,
                                                             TC* __restrict__ fc, TC* __restrict__ ec, int pblocks,
-                                                            typename Compute<TC>::type seed_h2,
-                                                            typename Compute<TC>::type inv2d)
+                                                            float seed_h2, float inv2d)
 {
-    using C = typename Compute<TC>::type;
+    static_assert(sizeof(TF) == 2 && sizeof(TC) == 4, "FP16 fine level, FP32 coarse level");
+    using C = float;
     if (batch_idle(gf)) return;
     u = batch_at(u, gf);
     f = batch_at(f, gf);
@@ -2148,82 +2234,46 @@ __global__ void __launch_bounds__(kBlock) k_restrict3_pair(const TF* __restrict_
     const int K1 = min(K0 + kRestrictPairChunk - 1, Ncz);
     const size_t fplane = gf.ps;
     const unsigned row0 = (unsigned)((2 * J - 2) * gf.hx + h0);
-    // v[m] = a(x = 2 h0 + m) for m = 0..5 in fine row 2J - 2 + r of plane z:
-    // x = 2 h0 + 2 i is in colour (y + z + 1) & 1 at compact h0 + i, the odd
-    // x in the other colour
-    auto seg = [&](const TF* __restrict__ a, int r, int z, C (&v)[6]) {
+    // fine row 2J - 2 + r of plane z: x = 2 h0 + 2 i is in colour (y + z + 1) & 1
+    // at compact h0 + i, the odd x in the other colour
+    auto seg = [&](const TF* __restrict__ a, int r, int z) -> HRow {
         const int y = 2 * J - 2 + r;
         const bool ca = ((y + z + 1) & 1) != 0;
         const TF* __restrict__ pl = a + (size_t)z * fplane + (row0 + (unsigned)(r * gf.hx));
-        const Pair<TF> A = *(const Pair<TF>*)(pl + (ca ? gf.cs : 0));
-        const Pair<TF> B = *(const Pair<TF>*)(pl + (ca ? 0 : gf.cs));
-        v[0] = (C)A.a;
-        v[2] = (C)A.b;
-        v[4] = (C)next_first(A);
-        v[1] = (C)B.a;
-        v[3] = (C)B.b;
-        v[5] = (C)next_first(B);
-    };
-    // the residuals of fine plane z (rows 2J - 1 + dy, x = 2 h0 + 1 + j) added to
-    // the two coarse sums in the order dy, dx: c1, c2 the rows 2J - 1, 2J of the
-    // plane, y0, y3 the rows 2J - 2, 2J + 1, zm / zp rows 2J - 1, 2J of the
-    // planes below and above, f1, f2 the right-hand side
-    auto plane_sums = [&](const C (&zm)[2][6], const C (&c)[2][6], const C (&zp)[2][6], const C (&y0)[6],
-                          const C (&y3)[6], const C (&fr)[2][6], C& sa, C& sb) {
-#pragma unroll
-        for (int half = 0; half < 2; half++) {
-            C& sum = half ? sb : sa;
-#pragma unroll
-            for (int dy = 0; dy < 2; dy++) {
-#pragma unroll
-                for (int dx = 0; dx < 2; dx++) {
-                    const int m = 1 + 2 * half + dx;
-                    const C uc = c[dy][m];
-                    C s = c[dy][m - 1] + c[dy][m + 1];
-                    s = s + (dy ? c[0][m] : y0[m]);
-                    s = s + (dy ? y3[m] : c[1][m]);
-                    s = s + zm[dy][m];
-                    s = s + zp[dy][m];
-                    sum += fr[dy][m] - (s - (C)6 * uc) * inv_h2;
-                }
-            }
-        }
+        return hrow(*(const uint32_t*)(pl + (ca ? gf.cs : 0)), *(const uint32_t*)(pl + (ca ? 0 : gf.cs)));
     };
     const C scale = (C)0.125 * out_scale;
+    const C m6 = -6.0f, ninv_h2 = -inv_h2;
     const int I = h0 + 1;
     const bool store_b = lane != 63 && I + 1 <= Ncx, store_a = lane != 63;
-    C lo[2][6], mid[2][6];  // rows 2J - 1, 2J of fine planes 2K - 2, 2K - 1
+    HRow lo[2], mid[2];  // rows 2J - 1, 2J of fine planes 2K - 2, 2K - 1
 #pragma unroll
     for (int r = 0; r < 2; r++) {
-        seg(u, 1 + r, 2 * K0 - 2, lo[r]);
-        seg(u, 1 + r, 2 * K0 - 1, mid[r]);
+        lo[r] = seg(u, 1 + r, 2 * K0 - 2);
+        mid[r] = seg(u, 1 + r, 2 * K0 - 1);
     }
     auto step = [&](int K) {
-        C n1[2][6], n2[2][6], ya[6], yb[6], yc[6], yd[6], fa[2][6], fb[2][6];
+        HRow n1[2], n2[2], fa[2], fb[2];
 #pragma unroll
         for (int r = 0; r < 2; r++) {
-            seg(u, 1 + r, 2 * K, n1[r]);
-            seg(u, 1 + r, 2 * K + 1, n2[r]);
-            seg(f, 1 + r, 2 * K - 1, fa[r]);
-            seg(f, 1 + r, 2 * K, fb[r]);
+            n1[r] = seg(u, 1 + r, 2 * K);
+            n2[r] = seg(u, 1 + r, 2 * K + 1);
+            fa[r] = seg(f, 1 + r, 2 * K - 1);
+            fb[r] = seg(f, 1 + r, 2 * K);
         }
-        seg(u, 0, 2 * K - 1, ya);
-        seg(u, 3, 2 * K - 1, yb);
-        seg(u, 0, 2 * K, yc);
-        seg(u, 3, 2 * K, yd);
+        const HRow ya = seg(u, 0, 2 * K - 1), yb = seg(u, 3, 2 * K - 1);
+        const HRow yc = seg(u, 0, 2 * K), yd = seg(u, 3, 2 * K);
         C sa = 0, sb = 0;
-        plane_sums(lo, mid, n1, ya, yb, fa, sa, sb);
-        plane_sums(mid, n1, n2, yc, yd, fb, sa, sb);
+        pair_plane_sums(lo, mid, n1, ya, yb, fa, m6, ninv_h2, sa, sb);
+        pair_plane_sums(mid, n1, n2, yc, yd, fb, m6, ninv_h2, sa, sb);
         if (store_a) coarse_out<3, TC, C>(fc, ec, pos<3, TC>(gc, I, J, K), I, J, K, sa * scale, seed_h2, inv2d);
         if (store_b)
             coarse_out<3, TC, C>(fc, ec, pos<3, TC>(gc, I + 1, J, K), I + 1, J, K, sb * scale, seed_h2, inv2d);
 #pragma unroll
-        for (int r = 0; r < 2; r++)
-#pragma unroll
-            for (int m = 0; m < 6; m++) {
-                lo[r][m] = n1[r][m];
-                mid[r][m] = n2[r][m];
-            }
+        for (int r = 0; r < 2; r++) {
+            lo[r] = n1[r];
+            mid[r] = n2[r];
+        }
     };
     if (K1 - K0 + 1 == kRestrictPairChunk) {
 #pragma unroll
@@ -2231,6 +2281,230 @@ __global__ void __launch_bounds__(kBlock) k_restrict3_pair(const TF* __restrict_
     } else {
         for (int K = K0; K <= K1; K++) step(K);
     }
+}
+
+// ------------------------------------------------------------------ black sweep + restriction
+// The last pre-smoothing black half sweep of multigrid level 0 in 2-byte
+// storage, fused with the residual and its restriction (Sec. 2.3 steps 2-5:
+// the sweep, then eqn:restriction3D of f - lap u).  Threads are laid out as in
+// k_restrict3_pair (a pair of coarse points I = h0 + 1, I + 1 of coarse row J,
+// a chunk of coarse planes), except that a wave owns the 62 pairs of its lanes
+// 1..62: lane 0 only supplies red values to lane 1 and lane 63 the first values
+// of its pair to lane 62.  The residuals of a thread read the final values of
+// fine rows 2J - 2 .. 2J + 1 of the fine planes 2K0 - 2 .. 2K1 + 1; the thread
+// forms their black values itself from the red values and the right-hand
+// side, with the arithmetic of k_smooth_zmarch3_pair (the red values are not
+// changed by a black half sweep), keeps them in registers and stores the black
+// points it owns (fine rows 2J - 1, 2J, planes 2K0 - 1 .. 2K1, compact slots
+// h0, h0 + 1).  The residual and the sums are those of k_restrict3_pair, so
+// the result equals the black half sweep followed by that restriction, bit for
+// bit.  No thread reads what another writes: black values are read only on the
+// ghost layer, which no kernel writes.
+// SEED: the red values are those of a red half sweep from zero, formed from the
+// defect f (red) as k_smooth_zmarch3_pair<T, 2> forms them, and stored.
+constexpr int kBrChunk = 4;  // coarse planes per thread
+
+template <int SEED>
+__global__ void __launch_bounds__(kBlock) k_black_restrict3_pair(__half* __restrict__ u, const __half* __restrict__ f,
+                                                                  SGrid gf, float h2, float inv_h2, float out_scale,
+                                                                  SGrid gc, float* __restrict__ fc,
+                                                                  float* __restrict__ ec, int pblocks, float seed_h2,
+                                                                  float inv2d)
+{
+    using T = __half;
+    using C = float;
+    typedef uint32_t W;  // a pair of compact FP16 values, the lower one first
+    if (batch_idle(gf)) return;
+    u = batch_at(u, gf);
+    f = batch_at(f, gf);
+    fc = batch_at(fc, gc);
+    ec = batch_at(ec, gc);
+    const int Ncx = gc.nx - 2, Ncy = gc.ny - 2, Ncz = gc.nz - 2;
+    const int Nfx = gf.nx - 2, Nfy = gf.ny - 2, Nfz = gf.nz - 2;
+    const int lb = (int)xcd_block();
+    const int zc = lb / pblocks;
+    const int lane = (int)(threadIdx.x & 63);
+    const int w = (lb - zc * pblocks) * (kBlock / 64) + (int)(threadIdx.x >> 6);
+    const int P = gf.hx >> 1;  // pairs per fine row
+    const int e = max(62 * w + lane - 1, 0);
+    if (e >= P * Ncy) return;
+    const bool own = lane >= 1 && lane <= 62;
+    const int J = 1 + e / P;
+    const int hp = e - (J - 1) * P;
+    const int h0 = 2 * hp;
+    const int K0 = 1 + zc * kBrChunk;
+    const int K1 = min(K0 + kBrChunk - 1, Ncz);
+    const size_t ps = gf.ps;
+    const T* __restrict__ rsrc = SEED ? f : u;  // red values (colour 0), formed from f with SEED
+    const T* __restrict__ fblk = f + gf.cs;
+    T* __restrict__ ublk = u + gf.cs;
+    const auto half_of = [](W v, int hi) -> T { return __builtin_bit_cast(T, (uint16_t)(hi ? v >> 16 : v & 0xffffu)); };
+    const auto pack = [](T a, T b) -> W {
+        return (W)__builtin_bit_cast(uint16_t, a) | ((W)__builtin_bit_cast(uint16_t, b) << 16);
+    };
+    // word at compact h0 of fine row y (clamped to the grid) of plane z
+    const auto ld = [&](const T* __restrict__ a, int z, int y) -> W {
+        y = min(max(y, 0), Nfy + 1);
+        return *(const W*)(a + (size_t)z * ps + (unsigned)(y * gf.hx + h0));
+    };
+    // red words of rows 2J - 3 .. 2J + 2 of plane z; outside the grid (needed only
+    // by the ghost planes, whose black values are not formed) the nearest plane's,
+    // so that every load is unconditional
+    const auto red_plane = [&](int z, W (&r)[6]) {
+        z = min(max(z, 0), Nfz + 1);
+#pragma unroll
+        for (int i = 0; i < 6; i++) {
+            W v = ld(rsrc, z, 2 * J - 3 + i);
+            if (SEED)
+                v = pack(gs_value<T, C>((C)0, half_of(v, 0), h2, inv2d), gs_value<T, C>((C)0, half_of(v, 1), h2, inv2d));
+            r[i] = v;
+        }
+    };
+    // right-hand side of the black points of rows 2J - 2 .. 2J + 1 of plane z
+    const auto fblk_plane = [&](int z, W (&b)[4]) {
+#pragma unroll
+        for (int i = 0; i < 4; i++) b[i] = ld(fblk, z, 2 * J - 2 + i);
+    };
+    // Final values of rows 2J - 2 .. 2J + 1 of plane z (as k_restrict3_pair reads
+    // them) and its black words, from the red words of planes z - 1, z, z + 1
+    // and the black right-hand side of z.
+    const auto produce = [&](int z, const W (&rm)[6], const W (&rc)[6], const W (&rp)[6], const W (&fb)[4],
+                             HRow (&v)[4], W (&bw)[4]) {
+        const bool gz = z == 0 || z == Nfz + 1;
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            const int y = 2 * J - 2 + r;
+            const int o = (y + z + 1) & 1;  // x offset of the red points in this row
+            const W rw = rc[r + 1];
+            const W pw = dpp_prev(rw), nw = dpp_next(rw);
+            // the black points x = 2 h0 + 1 - o and x + 2: their x-neighbours
+            // (the previous lane's upper red value or this lane's, and this
+            // lane's lower one or the next lane's), then rows y - 1, y + 1 and
+            // planes z - 1, z + 1, one rounding per addition, as the half sweep
+            C sa = mix_add2<1, 0>(o ? pw : rw, rw);
+            C sb = mix_add2<1, 0>(rw, o ? rw : nw);
+            sa = mix_add<0>(sa, rc[r]);
+            sb = mix_add<1>(sb, rc[r]);
+            sa = mix_add<0>(sa, rc[r + 2]);
+            sb = mix_add<1>(sb, rc[r + 2]);
+            sa = mix_add<0>(sa, rm[r + 1]);
+            sb = mix_add<1>(sb, rm[r + 1]);
+            sa = mix_add<0>(sa, rp[r + 1]);
+            sb = mix_add<1>(sb, rp[r + 1]);
+            W b = pack(gs_value<T, C>(sa, half_of(fb[r], 0), h2, inv2d), gs_value<T, C>(sb, half_of(fb[r], 1), h2, inv2d));
+            // ghost points keep their stored values
+            const int xa = 2 * h0 + 1 - o;
+            const bool gr = gz || y == 0 || y == Nfy + 1;
+            const bool ga = gr || xa == 0 || xa == Nfx + 1, gb = gr || xa + 2 == Nfx + 1;
+            if (ga || gb) {
+                const W g = ld(ublk, z, y);
+                b = (ga ? (g & 0xffffu) : (b & 0xffffu)) | (gb ? (g & 0xffff0000u) : (b & 0xffff0000u));
+            }
+            bw[r] = b;
+            v[r] = hrow(o ? b : rw, o ? rw : b);  // even x, odd x
+        }
+    };
+    // right-hand side of rows 2J - 1, 2J of plane z as k_restrict3_pair reads it
+    const auto rhs = [&](int z, const W (&fr)[2], const W (&fb)[2], HRow (&v)[2]) {
+#pragma unroll
+        for (int dy = 0; dy < 2; dy++) {
+            const int o = (2 * J - 1 + dy + z + 1) & 1;
+            v[dy] = hrow(o ? fb[dy] : fr[dy], o ? fr[dy] : fb[dy]);
+        }
+    };
+    // stores of the owned points of rows 2J - 1, 2J of an active plane z
+    const auto store_plane = [&](int z, const W (&bw)[4], const W (&rw)[6]) {
+        if (!own) return;
+#pragma unroll
+        for (int dy = 0; dy < 2; dy++) {
+            const int y = 2 * J - 1 + dy;
+            const size_t here = (size_t)z * ps + (unsigned)(y * gf.hx + h0);
+            const int xa = 2 * h0 + 1 - ((y + z + 1) & 1);
+            const bool a0 = xa >= 1, a1 = xa + 2 <= Nfx;
+            if (a0 && a1) {
+                *(W*)(ublk + here) = bw[1 + dy];
+            } else {
+                if (a0) ublk[here] = half_of(bw[1 + dy], 0);
+                if (a1) ublk[here + 1] = half_of(bw[1 + dy], 1);
+            }
+            if (SEED) *(W*)(u + here) = rw[2 + dy];
+        }
+    };
+    const C scale = (C)0.125 * out_scale;
+    const C m6 = -6.0f, ninv_h2 = -inv_h2;
+    const int I = h0 + 1;
+    const bool store_b = own && I + 1 <= Ncx;
+    // planes 2K0 - 2 and 2K0 - 1
+    W rA[6], rB[6], rC[6], rD[6], fA[4], fB[4];
+    red_plane(2 * K0 - 3, rA);
+    red_plane(2 * K0 - 2, rB);
+    red_plane(2 * K0 - 1, rC);
+    red_plane(2 * K0, rD);
+    fblk_plane(2 * K0 - 2, fA);
+    fblk_plane(2 * K0 - 1, fB);
+    HRow v0[4], v1[4];
+    W b0[4], b1[4];
+    produce(2 * K0 - 2, rA, rB, rC, fA, v0, b0);
+    produce(2 * K0 - 1, rB, rC, rD, fB, v1, b1);
+    // carried between coarse planes: final rows 2J - 1, 2J of fine plane 2K - 2,
+    // all four rows of 2K - 1 and its black words, red words and black
+    // right-hand side, and the red words of plane 2K
+    HRow zlo[2] = {v0[1], v0[2]};
+    W rp1[6], rc0[6], fbp[2];
+#pragma unroll
+    for (int i = 0; i < 6; i++) {
+        rp1[i] = rC[i];
+        rc0[i] = rD[i];
+    }
+    fbp[0] = fB[1];
+    fbp[1] = fB[2];
+    auto step = [&](int K) {
+        // fine planes 2K, 2K + 1 produced; residuals of 2K - 1, 2K
+        W rn1[6], rn2[6], fn0[4], fn1[4], fr0[2], fr1[2];
+        red_plane(2 * K + 1, rn1);
+        red_plane(2 * K + 2, rn2);
+        fblk_plane(2 * K, fn0);
+        fblk_plane(2 * K + 1, fn1);
+#pragma unroll
+        for (int dy = 0; dy < 2; dy++) {
+            fr0[dy] = ld(f, 2 * K - 1, 2 * J - 1 + dy);
+            fr1[dy] = ld(f, 2 * K, 2 * J - 1 + dy);
+        }
+        HRow v2[4], v3[4], fa[2], fbv[2];
+        W b2[4], b3[4];
+        produce(2 * K, rp1, rc0, rn1, fn0, v2, b2);
+        const HRow c1[2] = {v1[1], v1[2]}, c2[2] = {v2[1], v2[2]};
+        rhs(2 * K - 1, fr0, fbp, fa);
+        C sa = 0, sb = 0;
+        pair_plane_sums(zlo, c1, c2, v1[0], v1[3], fa, m6, ninv_h2, sa, sb);
+        store_plane(2 * K - 1, b1, rp1);
+        produce(2 * K + 1, rc0, rn1, rn2, fn1, v3, b3);
+        const HRow z3[2] = {v3[1], v3[2]};
+        const W fbc[2] = {fn0[1], fn0[2]};
+        rhs(2 * K, fr1, fbc, fbv);
+        pair_plane_sums(c1, c2, z3, v2[0], v2[3], fbv, m6, ninv_h2, sa, sb);
+        store_plane(2 * K, b2, rc0);
+        if (own) coarse_out<3, float, C>(fc, ec, pos<3, float>(gc, I, J, K), I, J, K, sa * scale, seed_h2, inv2d);
+        if (store_b)
+            coarse_out<3, float, C>(fc, ec, pos<3, float>(gc, I + 1, J, K), I + 1, J, K, sb * scale, seed_h2, inv2d);
+        // advance by two fine planes
+        zlo[0] = c2[0];
+        zlo[1] = c2[1];
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            v1[r] = v3[r];
+            b1[r] = b3[r];
+        }
+#pragma unroll
+        for (int i = 0; i < 6; i++) {
+            rp1[i] = rn1[i];
+            rc0[i] = rn2[i];
+        }
+        fbp[0] = fn1[1];
+        fbp[1] = fn1[2];
+    };
+#pragma unroll 1
+    for (int K = K0; K <= K1; K++) step(K);
 }
 
 // u += P(e) on the fine active points (eqn:prolongation2D/3D as the tensor
@@ -3497,6 +3771,29 @@ void launch_resid_restrict(int dim, hipStream_t st, SGrid gf, const TF* u, const
             hipLaunchKernelGGL((k_resid_restrict<2, TF, TC, false>), grid, dim3(kBlock), 0, st, u, f, gf, (C)inv_h2,
                                (C)out_scale, gc, fc, ec, gr, sh2, inv2d);
     }
+}
+
+bool black_restrict_fits(const SGrid& gf, const SGrid& gc)
+{
+    const long Ncx = gc.nx - 2, Ncy = gc.ny - 2, Ncz = gc.nz - 2;
+    return gf.nz > 1 && gf.nx - 2 == 2 * Ncx && gf.ny - 2 == 2 * Ncy && gf.nz - 2 == 2 * Ncz && gf.hx % 2 == 0 &&
+           2 * gf.cs < (1ull << 31);
+}
+
+void launch_black_restrict(hipStream_t st, SGrid gf, __half* u, const __half* f, double h2, double inv_h2,
+                           double out_scale, SGrid gc, float* fc, float* ec, double seed_h2, int seed)
+{
+    const long Ncy = gc.ny - 2, Ncz = gc.nz - 2;
+    const long waves = ceil_div((long)(gf.hx / 2) * Ncy, 62);
+    const int pb = ceil_div(waves, kBlock / 64);
+    const dim3 grid(pb * ceil_div(Ncz, kBrChunk), gf.nb);
+    const float inv2d = (float)(1.0 / 6.0);
+    if (seed)
+        hipLaunchKernelGGL((k_black_restrict3_pair<1>), grid, dim3(kBlock), 0, st, u, f, gf, (float)h2, (float)inv_h2,
+                           (float)out_scale, gc, fc, ec, pb, (float)seed_h2, inv2d);
+    else
+        hipLaunchKernelGGL((k_black_restrict3_pair<0>), grid, dim3(kBlock), 0, st, u, f, gf, (float)h2, (float)inv_h2,
+                           (float)out_scale, gc, fc, ec, pb, (float)seed_h2, inv2d);
 }
 
 template <typename TC, typename TF>

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <type_traits>
 #include <utility>
 #include <vector>
 
@@ -94,7 +95,8 @@ bool validate(const np_config* c, char* why, size_t nwhy)
         return fail("the interpolated buffer runs with FP64, the interpolated guess and the residual stop "
                     "rule only");
     if (c->batch != 0 && c->batch != 1) return fail("batch must be 0 or 1 (got %d)", c->batch);
-    if (c->sweep != NP_SWEEP_FULL && c->sweep != NP_SWEEP_HALF) return fail("bad sweep %d", c->sweep);
+    if (c->sweep != NP_SWEEP_FULL && c->sweep != NP_SWEEP_HALF && c->sweep != NP_SWEEP_FUSED)
+        return fail("bad sweep %d", c->sweep);
     return true;
 }
 
@@ -597,8 +599,19 @@ int vcycle_t(np_solver* s, int l, T0* u0, const T0* f0, double h2_0, double inv_
     // (the seeded black half sweep, whose bytes differ, has an interval and a
     // class of its own)
     int nsweep = 0;
-    auto sweep0 = [&]() {
+    // NP_SWEEP_FUSED with 2-byte storage: the last pre-smoothing black half sweep
+    // runs inside the restriction (launch_black_restrict); fused_seed: it is
+    // the step's seeded first half sweep
+    bool fuse = false, fused_seed = false;
+    if constexpr (std::is_same<T0, __half>::value && std::is_same<TC, float>::value)
+        fuse = d == 3 && c.n_pre > 0 && c.sweep == NP_SWEEP_FUSED && black_restrict_fits(v.g[0], v.g[1]);
+    auto sweep0 = [&](bool fuse_black) {
         for (int colour = red_done ? 1 : 0; colour < 2; colour++) {
+            if (colour == 1 && fuse_black) {
+                fused_seed = red_done && red_unstored;
+                red_done = false;
+                break;
+            }
             bool seeded = false;
             if constexpr (sizeof(T0) <= 4) {
                 if (red_done && red_unstored) {
@@ -617,20 +630,30 @@ int vcycle_t(np_solver* s, int l, T0* u0, const T0* f0, double h2_0, double inv_
             red_done = false;
         }
     };
-    auto smooth0 = [&](int sweeps) {
+    auto smooth0 = [&](int sweeps, bool fuse_last) {
         if (sweeps <= 0) return;
         nsweep = 0;
-        for (int it = 0; it < sweeps; it++) sweep0();
+        for (int it = 0; it < sweeps; it++) sweep0(fuse_last && it == sweeps - 1);
         if (nsweep) prof_end(s, nsweep);
     };
-    smooth0(c.n_pre);
+    smooth0(c.n_pre, fuse);
     // the restriction does multigrid level 1's first red half sweep unless the
     // coarse tail starts at level 1 (coarse_part then skips it)
     const bool seed1 = c.n_pre > 0 && tail_level(s, l, sizeof(TC)) != 1;
-    prof_begin(s, NP_KCLASS_RESTRICT);
-    launch_resid_restrict<T0, TC>(d, st, v.g[0], u0, f0, inv_h2_0, out_scale_0, v.g[1], v.f[1], v.u[1], 0, Rule3{},
-                                  seed1 ? v.h[1] * v.h[1] : 0.0);
-    prof_end(s);
+    if constexpr (std::is_same<T0, __half>::value && std::is_same<TC, float>::value) {
+        if (fuse) {
+            prof_begin(s, NP_KCLASS_BLACK_RESTRICT);
+            launch_black_restrict(st, v.g[0], u0, f0, h2_0, inv_h2_0, out_scale_0, v.g[1], v.f[1], v.u[1],
+                                  seed1 ? v.h[1] * v.h[1] : 0.0, fused_seed);
+            prof_end(s);
+        }
+    }
+    if (!fuse) {
+        prof_begin(s, NP_KCLASS_RESTRICT);
+        launch_resid_restrict<T0, TC>(d, st, v.g[0], u0, f0, inv_h2_0, out_scale_0, v.g[1], v.f[1], v.u[1], 0,
+                                      Rule3{}, seed1 ? v.h[1] * v.h[1] : 0.0);
+        prof_end(s);
+    }
     prof_begin(s, NP_KCLASS_COARSE);
     int rc = run_coarse(s, l, v, exec);
     prof_end(s);
@@ -640,7 +663,7 @@ int vcycle_t(np_solver* s, int l, T0* u0, const T0* f0, double h2_0, double inv_
     // post-smoothing red half sweep follows: it reads only black points
     launch_prolong_add<TC, T0>(d, st, v.g[1], v.u[1], v.g[0], u0, c.n_post > 0, rule_of(s, l, 1));
     prof_end(s);
-    smooth0(c.n_post);
+    smooth0(c.n_post, false);
     return NP_OK;
 }
 
@@ -656,7 +679,7 @@ int vcycle(np_solver* s, int l)
 bool full_sweeps(const np_solver* s, int l)
 {
     const np_config& c = s->cfg;
-    return c.dim == 3 && c.precision == NP_PREC_FP64 && c.sweep == NP_SWEEP_FULL && s->phi_alt && c.n_pre >= 1 &&
+    return c.dim == 3 && c.precision == NP_PREC_FP64 && c.sweep != NP_SWEEP_HALF && s->phi_alt && c.n_pre >= 1 &&
            c.n_post >= 1 && !(l > 0 && c.buffer == NP_BUFFER_INTERP);
 }
 
@@ -1342,7 +1365,7 @@ int nested_poisson_create(const np_config* cfg, void* hip_stream, np_solver** ou
         s->alt_cap = best * sizeof(double);
         if (rc == NP_OK) rc = alloc_dev(s, (void**)&s->phi_alt, s->alt_cap);
     }
-    if (rc == NP_OK && !dc && d == 3 && cfg->sweep == NP_SWEEP_FULL && cfg->n_pre >= 1 && cfg->n_post >= 1) {
+    if (rc == NP_OK && !dc && d == 3 && cfg->sweep != NP_SWEEP_HALF && cfg->n_pre >= 1 && cfg->n_post >= 1) {
         // the second potential buffer of the full sweeps
         size_t best = 0;
         for (int l = 0; l < cfg->nlevels; l++)
