@@ -322,8 +322,10 @@ def run_variant(name, wl, rho, phi_outer, Fs, steps, warmup, inner_cycles, stop_
             solver.forces(l, out=Fs[l])
         return st
 
+    warm = []
     for i in range(warmup):
         st = step()
+        warm.append(st)
         log(name, "warmup", i, "cycles", st["cycles"], "ms %.1f" % st["total_ms"])
     # timed region: `steps` steps as a caller runs them (no per-kernel events)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -414,6 +416,13 @@ def run_variant(name, wl, rho, phi_outer, Fs, steps, warmup, inner_cycles, stop_
         cycles_per_level=stats[-1]["cycles"],
         outer_steps_per_level=stats[-1]["outer_steps"],
         learned_kept=stats[-1]["learned_used"],
+        # the learned guess's cost gate: where the network ran, in the first
+        # (warm-up) solve and in the timed ones, and that first solve's host time
+        learned_ran_first=warm[0]["learned_ran"] if warm else None,
+        learned_kept_first=warm[0]["learned_used"] if warm else None,
+        first_solve_host_ms=round(warm[0]["total_ms"], 3) if warm else None,
+        guess_ms_first=[round(x, 3) for x in warm[0]["guess_ms"]] if warm else None,
+        learned_ran=stats[-1]["learned_ran"],
         linf_force_error=linf,
         deviation_from_fp64=dev,
         edge_force_error_per_level=edge,

@@ -135,11 +135,22 @@ typedef struct np_config {
                                        interpolated guess, relaxed buffer, residual stop rule;
                                        otherwise one after another); 0: one after another */
     int sweep;                      /* NP_SWEEP_* (default NP_SWEEP_FULL) */
+    int guess_gate;                 /* NP_GUESS_LEARNED: 1 (default) runs the network on a level only
+                                       while it pays.  After each inference the solve compares the
+                                       host time the learned guess took with the V-cycles it is
+                                       predicted to save (log of its restricted-residual ratio over
+                                       log of the parent's measured contraction per cycle, the keep
+                                       test's terms) times the level's time per V-cycle; where it
+                                       does not pay, later solves of the handle start that level from
+                                       the interpolated guess without running the network
+                                       (nested_poisson_set_guess_weights re-arms every level).
+                                       0: the network runs in every solve */
 } np_config;
 
 /* Fills `cfg` with the paper's solver settings (N_pre = 2, N_post = 1,
  * Sec. 3) and tol = 1e-10, max_cycles = 50, FP64, residual stop,
- * interpolated guess, relaxed buffer, parent[l] = l - 1, batch = 1.  The other
+ * interpolated guess, relaxed buffer, parent[l] = l - 1, batch = 1,
+ * guess_gate = 1.  The other
  * geometry fields (extent included: cubic patches) are zeroed. */
 void nested_poisson_default_config(np_config* cfg);
 
@@ -202,6 +213,9 @@ typedef struct np_stats {
     int outer_steps[NP_MAX_LEVELS];           /* defect-correction steps (0 for NP_PREC_FP64) */
     double guess_box_ratio[NP_MAX_LEVELS];    /* learned guess: its residual restricted twice (mean over
                                                  4^3 boxes, max norm) over the interpolated guess's */
+    int learned_ran[NP_MAX_LEVELS];           /* 1 where the network ran in this solve */
+    double guess_ms[NP_MAX_LEVELS];           /* host time of the learned guess (inference, its
+                                                 residual norms and a rejected guess's refill) */
 } np_stats;
 int nested_poisson_solve(np_solver* s, const double* const* rho, const double* phi_outer, np_stats* stats);
 

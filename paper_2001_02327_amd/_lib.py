@@ -51,6 +51,7 @@ class NpConfig(ctypes.Structure):
         ("extent", (ctypes.c_int * 3) * NP_MAX_LEVELS),
         ("batch", ctypes.c_int),
         ("sweep", ctypes.c_int),
+        ("guess_gate", ctypes.c_int),
     ]
 
 
@@ -75,6 +76,8 @@ class NpStats(ctypes.Structure):
         ("interp_rel_residual", ctypes.c_double * NP_MAX_LEVELS),
         ("outer_steps", ctypes.c_int * NP_MAX_LEVELS),
         ("guess_box_ratio", ctypes.c_double * NP_MAX_LEVELS),
+        ("learned_ran", ctypes.c_int * NP_MAX_LEVELS),
+        ("guess_ms", ctypes.c_double * NP_MAX_LEVELS),
     ]
 
 
@@ -159,7 +162,7 @@ class NestedPoissonError(RuntimeError):
 
 
 def make_config(geom, n_pre=2, n_post=1, tol=1e-10, max_cycles=50, stop_rule="residual", precision="fp64",
-                inner_cycles=1, guess="interp", buffer="relaxed", batch=True, sweep="full"):
+                inner_cycles=1, guess="interp", buffer="relaxed", batch=True, sweep="full", guess_gate=True):
     """np_config from a geometry (attributes dim, n, off, dx0, G) and solver settings."""
     c = NpConfig()
     lib().nested_poisson_default_config(ctypes.byref(c))
@@ -187,6 +190,7 @@ def make_config(geom, n_pre=2, n_post=1, tol=1e-10, max_cycles=50, stop_rule="re
     c.buffer = BUFFERS[buffer] if isinstance(buffer, str) else int(buffer)
     c.batch = 1 if batch else 0
     c.sweep = SWEEPS[sweep] if isinstance(sweep, str) else int(sweep)
+    c.guess_gate = 1 if guess_gate else 0
     parent = getattr(geom, "parent", None)
     if parent is not None:
         for l, p in enumerate(parent):

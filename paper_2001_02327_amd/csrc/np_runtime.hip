@@ -95,6 +95,7 @@ bool validate(const np_config* c, char* why, size_t nwhy)
         return fail("the interpolated buffer runs with FP64, the interpolated guess and the residual stop "
                     "rule only");
     if (c->batch != 0 && c->batch != 1) return fail("batch must be 0 or 1 (got %d)", c->batch);
+    if (c->guess_gate != 0 && c->guess_gate != 1) return fail("guess_gate must be 0 or 1 (got %d)", c->guess_gate);
     if (c->sweep != NP_SWEEP_FULL && c->sweep != NP_SWEEP_HALF && c->sweep != NP_SWEEP_FUSED)
         return fail("bad sweep %d", c->sweep);
     return true;
@@ -348,6 +349,8 @@ struct np_solver {
     // each level's learned guess against the interpolated one
     double rho_meas[NP_MAX_LEVELS] = {};
     double guess_box_ratio[NP_MAX_LEVELS] = {};
+    // levels on which the learned guess was found not to pay (guess_gate)
+    bool guess_off[NP_MAX_LEVELS] = {};
     uint16_t* net_w[3] = {};
     float* net_b[3] = {};
     uint16_t* net_x = nullptr;
@@ -960,10 +963,12 @@ int box_resid_sync(np_solver* s, int l, double* out)
 // is finite; otherwise the interpolated guess is restored.  *r is the max-norm
 // residual of the guess in effect on return.
 int learned_guess(np_solver* s, int l, const double* rho_l, double fourpiG, double fnorm, double rho, double* r,
-                  int* used)
+                  int* used, int* ran)
 {
     *used = 0;
+    *ran = 0;
     if (!s->have_weights || !(fnorm > 0.0) || !std::isfinite(*r)) return NP_OK;
+    *ran = 1;
     const np_config& c = s->cfg;
     hipStream_t st = s->stream;
     SGrid g = s->lg[l];
@@ -1264,6 +1269,7 @@ void nested_poisson_default_config(np_config* c)
     c->guess = NP_GUESS_INTERP;
     c->buffer = NP_BUFFER_RELAXED;
     c->batch = 1;
+    c->guess_gate = 1;
     for (int l = 0; l < NP_MAX_LEVELS; l++) c->parent[l] = l - 1;
 }
 
@@ -1509,15 +1515,21 @@ int nested_poisson_solve(np_solver* s, const double* const* rho, const double* p
         // f - lap phi in FP32, the source of the level's first scaled defect
         // (unless the learned guess changes phi after it)
         const bool dc = c.precision != NP_PREC_FP64;
-        const bool r32_start = dc && c.guess != NP_GUESS_LEARNED;
+        // the learned guess runs unless it was found not to pay on this level
+        const bool net = l > 0 && c.guess == NP_GUESS_LEARNED && s->have_weights && !(c.guess_gate && s->guess_off[l]);
+        const bool r32_start = dc && !net;
         double r = 0.0;
         rc = r32_start ? dc_first_residual(s, l, &r) : norm_sync(s, l, 0, &r);
         if (rc) return rc;
         st.interp_rel_residual[l] = scale > 0 ? r / scale : r;
-        if (l > 0 && c.guess == NP_GUESS_LEARNED) {
-            const double rho_p = s->rho_meas[c.parent[l]] > 0.0 ? s->rho_meas[c.parent[l]] : kAdaptiveRho0;
-            rc = learned_guess(s, l, rho[l], fourpiG, fnorm, rho_p, &r, &st.learned_used[l]);
+        const double rho_p = l > 0 && s->rho_meas[c.parent[l]] > 0.0 ? s->rho_meas[c.parent[l]] : kAdaptiveRho0;
+        double t_guess = 0.0;
+        if (net) {
+            const auto tg = std::chrono::steady_clock::now();
+            rc = learned_guess(s, l, rho[l], fourpiG, fnorm, rho_p, &r, &st.learned_used[l], &st.learned_ran[l]);
             if (rc) return rc;
+            t_guess = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tg).count();
+            st.guess_ms[l] = t_guess;
             st.guess_box_ratio[l] = s->guess_box_ratio[l];
         }
         double Fdelta = 0.0;
@@ -1639,6 +1651,18 @@ int nested_poisson_solve(np_solver* s, const double* const* rho, const double* p
         st.initial_rel_residual[l] = s->hist[l].front();
         st.final_rel_residual[l] = scale > 0 ? r / scale : r;
         st.level_ms[l] = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        if (net && c.guess_gate) {
+            // V-cycles the kept guess is predicted to save (its restricted
+            // residual over the interpolated guess's, in contractions of one
+            // cycle, the keep test's terms) at this level's time per cycle,
+            // against the time the learned guess took
+            const double ratio = st.guess_box_ratio[l];
+            double n_save = 0.0;
+            if (st.learned_used[l] && ratio > 0.0 && ratio < 1.0 && rho_p > 0.0 && rho_p < 1.0)
+                n_save = std::log(ratio) / std::log(rho_p);
+            const double per_cycle = q > 0 ? (st.level_ms[l] - t_guess) / q : 0.0;
+            if (!(n_save * per_cycle > t_guess)) s->guess_off[l] = true;
+        }
         if (lvl == NP_ENONFINITE || lvl == NP_EDIVERGED) {
             if (stats) *stats = st;
             return set_err(s, lvl, "level %d: %s after %d cycles", l,
@@ -1787,6 +1811,7 @@ int nested_poisson_set_guess_weights(np_solver* s, const void* blob, size_t nbyt
     }
     HIPCHK(s, hipStreamSynchronize(s->stream));
     s->have_weights = true;
+    for (int l = 0; l < NP_MAX_LEVELS; l++) s->guess_off[l] = false;
     return NP_OK;
 }
 

@@ -72,6 +72,8 @@ class NestedPoissonSolver:
             interp_rel_residual=[st.interp_rel_residual[l] for l in range(L)],
             outer_steps=[st.outer_steps[l] for l in range(L)],
             guess_box_ratio=[st.guess_box_ratio[l] for l in range(L)],
+            learned_ran=[st.learned_ran[l] for l in range(L)],
+            guess_ms=[st.guess_ms[l] for l in range(L)],
         )
         return self.last_stats
 

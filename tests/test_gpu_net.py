@@ -332,3 +332,50 @@ def test_trained_network_gain(precision):
     print("%s, refined levels of 4 held-out seeds: V-cycles %d (interpolated guess) vs %d (learned, kept on %d of "
           "8 levels); host time %.1f vs %.1f ms; restricted-residual ratios %s"
           % (precision, tot0, tot1, kept, ms0, ms1, ", ".join("%.2f" % x for x in ratios)))
+
+
+@pytest.mark.skipif(not os.path.exists(learned.DEFAULT_WEIGHTS), reason="no trained weights in the tree")
+@pytest.mark.parametrize("precision", ["fp64", "fp16s_dc"])
+def test_guess_gate(precision):
+    """The cost gate of the learned guess: the network runs on every refined
+    level in a handle's first solve; a level where the guess did not save more
+    V-cycle time than it took skips the network in later solves, and a solve
+    that skips it everywhere equals the interpolated-guess solve bit for bit
+    (the same start, the same iterates); new weights re-arm every level;
+    guess_gate = 0 runs the network in every solve."""
+    theta = learned.load_weights()
+    wl = W.c4_multi_plummer(200002, N=64)
+    L = wl.geom.nlevels
+    kw = dict(precision=precision, inner_cycles="adaptive") if precision != "fp64" else {}
+    rho, po = W.make_inputs(wl.geom, wl.prob, device="cuda")
+    plain = NestedPoissonSolver(wl.geom, **kw)
+    st0 = plain.solve(rho, po)
+    phi0 = [plain.potential(l).cpu().numpy() for l in range(L)]
+    plain.close()
+    s = NestedPoissonSolver(wl.geom, guess="learned", **kw)
+    s.set_guess_weights(theta)
+    st1 = s.solve(rho, po)
+    assert st1["learned_ran"] == [0] + [1] * (L - 1)
+    assert all(st1["guess_ms"][l] > 0 for l in range(1, L))
+    st2 = s.solve(rho, po)
+    phi2 = [s.potential(l).cpu().numpy() for l in range(L)]
+    print("%s: network ran on levels %s then %s; guess host ms %s; cycles %s / %s / plain %s"
+          % (precision, st1["learned_ran"], st2["learned_ran"], ["%.2f" % x for x in st1["guess_ms"]],
+             st1["cycles"], st2["cycles"], st0["cycles"]))
+    for l in range(1, L):
+        # a level keeps running the network only where its guess was kept
+        assert st2["learned_ran"][l] <= st1["learned_used"][l]
+    if not any(st2["learned_ran"]):
+        assert st2["cycles"] == st0["cycles"]
+        for l in range(L):
+            assert np.array_equal(phi2[l], phi0[l]), l
+    for l in range(L):
+        assert np.abs(phi2[l] - phi0[l]).max() <= 1e-8 * np.abs(phi0[l]).max()
+    s.set_guess_weights(theta)
+    assert s.solve(rho, po)["learned_ran"] == [0] + [1] * (L - 1)
+    s.close()
+    s = NestedPoissonSolver(wl.geom, guess="learned", guess_gate=False, **kw)
+    s.set_guess_weights(theta)
+    for _ in range(2):
+        assert s.solve(rho, po)["learned_ran"] == [0] + [1] * (L - 1)
+    s.close()
