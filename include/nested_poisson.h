@@ -145,12 +145,18 @@ typedef struct np_config {
                                        the interpolated guess without running the network
                                        (nested_poisson_set_guess_weights re-arms every level).
                                        0: the network runs in every solve */
+    int coarse_post;                /* post-smoothing sweeps on the multigrid levels below level 0
+                                       (the coarse part of every V-cycle, coarse tail included),
+                                       0..16; -1 (default): n_post.  The defect correction's inner
+                                       V-cycles only precondition its FP64 iteration, so their
+                                       schedule is free; the FP64 V-cycle of Sec. 2.3 is V(n_pre,
+                                       n_post) on every level */
 } np_config;
 
 /* Fills `cfg` with the paper's solver settings (N_pre = 2, N_post = 1,
  * Sec. 3) and tol = 1e-10, max_cycles = 50, FP64, residual stop,
  * interpolated guess, relaxed buffer, parent[l] = l - 1, batch = 1,
- * guess_gate = 1.  The other
+ * guess_gate = 1, coarse_post = -1.  The other
  * geometry fields (extent included: cubic patches) are zeroed. */
 void nested_poisson_default_config(np_config* cfg);
 

@@ -52,6 +52,7 @@ class NpConfig(ctypes.Structure):
         ("batch", ctypes.c_int),
         ("sweep", ctypes.c_int),
         ("guess_gate", ctypes.c_int),
+        ("coarse_post", ctypes.c_int),
     ]
 
 
@@ -162,7 +163,8 @@ class NestedPoissonError(RuntimeError):
 
 
 def make_config(geom, n_pre=2, n_post=1, tol=1e-10, max_cycles=50, stop_rule="residual", precision="fp64",
-                inner_cycles=1, guess="interp", buffer="relaxed", batch=True, sweep="full", guess_gate=True):
+                inner_cycles=1, guess="interp", buffer="relaxed", batch=True, sweep="full", guess_gate=True,
+                coarse_post=None):
     """np_config from a geometry (attributes dim, n, off, dx0, G) and solver settings."""
     c = NpConfig()
     lib().nested_poisson_default_config(ctypes.byref(c))
@@ -191,6 +193,7 @@ def make_config(geom, n_pre=2, n_post=1, tol=1e-10, max_cycles=50, stop_rule="re
     c.batch = 1 if batch else 0
     c.sweep = SWEEPS[sweep] if isinstance(sweep, str) else int(sweep)
     c.guess_gate = 1 if guess_gate else 0
+    c.coarse_post = -1 if coarse_post is None else int(coarse_post)
     parent = getattr(geom, "parent", None)
     if parent is not None:
         for l, p in enumerate(parent):

@@ -96,6 +96,7 @@ bool validate(const np_config* c, char* why, size_t nwhy)
                     "rule only");
     if (c->batch != 0 && c->batch != 1) return fail("batch must be 0 or 1 (got %d)", c->batch);
     if (c->guess_gate != 0 && c->guess_gate != 1) return fail("guess_gate must be 0 or 1 (got %d)", c->guess_gate);
+    if (c->coarse_post < -1 || c->coarse_post > 16) return fail("coarse_post must be -1..16 (got %d)", c->coarse_post);
     if (c->sweep != NP_SWEEP_FULL && c->sweep != NP_SWEEP_HALF && c->sweep != NP_SWEEP_FUSED)
         return fail("bad sweep %d", c->sweep);
     return true;
@@ -521,6 +522,7 @@ void coarse_part(const np_solver* s, int l, const MGView<T>& v, hipStream_t st)
     const np_config& c = s->cfg;
     const int d = c.dim;
     const int Lt = tail_level(s, l, sizeof(T));
+    const int npost = c.coarse_post >= 0 ? c.coarse_post : c.n_post;  // post-smoothing below level 0
     auto tail = [&](int L0) {
         const int nlev = s->plan.nmg[l] - L0;
         double h[kTailMaxLevels];
@@ -529,7 +531,7 @@ void coarse_part(const np_solver* s, int l, const MGView<T>& v, hipStream_t st)
             rules[a] = rule_of(s, l, L0 + a);
             h[a] = v.h[L0 + a];
         }
-        launch_coarse_tail<T>(d, st, nlev, &s->plan.N[l][L0], h, rules, c.n_pre, c.n_post, v.g[L0], v.f[L0],
+        launch_coarse_tail<T>(d, st, nlev, &s->plan.N[l][L0], h, rules, c.n_pre, npost, v.g[L0], v.f[L0],
                               v.u[L0]);
     };
     if (Lt == 1) {
@@ -554,7 +556,7 @@ void coarse_part(const np_solver* s, int l, const MGView<T>& v, hipStream_t st)
     }
     while (L > 1) {
         launch_prolong_add<T, T>(d, st, v.g[L], v.u[L], v.g[L - 1], v.u[L - 1], 0, rule_of(s, l, L));
-        for (int it = 0; it < c.n_post; it++) coarse_sweep(s, l, v, L - 1, st);
+        for (int it = 0; it < npost; it++) coarse_sweep(s, l, v, L - 1, st);
         L--;
     }
 }
@@ -1270,6 +1272,7 @@ void nested_poisson_default_config(np_config* c)
     c->buffer = NP_BUFFER_RELAXED;
     c->batch = 1;
     c->guess_gate = 1;
+    c->coarse_post = -1;
     for (int l = 0; l < NP_MAX_LEVELS; l++) c->parent[l] = l - 1;
 }
 

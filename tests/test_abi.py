@@ -109,7 +109,7 @@ def _bad(**kw):
     dict(off=(2, 2, 9)), dict(dx0=0.0), dict(tol=-1.0), dict(max_cycles=0), dict(max_cycles=100000),
     dict(n_pre=-1), dict(stop_rule=7), dict(inner_cycles=-1), dict(inner_cycles=9), dict(buffer=2),
     dict(buffer=1, precision=1), dict(buffer=1, precision=2), dict(buffer=1, guess=1), dict(buffer=1, stop_rule=1),
-    dict(sweep=3), dict(sweep=-1), dict(batch=2), dict(guess_gate=2), dict(guess_gate=-1),
+    dict(sweep=3), dict(sweep=-1), dict(batch=2), dict(guess_gate=2), dict(guess_gate=-1), dict(coarse_post=-2), dict(coarse_post=17),
 ], ids=lambda k: ",".join("%s=%s" % kv for kv in k.items()))
 def test_invalid_geometry_rejected_before_any_device_call(kw):
     cfg = _bad(**kw)
@@ -179,12 +179,13 @@ def test_default_parents_are_the_stack():
 
 
 def test_default_settings():
-    """The defaults the header states: the paper's V(2,1), tol 1e-10, 50 cycles,
-    FP64, full sweeps, batched patches and the learned guess's cost gate on."""
+    """The defaults the header states: the paper's V(2,1) on every level, tol
+    1e-10, 50 cycles, FP64, full sweeps, batched patches and the learned guess's
+    cost gate on."""
     cfg = _lib.NpConfig()
     _lib.lib().nested_poisson_default_config(ctypes.byref(cfg))
     assert (cfg.n_pre, cfg.n_post, cfg.tol, cfg.max_cycles) == (2, 1, 1e-10, 50)
-    assert (cfg.precision, cfg.sweep, cfg.batch, cfg.guess_gate) == (0, _lib.SWEEPS["full"], 1, 1)
+    assert (cfg.precision, cfg.sweep, cfg.batch, cfg.guess_gate, cfg.coarse_post) == (0, _lib.SWEEPS["full"], 1, 1, -1)
     assert _lib.make_config(W.c2_plummer(16).geom).guess_gate == 1
     assert _lib.make_config(W.c2_plummer(16).geom, guess_gate=False).guess_gate == 0
 

@@ -331,3 +331,26 @@ def test_dc_configured_size_plummer_offset(precision, n_pre):
     e64 = _linf_force_error(wl, F64)
     e = _linf_force_error(wl, F)
     assert abs(e - e64) <= 5e-3 * e64, (e, e64)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_dc", "fp16s_dc"])
+def test_coarse_post_smoothing(precision):
+    """V(1,1) on multigrid level 0 with two post-smoothing sweeps on the levels
+    below (np_config.coarse_post, the benchmark's fastest inner-cycle
+    schedule): the solve reaches the oracle's converged solution at the bar
+    above on an offset patch stack and on 16^3 levels (most coarse levels in
+    the single-workgroup tail, which takes the count too), and coarse_post =
+    n_post is the default schedule bit for bit."""
+    kw = dict(n_pre=1, n_post=1)
+    if precision != "fp64":
+        kw.update(precision=precision, inner_cycles="adaptive")
+    for wl in (W.c3_plummer_offset(32), W.c2_plummer(16)):
+        phi, F, st = _solve(wl, coarse_post=2, **kw)
+        assert all(r <= 1e-10 for r in st["final_rel_residual"])
+        _assert_close_to_oracle(wl, phi, _oracle_phi(wl))
+    wl = W.c2_plummer(32)
+    a = _solve(wl, coarse_post=1, **kw)
+    b = _solve(wl, **kw)
+    assert a[2]["cycles"] == b[2]["cycles"]
+    for l in range(wl.geom.nlevels):
+        assert np.array_equal(a[0][l], b[0][l])
