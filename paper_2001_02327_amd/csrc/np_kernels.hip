@@ -2111,24 +2111,6 @@ __global__ void __launch_bounds__(kBlock) k_restrict3_l0(const TF* __restrict__ 
 // measured slower than k_restrict3_l0 (325 vs 278 us, 597 vs 537 us).
 constexpr int kRestrictPairChunk = 4;  // coarse planes per thread
 
-template <typename T>
-__device__ __forceinline__ T next_first(const Pair<T>& p);
-template <>
-__device__ __forceinline__ __half next_first(const Pair<__half>& p)
-{
-    return __builtin_bit_cast(__half, (uint16_t)(dpp_next(__builtin_bit_cast(uint32_t, p)) & 0xffffu));
-}
-template <>
-__device__ __forceinline__ float next_first(const Pair<float>& p)
-{
-    return dpp_next(p.a);
-}
-template <>
-__device__ __forceinline__ double next_first(const Pair<double>& p)
-{
-    return dpp_next(p.a);
-}
-
 // One fine row of a pair of coarse points in packed FP16 words: x = 2 h0 + m
 // for m = 0..5 is the lower (m = 0, 1, 4, 5) or upper (m = 2, 3) half of A (even
 // x = 2 h0, 2 h0 + 2), B (odd x), An and Bn (the next lane's A and B: x =
