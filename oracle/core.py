@@ -34,6 +34,7 @@ class OrcConfig(ctypes.Structure):
         ("ghost_literal", ctypes.c_int),
         ("buffer_interp", ctypes.c_int),
         ("parent", ctypes.c_int * MAXLEV),
+        ("coarse_post", ctypes.c_int),
     ]
 
 
@@ -223,7 +224,7 @@ STATUS = {0: "ok", -1: "invalid", -2: "nonfinite", -3: "not converged", -4: "div
 
 
 def make_config(geom, n_pre=2, n_post=1, tol=1e-10, max_cycles=50, stop_rule=0, ghost_literal=False,
-                buffer_interp=False):
+                buffer_interp=False, coarse_post=None):
     c = OrcConfig()
     c.dim = geom.dim
     c.nlevels = geom.nlevels
@@ -241,6 +242,7 @@ def make_config(geom, n_pre=2, n_post=1, tol=1e-10, max_cycles=50, stop_rule=0, 
     c.stop_rule = stop_rule
     c.ghost_literal = int(ghost_literal)
     c.buffer_interp = int(buffer_interp)
+    c.coarse_post = -1 if coarse_post is None else int(coarse_post)
     parent = getattr(geom, "parent", None)
     for l in range(geom.nlevels):
         c.parent[l] = int(parent[l]) if parent is not None else l - 1

@@ -51,6 +51,8 @@ typedef struct {
     int parent[ORC_MAXLEV];     /* l>=1: the patch Omega^l is refined out of (earlier entry); the
                                    stack of Sec. 2.1 has parent[l] = l-1, a tree gives several
                                    disjoint patches per level */
+    int coarse_post;            /* post-smoothing sweeps on multigrid levels L >= 1; -1: n_post
+                                   (Sec. 2.3 smooths every level alike) */
 } orc_config;
 
 /* refinement depth of entry l: number of parent links down to the base level */
@@ -383,7 +385,10 @@ static size_t mg_points(int dim, const int *N)
     return npts(q);
 }
 
-static void vcycle(orc_mg *m, int n_pre, int n_post)
+/* One V-cycle (Sec. 2.3 steps 2-13): n_pre sweeps before the restriction on
+ * every level, n_post after the prolongation on level 0 and n_post_coarse on
+ * the levels below it. */
+static void vcycle(orc_mg *m, int n_pre, int n_post, int n_post_coarse)
 {
     int d = m->dim;
     for (int s = 0; s < n_pre; s++) orc_rb_sweep(d, m->N0, 0, m->N[0], m->h[0], m->u[0], m->f[0], m->literal);
@@ -400,7 +405,7 @@ static void vcycle(orc_mg *m, int n_pre, int n_post)
     while (L > 0) {
         orc_ghost_fill(d, m->N0, L, m->N[L], m->u[L], m->literal);
         orc_prolong_add(d, m->N[L], m->u[L], m->N[L - 1], m->u[L - 1]);
-        for (int s = 0; s < n_post; s++)
+        for (int s = 0; s < (L - 1 > 0 ? n_post_coarse : n_post); s++)
             orc_rb_sweep(d, m->N0, L - 1, m->N[L - 1], m->h[L - 1], m->u[L - 1], m->f[L - 1], m->literal);
         L--;
     }
@@ -715,7 +720,7 @@ int orc_solve(const orc_config *cfg, const double *const *rho, const double *phi
                     break;
                 }
                 if (q >= cfg->max_cycles) { lvl_status = -3; break; }
-                vcycle(&m, cfg->n_pre, cfg->n_post);
+                vcycle(&m, cfg->n_pre, cfg->n_post, cfg->coarse_post >= 0 ? cfg->coarse_post : cfg->n_post);
                 q++;
                 r = orc_residual_norm(d, m.N[0], m.h[0], us, fs);
                 if (hl && q <= cfg->max_cycles) hl[q] = scale > 0 ? r / scale : r;
@@ -775,7 +780,7 @@ int orc_vcycle_patch(int dim, const int *N0, double h0, double *u, const double 
         }
         m.r[L] = calloc(mm, sizeof(double));
     }
-    vcycle(&m, n_pre, n_post);
+    vcycle(&m, n_pre, n_post, n_post);
     for (int L = 0; L < m.nmg; L++) {
         if (L > 0) { free(m.u[L]); free(m.f[L]); }
         free(m.r[L]);

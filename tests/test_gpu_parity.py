@@ -160,6 +160,25 @@ def test_other_smoothing_counts(n_pre, n_post):
     assert_parity(wl, phi_g, F_g, res, F_o)
 
 
+@pytest.mark.parametrize("wl", [W.c2_plummer(16), _ragged3d(), W.paper2d(16)], ids=lambda w: w.name)
+def test_coarse_post_parity(wl):
+    """V(1,1) on multigrid level 0 with two post-smoothing sweeps below it
+    (np_config.coarse_post; the coarse tail takes the count too): the iterates
+    after one and two cycles on level 0 and at the oracle's own stop equal the
+    oracle's with the same schedule."""
+    L = wl.geom.nlevels
+    kw = dict(n_pre=1, n_post=1, coarse_post=2)
+    for k in (1, 2):
+        fixed = [k] + [min(k, 1)] * (L - 1)
+        res, F_o = oracle_solve(wl, fixed=fixed, **kw)
+        phi_g, F_g, st, _ = gpu_solve(wl, fixed=fixed, **kw)
+        assert_parity(wl, phi_g, F_g, res, F_o)
+    res, F_o = oracle_solve(wl, max_cycles=120, **kw)
+    assert res["status"] == 0
+    phi_g, F_g, st, _ = gpu_solve(wl, fixed=res["cycles"], max_cycles=120, **kw)
+    assert_parity(wl, phi_g, F_g, res, F_o)
+
+
 @pytest.mark.parametrize("dim", [2, 3])
 def test_linear_potential_zero_density(dim):
     """rho = 0, Phi linear: exact on every level (stop scale from the boundary residual)."""

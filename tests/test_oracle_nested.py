@@ -32,6 +32,30 @@ def test_multigrid_reaches_the_direct_solution(wl):
         assert err < 1e-11, (l, err)
 
 
+@pytest.mark.parametrize("wl", [W.paper2d(8), W.c2_plummer(8)], ids=lambda w: w.name)
+def test_coarse_post_schedule(wl):
+    """V(1,1) on multigrid level 0 with two post-smoothing sweeps on the levels
+    below it: the iteration still reaches the direct solution of the nested
+    system; coarse_post = n_post is the default schedule exactly; and the count
+    acts (one V-cycle of each schedule leaves different iterates)."""
+    rho, po = _inputs(wl)
+    res = core.solve(wl.geom, rho, po, n_pre=1, n_post=1, coarse_post=2, tol=1e-13, max_cycles=80)
+    assert res["status"] in (0, -3)
+    ex, _ = dense.solve(wl.geom, rho, po)
+    for l in range(wl.geom.nlevels):
+        err = np.abs(res["phi"][l] - ex[l]).max() / np.abs(ex[l]).max()
+        assert err < 1e-11, (l, err)
+    a = core.solve(wl.geom, rho, po, n_pre=1, n_post=1, coarse_post=1)
+    b = core.solve(wl.geom, rho, po, n_pre=1, n_post=1)
+    assert a["cycles"] == b["cycles"]
+    for l in range(wl.geom.nlevels):
+        assert np.array_equal(a["phi"][l], b["phi"][l])
+    one = [1] * wl.geom.nlevels
+    c1 = core.solve(wl.geom, rho, po, n_pre=1, n_post=1, fixed_cycles=one)
+    c2 = core.solve(wl.geom, rho, po, n_pre=1, n_post=1, coarse_post=2, fixed_cycles=one)
+    assert not np.array_equal(c1["phi"][0], c2["phi"][0])
+
+
 @pytest.mark.parametrize("dim", [2, 3])
 def test_sixteen_levels_reach_the_direct_solution(dim):
     """The deepest nesting a solve takes (16 levels of 8^d, spacings from 1/8 to
