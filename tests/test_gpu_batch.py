@@ -90,6 +90,24 @@ def test_batched_parity_with_oracle(wl):
         assert st2["final_rel_residual"][l] <= 1e-10
 
 
+@pytest.mark.parametrize("wl", [CASES[0], CASES[2]], ids=lambda w: w.name)
+def test_batched_coarse_post(wl):
+    """V(1,1) on multigrid level 0 with two post-smoothing sweeps below it
+    (np_config.coarse_post) on batched patches: equal to the one-after-another
+    solve bit for bit, and to the oracle with the same schedule at its own
+    per-entry cycle counts."""
+    kw = dict(n_pre=1, n_post=1, coarse_post=2)
+    res, F_o = oracle_solve(wl, max_cycles=120, **kw)
+    assert res["status"] == 0
+    a = _run(wl, fixed=res["cycles"], max_cycles=120, **kw)
+    b = _run(wl, fixed=res["cycles"], max_cycles=120, batch=False, **kw)
+    assert a[2]["cycles"] == res["cycles"]
+    assert_parity(wl, a[0], a[1], res, F_o)
+    for l in range(wl.geom.nlevels):
+        assert np.array_equal(a[0][l], b[0][l]), l
+        assert a[3][l] == b[3][l], l
+
+
 def test_batch_cap_and_error_codes():
     """A cap that stops every member early reports NP_ENOTCONV with valid
     results, as one patch at a time does."""
