@@ -88,7 +88,7 @@ def lib():
                                 _ip, _dp, _dp]
         L.orc_solve.restype = ctypes.c_int
         L.orc_vcycle_patch.argtypes = [ctypes.c_int, _i3, ctypes.c_double, _dp, _dp, ctypes.c_int,
-                                       ctypes.c_int, ctypes.c_int]
+                                       ctypes.c_int, ctypes.c_int, ctypes.c_int]
         L.orc_vcycle_patch.restype = ctypes.c_int
         L.orc_num_threads.restype = ctypes.c_int
         L.orc_set_threads.argtypes = [ctypes.c_int]
@@ -213,8 +213,9 @@ def set_threads(n):
     lib().orc_set_threads(int(n))
 
 
-def vcycle_patch(dim, h0, u, f, n_pre=2, n_post=1, literal=False):
-    rc = lib().orc_vcycle_patch(dim, _i3(_act(dim, u, 1)), h0, _p(u), _p(f), n_pre, n_post, int(literal))
+def vcycle_patch(dim, h0, u, f, n_pre=2, n_post=1, literal=False, coarse_post=None):
+    rc = lib().orc_vcycle_patch(dim, _i3(_act(dim, u, 1)), h0, _p(u), _p(f), n_pre, n_post,
+                                -1 if coarse_post is None else int(coarse_post), int(literal))
     if rc:
         raise RuntimeError("vcycle_patch failed")
 

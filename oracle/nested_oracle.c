@@ -762,8 +762,10 @@ done:
 /* Single-patch entry points used by the operator tests. */
 
 /* one V-cycle on a single patch with caller-provided level-0 arrays
- * (N0[a] + 2 points per axis: potential with fixed ghosts, and f) */
-int orc_vcycle_patch(int dim, const int *N0, double h0, double *u, const double *f, int n_pre, int n_post, int literal)
+ * (N0[a] + 2 points per axis: potential with fixed ghosts, and f); the levels
+ * below level 0 take n_post_coarse post-smoothing sweeps (-1: n_post) */
+int orc_vcycle_patch(int dim, const int *N0, double h0, double *u, const double *f, int n_pre, int n_post,
+                     int n_post_coarse, int literal)
 {
     orc_mg m;
     memset(&m, 0, sizeof m);
@@ -780,7 +782,7 @@ int orc_vcycle_patch(int dim, const int *N0, double h0, double *u, const double 
         }
         m.r[L] = calloc(mm, sizeof(double));
     }
-    vcycle(&m, n_pre, n_post, n_post);
+    vcycle(&m, n_pre, n_post, n_post_coarse >= 0 ? n_post_coarse : n_post);
     for (int L = 0; L < m.nmg; L++) {
         if (L > 0) { free(m.u[L]); free(m.f[L]); }
         free(m.r[L]);

@@ -3,9 +3,11 @@
 that bench.py times, checked where the oracle can follow at that size:
 
 * one V(2,1) cycle of level 0 from the zero start against the oracle's cycle on
-  the same 514^3 problem, at every point (1e-12 of max|Phi|, the parity bar);
+  the same 514^3 problem, at every point (1e-12 of max|Phi|, the parity bar),
+  and one cycle of the benchmark's schedule (V(1,1) on level 0, V(1,2) below);
 * the converged solves of the plain FP64 path and of the FP16-storage defect
-  correction with adaptive inner cycles: on every level the outer ghost layer
+  correction with adaptive inner cycles (V(2,1), and V(1,1) on level 0 with
+  V(1,2) below as the benchmark runs it): on every level the outer ghost layer
   equals the oracle's interpolation of the GPU's level l-1 (1e-14), the stop
   criterion recomputed by the oracle in FP64 over every active point holds
   (||f - lap Phi||_inf <= 1e-10 ||f||_inf, the right-hand side of levels l >= 1
@@ -33,10 +35,13 @@ def problem():
     return wl, rho, po
 
 
-def test_one_cycle_of_level0_at_514(problem):
+@pytest.mark.parametrize("schedule", [dict(), dict(n_pre=1, n_post=1, coarse_post=2)], ids=["v21", "v11_v12"])
+def test_one_cycle_of_level0_at_514(problem, schedule):
+    """One FP64 V-cycle of level 0 from the zero start, the paper's V(2,1) and
+    the benchmark's V(1,1) with V(1,2) below level 0."""
     wl, rho, po = problem
     g = wl.geom
-    s = NestedPoissonSolver(g)
+    s = NestedPoissonSolver(g, **schedule)
     s.set_fixed_cycles([1] + [0] * (g.nlevels - 1))
     s.solve([r.cuda() for r in rho], po.cuda())
     got = s.potential(0).cpu().numpy()
@@ -45,14 +50,16 @@ def test_one_cycle_of_level0_at_514(problem):
     u[1:-1, 1:-1, 1:-1] = 0.0
     f = np.zeros_like(u)
     f[1:-1, 1:-1, 1:-1] = 4 * math.pi * g.G * rho[0].numpy()
-    core.vcycle_patch(3, g.dx0, u, f)
+    core.vcycle_patch(3, g.dx0, u, f, **schedule)
     err = np.abs(got - u).max() / np.abs(u).max()
-    print("one level-0 V-cycle at 514^3: max relative difference %.2e" % err)
+    print("one level-0 V-cycle at 514^3 (%s): max relative difference %.2e" % (schedule, err))
     assert err <= 1e-12
 
 
-@pytest.mark.parametrize("settings", [dict(), dict(precision="fp16s_dc", inner_cycles="adaptive")],
-                         ids=["fp64", "fp16s_dc_adaptive"])
+@pytest.mark.parametrize("settings", [dict(), dict(precision="fp16s_dc", inner_cycles="adaptive"),
+                                      dict(precision="fp16s_dc", inner_cycles="adaptive", n_pre=1, n_post=1,
+                                           coarse_post=2)],
+                         ids=["fp64", "fp16s_dc_adaptive", "fp16s_dc_v11_v12"])
 def test_converged_solve_at_514(problem, settings):
     wl, rho, po = problem
     g = wl.geom
