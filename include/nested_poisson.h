@@ -89,7 +89,9 @@ extern "C" {
                                residual stop rule only */
 
 /* How multigrid level 0 of a 3-D FP64 solve is smoothed (np_config.sweep).
- * NP_SWEEP_FULL: each red-black sweep is one pass from the level's potential
+ * NP_SWEEP_FULL: on level grids of at least 2^24 points (about 256^3 cells;
+ * below that the half sweeps, which occupy the chip better, run), each
+ * red-black sweep is one pass from the level's potential
  * into a second buffer (the handle's; the buffers then trade roles), and the
  * stop test's residual norm is taken inside the sweeps: over the black points
  * by the last post-smoothing sweep, over the red points by the next cycle's
@@ -97,15 +99,17 @@ extern "C" {
  * the level stops (needs n_pre >= 1 and n_post >= 1, the relaxed buffer on
  * levels l >= 1 and a level solved on its own; elsewhere the half sweeps run).
  * NP_SWEEP_HALF: two half sweeps in place and a separate residual pass.
+ * NP_SWEEP_FULL_ALL: as NP_SWEEP_FULL on every level, whatever its size.
  * NP_SWEEP_FUSED: as NP_SWEEP_FULL, and in the defect correction with 2-byte
  * storage (3-D) the last pre-smoothing black half sweep of multigrid level 0
  * runs inside the restriction that follows it (Sec. 2.3 steps 2-5 in one pass;
  * needs N^0 = 2 N^1 along every axis and an odd N^1_x, elsewhere they run
  * apart).  On MI355X this pass is slower than the two kernels it replaces, so
- * it is not the default.  The iterates are the same in all three. */
+ * it is not the default.  The iterates are the same in all four. */
 #define NP_SWEEP_FULL 0
 #define NP_SWEEP_HALF 1
 #define NP_SWEEP_FUSED 2
+#define NP_SWEEP_FULL_ALL 3
 
 typedef struct np_config {
     int dim;                        /* 2 or 3 */

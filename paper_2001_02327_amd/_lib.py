@@ -27,7 +27,7 @@ STOP_RULES = {"residual": 0, "force_delta": 1}
 PRECISIONS = {"fp64": 0, "fp32_dc": 1, "fp16s_dc": 2}
 GUESSES = {"interp": 0, "learned": 1}
 BUFFERS = {"relaxed": 0, "interp": 1}
-SWEEPS = {"full": 0, "half": 1, "fused": 2}
+SWEEPS = {"full": 0, "half": 1, "fused": 2, "full_all": 3}
 
 
 class NpConfig(ctypes.Structure):

@@ -97,7 +97,8 @@ bool validate(const np_config* c, char* why, size_t nwhy)
     if (c->batch != 0 && c->batch != 1) return fail("batch must be 0 or 1 (got %d)", c->batch);
     if (c->guess_gate != 0 && c->guess_gate != 1) return fail("guess_gate must be 0 or 1 (got %d)", c->guess_gate);
     if (c->coarse_post < -1 || c->coarse_post > 16) return fail("coarse_post must be -1..16 (got %d)", c->coarse_post);
-    if (c->sweep != NP_SWEEP_FULL && c->sweep != NP_SWEEP_HALF && c->sweep != NP_SWEEP_FUSED)
+    if (c->sweep != NP_SWEEP_FULL && c->sweep != NP_SWEEP_HALF && c->sweep != NP_SWEEP_FUSED &&
+        c->sweep != NP_SWEEP_FULL_ALL)
         return fail("bad sweep %d", c->sweep);
     return true;
 }
@@ -681,11 +682,21 @@ int vcycle(np_solver* s, int l)
 }
 
 // Whether nested level l (solved on its own) runs full sweeps on multigrid level 0.
+// On small grids the full sweep's threads (a pair of columns times kFsPairRows
+// rows times a 16-plane chunk each) do not fill the chip: the paper's 3 x 128^3
+// stack took 15.2 ms per solve with full sweeps and 8.6 ms with half sweeps,
+// eight 64^3 patches one after another 46.7 and 27.3 ms; from 256^3 on the two
+// are alike and at 512^3 the full sweeps win.
+constexpr size_t kFullSweepMinPoints = size_t(1) << 24;
+
 bool full_sweeps(const np_solver* s, int l)
 {
     const np_config& c = s->cfg;
-    return c.dim == 3 && c.precision == NP_PREC_FP64 && c.sweep != NP_SWEEP_HALF && s->phi_alt && c.n_pre >= 1 &&
-           c.n_post >= 1 && !(l > 0 && c.buffer == NP_BUFFER_INTERP);
+    const SGrid& g = s->lg[l];
+    const bool big = (size_t)g.nx * g.ny * g.nz >= kFullSweepMinPoints;
+    return c.dim == 3 && c.precision == NP_PREC_FP64 && c.sweep != NP_SWEEP_HALF &&
+           (big || c.sweep == NP_SWEEP_FULL_ALL) && s->phi_alt && c.n_pre >= 1 && c.n_post >= 1 &&
+           !(l > 0 && c.buffer == NP_BUFFER_INTERP);
 }
 
 // One full sweep of level l's multigrid level 0 from the potential into the

@@ -109,7 +109,7 @@ def _bad(**kw):
     dict(off=(2, 2, 9)), dict(dx0=0.0), dict(tol=-1.0), dict(max_cycles=0), dict(max_cycles=100000),
     dict(n_pre=-1), dict(stop_rule=7), dict(inner_cycles=-1), dict(inner_cycles=9), dict(buffer=2),
     dict(buffer=1, precision=1), dict(buffer=1, precision=2), dict(buffer=1, guess=1), dict(buffer=1, stop_rule=1),
-    dict(sweep=3), dict(sweep=-1), dict(batch=2), dict(guess_gate=2), dict(guess_gate=-1), dict(coarse_post=-2), dict(coarse_post=17),
+    dict(sweep=4), dict(sweep=-1), dict(batch=2), dict(guess_gate=2), dict(guess_gate=-1), dict(coarse_post=-2), dict(coarse_post=17),
 ], ids=lambda k: ",".join("%s=%s" % kv for kv in k.items()))
 def test_invalid_geometry_rejected_before_any_device_call(kw):
     cfg = _bad(**kw)

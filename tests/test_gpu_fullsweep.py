@@ -1,5 +1,6 @@
-"""Full red-black sweeps on multigrid level 0 (3-D FP64, NP_SWEEP_FULL, the
-default) against the half sweeps in place (NP_SWEEP_HALF).
+"""Full red-black sweeps on multigrid level 0 (3-D FP64: NP_SWEEP_FULL, the
+default, on level grids of at least 2^24 points; NP_SWEEP_FULL_ALL on every
+level) against the half sweeps in place (NP_SWEEP_HALF).
 
 A full sweep relaxes the red points and then the black ones in one pass from
 the potential into a second buffer, with the arithmetic of the two half
@@ -20,11 +21,14 @@ from paper_2001_02327_amd.solver import NestedPoissonSolver
 pytestmark = pytest.mark.gpu
 
 
-def _solve(wl, **kw):
+def _solve(wl, profile=False, **kw):
     dev = torch.device("cuda")
     rho, po = W.make_inputs(wl.geom, wl.prob, device=dev)
     s = NestedPoissonSolver(wl.geom, **kw)
+    if profile:
+        s.set_profiling(True)
     st = s.solve(rho, po)
+    st["profile"] = s.profile() if profile else None
     phi = [s.potential(l).cpu().numpy() for l in range(wl.geom.nlevels)]
     F = [tuple(a.cpu().numpy() for a in s.forces(l)) for l in range(wl.geom.nlevels)]
     hist = [s.history(l) for l in range(wl.geom.nlevels)]
@@ -61,7 +65,7 @@ def _assert_same(a, b):
 
 @pytest.mark.parametrize("wl", CASES, ids=lambda w: w.name)
 def test_full_equals_half_sweeps(wl):
-    full = _solve(wl, sweep="full")
+    full = _solve(wl, sweep="full_all")
     half = _solve(wl, sweep="half")
     _assert_same(full, half)
 
@@ -70,26 +74,40 @@ def test_full_equals_half_sweeps(wl):
 def test_full_equals_half_other_schedules(pre_post):
     wl = W.c2_plummer(32)
     n_pre, n_post = pre_post
-    _assert_same(_solve(wl, sweep="full", n_pre=n_pre, n_post=n_post),
+    _assert_same(_solve(wl, sweep="full_all", n_pre=n_pre, n_post=n_post),
                  _solve(wl, sweep="half", n_pre=n_pre, n_post=n_post))
 
 
 def test_full_equals_half_force_change_rule():
     wl = W.paper3d(32)
-    _assert_same(_solve(wl, sweep="full", stop_rule="force_delta"), _solve(wl, sweep="half", stop_rule="force_delta"))
+    _assert_same(_solve(wl, sweep="full_all", stop_rule="force_delta"), _solve(wl, sweep="half", stop_rule="force_delta"))
 
 
 def test_full_equals_half_patch_tree_and_interp_buffer():
     """A tree solved one patch after another, and the comparison scheme (whose
     refined levels keep the half sweeps)."""
     wl = W.two_patch_3d(32)
-    _assert_same(_solve(wl, sweep="full", batch=False), _solve(wl, sweep="half", batch=False))
+    _assert_same(_solve(wl, sweep="full_all", batch=False), _solve(wl, sweep="half", batch=False))
     wl = W.c2_plummer(32)
-    _assert_same(_solve(wl, sweep="full", buffer="interp"), _solve(wl, sweep="half", buffer="interp"))
+    _assert_same(_solve(wl, sweep="full_all", buffer="interp"), _solve(wl, sweep="half", buffer="interp"))
 
 
 def test_full_equals_half_at_size():
     """Five levels of 128^3 (130^3 points on multigrid level 0: several z-chunks
     and row groups per block, ragged last chunk)."""
     wl = W.c5_two_plummer(N=128)
-    _assert_same(_solve(wl, sweep="full"), _solve(wl, sweep="half"))
+    _assert_same(_solve(wl, sweep="full_all"), _solve(wl, sweep="half"))
+
+
+def test_default_takes_full_sweeps_on_large_levels_only():
+    """The default sweep setting runs full sweeps on a level of 260^3 points
+    (2 x 256^3) and half sweeps on one of 132^3 (3 x 128^3), with the iterates
+    of the half sweeps in both."""
+    big = W.c5_two_plummer(N=256, nlevels=2)
+    full = _solve(big, profile=True)
+    half = _solve(big, sweep="half")
+    _assert_same(full, half)
+    assert full[2]["profile"]["full"][0] > 0
+    small = W.c2_plummer(128)
+    st = _solve(small, profile=True)[2]
+    assert st["profile"]["full"][0] == 0 and st["profile"]["smooth"][0] > 0
