@@ -3278,8 +3278,9 @@ __global__ void __launch_bounds__(kBlock) k_dc_outer3(SGrid g, DcIn<TL, UPD> in,
 // Paired form of k_dc_outer3 (row length hx even): a thread owns the compact
 // points h0 = 2 hp and h0 + 1 of both colours and moves each pair of the
 // potential with one 16-byte access and each pair of e, r with one 2- or
-// 4-byte access; the extra x-neighbour (h0 - 1 or h0 + 2) is a single load.
-// Same arithmetic per point as k_dc_outer3.
+// 4-byte access; the extra x-neighbour (h0 - 1 or h0 + 2) is a single load,
+// or, in the pass without the update, comes from the adjacent lane by a DPP
+// shift (a load at a wave's edge).  Same arithmetic per point as k_dc_outer3.
 template <typename TL, bool UPD>
 __device__ __forceinline__ Pair<double> dc_pair(const DcIn<TL, UPD>& in, size_t i)
 {
@@ -3294,6 +3295,11 @@ __device__ __forceinline__ Pair<double> dc_pair(const DcIn<TL, UPD>& in, size_t 
 
 constexpr int kDcChunk = 8;  // planes per thread of the paired DC pass (aligned layout: 2, 4, 8 give 1.02, 0.93, 0.91 ms)
 constexpr int kDcGroup = 2;  // planes of the DC pass whose loads are issued together (1, 2, 4 measured alike)
+// residual pass without the update (UPD = false): extra x-neighbour from the
+// adjacent lane, edge lanes load it (611 -> 587 us at 514^3); with the update
+// the shifts measured slower (881 -> 945 us) and the load stays
+template <bool UPD>
+constexpr bool kDcDppExtra = !UPD;
 
 // OUT = false: only the max norm of the residual (the stop test's residual
 // pass), no outputs.  eout == nullptr: the next correction's start is not
@@ -3317,6 +3323,7 @@ __global__ void __launch_bounds__(kBlock) k_dc_outer3_pair(SGrid g, DcIn<TL, UPD
     const int lb = (int)xcd_block();
     const int zc = lb / pblocks;
     const int t = (lb - zc * pblocks) * kBlock + (int)threadIdx.x;
+    const int lane = (int)(threadIdx.x & 63);
     unsigned long long best = 0;
     // flat pair index over the whole (padded) plane, as in k_smooth_zmarch3_pair
     const int q = 2 * t;
@@ -3348,9 +3355,13 @@ __global__ void __launch_bounds__(kBlock) k_dc_outer3_pair(SGrid g, DcIn<TL, UPD
                 d.fv[c] = kDcLoadNt ? load_nt((const Pair<double>*)(f + c * cs + here))
                                     : *(const Pair<double>*)(f + c * cs + here);
                 // the extra x-neighbour of colour c's points (other colour o), inside
-                // the plane (neighbouring row at the row ends)
+                // the plane (neighbouring row at the row ends); with kDcDppExtra<UPD>
+                // only a wave's edge lane loads it, the others take it from the
+                // adjacent lane's pair in step
                 const int par = (c + pj + pk + 3) & 1;
-                d.ex[c] = in((c ^ 1) * cs + (par ? here + 2 : here - 1));
+                d.ex[c] = 0.0;
+                if (!kDcDppExtra<UPD> || (par ? lane == 63 : lane == 0))
+                    d.ex[c] = in((c ^ 1) * cs + (par ? here + 2 : here - 1));
             }
         };
         auto step = [&](int pk, const Plane& d) {
@@ -3360,7 +3371,15 @@ __global__ void __launch_bounds__(kBlock) k_dc_outer3_pair(SGrid g, DcIn<TL, UPD
                 const int par = (c + pj + pk + 3) & 1;
                 const int pi0 = 2 * h0 + par;
                 const bool a0 = pi0 >= 1, a1 = pi0 + 2 <= g.nx - 2;
-                const double ex = d.ex[c];
+                double ex = d.ex[c];
+                if (kDcDppExtra<UPD>) {
+                    // flat numbering: lane + 1 holds slots h0 + 2, h0 + 3 of colour o
+                    // in this plane and lane - 1 slots h0 - 2, h0 - 1 (the same
+                    // updated values the load would form); across a row end the
+                    // shifted value feeds only a point outside the active box
+                    const double nx = dpp_next(cur[o].a), pv = dpp_prev(cur[o].b);
+                    if (!(par ? lane == 63 : lane == 0)) ex = par ? nx : pv;
+                }
                 double xm0, xp0, xm1, xp1;
                 if (par) {
                     xm0 = cur[o].a;
