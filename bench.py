@@ -84,6 +84,10 @@ def workload(name, N):
         # non-cubic patches: the box stack 64 x 32 x 46 / 46 x 22 x 30 / 30 x 16 x 22
         # scaled by N / 64 (N = 512: 512 x 256 x 368 base)
         return W.box_plummer_3d(max(1, N // 64))
+    if name == "slab":
+        # one GPU's share of an eight-way z split of the two-Plummer level:
+        # N x N x N/8 cells (N = 512: 512 x 512 x 64), one level
+        return W.slab_two_plummer(N)
     raise SystemExit("unknown workload %s" % name)
 
 

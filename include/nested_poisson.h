@@ -89,8 +89,9 @@ extern "C" {
                                residual stop rule only */
 
 /* How multigrid level 0 of a 3-D FP64 solve is smoothed (np_config.sweep).
- * NP_SWEEP_FULL: on level grids of at least 2^24 points (about 256^3 cells;
- * below that the half sweeps, which occupy the chip better, run), each
+ * NP_SWEEP_FULL: on level grids whose full sweep starts at least 4096
+ * wavefronts (cubic levels from about 420^3 cells; on smaller or thin grids
+ * the half sweeps, which occupy the chip better, run), each
  * red-black sweep is one pass from the level's potential
  * into a second buffer (the handle's; the buffers then trade roles), and the
  * stop test's residual norm is taken inside the sweeps: over the black points

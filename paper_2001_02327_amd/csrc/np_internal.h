@@ -137,6 +137,8 @@ constexpr int kSweepResIn = 1, kSweepResOut = 2;
 template <typename T>
 void launch_full_sweep(hipStream_t st, SGrid g, const T* P, T* Q, const T* f, double h2, double inv_h2, int mode,
                        int rev, unsigned long long* maxbits);
+// wavefronts one launch_full_sweep on grid g starts
+long full_sweep_waves(const SGrid& g);
 // fine grid of type TF, coarse of type TC; the coarse right-hand side is
 // multiplied by out_scale; rule != 0: the fine grid is a level L >= 1.  The
 // coarse correction is cleared, or with seed_h2 > 0 (the coarse level's h^2)

@@ -3684,6 +3684,15 @@ void launch_half_sweep_seeded(hipStream_t st, SGrid g, T* u, const T* f, double 
                            u, f, g, 1, (C)h2, (C)(1.0 / 6.0), pblocks);
 }
 
+long full_sweep_waves(const SGrid& g)
+{
+    const int my = g.ny - 2, mz = g.nz - 2;
+    const bool paired = g.hx % 2 == 0;
+    const int nrg = ceil_div(my, paired ? kFsPairRows : kFsRows);
+    const long waves = ceil_div((long)nrg * (paired ? g.hx / 2 : g.hx), kFsOwn);
+    return (long)ceil_div(waves, kFsBlock / 64) * (kFsBlock / 64) * ceil_div(mz, paired ? kFsPairChunk : kFsChunk);
+}
+
 template <typename T>
 void launch_full_sweep(hipStream_t st, SGrid g, const T* P, T* Q, const T* f, double h2, double inv_h2, int mode,
                        int rev, unsigned long long* maxbits)

@@ -682,18 +682,20 @@ int vcycle(np_solver* s, int l)
 }
 
 // Whether nested level l (solved on its own) runs full sweeps on multigrid level 0.
-// On small grids the full sweep's threads (a pair of columns times kFsPairRows
-// rows times a 16-plane chunk each) do not fill the chip: the paper's 3 x 128^3
-// stack took 15.2 ms per solve with full sweeps and 8.6 ms with half sweeps,
-// eight 64^3 patches one after another 46.7 and 27.3 ms; from 256^3 on the two
-// are alike and at 512^3 the full sweeps win.
-constexpr size_t kFullSweepMinPoints = size_t(1) << 24;
+// A full sweep's thread takes a pair of columns times five rows times a chunk
+// of 16 planes and needs registers for one wave per SIMD, so a launch of fewer
+// than about four waves per SIMD leaves the chip partly idle: the paper's
+// 3 x 128^3 stack took 15.2 ms per solve with full sweeps and 8.6 ms with half
+// sweeps, eight 64^3 patches one after another 46.7 and 27.3 ms, a 512 x 512 x
+// 64 slab (1080 waves) 150 us per full sweep against two half sweeps of 48 us;
+// 2 x 256^3 (952 waves) alike, 512^3 (7128 waves) faster with full sweeps.
+constexpr long kFullSweepMinWaves = 4096;
 
 bool full_sweeps(const np_solver* s, int l)
 {
     const np_config& c = s->cfg;
     const SGrid& g = s->lg[l];
-    const bool big = (size_t)g.nx * g.ny * g.nz >= kFullSweepMinPoints;
+    const bool big = full_sweep_waves(g) >= kFullSweepMinWaves;
     return c.dim == 3 && c.precision == NP_PREC_FP64 && c.sweep != NP_SWEEP_HALF &&
            (big || c.sweep == NP_SWEEP_FULL_ALL) && s->phi_alt && c.n_pre >= 1 && c.n_post >= 1 &&
            !(l > 0 && c.buffer == NP_BUFFER_INTERP);

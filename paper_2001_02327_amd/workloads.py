@@ -484,6 +484,19 @@ def box_plummer_3d(scale: int = 1) -> Workload:
     return Workload("box_plummer_3d_%d" % k, g, Plummer([(1.0, 0.12, centre)]))
 
 
+def slab_two_plummer(N: int = 512, parts: int = 8) -> Workload:
+    """One z-slab of the two-Plummer level of c5_two_plummer: N x N x N/parts
+    cells of 2/N on [-1, 1]^2 x [-1/parts, 1/parts], the two spheres in its
+    mid-plane, a single level.  This is one GPU's share when a level of N^3
+    cells is split into `parts` slabs along z; the closed-form potential on
+    the z faces stands in for the halo planes the neighbouring slabs would
+    send."""
+    nz = N // parts
+    g = Geometry(dim=3, n=[(N, N, nz)], off=[(0, 0, 0)], lo0=(-1.0, -1.0, -nz / N), dx0=2.0 / N, G=1.0)
+    return Workload("slab_two_plummer_%dx%dx%d" % (N, N, nz), g,
+                    Plummer([(1.0, 0.03, (0, 0, 0)), (0.3, 0.015, (0.2, 0.0, 0.0))]))
+
+
 def box_gaussian_2d(scale: int = 1) -> Workload:
     """A 2-D stack of non-cubic patches around a manufactured Gaussian
     (s = 0.15): base 64 x 32 cells of 1/32, a 42 x 26 patch from base cell

@@ -7,8 +7,10 @@ Bars as in test_gpu_parity (FP64: 1e-12 relative potential, 1e-11 forces, at
 the oracle's cycle counts) and test_gpu_mixed (defect correction: within 1e-8
 of the oracle's converged solution).  Cases: 2-D and 3-D stacks of boxes
 whose row lengths are multiples of 4 (paired kernels) and 2 mod 4 (unpaired
-ones), a thin box whose short axis reaches one cell early, the interpolated
-buffer, the force-change stop rule, cycle-by-cycle iterates and a tree.
+ones), a thin box whose short axis reaches one cell early, z-slabs of a
+cubic level (one GPU's share of a split level, up to 512 x 512 x 64 cells),
+the interpolated buffer, the force-change stop rule, cycle-by-cycle iterates
+and a tree.
 """
 import numpy as np
 import pytest
@@ -56,7 +58,7 @@ def _box_tree3d():
 
 
 BOXES = [W.box_plummer_3d(1), W.box_gaussian_2d(1), W.box_gaussian_2d(2), _thin3d(), _odd_rows3d(),
-         _box_tree3d()]
+         _box_tree3d(), W.slab_two_plummer(64), W.slab_two_plummer(64, parts=4)]
 
 
 @pytest.mark.parametrize("wl", BOXES, ids=lambda w: w.name)
@@ -113,8 +115,8 @@ def test_box_force_change_stop():
 
 
 @pytest.mark.parametrize("precision", ["fp32_dc", "fp16s_dc"])
-@pytest.mark.parametrize("wl", [W.box_plummer_3d(1), _odd_rows3d(), W.box_gaussian_2d(2), _box_tree3d()],
-                         ids=lambda w: w.name)
+@pytest.mark.parametrize("wl", [W.box_plummer_3d(1), _odd_rows3d(), W.box_gaussian_2d(2), _box_tree3d(),
+                                W.slab_two_plummer(64)], ids=lambda w: w.name)
 def test_box_defect_correction(wl, precision):
     rho, po = W.make_inputs(wl.geom, wl.prob)
     ref = core.solve(wl.geom, [r.numpy() for r in rho], po.numpy(), tol=1e-12, max_cycles=150)
@@ -124,6 +126,27 @@ def test_box_defect_correction(wl, precision):
         err = np.abs(phi[l] - ref["phi"][l]).max() / np.abs(ref["phi"][l]).max()
         assert err <= 1e-8, (l, err)
         assert st["final_rel_residual"][l] <= 1e-10
+
+
+def test_slab_share_full_size():
+    """One GPU's share of an eight-way z split of the 512^3 two-Plummer level
+    (512 x 512 x 64 cells, one level; the benchmark's slab workload): FP64 at
+    the oracle's cycle count element by element, and the FP16-storage defect
+    correction with the benchmark's fastest inner schedule within 1e-8 of the
+    oracle's converged solution."""
+    wl = W.slab_two_plummer(512)
+    print("slab parity: %s" % wl.name, flush=True)
+    res, F_o = oracle_solve(wl)
+    assert res["status"] == 0, res["status_name"]
+    phi_g, F_g, st, _ = gpu_solve(wl, fixed=res["cycles"])
+    assert_parity(wl, phi_g, F_g, res, F_o)
+    rho, po = W.make_inputs(wl.geom, wl.prob)
+    ref = core.solve(wl.geom, [r.numpy() for r in rho], po.numpy(), tol=1e-12, max_cycles=150)
+    assert ref["status"] == 0
+    phi, _, st, _ = gpu_solve(wl, precision="fp16s_dc", inner_cycles="adaptive", n_pre=1, n_post=1, coarse_post=2)
+    err = np.abs(phi[0] - ref["phi"][0]).max() / np.abs(ref["phi"][0]).max()
+    assert err <= 1e-8, err
+    assert st["final_rel_residual"][0] <= 1e-10
 
 
 def test_box_learned_guess_runs():

@@ -1,6 +1,7 @@
 """Full red-black sweeps on multigrid level 0 (3-D FP64: NP_SWEEP_FULL, the
-default, on level grids of at least 2^24 points; NP_SWEEP_FULL_ALL on every
-level) against the half sweeps in place (NP_SWEEP_HALF).
+default, on level grids whose full sweep starts at least 4096 wavefronts;
+NP_SWEEP_FULL_ALL on every level) against the half sweeps in place
+(NP_SWEEP_HALF).
 
 A full sweep relaxes the red points and then the black ones in one pass from
 the potential into a second buffer, with the arithmetic of the two half
@@ -99,15 +100,27 @@ def test_full_equals_half_at_size():
     _assert_same(_solve(wl, sweep="full_all"), _solve(wl, sweep="half"))
 
 
+def _sweep_launches(wl, **kw):
+    """Launch counts of the full and the half sweeps in one default solve (no
+    arrays copied back)."""
+    rho, po = W.make_inputs(wl.geom, wl.prob, device=torch.device("cuda"))
+    s = NestedPoissonSolver(wl.geom, **kw)
+    s.set_profiling(True)
+    st = s.solve(rho, po)
+    prof = s.profile()
+    torch.cuda.synchronize()
+    s.close()
+    assert max(st["final_rel_residual"]) <= 1e-10
+    return prof["full"][0], prof["smooth"][0]
+
+
 def test_default_takes_full_sweeps_on_large_levels_only():
-    """The default sweep setting runs full sweeps on a level of 260^3 points
-    (2 x 256^3) and half sweeps on one of 132^3 (3 x 128^3), with the iterates
-    of the half sweeps in both."""
-    big = W.c5_two_plummer(N=256, nlevels=2)
-    full = _solve(big, profile=True)
-    half = _solve(big, sweep="half")
-    _assert_same(full, half)
-    assert full[2]["profile"]["full"][0] > 0
-    small = W.c2_plummer(128)
-    st = _solve(small, profile=True)[2]
-    assert st["profile"]["full"][0] == 0 and st["profile"]["smooth"][0] > 0
+    """The default sweep setting runs full sweeps on a 512^3 level (7128
+    wavefronts per full sweep) and half sweeps on a 512 x 512 x 64 slab (1080),
+    on 2 x 256^3 (952) and on 3 x 128^3; the iterates are those of the half
+    sweeps either way (the tests above)."""
+    full, half = _sweep_launches(W.c5_two_plummer(N=512, nlevels=1))
+    assert full > 0 and half == 0
+    for wl in (W.slab_two_plummer(512), W.c5_two_plummer(N=256, nlevels=2), W.c2_plummer(128)):
+        full, half = _sweep_launches(wl)
+        assert full == 0 and half > 0, wl.name
