@@ -2110,6 +2110,7 @@ __global__ void __launch_bounds__(kBlock) k_restrict3_l0(const TF* __restrict__ 
 // storage: 206 -> 162 us at 514^3; the FP32 and FP64 forms (138 and 230 VGPRs)
 // measured slower than k_restrict3_l0 (325 vs 278 us, 597 vs 537 us).
 constexpr int kRestrictPairChunk = 4;  // coarse planes per thread
+constexpr int kRestrictPairGroup = 4;  // coarse planes whose loads are issued together (divides the chunk; 1, 2, 4: 163, 161, 159 us)
 
 // One fine row of a pair of coarse points in packed FP16 words: x = 2 h0 + m
 // for m = 0..5 is the lower (m = 0, 1, 4, 5) or upper (m = 2, 3) half of A (even
@@ -2234,17 +2235,42 @@ __global__ void __launch_bounds__(kBlock) k_restrict3_pair(const TF* __restrict_
         lo[r] = seg(u, 1 + r, 2 * K0 - 2);
         mid[r] = seg(u, 1 + r, 2 * K0 - 1);
     }
-    auto step = [&](int K) {
+    // the packed words of one coarse plane's fine rows, loaded before any of
+    // them is used (the DPP shifts of hrow come with the arithmetic)
+    struct Raw {
+        uint32_t n1[2][2], n2[2][2], fa[2][2], fb[2][2], y[4][2];
+    };
+    auto segw = [&](const TF* __restrict__ a, int r, int z, uint32_t (&w)[2]) {
+        const int y = 2 * J - 2 + r;
+        const bool ca = ((y + z + 1) & 1) != 0;
+        const TF* __restrict__ pl = a + (size_t)z * fplane + (row0 + (unsigned)(r * gf.hx));
+        w[0] = *(const uint32_t*)(pl + (ca ? gf.cs : 0));
+        w[1] = *(const uint32_t*)(pl + (ca ? 0 : gf.cs));
+    };
+    auto load = [&](int K, Raw& d) {
+#pragma unroll
+        for (int r = 0; r < 2; r++) {
+            segw(u, 1 + r, 2 * K, d.n1[r]);
+            segw(u, 1 + r, 2 * K + 1, d.n2[r]);
+            segw(f, 1 + r, 2 * K - 1, d.fa[r]);
+            segw(f, 1 + r, 2 * K, d.fb[r]);
+        }
+        segw(u, 0, 2 * K - 1, d.y[0]);
+        segw(u, 3, 2 * K - 1, d.y[1]);
+        segw(u, 0, 2 * K, d.y[2]);
+        segw(u, 3, 2 * K, d.y[3]);
+    };
+    auto step = [&](int K, const Raw& d) {
         HRow n1[2], n2[2], fa[2], fb[2];
 #pragma unroll
         for (int r = 0; r < 2; r++) {
-            n1[r] = seg(u, 1 + r, 2 * K);
-            n2[r] = seg(u, 1 + r, 2 * K + 1);
-            fa[r] = seg(f, 1 + r, 2 * K - 1);
-            fb[r] = seg(f, 1 + r, 2 * K);
+            n1[r] = hrow(d.n1[r][0], d.n1[r][1]);
+            n2[r] = hrow(d.n2[r][0], d.n2[r][1]);
+            fa[r] = hrow(d.fa[r][0], d.fa[r][1]);
+            fb[r] = hrow(d.fb[r][0], d.fb[r][1]);
         }
-        const HRow ya = seg(u, 0, 2 * K - 1), yb = seg(u, 3, 2 * K - 1);
-        const HRow yc = seg(u, 0, 2 * K), yd = seg(u, 3, 2 * K);
+        const HRow ya = hrow(d.y[0][0], d.y[0][1]), yb = hrow(d.y[1][0], d.y[1][1]);
+        const HRow yc = hrow(d.y[2][0], d.y[2][1]), yd = hrow(d.y[3][0], d.y[3][1]);
         C sa = 0, sb = 0;
         pair_plane_sums(lo, mid, n1, ya, yb, fa, m6, ninv_h2, sa, sb);
         pair_plane_sums(mid, n1, n2, yc, yd, fb, m6, ninv_h2, sa, sb);
@@ -2258,10 +2284,22 @@ __global__ void __launch_bounds__(kBlock) k_restrict3_pair(const TF* __restrict_
         }
     };
     if (K1 - K0 + 1 == kRestrictPairChunk) {
+        // a full chunk in groups of kRestrictPairGroup coarse planes, every load
+        // of a group issued before its first residual
 #pragma unroll
-        for (int i = 0; i < kRestrictPairChunk; i++) step(K0 + i);
+        for (int i = 0; i < kRestrictPairChunk; i += kRestrictPairGroup) {
+            Raw d[kRestrictPairGroup];
+#pragma unroll
+            for (int q = 0; q < kRestrictPairGroup; q++) load(K0 + i + q, d[q]);
+#pragma unroll
+            for (int q = 0; q < kRestrictPairGroup; q++) step(K0 + i + q, d[q]);
+        }
     } else {
-        for (int K = K0; K <= K1; K++) step(K);
+        for (int K = K0; K <= K1; K++) {
+            Raw d;
+            load(K, d);
+            step(K, d);
+        }
     }
 }
 
