@@ -3979,16 +3979,20 @@ __global__ void __launch_bounds__(kBlock) k_dc_scale_flat(long n8, size_t cs, co
         const float4 a = *(const float4*)(r32 + i);
         const float4 b = *(const float4*)(r32 + i + 4);
         const float v[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
-        TL rl[8], el[8];
+        // the eight values of r (and e) go out in 16-byte stores
+        union Out {
+            TL v[8];
+            uint4 w[sizeof(TL) / 2];
+        } rl, el;
 #pragma unroll
         for (int k = 0; k < 8; k++) {
-            rl[k] = (TL)(float)((double)v[k] * rscale);
-            el[k] = (colour == 0 && first_red) ? (TL)((0.0f - h2l * (float)rl[k]) * inv2d) : (TL)0.0f;
+            rl.v[k] = (TL)(float)((double)v[k] * rscale);
+            el.v[k] = (colour == 0 && first_red) ? (TL)((0.0f - h2l * (float)rl.v[k]) * inv2d) : (TL)0.0f;
         }
 #pragma unroll
-        for (int k = 0; k < 8; k += 2) {
-            *(Pair<TL>*)(r + i + k) = Pair<TL>{rl[k], rl[k + 1]};
-            if (e) *(Pair<TL>*)(e + i + k) = Pair<TL>{el[k], el[k + 1]};
+        for (int k = 0; k < (int)(sizeof(TL) / 2); k++) {
+            ((uint4*)(r + i))[k] = rl.w[k];
+            if (e) ((uint4*)(e + i))[k] = el.w[k];
         }
     }
 }
