@@ -179,18 +179,25 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
     return v;
 }
 
-__device__ __forceinline__ void block_max_to(unsigned long long v, unsigned long long* out)
+// Atomic maximum of v over a block of NW wavefronts into *out.
+template <int NW>
+__device__ __forceinline__ void block_max_to_w(unsigned long long v, unsigned long long* out)
 {
-    __shared__ unsigned long long red[kBlock / 64];
+    __shared__ unsigned long long red[NW];
     v = wave_max_u64(v);
     int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (lane == 0) red[wave] = v;
     __syncthreads();
     if (threadIdx.x == 0) {
         unsigned long long m = red[0];
-        for (int w = 1; w < kBlock / 64; w++) m = red[w] > m ? red[w] : m;
+        for (int w = 1; w < NW; w++) m = red[w] > m ? red[w] : m;
         atomicMax(out, m);
     }
+}
+
+__device__ __forceinline__ void block_max_to(unsigned long long v, unsigned long long* out)
+{
+    block_max_to_w<kBlock / 64>(v, out);
 }
 
 __device__ __forceinline__ unsigned long long abs_bits(double a)
@@ -221,11 +228,22 @@ __global__ void __launch_bounds__(kBlock) k_level0_init(SGrid g, const double* _
     const long total = (long)g.nx * g.ny * g.nz;
     const long stride = (long)gridDim.x * kBlock;
     unsigned long long best = 0;
+    // 32-bit index arithmetic where the grid allows (a 64-bit division costs
+    // several times a 32-bit one, per point)
+    const bool narrow = total <= 0xffffffffL;
     for (long t = xcd_block() * kBlock + threadIdx.x; t < total; t += stride) {
-        int pi = (int)(t % g.nx);
-        long r = t / g.nx;
-        int pj = (int)(r % g.ny);
-        int pk = (int)(r / g.ny);
+        int pi, pj, pk;
+        if (narrow) {
+            const unsigned tu = (unsigned)t, r = tu / (unsigned)g.nx;
+            pi = (int)(tu - r * (unsigned)g.nx);
+            pj = (int)(r % (unsigned)g.ny);
+            pk = (int)(r / (unsigned)g.ny);
+        } else {
+            pi = (int)(t % g.nx);
+            const long r = t / g.nx;
+            pj = (int)(r % g.ny);
+            pk = (int)(r / g.ny);
+        }
         bool ring = pi == 0 || pi == g.nx - 1 || pj == 0 || pj == g.ny - 1 || (D == 3 && (pk == 0 || pk == g.nz - 1));
         size_t p = pos<D, double>(g, pi, pj, pk);
         if (ring) {
@@ -618,17 +636,23 @@ __global__ void __launch_bounds__(kBlock) k_forces(SGrid g, double m12dx, const 
 // The x-neighbours i-2 .. i+2 are the adjacent lanes' column values, moved by DPP
 // shifts: a wave owns the kForceOwn columns between its two first and two last
 // lanes, which only supply values; at the ends of a row (the buffer columns) the
-// lanes load them.  Same arithmetic as k_forces.
+// lanes load them.  Same arithmetic as k_forces.  DELTA: the force-change stop
+// test (Sec. 3.1): the arrays hold the previous iterate's forces, each point's
+// new value replaces the old one and max |F_new - F_old| over the points and
+// components goes to maxbits (as k_force_delta, value for value).
 // planes and rows per thread: (8, 4) measured best of (4, 1), (4, 2), (2, 4), (4, 4),
 // (4, 8), (2, 8) at 512^3 (1.61 -> 1.28 ms, with every x-neighbour loaded)
 constexpr int kForceChunk = 8;
 constexpr int kForceRows = 4;
 constexpr int kForceOwn = 60;  // columns a wave owns (lanes 2..61)
 
+template <bool DELTA>
 __global__ void __launch_bounds__(kForceBlock) k_forces3_zm(SGrid g, double m12dx, const double* __restrict__ phi,
                                                        double* __restrict__ fx, double* __restrict__ fy,
-                                                       double* __restrict__ fz, int pblocks)
+                                                       double* __restrict__ fz, int pblocks,
+                                                       unsigned long long* maxbits)
 {
+    unsigned long long best = 0;
     constexpr int R = kForceRows;
     constexpr int KC = kForceChunk;
     const int nx = g.nx - 4, ny = g.ny - 4, nz = g.nz - 4;
@@ -690,12 +714,25 @@ __global__ void __launch_bounds__(kForceBlock) k_forces3_zm(SGrid g, double m12d
                 if (!owner || j0 + r >= ny) continue;
                 const long o = ((long)(k0 + q) * ny + (j0 + r)) * nx + i;
                 const int w = r + 2;
-                store_nt(fx + o, (8.0 * (xp1 - xm1) - (xp2 - xm2)) * m12dx);
-                store_nt(fy + o, (8.0 * (yv(w + 1, q) - yv(w - 1, q)) - (yv(w + 2, q) - yv(w - 2, q))) * m12dx);
-                store_nt(fz + o, (8.0 * (col[r][q + 3] - col[r][q + 1]) - (col[r][q + 4] - col[r][q])) * m12dx);
+                const double vx = (8.0 * (xp1 - xm1) - (xp2 - xm2)) * m12dx;
+                const double vy = (8.0 * (yv(w + 1, q) - yv(w - 1, q)) - (yv(w + 2, q) - yv(w - 2, q))) * m12dx;
+                const double vz = (8.0 * (col[r][q + 3] - col[r][q + 1]) - (col[r][q + 4] - col[r][q])) * m12dx;
+                if (DELTA) {
+                    const double ox = fx[o], oy = fy[o], oz = fz[o];
+                    unsigned long long b = abs_bits(vx - ox);
+                    best = b > best ? b : best;
+                    b = abs_bits(vy - oy);
+                    best = b > best ? b : best;
+                    b = abs_bits(vz - oz);
+                    best = b > best ? b : best;
+                }
+                store_nt(fx + o, vx);
+                store_nt(fy + o, vy);
+                store_nt(fz + o, vz);
             }
         }
     }
+    if (DELTA) block_max_to_w<kForceBlock / 64>(best, maxbits);
 }
 
 // Forces into F (d arrays of n^d) and the maximum change against the values
@@ -3601,8 +3638,8 @@ void launch_forces(int dim, hipStream_t st, SGrid g, double dx, const double* ph
     if (dim == 3) {
         const long waves = ceil_div(nx * ((ny + kForceRows - 1) / kForceRows), kForceOwn);
         const int pblocks = ceil_div(waves, kForceBlock / 64);
-        hipLaunchKernelGGL(k_forces3_zm, dim3(pblocks * ceil_div(nz, kForceChunk)), dim3(kForceBlock), 0, st, g,
-                           m12dx, phi, fx, fy, fz, pblocks);
+        hipLaunchKernelGGL(k_forces3_zm<false>, dim3(pblocks * ceil_div(nz, kForceChunk)), dim3(kForceBlock), 0, st,
+                           g, m12dx, phi, fx, fy, fz, pblocks, nullptr);
         return;
     }
     Strip sp = make_strip((int)nx, (int)ny, 1, 16);
@@ -3614,6 +3651,15 @@ void launch_force_delta(int dim, hipStream_t st, SGrid g, double dx, const doubl
 {
     long total = (long)(g.nx - 4) * (g.ny - 4) * (dim == 3 ? g.nz - 4 : 1);
     double m12dx = -1.0 / (12.0 * dx);
+    if (dim == 3) {
+        // the z-march force kernel with the comparison (components at F, F + total, F + 2 total)
+        const long nx = g.nx - 4, ny = g.ny - 4, nz = g.nz - 4;
+        const long waves = ceil_div(nx * ((ny + kForceRows - 1) / kForceRows), kForceOwn);
+        const int pblocks = ceil_div(waves, kForceBlock / 64);
+        hipLaunchKernelGGL(k_forces3_zm<true>, dim3(pblocks * ceil_div(nz, kForceChunk)), dim3(kForceBlock), 0, st, g,
+                           m12dx, phi, F, F + total, F + 2 * total, pblocks, maxbits);
+        return;
+    }
     NP_DISPATCH(dim, k_force_delta, dim3(ceil_div(total, kBlock)), dim3(kBlock), st, g, m12dx, phi, F, maxbits);
 }
 
