@@ -259,7 +259,7 @@ int nested_poisson_potential(np_solver* s, int level, double* phi_padded);
 #define NP_KCLASS_RESTRICT 1 /* fused residual + restriction out of multigrid level 0 */
 #define NP_KCLASS_PROLONG 2  /* prolongation + correction into multigrid level 0 */
 #define NP_KCLASS_COARSE 3   /* all work on multigrid levels >= 1 (one interval per V-cycle) */
-#define NP_KCLASS_NORM 4     /* max-norm reductions of the stop test */
+#define NP_KCLASS_NORM 4     /* max-norm reductions of the stop test (residual, or force change) */
 #define NP_KCLASS_FILL 5     /* level-0 setup and coarse-to-fine fills */
 #define NP_KCLASS_FORCES 6   /* force evaluation */
 #define NP_KCLASS_DC 7       /* FP64 residual / correction passes of the defect correction */

@@ -818,7 +818,9 @@ int force_delta_sync(np_solver* s, int l, double* out)
 {
     double dx = level_dx(&s->cfg, l);
     launch_set_u64(s->stream, s->d_bits + 1, 1, 0ULL);
+    prof_begin(s, NP_KCLASS_NORM);
     launch_force_delta(s->cfg.dim, s->stream, s->lg[l], dx, s->phi[l], s->force_scratch, s->d_bits + 1);
+    prof_end(s);
     HIPCHK(s, hipGetLastError());
     HIPCHK(s, hipMemcpyAsync(s->h_bits + 1, s->d_bits + 1, sizeof(unsigned long long), hipMemcpyDeviceToHost, s->stream));
     HIPCHK(s, hipStreamSynchronize(s->stream));
